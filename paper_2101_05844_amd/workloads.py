@@ -1,0 +1,349 @@
+"""Seeded synthetic workloads for the Active Set dual bound.
+
+This module only draws random numbers and arranges them into the inputs the
+bounding problem takes (Sec. 2, problem eq:noncvx_pb): layer weights and
+biases, an l_inf input box, objective rows for logit-difference properties
+(Sec. 7.3.1: minimise true logit minus target logit), and the random draws
+that decide which ReLUs a branch-and-bound subdomain fixes.  It holds none of
+the bounding method's arithmetic, imports nothing from the rest of the
+package, and is shared by the GPU path, the tests and the benchmark.
+
+The networks stand in for the paper's trained CIFAR-10/MNIST models (Table 1
+"Wide" architecture; the MNIST MLP shape of App. G), which are not available:
+weights are N(0, 1/fan_in), biases N(0, 0.1) (second argument = variance),
+inputs U[0,1] images with an l_inf ball of radius eps clipped to [0, 1].
+
+Random draws happen in a fixed order: layer by layer (W then b), then the
+input centre, then the property, then the subdomain fixes.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+# ----------------------------------------------------------------------------
+# Layer specifications
+# ----------------------------------------------------------------------------
+
+
+@dataclasses.dataclass(frozen=True)
+class DenseSpec:
+    n_in: int
+    n_out: int
+
+
+@dataclasses.dataclass(frozen=True)
+class ConvSpec:
+    c_in: int
+    h_in: int
+    w_in: int
+    c_out: int
+    k: int
+    stride: int
+    pad: int
+
+    @property
+    def h_out(self) -> int:
+        return (self.h_in + 2 * self.pad - self.k) // self.stride + 1
+
+    @property
+    def w_out(self) -> int:
+        return (self.w_in + 2 * self.pad - self.k) // self.stride + 1
+
+
+def spec_sizes(spec) -> Tuple[int, int, int]:
+    """(n_in, n_out, fan_in) of a layer spec; conv neurons ordered (c, y, x)."""
+    if isinstance(spec, DenseSpec):
+        return spec.n_in, spec.n_out, spec.n_in
+    return (spec.c_in * spec.h_in * spec.w_in,
+            spec.c_out * spec.h_out * spec.w_out,
+            spec.c_in * spec.k * spec.k)
+
+
+@dataclasses.dataclass
+class Layer:
+    """One affine layer x_hat_k = W_k x_{k-1} + b_k (conv in (c, y, x) order)."""
+    spec: object
+    W: np.ndarray  # float32; dense [n_out, n_in], conv [c_out, c_in, k, k]
+    b: np.ndarray  # float32; dense [n_out], conv [c_out]
+
+    @property
+    def kind(self) -> str:
+        return "dense" if isinstance(self.spec, DenseSpec) else "conv"
+
+    @property
+    def n_in(self) -> int:
+        return spec_sizes(self.spec)[0]
+
+    @property
+    def n_out(self) -> int:
+        return spec_sizes(self.spec)[1]
+
+
+@dataclasses.dataclass
+class Schedule:
+    """Iteration schedule of the solver (Sec. 7.1 hyper-parameters)."""
+    bigm_iters: int = 180
+    as_iters: int = 500
+    add_every: int = 450      # omega: addition period
+    add_count: int = 2        # V: consecutive addition iterations per period
+    max_masks: int = 7        # K_max: cap on masks per layer
+    bigm_lr: Tuple[float, float] = (1e-2, 1e-4)
+    as_lr: Tuple[float, float] = (1e-3, 1e-6)
+    adam_beta1: float = 0.9
+    adam_beta2: float = 0.999
+    adam_eps: float = 1e-8
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    layers: List[Layer]
+    l0: np.ndarray            # float32 [S, n0]
+    u0: np.ndarray            # float32 [S, n0]
+    c: np.ndarray             # float32 [S, n_last] objective rows
+    schedule: Schedule
+    fix_draws: Optional["FixDraws"] = None
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def S(self) -> int:
+        return self.l0.shape[0]
+
+    @property
+    def relu_sizes(self) -> List[int]:
+        return [L.n_out for L in self.layers[:-1]]
+
+
+@dataclasses.dataclass
+class FixDraws:
+    """Random numbers that decide each subdomain's fixed ReLU phases.
+
+    count[s]   number of ReLUs subdomain s fixes (before capping at the number
+               of ambiguous ReLUs);
+    key[s, r]  uniform key per ReLU r (flattened over layers); the fixed ReLUs
+               are the `count[s]` ambiguous ones with the smallest keys;
+    phase[s,r] 1 = passing (pre-activation lower bound raised to 0),
+               0 = blocking (pre-activation upper bound lowered to 0).
+    """
+    count: np.ndarray
+    key: np.ndarray
+    phase: np.ndarray
+
+
+# ----------------------------------------------------------------------------
+# Drawing
+# ----------------------------------------------------------------------------
+
+
+def draw_layers(specs: Sequence, rng: np.random.Generator) -> List[Layer]:
+    layers = []
+    for sp in specs:
+        _, _, fan_in = spec_sizes(sp)
+        if isinstance(sp, DenseSpec):
+            W = rng.normal(0.0, np.sqrt(1.0 / fan_in), size=(sp.n_out, sp.n_in))
+            b = rng.normal(0.0, np.sqrt(0.1), size=(sp.n_out,))
+        else:
+            W = rng.normal(0.0, np.sqrt(1.0 / fan_in),
+                           size=(sp.c_out, sp.c_in, sp.k, sp.k))
+            b = rng.normal(0.0, np.sqrt(0.1), size=(sp.c_out,))
+        layers.append(Layer(sp, W.astype(np.float32), b.astype(np.float32)))
+    return layers
+
+
+def linf_box(centre: np.ndarray, eps: float, clip: Optional[Tuple[float, float]]):
+    lo = centre - eps
+    hi = centre + eps
+    if clip is not None:
+        lo = np.clip(lo, clip[0], clip[1])
+        hi = np.clip(hi, clip[0], clip[1])
+    return lo.astype(np.float32), hi.astype(np.float32)
+
+
+def logit_difference_rows(n_classes: int, true_cls: int, targets: Sequence[int]) -> np.ndarray:
+    """Objective rows c = e_true - e_target (minimise true minus target logit)."""
+    c = np.zeros((len(targets), n_classes), dtype=np.float32)
+    for r, j in enumerate(targets):
+        c[r, true_cls] = 1.0
+        c[r, j] = -1.0
+    return c
+
+
+def draw_fixes(rng: np.random.Generator, S: int, n_relu: int, max_count: int) -> FixDraws:
+    count = rng.integers(0, max_count + 1, size=S)
+    key = rng.random((S, n_relu))
+    phase = rng.integers(0, 2, size=(S, n_relu)).astype(np.int8)
+    return FixDraws(count=count, key=key, phase=phase)
+
+
+def select_fixes(draws: FixDraws, ambiguous: np.ndarray, s: int):
+    """Indices (into the flattened ReLU list) and phases fixed by subdomain s.
+
+    `ambiguous` is a boolean vector over all ReLUs (flattened over layers)
+    marking those whose pre-activation interval strictly contains 0 at the
+    root.  Pure selection: no bound arithmetic.
+    """
+    cand = np.flatnonzero(ambiguous)
+    n = min(int(draws.count[s]), cand.size)
+    if n == 0:
+        return np.zeros(0, dtype=np.int64), np.zeros(0, dtype=np.int8)
+    order = np.argsort(draws.key[s, cand], kind="stable")[:n]
+    idx = np.sort(cand[order])
+    return idx, draws.phase[s, idx]
+
+
+def subdomain_bounds(root_lhat: Sequence[np.ndarray], root_uhat: Sequence[np.ndarray],
+                     draws: Optional[FixDraws], S: int):
+    """Per-subdomain pre-activation bounds [S, n_k] from root bounds [n_k].
+
+    A branch-and-bound split fixes a ReLU's phase: passing sets the lower
+    pre-activation bound to 0, blocking sets the upper one to 0 (Sec. 7.3,
+    BaBSR splits a ReLU into its two phases).  The other bounds stay as they
+    are at the root, which remains valid on the subdomain.
+    """
+    lh = [np.repeat(np.asarray(a, np.float32)[None, :], S, axis=0) for a in root_lhat]
+    uh = [np.repeat(np.asarray(a, np.float32)[None, :], S, axis=0) for a in root_uhat]
+    if draws is None:
+        return lh, uh
+    flat_l = np.concatenate([np.asarray(a) for a in root_lhat])
+    flat_u = np.concatenate([np.asarray(a) for a in root_uhat])
+    ambiguous = (flat_l < 0) & (flat_u > 0)
+    offs = np.cumsum([0] + [len(a) for a in root_lhat])
+    for s in range(S):
+        idx, ph = select_fixes(draws, ambiguous, s)
+        for r, p in zip(idx, ph):
+            k = int(np.searchsorted(offs, r, side="right") - 1)
+            i = int(r - offs[k])
+            if p:
+                lh[k][s, i] = 0.0
+            else:
+                uh[k][s, i] = 0.0
+    return lh, uh
+
+
+# ----------------------------------------------------------------------------
+# The configurations
+# ----------------------------------------------------------------------------
+
+TINY_SPECS = [DenseSpec(5, 8), DenseSpec(8, 8), DenseSpec(8, 1)]
+MNIST_SPECS = [DenseSpec(784, 100), DenseSpec(100, 100), DenseSpec(100, 100), DenseSpec(100, 10)]
+CIFAR_WIDE_SPECS = [
+    ConvSpec(3, 32, 32, 16, 4, 2, 1),
+    ConvSpec(16, 16, 16, 32, 4, 2, 1),
+    DenseSpec(2048, 100),
+    DenseSpec(100, 10),
+]
+CIFAR_WIDER_SPECS = [
+    ConvSpec(3, 32, 32, 32, 4, 2, 1),
+    ConvSpec(32, 16, 16, 64, 4, 2, 1),
+    DenseSpec(4096, 512),
+    DenseSpec(512, 10),
+]
+
+
+def tiny_config(seed: int = 1000) -> Workload:
+    """5-8-8-1 ReLU net, box centre U[-1,1]^5 +- 0.1, one subproblem."""
+    rng = np.random.default_rng(seed)
+    layers = draw_layers(TINY_SPECS, rng)
+    centre = rng.uniform(-1.0, 1.0, size=5)
+    l0, u0 = linf_box(centre, 0.1, None)
+    c = np.ones((1, 1), dtype=np.float32)
+    sched = Schedule(bigm_iters=50, as_iters=50, add_every=10, add_count=2, max_masks=7)
+    return Workload("tiny-5-8-8-1", layers, l0[None, :], u0[None, :], c, sched,
+                    meta={"seed": seed, "eps": 0.1})
+
+
+def mnist_mlp_config(seed: int = 1001) -> Workload:
+    """784-100-100-100-10 MLP, eps 0.05, 9 logit-difference subproblems."""
+    rng = np.random.default_rng(seed)
+    layers = draw_layers(MNIST_SPECS, rng)
+    centre = rng.uniform(0.0, 1.0, size=784)
+    eps = 0.05
+    l0, u0 = linf_box(centre, eps, (0.0, 1.0))
+    t = int(rng.integers(0, 10))
+    targets = [j for j in range(10) if j != t]
+    c = logit_difference_rows(10, t, targets)
+    S = len(targets)
+    sched = Schedule(bigm_iters=500, as_iters=500, add_every=450, add_count=2, max_masks=7,
+                     bigm_lr=(1e-1, 1e-3), as_lr=(1e-3, 1e-6))
+    return Workload("mnist-mlp-784-100x3-10", layers, np.repeat(l0[None], S, 0),
+                    np.repeat(u0[None], S, 0), c, sched,
+                    meta={"seed": seed, "eps": eps, "true_class": t})
+
+
+def cifar_conv_config(seed: int = 1002, S: int = 512, specs=None, max_fixed: int = 20,
+                      name: str = "cifar-wide-conv") -> Workload:
+    """Table 1 "Wide" CIFAR conv net, eps 2/255, S branch-and-bound subdomains.
+
+    All subdomains share one input box and one property; each fixes
+    U{0..max_fixed} ambiguous ReLUs (drawn for 512 subdomains, so smaller S
+    takes a prefix of the same draws).
+    """
+    specs = CIFAR_WIDE_SPECS if specs is None else specs
+    rng = np.random.default_rng(seed)
+    layers = draw_layers(specs, rng)
+    centre = rng.uniform(0.0, 1.0, size=3 * 32 * 32)
+    eps = 2.0 / 255.0
+    l0, u0 = linf_box(centre, eps, (0.0, 1.0))
+    t = int(rng.integers(0, 10))
+    j = int(rng.choice([k for k in range(10) if k != t]))
+    c = logit_difference_rows(10, t, [j])
+    n_relu = sum(spec_sizes(sp)[1] for sp in specs[:-1])
+    S_draw = max(512, S)
+    draws = draw_fixes(rng, S_draw, n_relu, max_fixed)
+    draws = FixDraws(draws.count[:S], draws.key[:S], draws.phase[:S])
+    sched = Schedule(bigm_iters=180, as_iters=500, add_every=450, add_count=2, max_masks=7)
+    return Workload(name, layers, np.repeat(l0[None], S, 0), np.repeat(u0[None], S, 0),
+                    np.repeat(c, S, 0), sched, fix_draws=draws,
+                    meta={"seed": seed, "eps": eps, "true_class": t, "target": j})
+
+
+def custom_config(specs: Sequence, S: int, seed: int, eps: float = 0.05,
+                  centre_range=(0.0, 1.0), n_props: Optional[int] = None,
+                  max_fixed: int = 0, schedule: Optional[Schedule] = None,
+                  name: str = "custom") -> Workload:
+    """Arbitrary small net for parity tests (ragged sizes, several tiles).
+
+    Each subproblem gets its own random objective row (N(0,1) entries) unless
+    the last layer has one output, in which case c = 1.
+    """
+    rng = np.random.default_rng(seed)
+    layers = draw_layers(specs, rng)
+    n0 = layers[0].n_in
+    centre = rng.uniform(centre_range[0], centre_range[1], size=(S, n0))
+    clip = (0.0, 1.0) if centre_range == (0.0, 1.0) else None
+    l0, u0 = linf_box(centre, eps, clip)
+    n_last = layers[-1].n_out
+    if n_last == 1:
+        c = np.ones((S, 1), dtype=np.float32)
+    else:
+        c = rng.normal(0.0, 1.0, size=(S, n_last)).astype(np.float32)
+    draws = None
+    if max_fixed > 0:
+        n_relu = sum(L.n_out for L in layers[:-1])
+        draws = draw_fixes(rng, S, n_relu, max_fixed)
+    sched = schedule or Schedule(bigm_iters=20, as_iters=30, add_every=10, add_count=2,
+                                 max_masks=3)
+    return Workload(name, layers, l0, u0, c, sched, fix_draws=draws,
+                    meta={"seed": seed, "eps": eps})
+
+
+def make_config(i: int, S: Optional[int] = None) -> Workload:
+    """Configurations by index: 0 tiny, 1 MNIST MLP, 2 CIFAR conv (S default 512)."""
+    if i == 0:
+        return tiny_config()
+    if i == 1:
+        return mnist_mlp_config()
+    if i == 2:
+        return cifar_conv_config(S=512 if S is None else S)
+    raise ValueError(f"unknown configuration {i}")
+
+
+def random_points_in_box(l0: np.ndarray, u0: np.ndarray, n: int, seed: int) -> np.ndarray:
+    """n uniform points and the 2 extreme corners of a box [n0] (for sampled outputs)."""
+    rng = np.random.default_rng(seed)
+    pts = rng.uniform(0.0, 1.0, size=(n, l0.shape[0]))
+    pts = l0[None, :] + pts * (u0 - l0)[None, :]
+    return np.concatenate([pts, l0[None, :], u0[None, :]], axis=0)

@@ -1,0 +1,222 @@
+"""Benchmark: Active Set dual on the CIFAR-shaped conv net, one MI355X.
+
+One step is one whole solve of a batch of 512 branch-and-bound subdomains on
+the Table 1 "Wide" network (180 Big-M iterations, 500 Active Set iterations
+with mask additions, FP64 final bound), inputs resident in HBM.  The metric
+is subproblem-iterations per second of the Active Set phase,
+S * T_AS / (Active Set phase time), with the phase timed by HIP events on the
+stream the solver runs on.  The JSON line also carries the whole-step rate,
+the roofline figure of the dominant kernel and the FP64 oracle's rate on a
+bounded sample of the same workload.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "subproblem-iterations/sec, Active Set dual on CIFAR conv net; % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+
+
+def per_layer_state_bytes(n_k, n_prev, K):
+    """Algorithmic bytes the update of one ReLU layer must move per
+    subproblem-iteration: duals and Adam moments read and written (24 B per
+    multiplier), pre-activation bounds (8 B), LI/UI per mask (8 B), compact
+    mask bits (z bits of the layer, x bits of the layer before)."""
+    return 24 * (3 + K) * n_k + 8 * n_k + 8 * K * n_k + K * (n_k + n_prev) / 8.0
+
+
+def unit_bytes(sizes, K):
+    """Whole-network algorithmic bytes per subproblem-iteration with K masks:
+    every ReLU layer's update plus the input box (8 B per input) and the
+    objective row."""
+    n = len(sizes) - 1
+    tot = 8 * sizes[0] + 4 * (sizes[-1] + sizes[-2])
+    for k in range(1, n):
+        tot += per_layer_state_bytes(sizes[k], sizes[k - 1], K)
+    return tot
+
+
+def masks_at(t, sched):
+    """Active masks during Active Set iteration t (additions at t mod omega < V)."""
+    K = 0
+    for tt in range(t + 1):
+        if (tt % sched.add_every) < sched.add_count and K < sched.max_masks:
+            K += 1
+    return K
+
+
+def cpu_baseline(w, n_sub=2):
+    """The FP64 oracle on a bounded sample: the first n_sub subdomains, full
+    schedule; rate = Active Set subproblem-iterations per second."""
+    import numpy as np
+
+    from oracle import asd_oracle as O
+    from paper_2101_05844_amd import workloads as WL
+
+    ops = O.ops_from_workload_layers(w.layers)
+    lh, uh = O.interval_bounds(ops, w.l0[0].astype(float), w.u0[0].astype(float))
+    lh = [np.nextafter(a.astype(np.float32), np.float32(-np.inf)) for a in lh[:-1]]
+    uh = [np.nextafter(a.astype(np.float32), np.float32(np.inf)) for a in uh[:-1]]
+    L, U = WL.subdomain_bounds(lh, uh, w.fix_draws, w.S)
+    prm = O.params_from_schedule(w.schedule)
+    t_as = 0.0
+    for s in range(n_sub):
+        p = O.make_problem(ops, w.l0[s], w.u0[s], [a[s] for a in L], [a[s] for a in U], w.c[s])
+        st = O.zero_state(p)
+        for t in range(prm.bigm_iters):
+            O.bigm_iteration(p, st, O.linear_lr(*prm.bigm_lr, t, prm.bigm_iters), prm)
+        O.reset_moments(st)
+        t0 = time.perf_counter()
+        for t in range(prm.as_iters):
+            O.as_iteration(p, st, t, O.linear_lr(*prm.as_lr, t, prm.as_iters), prm)
+        t_as += time.perf_counter() - t0
+    rate = n_sub * prm.as_iters / t_as
+    return {"value": rate, "unit": "subproblem-iterations/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n_sub} of the {w.S} subdomains, full schedule "
+                      f"({prm.bigm_iters} Big-M + {prm.as_iters} Active Set iterations), "
+                      f"rate over the Active Set phase; NumPy/SciPy FP64, single thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--subproblems", type=int, default=512)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-profile", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the batch of subdomains would shard across GPUs with no per-iteration "
+              "communication, which this build does not implement.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2101_05844_amd import asdual as A
+    from paper_2101_05844_amd import workloads as WL
+
+    torch.cuda.set_device(0)
+    A.lib()
+    w = WL.cifar_conv_config(S=args.subproblems)
+    sched = w.schedule
+    S = w.S
+    dev = "cuda:0"
+    t32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=dev)
+    net = A.Net(w.layers, device=dev)
+    # intermediate bounds: interval propagation on the GPU at the root (all
+    # subdomains share the input box), then each subdomain's fixed phases
+    lh0, uh0 = net.interval_bounds(t32(w.l0[:1]), t32(w.u0[:1]))
+    lh0 = [a[0].cpu().numpy() for a in lh0[:-1]]
+    uh0 = [a[0].cpu().numpy() for a in uh0[:-1]]
+    L, U = WL.subdomain_bounds(lh0, uh0, w.fix_draws, S)
+    l0, u0, c = t32(w.l0), t32(w.u0), t32(w.c)
+    lh, uh = [t32(a) for a in L], [t32(a) for a in U]
+    plan = A.Plan(net, S, A.params_from_schedule(sched))
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        plan.init(l0, u0, lh, uh, c)
+        if ev:
+            ev[0].record(stream)
+        plan.run(A.ASD_PHASE_BIGM, 0, sched.bigm_iters)
+        if ev:
+            ev[1].record(stream)
+        plan.run(A.ASD_PHASE_AS, 0, sched.as_iters)
+        if ev:
+            ev[2].record(stream)
+        return plan.bound()
+
+    for _ in range(args.warmup):
+        lb = step()
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done ({args.warmup} solves)", file=sys.stderr, flush=True)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        lb = step(evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    bigm_ms = sum(e[0].elapsed_time(e[1]) for e in evs)
+    as_ms = sum(e[1].elapsed_time(e[2]) for e in evs)
+    value = S * sched.as_iters * args.steps / (as_ms / 1e3)
+    lb_np = lb.cpu().numpy()
+    print(f"[bench] timed {args.steps} solves: {wall:.3f} s; AS phase {as_ms / args.steps:.2f} ms/solve",
+          file=sys.stderr, flush=True)
+
+    sizes = [w.layers[0].n_in] + [Lr.n_out for Lr in w.layers]
+    Ks = [masks_at(t, sched) for t in range(sched.as_iters)]
+    alg_as = S * sum(unit_bytes(sizes, K) for K in Ks)
+    roofline = None
+    kernels = None
+    if not args.no_kernel_profile:
+        plan.profile(True)
+        step()
+        torch.cuda.synchronize()
+        prof = plan.profile_read()
+        plan.profile(False)
+        kernels = {f"{r}:{l}": {"launches": n, "avg_us": 1e3 * ms / n} for (r, l), (n, ms) in prof.items()}
+        dom = max(prof.items(), key=lambda kv: kv[1][1])
+        (role, layer), (n_launch, tot_ms) = dom
+        # algorithmic bytes of the dominant kernel over the solve: the forward
+        # (update) kernel of layer k moves its layer's state; every other
+        # kernel is charged the same layer state it reads
+        n_k = sizes[layer] if layer < len(sizes) else sizes[-1]
+        n_prev = sizes[layer - 1] if layer >= 1 else 0
+        per_iter = [per_layer_state_bytes(n_k, n_prev, masks_at(t, sched)) for t in range(sched.as_iters)]
+        K_bigm = [0] * sched.bigm_iters
+        per_iter = [per_layer_state_bytes(n_k, n_prev, K) for K in K_bigm] + per_iter
+        tot_bytes = S * sum(per_iter[:n_launch]) if n_launch <= len(per_iter) else None
+        if tot_bytes:
+            achieved = tot_bytes / (tot_ms / 1e3) / 1e9
+            roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "kernel": f"{role} layer {layer}", "avg_launch_us": round(1e3 * tot_ms / n_launch, 2)}
+    whole_as_gbs = alg_as / (as_ms / args.steps / 1e3) / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(w)
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "subproblem-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * wall / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "Table 1 Wide CIFAR conv net, 512 branch-and-bound subdomains "
+                               "(0-20 fixed ReLUs each), eps 2/255",
+                   "subproblems": S, "bigm_iters": sched.bigm_iters, "as_iters": sched.as_iters,
+                   "add_every": sched.add_every, "add_count": sched.add_count, "max_masks": sched.max_masks},
+        "whole_step_rate": round(S * (sched.bigm_iters + sched.as_iters) * args.steps / wall, 1),
+        "bigm_phase_ms": round(bigm_ms / args.steps, 3),
+        "as_phase_ms": round(as_ms / args.steps, 3),
+        "as_phase_alg_GBps": round(whole_as_gbs, 1),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+        "bound_mean": float(np.mean(lb_np)),
+        "verified_fraction": float(np.mean(lb_np > 0)),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,282 @@
+/*
+ * asdual.h - C ABI of the Active Set dual bound for ReLU networks on MI355X.
+ *
+ * Method: De Palma, Behl, Bunel, Torr, Kumar, "Scaling the Convex Barrier
+ * with Sparse Dual Algorithms" (JMLR 2024, arXiv:2101.05844).
+ *
+ * The library computes lower bounds on c^T x_hat_n over an l_inf input box
+ * for a feed-forward ReLU network (Sec. 2, problem eq:noncvx_pb) by
+ * maximising the dual of the Anderson-type relaxation (Sec. 2.2,
+ * eq:primal-anderson) restricted to an active set of multipliers
+ * (Sec. 4.1, eq:dual-active-set), with Algorithm 1 (Active Set) initialised by
+ * Algorithm 3 (the Big-M dual, App. B).  Any non-negative dual assignment
+ * gives a valid bound (weak duality, Sec. 3); the returned value is the dual
+ * objective at the final duals, evaluated in FP64.
+ *
+ * Conventions
+ *  - All arrays passed as pointers are DEVICE memory (HIP), unless a comment
+ *    says "host".  They are borrowed: the caller owns them and keeps them
+ *    alive until the stream-ordered call that uses them has completed.
+ *  - Per-subproblem arrays are row-major [S][n]: subproblem s, then the
+ *    neuron index of the layer.  Convolutional neurons are flattened in
+ *    (channel, y, x) order; weights of a convolution are [c_out][c_in][k][k].
+ *  - Functions return asd_status; on failure no kernel has been launched and
+ *    asd_last_error() describes the reason.  Calls are asynchronous on the
+ *    given stream unless stated otherwise.  No call allocates device memory:
+ *    all device storage comes from the caller's workspace.
+ *  - One plan must not be used by two streams at once.
+ */
+#ifndef ASDUAL_H
+#define ASDUAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ASD_ABI_VERSION 1
+#define ASD_MAX_LAYERS 16
+#define ASD_MAX_MASKS 8 /* compile-time cap on K_max (active masks per layer) */
+
+typedef enum {
+    ASD_OK = 0,
+    ASD_EINVAL = 1,      /* invalid argument (shape, size, pointer, parameter) */
+    ASD_ENOMEM = 2,      /* workspace too small */
+    ASD_EDEVICE = 3,     /* a HIP runtime call failed */
+    ASD_EUNSUPPORTED = 4 /* valid request outside what this build supports */
+} asd_status;
+
+typedef enum { ASD_LAYER_DENSE = 0, ASD_LAYER_CONV2D = 1 } asd_layer_kind;
+
+/* One affine layer x_hat_k = W_k x_{k-1} + b_k (Sec. 2).  Every layer but the
+ * last is followed by a ReLU.  The last layer must be dense: its outputs are
+ * combined by per-subproblem objective rows c (the paper's alpha_n).
+ * DENSE : in_c = inputs, out_c = outputs, in_h = in_w = 1, kernel/stride/pad
+ *         ignored; W is [out_c][in_c] row-major.
+ * CONV2D: cross-correlation with zero padding, square kernel `kernel`,
+ *         same stride and padding in both directions; W is
+ *         [out_c][in_c][kernel][kernel], b is [out_c]; out_h/out_w must equal
+ *         (in + 2 pad - kernel) / stride + 1.
+ * The input shape of layer k+1 must equal the output shape of layer k
+ * (a dense layer after a convolution reads the (c, y, x) flattening). */
+typedef struct {
+    int32_t kind;
+    int32_t in_c, in_h, in_w;
+    int32_t out_c, out_h, out_w;
+    int32_t kernel, stride, pad;
+    const float* W; /* device, borrowed for the lifetime of the net */
+    const float* b; /* device, borrowed for the lifetime of the net */
+} asd_layer_desc;
+
+typedef struct asd_net asd_net;
+typedef struct asd_plan asd_plan;
+
+/* Copies the descriptors; W and b stay borrowed until asd_net_destroy.
+ * Errors: ASD_EINVAL for n_layers outside [2, ASD_MAX_LAYERS], shape
+ * mismatches between consecutive layers, a non-dense last layer, null
+ * pointers or non-positive sizes. */
+asd_status asd_net_create(const asd_layer_desc* layers /* host */, int32_t n_layers,
+                          asd_net** out /* host */);
+void asd_net_destroy(asd_net* net);
+
+/* Update rules for the dual step H of Algorithm 1 (Sec. 7.1 uses Adam). */
+typedef enum { ASD_RULE_ADAM = 0, ASD_RULE_SUPERGRADIENT = 1 } asd_rule;
+
+/* Solver schedule (Sec. 7.1; readings: additions at Active Set iterations t
+ * with t mod add_every < add_count while fewer than max_masks masks are
+ * active; learning rates decrease linearly from lr0 at t = 0 to lr1 at
+ * t = T - 1; Adam moments and step counters of alpha/beta_0/beta_1 are reset
+ * when the Active Set phase starts; each added multiplier has its own). */
+typedef struct {
+    int32_t bigm_iters;   /* T_M, Algorithm 3 iterations (>= 0) */
+    int32_t as_iters;     /* T, Algorithm 1 iterations (>= 0) */
+    int32_t add_every;    /* omega (>= 1) */
+    int32_t add_count;    /* V (>= 0) */
+    int32_t max_masks;    /* K_max in [0, ASD_MAX_MASKS] */
+    int32_t rule;         /* asd_rule */
+    float bigm_lr0, bigm_lr1;
+    float as_lr0, as_lr1;
+    float adam_beta1, adam_beta2, adam_eps;
+} asd_params;
+
+/* Fills the defaults of Sec. 7.1 for CIFAR-10 branch and bound:
+ * T_M = 180, T = 500, omega = 450, V = 2, K_max = 7, Adam (0.9, 0.999, 1e-8),
+ * Big-M lr 1e-2 -> 1e-4, Active Set lr 1e-3 -> 1e-6. (host pointer) */
+void asd_params_default(asd_params* p);
+
+/* The problem batch: S independent subproblems on one net.  Every pointer is
+ * device memory in the row-major [S][n] layout.
+ *   l0, u0   [S][n_0]   input box, l0 <= u0
+ *   lhat[k], uhat[k]    (k = 0 .. n_layers-2) [S][n_{k+1}] pre-activation
+ *            bounds of ReLU layer k+1 (App. E), lhat <= uhat
+ *   c        [S][n_last] objective rows: the bound is on c_s^T x_hat_n
+ * `lhat` and `uhat` are HOST arrays of device pointers. */
+typedef struct {
+    int32_t S;
+    const float* l0;
+    const float* u0;
+    const float* const* lhat; /* host array [n_layers-1] of device pointers */
+    const float* const* uhat; /* host array [n_layers-1] of device pointers */
+    const float* c;
+} asd_batch;
+
+/* Device workspace needed by a plan for S subproblems (host output).
+ * Errors: ASD_EINVAL for S < 1 or invalid params. */
+asd_status asd_plan_workspace_size(const asd_net* net, int32_t S, const asd_params* params,
+                                   size_t* bytes /* host */);
+
+/* Binds a caller-owned device workspace (>= asd_plan_workspace_size bytes,
+ * 256-byte aligned) to a plan for S subproblems.  The plan keeps the
+ * workspace until asd_plan_destroy.  Runs set-up kernels on `stream`
+ * (sign-split weights).  Errors: ASD_EINVAL, ASD_ENOMEM if too small. */
+asd_status asd_plan_create(const asd_net* net, int32_t S, const asd_params* params,
+                           void* workspace, size_t bytes, hipStream_t stream,
+                           asd_plan** out /* host */);
+void asd_plan_destroy(asd_plan* plan);
+
+/* Loads a batch into the plan (copies bounds into the plan's layout) and sets
+ * every dual to zero with no active masks: the interval-propagation start of
+ * Algorithm 3 (App. B).  Errors: ASD_EINVAL on S mismatch or null pointers. */
+asd_status asd_init(asd_plan* plan, const asd_batch* batch, hipStream_t stream);
+
+/* Phases of the solve. */
+typedef enum { ASD_PHASE_BIGM = 0, ASD_PHASE_AS = 1 } asd_phase;
+
+/* Runs iterations [t_begin, t_begin + n_iters) of one phase with the plan's
+ * schedule (Algorithm 3 for ASD_PHASE_BIGM, Algorithm 1's inner loop with
+ * active-set extension for ASD_PHASE_AS).  Starting the AS phase at
+ * t_begin = 0 resets the Adam state of alpha/beta_0/beta_1.  Errors:
+ * ASD_EINVAL if the range leaves [0, T) of the phase. */
+asd_status asd_run(asd_plan* plan, int32_t phase /* asd_phase */, int32_t t_begin, int32_t n_iters,
+                   hipStream_t stream);
+
+/* Dual objective at the current duals (eq:dual-active-set), evaluated in FP64
+ * from the FP32 duals and the FP32 weights, written to out_lb [S] (device,
+ * double).  If x0 is not NULL, writes the input-layer minimiser x*_0 [S][n_0]
+ * (device, float) at which the network can be evaluated for an upper bound
+ * (Sec. 6.2 footnote). */
+asd_status asd_bound(asd_plan* plan, double* out_lb, float* x0, hipStream_t stream);
+
+/* Whole solve: asd_init, T_M Big-M iterations, T Active Set iterations,
+ * asd_bound.  out_lb [S] device doubles. */
+asd_status asd_solve(asd_plan* plan, const asd_batch* batch, double* out_lb, float* x0,
+                     hipStream_t stream);
+
+/* ---- Inspection and warm start (duals are the whole solver state) ---- */
+
+/* State fields, per ReLU layer k = 1..n-1 and mask slot q (for ASD_F_MASK_*). */
+typedef enum {
+    ASD_F_ALPHA = 0, ASD_F_BETA0 = 1, ASD_F_BETA1 = 2,
+    ASD_F_ALPHA_M = 3, ASD_F_ALPHA_V = 4,
+    ASD_F_BETA0_M = 5, ASD_F_BETA0_V = 6,
+    ASD_F_BETA1_M = 7, ASD_F_BETA1_V = 8,
+    ASD_F_MASK_BETA = 9, ASD_F_MASK_M = 10, ASD_F_MASK_V = 11,
+    ASD_F_MASK_LI = 12, ASD_F_MASK_UI = 13,
+    /* the integral primal point the oracle was called at for slot q: z*_k of
+     * layer k (0/1 per neuron) and x*_{k-1} of layer k-1 (values) */
+    ASD_F_MASK_Z = 14, ASD_F_MASK_XPREV = 15
+} asd_field;
+
+/* Copies one field between the plan and a caller array [S][n] (float, device;
+ * n = n_k, or n_{k-1} for ASD_F_MASK_XPREV).  asd_state_set of ASD_F_MASK_Z /
+ * ASD_F_MASK_XPREV re-derives the slot's compact mask; ASD_F_MASK_LI/UI are
+ * recomputed by asd_state_set_counts (below) when `recompute` is set.
+ * Errors: ASD_EINVAL for k outside [1, n-1] or q outside [0, max_masks). */
+asd_status asd_state_get(asd_plan* plan, int32_t field, int32_t k, int32_t q, float* dst,
+                         hipStream_t stream);
+asd_status asd_state_set(asd_plan* plan, int32_t field, int32_t k, int32_t q, const float* src,
+                         hipStream_t stream);
+
+/* Scalar state: number of active masks per layer, the shared Adam step of
+ * alpha/beta and each slot's Adam step (host values). */
+typedef struct {
+    int32_t n_masks;
+    int32_t step;
+    int32_t mask_step[ASD_MAX_MASKS];
+} asd_counts;
+asd_status asd_state_get_counts(const asd_plan* plan, asd_counts* out /* host */);
+/* Sets the counts; with recompute != 0 also recomputes LI/UI of every active
+ * slot from its stored primal point (runs kernels on `stream`). */
+asd_status asd_state_set_counts(asd_plan* plan, const asd_counts* in /* host */, int32_t recompute,
+                                hipStream_t stream);
+
+/* ---- Fixed-dual evaluation and the separation oracle ---- */
+
+/* At the current duals and masks, computes with FP32 arithmetic:
+ *   obj [S] (device, double): d_B (sum accumulated in FP64),
+ *   xstar[k] (k = 0..n-1) [S][n_k] float: the minimiser x*_k (eq:as-primalk-min,
+ *            eq:as-primal0-min), zstar[k] (k = 1..n-1) [S][n_k] float 0/1,
+ *   grad[field][k] for ASD_F_ALPHA/BETA0/BETA1 and grad_mask[k][q]: the
+ *            supergradient (eq:as-supergradient) as [S][n_k] floats.
+ * Host arrays of device pointers; any entry may be NULL to skip it. */
+typedef struct {
+    double* obj;
+    float* xstar[ASD_MAX_LAYERS];
+    float* zstar[ASD_MAX_LAYERS];
+    float* grad_alpha[ASD_MAX_LAYERS];
+    float* grad_beta0[ASD_MAX_LAYERS];
+    float* grad_beta1[ASD_MAX_LAYERS];
+    float* grad_mask[ASD_MAX_LAYERS][ASD_MAX_MASKS];
+} asd_eval_out;
+asd_status asd_eval(asd_plan* plan, const asd_eval_out* out /* host */, hipStream_t stream);
+
+/* Separation oracle (Sec. 2.2, eq:oracle) for layer k at an arbitrary primal
+ * point: x_prev [S][n_{k-1}] in the box of layer k-1, z [S][n_k] in [0,1].
+ * Writes the mask bits over each neuron's receptive field (fan-in F_k
+ * entries per neuron in the order of the weights: dense j = 0..n_{k-1}-1;
+ * conv (c_in, ky, kx), padding taps reported as 0) packed 32 per word,
+ * mask_bits [S][n_k][ceil(F_k/32)] (uint32, bit t of word w is entry
+ * 32 w + t), and LI, UI [S][n_k] (the row sums of W.I.Lcheck and
+ * W.(1-I).Ucheck).  Uses the batch loaded by asd_init (bounds of layer k-1). */
+asd_status asd_oracle(asd_plan* plan, int32_t k, const float* x_prev, const float* z,
+                      uint32_t* mask_bits, float* LI, float* UI, hipStream_t stream);
+
+/* ---- Intermediate bounds (App. E; interval propagation) ---- */
+
+/* Pre-activation bounds of layers 1..n (FP64 arithmetic on the FP32 weights,
+ * rounded to FP32): lhat[k], uhat[k] (k = 0..n_layers-1) [S][n_{k+1}] device
+ * floats, host array of device pointers.  l0, u0 [S][n_0]. */
+asd_status asd_interval_bounds(const asd_net* net, int32_t S, const float* l0, const float* u0,
+                               float* const* lhat, float* const* uhat, hipStream_t stream);
+
+/* ---- Kernel timing (for the benchmark's roofline figures) ---- */
+
+/* Kernels the library launches in the iteration, by role. */
+typedef enum {
+    ASD_K_BACKWARD = 0,   /* f_k, inner minimisation (FP32) */
+    ASD_K_FORWARD = 1,    /* products, supergradient, update */
+    ASD_K_MASK = 2,       /* active-set extension */
+    ASD_K_FINAL = 3,      /* FP64 final bound (all its kernels) */
+    ASD_K_OTHER = 4,
+    ASD_K_COUNT = 5
+} asd_kernel_role;
+
+typedef struct {
+    int32_t role;       /* asd_kernel_role */
+    int32_t layer;      /* layer index the launch works on (neuron layer for backward) */
+    int32_t launches;
+    double total_ms;    /* sum of HIP-event durations on the launch stream */
+} asd_kernel_time;
+
+/* Starts (enable = 1) or stops recording a HIP event pair around every kernel
+ * launch of this plan, on the launch stream.  Enabling clears earlier
+ * records.  Recording adds host work per launch; time runs without it. */
+asd_status asd_profile_enable(asd_plan* plan, int32_t enable);
+/* Waits for the recorded events and writes per (role, layer) sums (host
+ * array of `cap` entries); *count receives the number of entries. */
+asd_status asd_profile_read(asd_plan* plan, asd_kernel_time* out /* host */, int32_t cap,
+                            int32_t* count /* host */);
+
+/* Thread-local description of the last error (never NULL). */
+const char* asd_last_error(void);
+int32_t asd_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ASDUAL_H */

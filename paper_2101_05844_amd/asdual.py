@@ -1,0 +1,348 @@
+"""Python binding of libasdual (ctypes; argument marshalling only).
+
+Every computation runs in the HIP library; this module passes device
+pointers of torch tensors and the current HIP stream.  It refuses to work
+without the built library (no fallback of any kind).
+
+Function names follow the C ABI in include/asdual.h.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+import torch  # must be imported before the library so both share one HIP runtime
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libasdual.so")
+
+ASD_MAX_LAYERS = 16
+ASD_MAX_MASKS = 8
+ASD_LAYER_DENSE, ASD_LAYER_CONV2D = 0, 1
+ASD_RULE_ADAM, ASD_RULE_SUPERGRADIENT = 0, 1
+ASD_PHASE_BIGM, ASD_PHASE_AS = 0, 1
+(ASD_F_ALPHA, ASD_F_BETA0, ASD_F_BETA1, ASD_F_ALPHA_M, ASD_F_ALPHA_V, ASD_F_BETA0_M, ASD_F_BETA0_V,
+ ASD_F_BETA1_M, ASD_F_BETA1_V, ASD_F_MASK_BETA, ASD_F_MASK_M, ASD_F_MASK_V, ASD_F_MASK_LI,
+ ASD_F_MASK_UI, ASD_F_MASK_Z, ASD_F_MASK_XPREV) = range(16)
+
+STATUS = {0: "ASD_OK", 1: "ASD_EINVAL", 2: "ASD_ENOMEM", 3: "ASD_EDEVICE", 4: "ASD_EUNSUPPORTED"}
+
+
+class AsdError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class LayerDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("in_c", C.c_int32), ("in_h", C.c_int32), ("in_w", C.c_int32),
+                ("out_c", C.c_int32), ("out_h", C.c_int32), ("out_w", C.c_int32),
+                ("kernel", C.c_int32), ("stride", C.c_int32), ("pad", C.c_int32),
+                ("W", C.c_void_p), ("b", C.c_void_p)]
+
+
+class Params(C.Structure):
+    _fields_ = [("bigm_iters", C.c_int32), ("as_iters", C.c_int32), ("add_every", C.c_int32),
+                ("add_count", C.c_int32), ("max_masks", C.c_int32), ("rule", C.c_int32),
+                ("bigm_lr0", C.c_float), ("bigm_lr1", C.c_float), ("as_lr0", C.c_float),
+                ("as_lr1", C.c_float), ("adam_beta1", C.c_float), ("adam_beta2", C.c_float),
+                ("adam_eps", C.c_float)]
+
+
+class Batch(C.Structure):
+    _fields_ = [("S", C.c_int32), ("l0", C.c_void_p), ("u0", C.c_void_p),
+                ("lhat", C.POINTER(C.c_void_p)), ("uhat", C.POINTER(C.c_void_p)), ("c", C.c_void_p)]
+
+
+class Counts(C.Structure):
+    _fields_ = [("n_masks", C.c_int32), ("step", C.c_int32), ("mask_step", C.c_int32 * ASD_MAX_MASKS)]
+
+
+class KernelTime(C.Structure):
+    _fields_ = [("role", C.c_int32), ("layer", C.c_int32), ("launches", C.c_int32),
+                ("total_ms", C.c_double)]
+
+
+ASD_K_BACKWARD, ASD_K_FORWARD, ASD_K_MASK, ASD_K_FINAL, ASD_K_OTHER = range(5)
+ROLE_NAMES = {0: "backward", 1: "forward", 2: "mask", 3: "final", 4: "other"}
+
+
+class EvalOut(C.Structure):
+    _fields_ = [("obj", C.c_void_p),
+                ("xstar", C.c_void_p * ASD_MAX_LAYERS),
+                ("zstar", C.c_void_p * ASD_MAX_LAYERS),
+                ("grad_alpha", C.c_void_p * ASD_MAX_LAYERS),
+                ("grad_beta0", C.c_void_p * ASD_MAX_LAYERS),
+                ("grad_beta1", C.c_void_p * ASD_MAX_LAYERS),
+                ("grad_mask", (C.c_void_p * ASD_MAX_MASKS) * ASD_MAX_LAYERS)]
+
+
+_lib = None
+
+EXPORTED = ["asd_net_create", "asd_net_destroy", "asd_params_default", "asd_plan_workspace_size",
+            "asd_plan_create", "asd_plan_destroy", "asd_init", "asd_run", "asd_bound", "asd_solve",
+            "asd_state_get", "asd_state_set", "asd_state_get_counts", "asd_state_set_counts",
+            "asd_eval", "asd_oracle", "asd_interval_bounds", "asd_profile_enable", "asd_profile_read",
+            "asd_last_error", "asd_abi_version"]
+
+
+def lib():
+    """Loads libasdual.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2101_05844_amd.build` "
+                           "(there is no fallback implementation)")
+    L = C.CDLL(LIB_PATH)
+    vp, i32 = C.c_void_p, C.c_int32
+    L.asd_net_create.argtypes = [C.POINTER(LayerDesc), i32, C.POINTER(vp)]
+    L.asd_net_destroy.argtypes = [vp]
+    L.asd_net_destroy.restype = None
+    L.asd_params_default.argtypes = [C.POINTER(Params)]
+    L.asd_params_default.restype = None
+    L.asd_plan_workspace_size.argtypes = [vp, i32, C.POINTER(Params), C.POINTER(C.c_size_t)]
+    L.asd_plan_create.argtypes = [vp, i32, C.POINTER(Params), vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.asd_plan_destroy.argtypes = [vp]
+    L.asd_plan_destroy.restype = None
+    L.asd_init.argtypes = [vp, C.POINTER(Batch), vp]
+    L.asd_run.argtypes = [vp, i32, i32, i32, vp]
+    L.asd_bound.argtypes = [vp, vp, vp, vp]
+    L.asd_solve.argtypes = [vp, C.POINTER(Batch), vp, vp, vp]
+    L.asd_state_get.argtypes = [vp, i32, i32, i32, vp, vp]
+    L.asd_state_set.argtypes = [vp, i32, i32, i32, vp, vp]
+    L.asd_state_get_counts.argtypes = [vp, C.POINTER(Counts)]
+    L.asd_state_set_counts.argtypes = [vp, C.POINTER(Counts), i32, vp]
+    L.asd_eval.argtypes = [vp, C.POINTER(EvalOut), vp]
+    L.asd_oracle.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+    L.asd_interval_bounds.argtypes = [vp, i32, vp, vp, C.POINTER(vp), C.POINTER(vp), vp]
+    L.asd_profile_enable.argtypes = [vp, i32]
+    L.asd_profile_read.argtypes = [vp, C.POINTER(KernelTime), i32, C.POINTER(i32)]
+    L.asd_last_error.argtypes = []
+    L.asd_last_error.restype = C.c_char_p
+    L.asd_abi_version.argtypes = []
+    L.asd_abi_version.restype = i32
+    for name in EXPORTED:
+        if name not in ("asd_net_destroy", "asd_params_default", "asd_plan_destroy", "asd_last_error",
+                        "asd_abi_version"):
+            getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != 0:
+        raise AsdError(status, lib().asd_last_error().decode())
+
+
+def _stream(stream=None) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA/HIP tensors"
+    return t.data_ptr()
+
+
+# ----------------------------------------------------------------------------
+# Thin wrappers with the C names
+# ----------------------------------------------------------------------------
+
+
+def asd_params_default() -> Params:
+    p = Params()
+    lib().asd_params_default(C.byref(p))
+    return p
+
+
+def params_from_schedule(s) -> Params:
+    p = asd_params_default()
+    p.bigm_iters, p.as_iters = s.bigm_iters, s.as_iters
+    p.add_every, p.add_count, p.max_masks = s.add_every, s.add_count, s.max_masks
+    p.bigm_lr0, p.bigm_lr1 = s.bigm_lr
+    p.as_lr0, p.as_lr1 = s.as_lr
+    p.adam_beta1, p.adam_beta2, p.adam_eps = s.adam_beta1, s.adam_beta2, s.adam_eps
+    return p
+
+
+class Net:
+    """Device copy of a network's FP32 weights plus the library's net handle."""
+
+    def __init__(self, layers, device="cuda"):
+        self.layers = layers
+        self.W = [torch.as_tensor(np.ascontiguousarray(L.W), device=device) for L in layers]
+        self.b = [torch.as_tensor(np.ascontiguousarray(L.b), device=device) for L in layers]
+        descs = (LayerDesc * len(layers))()
+        for i, L in enumerate(layers):
+            d = descs[i]
+            sp = L.spec
+            if L.kind == "dense":
+                d.kind, d.in_c, d.in_h, d.in_w = ASD_LAYER_DENSE, sp.n_in, 1, 1
+                d.out_c, d.out_h, d.out_w = sp.n_out, 1, 1
+                d.kernel, d.stride, d.pad = 1, 1, 0
+            else:
+                d.kind, d.in_c, d.in_h, d.in_w = ASD_LAYER_CONV2D, sp.c_in, sp.h_in, sp.w_in
+                d.out_c, d.out_h, d.out_w = sp.c_out, sp.h_out, sp.w_out
+                d.kernel, d.stride, d.pad = sp.k, sp.stride, sp.pad
+            d.W, d.b = self.W[i].data_ptr(), self.b[i].data_ptr()
+        h = C.c_void_p()
+        _check(lib().asd_net_create(descs, len(layers), C.byref(h)))
+        self.handle = h
+        self.n = len(layers)
+        self.sizes = [layers[0].n_in] + [L.n_out for L in layers]
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.asd_net_destroy(self.handle)
+            self.handle = None
+
+    def interval_bounds(self, l0: torch.Tensor, u0: torch.Tensor, stream=None):
+        """asd_interval_bounds: pre-activation bounds of layers 1..n."""
+        S = l0.shape[0]
+        lh = [torch.empty(S, n, device=l0.device, dtype=torch.float32) for n in self.sizes[1:]]
+        uh = [torch.empty_like(t) for t in lh]
+        lp = (C.c_void_p * self.n)(*[t.data_ptr() for t in lh])
+        up = (C.c_void_p * self.n)(*[t.data_ptr() for t in uh])
+        _check(lib().asd_interval_bounds(self.handle, S, _ptr(l0), _ptr(u0), lp, up, _stream(stream)))
+        return lh, uh
+
+
+class Plan:
+    """A plan for S subproblems with its workspace (a torch uint8 tensor)."""
+
+    def __init__(self, net: Net, S: int, params: Params, stream=None):
+        self.net, self.S, self.params = net, S, params
+        nbytes = C.c_size_t()
+        _check(lib().asd_plan_workspace_size(net.handle, S, C.byref(params), C.byref(nbytes)))
+        self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device="cuda")
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        h = C.c_void_p()
+        _check(lib().asd_plan_create(net.handle, S, C.byref(params), aligned, nbytes.value,
+                                     _stream(stream), C.byref(h)))
+        self.handle = h
+        self._keep = None
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.asd_plan_destroy(self.handle)
+            self.handle = None
+
+    # -- batch ---------------------------------------------------------------
+    def init(self, l0, u0, lhat: Sequence[torch.Tensor], uhat: Sequence[torch.Tensor], c, stream=None):
+        """asd_init.  All tensors float32 on the device, [S][n] row-major."""
+        lh = (C.c_void_p * max(1, len(lhat)))(*[_ptr(t) for t in lhat])
+        uh = (C.c_void_p * max(1, len(uhat)))(*[_ptr(t) for t in uhat])
+        b = Batch(self.S, _ptr(l0), _ptr(u0), C.cast(lh, C.POINTER(C.c_void_p)),
+                  C.cast(uh, C.POINTER(C.c_void_p)), _ptr(c))
+        self._keep = (l0, u0, list(lhat), list(uhat), c)
+        _check(lib().asd_init(self.handle, C.byref(b), _stream(stream)))
+
+    def run(self, phase: int, t_begin: int, n_iters: int, stream=None):
+        _check(lib().asd_run(self.handle, phase, t_begin, n_iters, _stream(stream)))
+
+    def bound(self, want_x0: bool = False, stream=None):
+        out = torch.empty(self.S, dtype=torch.float64, device="cuda")
+        x0 = torch.empty(self.S, self.net.sizes[0], dtype=torch.float32, device="cuda") if want_x0 else None
+        _check(lib().asd_bound(self.handle, out.data_ptr(), _ptr(x0), _stream(stream)))
+        return (out, x0) if want_x0 else out
+
+    def solve(self, l0, u0, lhat, uhat, c, want_x0: bool = False, stream=None):
+        self.init(l0, u0, lhat, uhat, c, stream)
+        self.run(ASD_PHASE_BIGM, 0, self.params.bigm_iters, stream)
+        self.run(ASD_PHASE_AS, 0, self.params.as_iters, stream)
+        return self.bound(want_x0, stream)
+
+    # -- state ---------------------------------------------------------------
+    def _n(self, field, k):
+        return self.net.sizes[k - 1] if field == ASD_F_MASK_XPREV else self.net.sizes[k]
+
+    def get(self, field: int, k: int, q: int = 0, stream=None) -> torch.Tensor:
+        dst = torch.empty(self.S, self._n(field, k), dtype=torch.float32, device="cuda")
+        _check(lib().asd_state_get(self.handle, field, k, q, dst.data_ptr(), _stream(stream)))
+        return dst
+
+    def set(self, field: int, k: int, src: torch.Tensor, q: int = 0, stream=None):
+        src = src.to(device="cuda", dtype=torch.float32).contiguous()
+        assert tuple(src.shape) == (self.S, self._n(field, k))
+        _check(lib().asd_state_set(self.handle, field, k, q, src.data_ptr(), _stream(stream)))
+        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+
+    def counts(self) -> Counts:
+        c = Counts()
+        _check(lib().asd_state_get_counts(self.handle, C.byref(c)))
+        return c
+
+    def set_counts(self, n_masks: int, step: int, mask_step: Sequence[int], recompute: bool = True,
+                   stream=None):
+        c = Counts()
+        c.n_masks, c.step = n_masks, step
+        for q, v in enumerate(mask_step):
+            c.mask_step[q] = v
+        _check(lib().asd_state_set_counts(self.handle, C.byref(c), int(recompute), _stream(stream)))
+
+    # -- evaluation ----------------------------------------------------------
+    def eval(self, stream=None) -> Dict:
+        """asd_eval at the current duals: objective, x*, z*, supergradient."""
+        n, S, sizes = self.net.n, self.S, self.net.sizes
+        K = self.counts().n_masks
+        out = EvalOut()
+        res = {"obj": torch.empty(S, dtype=torch.float64, device="cuda"),
+               "x": [torch.empty(S, sizes[k], device="cuda") for k in range(n)],
+               "z": [None] + [torch.empty(S, sizes[k], device="cuda") for k in range(1, n)],
+               "ga": [None] + [torch.empty(S, sizes[k], device="cuda") for k in range(1, n)],
+               "gb0": [None] + [torch.empty(S, sizes[k], device="cuda") for k in range(1, n)],
+               "gb1": [None] + [torch.empty(S, sizes[k], device="cuda") for k in range(1, n)],
+               "gm": [None] + [[torch.empty(S, sizes[k], device="cuda") for _ in range(K)]
+                               for k in range(1, n)]}
+        out.obj = res["obj"].data_ptr()
+        for k in range(n):
+            out.xstar[k] = res["x"][k].data_ptr()
+            if k >= 1:
+                out.zstar[k] = res["z"][k].data_ptr()
+                out.grad_alpha[k] = res["ga"][k].data_ptr()
+                out.grad_beta0[k] = res["gb0"][k].data_ptr()
+                out.grad_beta1[k] = res["gb1"][k].data_ptr()
+                for q in range(K):
+                    out.grad_mask[k][q] = res["gm"][k][q].data_ptr()
+        _check(lib().asd_eval(self.handle, C.byref(out), _stream(stream)))
+        return res
+
+    def profile(self, enable: bool):
+        """asd_profile_enable: HIP-event pairs around every launch of this plan."""
+        _check(lib().asd_profile_enable(self.handle, int(enable)))
+
+    def profile_read(self):
+        """asd_profile_read: {(role, layer): (launches, total_ms)}."""
+        cap = 256
+        arr = (KernelTime * cap)()
+        n = C.c_int32()
+        _check(lib().asd_profile_read(self.handle, arr, cap, C.byref(n)))
+        return {(ROLE_NAMES[arr[i].role], arr[i].layer): (arr[i].launches, arr[i].total_ms)
+                for i in range(min(n.value, cap))}
+
+    def oracle(self, k: int, x_prev: torch.Tensor, z: torch.Tensor, stream=None):
+        """asd_oracle: explicit mask bits over each neuron's receptive field, LI, UI."""
+        L = self.net.layers[k - 1]
+        fan = L.spec.n_in if L.kind == "dense" else L.spec.c_in * L.spec.k * L.spec.k
+        nw = (fan + 31) // 32
+        n = self.net.sizes[k]
+        bits = torch.empty(self.S, n, nw, dtype=torch.int32, device="cuda")
+        LI = torch.empty(self.S, n, device="cuda")
+        UI = torch.empty(self.S, n, device="cuda")
+        _check(lib().asd_oracle(self.handle, k, _ptr(x_prev.contiguous()), _ptr(z.contiguous()),
+                                bits.data_ptr(), LI.data_ptr(), UI.data_ptr(), _stream(stream)))
+        return bits, LI, UI, fan
+
+
+def unpack_bits(bits: np.ndarray, fan: int) -> np.ndarray:
+    """[..., nw] uint32 words -> [..., fan] bool (bit t of word w = entry 32 w + t)."""
+    b = np.asarray(bits).astype(np.uint32)
+    shifts = np.arange(32, dtype=np.uint32)
+    out = ((b[..., :, None] >> shifts) & 1).astype(bool)
+    return out.reshape(*b.shape[:-1], -1)[..., :fan]

@@ -196,22 +196,27 @@ def select_fixes(draws: FixDraws, ambiguous: np.ndarray, s: int):
 
 def subdomain_bounds(root_lhat: Sequence[np.ndarray], root_uhat: Sequence[np.ndarray],
                      draws: Optional[FixDraws], S: int):
-    """Per-subdomain pre-activation bounds [S, n_k] from root bounds [n_k].
+    """Per-subdomain pre-activation bounds [S, n_k] from root bounds.
 
-    A branch-and-bound split fixes a ReLU's phase: passing sets the lower
-    pre-activation bound to 0, blocking sets the upper one to 0 (Sec. 7.3,
-    BaBSR splits a ReLU into its two phases).  The other bounds stay as they
-    are at the root, which remains valid on the subdomain.
+    Root bounds are [n_k] (one root shared by all subdomains) or [S, n_k]
+    (one root per subproblem).  A branch-and-bound split fixes a ReLU's phase:
+    passing sets the lower pre-activation bound to 0, blocking sets the upper
+    one to 0 (Sec. 7.3: BaBSR splits a ReLU into its two phases).  The other
+    bounds stay as they are at the root, which remains valid on the subdomain.
     """
-    lh = [np.repeat(np.asarray(a, np.float32)[None, :], S, axis=0) for a in root_lhat]
-    uh = [np.repeat(np.asarray(a, np.float32)[None, :], S, axis=0) for a in root_uhat]
+    def per_s(a):
+        a = np.asarray(a, np.float32)
+        return np.repeat(a[None, :], S, axis=0) if a.ndim == 1 else a.copy()
+
+    lh = [per_s(a) for a in root_lhat]
+    uh = [per_s(a) for a in root_uhat]
     if draws is None:
         return lh, uh
-    flat_l = np.concatenate([np.asarray(a) for a in root_lhat])
-    flat_u = np.concatenate([np.asarray(a) for a in root_uhat])
-    ambiguous = (flat_l < 0) & (flat_u > 0)
-    offs = np.cumsum([0] + [len(a) for a in root_lhat])
+    offs = np.cumsum([0] + [a.shape[1] for a in lh])
     for s in range(S):
+        flat_l = np.concatenate([a[s] for a in lh])
+        flat_u = np.concatenate([a[s] for a in uh])
+        ambiguous = (flat_l < 0) & (flat_u > 0)
         idx, ph = select_fixes(draws, ambiguous, s)
         for r, p in zip(idx, ph):
             k = int(np.searchsorted(offs, r, side="right") - 1)

@@ -86,6 +86,13 @@ void asd_net_destroy(asd_net* net);
 /* Update rules for the dual step H of Algorithm 1 (Sec. 7.1 uses Adam). */
 typedef enum { ASD_RULE_ADAM = 0, ASD_RULE_SUPERGRADIENT = 1 } asd_rule;
 
+/* Precision of a plan's state and arithmetic.  ASD_PREC_FP32 is the
+ * production form (FP32 duals, moments and sums; the final bound is
+ * re-evaluated in FP64).  ASD_PREC_FP64 keeps everything in FP64 (twice the
+ * memory and traffic); it exists to compare whole runs with an FP64
+ * reference.  Network weights and batch inputs are FP32 in both. */
+typedef enum { ASD_PREC_FP32 = 0, ASD_PREC_FP64 = 1 } asd_precision;
+
 /* Solver schedule (Sec. 7.1; readings: additions at Active Set iterations t
  * with t mod add_every < add_count while fewer than max_masks masks are
  * active; learning rates decrease linearly from lr0 at t = 0 to lr1 at
@@ -98,14 +105,15 @@ typedef struct {
     int32_t add_count;    /* V (>= 0) */
     int32_t max_masks;    /* K_max in [0, ASD_MAX_MASKS] */
     int32_t rule;         /* asd_rule */
-    float bigm_lr0, bigm_lr1;
-    float as_lr0, as_lr1;
-    float adam_beta1, adam_beta2, adam_eps;
+    double bigm_lr0, bigm_lr1;
+    double as_lr0, as_lr1;
+    double adam_beta1, adam_beta2, adam_eps;
+    int32_t precision;    /* asd_precision */
 } asd_params;
 
 /* Fills the defaults of Sec. 7.1 for CIFAR-10 branch and bound:
  * T_M = 180, T = 500, omega = 450, V = 2, K_max = 7, Adam (0.9, 0.999, 1e-8),
- * Big-M lr 1e-2 -> 1e-4, Active Set lr 1e-3 -> 1e-6. (host pointer) */
+ * Big-M lr 1e-2 -> 1e-4, Active Set lr 1e-3 -> 1e-6, FP32. (host pointer) */
 void asd_params_default(asd_params* p);
 
 /* The problem batch: S independent subproblems on one net.  Every pointer is
@@ -181,14 +189,15 @@ typedef enum {
     ASD_F_MASK_Z = 14, ASD_F_MASK_XPREV = 15
 } asd_field;
 
-/* Copies one field between the plan and a caller array [S][n] (float, device;
- * n = n_k, or n_{k-1} for ASD_F_MASK_XPREV).  asd_state_set of ASD_F_MASK_Z /
+/* Copies one field between the plan and a caller array [S][n] (device; float
+ * for an FP32 plan, double for an FP64 plan; n = n_k, or n_{k-1} for
+ * ASD_F_MASK_XPREV).  asd_state_set of ASD_F_MASK_Z /
  * ASD_F_MASK_XPREV re-derives the slot's compact mask; ASD_F_MASK_LI/UI are
  * recomputed by asd_state_set_counts (below) when `recompute` is set.
  * Errors: ASD_EINVAL for k outside [1, n-1] or q outside [0, max_masks). */
-asd_status asd_state_get(asd_plan* plan, int32_t field, int32_t k, int32_t q, float* dst,
+asd_status asd_state_get(asd_plan* plan, int32_t field, int32_t k, int32_t q, void* dst,
                          hipStream_t stream);
-asd_status asd_state_set(asd_plan* plan, int32_t field, int32_t k, int32_t q, const float* src,
+asd_status asd_state_set(asd_plan* plan, int32_t field, int32_t k, int32_t q, const void* src,
                          hipStream_t stream);
 
 /* Scalar state: number of active masks per layer, the shared Adam step of
@@ -206,34 +215,36 @@ asd_status asd_state_set_counts(asd_plan* plan, const asd_counts* in /* host */,
 
 /* ---- Fixed-dual evaluation and the separation oracle ---- */
 
-/* At the current duals and masks, computes with FP32 arithmetic:
+/* At the current duals and masks, computes with the plan's arithmetic:
  *   obj [S] (device, double): d_B (sum accumulated in FP64),
- *   xstar[k] (k = 0..n-1) [S][n_k] float: the minimiser x*_k (eq:as-primalk-min,
- *            eq:as-primal0-min), zstar[k] (k = 1..n-1) [S][n_k] float 0/1,
- *   grad[field][k] for ASD_F_ALPHA/BETA0/BETA1 and grad_mask[k][q]: the
- *            supergradient (eq:as-supergradient) as [S][n_k] floats.
- * Host arrays of device pointers; any entry may be NULL to skip it. */
+ *   xstar[k] (k = 0..n-1) [S][n_k]: the minimiser x*_k (eq:as-primalk-min,
+ *            eq:as-primal0-min), zstar[k] (k = 1..n-1) [S][n_k] 0/1 values,
+ *   grad_*[k] and grad_mask[k][q]: the supergradient (eq:as-supergradient)
+ *            as [S][n_k] arrays.
+ * Arrays are float for an FP32 plan and double for an FP64 plan.  Host arrays
+ * of device pointers; any entry may be NULL to skip it. */
 typedef struct {
     double* obj;
-    float* xstar[ASD_MAX_LAYERS];
-    float* zstar[ASD_MAX_LAYERS];
-    float* grad_alpha[ASD_MAX_LAYERS];
-    float* grad_beta0[ASD_MAX_LAYERS];
-    float* grad_beta1[ASD_MAX_LAYERS];
-    float* grad_mask[ASD_MAX_LAYERS][ASD_MAX_MASKS];
+    void* xstar[ASD_MAX_LAYERS];
+    void* zstar[ASD_MAX_LAYERS];
+    void* grad_alpha[ASD_MAX_LAYERS];
+    void* grad_beta0[ASD_MAX_LAYERS];
+    void* grad_beta1[ASD_MAX_LAYERS];
+    void* grad_mask[ASD_MAX_LAYERS][ASD_MAX_MASKS];
 } asd_eval_out;
 asd_status asd_eval(asd_plan* plan, const asd_eval_out* out /* host */, hipStream_t stream);
 
 /* Separation oracle (Sec. 2.2, eq:oracle) for layer k at an arbitrary primal
- * point: x_prev [S][n_{k-1}] in the box of layer k-1, z [S][n_k] in [0,1].
+ * point: x_prev [S][n_{k-1}] in the box of layer k-1, z [S][n_k] in [0,1]
+ * (x_prev, z, LI, UI are float for an FP32 plan, double for an FP64 plan).
  * Writes the mask bits over each neuron's receptive field (fan-in F_k
  * entries per neuron in the order of the weights: dense j = 0..n_{k-1}-1;
  * conv (c_in, ky, kx), padding taps reported as 0) packed 32 per word,
  * mask_bits [S][n_k][ceil(F_k/32)] (uint32, bit t of word w is entry
  * 32 w + t), and LI, UI [S][n_k] (the row sums of W.I.Lcheck and
  * W.(1-I).Ucheck).  Uses the batch loaded by asd_init (bounds of layer k-1). */
-asd_status asd_oracle(asd_plan* plan, int32_t k, const float* x_prev, const float* z,
-                      uint32_t* mask_bits, float* LI, float* UI, hipStream_t stream);
+asd_status asd_oracle(asd_plan* plan, int32_t k, const void* x_prev, const void* z,
+                      uint32_t* mask_bits, void* LI, void* UI, hipStream_t stream);
 
 /* ---- Intermediate bounds (App. E; interval propagation) ---- */
 

@@ -22,6 +22,7 @@ ASD_MAX_LAYERS = 16
 ASD_MAX_MASKS = 8
 ASD_LAYER_DENSE, ASD_LAYER_CONV2D = 0, 1
 ASD_RULE_ADAM, ASD_RULE_SUPERGRADIENT = 0, 1
+ASD_PREC_FP32, ASD_PREC_FP64 = 0, 1
 ASD_PHASE_BIGM, ASD_PHASE_AS = 0, 1
 (ASD_F_ALPHA, ASD_F_BETA0, ASD_F_BETA1, ASD_F_ALPHA_M, ASD_F_ALPHA_V, ASD_F_BETA0_M, ASD_F_BETA0_V,
  ASD_F_BETA1_M, ASD_F_BETA1_V, ASD_F_MASK_BETA, ASD_F_MASK_M, ASD_F_MASK_V, ASD_F_MASK_LI,
@@ -46,9 +47,9 @@ class LayerDesc(C.Structure):
 class Params(C.Structure):
     _fields_ = [("bigm_iters", C.c_int32), ("as_iters", C.c_int32), ("add_every", C.c_int32),
                 ("add_count", C.c_int32), ("max_masks", C.c_int32), ("rule", C.c_int32),
-                ("bigm_lr0", C.c_float), ("bigm_lr1", C.c_float), ("as_lr0", C.c_float),
-                ("as_lr1", C.c_float), ("adam_beta1", C.c_float), ("adam_beta2", C.c_float),
-                ("adam_eps", C.c_float)]
+                ("bigm_lr0", C.c_double), ("bigm_lr1", C.c_double), ("as_lr0", C.c_double),
+                ("as_lr1", C.c_double), ("adam_beta1", C.c_double), ("adam_beta2", C.c_double),
+                ("adam_eps", C.c_double), ("precision", C.c_int32)]
 
 
 class Batch(C.Structure):
@@ -160,8 +161,9 @@ def asd_params_default() -> Params:
     return p
 
 
-def params_from_schedule(s) -> Params:
+def params_from_schedule(s, precision: int = ASD_PREC_FP32) -> Params:
     p = asd_params_default()
+    p.precision = precision
     p.bigm_iters, p.as_iters = s.bigm_iters, s.as_iters
     p.add_every, p.add_count, p.max_masks = s.add_every, s.add_count, s.max_masks
     p.bigm_lr0, p.bigm_lr1 = s.bigm_lr
@@ -217,6 +219,7 @@ class Plan:
 
     def __init__(self, net: Net, S: int, params: Params, stream=None):
         self.net, self.S, self.params = net, S, params
+        self.dtype = torch.float64 if params.precision == ASD_PREC_FP64 else torch.float32
         nbytes = C.c_size_t()
         _check(lib().asd_plan_workspace_size(net.handle, S, C.byref(params), C.byref(nbytes)))
         self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device="cuda")
@@ -263,12 +266,12 @@ class Plan:
         return self.net.sizes[k - 1] if field == ASD_F_MASK_XPREV else self.net.sizes[k]
 
     def get(self, field: int, k: int, q: int = 0, stream=None) -> torch.Tensor:
-        dst = torch.empty(self.S, self._n(field, k), dtype=torch.float32, device="cuda")
+        dst = torch.empty(self.S, self._n(field, k), dtype=self.dtype, device="cuda")
         _check(lib().asd_state_get(self.handle, field, k, q, dst.data_ptr(), _stream(stream)))
         return dst
 
     def set(self, field: int, k: int, src: torch.Tensor, q: int = 0, stream=None):
-        src = src.to(device="cuda", dtype=torch.float32).contiguous()
+        src = src.to(device="cuda", dtype=self.dtype).contiguous()
         assert tuple(src.shape) == (self.S, self._n(field, k))
         _check(lib().asd_state_set(self.handle, field, k, q, src.data_ptr(), _stream(stream)))
         torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
@@ -292,14 +295,14 @@ class Plan:
         n, S, sizes = self.net.n, self.S, self.net.sizes
         K = self.counts().n_masks
         out = EvalOut()
+        E = lambda k: torch.empty(S, sizes[k], device="cuda", dtype=self.dtype)
         res = {"obj": torch.empty(S, dtype=torch.float64, device="cuda"),
-               "x": [torch.empty(S, sizes[k], device="cuda") for k in range(n)],
-               "z": [None] + [torch.empty(S, sizes[k], device="cuda") for k in range(1, n)],
-               "ga": [None] + [torch.empty(S, sizes[k], device="cuda") for k in range(1, n)],
-               "gb0": [None] + [torch.empty(S, sizes[k], device="cuda") for k in range(1, n)],
-               "gb1": [None] + [torch.empty(S, sizes[k], device="cuda") for k in range(1, n)],
-               "gm": [None] + [[torch.empty(S, sizes[k], device="cuda") for _ in range(K)]
-                               for k in range(1, n)]}
+               "x": [E(k) for k in range(n)],
+               "z": [None] + [E(k) for k in range(1, n)],
+               "ga": [None] + [E(k) for k in range(1, n)],
+               "gb0": [None] + [E(k) for k in range(1, n)],
+               "gb1": [None] + [E(k) for k in range(1, n)],
+               "gm": [None] + [[E(k) for _ in range(K)] for k in range(1, n)]}
         out.obj = res["obj"].data_ptr()
         for k in range(n):
             out.xstar[k] = res["x"][k].data_ptr()
@@ -333,9 +336,11 @@ class Plan:
         nw = (fan + 31) // 32
         n = self.net.sizes[k]
         bits = torch.empty(self.S, n, nw, dtype=torch.int32, device="cuda")
-        LI = torch.empty(self.S, n, device="cuda")
-        UI = torch.empty(self.S, n, device="cuda")
-        _check(lib().asd_oracle(self.handle, k, _ptr(x_prev.contiguous()), _ptr(z.contiguous()),
+        LI = torch.empty(self.S, n, device="cuda", dtype=self.dtype)
+        UI = torch.empty(self.S, n, device="cuda", dtype=self.dtype)
+        x_prev = x_prev.to(self.dtype).contiguous()
+        z = z.to(self.dtype).contiguous()
+        _check(lib().asd_oracle(self.handle, k, _ptr(x_prev), _ptr(z),
                                 bits.data_ptr(), LI.data_ptr(), UI.data_ptr(), _stream(stream)))
         return bits, LI, UI, fan
 

@@ -9,6 +9,7 @@
 
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "asd_kernels.h"
@@ -43,6 +44,12 @@ asd_status fail(asd_status st, const char* fmt, ...) {
             return fail(ASD_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e_)); \
     } while (0)
 
+#define TRY(expr)                      \
+    do {                               \
+        asd_status s_ = (expr);        \
+        if (s_ != ASD_OK) return s_;   \
+    } while (0)
+
 NeuronLayout make_layout(int C, int H, int W, int S) {
     NeuronLayout nl;
     nl.C = C;
@@ -56,16 +63,16 @@ NeuronLayout make_layout(int C, int H, int W, int S) {
     return nl;
 }
 
+struct ProfRec {
+    int role, layer;
+    hipEvent_t a, b;
+};
+
 }  // namespace
 
 struct asd_net {
     int n;  // layers
     std::vector<asd_layer_desc> L;
-};
-
-struct ProfRec {
-    int role, layer;
-    hipEvent_t a, b;
 };
 
 struct asd_plan {
@@ -75,9 +82,13 @@ struct asd_plan {
     asd_params prm;
     NeuronLayout nl[kMaxLayers + 1];  // 0..n
     LayerGeo geo[kMaxLayers + 1];     // 1..n
-    NeuronArrays na[kMaxLayers];      // 0..n-1
-    ReluLayer R[kMaxLayers];          // 1..n-1
-    float* cvec;                      // objective rows, layout n
+    // typed views of the workspace; only those of the plan's precision are set
+    NeuronArraysT<float> naf[kMaxLayers];
+    NeuronArraysT<double> nad[kMaxLayers];
+    ReluLayerT<float> Rf[kMaxLayers];
+    ReluLayerT<double> Rd[kMaxLayers];
+    float* cvecf;
+    double* cvecd;
     // scalar state
     int n_masks;
     int step;
@@ -91,6 +102,18 @@ struct asd_plan {
 };
 
 namespace {
+
+template <typename T> NeuronArraysT<T>* NA(asd_plan* P);
+template <> NeuronArraysT<float>* NA<float>(asd_plan* P) { return P->naf; }
+template <> NeuronArraysT<double>* NA<double>(asd_plan* P) { return P->nad; }
+template <typename T> ReluLayerT<T>* RL(asd_plan* P);
+template <> ReluLayerT<float>* RL<float>(asd_plan* P) { return P->Rf; }
+template <> ReluLayerT<double>* RL<double>(asd_plan* P) { return P->Rd; }
+template <typename T> T* CV(asd_plan* P);
+template <> float* CV<float>(asd_plan* P) { return P->cvecf; }
+template <> double* CV<double>(asd_plan* P) { return P->cvecd; }
+
+bool is64(const asd_plan* P) { return P->prm.precision == ASD_PREC_FP64; }
 
 // Event pair around one launch when profiling is on.
 struct ProfScope {
@@ -117,13 +140,9 @@ struct ProfScope {
     }
 };
 
-}  // namespace
-
 // ---------------------------------------------------------------------------
 // Workspace carving (two passes: measure, then assign).
 // ---------------------------------------------------------------------------
-namespace {
-
 struct Carver {
     char* base;
     size_t off;
@@ -136,15 +155,16 @@ struct Carver {
     }
 };
 
-void carve(asd_plan* P, Carver& cv) {
+template <typename T>
+void carve_t(asd_plan* P, Carver& cv) {
     const int S = P->S;
     for (int k = 0; k < P->n; ++k) {
         const NeuronLayout& nl = P->nl[k];
         const size_t ns = (size_t)nl.N * S;
-        NeuronArrays& a = P->na[k];
-        a.lo = cv.take<float>(ns);
-        a.hi = cv.take<float>(ns);
-        a.xstar = cv.take<float>(ns);
+        NeuronArraysT<T>& a = NA<T>(P)[k];
+        a.lo = cv.take<T>(ns);
+        a.hi = cv.take<T>(ns);
+        a.xstar = cv.take<T>(ns);
         a.xbits = cv.take<uint32_t>(nl.words);
         a.deg = cv.take<uint32_t>(nl.words);
         a.term = cv.take<double>(ns);
@@ -152,39 +172,48 @@ void carve(asd_plan* P, Carver& cv) {
     for (int k = 1; k < P->n; ++k) {
         const NeuronLayout& nl = P->nl[k];
         const size_t ns = (size_t)nl.N * S;
-        ReluLayer& r = P->R[k];
+        ReluLayerT<T>& r = RL<T>(P)[k];
         memset(&r, 0, sizeof(r));
-        r.lhat = cv.take<float>(ns);
-        r.uhat = cv.take<float>(ns);
-        r.alpha = cv.take<float>(ns);
-        r.beta0 = cv.take<float>(ns);
-        r.beta1 = cv.take<float>(ns);
-        r.alpha_m = cv.take<float>(ns);
-        r.alpha_v = cv.take<float>(ns);
-        r.beta0_m = cv.take<float>(ns);
-        r.beta0_v = cv.take<float>(ns);
-        r.beta1_m = cv.take<float>(ns);
-        r.beta1_v = cv.take<float>(ns);
-        r.own = cv.take<float>(ns);
-        r.g = cv.take<float>(ns);
-        r.vdn = cv.take<float>(ns);
+        r.lhat = cv.take<T>(ns);
+        r.uhat = cv.take<T>(ns);
+        r.alpha = cv.take<T>(ns);
+        r.beta0 = cv.take<T>(ns);
+        r.beta1 = cv.take<T>(ns);
+        r.alpha_m = cv.take<T>(ns);
+        r.alpha_v = cv.take<T>(ns);
+        r.beta0_m = cv.take<T>(ns);
+        r.beta0_v = cv.take<T>(ns);
+        r.beta1_m = cv.take<T>(ns);
+        r.beta1_v = cv.take<T>(ns);
+        r.own = cv.take<T>(ns);
+        r.g = cv.take<T>(ns);
+        r.vdn = cv.take<T>(ns);
         r.zbits = cv.take<uint32_t>(nl.words);
-        r.own64 = cv.take<double>(ns);
-        r.g64 = cv.take<double>(ns);
-        r.const64 = cv.take<double>(ns);
+        if (sizeof(T) == 4) {
+            r.own64 = cv.take<double>(ns);
+            r.g64 = cv.take<double>(ns);
+            r.const64 = cv.take<double>(ns);
+        }
         for (int q = 0; q < P->prm.max_masks; ++q) {
-            MaskSlot& m = r.slot[q];
-            m.beta = cv.take<float>(ns);
-            m.m = cv.take<float>(ns);
-            m.v = cv.take<float>(ns);
-            m.LI = cv.take<float>(ns);
-            m.UI = cv.take<float>(ns);
-            m.u = cv.take<float>(ns);
+            MaskSlotT<T>& m = r.slot[q];
+            m.beta = cv.take<T>(ns);
+            m.m = cv.take<T>(ns);
+            m.v = cv.take<T>(ns);
+            m.LI = cv.take<T>(ns);
+            m.UI = cv.take<T>(ns);
+            m.u = cv.take<T>(ns);
             m.zbits = cv.take<uint32_t>(nl.words);
             m.xbits = cv.take<uint32_t>(P->nl[k - 1].words);
         }
     }
-    P->cvec = cv.take<float>((size_t)P->nl[P->n].N * S);
+    T* cv_arr = cv.take<T>((size_t)P->nl[P->n].N * S);
+    if (sizeof(T) == 4) P->cvecf = reinterpret_cast<float*>(cv_arr);
+    else P->cvecd = reinterpret_cast<double*>(cv_arr);
+}
+
+void carve(asd_plan* P, Carver& cv) {
+    if (is64(P)) carve_t<double>(P, cv);
+    else carve_t<float>(P, cv);
 }
 
 asd_status check_params(const asd_params* p) {
@@ -195,13 +224,15 @@ asd_status check_params(const asd_params* p) {
     if (p->max_masks < 0 || p->max_masks > ASD_MAX_MASKS)
         return fail(ASD_EINVAL, "max_masks must be in [0, %d]", ASD_MAX_MASKS);
     if (p->rule != ASD_RULE_ADAM && p->rule != ASD_RULE_SUPERGRADIENT) return fail(ASD_EINVAL, "unknown rule");
-    if (!(p->adam_beta1 >= 0.f && p->adam_beta1 < 1.f && p->adam_beta2 >= 0.f && p->adam_beta2 < 1.f))
+    if (p->precision != ASD_PREC_FP32 && p->precision != ASD_PREC_FP64)
+        return fail(ASD_EINVAL, "unknown precision %d", p->precision);
+    if (!(p->adam_beta1 >= 0.0 && p->adam_beta1 < 1.0 && p->adam_beta2 >= 0.0 && p->adam_beta2 < 1.0))
         return fail(ASD_EINVAL, "Adam betas must be in [0, 1)");
-    if (!(p->adam_eps > 0.f)) return fail(ASD_EINVAL, "Adam eps must be > 0");
+    if (!(p->adam_eps > 0.0)) return fail(ASD_EINVAL, "Adam eps must be > 0");
     return ASD_OK;
 }
 
-asd_status setup_plan_geometry(asd_plan* P) {
+void setup_plan_geometry(asd_plan* P) {
     const asd_net* net = P->net;
     const int S = P->S;
     const asd_layer_desc& d0 = net->L[0];
@@ -229,27 +260,23 @@ asd_status setup_plan_geometry(asd_plan* P) {
         }
         g.out = P->nl[L];
     }
-    return ASD_OK;
 }
 
 inline dim3 grid_cols(const NeuronLayout& nl, int chan_per_block) {
     return dim3((unsigned)(nl.colpad / 64), (unsigned)((nl.C + chan_per_block - 1) / chan_per_block));
 }
 
-asd_status zero_floats(float* p, size_t n, hipStream_t st) {
+asd_status zero_words(void* p, long n, hipStream_t st) {
     if (n == 0) return ASD_OK;
-    const long words = (long)n;
-    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, st,
-                       reinterpret_cast<uint32_t*>(p), words);
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       reinterpret_cast<uint32_t*>(p), n);
     LAUNCH_CHECK();
     return ASD_OK;
 }
 
-asd_status zero_words(uint32_t* p, long n, hipStream_t st) {
-    if (n == 0) return ASD_OK;
-    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
-    LAUNCH_CHECK();
-    return ASD_OK;
+template <typename T>
+asd_status zero_arr(T* p, size_t n, hipStream_t st) {
+    return zero_words(p, (long)(n * sizeof(T) / 4), st);
 }
 
 asd_status copy_words(uint32_t* dst, const uint32_t* src, long n, hipStream_t st) {
@@ -258,17 +285,18 @@ asd_status copy_words(uint32_t* dst, const uint32_t* src, long n, hipStream_t st
     return ASD_OK;
 }
 
-asd_status launch_layout(float* dst, const float* src, const NeuronLayout& nl, int S, int mode,
-                         hipStream_t st) {
+template <typename Ti, typename Te>
+asd_status launch_layout(Ti* in_arr, Te* ex_arr, const NeuronLayout& nl, int S, int mode, hipStream_t st) {
     dim3 grid((unsigned)((nl.cols + 255) / 256), (unsigned)nl.C);
-    hipLaunchKernelGGL(k_layout, grid, dim3(256), 0, st, dst, src, nl, S, mode);
+    hipLaunchKernelGGL((k_layout<Ti, Te>), grid, dim3(256), 0, st, in_arr, ex_arr, nl, S, mode);
     LAUNCH_CHECK();
     return ASD_OK;
 }
 
-asd_status launch_bits(const NeuronLayout& nl, int S, int mode, uint32_t* bits, float* fext,
-                       const float* lo, const float* hi, hipStream_t st) {
-    BitArgs a;
+template <typename T, typename Te>
+asd_status launch_bits(const NeuronLayout& nl, int S, int mode, uint32_t* bits, Te* fext, const T* lo,
+                       const T* hi, hipStream_t st) {
+    BitArgs<T, Te> a;
     a.nl = nl;
     a.S = S;
     a.mode = mode;
@@ -277,28 +305,29 @@ asd_status launch_bits(const NeuronLayout& nl, int S, int mode, uint32_t* bits, 
     a.lo = lo;
     a.hi = hi;
     dim3 grid((unsigned)(nl.colpad / 256 + 1), (unsigned)nl.C);
-    hipLaunchKernelGGL(k_bits, grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_bits<T, Te>), grid, dim3(256), 0, st, a);
     LAUNCH_CHECK();
     return ASD_OK;
 }
 
+template <typename T>
 asd_status derive_layer(asd_plan* P, int k, hipStream_t st) {
-    DeriveArgs a;
+    DeriveArgs<T> a;
     a.nl = P->nl[k];
     a.S = P->S;
     a.nm = P->n_masks;
     a.b = P->geo[k].b;
-    a.R = P->R[k];
+    a.R = RL<T>(P)[k];
     dim3 grid((unsigned)((a.nl.cols + 255) / 256), (unsigned)a.nl.C);
-    hipLaunchKernelGGL(k_derive, grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_derive<T>, grid, dim3(256), 0, st, a);
     LAUNCH_CHECK();
     return ASD_OK;
 }
 
 // Backward pass for neuron layer k (f_k, inner minimisation, terms).
-template <typename T>
-asd_status launch_backward(asd_plan* P, int k, int want_obj, hipStream_t st) {
-    BwdArgs a;
+template <typename Tc, typename Ts>
+asd_status launch_backward(asd_plan* P, int k, int want_obj, int role, hipStream_t st) {
+    BwdArgs<Ts> a;
     memset(&a, 0, sizeof(a));
     a.gn = P->geo[k + 1];
     a.S = P->S;
@@ -306,153 +335,156 @@ asd_status launch_backward(asd_plan* P, int k, int want_obj, hipStream_t st) {
     a.last = (k + 1 == P->n);
     a.nm_next = a.last ? 0 : P->n_masks;
     a.nm_own = k >= 1 ? P->n_masks : 0;
-    a.cvec = P->cvec;
-    if (!a.last) a.Rn = P->R[k + 1];
+    a.cvec = CV<Ts>(P);
+    if (!a.last) a.Rn = RL<Ts>(P)[k + 1];
     if (k >= 1) {
-        a.Rk = P->R[k];
+        a.Rk = RL<Ts>(P)[k];
         a.bk = P->geo[k].b;
     }
-    a.nk = P->na[k];
+    a.nk = NA<Ts>(P)[k];
     a.want_obj = want_obj;
-    const size_t lds = (size_t)KS * CB * kWave * sizeof(T);
-    ProfScope ps(P, st, sizeof(T) == 8 ? ASD_K_FINAL : ASD_K_BACKWARD, k);
-    hipLaunchKernelGGL(k_backward<T>, grid_cols(P->nl[k], CB), dim3(kWave, KS), lds, st, a);
+    const size_t lds = (size_t)KS * CB * kWave * sizeof(Tc);
+    ProfScope ps(P, st, role, k);
+    hipLaunchKernelGGL((k_backward<Tc, Ts>), grid_cols(P->nl[k], CB), dim3(kWave, KS), lds, st, a);
     LAUNCH_CHECK();
     return ASD_OK;
 }
 
-asd_status launch_forward(asd_plan* P, int k, const StepArgs& sa, int mode, float* const* gout,
+template <typename T>
+asd_status launch_forward(asd_plan* P, int k, const StepArgsT<T>& sa, int mode, void* const* gout,
                           hipStream_t st) {
-    FwdArgs a;
+    FwdArgs<T> a;
     memset(&a, 0, sizeof(a));
     a.g = P->geo[k];
     a.S = P->S;
     a.nm = P->n_masks;
-    a.xin = P->na[k - 1].xstar;
-    a.deg_in = P->na[k - 1].deg;
-    a.xout = P->na[k].xstar;
-    a.zbits = P->R[k].zbits;
-    a.R = P->R[k];
+    a.xin = NA<T>(P)[k - 1].xstar;
+    a.deg_in = NA<T>(P)[k - 1].deg;
+    a.xout = NA<T>(P)[k].xstar;
+    a.zbits = RL<T>(P)[k].zbits;
+    a.R = RL<T>(P)[k];
     a.st = sa;
     a.mode = mode;
     if (gout)
-        for (int i = 0; i < 3 + kMaxMasks; ++i) a.gout[i] = gout[i];
-    const size_t lds = (size_t)KS * CB * (1 + a.nm) * kWave * sizeof(float);
+        for (int i = 0; i < 3 + kMaxMasks; ++i) a.gout[i] = reinterpret_cast<T*>(gout[i]);
+    const size_t lds = (size_t)KS * CB * (1 + a.nm) * kWave * sizeof(T);
     ProfScope ps(P, st, mode == 0 ? ASD_K_FORWARD : ASD_K_OTHER, k);
-    hipLaunchKernelGGL(k_forward, grid_cols(P->nl[k], CB), dim3(kWave, KS), lds, st, a);
+    hipLaunchKernelGGL(k_forward<T>, grid_cols(P->nl[k], CB), dim3(kWave, KS), lds, st, a);
     LAUNCH_CHECK();
     return ASD_OK;
 }
 
-// Mask constants of slot q of layer k from the given bit sources (FP32).
+// Mask constants of slot q of layer k from the given bit sources.
+template <typename T>
 asd_status launch_mask_consts(asd_plan* P, int k, int q, const uint32_t* zsrc, const uint32_t* xsrc,
                               int zero_state, hipStream_t st) {
-    MaskArgs a;
+    MaskArgs<T> a;
     memset(&a, 0, sizeof(a));
     a.g = P->geo[k];
     a.S = P->S;
     a.q = q;
     a.nm = 1;
-    a.lo_in = P->na[k - 1].lo;
-    a.hi_in = P->na[k - 1].hi;
+    a.lo_in = NA<T>(P)[k - 1].lo;
+    a.hi_in = NA<T>(P)[k - 1].hi;
     a.zsrc = zsrc;
     a.xsrc = xsrc;
     a.zero_state = zero_state;
-    a.deg_in = P->na[k - 1].deg;
-    a.R = P->R[k];
-    const size_t lds = (size_t)KS * CB * 2 * kWave * sizeof(float);
+    a.deg_in = NA<T>(P)[k - 1].deg;
+    a.R = RL<T>(P)[k];
+    const size_t lds = (size_t)KS * CB * 2 * kWave * sizeof(T);
     ProfScope ps(P, st, ASD_K_MASK, k);
-    hipLaunchKernelGGL(k_mask_consts<float>, grid_cols(P->nl[k], CB), dim3(kWave, KS), lds, st, a);
+    hipLaunchKernelGGL((k_mask_consts<T, T>), grid_cols(P->nl[k], CB), dim3(kWave, KS), lds, st, a);
     LAUNCH_CHECK();
     return ASD_OK;
 }
 
+// FP64 per-neuron sums of the final bound of an FP32 plan.
 asd_status launch_final_sums(asd_plan* P, int k, hipStream_t st) {
-    MaskArgs a;
+    MaskArgs<float> a;
     memset(&a, 0, sizeof(a));
     a.g = P->geo[k];
     a.S = P->S;
     a.q = 0;
     a.nm = P->n_masks;
-    a.lo_in = P->na[k - 1].lo;
-    a.hi_in = P->na[k - 1].hi;
-    a.deg_in = P->na[k - 1].deg;
-    a.R = P->R[k];
+    a.lo_in = P->naf[k - 1].lo;
+    a.hi_in = P->naf[k - 1].hi;
+    a.deg_in = P->naf[k - 1].deg;
+    a.R = P->Rf[k];
     const size_t lds = (size_t)KS * CB * 2 * kWave * sizeof(double);
     ProfScope ps(P, st, ASD_K_FINAL, k);
-    hipLaunchKernelGGL(k_mask_consts<double>, grid_cols(P->nl[k], CB), dim3(kWave, KS), lds, st, a);
+    hipLaunchKernelGGL((k_mask_consts<double, float>), grid_cols(P->nl[k], CB), dim3(kWave, KS), lds, st, a);
     LAUNCH_CHECK();
     return ASD_OK;
 }
 
+template <typename T>
 asd_status reduce_objective(asd_plan* P, double* out, hipStream_t st) {
-    ReduceArgs a;
+    ReduceArgs<T> a;
     memset(&a, 0, sizeof(a));
     a.S = P->S;
     a.nlayers = P->n;
     for (int k = 0; k < P->n; ++k) {
         a.nl[k] = P->nl[k];
-        a.term[k] = P->na[k].term;
+        a.term[k] = NA<T>(P)[k].term;
     }
     // b_n^T c_s from the internal copy of c (layout n: [n_last][S])
-    a.cint = P->cvec;
+    a.cint = CV<T>(P);
     a.bn = P->geo[P->n].b;
     a.n_last = P->nl[P->n].C;
     a.out = out;
-    hipLaunchKernelGGL(k_reduce_obj, dim3((unsigned)P->S), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_reduce_obj<T>, dim3((unsigned)P->S), dim3(256), 0, st, a);
     LAUNCH_CHECK();
     return ASD_OK;
 }
 
-float linear_lr(float lr0, float lr1, int t, int T) {
+double linear_lr(double lr0, double lr1, int t, int T) {
     if (T <= 1) return lr0;
-    return (float)((double)lr0 + ((double)lr1 - (double)lr0) * (double)t / (double)(T - 1));
+    return lr0 + (lr1 - lr0) * (double)t / (double)(T - 1);
 }
 
-StepArgs make_step_args(const asd_plan* P, float lr) {
-    StepArgs sa;
+template <typename T>
+StepArgsT<T> make_step_args(const asd_plan* P, double lr) {
+    StepArgsT<T> sa;
     memset(&sa, 0, sizeof(sa));
     sa.rule = P->prm.rule;
-    sa.lr = lr;
-    sa.b1 = P->prm.adam_beta1;
-    sa.b2 = P->prm.adam_beta2;
-    sa.eps = P->prm.adam_eps;
-    auto bc = [&](int step, float* c1, float* c2) {
+    sa.lr = (T)lr;
+    sa.b1 = (T)P->prm.adam_beta1;
+    sa.b2 = (T)P->prm.adam_beta2;
+    sa.eps = (T)P->prm.adam_eps;
+    auto bc = [&](int step, T* c1, T* c2) {
         const int s = step > 0 ? step : 1;
-        *c1 = (float)(1.0 - pow((double)P->prm.adam_beta1, (double)s));
-        *c2 = (float)(1.0 - pow((double)P->prm.adam_beta2, (double)s));
+        *c1 = (T)(1.0 - pow(P->prm.adam_beta1, (double)s));
+        *c2 = (T)(1.0 - pow(P->prm.adam_beta2, (double)s));
     };
     bc(P->step, &sa.bc1[0], &sa.bc2[0]);
     for (int q = 0; q < kMaxMasks; ++q) bc(q < P->n_masks ? P->mask_step[q] : 1, &sa.bc1[1 + q], &sa.bc2[1 + q]);
     return sa;
 }
 
+template <typename T>
 asd_status reset_group_moments(asd_plan* P, hipStream_t st) {
     for (int k = 1; k < P->n; ++k) {
         const size_t ns = (size_t)P->nl[k].N * P->S;
-        ReluLayer& r = P->R[k];
-        float* arrs[6] = {r.alpha_m, r.alpha_v, r.beta0_m, r.beta0_v, r.beta1_m, r.beta1_v};
-        for (float* a : arrs) {
-            asd_status s = zero_floats(a, ns, st);
-            if (s) return s;
-        }
+        ReluLayerT<T>& r = RL<T>(P)[k];
+        T* arrs[6] = {r.alpha_m, r.alpha_v, r.beta0_m, r.beta0_v, r.beta1_m, r.beta1_v};
+        for (T* a : arrs) TRY(zero_arr(a, ns, st));
     }
     P->step = 0;
     return ASD_OK;
 }
 
 // One iteration: backward pass, optional active-set extension, forward pass.
-asd_status iteration(asd_plan* P, bool as_phase, int t, float lr, hipStream_t st) {
-    asd_status s;
-    for (int k = P->n - 1; k >= 0; --k)
-        if ((s = launch_backward<float>(P, k, 0, st))) return s;
+template <typename T>
+asd_status iteration(asd_plan* P, bool as_phase, int t, double lr, hipStream_t st) {
+    for (int k = P->n - 1; k >= 0; --k) TRY((launch_backward<T, T>(P, k, 0, ASD_K_BACKWARD, st)));
     if (as_phase && P->n >= 2 && (t % P->prm.add_every) < P->prm.add_count &&
         P->n_masks < P->prm.max_masks) {
         const int q = P->n_masks;
         for (int k = 1; k < P->n; ++k) {
-            if ((s = copy_words(P->R[k].slot[q].zbits, P->R[k].zbits, P->nl[k].words, st))) return s;
-            if ((s = copy_words(P->R[k].slot[q].xbits, P->na[k - 1].xbits, P->nl[k - 1].words, st))) return s;
-            if ((s = launch_mask_consts(P, k, q, P->R[k].zbits, P->na[k - 1].xbits, 1, st))) return s;
+            ReluLayerT<T>& r = RL<T>(P)[k];
+            TRY(copy_words(r.slot[q].zbits, r.zbits, P->nl[k].words, st));
+            TRY(copy_words(r.slot[q].xbits, NA<T>(P)[k - 1].xbits, P->nl[k - 1].words, st));
+            TRY(launch_mask_consts<T>(P, k, q, r.zbits, NA<T>(P)[k - 1].xbits, 1, st));
         }
         P->mask_step[q] = 0;
         P->n_masks = q + 1;
@@ -461,9 +493,182 @@ asd_status iteration(asd_plan* P, bool as_phase, int t, float lr, hipStream_t st
         P->step += 1;
         for (int q = 0; q < P->n_masks; ++q) P->mask_step[q] += 1;
     }
-    const StepArgs sa = make_step_args(P, lr);
-    for (int k = 1; k < P->n; ++k)
-        if ((s = launch_forward(P, k, sa, 0, nullptr, st))) return s;
+    const StepArgsT<T> sa = make_step_args<T>(P, lr);
+    for (int k = 1; k < P->n; ++k) TRY(launch_forward<T>(P, k, sa, 0, nullptr, st));
+    return ASD_OK;
+}
+
+template <typename T>
+asd_status init_t(asd_plan* P, const asd_batch* b, hipStream_t st) {
+    const int S = P->S;
+    NeuronArraysT<T>* na = NA<T>(P);
+    TRY((launch_layout<T, const float>(na[0].lo, b->l0, P->nl[0], S, 0, st)));
+    TRY((launch_layout<T, const float>(na[0].hi, b->u0, P->nl[0], S, 0, st)));
+    for (int k = 1; k < P->n; ++k) {
+        ReluLayerT<T>& r = RL<T>(P)[k];
+        TRY((launch_layout<T, const float>(r.lhat, b->lhat[k - 1], P->nl[k], S, 0, st)));
+        TRY((launch_layout<T, const float>(r.uhat, b->uhat[k - 1], P->nl[k], S, 0, st)));
+        TRY((launch_layout<T, const float>(na[k].lo, b->lhat[k - 1], P->nl[k], S, 1, st)));
+        TRY((launch_layout<T, const float>(na[k].hi, b->uhat[k - 1], P->nl[k], S, 1, st)));
+    }
+    for (int k = 0; k < P->n; ++k)
+        TRY((launch_bits<T, T>(P->nl[k], S, 3, na[k].deg, nullptr, na[k].lo, na[k].hi, st)));
+    TRY((launch_layout<T, const float>(CV<T>(P), b->c, P->nl[P->n], S, 0, st)));
+    for (int k = 1; k < P->n; ++k) {
+        const size_t ns = (size_t)P->nl[k].N * S;
+        ReluLayerT<T>& r = RL<T>(P)[k];
+        T* arrs[12] = {r.alpha, r.beta0, r.beta1, r.alpha_m, r.alpha_v, r.beta0_m,
+                       r.beta0_v, r.beta1_m, r.beta1_v, r.own, r.g, r.vdn};
+        for (T* a : arrs) TRY(zero_arr(a, ns, st));
+        for (int q = 0; q < P->prm.max_masks; ++q) {
+            MaskSlotT<T>& m = r.slot[q];
+            T* sarr[6] = {m.beta, m.m, m.v, m.LI, m.UI, m.u};
+            for (T* a : sarr) TRY(zero_arr(a, ns, st));
+            TRY(zero_words(m.zbits, P->nl[k].words, st));
+            TRY(zero_words(m.xbits, P->nl[k - 1].words, st));
+        }
+    }
+    return ASD_OK;
+}
+
+template <typename T>
+asd_status run_t(asd_plan* P, bool as, int t_begin, int n_iters, int T_, hipStream_t st) {
+    if (as && t_begin == 0 && n_iters > 0 && P->prm.rule == ASD_RULE_ADAM) TRY(reset_group_moments<T>(P, st));
+    for (int t = t_begin; t < t_begin + n_iters; ++t) {
+        const double lr = as ? linear_lr(P->prm.as_lr0, P->prm.as_lr1, t, T_)
+                             : linear_lr(P->prm.bigm_lr0, P->prm.bigm_lr1, t, T_);
+        TRY(iteration<T>(P, as, t, lr, st));
+    }
+    return ASD_OK;
+}
+
+asd_status bound_f32(asd_plan* P, double* out_lb, float* x0, hipStream_t st) {
+    for (int k = 1; k < P->n; ++k) TRY(launch_final_sums(P, k, st));
+    for (int k = P->n - 1; k >= 0; --k) TRY((launch_backward<double, float>(P, k, 1, ASD_K_FINAL, st)));
+    TRY(reduce_objective<float>(P, out_lb, st));
+    if (x0) TRY((launch_layout<float, float>(P->naf[0].xstar, x0, P->nl[0], P->S, 2, st)));
+    return ASD_OK;
+}
+
+asd_status bound_f64(asd_plan* P, double* out_lb, float* x0, hipStream_t st) {
+    for (int k = P->n - 1; k >= 0; --k) TRY((launch_backward<double, double>(P, k, 1, ASD_K_FINAL, st)));
+    TRY(reduce_objective<double>(P, out_lb, st));
+    if (x0) TRY((launch_layout<double, float>(P->nad[0].xstar, x0, P->nl[0], P->S, 2, st)));
+    return ASD_OK;
+}
+
+template <typename T>
+T* field_ptr(asd_plan* P, int field, int k, int q) {
+    ReluLayerT<T>& r = RL<T>(P)[k];
+    switch (field) {
+        case ASD_F_ALPHA: return r.alpha;
+        case ASD_F_BETA0: return r.beta0;
+        case ASD_F_BETA1: return r.beta1;
+        case ASD_F_ALPHA_M: return r.alpha_m;
+        case ASD_F_ALPHA_V: return r.alpha_v;
+        case ASD_F_BETA0_M: return r.beta0_m;
+        case ASD_F_BETA0_V: return r.beta0_v;
+        case ASD_F_BETA1_M: return r.beta1_m;
+        case ASD_F_BETA1_V: return r.beta1_v;
+        case ASD_F_MASK_BETA: return r.slot[q].beta;
+        case ASD_F_MASK_M: return r.slot[q].m;
+        case ASD_F_MASK_V: return r.slot[q].v;
+        case ASD_F_MASK_LI: return r.slot[q].LI;
+        case ASD_F_MASK_UI: return r.slot[q].UI;
+        default: return nullptr;
+    }
+}
+
+asd_status check_field(asd_plan* P, int field, int k, int q) {
+    if (!P) return fail(ASD_EINVAL, "NULL plan");
+    if (!P->loaded) return fail(ASD_EINVAL, "asd_init has not been called");
+    if (k < 1 || k >= P->n) return fail(ASD_EINVAL, "layer %d outside [1, %d]", k, P->n - 1);
+    if (field < ASD_F_ALPHA || field > ASD_F_MASK_XPREV) return fail(ASD_EINVAL, "unknown field %d", field);
+    if (field >= ASD_F_MASK_BETA && (q < 0 || q >= P->prm.max_masks))
+        return fail(ASD_EINVAL, "slot %d outside [0, %d)", q, P->prm.max_masks);
+    return ASD_OK;
+}
+
+template <typename T>
+asd_status state_get_t(asd_plan* P, int field, int k, int q, T* dst, hipStream_t st) {
+    ReluLayerT<T>& r = RL<T>(P)[k];
+    if (field == ASD_F_MASK_Z)
+        return launch_bits<T, T>(P->nl[k], P->S, 0, r.slot[q].zbits, dst, nullptr, nullptr, st);
+    if (field == ASD_F_MASK_XPREV)
+        return launch_bits<T, T>(P->nl[k - 1], P->S, 4, r.slot[q].xbits, dst, NA<T>(P)[k - 1].lo,
+                                 NA<T>(P)[k - 1].hi, st);
+    return launch_layout<T, T>(field_ptr<T>(P, field, k, q), dst, P->nl[k], P->S, 2, st);
+}
+
+template <typename T>
+asd_status state_set_t(asd_plan* P, int field, int k, int q, const T* src, hipStream_t st) {
+    ReluLayerT<T>& r = RL<T>(P)[k];
+    T* s = const_cast<T*>(src);
+    if (field == ASD_F_MASK_Z) {
+        TRY((launch_bits<T, T>(P->nl[k], P->S, 2, r.slot[q].zbits, s, nullptr, nullptr, st)));
+    } else if (field == ASD_F_MASK_XPREV) {
+        TRY((launch_bits<T, T>(P->nl[k - 1], P->S, 1, r.slot[q].xbits, s, NA<T>(P)[k - 1].lo,
+                               NA<T>(P)[k - 1].hi, st)));
+    } else {
+        TRY((launch_layout<T, T>(field_ptr<T>(P, field, k, q), s, P->nl[k], P->S, 0, st)));
+    }
+    return derive_layer<T>(P, k, st);
+}
+
+template <typename T>
+asd_status set_counts_t(asd_plan* P, int recompute, hipStream_t st) {
+    if (recompute) {
+        for (int k = 1; k < P->n; ++k)
+            for (int q = 0; q < P->n_masks; ++q) {
+                ReluLayerT<T>& r = RL<T>(P)[k];
+                TRY(launch_mask_consts<T>(P, k, q, r.slot[q].zbits, r.slot[q].xbits, 0, st));
+            }
+    }
+    for (int k = 1; k < P->n; ++k) TRY(derive_layer<T>(P, k, st));
+    return ASD_OK;
+}
+
+template <typename T>
+asd_status eval_t(asd_plan* P, const asd_eval_out* out, hipStream_t st) {
+    for (int k = P->n - 1; k >= 0; --k) TRY((launch_backward<T, T>(P, k, 1, ASD_K_OTHER, st)));
+    if (out->obj) TRY(reduce_objective<T>(P, out->obj, st));
+    for (int k = 0; k < P->n; ++k) {
+        if (out->xstar[k])
+            TRY((launch_layout<T, T>(NA<T>(P)[k].xstar, reinterpret_cast<T*>(out->xstar[k]), P->nl[k], P->S, 2,
+                                     st)));
+        if (k >= 1 && out->zstar[k])
+            TRY((launch_bits<T, T>(P->nl[k], P->S, 0, RL<T>(P)[k].zbits, reinterpret_cast<T*>(out->zstar[k]),
+                                   nullptr, nullptr, st)));
+    }
+    const StepArgsT<T> sa = make_step_args<T>(P, 0.0);
+    for (int k = 1; k < P->n; ++k) {
+        void* gout[3 + kMaxMasks] = {out->grad_alpha[k], out->grad_beta0[k], out->grad_beta1[k]};
+        bool any = gout[0] || gout[1] || gout[2];
+        for (int q = 0; q < kMaxMasks; ++q) {
+            gout[3 + q] = out->grad_mask[k][q];
+            any = any || gout[3 + q];
+        }
+        if (any) TRY(launch_forward<T>(P, k, sa, 1, gout, st));
+    }
+    return ASD_OK;
+}
+
+template <typename T>
+asd_status oracle_t(asd_plan* P, int k, const T* x_prev, const T* z, uint32_t* bits, T* LI, T* UI,
+                    hipStream_t st) {
+    OracleArgs<T> a;
+    a.g = P->geo[k];
+    a.S = P->S;
+    a.xprev = x_prev;
+    a.z = z;
+    a.lo_in = NA<T>(P)[k - 1].lo;
+    a.hi_in = NA<T>(P)[k - 1].hi;
+    a.bits = bits;
+    a.LI = LI;
+    a.UI = UI;
+    const long n = (long)P->S * a.g.out.N;
+    hipLaunchKernelGGL(k_oracle<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+    LAUNCH_CHECK();
     return ASD_OK;
 }
 
@@ -485,13 +690,14 @@ void asd_params_default(asd_params* p) {
     p->add_count = 2;
     p->max_masks = 7;
     p->rule = ASD_RULE_ADAM;
-    p->bigm_lr0 = 1e-2f;
-    p->bigm_lr1 = 1e-4f;
-    p->as_lr0 = 1e-3f;
-    p->as_lr1 = 1e-6f;
-    p->adam_beta1 = 0.9f;
-    p->adam_beta2 = 0.999f;
-    p->adam_eps = 1e-8f;
+    p->bigm_lr0 = 1e-2;
+    p->bigm_lr1 = 1e-4;
+    p->as_lr0 = 1e-3;
+    p->as_lr1 = 1e-6;
+    p->adam_beta1 = 0.9;
+    p->adam_beta2 = 0.999;
+    p->adam_eps = 1e-8;
+    p->precision = ASD_PREC_FP32;
 }
 
 asd_status asd_net_create(const asd_layer_desc* layers, int32_t n_layers, asd_net** out) {
@@ -528,8 +734,7 @@ asd_status asd_net_create(const asd_layer_desc* layers, int32_t n_layers, asd_ne
             }
         }
     }
-    if (layers[n_layers - 1].kind != ASD_LAYER_DENSE)
-        return fail(ASD_EINVAL, "the last layer must be dense");
+    if (layers[n_layers - 1].kind != ASD_LAYER_DENSE) return fail(ASD_EINVAL, "the last layer must be dense");
     asd_net* net = new (std::nothrow) asd_net;
     if (!net) return fail(ASD_EINVAL, "host allocation failed");
     net->n = n_layers;
@@ -543,8 +748,7 @@ void asd_net_destroy(asd_net* net) { delete net; }
 asd_status asd_plan_workspace_size(const asd_net* net, int32_t S, const asd_params* params, size_t* bytes) {
     if (!net || !bytes) return fail(ASD_EINVAL, "NULL argument");
     if (S < 1) return fail(ASD_EINVAL, "S must be >= 1");
-    asd_status s = check_params(params);
-    if (s) return s;
+    TRY(check_params(params));
     asd_plan tmp{};
     tmp.net = net;
     tmp.S = S;
@@ -562,8 +766,7 @@ asd_status asd_plan_create(const asd_net* net, int32_t S, const asd_params* para
     (void)stream;
     if (!net || !out || !workspace) return fail(ASD_EINVAL, "NULL argument");
     size_t need = 0;
-    asd_status s = asd_plan_workspace_size(net, S, params, &need);
-    if (s) return s;
+    TRY(asd_plan_workspace_size(net, S, params, &need));
     if (bytes < need) return fail(ASD_ENOMEM, "workspace has %zu bytes, needs %zu", bytes, need);
     if ((uintptr_t)workspace % 256) return fail(ASD_EINVAL, "workspace must be 256-byte aligned");
     asd_plan* P = new (std::nothrow) asd_plan();  // value-initialised
@@ -626,36 +829,8 @@ asd_status asd_init(asd_plan* P, const asd_batch* b, hipStream_t st) {
     if (P->n > 1 && (!b->lhat || !b->uhat)) return fail(ASD_EINVAL, "NULL lhat/uhat");
     for (int k = 1; k < P->n; ++k)
         if (!b->lhat[k - 1] || !b->uhat[k - 1]) return fail(ASD_EINVAL, "NULL bound of layer %d", k);
-    asd_status s;
-    const int S = P->S;
-    if ((s = launch_layout(P->na[0].lo, b->l0, P->nl[0], S, 0, st))) return s;
-    if ((s = launch_layout(P->na[0].hi, b->u0, P->nl[0], S, 0, st))) return s;
-    for (int k = 1; k < P->n; ++k) {
-        ReluLayer& r = P->R[k];
-        if ((s = launch_layout(r.lhat, b->lhat[k - 1], P->nl[k], S, 0, st))) return s;
-        if ((s = launch_layout(r.uhat, b->uhat[k - 1], P->nl[k], S, 0, st))) return s;
-        if ((s = launch_layout(P->na[k].lo, b->lhat[k - 1], P->nl[k], S, 1, st))) return s;
-        if ((s = launch_layout(P->na[k].hi, b->uhat[k - 1], P->nl[k], S, 1, st))) return s;
-    }
-    for (int k = 0; k < P->n; ++k)
-        if ((s = launch_bits(P->nl[k], S, 3, P->na[k].deg, nullptr, P->na[k].lo, P->na[k].hi, st))) return s;
-    if ((s = launch_layout(P->cvec, b->c, P->nl[P->n], S, 0, st))) return s;
-    for (int k = 1; k < P->n; ++k) {
-        const size_t ns = (size_t)P->nl[k].N * S;
-        ReluLayer& r = P->R[k];
-        float* arrs[12] = {r.alpha, r.beta0, r.beta1, r.alpha_m, r.alpha_v, r.beta0_m,
-                           r.beta0_v, r.beta1_m, r.beta1_v, r.own, r.g, r.vdn};
-        for (float* a : arrs)
-            if ((s = zero_floats(a, ns, st))) return s;
-        for (int q = 0; q < P->prm.max_masks; ++q) {
-            MaskSlot& m = r.slot[q];
-            float* sarr[6] = {m.beta, m.m, m.v, m.LI, m.UI, m.u};
-            for (float* a : sarr)
-                if ((s = zero_floats(a, ns, st))) return s;
-            if ((s = zero_words(m.zbits, P->nl[k].words, st))) return s;
-            if ((s = zero_words(m.xbits, P->nl[k - 1].words, st))) return s;
-        }
-    }
+    if (is64(P)) TRY(init_t<double>(P, b, st));
+    else TRY(init_t<float>(P, b, st));
     P->n_masks = 0;
     P->step = 0;
     for (int q = 0; q < kMaxMasks; ++q) P->mask_step[q] = 0;
@@ -670,96 +845,36 @@ asd_status asd_run(asd_plan* P, int32_t phase, int32_t t_begin, int32_t n_iters,
     const int T = phase == ASD_PHASE_BIGM ? P->prm.bigm_iters : P->prm.as_iters;
     if (t_begin < 0 || n_iters < 0 || t_begin + n_iters > T)
         return fail(ASD_EINVAL, "iterations [%d, %d) outside [0, %d)", t_begin, t_begin + n_iters, T);
-    asd_status s;
     const bool as = phase == ASD_PHASE_AS;
-    if (as && t_begin == 0 && n_iters > 0 && P->prm.rule == ASD_RULE_ADAM)
-        if ((s = reset_group_moments(P, st))) return s;
-    for (int t = t_begin; t < t_begin + n_iters; ++t) {
-        const float lr = as ? linear_lr(P->prm.as_lr0, P->prm.as_lr1, t, T)
-                            : linear_lr(P->prm.bigm_lr0, P->prm.bigm_lr1, t, T);
-        if ((s = iteration(P, as, t, lr, st))) return s;
-    }
-    return ASD_OK;
+    if (is64(P)) return run_t<double>(P, as, t_begin, n_iters, T, st);
+    return run_t<float>(P, as, t_begin, n_iters, T, st);
 }
 
 asd_status asd_bound(asd_plan* P, double* out_lb, float* x0, hipStream_t st) {
     if (!P || !out_lb) return fail(ASD_EINVAL, "NULL argument");
     if (!P->loaded) return fail(ASD_EINVAL, "asd_init has not been called");
-    asd_status s;
-    for (int k = 1; k < P->n; ++k)
-        if ((s = launch_final_sums(P, k, st))) return s;
-    for (int k = P->n - 1; k >= 0; --k)
-        if ((s = launch_backward<double>(P, k, 1, st))) return s;
-    if ((s = reduce_objective(P, out_lb, st))) return s;
-    if (x0 && (s = launch_layout(x0, P->na[0].xstar, P->nl[0], P->S, 2, st))) return s;
-    return ASD_OK;
+    return is64(P) ? bound_f64(P, out_lb, x0, st) : bound_f32(P, out_lb, x0, st);
 }
 
 asd_status asd_solve(asd_plan* P, const asd_batch* b, double* out_lb, float* x0, hipStream_t st) {
-    asd_status s;
-    if ((s = asd_init(P, b, st))) return s;
-    if ((s = asd_run(P, ASD_PHASE_BIGM, 0, P->prm.bigm_iters, st))) return s;
-    if ((s = asd_run(P, ASD_PHASE_AS, 0, P->prm.as_iters, st))) return s;
+    TRY(asd_init(P, b, st));
+    TRY(asd_run(P, ASD_PHASE_BIGM, 0, P->prm.bigm_iters, st));
+    TRY(asd_run(P, ASD_PHASE_AS, 0, P->prm.as_iters, st));
     return asd_bound(P, out_lb, x0, st);
 }
 
-static float* field_ptr(asd_plan* P, int field, int k, int q) {
-    ReluLayer& r = P->R[k];
-    switch (field) {
-        case ASD_F_ALPHA: return r.alpha;
-        case ASD_F_BETA0: return r.beta0;
-        case ASD_F_BETA1: return r.beta1;
-        case ASD_F_ALPHA_M: return r.alpha_m;
-        case ASD_F_ALPHA_V: return r.alpha_v;
-        case ASD_F_BETA0_M: return r.beta0_m;
-        case ASD_F_BETA0_V: return r.beta0_v;
-        case ASD_F_BETA1_M: return r.beta1_m;
-        case ASD_F_BETA1_V: return r.beta1_v;
-        case ASD_F_MASK_BETA: return r.slot[q].beta;
-        case ASD_F_MASK_M: return r.slot[q].m;
-        case ASD_F_MASK_V: return r.slot[q].v;
-        case ASD_F_MASK_LI: return r.slot[q].LI;
-        case ASD_F_MASK_UI: return r.slot[q].UI;
-        default: return nullptr;
-    }
-}
-
-static asd_status check_field(asd_plan* P, int field, int k, int q) {
-    if (!P) return fail(ASD_EINVAL, "NULL plan");
-    if (!P->loaded) return fail(ASD_EINVAL, "asd_init has not been called");
-    if (k < 1 || k >= P->n) return fail(ASD_EINVAL, "layer %d outside [1, %d]", k, P->n - 1);
-    if (field < ASD_F_ALPHA || field > ASD_F_MASK_XPREV) return fail(ASD_EINVAL, "unknown field %d", field);
-    if (field >= ASD_F_MASK_BETA && (q < 0 || q >= P->prm.max_masks))
-        return fail(ASD_EINVAL, "slot %d outside [0, %d)", q, P->prm.max_masks);
-    return ASD_OK;
-}
-
-asd_status asd_state_get(asd_plan* P, int32_t field, int32_t k, int32_t q, float* dst, hipStream_t st) {
-    asd_status s = check_field(P, field, k, q);
-    if (s) return s;
+asd_status asd_state_get(asd_plan* P, int32_t field, int32_t k, int32_t q, void* dst, hipStream_t st) {
+    TRY(check_field(P, field, k, q));
     if (!dst) return fail(ASD_EINVAL, "NULL destination");
-    if (field == ASD_F_MASK_Z)
-        return launch_bits(P->nl[k], P->S, 0, P->R[k].slot[q].zbits, dst, nullptr, nullptr, st);
-    if (field == ASD_F_MASK_XPREV)
-        return launch_bits(P->nl[k - 1], P->S, 4, P->R[k].slot[q].xbits, dst, P->na[k - 1].lo,
-                           P->na[k - 1].hi, st);
-    return launch_layout(dst, field_ptr(P, field, k, q), P->nl[k], P->S, 2, st);
+    if (is64(P)) return state_get_t<double>(P, field, k, q, reinterpret_cast<double*>(dst), st);
+    return state_get_t<float>(P, field, k, q, reinterpret_cast<float*>(dst), st);
 }
 
-asd_status asd_state_set(asd_plan* P, int32_t field, int32_t k, int32_t q, const float* src, hipStream_t st) {
-    asd_status s = check_field(P, field, k, q);
-    if (s) return s;
+asd_status asd_state_set(asd_plan* P, int32_t field, int32_t k, int32_t q, const void* src, hipStream_t st) {
+    TRY(check_field(P, field, k, q));
     if (!src) return fail(ASD_EINVAL, "NULL source");
-    if (field == ASD_F_MASK_Z) {
-        s = launch_bits(P->nl[k], P->S, 2, P->R[k].slot[q].zbits, const_cast<float*>(src), nullptr, nullptr, st);
-    } else if (field == ASD_F_MASK_XPREV) {
-        s = launch_bits(P->nl[k - 1], P->S, 1, P->R[k].slot[q].xbits, const_cast<float*>(src),
-                        P->na[k - 1].lo, P->na[k - 1].hi, st);
-    } else {
-        s = launch_layout(field_ptr(P, field, k, q), src, P->nl[k], P->S, 0, st);
-    }
-    if (s) return s;
-    return derive_layer(P, k, st);
+    if (is64(P)) return state_set_t<double>(P, field, k, q, reinterpret_cast<const double*>(src), st);
+    return state_set_t<float>(P, field, k, q, reinterpret_cast<const float*>(src), st);
 }
 
 asd_status asd_state_get_counts(const asd_plan* P, asd_counts* out) {
@@ -782,63 +897,25 @@ asd_status asd_state_set_counts(asd_plan* P, const asd_counts* in, int32_t recom
     P->n_masks = in->n_masks;
     P->step = in->step;
     for (int q = 0; q < kMaxMasks; ++q) P->mask_step[q] = q < in->n_masks ? in->mask_step[q] : 0;
-    asd_status s;
-    if (recompute) {
-        for (int k = 1; k < P->n; ++k)
-            for (int q = 0; q < P->n_masks; ++q)
-                if ((s = launch_mask_consts(P, k, q, P->R[k].slot[q].zbits, P->R[k].slot[q].xbits, 0, st)))
-                    return s;
-    }
-    for (int k = 1; k < P->n; ++k)
-        if ((s = derive_layer(P, k, st))) return s;
-    return ASD_OK;
+    return is64(P) ? set_counts_t<double>(P, recompute, st) : set_counts_t<float>(P, recompute, st);
 }
 
 asd_status asd_eval(asd_plan* P, const asd_eval_out* out, hipStream_t st) {
     if (!P || !out) return fail(ASD_EINVAL, "NULL argument");
     if (!P->loaded) return fail(ASD_EINVAL, "asd_init has not been called");
-    asd_status s;
-    for (int k = P->n - 1; k >= 0; --k)
-        if ((s = launch_backward<float>(P, k, 1, st))) return s;
-    if (out->obj && (s = reduce_objective(P, out->obj, st))) return s;
-    for (int k = 0; k < P->n; ++k) {
-        if (out->xstar[k] && (s = launch_layout(out->xstar[k], P->na[k].xstar, P->nl[k], P->S, 2, st))) return s;
-        if (k >= 1 && out->zstar[k] &&
-            (s = launch_bits(P->nl[k], P->S, 0, P->R[k].zbits, out->zstar[k], nullptr, nullptr, st)))
-            return s;
-    }
-    const StepArgs sa = make_step_args(P, 0.f);
-    for (int k = 1; k < P->n; ++k) {
-        float* gout[3 + kMaxMasks] = {out->grad_alpha[k], out->grad_beta0[k], out->grad_beta1[k]};
-        bool any = gout[0] || gout[1] || gout[2];
-        for (int q = 0; q < kMaxMasks; ++q) {
-            gout[3 + q] = out->grad_mask[k][q];
-            any = any || gout[3 + q];
-        }
-        if (any && (s = launch_forward(P, k, sa, 1, gout, st))) return s;
-    }
-    return ASD_OK;
+    return is64(P) ? eval_t<double>(P, out, st) : eval_t<float>(P, out, st);
 }
 
-asd_status asd_oracle(asd_plan* P, int32_t k, const float* x_prev, const float* z, uint32_t* mask_bits,
-                      float* LI, float* UI, hipStream_t st) {
+asd_status asd_oracle(asd_plan* P, int32_t k, const void* x_prev, const void* z, uint32_t* mask_bits, void* LI,
+                      void* UI, hipStream_t st) {
     if (!P || !x_prev || !z || !mask_bits || !LI || !UI) return fail(ASD_EINVAL, "NULL argument");
     if (!P->loaded) return fail(ASD_EINVAL, "asd_init has not been called");
     if (k < 1 || k >= P->n) return fail(ASD_EINVAL, "layer %d outside [1, %d]", k, P->n - 1);
-    OracleArgs a;
-    a.g = P->geo[k];
-    a.S = P->S;
-    a.xprev = x_prev;
-    a.z = z;
-    a.lo_in = P->na[k - 1].lo;
-    a.hi_in = P->na[k - 1].hi;
-    a.bits = mask_bits;
-    a.LI = LI;
-    a.UI = UI;
-    const long n = (long)P->S * a.g.out.N;
-    hipLaunchKernelGGL(k_oracle, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
-    LAUNCH_CHECK();
-    return ASD_OK;
+    if (is64(P))
+        return oracle_t<double>(P, k, reinterpret_cast<const double*>(x_prev), reinterpret_cast<const double*>(z),
+                                mask_bits, reinterpret_cast<double*>(LI), reinterpret_cast<double*>(UI), st);
+    return oracle_t<float>(P, k, reinterpret_cast<const float*>(x_prev), reinterpret_cast<const float*>(z),
+                           mask_bits, reinterpret_cast<float*>(LI), reinterpret_cast<float*>(UI), st);
 }
 
 asd_status asd_interval_bounds(const asd_net* net, int32_t S, const float* l0, const float* u0,

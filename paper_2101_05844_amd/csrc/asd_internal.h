@@ -7,9 +7,13 @@
 // so per-neuron state is read and written in contiguous 256-byte runs while
 // the weights a thread needs are uniform across the wavefront.
 //
-// Bit arrays (primal choices, compact masks, degenerate boxes) use bit index
+// Bit arrays (primal choices, compact masks, point boxes) use bit index
 // c * colpad + col with colpad = S * P rounded up to a multiple of 64, so one
 // wavefront's 64 bits are two whole 32-bit words written by a ballot.
+//
+// Precision.  A plan keeps its duals, moments, bounds and every intermediate
+// in T = float (the production form) or T = double (used to check whole runs
+// against the FP64 reference); network weights and caller inputs are FP32.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -43,55 +47,53 @@ struct LayerGeo {
     const float* b;
 };
 
-__host__ __device__ inline long nidx(const NeuronLayout& nl, int S, int c, int s, int p) {
-    return ((long)c * S + s) * nl.P + p;
-}
-__host__ __device__ inline long bidx(const NeuronLayout& nl, int c, long col) {
-    return (long)c * nl.colpad + col;
-}
-
-// Per-ReLU-layer device arrays inside the workspace.
-struct MaskSlot {
-    float* beta;   // beta_{k,I} >= 0
-    float* m;      // Adam moments
-    float* v;
-    float* LI;     // (W . I . Lcheck) row sums
-    float* UI;     // (W . (1 - I) . Ucheck) row sums
-    float* u;      // derived: (1 - z_I) * beta_{k,I}
+// Arrays of one active-set slot of a ReLU layer.
+template <typename T>
+struct MaskSlotT {
+    T* beta;   // beta_{k,I} >= 0
+    T* m;      // Adam moments
+    T* v;
+    T* LI;     // (W . I . Lcheck) row sums
+    T* UI;     // (W . (1 - I) . Ucheck) row sums
+    T* u;      // derived: (1 - z_I) * beta_{k,I}
     uint32_t* zbits;  // z*_k at addition (layout of layer k)
     uint32_t* xbits;  // x*_{k-1} == upper end at addition (layout of layer k-1)
 };
 
-struct ReluLayer {
-    float* lhat; float* uhat;             // pre-activation bounds
-    float* alpha; float* beta0; float* beta1;
-    float* alpha_m; float* alpha_v;
-    float* beta0_m; float* beta0_v;
-    float* beta1_m; float* beta1_v;
-    float* own;   // derived: alpha - beta0 - beta1 - sum_I beta_I
-    float* g;     // derived: g_k (eq:dual-anderson-functions)
-    float* vdn;   // derived: -alpha + beta1 + sum_I z_I beta_I (dense backward operand)
+// Arrays of one ReLU layer.
+template <typename T>
+struct ReluLayerT {
+    T* lhat; T* uhat;             // pre-activation bounds
+    T* alpha; T* beta0; T* beta1;
+    T* alpha_m; T* alpha_v;
+    T* beta0_m; T* beta0_v;
+    T* beta1_m; T* beta1_v;
+    T* own;   // derived: alpha - beta0 - beta1 - sum_I beta_I
+    T* g;     // derived: g_k (eq:dual-anderson-functions)
+    T* vdn;   // derived: -alpha + beta1 + sum_I z_I beta_I (dense backward operand)
     uint32_t* zbits;  // z*_k at the current iterate
-    MaskSlot slot[kMaxMasks];
-    // FP64 final evaluation scratch
+    MaskSlotT<T> slot[kMaxMasks];
+    // FP64 sums for the final bound of an FP32 plan
     double* own64; double* g64; double* const64;
 };
 
-struct NeuronArrays {
-    float* lo; float* hi;      // post-activation box (k = 0: input box)
-    float* xstar;              // current minimiser x*_k
+template <typename T>
+struct NeuronArraysT {
+    T* lo; T* hi;              // post-activation box (k = 0: input box)
+    T* xstar;                  // current minimiser x*_k
     uint32_t* xbits;           // x*_k == hi
     uint32_t* deg;             // lo == hi
     double* term;              // objective terms per neuron
 };
 
 // Adam / step arguments of one iteration.
-struct StepArgs {
+template <typename T>
+struct StepArgsT {
     int rule;          // asd_rule
-    float lr;
-    float b1, b2, eps;
-    float bc1[1 + kMaxMasks];   // 1 - b1^step for the alpha/beta group and each slot
-    float bc2[1 + kMaxMasks];
+    T lr;
+    T b1, b2, eps;
+    T bc1[1 + kMaxMasks];   // 1 - b1^step for the alpha/beta group and each slot
+    T bc2[1 + kMaxMasks];
 };
 
 }  // namespace asd

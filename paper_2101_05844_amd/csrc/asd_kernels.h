@@ -30,6 +30,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <type_traits>
+
 #include "asd_internal.h"
 
 namespace asd {
@@ -50,6 +52,11 @@ __device__ __forceinline__ void put_wave_bits(uint32_t* bits, long base, bool pr
         bits[(base >> 5) + 1] = (uint32_t)(m >> 32);
     }
 }
+
+template <typename T> __device__ __forceinline__ T tmax0(T a) { return a > (T)0 ? a : (T)0; }
+template <typename T> __device__ __forceinline__ T tmin0(T a) { return a < (T)0 ? a : (T)0; }
+__device__ __forceinline__ float tsqrt(float a) { return sqrtf(a); }
+__device__ __forceinline__ double tsqrt(double a) { return sqrt(a); }
 
 // ---------------------------------------------------------------------------
 // Tap enumeration of layer L's receptive field for output column (s, p).
@@ -88,22 +95,25 @@ __device__ __forceinline__ FwdTap fwd_tap(const LayerGeo& g, int S, int s, int p
 // ---------------------------------------------------------------------------
 // Forward pass: products, supergradient, update (or export) for ReLU layer k.
 // ---------------------------------------------------------------------------
+template <typename T>
 struct FwdArgs {
     LayerGeo g;                 // layer k
     int S;
     int nm;                     // active masks
-    const float* xin;           // x*_{k-1}
+    const T* xin;               // x*_{k-1}
     const uint32_t* deg_in;     // point boxes of layer k-1
-    const float* xout;          // x*_k
+    const T* xout;              // x*_k
     const uint32_t* zbits;      // z*_k
-    ReluLayer R;                // layer k arrays
-    StepArgs st;
+    ReluLayerT<T> R;            // layer k arrays
+    StepArgsT<T> st;
     int mode;                   // 0 update, 1 export supergradient
-    float* gout[3 + kMaxMasks]; // export targets, caller layout [S][n_k]
+    T* gout[3 + kMaxMasks];     // export targets, caller layout [S][n_k]
 };
 
-__global__ void __launch_bounds__(kWave * KS) k_forward(FwdArgs A) {
-    extern __shared__ float red[];  // [KS][CB][1 + nm][64]
+template <typename T>
+__global__ void __launch_bounds__(kWave * KS) k_forward(FwdArgs<T> A) {
+    extern __shared__ unsigned char red_raw[];
+    T* red = reinterpret_cast<T*>(red_raw);  // [KS][CB][1 + nm][64]
     const LayerGeo& g = A.g;
     const int lane = threadIdx.x, wave = threadIdx.y;
     const long col = (long)blockIdx.x * kWave + lane;
@@ -113,13 +123,13 @@ __global__ void __launch_bounds__(kWave * KS) k_forward(FwdArgs A) {
     const int s = colok ? (int)(col / g.out.P) : 0;
     const int p = colok ? (int)(col - (long)s * g.out.P) : 0;
 
-    float acc[CB];
-    float accm[kMaxMasks][CB];
+    T acc[CB];
+    T accm[kMaxMasks][CB];
 #pragma unroll
     for (int e = 0; e < CB; ++e) {
-        acc[e] = 0.f;
+        acc[e] = 0;
 #pragma unroll
-        for (int q = 0; q < kMaxMasks; ++q) accm[q][e] = 0.f;
+        for (int q = 0; q < kMaxMasks; ++q) accm[q][e] = 0;
     }
     const int F = g.fan;
     const int t0 = (int)((long)F * wave / KS), t1 = (int)((long)F * (wave + 1) / KS);
@@ -127,24 +137,23 @@ __global__ void __launch_bounds__(kWave * KS) k_forward(FwdArgs A) {
         for (int t = t0; t < t1; ++t) {
             const FwdTap tp = fwd_tap(g, S, s, p, t);
             const bool ok = tp.a >= 0;
-            const float x = ok ? A.xin[tp.a] : 0.f;
+            const T x = ok ? A.xin[tp.a] : (T)0;
             const unsigned dg = ok ? getbit(A.deg_in, tp.bi) : 0u;
-            float w[CB];
+            T w[CB];
 #pragma unroll
             for (int e = 0; e < CB; ++e) {
                 const int c = c0 + e;
-                w[e] = c < g.out.C ? g.W[(long)c * F + t] : 0.f;
-                acc[e] = fmaf(w[e], x, acc[e]);
+                w[e] = c < g.out.C ? (T)g.W[(long)c * F + t] : (T)0;
+                acc[e] += w[e] * x;
             }
 #pragma unroll
             for (int q = 0; q < kMaxMasks; ++q) {
                 if (q < nm) {
                     const unsigned xb = ok ? getbit(A.R.slot[q].xbits, tp.bi) : 0u;
-                    const float aL = (!xb || dg) ? x : 0.f;
-                    const float aH = (xb || dg) ? x : 0.f;
+                    const T aL = (!xb || dg) ? x : (T)0;
+                    const T aH = (xb || dg) ? x : (T)0;
 #pragma unroll
-                    for (int e = 0; e < CB; ++e)
-                        accm[q][e] = fmaf(fmaxf(w[e], 0.f), aL, fmaf(fminf(w[e], 0.f), aH, accm[q][e]));
+                    for (int e = 0; e < CB; ++e) accm[q][e] += tmax0(w[e]) * aL + tmin0(w[e]) * aH;
                 }
             }
         }
@@ -162,36 +171,36 @@ __global__ void __launch_bounds__(kWave * KS) k_forward(FwdArgs A) {
     const int e = wave;
     const int c = c0 + e;
     if (!colok || c >= g.out.C) return;
-    float yd = 0.f;
-    float ym[kMaxMasks];
+    T yd = 0;
+    T ym[kMaxMasks];
     for (int w = 0; w < KS; ++w) yd += red[((w * CB + e) * ncomp + 0) * kWave + lane];
 #pragma unroll
     for (int q = 0; q < kMaxMasks; ++q) {
-        ym[q] = 0.f;
+        ym[q] = 0;
         if (q < nm)
             for (int w = 0; w < KS; ++w) ym[q] += red[((w * CB + e) * ncomp + 1 + q) * kWave + lane];
     }
     const long idx = ((long)c * S + s) * g.out.P + p;
     const long bi = (long)c * g.out.colpad + col;
-    const float bb = g.b[c];
-    const float xhat = yd + bb;
-    const float x = A.xout[idx];
-    const float z = (float)getbit(A.zbits, bi);
-    const float lh = A.R.lhat[idx], uh = A.R.uhat[idx];
-    const float ga = xhat - x;
-    const float gb0 = x - z * uh;
-    const float gb1 = x - xhat + (1.f - z) * lh;
-    float gm[kMaxMasks];
-    float zq[kMaxMasks];
+    const T bb = (T)g.b[c];
+    const T xhat = yd + bb;
+    const T x = A.xout[idx];
+    const T z = (T)getbit(A.zbits, bi);
+    const T lh = A.R.lhat[idx], uh = A.R.uhat[idx];
+    const T ga = xhat - x;
+    const T gb0 = x - z * uh;
+    const T gb1 = x - xhat + ((T)1 - z) * lh;
+    T gm[kMaxMasks];
+    T zq[kMaxMasks];
 #pragma unroll
     for (int q = 0; q < kMaxMasks; ++q) {
-        gm[q] = 0.f;
-        zq[q] = 0.f;
+        gm[q] = 0;
+        zq[q] = 0;
         if (q < nm) {
-            const MaskSlot& M = A.R.slot[q];
-            zq[q] = (float)getbit(M.zbits, bi);
-            const float mq = zq[q] != 0.f ? yd : ym[q];
-            gm[q] = x - mq + M.LI[idx] * (1.f - z) - z * bb - M.UI[idx] * z;
+            const MaskSlotT<T>& M = A.R.slot[q];
+            zq[q] = (T)getbit(M.zbits, bi);
+            const T mq = zq[q] != (T)0 ? yd : ym[q];
+            gm[q] = x - mq + M.LI[idx] * ((T)1 - z) - z * bb - M.UI[idx] * z;
         }
     }
     if (A.mode == 1) {
@@ -204,36 +213,36 @@ __global__ void __launch_bounds__(kWave * KS) k_forward(FwdArgs A) {
             if (q < nm && A.gout[3 + q]) A.gout[3 + q][ex] = gm[q];
         return;
     }
-    const StepArgs& st = A.st;
-    auto step = [&](float th, float* m, float* v, float gr, int grp) -> float {
-        if (st.rule == ASD_RULE_SUPERGRADIENT) return fmaxf(th + st.lr * gr, 0.f);
-        float mm = st.b1 * m[idx] + (1.f - st.b1) * gr;
-        float vv = st.b2 * v[idx] + (1.f - st.b2) * gr * gr;
+    const StepArgsT<T>& st = A.st;
+    auto step = [&](T th, T* m, T* v, T gr, int grp) -> T {
+        if (st.rule == ASD_RULE_SUPERGRADIENT) return tmax0(th + st.lr * gr);
+        const T mm = st.b1 * m[idx] + ((T)1 - st.b1) * gr;
+        const T vv = st.b2 * v[idx] + ((T)1 - st.b2) * gr * gr;
         m[idx] = mm;
         v[idx] = vv;
-        const float mh = mm / st.bc1[grp];
-        const float vh = vv / st.bc2[grp];
-        return fmaxf(th + st.lr * mh / (sqrtf(vh) + st.eps), 0.f);
+        const T mh = mm / st.bc1[grp];
+        const T vh = vv / st.bc2[grp];
+        return tmax0(th + st.lr * mh / (tsqrt(vh) + st.eps));
     };
-    const float al = step(A.R.alpha[idx], A.R.alpha_m, A.R.alpha_v, ga, 0);
-    const float b0 = step(A.R.beta0[idx], A.R.beta0_m, A.R.beta0_v, gb0, 0);
-    const float b1 = step(A.R.beta1[idx], A.R.beta1_m, A.R.beta1_v, gb1, 0);
+    const T al = step(A.R.alpha[idx], A.R.alpha_m, A.R.alpha_v, ga, 0);
+    const T b0 = step(A.R.beta0[idx], A.R.beta0_m, A.R.beta0_v, gb0, 0);
+    const T b1 = step(A.R.beta1[idx], A.R.beta1_m, A.R.beta1_v, gb1, 0);
     A.R.alpha[idx] = al;
     A.R.beta0[idx] = b0;
     A.R.beta1[idx] = b1;
-    float own = al - b0 - b1;
-    float gg = b0 * uh + b1 * lh;
-    float vdn = -al + b1;
+    T own = al - b0 - b1;
+    T gg = b0 * uh + b1 * lh;
+    T vdn = -al + b1;
 #pragma unroll
     for (int q = 0; q < kMaxMasks; ++q) {
         if (q < nm) {
-            const MaskSlot& M = A.R.slot[q];
-            const float bq = step(M.beta[idx], M.m, M.v, gm[q], 1 + q);
+            const MaskSlotT<T>& M = A.R.slot[q];
+            const T bq = step(M.beta[idx], M.m, M.v, gm[q], 1 + q);
             M.beta[idx] = bq;
             own -= bq;
             gg += bq * (M.LI[idx] + M.UI[idx] + bb);
             vdn += zq[q] * bq;
-            M.u[idx] = (1.f - zq[q]) * bq;
+            M.u[idx] = ((T)1 - zq[q]) * bq;
         }
     }
     A.R.own[idx] = own;
@@ -243,9 +252,12 @@ __global__ void __launch_bounds__(kWave * KS) k_forward(FwdArgs A) {
 
 // ---------------------------------------------------------------------------
 // Backward pass: f_k, the inner minimisation, objective terms.
-// Template T = float (iterations, fixed-dual evaluation) or double (final
-// bound: every sum in FP64 from the FP32 duals and weights).
+// Tc = compute type, Ts = state type.  Tc == Ts in the iterations (and for the
+// final bound of an FP64 plan); Tc = double, Ts = float for the final bound of
+// an FP32 plan: then every sum runs in FP64 from the FP32 duals, with the
+// per-neuron sums from k_mask_consts<double, float>.
 // ---------------------------------------------------------------------------
+template <typename Ts>
 struct BwdArgs {
     LayerGeo gn;                // layer k+1 (its input layout is layer k)
     int S;
@@ -253,29 +265,29 @@ struct BwdArgs {
     int last;                   // k + 1 == n: backward operand is -c
     int nm_next;                // active masks of layer k+1 (0 if last)
     int nm_own;                 // active masks of layer k (k >= 1)
-    const float* cvec;          // objective rows, layout of layer n
-    ReluLayer Rn;               // layer k+1 arrays (if not last)
-    ReluLayer Rk;               // layer k arrays (if k >= 1)
-    NeuronArrays nk;            // layer k box, outputs
+    const Ts* cvec;             // objective rows, layout of layer n
+    ReluLayerT<Ts> Rn;          // layer k+1 arrays (if not last)
+    ReluLayerT<Ts> Rk;          // layer k arrays (if k >= 1)
+    NeuronArraysT<Ts> nk;       // layer k box, outputs
     const float* bk;            // bias of layer k (k >= 1), per channel
     int want_obj;
 };
 
-template <typename T>
-__device__ __forceinline__ T bwd_operand(const BwdArgs& A, long a, long bi, T* uq) {
+template <typename Tc, typename Ts>
+__device__ __forceinline__ Tc bwd_operand(const BwdArgs<Ts>& A, long a, long bi, Tc* uq) {
     // dense operand v and masked operands u_q at output neuron address a of layer k+1
-    if (A.last) return -(T)A.cvec[a];
-    if (sizeof(T) == 4) {
+    if (A.last) return -(Tc)A.cvec[a];
+    if (sizeof(Tc) == sizeof(Ts)) {
 #pragma unroll
         for (int q = 0; q < kMaxMasks; ++q)
-            if (q < A.nm_next) uq[q] = (T)A.Rn.slot[q].u[a];
-        return (T)A.Rn.vdn[a];
+            if (q < A.nm_next) uq[q] = (Tc)A.Rn.slot[q].u[a];
+        return (Tc)A.Rn.vdn[a];
     }
-    T v = -(T)A.Rn.alpha[a] + (T)A.Rn.beta1[a];
+    Tc v = -(Tc)A.Rn.alpha[a] + (Tc)A.Rn.beta1[a];
 #pragma unroll
     for (int q = 0; q < kMaxMasks; ++q) {
         if (q < A.nm_next) {
-            const T bq = (T)A.Rn.slot[q].beta[a];
+            const Tc bq = (Tc)A.Rn.slot[q].beta[a];
             const unsigned zb = getbit(A.Rn.slot[q].zbits, bi);
             if (zb) {
                 v += bq;
@@ -288,10 +300,11 @@ __device__ __forceinline__ T bwd_operand(const BwdArgs& A, long a, long bi, T* u
     return v;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kWave * KS) k_backward(BwdArgs A) {
+template <typename Tc, typename Ts>
+__global__ void __launch_bounds__(kWave * KS) k_backward(BwdArgs<Ts> A) {
     extern __shared__ unsigned char red_raw[];
-    T* red = reinterpret_cast<T*>(red_raw);  // [KS][CB][64]
+    Tc* red = reinterpret_cast<Tc*>(red_raw);  // [KS][CB][64]
+    constexpr bool kFinal64 = sizeof(Tc) > sizeof(Ts);
     const LayerGeo& g = A.gn;
     const NeuronLayout& L = g.in;   // layer k
     const NeuronLayout& O = g.out;  // layer k+1
@@ -303,8 +316,8 @@ __global__ void __launch_bounds__(kWave * KS) k_backward(BwdArgs A) {
     const int s = colok ? (int)(col / L.P) : 0;
     const int p = colok ? (int)(col - (long)s * L.P) : 0;
 
-    T acc[CB];
-    T accP[kMaxMasks][CB], accQ[kMaxMasks][CB];
+    Tc acc[CB];
+    Tc accP[kMaxMasks][CB], accQ[kMaxMasks][CB];
 #pragma unroll
     for (int e = 0; e < CB; ++e) {
         acc[e] = 0;
@@ -319,18 +332,18 @@ __global__ void __launch_bounds__(kWave * KS) k_backward(BwdArgs A) {
             for (int i = i0; i < i1; ++i) {
                 const long a = (long)i * S + s;  // dense output layout, P = 1
                 const long bi = (long)i * O.colpad + s;
-                T uq[kMaxMasks];
-                const T v = bwd_operand<T>(A, a, bi, uq);
+                Tc uq[kMaxMasks];
+                const Tc v = bwd_operand<Tc, Ts>(A, a, bi, uq);
 #pragma unroll
                 for (int e = 0; e < CB; ++e) {
                     const int c = c0 + e;
-                    const T w = c < L.C ? (T)g.W[(long)i * g.fan + (long)c * L.P + p] : (T)0;
+                    const Tc w = c < L.C ? (Tc)g.W[(long)i * g.fan + (long)c * L.P + p] : (Tc)0;
                     acc[e] += w * v;
 #pragma unroll
                     for (int q = 0; q < kMaxMasks; ++q) {
                         if (q < nm) {
-                            accP[q][e] += (w > 0 ? w : (T)0) * uq[q];
-                            accQ[q][e] += (w < 0 ? w : (T)0) * uq[q];
+                            accP[q][e] += tmax0(w) * uq[q];
+                            accQ[q][e] += tmin0(w) * uq[q];
                         }
                     }
                 }
@@ -352,18 +365,18 @@ __global__ void __launch_bounds__(kWave * KS) k_backward(BwdArgs A) {
                         const int op = oy * O.W + ox;
                         const long a = ((long)co * S + s) * O.P + op;
                         const long bi = (long)co * O.colpad + (long)s * O.P + op;
-                        T uq[kMaxMasks];
-                        const T v = bwd_operand<T>(A, a, bi, uq);
+                        Tc uq[kMaxMasks];
+                        const Tc v = bwd_operand<Tc, Ts>(A, a, bi, uq);
 #pragma unroll
                         for (int e = 0; e < CB; ++e) {
                             const int c = c0 + e;
-                            const T w = c < L.C ? (T)g.W[(((long)co * L.C + c) * ks + ky) * ks + kx] : (T)0;
+                            const Tc w = c < L.C ? (Tc)g.W[(((long)co * L.C + c) * ks + ky) * ks + kx] : (Tc)0;
                             acc[e] += w * v;
 #pragma unroll
                             for (int q = 0; q < kMaxMasks; ++q) {
                                 if (q < nm) {
-                                    accP[q][e] += (w > 0 ? w : (T)0) * uq[q];
-                                    accQ[q][e] += (w < 0 ? w : (T)0) * uq[q];
+                                    accP[q][e] += tmax0(w) * uq[q];
+                                    accQ[q][e] += tmin0(w) * uq[q];
                                 }
                             }
                         }
@@ -392,7 +405,7 @@ __global__ void __launch_bounds__(kWave * KS) k_backward(BwdArgs A) {
         }
 #pragma unroll
         for (int e = 0; e < CB; ++e) {
-            T part = acc[e];
+            Tc part = acc[e];
             const bool dg = (dg4 >> e) & 1u;
 #pragma unroll
             for (int q = 0; q < kMaxMasks; ++q) {
@@ -410,36 +423,28 @@ __global__ void __launch_bounds__(kWave * KS) k_backward(BwdArgs A) {
     const int c = c0 + e;
     if (c >= L.C) return;  // whole wave leaves together
     const long idx = ((long)c * S + s) * L.P + p;
-    T f = 0;
+    Tc f = 0;
     bool xb = false, zb = false;
     if (colok) {
         for (int w = 0; w < KS; ++w) f += red[(w * CB + e) * kWave + lane];
         const int nmo = A.nm_own;
-        if (A.k >= 1) {
-            if (sizeof(T) == 4) {
-                f += (T)A.Rk.own[idx];
-            } else {
-                f += (T)A.Rk.own64[idx];
-            }
-        }
+        if (A.k >= 1) f += kFinal64 ? (Tc)A.Rk.own64[idx] : (Tc)A.Rk.own[idx];
         xb = f >= 0;
-        const T xv = xb ? (T)A.nk.hi[idx] : (T)A.nk.lo[idx];
-        A.nk.xstar[idx] = (float)xv;
-        T term = -f * xv;
+        const Tc xv = xb ? (Tc)A.nk.hi[idx] : (Tc)A.nk.lo[idx];
+        A.nk.xstar[idx] = (Ts)xv;
+        Tc term = -f * xv;
         if (A.k >= 1) {
-            T gk;
-            if (sizeof(T) == 4) gk = (T)A.Rk.g[idx];
-            else gk = (T)A.Rk.g64[idx];
+            const Tc gk = kFinal64 ? (Tc)A.Rk.g64[idx] : (Tc)A.Rk.g[idx];
             zb = gk >= 0;
-            term -= zb ? gk : (T)0;
+            term -= zb ? gk : (Tc)0;
             if (A.want_obj) {
-                if (sizeof(T) == 4) {
-                    const T bb = (T)A.bk[c];
-                    T cst = bb * (T)A.Rk.alpha[idx] + (T)A.Rk.beta1[idx] * ((T)A.Rk.lhat[idx] - bb);
-                    for (int q = 0; q < nmo; ++q) cst += (T)A.Rk.slot[q].LI[idx] * (T)A.Rk.slot[q].beta[idx];
-                    term += cst;
+                if (kFinal64) {
+                    term += (Tc)A.Rk.const64[idx];
                 } else {
-                    term += (T)A.Rk.const64[idx];
+                    const Tc bb = (Tc)A.bk[c];
+                    Tc cst = bb * (Tc)A.Rk.alpha[idx] + (Tc)A.Rk.beta1[idx] * ((Tc)A.Rk.lhat[idx] - bb);
+                    for (int q = 0; q < nmo; ++q) cst += (Tc)A.Rk.slot[q].LI[idx] * (Tc)A.Rk.slot[q].beta[idx];
+                    term += cst;
                 }
             }
         }
@@ -450,46 +455,44 @@ __global__ void __launch_bounds__(kWave * KS) k_backward(BwdArgs A) {
     if (A.k >= 1) put_wave_bits(A.Rk.zbits, base, colok && zb, lane);
 }
 
-template __global__ void k_backward<float>(BwdArgs);
-template __global__ void k_backward<double>(BwdArgs);
-
 // ---------------------------------------------------------------------------
-// Active-set extension: store the compact mask of slot q of ReLU layer k and
-// its constants LI, UI (T = float), or recompute every active slot's
-// constants in FP64 and the FP64 per-neuron sums of the final bound
-// (T = double).
+// Active-set extension: the constants LI, UI of slot q of ReLU layer k from
+// the given compact mask bits (Tc == Ts), or, for the final bound of an FP32
+// plan (Tc = double, Ts = float), every active slot's constants in FP64 and
+// the FP64 per-neuron sums of the bound.
 // ---------------------------------------------------------------------------
+template <typename Ts>
 struct MaskArgs {
     LayerGeo g;                 // layer k
     int S;
-    int q;                      // slot to fill (T = float)
-    int nm;                     // active masks (T = double)
-    const float* lo_in; const float* hi_in;   // box of layer k-1
-    const uint32_t* zsrc;       // z bits of layer k (T = float)
-    const uint32_t* xsrc;       // x*_{k-1} == hi bits of layer k-1 (T = float)
-    int zero_state;             // T = float: also zero the slot's beta, moments, u
+    int q;                      // slot to fill (Tc == Ts)
+    int nm;                     // active masks (final sums)
+    const Ts* lo_in; const Ts* hi_in;   // box of layer k-1
+    const uint32_t* zsrc;       // z bits of layer k (Tc == Ts)
+    const uint32_t* xsrc;       // x*_{k-1} == hi bits of layer k-1 (Tc == Ts)
+    int zero_state;             // Tc == Ts: also zero the slot's beta, moments, u
     const uint32_t* deg_in;
-    ReluLayer R;
+    ReluLayerT<Ts> R;
 };
 
-template <typename T>
-__global__ void __launch_bounds__(kWave * KS) k_mask_consts(MaskArgs A) {
+template <typename Tc, typename Ts>
+__global__ void __launch_bounds__(kWave * KS) k_mask_consts(MaskArgs<Ts> A) {
     extern __shared__ unsigned char red_raw[];
-    T* red = reinterpret_cast<T*>(red_raw);  // [KS][CB][2][64]
+    Tc* red = reinterpret_cast<Tc*>(red_raw);  // [KS][CB][2][64]
+    constexpr bool kFinal64 = sizeof(Tc) > sizeof(Ts);
     const LayerGeo& g = A.g;
     const int lane = threadIdx.x, wave = threadIdx.y;
     const long col = (long)blockIdx.x * kWave + lane;
     const int c0 = blockIdx.y * CB;
     const int S = A.S;
-    const bool f64 = sizeof(T) == 8;
-    const int q0 = f64 ? 0 : A.q;
-    const int nsl = f64 ? A.nm : 1;
+    const int q0 = kFinal64 ? 0 : A.q;
+    const int nsl = kFinal64 ? A.nm : 1;
     const bool colok = col < g.out.cols;
     const int s = colok ? (int)(col / g.out.P) : 0;
     const int p = colok ? (int)(col - (long)s * g.out.P) : 0;
     const long bicol0 = (long)c0 * g.out.colpad + col;
 
-    T LI[kMaxMasks][CB], UI[kMaxMasks][CB];
+    Tc LI[kMaxMasks][CB], UI[kMaxMasks][CB];
     unsigned zmask[kMaxMasks];
 #pragma unroll
     for (int j = 0; j < kMaxMasks; ++j) {
@@ -501,7 +504,7 @@ __global__ void __launch_bounds__(kWave * KS) k_mask_consts(MaskArgs A) {
 #pragma unroll
         for (int j = 0; j < kMaxMasks; ++j) {
             if (j < nsl) {
-                const uint32_t* zb = f64 ? A.R.slot[q0 + j].zbits : A.zsrc;
+                const uint32_t* zb = kFinal64 ? A.R.slot[q0 + j].zbits : A.zsrc;
 #pragma unroll
                 for (int e = 0; e < CB; ++e)
                     if (c0 + e < g.out.C) zmask[j] |= getbit(zb, bicol0 + (long)e * g.out.colpad) << e;
@@ -512,20 +515,20 @@ __global__ void __launch_bounds__(kWave * KS) k_mask_consts(MaskArgs A) {
         for (int t = t0; t < t1; ++t) {
             const FwdTap tp = fwd_tap(g, S, s, p, t);
             if (tp.a < 0) continue;
-            const T lo = (T)A.lo_in[tp.a], hi = (T)A.hi_in[tp.a];
+            const Tc lo = (Tc)A.lo_in[tp.a], hi = (Tc)A.hi_in[tp.a];
             const unsigned dg = getbit(A.deg_in, tp.bi);
 #pragma unroll
             for (int j = 0; j < kMaxMasks; ++j) {
                 if (j < nsl) {
-                    const uint32_t* xbits = f64 ? A.R.slot[q0 + j].xbits : A.xsrc;
+                    const uint32_t* xbits = kFinal64 ? A.R.slot[q0 + j].xbits : A.xsrc;
                     const unsigned xb = getbit(xbits, tp.bi);
                     const bool eL = !xb || dg, eH = xb || dg;
 #pragma unroll
                     for (int e = 0; e < CB; ++e) {
                         const int c = c0 + e;
-                        const T w = c < g.out.C ? (T)g.W[(long)c * F + t] : (T)0;
-                        const T wl = w >= 0 ? w * lo : w * hi;   // W . Lcheck
-                        const T wu = w >= 0 ? w * hi : w * lo;   // W . Ucheck
+                        const Tc w = c < g.out.C ? (Tc)g.W[(long)c * F + t] : (Tc)0;
+                        const Tc wl = w >= 0 ? w * lo : w * hi;   // W . Lcheck
+                        const Tc wu = w >= 0 ? w * hi : w * lo;   // W . Ucheck
                         const bool zi = (zmask[j] >> e) & 1u;
                         const bool bit = zi || (w > 0 ? eL : (w < 0 ? eH : true));
                         if (bit) LI[j][e] += wl;
@@ -535,14 +538,13 @@ __global__ void __launch_bounds__(kWave * KS) k_mask_consts(MaskArgs A) {
             }
         }
     }
-    // FP32 (one slot): reduce LI and UI.  FP64 (every active slot): each wave
-    // folds its partial LI/UI of all slots with the slot multipliers into the
-    // two sums the final bound needs, sum_q beta_q (LI_q + UI_q) and
-    // sum_q beta_q LI_q, then the waves' partials are reduced.
+    // one slot: reduce LI and UI.  Final sums: each wave folds its partial
+    // LI/UI of all slots with the slot multipliers into the two sums the
+    // bound needs, sum_q beta_q (LI_q + UI_q) and sum_q beta_q LI_q.
 #pragma unroll
     for (int e = 0; e < CB; ++e) {
-        T r0 = 0, r1 = 0;
-        if (!f64) {
+        Tc r0 = 0, r1 = 0;
+        if (!kFinal64) {
             r0 = LI[0][e];
             r1 = UI[0][e];
         } else if (colok && c0 + e < g.out.C) {
@@ -550,7 +552,7 @@ __global__ void __launch_bounds__(kWave * KS) k_mask_consts(MaskArgs A) {
 #pragma unroll
             for (int j = 0; j < kMaxMasks; ++j) {
                 if (j < nsl) {
-                    const T bq = (T)A.R.slot[j].beta[idx_e];
+                    const Tc bq = (Tc)A.R.slot[j].beta[idx_e];
                     r0 += bq * (LI[j][e] + UI[j][e]);
                     r1 += bq * LI[j][e];
                 }
@@ -564,20 +566,20 @@ __global__ void __launch_bounds__(kWave * KS) k_mask_consts(MaskArgs A) {
     const int c = c0 + e;
     if (!colok || c >= g.out.C) return;
     const long idx = ((long)c * S + s) * g.out.P + p;
-    T r0 = 0, r1 = 0;
+    Tc r0 = 0, r1 = 0;
     for (int w = 0; w < KS; ++w) {
         r0 += red[((w * CB + e) * 2 + 0) * kWave + lane];
         r1 += red[((w * CB + e) * 2 + 1) * kWave + lane];
     }
-    if (!f64) {
-        MaskSlot M = A.R.slot[q0];
-        M.LI[idx] = (float)r0;
-        M.UI[idx] = (float)r1;
+    if (!kFinal64) {
+        MaskSlotT<Ts> M = A.R.slot[q0];
+        M.LI[idx] = (Ts)r0;
+        M.UI[idx] = (Ts)r1;
         if (A.zero_state) {
-            M.beta[idx] = 0.f;
-            M.m[idx] = 0.f;
-            M.v[idx] = 0.f;
-            M.u[idx] = 0.f;
+            M.beta[idx] = 0;
+            M.m[idx] = 0;
+            M.v[idx] = 0;
+            M.u[idx] = 0;
         }
         return;
     }
@@ -595,9 +597,6 @@ __global__ void __launch_bounds__(kWave * KS) k_mask_consts(MaskArgs A) {
     A.R.const64[idx] = bb * al + b1 * (lh - bb) + (double)r1;
 }
 
-template __global__ void k_mask_consts<float>(MaskArgs);
-template __global__ void k_mask_consts<double>(MaskArgs);
-
 // Copies n 32-bit words.
 __global__ void k_copy_words(uint32_t* dst, const uint32_t* src, long n) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -611,35 +610,37 @@ __global__ void k_zero_words(uint32_t* dst, long n) {
 }
 
 // Recomputes the derived per-neuron sums from the duals (after an import or
-// at initialisation): own, g, vdn and u_q (FP32).
+// at initialisation): own, g, vdn and u_q.
+template <typename T>
 struct DeriveArgs {
     NeuronLayout nl;
     int S;
     int nm;
     const float* b;
-    ReluLayer R;
+    ReluLayerT<T> R;
 };
 
-__global__ void k_derive(DeriveArgs A) {
+template <typename T>
+__global__ void k_derive(DeriveArgs<T> A) {
     const long col = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
     if (col >= A.nl.cols) return;
     const int s = (int)(col / A.nl.P), p = (int)(col - (long)s * A.nl.P);
     const long idx = ((long)c * A.S + s) * A.nl.P + p;
     const long bi = (long)c * A.nl.colpad + col;
-    const float al = A.R.alpha[idx], b0 = A.R.beta0[idx], b1 = A.R.beta1[idx];
-    const float bb = A.b[c];
-    float own = al - b0 - b1;
-    float gg = b0 * A.R.uhat[idx] + b1 * A.R.lhat[idx];
-    float vdn = -al + b1;
+    const T al = A.R.alpha[idx], b0 = A.R.beta0[idx], b1 = A.R.beta1[idx];
+    const T bb = (T)A.b[c];
+    T own = al - b0 - b1;
+    T gg = b0 * A.R.uhat[idx] + b1 * A.R.lhat[idx];
+    T vdn = -al + b1;
     for (int q = 0; q < A.nm; ++q) {
-        const MaskSlot& M = A.R.slot[q];
-        const float bq = M.beta[idx];
-        const float zq = (float)getbit(M.zbits, bi);
+        const MaskSlotT<T>& M = A.R.slot[q];
+        const T bq = M.beta[idx];
+        const T zq = (T)getbit(M.zbits, bi);
         own -= bq;
         gg += bq * (M.LI[idx] + M.UI[idx] + bb);
         vdn += zq * bq;
-        M.u[idx] = (1.f - zq) * bq;
+        M.u[idx] = ((T)1 - zq) * bq;
     }
     A.R.own[idx] = own;
     A.R.g[idx] = gg;
@@ -648,35 +649,42 @@ __global__ void k_derive(DeriveArgs A) {
 
 // ---------------------------------------------------------------------------
 // Layout conversion between the caller's [S][N] arrays and the internal one.
+// mode 0: int = ext; 1: int = max(ext, 0); 2: ext = int.
 // ---------------------------------------------------------------------------
-// mode 0: dst_int = src_ext; 1: dst_int = max(src_ext, 0); 2: dst_ext = src_int
-__global__ void k_layout(float* dst, const float* src, NeuronLayout nl, int S, int mode) {
+template <typename Ti, typename Te>
+__global__ void k_layout(Ti* in_arr, Te* ex_arr, NeuronLayout nl, int S, int mode) {
     const long col = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
     if (col >= nl.cols) return;
     const int s = (int)(col / nl.P), p = (int)(col - (long)s * nl.P);
     const long in_ = ((long)c * S + s) * nl.P + p;
     const long ex = (long)s * nl.N + (long)c * nl.P + p;
-    if (mode == 0) dst[in_] = src[ex];
-    else if (mode == 1) dst[in_] = fmaxf(src[ex], 0.f);
-    else dst[ex] = src[in_];
+    if (mode == 0) {
+        in_arr[in_] = (Ti)ex_arr[ex];
+    } else if (mode == 1) {
+        in_arr[in_] = ex_arr[ex] > 0 ? (Ti)ex_arr[ex] : (Ti)0;
+    } else {
+        if constexpr (!std::is_const<Te>::value) ex_arr[ex] = (Te)in_arr[in_];
+    }
 }
 
-// Bits of an internal bit array -> caller [S][N] floats (0/1, mode 0), or
-// "value == hi" bits from caller floats (mode 1), or "value >= 0.5" (mode 2),
+// Bits of an internal bit array -> caller [S][N] values 0/1 (mode 0), or
+// "value == hi" bits from caller values (mode 1), or "value >= 0.5" (mode 2),
 // or point-box bits lo == hi from internal arrays (mode 3), or bits ->
 // caller values hi / lo (mode 4).
+template <typename T, typename Te>
 struct BitArgs {
     NeuronLayout nl;
     int S;
     int mode;
     uint32_t* bits;
-    float* fext;
-    const float* hi;   // internal (mode 1)
-    const float* lo;   // internal (mode 3)
+    Te* fext;
+    const T* hi;   // internal (modes 1, 3, 4)
+    const T* lo;   // internal (modes 3, 4)
 };
 
-__global__ void k_bits(BitArgs A) {
+template <typename T, typename Te>
+__global__ void k_bits(BitArgs<T, Te> A) {
     const int lane = threadIdx.x & 63;
     const long col = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
@@ -687,35 +695,37 @@ __global__ void k_bits(BitArgs A) {
     const long ex = (long)s * A.nl.N + (long)c * A.nl.P + p;
     const long bi = (long)c * A.nl.colpad + col;
     if (A.mode == 0) {
-        if (ok) A.fext[ex] = (float)getbit(A.bits, bi);
+        if (ok) A.fext[ex] = (Te)getbit(A.bits, bi);
         return;
     }
     if (A.mode == 4) {
-        if (ok) A.fext[ex] = getbit(A.bits, bi) ? A.hi[in_] : A.lo[in_];
+        if (ok) A.fext[ex] = (Te)(getbit(A.bits, bi) ? A.hi[in_] : A.lo[in_]);
         return;
     }
     bool pred = false;
     if (ok) {
-        if (A.mode == 1) pred = A.fext[ex] == A.hi[in_];
-        else if (A.mode == 2) pred = A.fext[ex] >= 0.5f;
+        if (A.mode == 1) pred = (T)A.fext[ex] == A.hi[in_];
+        else if (A.mode == 2) pred = A.fext[ex] >= (Te)0.5;
         else pred = A.lo[in_] == A.hi[in_];
     }
     if (col - lane < A.nl.colpad) put_wave_bits(A.bits, (long)c * A.nl.colpad + (col - lane), pred, lane);
 }
 
 // Per-subproblem objective: sum of every neuron term (fixed order) plus b_n^T c.
+template <typename T>
 struct ReduceArgs {
     int S;
     int nlayers;                       // neuron layers 0..n-1
     NeuronLayout nl[kMaxLayers];
     const double* term[kMaxLayers];
-    const float* cint;                 // objective rows, internal layout [n_last][S]
+    const T* cint;                     // objective rows, internal layout [n_last][S]
     const float* bn;
     int n_last;
     double* out;
 };
 
-__global__ void __launch_bounds__(256) k_reduce_obj(ReduceArgs A) {
+template <typename T>
+__global__ void __launch_bounds__(256) k_reduce_obj(ReduceArgs<T> A) {
     __shared__ double part[256];
     const int s = blockIdx.x;
     double acc = 0;
@@ -741,27 +751,29 @@ __global__ void __launch_bounds__(256) k_reduce_obj(ReduceArgs A) {
 // General separation oracle (eq:oracle) at an arbitrary primal point, caller
 // layout: x_prev [S][n_{k-1}], z [S][n_k]; bits [S][n_k][ceil(F/32)].
 // ---------------------------------------------------------------------------
+template <typename T>
 struct OracleArgs {
     LayerGeo g;
     int S;
-    const float* xprev;
-    const float* z;
-    const float* lo_in; const float* hi_in;  // internal layout, layer k-1
+    const T* xprev;
+    const T* z;
+    const T* lo_in; const T* hi_in;  // internal layout, layer k-1
     uint32_t* bits;
-    float* LI; float* UI;
+    T* LI; T* UI;
 };
 
-__global__ void k_oracle(OracleArgs A) {
+template <typename T>
+__global__ void k_oracle(OracleArgs<T> A) {
     const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const LayerGeo& g = A.g;
     if (gid >= (long)A.S * g.out.N) return;
     const int s = (int)(gid / g.out.N);
     const long i = gid - (long)s * g.out.N;
     const int c = (int)(i / g.out.P), p = (int)(i - (long)c * g.out.P);
-    const float zi = A.z[gid];
+    const T zi = A.z[gid];
     const int F = g.fan, nw = (F + 31) / 32;
     uint32_t word = 0;
-    float LI = 0.f, UI = 0.f;
+    T LI = 0, UI = 0;
     for (int t = 0; t < F; ++t) {
         const FwdTap tp = fwd_tap(g, A.S, s, p, t);
         bool bit = false;
@@ -769,14 +781,15 @@ __global__ void k_oracle(OracleArgs A) {
             // caller index of the input neuron
             const long ci = tp.a / ((long)A.S * g.in.P);
             const long pin = tp.a - (ci * A.S + s) * g.in.P;
-            const float x = A.xprev[(long)s * g.in.N + ci * g.in.P + pin];
-            const float lo = A.lo_in[tp.a], hi = A.hi_in[tp.a];
-            const float w = g.W[(long)c * F + t];
-            const float Lc = w >= 0 ? lo : hi, Uc = w >= 0 ? hi : lo;
-            const float d = (1.f - zi) * Lc + zi * Uc - x;
-            bit = (d == 0.f) || (w == 0.f) || ((d > 0.f) == (w > 0.f));
-            if (bit) LI = fmaf(w, Lc, LI);
-            else UI = fmaf(w, Uc, UI);
+            const T x = A.xprev[(long)s * g.in.N + ci * g.in.P + pin];
+            const T lo = A.lo_in[tp.a], hi = A.hi_in[tp.a];
+            const T w = (T)g.W[(long)c * F + t];
+            const T Lc = w >= 0 ? lo : hi, Uc = w >= 0 ? hi : lo;
+            const T d = ((T)1 - zi) * Lc + zi * Uc - x;
+            // sign of d * w without forming the product (no underflow to 0)
+            bit = (d == (T)0) || (w == (T)0) || ((d > (T)0) == (w > (T)0));
+            if (bit) LI += w * Lc;
+            else UI += w * Uc;
         }
         if (bit) word |= 1u << (t & 31);
         if ((t & 31) == 31 || t == F - 1) {
@@ -790,9 +803,9 @@ __global__ void k_oracle(OracleArgs A) {
 
 // ---------------------------------------------------------------------------
 // Interval propagation (App. E), FP64 sums, outward rounding to FP32.
-// Caller layout; lo_in/hi_in are the previous layer's post-activation box
-// (for layer 1 the input box; later layers read the pre-activation bounds
-// of the previous layer and clamp at 0).
+// Caller layout; lo_in/hi_in are the previous layer's bounds (for layer 1 the
+// input box; later layers read the pre-activation bounds of the previous
+// layer and clamp at 0).
 // ---------------------------------------------------------------------------
 struct IbpArgs {
     LayerGeo g;

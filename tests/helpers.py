@@ -68,7 +68,7 @@ def import_states(plan, problems, states):
     n = problems[0].n
     S = len(states)
     dev = "cuda"
-    t = lambda rows: torch.as_tensor(f32(np.stack(rows)), device=dev)
+    t = lambda rows: torch.as_tensor(np.stack(rows), device=dev).to(plan.dtype)
     K = len(states[0].masks[0]) if n > 1 else 0
     for k in range(1, n):
         plan.set(A.ASD_F_ALPHA, k, t([st.alpha[k - 1] for st in states]))

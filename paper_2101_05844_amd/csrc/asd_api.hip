@@ -1,5 +1,7 @@
 // Host side of libasdual: validation, workspace layout, and the iteration
-// driver of Algorithm 1 / Algorithm 3 (kernels in asd_kernels.h).
+// driver of Algorithm 1 / Algorithm 3.  Iterations run the kernels of
+// asd_fast.h; evaluation at fixed duals, the final bound and the oracle run
+// the general kernels of asd_kernels.h.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -7,12 +9,13 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <type_traits>
 #include <vector>
 
-#include "asd_kernels.h"
+#include "asd_fast.h"
 
 using namespace asd;
 
@@ -89,6 +92,15 @@ struct asd_plan {
     ReluLayerT<double> Rd[kMaxLayers];
     float* cvecf;
     double* cvecd;
+    // weight copies made at asd_init and iteration buffers
+    float* Wt[kMaxLayers + 1];        // [fan][Cpad] (ReLU layers)
+    int Cpad[kMaxLayers + 1];
+    float* Wr[kMaxLayers + 1];        // [n_out][fanpad] (dense layers)
+    int fanpad[kMaxLayers + 1];
+    int ksplit[kMaxLayers + 1];       // dense forward: blocks over the fan-in
+    void* part;                       // dense forward partial products
+    int* pointflag;                   // [kMaxLayers]: point box away from zero in layer k
+    void* Rdev;                       // device copy of the ReluLayerT array (update kernels)
     // scalar state
     int n_masks;
     int step;
@@ -109,6 +121,7 @@ template <> NeuronArraysT<double>* NA<double>(asd_plan* P) { return P->nad; }
 template <typename T> ReluLayerT<T>* RL(asd_plan* P);
 template <> ReluLayerT<float>* RL<float>(asd_plan* P) { return P->Rf; }
 template <> ReluLayerT<double>* RL<double>(asd_plan* P) { return P->Rd; }
+template <typename T> ReluLayerT<T>* RdevT(asd_plan* P) { return reinterpret_cast<ReluLayerT<T>*>(P->Rdev); }
 template <typename T> T* CV(asd_plan* P);
 template <> float* CV<float>(asd_plan* P) { return P->cvecf; }
 template <> double* CV<double>(asd_plan* P) { return P->cvecd; }
@@ -168,6 +181,7 @@ void carve_t(asd_plan* P, Carver& cv) {
         a.xbits = cv.take<uint32_t>(nl.words);
         a.deg = cv.take<uint32_t>(nl.words);
         a.term = cv.take<double>(ns);
+        a.xpk = k + 1 < P->n ? cv.take<uint16_t>(ns) : nullptr;
     }
     for (int k = 1; k < P->n; ++k) {
         const NeuronLayout& nl = P->nl[k];
@@ -187,8 +201,9 @@ void carve_t(asd_plan* P, Carver& cv) {
         r.beta1_v = cv.take<T>(ns);
         r.own = cv.take<T>(ns);
         r.g = cv.take<T>(ns);
-        r.vdn = cv.take<T>(ns);
+        r.vs = cv.take<T>(ns);
         r.zbits = cv.take<uint32_t>(nl.words);
+        r.zpk = cv.take<uint8_t>(ns);
         if (sizeof(T) == 4) {
             r.own64 = cv.take<double>(ns);
             r.g64 = cv.take<double>(ns);
@@ -209,6 +224,19 @@ void carve_t(asd_plan* P, Carver& cv) {
     T* cv_arr = cv.take<T>((size_t)P->nl[P->n].N * S);
     if (sizeof(T) == 4) P->cvecf = reinterpret_cast<float*>(cv_arr);
     else P->cvecd = reinterpret_cast<double*>(cv_arr);
+    size_t part = 0;
+    for (int L = 1; L <= P->n; ++L) {
+        const LayerGeo& g = P->geo[L];
+        if (L < P->n) P->Wt[L] = cv.take<float>((size_t)g.fan * P->Cpad[L]);
+        if (g.kind == ASD_LAYER_DENSE) {
+            P->Wr[L] = cv.take<float>((size_t)g.out.C * P->fanpad[L]);
+            if (L < P->n)
+                part = std::max(part, (size_t)P->ksplit[L] * (1 + P->prm.max_masks) * P->Cpad[L] * S);
+        }
+    }
+    P->part = cv.take<T>(part);
+    P->pointflag = cv.take<int>(kMaxLayers);
+    P->Rdev = cv.take<ReluLayerT<T>>(kMaxLayers);
 }
 
 void carve(asd_plan* P, Carver& cv) {
@@ -259,6 +287,16 @@ void setup_plan_geometry(asd_plan* P) {
             g.fan = d.in_c * d.kernel * d.kernel;
         }
         g.out = P->nl[L];
+        P->Cpad[L] = (g.out.C + 31) / 32 * 32;
+        P->fanpad[L] = (g.in.C + 7) / 8 * 8 * g.in.P;
+        P->ksplit[L] = 1;
+        if (d.kind == ASD_LAYER_DENSE) {
+            // enough blocks to fill the chip, at least one 64-tap tile each
+            const long base = (long)((S + 63) / 64) * ((g.out.C + 31) / 32);
+            const long want = (1024 + base - 1) / base;
+            const long cap = std::max(1L, std::min(16L, (long)(g.fan / 64)));
+            P->ksplit[L] = (int)std::max(1L, std::min(want, cap));
+        }
     }
 }
 
@@ -322,6 +360,214 @@ asd_status derive_layer(asd_plan* P, int k, hipStream_t st) {
     hipLaunchKernelGGL(k_derive<T>, grid, dim3(256), 0, st, a);
     LAUNCH_CHECK();
     return ASD_OK;
+}
+
+// Packed x words of layer k (for the slots of ReLU layer k+1) and, with
+// with_flag, the flag of point boxes away from zero.
+template <typename T>
+asd_status pack_layer_x(asd_plan* P, int k, int with_flag, hipStream_t st) {
+    PackArgs<T> a;
+    memset(&a, 0, sizeof(a));
+    a.nl = P->nl[k];
+    a.S = P->S;
+    a.nm = P->n_masks;
+    const ReluLayerT<T>& rn = RL<T>(P)[k + 1];
+    for (int q = 0; q < a.nm; ++q) a.bits[q] = rn.slot[q].xbits;
+    a.deg = NA<T>(P)[k].deg;
+    a.lo = NA<T>(P)[k].lo;
+    a.xpk = NA<T>(P)[k].xpk;
+    a.pointflag = with_flag ? P->pointflag + k : nullptr;
+    dim3 grid((unsigned)((a.nl.cols + 255) / 256), (unsigned)a.nl.C);
+    hipLaunchKernelGGL(k_pack<T>, grid, dim3(256), 0, st, a);
+    LAUNCH_CHECK();
+    return ASD_OK;
+}
+
+// Packed z bytes of ReLU layer k.
+template <typename T>
+asd_status pack_layer_z(asd_plan* P, int k, hipStream_t st) {
+    PackArgs<T> a;
+    memset(&a, 0, sizeof(a));
+    a.nl = P->nl[k];
+    a.S = P->S;
+    a.nm = P->n_masks;
+    const ReluLayerT<T>& r = RL<T>(P)[k];
+    for (int q = 0; q < a.nm; ++q) a.bits[q] = r.slot[q].zbits;
+    a.zpk = r.zpk;
+    dim3 grid((unsigned)((a.nl.cols + 255) / 256), (unsigned)a.nl.C);
+    hipLaunchKernelGGL(k_pack<T>, grid, dim3(256), 0, st, a);
+    LAUNCH_CHECK();
+    return ASD_OK;
+}
+
+template <typename T>
+asd_status pack_all(asd_plan* P, int with_flag, hipStream_t st) {
+    for (int k = 0; k + 1 < P->n; ++k) TRY(pack_layer_x<T>(P, k, with_flag, st));
+    for (int k = 1; k < P->n; ++k) TRY(pack_layer_z<T>(P, k, st));
+    return ASD_OK;
+}
+
+// Weight copies of the iteration kernels (transposed forward weights, padded
+// dense rows).
+asd_status prepare_weights(asd_plan* P, hipStream_t st) {
+    for (int L = 1; L <= P->n; ++L) {
+        const LayerGeo& g = P->geo[L];
+        if (L < P->n) {
+            const long n = (long)g.fan * P->Cpad[L];
+            hipLaunchKernelGGL(k_transpose_w, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g.W, P->Wt[L],
+                               g.out.C, g.fan, P->Cpad[L]);
+            LAUNCH_CHECK();
+        }
+        if (g.kind == ASD_LAYER_DENSE) {
+            const long n = (long)g.out.C * P->fanpad[L];
+            hipLaunchKernelGGL(k_pad_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g.W, P->Wr[L],
+                               g.out.C, g.fan, P->fanpad[L]);
+            LAUNCH_CHECK();
+        }
+    }
+    return ASD_OK;
+}
+
+#define ASD_NM_DISPATCH(nm, CALL)                                          \
+    switch (nm) {                                                          \
+        case 0: CALL(0);                                                   \
+        case 1: CALL(1);                                                   \
+        case 2: CALL(2);                                                   \
+        case 3: CALL(3);                                                   \
+        case 4: CALL(4);                                                   \
+        case 5: CALL(5);                                                   \
+        case 6: CALL(6);                                                   \
+        case 7: CALL(7);                                                   \
+        case 8: CALL(8);                                                   \
+        default: return fail(ASD_EINVAL, "mask count %d outside [0, 8]", (int)(nm)); \
+    }
+
+// Iteration forward pass of ReLU layer k with NM active masks.
+template <typename T, int NM>
+asd_status fwd_fast_nm(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t st) {
+    FastFwdArgs<T> a;
+    memset(&a, 0, sizeof(a));
+    a.g = P->geo[k];
+    a.S = P->S;
+    a.nm = NM;
+    a.Cpad = P->Cpad[k];
+    a.ksplit = P->ksplit[k];
+    a.Wt = P->Wt[k];
+    a.xin = NA<T>(P)[k - 1].xstar;
+    a.xpk = NA<T>(P)[k - 1].xpk;
+    a.pointflag = P->pointflag + (k - 1);
+    a.xout = NA<T>(P)[k].xstar;
+    a.R = RdevT<T>(P) + k;
+    a.st = sa;
+    a.part = reinterpret_cast<T*>(P->part);
+    const LayerGeo& g = a.g;
+    constexpr int CB = sizeof(T) == 4 ? 8 : 4;
+    ProfScope ps(P, st, ASD_K_FORWARD, k);
+    if (g.kind == ASD_LAYER_CONV2D) {
+        dim3 grid((unsigned)(g.out.colpad / kWave), (unsigned)((g.out.C + CB - 1) / CB));
+        if (g.ksz == 4)
+            hipLaunchKernelGGL((k_fwd_conv<T, NM, CB, 4>), grid, dim3(kWave, KS), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_fwd_conv<T, NM, CB, 0>), grid, dim3(kWave, KS), 0, st, a);
+        LAUNCH_CHECK();
+        return ASD_OK;
+    }
+    dim3 grid((unsigned)((P->S + kWave - 1) / kWave), (unsigned)((g.out.C + KS * CB - 1) / (KS * CB)),
+              (unsigned)a.ksplit);
+    hipLaunchKernelGGL((k_fwd_dense_part<T, NM, CB>), grid, dim3(kWave, KS), 0, st, a);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_fwd_dense_epi<T, NM>), dim3((unsigned)((P->S + 255) / 256), (unsigned)g.out.C), dim3(256),
+                       0, st, a);
+    LAUNCH_CHECK();
+    return ASD_OK;
+}
+
+template <typename T>
+asd_status fwd_fast(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t st) {
+#define ASD_FWD_CALL(N) return fwd_fast_nm<T, N>(P, k, sa, st)
+    ASD_NM_DISPATCH(P->n_masks, ASD_FWD_CALL)
+#undef ASD_FWD_CALL
+}
+
+template <typename Tc, typename Ts>
+asd_status launch_backward(asd_plan* P, int k, int want_obj, int role, hipStream_t st);
+
+// Iteration backward pass into neuron layer k; NM = masks of layer k+1.
+template <typename T, int NM>
+asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
+    FastBwdArgs<T> a;
+    memset(&a, 0, sizeof(a));
+    a.gn = P->geo[k + 1];
+    a.S = P->S;
+    a.k = k;
+    a.last = (k + 1 == P->n);
+    a.nm = NM;
+    a.Wr = P->Wr[k + 1];
+    a.fanpad = P->fanpad[k + 1];
+    a.cvec = CV<T>(P);
+    if (!a.last) {
+        const ReluLayerT<T>& rn = RL<T>(P)[k + 1];
+        a.vs = rn.vs;
+        for (int q = 0; q < NM; ++q) a.u[q] = rn.slot[q].u;
+    }
+    a.xpk = NA<T>(P)[k].xpk;
+    a.nk = NA<T>(P)[k];
+    if (k >= 1) {
+        const ReluLayerT<T>& r = RL<T>(P)[k];
+        a.own = r.own;
+        a.gk = r.g;
+        a.zbits = r.zbits;
+    }
+    const LayerGeo& g = a.gn;
+    const NeuronLayout& L = g.in;
+    if (g.kind == ASD_LAYER_CONV2D) {
+        const int CB = (sizeof(T) == 4 && L.C > 4) ? 8 : 4;
+        const size_t dyn = (size_t)g.out.C * g.ksz * g.ksz * CB * sizeof(float);
+        const size_t stat = (size_t)KS * CB * kWave * sizeof(T);
+        if (dyn + stat > 64 * 1024) return launch_backward<T, T>(P, k, 0, ASD_K_BACKWARD, st);
+        ProfScope ps(P, st, ASD_K_BACKWARD, k);
+        dim3 grid((unsigned)(L.colpad / kWave), (unsigned)((L.C + CB - 1) / CB));
+        const bool k4s2 = g.ksz == 4 && g.stride == 2;
+        if constexpr (sizeof(T) == 4) {
+            if (CB == 8) {
+                if (k4s2)
+                    hipLaunchKernelGGL((k_bwd_conv<T, NM, 8, 4, 2>), grid, dim3(kWave, KS), dyn, st, a);
+                else
+                    hipLaunchKernelGGL((k_bwd_conv<T, NM, 8, 0, 0>), grid, dim3(kWave, KS), dyn, st, a);
+                LAUNCH_CHECK();
+                return ASD_OK;
+            }
+        }
+        if (k4s2)
+            hipLaunchKernelGGL((k_bwd_conv<T, NM, 4, 4, 2>), grid, dim3(kWave, KS), dyn, st, a);
+        else
+            hipLaunchKernelGGL((k_bwd_conv<T, NM, 4, 0, 0>), grid, dim3(kWave, KS), dyn, st, a);
+        LAUNCH_CHECK();
+        return ASD_OK;
+    }
+    ProfScope ps(P, st, ASD_K_BACKWARD, k);
+    constexpr int SB = sizeof(T) == 4 ? 8 : 4;
+    if (L.P % kWave == 0 && P->S >= SB) {
+        dim3 grid((unsigned)(L.C * (L.P / kWave)), (unsigned)((P->S + SB - 1) / SB));
+        hipLaunchKernelGGL((k_bwd_dense_pos<T, NM, SB>), grid, dim3(kWave, KS), 0, st, a);
+    } else {
+        constexpr int CB = sizeof(T) == 4 ? 8 : 4;
+        dim3 grid((unsigned)(L.colpad / kWave), (unsigned)((L.C + CB - 1) / CB));
+        if (L.P == 1)
+            hipLaunchKernelGGL((k_bwd_dense<T, NM, CB, true>), grid, dim3(kWave, KS), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_bwd_dense<T, NM, CB, false>), grid, dim3(kWave, KS), 0, st, a);
+    }
+    LAUNCH_CHECK();
+    return ASD_OK;
+}
+
+template <typename T>
+asd_status bwd_fast(asd_plan* P, int k, hipStream_t st) {
+    const int nm = (k + 1 == P->n) ? 0 : P->n_masks;
+#define ASD_BWD_CALL(N) return bwd_fast_nm<T, N>(P, k, st)
+    ASD_NM_DISPATCH(nm, ASD_BWD_CALL)
+#undef ASD_BWD_CALL
 }
 
 // Backward pass for neuron layer k (f_k, inner minimisation, terms).
@@ -474,9 +720,20 @@ asd_status reset_group_moments(asd_plan* P, hipStream_t st) {
 }
 
 // One iteration: backward pass, optional active-set extension, forward pass.
+// FP32 plans run the (1 + K) kernels of asd_fast.h.  FP64 plans run the
+// general kernels, whose masked products add the same terms as the mask
+// constants (term by term, same order), so a supergradient entry that is
+// exactly zero in exact arithmetic (for instance a fresh mask's row at the
+// point it was added from, x = 0) is exactly zero here as in the FP64
+// reference, and primal ties are broken the same way; the (1 + K) form
+// reaches such entries through a cancellation that leaves a rounding residue.
 template <typename T>
 asd_status iteration(asd_plan* P, bool as_phase, int t, double lr, hipStream_t st) {
-    for (int k = P->n - 1; k >= 0; --k) TRY((launch_backward<T, T>(P, k, 0, ASD_K_BACKWARD, st)));
+    constexpr bool kGeneral = sizeof(T) == 8;
+    for (int k = P->n - 1; k >= 0; --k) {
+        if constexpr (kGeneral) TRY((launch_backward<T, T>(P, k, 0, ASD_K_BACKWARD, st)));
+        else TRY(bwd_fast<T>(P, k, st));
+    }
     if (as_phase && P->n >= 2 && (t % P->prm.add_every) < P->prm.add_count &&
         P->n_masks < P->prm.max_masks) {
         const int q = P->n_masks;
@@ -488,13 +745,17 @@ asd_status iteration(asd_plan* P, bool as_phase, int t, double lr, hipStream_t s
         }
         P->mask_step[q] = 0;
         P->n_masks = q + 1;
+        TRY(pack_all<T>(P, 0, st));
     }
     if (P->prm.rule == ASD_RULE_ADAM) {
         P->step += 1;
         for (int q = 0; q < P->n_masks; ++q) P->mask_step[q] += 1;
     }
     const StepArgsT<T> sa = make_step_args<T>(P, lr);
-    for (int k = 1; k < P->n; ++k) TRY(launch_forward<T>(P, k, sa, 0, nullptr, st));
+    for (int k = 1; k < P->n; ++k) {
+        if constexpr (kGeneral) TRY(launch_forward<T>(P, k, sa, 0, nullptr, st));
+        else TRY(fwd_fast<T>(P, k, sa, st));
+    }
     return ASD_OK;
 }
 
@@ -518,7 +779,7 @@ asd_status init_t(asd_plan* P, const asd_batch* b, hipStream_t st) {
         const size_t ns = (size_t)P->nl[k].N * S;
         ReluLayerT<T>& r = RL<T>(P)[k];
         T* arrs[12] = {r.alpha, r.beta0, r.beta1, r.alpha_m, r.alpha_v, r.beta0_m,
-                       r.beta0_v, r.beta1_m, r.beta1_v, r.own, r.g, r.vdn};
+                       r.beta0_v, r.beta1_m, r.beta1_v, r.own, r.g, r.vs};
         for (T* a : arrs) TRY(zero_arr(a, ns, st));
         for (int q = 0; q < P->prm.max_masks; ++q) {
             MaskSlotT<T>& m = r.slot[q];
@@ -528,7 +789,12 @@ asd_status init_t(asd_plan* P, const asd_batch* b, hipStream_t st) {
             TRY(zero_words(m.xbits, P->nl[k - 1].words, st));
         }
     }
-    return ASD_OK;
+    TRY(prepare_weights(P, st));
+    TRY(zero_words(P->pointflag, kMaxLayers, st));
+    // the update kernels read the layer arrays from a device copy (the host
+    // array lives in the plan, so the copy may complete asynchronously)
+    HIP_TRY(hipMemcpyAsync(P->Rdev, RL<T>(P), sizeof(ReluLayerT<T>) * kMaxLayers, hipMemcpyHostToDevice, st));
+    return pack_all<T>(P, 1, st);
 }
 
 template <typename T>
@@ -612,6 +878,7 @@ asd_status state_set_t(asd_plan* P, int field, int k, int q, const T* src, hipSt
     } else {
         TRY((launch_layout<T, T>(field_ptr<T>(P, field, k, q), s, P->nl[k], P->S, 0, st)));
     }
+    if (field == ASD_F_MASK_Z || field == ASD_F_MASK_XPREV) TRY(pack_all<T>(P, 0, st));
     return derive_layer<T>(P, k, st);
 }
 
@@ -625,7 +892,7 @@ asd_status set_counts_t(asd_plan* P, int recompute, hipStream_t st) {
             }
     }
     for (int k = 1; k < P->n; ++k) TRY(derive_layer<T>(P, k, st));
-    return ASD_OK;
+    return pack_all<T>(P, 0, st);
 }
 
 template <typename T>
@@ -713,6 +980,7 @@ asd_status asd_net_create(const asd_layer_desc* layers, int32_t n_layers, asd_ne
             if (d.in_c < 1 || d.in_h < 1 || d.in_w < 1 || d.out_c < 1 || d.kernel < 1 || d.stride < 1 ||
                 d.pad < 0)
                 return fail(ASD_EINVAL, "layer %d: invalid convolution parameters", i + 1);
+            if (d.kernel > 32) return fail(ASD_EINVAL, "layer %d: kernel size %d above 32", i + 1, d.kernel);
             const int oh = (d.in_h + 2 * d.pad - d.kernel) / d.stride + 1;
             const int ow = (d.in_w + 2 * d.pad - d.kernel) / d.stride + 1;
             if (oh < 1 || ow < 1 || oh != d.out_h || ow != d.out_w)
@@ -829,11 +1097,11 @@ asd_status asd_init(asd_plan* P, const asd_batch* b, hipStream_t st) {
     if (P->n > 1 && (!b->lhat || !b->uhat)) return fail(ASD_EINVAL, "NULL lhat/uhat");
     for (int k = 1; k < P->n; ++k)
         if (!b->lhat[k - 1] || !b->uhat[k - 1]) return fail(ASD_EINVAL, "NULL bound of layer %d", k);
-    if (is64(P)) TRY(init_t<double>(P, b, st));
-    else TRY(init_t<float>(P, b, st));
     P->n_masks = 0;
     P->step = 0;
     for (int q = 0; q < kMaxMasks; ++q) P->mask_step[q] = 0;
+    if (is64(P)) TRY(init_t<double>(P, b, st));
+    else TRY(init_t<float>(P, b, st));
     P->loaded = true;
     return ASD_OK;
 }

@@ -55,7 +55,7 @@ struct MaskSlotT {
     T* v;
     T* LI;     // (W . I . Lcheck) row sums
     T* UI;     // (W . (1 - I) . Ucheck) row sums
-    T* u;      // derived: (1 - z_I) * beta_{k,I}
+    T* u;      // derived: (1 - z_I) * beta_{k,I} (operand of the |W|^T product of the slot)
     uint32_t* zbits;  // z*_k at addition (layout of layer k)
     uint32_t* xbits;  // x*_{k-1} == upper end at addition (layout of layer k-1)
 };
@@ -70,8 +70,9 @@ struct ReluLayerT {
     T* beta1_m; T* beta1_v;
     T* own;   // derived: alpha - beta0 - beta1 - sum_I beta_I
     T* g;     // derived: g_k (eq:dual-anderson-functions)
-    T* vdn;   // derived: -alpha + beta1 + sum_I z_I beta_I (dense backward operand)
+    T* vs;    // derived: -alpha + beta1 + sum_I (1 + z_I) beta_I / 2 (operand of the W^T product)
     uint32_t* zbits;  // z*_k at the current iterate
+    uint8_t* zpk;     // per neuron: bit q = z bit of slot q
     MaskSlotT<T> slot[kMaxMasks];
     // FP64 sums for the final bound of an FP32 plan
     double* own64; double* g64; double* const64;
@@ -84,6 +85,9 @@ struct NeuronArraysT {
     uint32_t* xbits;           // x*_k == hi
     uint32_t* deg;             // lo == hi
     double* term;              // objective terms per neuron
+    // per neuron, for the masks of the next ReLU layer: bit q (q < 8) = x-bit
+    // of slot q OR point box; bit 15 = point box away from zero
+    uint16_t* xpk;
 };
 
 // Adam / step arguments of one iteration.

@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(kWave * KS) k_forward(FwdArgs<T> A) {
     A.R.beta1[idx] = b1;
     T own = al - b0 - b1;
     T gg = b0 * uh + b1 * lh;
-    T vdn = -al + b1;
+    T vs = -al + b1;
 #pragma unroll
     for (int q = 0; q < kMaxMasks; ++q) {
         if (q < nm) {
@@ -241,13 +241,13 @@ __global__ void __launch_bounds__(kWave * KS) k_forward(FwdArgs<T> A) {
             M.beta[idx] = bq;
             own -= bq;
             gg += bq * (M.LI[idx] + M.UI[idx] + bb);
-            vdn += zq[q] * bq;
-            M.u[idx] = ((T)1 - zq[q]) * bq;
+            vs += zq[q] != (T)0 ? bq : (T)0.5 * bq;
+            M.u[idx] = zq[q] != (T)0 ? (T)0 : bq;
         }
     }
     A.R.own[idx] = own;
     A.R.g[idx] = gg;
-    A.R.vdn[idx] = vdn;
+    A.R.vs[idx] = vs;
 }
 
 // ---------------------------------------------------------------------------
@@ -275,14 +275,9 @@ struct BwdArgs {
 
 template <typename Tc, typename Ts>
 __device__ __forceinline__ Tc bwd_operand(const BwdArgs<Ts>& A, long a, long bi, Tc* uq) {
-    // dense operand v and masked operands u_q at output neuron address a of layer k+1
+    // dense operand v and masked operands u_q at output neuron address a of
+    // layer k+1, formed from the duals and the slots' z bits
     if (A.last) return -(Tc)A.cvec[a];
-    if (sizeof(Tc) == sizeof(Ts)) {
-#pragma unroll
-        for (int q = 0; q < kMaxMasks; ++q)
-            if (q < A.nm_next) uq[q] = (Tc)A.Rn.slot[q].u[a];
-        return (Tc)A.Rn.vdn[a];
-    }
     Tc v = -(Tc)A.Rn.alpha[a] + (Tc)A.Rn.beta1[a];
 #pragma unroll
     for (int q = 0; q < kMaxMasks; ++q) {
@@ -387,8 +382,9 @@ __global__ void __launch_bounds__(kWave * KS) k_backward(BwdArgs<Ts> A) {
     }
     // fold the masked products with this neuron's e-bits before reducing
     // across waves: f gets eL (W+^T u) + eH (W-^T u) per mask
+    unsigned dg4 = 0;
     {
-        unsigned dg4 = 0, xq4[kMaxMasks];
+        unsigned xq4[kMaxMasks];
 #pragma unroll
         for (int q = 0; q < kMaxMasks; ++q) xq4[q] = 0;
         if (colok) {
@@ -429,7 +425,8 @@ __global__ void __launch_bounds__(kWave * KS) k_backward(BwdArgs<Ts> A) {
         for (int w = 0; w < KS; ++w) f += red[(w * CB + e) * kWave + lane];
         const int nmo = A.nm_own;
         if (A.k >= 1) f += kFinal64 ? (Tc)A.Rk.own64[idx] : (Tc)A.Rk.own[idx];
-        xb = f >= 0;
+        // x-bit "x* = upper end"; a point box counts as both ends and keeps the bit set
+        xb = f >= 0 || ((dg4 >> e) & 1u);
         const Tc xv = xb ? (Tc)A.nk.hi[idx] : (Tc)A.nk.lo[idx];
         A.nk.xstar[idx] = (Ts)xv;
         Tc term = -f * xv;
@@ -610,7 +607,7 @@ __global__ void k_zero_words(uint32_t* dst, long n) {
 }
 
 // Recomputes the derived per-neuron sums from the duals (after an import or
-// at initialisation): own, g, vdn and u_q.
+// at initialisation): own, g, vs and u_q.
 template <typename T>
 struct DeriveArgs {
     NeuronLayout nl;
@@ -632,19 +629,19 @@ __global__ void k_derive(DeriveArgs<T> A) {
     const T bb = (T)A.b[c];
     T own = al - b0 - b1;
     T gg = b0 * A.R.uhat[idx] + b1 * A.R.lhat[idx];
-    T vdn = -al + b1;
+    T vs = -al + b1;
     for (int q = 0; q < A.nm; ++q) {
         const MaskSlotT<T>& M = A.R.slot[q];
         const T bq = M.beta[idx];
-        const T zq = (T)getbit(M.zbits, bi);
+        const bool zq = getbit(M.zbits, bi);
         own -= bq;
         gg += bq * (M.LI[idx] + M.UI[idx] + bb);
-        vdn += zq * bq;
-        M.u[idx] = ((T)1 - zq) * bq;
+        vs += zq ? bq : (T)0.5 * bq;
+        M.u[idx] = zq ? (T)0 : bq;
     }
     A.R.own[idx] = own;
     A.R.g[idx] = gg;
-    A.R.vdn[idx] = vdn;
+    A.R.vs[idx] = vs;
 }
 
 // ---------------------------------------------------------------------------

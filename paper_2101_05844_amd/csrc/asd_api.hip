@@ -98,6 +98,8 @@ struct asd_plan {
     float* Wr[kMaxLayers + 1];        // [n_out][fanpad] (dense layers)
     int fanpad[kMaxLayers + 1];
     int ksplit[kMaxLayers + 1];       // dense forward: blocks over the fan-in
+    float* Wb[kMaxLayers + 1];        // convolution: class weights of the transposed product
+    int nkp[kMaxLayers + 1];
     void* part;                       // dense forward partial products
     int* pointflag;                   // [kMaxLayers]: point box away from zero in layer k
     void* Rdev;                       // device copy of the ReluLayerT array (update kernels)
@@ -228,6 +230,8 @@ void carve_t(asd_plan* P, Carver& cv) {
     for (int L = 1; L <= P->n; ++L) {
         const LayerGeo& g = P->geo[L];
         if (L < P->n) P->Wt[L] = cv.take<float>((size_t)g.fan * P->Cpad[L]);
+        if (g.kind == ASD_LAYER_CONV2D)
+            P->Wb[L] = cv.take<float>((size_t)((g.in.C + 15) / 16) * g.stride * g.stride * P->nkp[L] * 16);
         if (g.kind == ASD_LAYER_DENSE) {
             P->Wr[L] = cv.take<float>((size_t)g.out.C * P->fanpad[L]);
             if (L < P->n)
@@ -288,13 +292,18 @@ void setup_plan_geometry(asd_plan* P) {
         }
         g.out = P->nl[L];
         P->Cpad[L] = (g.out.C + 31) / 32 * 32;
+        {
+            const int J = (g.ksz + g.stride - 1) / g.stride;
+            P->nkp[L] = (g.out.C * J * J + 3) / 4 * 4;
+        }
         P->fanpad[L] = (g.in.C + 7) / 8 * 8 * g.in.P;
         P->ksplit[L] = 1;
         if (d.kind == ASD_LAYER_DENSE) {
-            // enough blocks to fill the chip, at least one 64-tap tile each
-            const long base = (long)((S + 63) / 64) * ((g.out.C + 31) / 32);
-            const long want = (1024 + base - 1) / base;
-            const long cap = std::max(1L, std::min(16L, (long)(g.fan / 64)));
+            // about two waves per SIMD (2048 waves of KS per 32 x 32 tile), at
+            // least 32 taps per wave, at most 8 partial sums per output
+            const long tiles = (long)((S + 31) / 32) * (P->Cpad[L] / 32);
+            const long want = (2048 / KS + tiles - 1) / tiles;
+            const long cap = std::max(1L, std::min(8L, (long)(g.fan / (32 * KS))));
             P->ksplit[L] = (int)std::max(1L, std::min(want, cap));
         }
     }
@@ -418,6 +427,12 @@ asd_status prepare_weights(asd_plan* P, hipStream_t st) {
                                g.out.C, g.fan, P->Cpad[L]);
             LAUNCH_CHECK();
         }
+        if (g.kind == ASD_LAYER_CONV2D) {
+            const long n = (long)((g.in.C + 15) / 16) * g.stride * g.stride * P->nkp[L] * 16;
+            hipLaunchKernelGGL(k_class_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g.W, P->Wb[L],
+                               g.in.C, g.out.C, g.ksz, g.stride, P->nkp[L], n);
+            LAUNCH_CHECK();
+        }
         if (g.kind == ASD_LAYER_DENSE) {
             const long n = (long)g.out.C * P->fanpad[L];
             hipLaunchKernelGGL(k_pad_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g.W, P->Wr[L],
@@ -463,7 +478,9 @@ asd_status fwd_fast_nm(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t s
     const LayerGeo& g = a.g;
     constexpr int CB = sizeof(T) == 4 ? 8 : 4;
     ProfScope ps(P, st, ASD_K_FORWARD, k);
-    if (g.kind == ASD_LAYER_CONV2D) {
+    if (g.kind == ASD_LAYER_CONV2D && g.out.C < 32) {
+        // narrow layer: a 32-row matrix tile would be half empty, and the
+        // update's memory traffic bounds it anyway
         dim3 grid((unsigned)(g.out.colpad / kWave), (unsigned)((g.out.C + CB - 1) / CB));
         if (g.ksz == 4)
             hipLaunchKernelGGL((k_fwd_conv<T, NM, CB, 4>), grid, dim3(kWave, KS), 0, st, a);
@@ -472,9 +489,18 @@ asd_status fwd_fast_nm(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t s
         LAUNCH_CHECK();
         return ASD_OK;
     }
-    dim3 grid((unsigned)((P->S + kWave - 1) / kWave), (unsigned)((g.out.C + KS * CB - 1) / (KS * CB)),
-              (unsigned)a.ksplit);
-    hipLaunchKernelGGL((k_fwd_dense_part<T, NM, CB>), grid, dim3(kWave, KS), 0, st, a);
+    if (g.kind == ASD_LAYER_CONV2D) {
+        // one 32-column tile per block, its waves splitting the taps
+        const long ntiles = (g.out.cols + 31) / 32;
+        dim3 grid((unsigned)ntiles, (unsigned)(a.Cpad / 32));
+        if (g.ksz == 4) hipLaunchKernelGGL((k_fwd_conv_mfma<NM, true, 4>), grid, dim3(kWave, KS), 0, st, a);
+        else hipLaunchKernelGGL((k_fwd_conv_mfma<NM, true, 0>), grid, dim3(kWave, KS), 0, st, a);
+        (void)CB;
+        LAUNCH_CHECK();
+        return ASD_OK;
+    }
+    dim3 grid((unsigned)((P->S + 31) / 32), (unsigned)(a.Cpad / 32), (unsigned)a.ksplit);
+    hipLaunchKernelGGL((k_fwd_dense_mfma<NM>), grid, dim3(kWave, KS), 0, st, a);
     LAUNCH_CHECK();
     hipLaunchKernelGGL((k_fwd_dense_epi<T, NM>), dim3((unsigned)((P->S + 255) / 256), (unsigned)g.out.C), dim3(256),
                        0, st, a);
@@ -520,6 +546,20 @@ asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
     }
     const LayerGeo& g = a.gn;
     const NeuronLayout& L = g.in;
+    a.Wb = P->Wb[k + 1];
+    a.nkp = P->nkp[k + 1];
+    if (g.kind == ASD_LAYER_CONV2D && L.C >= 16 && L.P % kWave == 0 && (size_t)16 * L.P * 4 <= 48 * 1024) {
+        // matrix-core transposed convolution over parity classes
+        ProfScope ps(P, st, ASD_K_BACKWARD, k);
+        dim3 grid((unsigned)P->S, (unsigned)((L.C + 15) / 16));
+        const size_t dyn = (size_t)std::min(16, L.C) * L.P * sizeof(float);
+        if (g.ksz == 4 && g.stride == 2)
+            hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 4, 2>), grid, dim3(kWave, KS), dyn, st, a);
+        else
+            hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 0, 0>), grid, dim3(kWave, KS), dyn, st, a);
+        LAUNCH_CHECK();
+        return ASD_OK;
+    }
     if (g.kind == ASD_LAYER_CONV2D) {
         const int CB = (sizeof(T) == 4 && L.C > 4) ? 8 : 4;
         const size_t dyn = (size_t)g.out.C * g.ksz * g.ksz * CB * sizeof(float);

@@ -60,6 +60,20 @@ template <typename T> __device__ __forceinline__ T flip(T x, unsigned bit) { ret
 
 constexpr int kPointBit = 15;
 
+// Workgroups go to the 8 XCDs round-robin by linear id, and each XCD has its
+// own L2.  Column kernels renumber their workgroups so that every XCD gets one
+// contiguous range of (column tile, channel group) pairs, all channel groups
+// of a column tile next to each other: tiles that read the same inputs then
+// share one L2.  Returns (column tile, channel group).
+__device__ __forceinline__ void xcd_tile(int& tile, int& group) {
+    const unsigned gx = gridDim.x, gy = gridDim.y, n = gx * gy;
+    const unsigned lin = blockIdx.y * gx + blockIdx.x;
+    const unsigned x = lin & 7u, q = n >> 3, r = n & 7u;
+    const unsigned logical = (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + (lin >> 3);
+    tile = (int)(logical / gy);
+    group = (int)(logical - (logical / gy) * gy);
+}
+
 // ---------------------------------------------------------------------------
 // Shared forward update of one neuron (c, s, p) of ReLU layer k from its
 // products: yd = (W x)[i], ym[q] = (|W| (sigma_q . x))[i] + 2 (W+ x_point)[i].
@@ -84,41 +98,82 @@ struct FastFwdArgs {
     T* part;                    // dense: partial products [ksplit][1 + nm][Cpad][S]
 };
 
+// State of one neuron read by the update (loads only, so that the loads of
+// several neurons can be in flight together: the compiler cannot move a
+// neuron's loads above an earlier neuron's stores).
 template <typename T, int NM>
-__device__ __forceinline__ void fwd_update(const FastFwdArgs<T>& A, int c, long idx, long bi, T yd,
-                                           const T* ym) {
+struct FwdIn {
+    T x, lh, uh, z, bb;
+    T th[3], m[3], v[3];  // alpha, beta0, beta1 and their moments
+    unsigned zq;
+    T LI[NM > 0 ? NM : 1], UI[NM > 0 ? NM : 1], bq[NM > 0 ? NM : 1], mq[NM > 0 ? NM : 1], vq[NM > 0 ? NM : 1];
+};
+
+template <typename T, int NM>
+__device__ __forceinline__ void fwd_load(const FastFwdArgs<T>& A, int c, long idx, long bi, FwdIn<T, NM>& in) {
     const cptr_t<ReluLayerT<T>> R = kconst_t(A.R);
-    const T bb = (T)A.g.b[c];
-    const T xhat = yd + bb;
-    const T x = A.xout[idx];
-    const T z = (T)getbit(R->zbits, bi);
-    const T lh = R->lhat[idx], uh = R->uhat[idx];
-    const T ga = xhat - x;
-    const T gb0 = x - z * uh;
-    const T gb1 = x - xhat + ((T)1 - z) * lh;
-    const unsigned zq = NM > 0 ? (unsigned)R->zpk[idx] : 0u;
-    T gm[NM > 0 ? NM : 1], LI[NM > 0 ? NM : 1], UI[NM > 0 ? NM : 1];
+    const bool adam = A.st.rule != ASD_RULE_SUPERGRADIENT;
+    in.bb = (T)A.g.b[c];
+    in.x = A.xout[idx];
+    in.z = (T)getbit(R->zbits, bi);
+    in.lh = R->lhat[idx];
+    in.uh = R->uhat[idx];
+    in.th[0] = R->alpha[idx];
+    in.th[1] = R->beta0[idx];
+    in.th[2] = R->beta1[idx];
+    for (int j = 0; j < 3; ++j) in.m[j] = in.v[j] = (T)0;
+#pragma unroll
+    for (int q = 0; q < (NM > 0 ? NM : 1); ++q) in.mq[q] = in.vq[q] = (T)0;
+    if (adam) {
+        in.m[0] = R->alpha_m[idx];
+        in.v[0] = R->alpha_v[idx];
+        in.m[1] = R->beta0_m[idx];
+        in.v[1] = R->beta0_v[idx];
+        in.m[2] = R->beta1_m[idx];
+        in.v[2] = R->beta1_v[idx];
+    }
+    in.zq = NM > 0 ? (unsigned)R->zpk[idx] : 0u;
 #pragma unroll
     for (int q = 0; q < NM; ++q) {
-        LI[q] = R->slot[q].LI[idx];
-        UI[q] = R->slot[q].UI[idx];
-        const T mq = ((zq >> q) & 1u) ? yd : (T)0.5 * (yd + ym[q]);
-        gm[q] = x - mq + LI[q] * ((T)1 - z) - z * bb - UI[q] * z;
+        const cptr_t<MaskSlotT<T>> M = &R->slot[q];
+        in.LI[q] = M->LI[idx];
+        in.UI[q] = M->UI[idx];
+        in.bq[q] = M->beta[idx];
+        if (adam) {
+            in.mq[q] = M->m[idx];
+            in.vq[q] = M->v[idx];
+        }
     }
+}
+
+// Supergradient eq:as-supergradient from the products yd = (W x)[i] and
+// ym[q] = (|W| (sigma_q . x))[i] + 2 (W+ x_point)[i], the projected step, the
+// derived sums own, g, vs, u_q; stores only.
+template <typename T, int NM>
+__device__ __forceinline__ void fwd_store(const FastFwdArgs<T>& A, long idx, const FwdIn<T, NM>& in, T yd,
+                                          const T* ym) {
+    const cptr_t<ReluLayerT<T>> R = kconst_t(A.R);
     const StepArgsT<T>& st = A.st;
-    auto step = [&](T th, T* m, T* v, T gr, int grp) -> T {
-        if (st.rule == ASD_RULE_SUPERGRADIENT) return tmax0(th + st.lr * gr);
-        const T mm = st.b1 * m[idx] + ((T)1 - st.b1) * gr;
-        const T vv = st.b2 * v[idx] + ((T)1 - st.b2) * gr * gr;
-        m[idx] = mm;
-        v[idx] = vv;
+    const bool adam = st.rule != ASD_RULE_SUPERGRADIENT;
+    const T x = in.x, z = in.z, bb = in.bb, lh = in.lh, uh = in.uh;
+    const T xhat = yd + bb;
+    T gr[3];
+    gr[0] = xhat - x;
+    gr[1] = x - z * uh;
+    gr[2] = x - xhat + ((T)1 - z) * lh;
+    auto step = [&](T th, T m, T v, T g, int grp, T* mo, T* vo) -> T {
+        if (!adam) return tmax0(th + st.lr * g);
+        const T mm = st.b1 * m + ((T)1 - st.b1) * g;
+        const T vv = st.b2 * v + ((T)1 - st.b2) * g * g;
+        mo[idx] = mm;
+        vo[idx] = vv;
         const T mh = mm / st.bc1[grp];
         const T vh = vv / st.bc2[grp];
         return tmax0(th + st.lr * mh / (tsqrt(vh) + st.eps));
     };
-    const T al = step(R->alpha[idx], R->alpha_m, R->alpha_v, ga, 0);
-    const T b0 = step(R->beta0[idx], R->beta0_m, R->beta0_v, gb0, 0);
-    const T b1 = step(R->beta1[idx], R->beta1_m, R->beta1_v, gb1, 0);
+    const T al = step(in.th[0], in.m[0], in.v[0], gr[0], 0, R->alpha_m, R->alpha_v);
+    const T b0 = step(in.th[1], in.m[1], in.v[1], gr[1], 0, R->beta0_m, R->beta0_v);
+    const T b1 = step(in.th[2], in.m[2], in.v[2], gr[2], 0, R->beta1_m, R->beta1_v);
     R->alpha[idx] = al;
     R->beta0[idx] = b0;
     R->beta1[idx] = b1;
@@ -128,17 +183,27 @@ __device__ __forceinline__ void fwd_update(const FastFwdArgs<T>& A, int c, long 
 #pragma unroll
     for (int q = 0; q < NM; ++q) {
         const cptr_t<MaskSlotT<T>> M = &R->slot[q];
-        const T bq = step(M->beta[idx], M->m, M->v, gm[q], 1 + q);
+        const bool zb = (in.zq >> q) & 1u;
+        const T mq = zb ? yd : (T)0.5 * (yd + ym[q]);
+        const T gm = x - mq + in.LI[q] * ((T)1 - z) - z * bb - in.UI[q] * z;
+        const T bq = step(in.bq[q], in.mq[q], in.vq[q], gm, 1 + q, M->m, M->v);
         M->beta[idx] = bq;
         own -= bq;
-        gg += bq * (LI[q] + UI[q] + bb);
-        const bool zb = (zq >> q) & 1u;
+        gg += bq * (in.LI[q] + in.UI[q] + bb);
         vs += zb ? bq : (T)0.5 * bq;
         M->u[idx] = zb ? (T)0 : bq;
     }
     R->own[idx] = own;
     R->g[idx] = gg;
     R->vs[idx] = vs;
+}
+
+template <typename T, int NM>
+__device__ __forceinline__ void fwd_update(const FastFwdArgs<T>& A, int c, long idx, long bi, T yd,
+                                           const T* ym) {
+    FwdIn<T, NM> in;
+    fwd_load<T, NM>(A, c, idx, bi, in);
+    fwd_store<T, NM>(A, idx, in, yd, ym);
 }
 
 // ---------------------------------------------------------------------------
@@ -154,8 +219,10 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_conv(FastFwdArgs<T> A) {
     const LayerGeo& g = A.g;
     const int lane = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);  // wave-uniform
-    const long col = (long)blockIdx.x * kWave + lane;
-    const int c0 = blockIdx.y * CB;
+    int tile, group;
+    xcd_tile(tile, group);
+    const long col = (long)tile * kWave + lane;
+    const int c0 = group * CB;
     const int S = A.S;
     const bool colok = col < g.out.cols;
     const int s = colok ? (int)(col / g.out.P) : 0;
@@ -264,120 +331,287 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_conv(FastFwdArgs<T> A) {
         __syncthreads();
     }
     if (!colok) return;
+    FwdIn<T, NM> in[EPW];
+#pragma unroll
+    for (int j = 0; j < EPW; ++j) {  // loads of every neuron first
+        const int c = min(c0 + wave * EPW + j, g.out.C - 1);
+        fwd_load<T, NM>(A, c, ((long)c * S + s) * g.out.P + p, (long)c * g.out.colpad + col, in[j]);
+    }
 #pragma unroll
     for (int j = 0; j < EPW; ++j) {
         const int c = c0 + wave * EPW + j;
         if (c >= g.out.C) break;
-        const long idx = ((long)c * S + s) * g.out.P + p;
-        const long bi = (long)c * g.out.colpad + col;
         T ymj[NA];
 #pragma unroll
         for (int q = 0; q < NM; ++q) ymj[q] = tot[1 + q][j];
-        fwd_update<T, NM>(A, c, idx, bi, tot[0][j], ymj);
+        fwd_store<T, NM>(A, ((long)c * S + s) * g.out.P + p, in[j], tot[0][j], ymj);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Forward pass of a dense ReLU layer k, split over the fan-in.
-// Part kernel: grid (ceil(S / 64), ceil(C_k / (KS * CB)), ksplit), block
-// (64, KS): lanes = subproblems, wave = CB output channels; x tiles of 64
-// taps x 64 subproblems are staged in LDS.
+// Forward pass of a dense ReLU layer k on the matrix cores, split over the
+// fan-in: every product is a GEMM, (W | |W|)[C_k x fan] times the input
+// columns [fan x S] (x*_{k-1} for W, sigma_q . x*_{k-1} for |W|), tiled
+// 32 x 32 with v_mfma_f32_32x32x2f32.  Operand layout of that instruction
+// (lane l of 64): A[l % 32][l / 32], B[l / 32][l % 32]; accumulator register
+// r holds C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
+// Grid (ceil(S / 32), Cpad / 32, ksplit), block (64, KS): the block owns one
+// 32 x 32 output tile and a ksplit-th of the fan-in, its waves split that
+// range again and add their tiles through LDS in a fixed order.  Writes
+// partial products [ksplit][1 + NM][Cpad][S].
 // ---------------------------------------------------------------------------
-constexpr int kDenseTile = 64;
+typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-template <typename T, int NM, int CB>
-__global__ void __launch_bounds__(kWave * KS) k_fwd_dense_part(FastFwdArgs<T> A) {
-    constexpr int NA = NM > 0 ? NM : 1;
-    __shared__ T xs[kDenseTile][kWave + 1];
-    __shared__ uint16_t hs[kDenseTile][kWave + 2];
+template <int NM>
+__global__ void __launch_bounds__(kWave * KS) k_fwd_dense_mfma(FastFwdArgs<float> A) {
+    constexpr int U = 4;  // steps of 2 taps per trip
+    __shared__ float red[KS][16][kWave];
     const LayerGeo& g = A.g;
     const int lane = threadIdx.x;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);  // wave-uniform
-    const int tid = wave * kWave + lane;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
     const int S = A.S;
-    const int s0 = blockIdx.x * kWave;
-    const int cb = (blockIdx.y * KS + wave) * CB;
-    const int F = g.fan;
-    const int Pin = g.in.P;
-    const int t0 = (int)((long)F * blockIdx.z / A.ksplit), t1 = (int)((long)F * (blockIdx.z + 1) / A.ksplit);
-    const cfloat_p Wt = kconst(A.Wt);
     const int Cp = A.Cpad;
+    const int m0 = blockIdx.y * 32;
+    const int n0 = blockIdx.x * 32;
+    const int F = g.fan;
+    const long zr = (long)blockIdx.z * KS + wave, nz = (long)A.ksplit * KS;
+    const int t0 = (int)(F * zr / nz), t1 = (int)(F * (zr + 1) / nz);
+    const int Pin = g.in.P;
+    const int half = lane >> 5;          // k offset of this lane within a step
+    const int col = lane & 31;           // A row / B column of this lane
+    const int s = min(n0 + col, S - 1);  // clamped: columns past S are computed and dropped
     const bool pointin = NM > 0 && *kconst_t<int>(A.pointflag) != 0;
-    T yd[CB], ym[NA][CB];
+    floatx16 acc[1 + NM], accp;
 #pragma unroll
-    for (int e = 0; e < CB; ++e) {
-        yd[e] = 0;
+    for (int r = 0; r <= NM; ++r)
 #pragma unroll
-        for (int q = 0; q < NA; ++q) ym[q][e] = 0;
-    }
-    for (int tc = t0; tc < t1; tc += kDenseTile) {
-        const int nt = min(kDenseTile, t1 - tc);
-        // stage: runs of consecutive positions of one subproblem when the
-        // input has positions, runs of subproblems otherwise
-        for (int e = tid; e < kDenseTile * kWave; e += kWave * KS) {
-            const int sl = Pin > 1 ? e / kDenseTile : e % kWave;
-            const int tl = Pin > 1 ? e % kDenseTile : e / kWave;
-            const int s = s0 + sl;
-            T v = 0;
-            uint16_t h = 0;
-            if (s < S && tl < nt) {
-                const int t = tc + tl;
-                const int ci = t / Pin, pp = t - (t / Pin) * Pin;
-                const long a = ((long)ci * S + s) * Pin + pp;
-                v = A.xin[a];
-                if (NM > 0) h = A.xpk[a];
-            }
-            xs[tl][sl] = v;
-            hs[tl][sl] = h;
+        for (int i = 0; i < 16; ++i) acc[r][i] = 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) accp[i] = 0.f;
+    float wv[U], xv[U];
+    unsigned hv[U];
+    // loads of the trip starting at tap k (lanes past t1 read tap t0 and get 0)
+    auto load = [&](int k) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = k + 2 * u + half;
+            const int tt = t < t1 ? t : t0;
+            const int ci = tt / Pin, pp = tt - (tt / Pin) * Pin;
+            const long b_idx = ((long)ci * S + s) * Pin + pp;
+            wv[u] = A.Wt[(long)tt * Cp + m0 + col];
+            xv[u] = A.xin[b_idx];
+            hv[u] = NM > 0 ? (unsigned)A.xpk[b_idx] : 0u;
         }
-        __syncthreads();
-        if (cb < g.out.C) {
-#pragma unroll 4
-            for (int tl = 0; tl < nt; ++tl) {
-                const T x = xs[tl][lane];
-                const unsigned h = NM > 0 ? (unsigned)hs[tl][lane] : 0u;
-                float w[CB];
-                const long wrow = (long)(tc + tl) * Cp + cb;
+    };
+    if (t0 < t1) load(t0);
+    for (int k = t0; k < t1; k += 2 * U) {
+        float w2[U], x2[U];
+        unsigned h2[U];
 #pragma unroll
-                for (int e = 0; e < CB; ++e) w[e] = Wt[wrow + e];
+        for (int u = 0; u < U; ++u) {
+            w2[u] = wv[u];
+            x2[u] = xv[u];
+            h2[u] = hv[u];
+        }
+        if (k + 2 * U < t1) load(k + 2 * U);  // next trip's loads in flight during this trip
+        // taps past the range contribute nothing
 #pragma unroll
-                for (int e = 0; e < CB; ++e) yd[e] += (T)w[e] * x;
+        for (int u = 0; u < U; ++u) {
+            const bool tok = k + 2 * u + half < t1;
+            w2[u] = tok ? w2[u] : 0.f;
+            x2[u] = tok ? x2[u] : 0.f;
+        }
 #pragma unroll
-                for (int q = 0; q < NM; ++q) {
-                    const T sx = flip(x, (h >> q) & 1u);
+        for (int u = 0; u < U; ++u) {
+            acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(w2[u], x2[u], acc[0], 0, 0, 0);
+            const float wabs = fabsf(w2[u]);
 #pragma unroll
-                    for (int e = 0; e < CB; ++e) ym[q][e] += (T)fabsf(w[e]) * sx;
-                }
-            }
-            if (pointin) {
-                // point boxes away from zero: (W . I) x gains W+ x_point on z = 0 rows
-                T yp[CB];
+            for (int q = 0; q < NM; ++q)
+                acc[1 + q] =
+                    __builtin_amdgcn_mfma_f32_32x32x2f32(wabs, flip(x2[u], (h2[u] >> q) & 1u), acc[1 + q], 0, 0, 0);
+        }
+        if (pointin) {
+            // point boxes away from zero: (W . I) x gains W+ x_point on z = 0 rows
 #pragma unroll
-                for (int e = 0; e < CB; ++e) yp[e] = 0;
-                for (int tl = 0; tl < nt; ++tl) {
-                    const T xp = ((hs[tl][lane] >> kPointBit) & 1u) ? xs[tl][lane] : (T)0;
-                    const long wrow = (long)(tc + tl) * Cp + cb;
-#pragma unroll
-                    for (int e = 0; e < CB; ++e) yp[e] += (T)fmaxf(Wt[wrow + e], 0.f) * xp;
-                }
-#pragma unroll
-                for (int q = 0; q < NM; ++q)
-#pragma unroll
-                    for (int e = 0; e < CB; ++e) ym[q][e] += (T)2 * yp[e];
+            for (int u = 0; u < U; ++u) {
+                const float xp = ((h2[u] >> kPointBit) & 1u) ? x2[u] : 0.f;
+                accp = __builtin_amdgcn_mfma_f32_32x32x2f32(fmaxf(w2[u], 0.f), xp, accp, 0, 0, 0);
             }
         }
-        __syncthreads();
     }
-    const int s = s0 + lane;
-    if (s >= S) return;
+    // add the waves' tiles (fixed order), one product at a time; wave w
+    // finishes accumulator registers 4w .. 4w + 3
+    const int sw = n0 + col;
     const long zs = (long)blockIdx.z * (1 + NM);
 #pragma unroll
-    for (int e = 0; e < CB; ++e) {
-        const int c = cb + e;
-        if (c >= g.out.C) break;
-        A.part[((zs + 0) * Cp + c) * S + s] = yd[e];
+    for (int r = 0; r <= NM; ++r) {
 #pragma unroll
-        for (int q = 0; q < NM; ++q) A.part[((zs + 1 + q) * Cp + c) * S + s] = ym[q][e];
+        for (int i = 0; i < 16; ++i) red[wave][i][lane] = r == 0 ? acc[0][i] : acc[r][i] + 2.f * accp[i];
+        __syncthreads();
+#pragma unroll
+        for (int ii = 0; ii < 16 / KS; ++ii) {
+            const int i = wave * (16 / KS) + ii;
+            float v = 0.f;
+#pragma unroll
+            for (int w = 0; w < KS; ++w) v += red[w][i][lane];
+            const int m = m0 + 8 * (i / 4) + 4 * half + (i % 4);
+            if (sw < S && m < g.out.C) A.part[((zs + r) * Cp + m) * S + sw] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Forward pass of a convolutional ReLU layer k on the matrix cores (implicit
+// GEMM, same instruction and operand layout as the dense kernel): output tile
+// = 32 channels x 32 consecutive columns (subproblem, position); B gathers
+// x*_{k-1} at each column's receptive field (zero outside the image).  With
+// SPLITK the 4 waves of a block split the taps of one tile and add their
+// tiles through LDS in a fixed order, then each updates 4 accumulator
+// registers' neurons; without it each wave owns a tile.  The update
+// (fwd_update) is fused: register r of lane l is neuron (channel
+// m0 + 8 (r / 4) + 4 (l / 32) + r % 4, column n0 + l % 32), so every
+// register's state access is two 128-byte runs.
+// Grid (column tiles / (SPLITK ? 1 : KS), Cpad / 32), block (64, KS).
+// ---------------------------------------------------------------------------
+template <int NM, bool SPLITK, int KSZ>
+__global__ void __launch_bounds__(kWave * KS) k_fwd_conv_mfma(FastFwdArgs<float> A) {
+    constexpr int U = 4;  // steps of 2 taps per trip
+    __shared__ float red[SPLITK ? KS : 1][16][kWave];
+    const LayerGeo& g = A.g;
+    const int lane = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    int tile, group;
+    xcd_tile(tile, group);
+    const long ntile = SPLITK ? tile : (long)tile * KS + wave;
+    const int m0 = group * 32;
+    const long n0 = ntile * 32;
+    if (!SPLITK && n0 >= g.out.cols) return;  // whole wave, no barrier below
+    const int S = A.S;
+    const int Cp = A.Cpad;
+    const int half = lane >> 5, cl = lane & 31;
+    const long col = n0 + cl;
+    const bool colok = col < g.out.cols;
+    const long cc = colok ? col : g.out.cols - 1;  // clamped column for the gathers
+    const int s = (int)(cc / g.out.P);
+    const int p = (int)(cc - (long)s * g.out.P);
+    const int oy = p / g.out.W, ox = p - (p / g.out.W) * g.out.W;
+    const int ks = KSZ > 0 ? KSZ : g.ksz;
+    const int ks2 = ks * ks;
+    const int iy0 = oy * g.stride - g.pad, ix0 = ox * g.stride - g.pad;
+    const long xbase = (long)s * g.in.P;
+    const long cstride = (long)S * g.in.P;
+    const int F = g.fan;
+    const int t0 = SPLITK ? F * wave / KS : 0, t1 = SPLITK ? F * (wave + 1) / KS : F;
+    const bool pointin = NM > 0 && *kconst_t<int>(A.pointflag) != 0;
+    floatx16 acc[1 + NM], accp;
+#pragma unroll
+    for (int r = 0; r <= NM; ++r)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[r][i] = 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) accp[i] = 0.f;
+    float wv[U], xv[U];
+    unsigned hv[U];
+    bool okv[U];
+    auto load = [&](int k) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = k + 2 * u + half;
+            const bool tok = t < t1;
+            const int tt = tok ? t : t0;
+            const int ci = tt / ks2, rr = tt - (tt / ks2) * ks2;
+            const int ky = rr / ks, kx = rr - (rr / ks) * ks;
+            const int iy = iy0 + ky, ix = ix0 + kx;
+            const bool ok = tok && iy >= 0 && iy < g.in.H && ix >= 0 && ix < g.in.W;
+            const long b_idx = ok ? (long)ci * cstride + xbase + (long)iy * g.in.W + ix : 0;
+            wv[u] = A.Wt[(long)tt * Cp + m0 + cl];
+            xv[u] = A.xin[b_idx];
+            hv[u] = NM > 0 ? (unsigned)A.xpk[b_idx] : 0u;
+            okv[u] = ok;
+        }
+    };
+    if (t0 < t1) load(t0);
+    for (int k = t0; k < t1; k += 2 * U) {
+        float w2[U], x2[U];
+        unsigned h2[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            w2[u] = k + 2 * u + half < t1 ? wv[u] : 0.f;
+            x2[u] = okv[u] ? xv[u] : 0.f;
+            h2[u] = okv[u] ? hv[u] : 0u;
+        }
+        if (k + 2 * U < t1) load(k + 2 * U);  // next trip's loads in flight during this trip
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(w2[u], x2[u], acc[0], 0, 0, 0);
+            const float wabs = fabsf(w2[u]);
+#pragma unroll
+            for (int q = 0; q < NM; ++q)
+                acc[1 + q] =
+                    __builtin_amdgcn_mfma_f32_32x32x2f32(wabs, flip(x2[u], (h2[u] >> q) & 1u), acc[1 + q], 0, 0, 0);
+        }
+        if (pointin) {
+            // point boxes away from zero: (W . I) x gains W+ x_point on z = 0 rows
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const float xp = ((h2[u] >> kPointBit) & 1u) ? x2[u] : 0.f;
+                accp = __builtin_amdgcn_mfma_f32_32x32x2f32(fmaxf(w2[u], 0.f), xp, accp, 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NM; ++q)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[1 + q][i] += 2.f * accp[i];
+    constexpr int NR = SPLITK ? 16 / KS : 16;  // accumulator registers this wave updates
+    float tot[1 + NM][NR];
+    if constexpr (SPLITK) {
+#pragma unroll
+        for (int r = 0; r <= NM; ++r) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) red[wave][i][lane] = acc[r][i];
+            __syncthreads();
+#pragma unroll
+            for (int ii = 0; ii < NR; ++ii) {
+                float v = 0.f;
+#pragma unroll
+                for (int w = 0; w < KS; ++w) v += red[w][wave * NR + ii][lane];
+                tot[r][ii] = v;
+            }
+            __syncthreads();
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r <= NM; ++r)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) tot[r][i] = acc[r][i];
+    }
+    if (!colok) return;
+    // update in batches of NB neurons, each batch's loads issued together
+    constexpr int NB = NM <= 2 ? 4 : (NM <= 4 ? 2 : 1);
+    static_assert(NR % NB == 0, "batch size");
+#pragma unroll
+    for (int b0 = 0; b0 < NR; b0 += NB) {
+        FwdIn<float, NM> in[NB];
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) {
+            const int ii = b0 + jb;
+            const int i = SPLITK ? wave * NR + ii : ii;
+            const int c = min(m0 + 8 * (i / 4) + 4 * half + (i % 4), g.out.C - 1);
+            fwd_load<float, NM>(A, c, (long)c * g.out.cols + col, (long)c * g.out.colpad + col, in[jb]);
+        }
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) {
+            const int ii = b0 + jb;
+            const int i = SPLITK ? wave * NR + ii : ii;
+            const int c = m0 + 8 * (i / 4) + 4 * half + (i % 4);
+            if (c >= g.out.C) continue;
+            float ym[NM > 0 ? NM : 1];
+#pragma unroll
+            for (int q = 0; q < NM; ++q) ym[q] = tot[1 + q][ii];
+            fwd_store<float, NM>(A, (long)c * g.out.cols + col, in[jb], tot[0][ii], ym);
+        }
     }
 }
 
@@ -420,6 +654,8 @@ struct FastBwdArgs {
     int nm;                     // masks of layer k+1
     const float* Wr;            // dense: W rows padded to fanpad (zeros past layer k)
     int fanpad;
+    const float* Wb;            // convolution: class weights [group][class][nkp][16]
+    int nkp;                    // taps per class (C_{k+1} J^2) rounded up to 4
     const T* cvec;              // objective rows (layout of layer n)
     const T* vs;                // layer k+1 operand of the W^T product
     const T* u[kMaxMasks];      // layer k+1 operands of the |W|^T products
@@ -430,18 +666,40 @@ struct FastBwdArgs {
     uint32_t* zbits;            // layer k (k >= 1)
 };
 
-// Finishes neuron (c, col) of layer k from its f (without own): x*, bits.
-// Every lane of the wave calls it (ballots).
+// Finishing a neuron of layer k from its f (without own): x*, bits, in
+// loads and stores so that several neurons' loads can be in flight
+// together; the stores' ballots need every lane of the wave.
 template <typename T>
-__device__ __forceinline__ void bwd_finish(const FastBwdArgs<T>& A, int c, long col, bool ok, long idx, T f,
-                                           long wave_base, int lane) {
+struct BwdIn {
+    T own, g, lo, hi;
+    bool dg;
+};
+
+template <typename T>
+__device__ __forceinline__ void bwd_load(const FastBwdArgs<T>& A, int c, long col, bool ok, long idx, BwdIn<T>& in) {
+    in.own = in.g = (T)0;
+    in.lo = in.hi = (T)0;
+    in.dg = false;
+    if (!ok) return;
+    const long bi = (long)c * A.gn.in.colpad + col;
+    if (A.k >= 1) {
+        in.own = A.own[idx];
+        in.g = A.gk[idx];
+    }
+    in.lo = A.nk.lo[idx];
+    in.hi = A.nk.hi[idx];
+    in.dg = getbit(A.nk.deg, bi) != 0u;
+}
+
+template <typename T>
+__device__ __forceinline__ void bwd_store(const FastBwdArgs<T>& A, bool ok, long idx, T f, const BwdIn<T>& in,
+                                          long wave_base, int lane) {
     bool xb = false, zb = false;
     if (ok) {
-        const long bi = (long)c * A.gn.in.colpad + col;
-        if (A.k >= 1) f += A.own[idx];
-        xb = f >= (T)0 || getbit(A.nk.deg, bi);
-        A.nk.xstar[idx] = xb ? A.nk.hi[idx] : A.nk.lo[idx];
-        if (A.k >= 1) zb = A.gk[idx] >= (T)0;
+        if (A.k >= 1) f += in.own;
+        xb = f >= (T)0 || in.dg;
+        A.nk.xstar[idx] = xb ? in.hi : in.lo;
+        if (A.k >= 1) zb = in.g >= (T)0;
     }
     put_wave_bits(A.nk.xbits, wave_base, xb, lane);
     if (A.k >= 1) put_wave_bits(A.zbits, wave_base, zb, lane);
@@ -464,8 +722,10 @@ __global__ void __launch_bounds__(kWave * KS) k_bwd_conv(FastBwdArgs<T> A) {
     const int lane = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);  // wave-uniform
     const int tid = wave * kWave + lane;
-    const long col = (long)blockIdx.x * kWave + lane;
-    const int c0 = blockIdx.y * CB;
+    int tile, group;
+    xcd_tile(tile, group);
+    const long col = (long)tile * kWave + lane;
+    const int c0 = group * CB;
     const int S = A.S;
     const int ks = g.ksz, st = g.stride;
     const int nw = O.C * ks * ks * CB;
@@ -550,7 +810,13 @@ __global__ void __launch_bounds__(kWave * KS) k_bwd_conv(FastBwdArgs<T> A) {
         red[wave][e][lane] = part;
     }
     __syncthreads();
-    const long wave_base = (long)blockIdx.x * kWave;
+    const long wave_base = (long)tile * kWave;
+    BwdIn<T> in[EPW];
+#pragma unroll
+    for (int j = 0; j < EPW; ++j) {  // loads of every neuron first
+        const int c = min(c0 + wave * EPW + j, L.C - 1);
+        bwd_load<T>(A, c, col, colok, ((long)c * S + s) * L.P + p, in[j]);
+    }
 #pragma unroll
     for (int j = 0; j < EPW; ++j) {
         const int e = wave * EPW + j;
@@ -559,9 +825,196 @@ __global__ void __launch_bounds__(kWave * KS) k_bwd_conv(FastBwdArgs<T> A) {
         T f = 0;
 #pragma unroll
         for (int w = 0; w < KS; ++w) f += red[w][e][lane];
-        const long idx = ((long)c * S + s) * L.P + p;
-        bwd_finish<T>(A, c, col, colok, idx, f, (long)c * L.colpad + wave_base, lane);
+        bwd_store<T>(A, colok, ((long)c * S + s) * L.P + p, f, in[j], (long)c * L.colpad + wave_base, lane);
     }
+}
+
+// Transposed convolution on the matrix cores (v_mfma_f32_16x16x4f32: lane l
+// holds A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator register r is
+// C[4 (l / 16) + r][l % 16]).  The positions (y, x) of layer k fall into
+// stride^2 parity classes ((y + pad) % st, (x + pad) % st); within a class
+// every position receives output (qy - jy, qx - jx) of layer k+1 through tap
+// (ry + st jy, rx + st jx), (qy, qx) = ((y + pad) / st, (x + pad) / st), so
+// f over a class is a dense GEMM: A = the class's weights (16 channels x
+// C_{k+1} J^2 taps, J = ceil(ks / st), zero where a tap falls outside the
+// kernel), B = the gathered operands (zero outside layer k+1).
+// Grid (S, ceil(C_k / 16)), block (64, KS): a block owns one subproblem and
+// 16 channels; its waves take (class, group of 4 column tiles) items in
+// turn.  Partial f (sigma_q folded) goes to LDS in natural position order,
+// then the waves finish 64-position runs (P_k % 64 == 0).
+template <int NM, int KSZ, int STR>
+__global__ void __launch_bounds__(kWave * KS) k_bwd_conv_mfma(FastBwdArgs<float> A) {
+    typedef float floatx4 __attribute__((ext_vector_type(4)));
+    constexpr int NT = 4;  // column tiles of 16 per item
+    extern __shared__ float fbuf[];  // [rows][P_k]
+    const LayerGeo& g = A.gn;
+    const NeuronLayout& L = g.in;
+    const NeuronLayout& O = g.out;
+    const int lane = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    const int S = A.S;
+    const int s = blockIdx.x;
+    const int grp = blockIdx.y;
+    const int c0 = grp * 16;
+    const int rows = min(16, L.C - c0);
+    const int ks = KSZ > 0 ? KSZ : g.ksz;
+    const int st = STR > 0 ? STR : g.stride;
+    const int pd = g.pad;
+    const int J = (ks + st - 1) / st;
+    const int nk = O.C * J * J;
+    const int nkp = A.nkp;
+    const int r4 = lane >> 4, cl = lane & 15;
+    const long obase = (long)s * O.P;
+    const long ostride = (long)S * O.P;
+    int counter = 0;
+    for (int cls = 0; cls < st * st; ++cls) {
+        const int ry = cls / st, rx = cls - (cls / st) * st;
+        const int yf = ((ry - pd) % st + st) % st, xf = ((rx - pd) % st + st) % st;
+        const int ny = yf < L.H ? (L.H - 1 - yf) / st + 1 : 0;
+        const int nx = xf < L.W ? (L.W - 1 - xf) / st + 1 : 0;
+        const int cnt = ny * nx;
+        const float* Wc = A.Wb + ((long)grp * st * st + cls) * nkp * 16;
+        for (int n0 = 0; n0 < cnt; n0 += NT * 16) {
+            if ((counter++ % KS) != wave) continue;  // uniform
+            // this lane's column in each of the NT tiles
+            int qy[NT], qx[NT], pos[NT];
+            bool nok[NT];
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const int n = n0 + j * 16 + cl;
+                nok[j] = n < cnt;
+                const int nn = nok[j] ? n : 0;
+                const int iy = nn / nx, ix = nn - (nn / nx) * nx;
+                const int y = yf + st * iy, x = xf + st * ix;
+                qy[j] = (y + pd) / st;
+                qx[j] = (x + pd) / st;
+                pos[j] = y * L.W + x;
+            }
+            floatx4 acc[NT][1 + NM];
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+#pragma unroll
+                for (int r = 0; r <= NM; ++r) acc[j][r] = floatx4{0.f, 0.f, 0.f, 0.f};
+            // U steps of 4 taps per trip; the next trip's loads are issued
+            // before this trip's products
+            constexpr int U = 2;
+            float wv[U], bvv[U][NT], buv[U][NT][NM > 0 ? NM : 1];
+            bool okk[U][NT];
+            auto load = [&](int kt) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int k = kt + 4 * u + r4;
+                    const bool kok = k < nk;
+                    const int kk = kok ? k : 0;
+                    const int co = kk / (J * J), rem = kk - (kk / (J * J)) * (J * J);
+                    const int jy = rem / J, jx = rem - (rem / J) * J;
+                    wv[u] = Wc[(long)(kt + 4 * u < nkp ? k : r4) * 16 + cl];
+#pragma unroll
+                    for (int j = 0; j < NT; ++j) {
+                        const int oy = qy[j] - jy, ox = qx[j] - jx;
+                        const bool ok = kok && nok[j] && oy >= 0 && oy < O.H && ox >= 0 && ox < O.W;
+                        const long a = ok ? (long)co * ostride + obase + (long)oy * O.W + ox : 0;
+                        bvv[u][j] = A.vs[a];
+#pragma unroll
+                        for (int q = 0; q < NM; ++q) buv[u][j][q] = A.u[q][a];
+                        okk[u][j] = ok;
+                    }
+                }
+            };
+            load(0);
+            for (int kt = 0; kt < nkp; kt += 4 * U) {
+                float w2[U], b2[U][NT], u2[U][NT][NM > 0 ? NM : 1];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    w2[u] = kt + 4 * u < nkp ? wv[u] : 0.f;
+#pragma unroll
+                    for (int j = 0; j < NT; ++j) {
+                        b2[u][j] = okk[u][j] ? bvv[u][j] : 0.f;
+#pragma unroll
+                        for (int q = 0; q < NM; ++q) u2[u][j][q] = okk[u][j] ? buv[u][j][q] : 0.f;
+                    }
+                }
+                if (kt + 4 * U < nkp) load(kt + 4 * U);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const float wabs = fabsf(w2[u]);
+#pragma unroll
+                    for (int j = 0; j < NT; ++j) {
+                        acc[j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(w2[u], b2[u][j], acc[j][0], 0, 0, 0);
+#pragma unroll
+                        for (int q = 0; q < NM; ++q)
+                            acc[j][1 + q] =
+                                __builtin_amdgcn_mfma_f32_16x16x4f32(wabs, u2[u][j][q], acc[j][1 + q], 0, 0, 0);
+                    }
+                }
+            }
+            // fold sigma_q of each neuron and park f in natural order
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                if (!nok[j]) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int c = 4 * r4 + r;
+                    if (c >= rows) continue;
+                    float f = acc[j][0][r];
+                    if (NM > 0) {
+                        const unsigned h = A.xpk[((long)(c0 + c) * S + s) * L.P + pos[j]];
+#pragma unroll
+                        for (int q = 0; q < NM; ++q) f += 0.5f * flip(acc[j][1 + q][r], (h >> q) & 1u);
+                    }
+                    fbuf[c * L.P + pos[j]] = f;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // finish 64-position runs, NB runs' loads in flight together
+    constexpr int NB = 4;
+    const int runs = L.P / kWave;
+    const int nrun = rows * runs;
+    for (int ch0 = wave * NB; ch0 < nrun; ch0 += KS * NB) {
+        BwdIn<float> in[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int ch = min(ch0 + b, nrun - 1);
+            const int c = ch / runs;
+            const int p = (ch - c * runs) * kWave + lane;
+            bwd_load<float>(A, c0 + c, (long)s * L.P + p, true, ((long)(c0 + c) * S + s) * L.P + p, in[b]);
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int ch = ch0 + b;
+            if (ch >= nrun) break;  // uniform
+            const int c = ch / runs;
+            const int p = (ch - c * runs) * kWave + lane;
+            const long col = (long)s * L.P + p;
+            bwd_store<float>(A, true, ((long)(c0 + c) * S + s) * L.P + p, fbuf[c * L.P + p], in[b],
+                             (long)(c0 + c) * L.colpad + col - lane, lane);
+        }
+    }
+}
+
+// Class weights for k_bwd_conv_mfma: Wb[grp][cls][k][c] = W[co][16 grp + c][ky][kx]
+// with k = (co J + jy) J + jx, ky = ry + st jy, kx = rx + st jx, zero past
+// the kernel, past C_k or past C_{k+1} J^2.
+__global__ void __launch_bounds__(256) k_class_weights(const float* W, float* Wb, int Ck, int C1, int ks, int st,
+                                                       int nkp, long n) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = (int)(i % 16);
+    const long r1 = i / 16;
+    const int k = (int)(r1 % nkp);
+    const long r2 = r1 / nkp;
+    const int cls = (int)(r2 % (st * st));
+    const int grp = (int)(r2 / (st * st));
+    const int J = (ks + st - 1) / st;
+    const int ry = cls / st, rx = cls % st;
+    const int co = k / (J * J), jy = (k / J) % J, jx = k % J;
+    const int ky = ry + st * jy, kx = rx + st * jx;
+    const int cc = grp * 16 + c;
+    float v = 0.f;
+    if (co < C1 && ky < ks && kx < ks && cc < Ck) v = W[(((long)co * Ck + cc) * ks + ky) * ks + kx];
+    Wb[i] = v;
 }
 
 // Dense layer k+1 into layer k, column mapping (any P_k; P1 = (P_k == 1),
@@ -577,8 +1030,10 @@ __global__ void __launch_bounds__(kWave * KS) k_bwd_dense(FastBwdArgs<T> A) {
     const NeuronLayout& L = g.in;
     const int lane = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);  // wave-uniform
-    const long col = (long)blockIdx.x * kWave + lane;
-    const int c0 = blockIdx.y * CB;
+    int tile, group;
+    xcd_tile(tile, group);
+    const long col = (long)tile * kWave + lane;
+    const int c0 = group * CB;
     const int S = A.S;
     const bool colok = col < L.cols;
     const int s = colok ? (int)(col / L.P) : 0;
@@ -622,17 +1077,22 @@ __global__ void __launch_bounds__(kWave * KS) k_bwd_dense(FastBwdArgs<T> A) {
         red[wave][e][lane] = part;
     }
     __syncthreads();
-    const long wave_base = (long)blockIdx.x * kWave;
+    const long wave_base = (long)tile * kWave;
+    BwdIn<T> in[EPW];
+#pragma unroll
+    for (int j = 0; j < EPW; ++j) {  // loads of every neuron first
+        const int c = min(c0 + wave * EPW + j, L.C - 1);
+        bwd_load<T>(A, c, col, colok, ((long)c * S + s) * L.P + p, in[j]);
+    }
 #pragma unroll
     for (int j = 0; j < EPW; ++j) {
         const int e = wave * EPW + j;
         const int c = c0 + e;
-        if (c >= L.C) break;
+        if (c >= L.C) break;  // uniform
         T f = 0;
 #pragma unroll
         for (int w = 0; w < KS; ++w) f += red[w][e][lane];
-        const long idx = ((long)c * S + s) * L.P + p;
-        bwd_finish<T>(A, c, col, colok, idx, f, (long)c * L.colpad + wave_base, lane);
+        bwd_store<T>(A, colok, ((long)c * S + s) * L.P + p, f, in[j], (long)c * L.colpad + wave_base, lane);
     }
 }
 
@@ -695,6 +1155,12 @@ __global__ void __launch_bounds__(kWave * KS) k_bwd_dense_pos(FastBwdArgs<T> A) 
         red[wave][j][lane] = part;
     }
     __syncthreads();
+    BwdIn<T> in[EPW];
+#pragma unroll
+    for (int jj = 0; jj < EPW; ++jj) {  // loads of every neuron first
+        const int s = sb + wave * EPW + jj;
+        bwd_load<T>(A, c, (long)s * L.P + p, true, ((long)c * S + s) * L.P + p, in[jj]);
+    }
 #pragma unroll
     for (int jj = 0; jj < EPW; ++jj) {
         const int j = wave * EPW + jj;
@@ -704,8 +1170,7 @@ __global__ void __launch_bounds__(kWave * KS) k_bwd_dense_pos(FastBwdArgs<T> A) 
 #pragma unroll
         for (int w = 0; w < KS; ++w) f += red[w][j][lane];
         const long idx = ((long)c * S + s) * L.P + p;
-        const long col = (long)s * L.P + p;
-        bwd_finish<T>(A, c, col, true, idx, f, (long)c * L.colpad + (long)s * L.P + (p - lane), lane);
+        bwd_store<T>(A, true, idx, f, in[jj], (long)c * L.colpad + (long)s * L.P + (p - lane), lane);
     }
 }
 

@@ -28,6 +28,12 @@ pytestmark = pytest.mark.gpu
 SMALL_CONV = [WL.ConvSpec(2, 7, 9, 5, 3, 1, 1), WL.ConvSpec(5, 7, 9, 6, 4, 2, 1),
               WL.DenseSpec(6 * 3 * 4, 13), WL.DenseSpec(13, 3)]
 SMALL_DENSE = [WL.DenseSpec(37, 53), WL.DenseSpec(53, 29), WL.DenseSpec(29, 4)]
+# shapes that take the matrix-core kernels of FP32 plans: a 32-channel
+# convolution forward (kernel 4, stride 2), a transposed convolution into a
+# 16-channel layer of 256 positions, a dense layer fed by 64-position
+# channels (forward on matrix cores, backward with positions on lanes)
+MFMA_CONV = [WL.ConvSpec(2, 16, 16, 16, 3, 1, 1), WL.ConvSpec(16, 16, 16, 32, 4, 2, 1),
+             WL.DenseSpec(32 * 8 * 8, 20), WL.DenseSpec(20, 3)]
 
 
 def _A():
@@ -58,6 +64,8 @@ def workloads_small():
                          max_fixed=3, name="dense-37-53-29-4"),
         WL.custom_config(SMALL_CONV, S=11, seed=22, eps=0.05, schedule=sched, max_fixed=4,
                          name="conv-2x7x9"),
+        WL.custom_config(MFMA_CONV, S=9, seed=23, eps=0.03, schedule=sched, max_fixed=6,
+                         name="conv-2x16x16"),
     ]
 
 
@@ -214,7 +222,7 @@ def _window_plan(prec, rule):
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 @pytest.mark.parametrize("rule", ["supergradient", "adam"])
-@pytest.mark.parametrize("wi", [0, 1])
+@pytest.mark.parametrize("wi", [0, 1, 2])
 def test_iteration_windows_match_oracle(wi, rule, prec):
     """Import the oracle's state at points of its run (the Big-M start, mid
     Big-M, the Active Set start with its mask additions, and later), advance
@@ -235,10 +243,13 @@ def test_iteration_windows_match_oracle(wi, rule, prec):
     A, ops, probs, net, plan, _ = _setup(w, params)
     want = set(starts) | {(ph, t + win) for ph, t in starts}
     runs = [O.solve(p, prm, snapshot_at=sorted(want, key=str)) for p in probs]
-    # FP32 under Adam: an entry whose supergradient has stayed within rounding
-    # of zero keeps a near-zero second moment, so its step is still decided by
-    # rounding; allow at most 0.5% of entries to differ, each by at most 2.5
-    # step sizes
+    # FP32 under Adam: Adam's step is the supergradient divided by the root of
+    # its second moment, so an entry whose supergradient is zero in exact
+    # arithmetic (and whose second moment is still near zero) moves by about
+    # one step size in the direction of its rounding residue.  Such an entry
+    # may differ, by at most 2.5 step sizes, only where the oracle's
+    # supergradient at the window start is within rounding of zero; every
+    # other entry must match.
     loose = prec == "fp32" and rule == "adam"
     lr_max = max(prm.bigm_lr[0], prm.as_lr[0])
     n_ent = n_bad = 0
@@ -257,19 +268,35 @@ def test_iteration_windows_match_oracle(wi, rule, prec):
         for s, (p, e) in enumerate(zip(probs, ends)):
             d_ora = O.evaluate(p, e)[0]
             assert abs(lb[s] - d_ora) <= tol * max(1.0, abs(d_ora)), (ph, t, s, lb[s], d_ora)
+            if loose:
+                st0 = sts[s]
+                _, x0, z0, _, _ = O.evaluate(p, st0)
+                sg0 = O.supergradient(p, st0, x0, z0)
             for k in range(1, len(ops)):
                 pairs = [(duals[("alpha", k)][s], e.alpha[k - 1]), (duals[("beta0", k)][s], e.beta0[k - 1]),
                          (duals[("beta1", k)][s], e.beta1[k - 1])]
                 pairs += [(duals[("mask", k, q)][s], e.masks[k - 1][q].beta) for q in range(K)]
-                for name, (a, b) in zip(["alpha", "beta0", "beta1"] + [f"mask{q}" for q in range(K)], pairs):
+                names = ["alpha", "beta0", "beta1"] + [f"mask{q}" for q in range(K)]
+                if loose:
+                    # rounding scale of a supergradient entry of layer k
+                    lh_, uh_ = p.hat(k)
+                    lp_, up_ = p.lu(k - 1)
+                    op = p.W(k)
+                    scale = 1 + np.abs(x0[k]) + np.abs(lh_) + np.abs(uh_) + np.abs(op.b) + \
+                        op.with_data(np.abs(op.w)) @ (np.abs(lp_) + np.abs(up_))
+                    grads = [sg0["alpha"][k - 1], sg0["beta0"][k - 1], sg0["beta1"][k - 1]] + \
+                        [sg0["masks"][k - 1][q] for q in range(K)]
+                for j, (name, (a, b)) in enumerate(zip(names, pairs)):
                     ok = np.abs(a - b) <= eps * (1 + np.abs(b))
                     n_ent += ok.size
                     n_bad += int((~ok).sum())
                     if loose:
+                        tie = np.abs(grads[j]) <= eps * scale
+                        assert np.all(ok | tie), (ph, t, s, k, name, np.flatnonzero(~(ok | tie))[:5])
                         assert np.all(np.abs(a - b) <= 2.5 * lr_max + eps * (1 + np.abs(b))), (ph, t, s, k, name)
                     else:
                         assert ok.all(), (ph, t, s, k, name, np.flatnonzero(~ok)[:5])
-    assert n_bad <= 0.005 * n_ent, (n_bad, n_ent)
+    print(f"{n_bad} of {n_ent} entries differ (ties under Adam's normalised step)" if loose else "", flush=True)
 
 
 def _sampled_min(ops, p, l0, u0, seed, n=400):
@@ -289,10 +316,10 @@ def _sampled_min(ops, p, l0, u0, seed, n=400):
 
 
 def e2e_workloads():
-    return workloads_small() + [WL.mnist_mlp_config()]
+    return workloads_small()[:2] + [WL.mnist_mlp_config(), workloads_small()[2]]
 
 
-@pytest.mark.parametrize("wi", [0, 1, 2])
+@pytest.mark.parametrize("wi", [0, 1, 2, 3])
 def test_end_to_end_fp64(wi):
     """Whole runs (Big-M, Active Set with additions, final bound) in an FP64
     plan agree with the FP64 oracle; sampled outputs bound them from above."""
@@ -308,7 +335,7 @@ def test_end_to_end_fp64(wi):
         assert lb[s] <= _sampled_min(ops, p, w.l0[s], w.u0[s], s) + 1e-9
 
 
-@pytest.mark.parametrize("wi", [0, 1, 2])
+@pytest.mark.parametrize("wi", [0, 1, 2, 3])
 def test_end_to_end_fp32(wi):
     """Whole runs in an FP32 plan: validity, plus a sanity band against the
     FP64 oracle.  A run's final bound depends on every near-tie the

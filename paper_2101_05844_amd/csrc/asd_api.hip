@@ -548,17 +548,43 @@ asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
     const NeuronLayout& L = g.in;
     a.Wb = P->Wb[k + 1];
     a.nkp = P->nkp[k + 1];
-    if (g.kind == ASD_LAYER_CONV2D && L.C >= 16 && L.P % kWave == 0 && (size_t)16 * L.P * 4 <= 48 * 1024) {
-        // matrix-core transposed convolution over parity classes
-        ProfScope ps(P, st, ASD_K_BACKWARD, k);
-        dim3 grid((unsigned)P->S, (unsigned)((L.C + 15) / 16));
-        const size_t dyn = (size_t)std::min(16, L.C) * L.P * sizeof(float);
-        if (g.ksz == 4 && g.stride == 2)
-            hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 4, 2>), grid, dim3(kWave, KS), dyn, st, a);
-        else
-            hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 0, 0>), grid, dim3(kWave, KS), dyn, st, a);
-        LAUNCH_CHECK();
-        return ASD_OK;
+    if (g.kind == ASD_LAYER_CONV2D && L.P % kWave == 0 && L.C >= 16) {
+        // matrix-core transposed convolution over parity classes, operands
+        // staged in LDS (see k_bwd_conv_mfma); shapes it cannot hold fall
+        // through to the column kernel
+        BwdConvShape sh;
+        const int st_ = g.stride, pd = g.pad;
+        sh.J = (g.ksz + st_ - 1) / st_;
+        sh.off = sh.J - 1;
+        const int qymax = (L.H - 1 + pd) / st_, qxmax = (L.W - 1 + pd) / st_;
+        sh.Hp = std::max(g.out.H, qymax + 1) + sh.off;
+        sh.Wp = std::max(g.out.W, qxmax + 1) + sh.off;
+        sh.items = 0;
+        for (int c = 0; c < st_ * st_; ++c) {
+            const int ry = c / st_, rx = c % st_;
+            const int yf = ((ry - pd) % st_ + st_) % st_, xf = ((rx - pd) % st_ + st_) % st_;
+            const int ny = yf < L.H ? (L.H - 1 - yf) / st_ + 1 : 0;
+            const int nx = xf < L.W ? (L.W - 1 - xf) / st_ + 1 : 0;
+            sh.items += (ny * nx + 63) / 64;
+        }
+        sh.NW = std::min(sh.items, 8);
+        sh.dimg = FastDiv{sh.Hp * sh.Wp, 1.0f / (float)(sh.Hp * sh.Wp)};
+        sh.dWp = FastDiv{sh.Wp, 1.0f / (float)sh.Wp};
+        const size_t fbytes = (size_t)std::min(16, L.C) * L.P * sizeof(float);
+        const size_t per_ch = (size_t)(1 + NM) * sh.Hp * sh.Wp * sizeof(float);
+        const size_t budget = 48 * 1024;
+        if (sh.items <= sh.NW && fbytes <= budget && per_ch <= budget) {
+            sh.CC = (int)std::min<size_t>((size_t)g.out.C, budget / per_ch);
+            const size_t dyn = std::max(fbytes, (size_t)sh.CC * per_ch);
+            ProfScope ps(P, st, ASD_K_BACKWARD, k);
+            dim3 grid((unsigned)P->S, (unsigned)((L.C + 15) / 16));
+            if (g.ksz == 4 && g.stride == 2)
+                hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 4, 2>), grid, dim3(kWave, sh.NW), dyn, st, a, sh);
+            else
+                hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 0, 0>), grid, dim3(kWave, sh.NW), dyn, st, a, sh);
+            LAUNCH_CHECK();
+            return ASD_OK;
+        }
     }
     if (g.kind == ASD_LAYER_CONV2D) {
         const int CB = (sizeof(T) == 4 && L.C > 4) ? 8 : 4;
@@ -744,6 +770,12 @@ StepArgsT<T> make_step_args(const asd_plan* P, double lr) {
     };
     bc(P->step, &sa.bc1[0], &sa.bc2[0]);
     for (int q = 0; q < kMaxMasks; ++q) bc(q < P->n_masks ? P->mask_step[q] : 1, &sa.bc1[1 + q], &sa.bc2[1 + q]);
+    for (int g = 0; g < 1 + kMaxMasks; ++g) {
+        const int stp = g == 0 ? P->step : (g - 1 < P->n_masks ? P->mask_step[g - 1] : 1);
+        const int s1 = stp > 0 ? stp : 1;
+        sa.c1[g] = (T)(lr / (1.0 - pow(P->prm.adam_beta1, (double)s1)));
+        sa.ib2[g] = (T)(1.0 / (1.0 - pow(P->prm.adam_beta2, (double)s1)));
+    }
     return sa;
 }
 
@@ -1063,6 +1095,10 @@ asd_status asd_plan_workspace_size(const asd_net* net, int32_t S, const asd_para
     tmp.n = net->n;
     tmp.prm = *params;
     setup_plan_geometry(&tmp);
+    for (int k = 0; k <= tmp.n; ++k)
+        if ((long)tmp.nl[k].C * tmp.nl[k].colpad >= (1L << 31))
+            return fail(ASD_EINVAL, "layer %d holds %ld neurons over the batch; at most 2^31 are supported", k,
+                        (long)tmp.nl[k].C * tmp.nl[k].colpad);
     Carver cv{nullptr, 0};
     carve(&tmp, cv);
     *bytes = cv.off + 256;

@@ -65,6 +65,19 @@ constexpr int kPointBit = 15;
 // contiguous range of (column tile, channel group) pairs, all channel groups
 // of a column tile next to each other: tiles that read the same inputs then
 // share one L2.  Returns (column tile, channel group).
+// Integer division n / d for 0 <= n < 2^22 by a divisor known only at run
+// time: a float reciprocal estimate, corrected once.
+struct FastDiv {
+    int d;
+    float rcp;
+};
+__device__ __forceinline__ int fdiv(int n, FastDiv f) {
+    int q = (int)((float)n * f.rcp);
+    const int r = n - q * f.d;
+    q += (r >= f.d ? 1 : 0) - (r < 0 ? 1 : 0);
+    return q;
+}
+
 __device__ __forceinline__ void xcd_tile(int& tile, int& group) {
     const unsigned gx = gridDim.x, gy = gridDim.y, n = gx * gy;
     const unsigned lin = blockIdx.y * gx + blockIdx.x;
@@ -110,7 +123,8 @@ struct FwdIn {
 };
 
 template <typename T, int NM>
-__device__ __forceinline__ void fwd_load(const FastFwdArgs<T>& A, int c, long idx, long bi, FwdIn<T, NM>& in) {
+__device__ __forceinline__ void fwd_load(const FastFwdArgs<T>& A, int c, uint32_t idx, uint32_t bi, FwdIn<T, NM>& in) {
+    __builtin_assume(idx < (1u << 30));  // byte offsets fit 32 bits (checked at plan creation)
     const cptr_t<ReluLayerT<T>> R = kconst_t(A.R);
     const bool adam = A.st.rule != ASD_RULE_SUPERGRADIENT;
     in.bb = (T)A.g.b[c];
@@ -150,8 +164,9 @@ __device__ __forceinline__ void fwd_load(const FastFwdArgs<T>& A, int c, long id
 // ym[q] = (|W| (sigma_q . x))[i] + 2 (W+ x_point)[i], the projected step, the
 // derived sums own, g, vs, u_q; stores only.
 template <typename T, int NM>
-__device__ __forceinline__ void fwd_store(const FastFwdArgs<T>& A, long idx, const FwdIn<T, NM>& in, T yd,
+__device__ __forceinline__ void fwd_store(const FastFwdArgs<T>& A, uint32_t idx, const FwdIn<T, NM>& in, T yd,
                                           const T* ym) {
+    __builtin_assume(idx < (1u << 30));
     const cptr_t<ReluLayerT<T>> R = kconst_t(A.R);
     const StepArgsT<T>& st = A.st;
     const bool adam = st.rule != ASD_RULE_SUPERGRADIENT;
@@ -161,15 +176,20 @@ __device__ __forceinline__ void fwd_store(const FastFwdArgs<T>& A, long idx, con
     gr[0] = xhat - x;
     gr[1] = x - z * uh;
     gr[2] = x - xhat + ((T)1 - z) * lh;
+    // Adam: theta + (lr / (1 - b1^t)) m / (sqrt(v / (1 - b2^t)) + eps), with
+    // the hardware square root and reciprocal (a few ulps in FP32)
     auto step = [&](T th, T m, T v, T g, int grp, T* mo, T* vo) -> T {
         if (!adam) return tmax0(th + st.lr * g);
         const T mm = st.b1 * m + ((T)1 - st.b1) * g;
         const T vv = st.b2 * v + ((T)1 - st.b2) * g * g;
         mo[idx] = mm;
         vo[idx] = vv;
-        const T mh = mm / st.bc1[grp];
-        const T vh = vv / st.bc2[grp];
-        return tmax0(th + st.lr * mh / (tsqrt(vh) + st.eps));
+        if constexpr (sizeof(T) == 4) {
+            const float den = __builtin_amdgcn_sqrtf(vv * st.ib2[grp]) + st.eps;
+            return tmax0(th + st.c1[grp] * mm * __builtin_amdgcn_rcpf(den));
+        } else {
+            return tmax0(th + st.c1[grp] * mm / (tsqrt(vv * st.ib2[grp]) + st.eps));
+        }
     };
     const T al = step(in.th[0], in.m[0], in.v[0], gr[0], 0, R->alpha_m, R->alpha_v);
     const T b0 = step(in.th[1], in.m[1], in.v[1], gr[1], 0, R->beta0_m, R->beta0_v);
@@ -199,7 +219,7 @@ __device__ __forceinline__ void fwd_store(const FastFwdArgs<T>& A, long idx, con
 }
 
 template <typename T, int NM>
-__device__ __forceinline__ void fwd_update(const FastFwdArgs<T>& A, int c, long idx, long bi, T yd,
+__device__ __forceinline__ void fwd_update(const FastFwdArgs<T>& A, int c, uint32_t idx, uint32_t bi, T yd,
                                            const T* ym) {
     FwdIn<T, NM> in;
     fwd_load<T, NM>(A, c, idx, bi, in);
@@ -676,24 +696,26 @@ struct BwdIn {
 };
 
 template <typename T>
-__device__ __forceinline__ void bwd_load(const FastBwdArgs<T>& A, int c, long col, bool ok, long idx, BwdIn<T>& in) {
+__device__ __forceinline__ void bwd_load(const FastBwdArgs<T>& A, int c, long col, bool ok, uint32_t idx,
+                                         BwdIn<T>& in) {
+    __builtin_assume(idx < (1u << 30));
     in.own = in.g = (T)0;
     in.lo = in.hi = (T)0;
     in.dg = false;
     if (!ok) return;
-    const long bi = (long)c * A.gn.in.colpad + col;
     if (A.k >= 1) {
         in.own = A.own[idx];
         in.g = A.gk[idx];
     }
     in.lo = A.nk.lo[idx];
     in.hi = A.nk.hi[idx];
-    in.dg = getbit(A.nk.deg, bi) != 0u;
+    in.dg = in.lo == in.hi;  // point box
 }
 
 template <typename T>
-__device__ __forceinline__ void bwd_store(const FastBwdArgs<T>& A, bool ok, long idx, T f, const BwdIn<T>& in,
+__device__ __forceinline__ void bwd_store(const FastBwdArgs<T>& A, bool ok, uint32_t idx, T f, const BwdIn<T>& in,
                                           long wave_base, int lane) {
+    __builtin_assume(idx < (1u << 30));
     bool xb = false, zb = false;
     if (ok) {
         if (A.k >= 1) f += in.own;
@@ -837,21 +859,34 @@ __global__ void __launch_bounds__(kWave * KS) k_bwd_conv(FastBwdArgs<T> A) {
 // (ry + st jy, rx + st jx), (qy, qx) = ((y + pad) / st, (x + pad) / st), so
 // f over a class is a dense GEMM: A = the class's weights (16 channels x
 // C_{k+1} J^2 taps, J = ceil(ks / st), zero where a tap falls outside the
-// kernel), B = the gathered operands (zero outside layer k+1).
-// Grid (S, ceil(C_k / 16)), block (64, KS): a block owns one subproblem and
-// 16 channels; its waves take (class, group of 4 column tiles) items in
-// turn.  Partial f (sigma_q folded) goes to LDS in natural position order,
-// then the waves finish 64-position runs (P_k % 64 == 0).
+// kernel), B = the operands of layer k+1 at those outputs (zero outside it).
+// Grid (S, ceil(C_k / 16)), block (64, NW): a block owns one subproblem and
+// 16 channels.  Work items are (class, 64 positions of the class); in round
+// r wave w takes item r NW + w (one round: items <= NW).  The operand images
+// of the subproblem (v and every u_q, with a zero border of J - 1 outputs)
+// are staged in LDS in chunks of CC output channels, so the B gathers are LDS
+// reads.  Partial f (sigma_q folded) is then parked in the same LDS in
+// natural position order, and the waves finish 64-position runs
+// (P_k % 64 == 0).
+struct BwdConvShape {
+    int J, off, Hp, Wp;   // taps per axis, border, staged image size
+    int CC;               // output channels per staged chunk
+    int items, NW;        // work items, waves per block
+    FastDiv dimg, dWp;    // divisions by Hp Wp and by Wp
+};
+
 template <int NM, int KSZ, int STR>
-__global__ void __launch_bounds__(kWave * KS) k_bwd_conv_mfma(FastBwdArgs<float> A) {
+__global__ void __launch_bounds__(kWave * 8) k_bwd_conv_mfma(FastBwdArgs<float> A, BwdConvShape B) {
     typedef float floatx4 __attribute__((ext_vector_type(4)));
     constexpr int NT = 4;  // column tiles of 16 per item
-    extern __shared__ float fbuf[];  // [rows][P_k]
+    extern __shared__ float lds[];
     const LayerGeo& g = A.gn;
     const NeuronLayout& L = g.in;
     const NeuronLayout& O = g.out;
     const int lane = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    const int NW = B.NW;
+    const int tid = wave * kWave + lane;
     const int S = A.S;
     const int s = blockIdx.x;
     const int grp = blockIdx.y;
@@ -860,95 +895,150 @@ __global__ void __launch_bounds__(kWave * KS) k_bwd_conv_mfma(FastBwdArgs<float>
     const int ks = KSZ > 0 ? KSZ : g.ksz;
     const int st = STR > 0 ? STR : g.stride;
     const int pd = g.pad;
-    const int J = (ks + st - 1) / st;
-    const int nk = O.C * J * J;
+    constexpr int JC = (KSZ > 0 && STR > 0) ? (KSZ + STR - 1) / STR : 0;  // taps per axis if fixed
+    const int J = JC > 0 ? JC : B.J, J2 = J * J, off = B.off, Wp = B.Wp, img = B.Hp * B.Wp;
     const int nkp = A.nkp;
     const int r4 = lane >> 4, cl = lane & 15;
+    const int CC = B.CC;
+    float* opnd = lds;  // [1 + NM][CC][Hp][Wp] while products run
+    float* fbuf = lds;  // [rows][P_k] afterwards (same storage)
     const long obase = (long)s * O.P;
     const long ostride = (long)S * O.P;
-    int counter = 0;
-    for (int cls = 0; cls < st * st; ++cls) {
-        const int ry = cls / st, rx = cls - (cls / st) * st;
-        const int yf = ((ry - pd) % st + st) % st, xf = ((rx - pd) % st + st) % st;
-        const int ny = yf < L.H ? (L.H - 1 - yf) / st + 1 : 0;
-        const int nx = xf < L.W ? (L.W - 1 - xf) / st + 1 : 0;
-        const int cnt = ny * nx;
-        const float* Wc = A.Wb + ((long)grp * st * st + cls) * nkp * 16;
-        for (int n0 = 0; n0 < cnt; n0 += NT * 16) {
-            if ((counter++ % KS) != wave) continue;  // uniform
-            // this lane's column in each of the NT tiles
-            int qy[NT], qx[NT], pos[NT];
-            bool nok[NT];
-#pragma unroll
-            for (int j = 0; j < NT; ++j) {
-                const int n = n0 + j * 16 + cl;
-                nok[j] = n < cnt;
-                const int nn = nok[j] ? n : 0;
-                const int iy = nn / nx, ix = nn - (nn / nx) * nx;
-                const int y = yf + st * iy, x = xf + st * ix;
-                qy[j] = (y + pd) / st;
-                qx[j] = (x + pd) / st;
-                pos[j] = y * L.W + x;
+    const int rounds = (B.items + NW - 1) / NW;
+    for (int rd = 0; rd < rounds; ++rd) {
+        // find this wave's item: class cls, first position n0 within the class
+        const int item = rd * NW + wave;
+        int cls = -1, n0 = 0, cnt = 0, yf = 0, xf = 0, nx = 1;
+        {
+            int idx = 0;
+            for (int c = 0; c < st * st && cls < 0; ++c) {
+                const int ry = c / st, rx = c - (c / st) * st;
+                const int yf_ = ((ry - pd) % st + st) % st, xf_ = ((rx - pd) % st + st) % st;
+                const int ny_ = yf_ < L.H ? (L.H - 1 - yf_) / st + 1 : 0;
+                const int nx_ = xf_ < L.W ? (L.W - 1 - xf_) / st + 1 : 0;
+                const int cnt_ = ny_ * nx_;
+                const int groups = (cnt_ + NT * 16 - 1) / (NT * 16);
+                if (item < idx + groups) {
+                    cls = c;
+                    n0 = (item - idx) * NT * 16;
+                    cnt = cnt_;
+                    yf = yf_;
+                    xf = xf_;
+                    nx = nx_;
+                }
+                idx += groups;
             }
-            floatx4 acc[NT][1 + NM];
+        }
+        const bool has = cls >= 0;  // uniform
+        int qy[NT], qx[NT], pos[NT];
+        bool nok[NT];
 #pragma unroll
-            for (int j = 0; j < NT; ++j)
+        for (int j = 0; j < NT; ++j) {
+            const int n = n0 + j * 16 + cl;
+            nok[j] = has && n < cnt;
+            const int nn = nok[j] ? n : 0;
+            const int iy = nn / nx, ix = nn - (nn / nx) * nx;
+            const int y = yf + st * iy, x = xf + st * ix;
+            qy[j] = (y + pd) / st + off;  // staged-image coordinates of tap jy = 0
+            qx[j] = (x + pd) / st + off;
+            pos[j] = y * L.W + x;
+        }
+        floatx4 acc[NT][1 + NM];
 #pragma unroll
-                for (int r = 0; r <= NM; ++r) acc[j][r] = floatx4{0.f, 0.f, 0.f, 0.f};
-            // U steps of 4 taps per trip; the next trip's loads are issued
-            // before this trip's products
-            constexpr int U = 2;
-            float wv[U], bvv[U][NT], buv[U][NT][NM > 0 ? NM : 1];
-            bool okk[U][NT];
-            auto load = [&](int kt) {
+        for (int j = 0; j < NT; ++j)
+#pragma unroll
+            for (int r = 0; r <= NM; ++r) acc[j][r] = floatx4{0.f, 0.f, 0.f, 0.f};
+        // the packed x-bits of this lane's neurons, loaded now so their latency
+        // overlaps the products
+        unsigned hb[NT][4];
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int c = min(4 * r4 + r, rows - 1);
+                hb[j][r] = NM > 0 ? (unsigned)A.xpk[((long)(c0 + c) * S + s) * L.P + pos[j]] : 0u;
+            }
+        const float* Wc = A.Wb + ((long)grp * st * st + (has ? cls : 0)) * nkp * 16;
+        for (int cb = 0; cb < O.C; cb += CC) {
+            const int cc = min(CC, O.C - cb);
+            __syncthreads();  // the previous chunk's reads are done
+            // rows (component r, channel col) of img pixels; 16 loads per
+            // thread in flight, then their LDS stores
+            constexpr int UL = 16;
+            const int total = (1 + NM) * cc * img;
+            const int nthr = kWave * NW;
+            for (int e0 = tid; e0 < total; e0 += UL * nthr) {
+                float v[UL];
+                int dst[UL];
+#pragma unroll
+                for (int u = 0; u < UL; ++u) {
+                    const int e = e0 + u * nthr;
+                    const int ee = e < total ? e : 0;
+                    const int row = fdiv(ee, B.dimg);  // r * cc + col
+                    const int pix = ee - row * img;
+                    int r = 0;
+#pragma unroll
+                    for (int i = 1; i <= NM; ++i) r += row >= i * cc ? 1 : 0;
+                    const int col = row - r * cc;
+                    const int py = fdiv(pix, B.dWp);
+                    const int oy = py - off, ox = pix - py * Wp - off;
+                    const bool ok = e < total && oy >= 0 && oy < O.H && ox >= 0 && ox < O.W;
+                    const long a = ok ? (long)(cb + col) * ostride + obase + (long)oy * O.W + ox : 0;
+                    const float* src = r == 0 ? A.vs : A.u[r - 1];
+                    const float vl = src[a];
+                    v[u] = ok ? vl : 0.f;
+                    dst[u] = e < total ? (r * CC + col) * img + pix : -1;
+                }
+#pragma unroll
+                for (int u = 0; u < UL; ++u)
+                    if (dst[u] >= 0) opnd[dst[u]] = v[u];
+            }
+            __syncthreads();
+            if (!has) continue;
+            // steps of 4 taps; the weights of the next U steps are loaded
+            // while this trip's products run
+            const int kbeg = cb * J2, kend = (cb + cc) * J2;
+            constexpr int U = 8;
+            float wq[U];
+            auto wload = [&](int kt) {
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int k = kt + 4 * u + r4;
-                    const bool kok = k < nk;
-                    const int kk = kok ? k : 0;
-                    const int co = kk / (J * J), rem = kk - (kk / (J * J)) * (J * J);
-                    const int jy = rem / J, jx = rem - (rem / J) * J;
-                    wv[u] = Wc[(long)(kt + 4 * u < nkp ? k : r4) * 16 + cl];
-#pragma unroll
-                    for (int j = 0; j < NT; ++j) {
-                        const int oy = qy[j] - jy, ox = qx[j] - jx;
-                        const bool ok = kok && nok[j] && oy >= 0 && oy < O.H && ox >= 0 && ox < O.W;
-                        const long a = ok ? (long)co * ostride + obase + (long)oy * O.W + ox : 0;
-                        bvv[u][j] = A.vs[a];
-#pragma unroll
-                        for (int q = 0; q < NM; ++q) buv[u][j][q] = A.u[q][a];
-                        okk[u][j] = ok;
-                    }
+                    wq[u] = Wc[(long)(k < kend ? k : kbeg) * 16 + cl];
                 }
             };
-            load(0);
-            for (int kt = 0; kt < nkp; kt += 4 * U) {
-                float w2[U], b2[U][NT], u2[U][NT][NM > 0 ? NM : 1];
+            wload(kbeg);
+            for (int kt = kbeg; kt < kend; kt += 4 * U) {
+                float w2[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) w2[u] = kt + 4 * u + r4 < kend ? wq[u] : 0.f;
+                if (kt + 4 * U < kend) wload(kt + 4 * U);
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    w2[u] = kt + 4 * u < nkp ? wv[u] : 0.f;
+                    if (kt + 4 * u >= kend) break;  // uniform
+                    const int k = kt + 4 * u + r4;
+                    const int kk = k < kend ? k : kbeg;
+                    const int col = kk / J2 - cb, rem = kk - (kk / J2) * J2;
+                    const int jy = rem / J, jx = rem - (rem / J) * J;
+                    const float wa = w2[u];
+                    const float wabs = fabsf(wa);
+                    const int ib = col * img - jy * Wp - jx;
 #pragma unroll
                     for (int j = 0; j < NT; ++j) {
-                        b2[u][j] = okk[u][j] ? bvv[u][j] : 0.f;
-#pragma unroll
-                        for (int q = 0; q < NM; ++q) u2[u][j][q] = okk[u][j] ? buv[u][j][q] : 0.f;
-                    }
-                }
-                if (kt + 4 * U < nkp) load(kt + 4 * U);
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const float wabs = fabsf(w2[u]);
-#pragma unroll
-                    for (int j = 0; j < NT; ++j) {
-                        acc[j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(w2[u], b2[u][j], acc[j][0], 0, 0, 0);
+                        const int li = ib + qy[j] * Wp + qx[j];
+                        acc[j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa, opnd[li], acc[j][0], 0, 0, 0);
 #pragma unroll
                         for (int q = 0; q < NM; ++q)
-                            acc[j][1 + q] =
-                                __builtin_amdgcn_mfma_f32_16x16x4f32(wabs, u2[u][j][q], acc[j][1 + q], 0, 0, 0);
+                            acc[j][1 + q] = __builtin_amdgcn_mfma_f32_16x16x4f32(wabs, opnd[(1 + q) * CC * img + li],
+                                                                                 acc[j][1 + q], 0, 0, 0);
                     }
                 }
             }
-            // fold sigma_q of each neuron and park f in natural order
+        }
+        // fold sigma_q of each neuron and park f in natural order (the
+        // storage of the staged operands: every wave is past its products)
+        __syncthreads();
+        if (has) {
 #pragma unroll
             for (int j = 0; j < NT; ++j) {
                 if (!nok[j]) continue;
@@ -957,11 +1047,8 @@ __global__ void __launch_bounds__(kWave * KS) k_bwd_conv_mfma(FastBwdArgs<float>
                     const int c = 4 * r4 + r;
                     if (c >= rows) continue;
                     float f = acc[j][0][r];
-                    if (NM > 0) {
-                        const unsigned h = A.xpk[((long)(c0 + c) * S + s) * L.P + pos[j]];
 #pragma unroll
-                        for (int q = 0; q < NM; ++q) f += 0.5f * flip(acc[j][1 + q][r], (h >> q) & 1u);
-                    }
+                    for (int q = 0; q < NM; ++q) f += 0.5f * flip(acc[j][1 + q][r], (hb[j][r] >> q) & 1u);
                     fbuf[c * L.P + pos[j]] = f;
                 }
             }
@@ -969,10 +1056,10 @@ __global__ void __launch_bounds__(kWave * KS) k_bwd_conv_mfma(FastBwdArgs<float>
     }
     __syncthreads();
     // finish 64-position runs, NB runs' loads in flight together
-    constexpr int NB = 4;
+    constexpr int NB = 8;
     const int runs = L.P / kWave;
     const int nrun = rows * runs;
-    for (int ch0 = wave * NB; ch0 < nrun; ch0 += KS * NB) {
+    for (int ch0 = wave * NB; ch0 < nrun; ch0 += NW * NB) {
         BwdIn<float> in[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b) {

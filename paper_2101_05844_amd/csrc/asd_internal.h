@@ -98,6 +98,8 @@ struct StepArgsT {
     T b1, b2, eps;
     T bc1[1 + kMaxMasks];   // 1 - b1^step for the alpha/beta group and each slot
     T bc2[1 + kMaxMasks];
+    T c1[1 + kMaxMasks];    // lr / (1 - b1^step)  (rounded once, on the host)
+    T ib2[1 + kMaxMasks];   // 1 / (1 - b2^step)
 };
 
 }  // namespace asd

@@ -32,6 +32,57 @@ def per_layer_state_bytes(n_k, n_prev, K):
     return 24 * (3 + K) * n_k + 8 * n_k + 8 * K * n_k + K * (n_k + n_prev) / 8.0
 
 
+def kernel_unit_bytes(role, layer, sizes, K):
+    """Algorithmic bytes per subproblem of one launch of an iteration kernel.
+
+    forward k (update of ReLU layer k): the layer's state (per_layer_state_bytes)
+    plus reading x*_k and x*_{k-1} (4 B each).
+    backward k (inner minimisation of layer k): the 1 + K operands of layer
+    k+1 the transposed products read (4 B each; K = 0 into the last layer's
+    inputs, whose operand is the objective row), the box of layer k (8 B) and
+    x*_k written (4 B)."""
+    if role == "forward":
+        return per_layer_state_bytes(sizes[layer], sizes[layer - 1], K) + 4 * (sizes[layer] + sizes[layer - 1])
+    if role == "backward":
+        nxt = sizes[layer + 1]
+        kk = K if layer + 1 < len(sizes) - 1 else 0
+        return 4 * (1 + kk) * nxt + 12 * sizes[layer]
+    return None
+
+
+def source_digest():
+    """SHA-256 over the library sources (the traffic figures of a committed
+    profile apply only to the kernels they were measured on)."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2101_05844_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".h", ".hip")):
+            h.update(name.encode())
+            h.update(open(os.path.join(d, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(kernel_key):
+    """HBM bytes per launch of the kernel from the counter summary under
+    profiles/ (FETCH_SIZE and WRITE_SIZE passes, scaled by a copy-kernel
+    calibration), or None when the summary is missing or was measured on
+    other sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_cifar_wide_s512.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    start = text.find("```json")
+    if start < 0:
+        return None
+    block = text[start + 7:text.find("```", start + 7)]
+    data = json.loads(block)
+    if data.get("source_digest") != source_digest():
+        return None
+    entry = data.get("kernels", {}).get(kernel_key)
+    return None if entry is None else entry["hbm_bytes_per_launch"]
+
+
 def unit_bytes(sizes, K):
     """Whole-network algorithmic bytes per subproblem-iteration with K masks:
     every ReLU layer's update plus the input box (8 B per input) and the
@@ -179,22 +230,26 @@ def main():
         prof = plan.profile_read()
         plan.profile(False)
         kernels = {f"{r}:{l}": {"launches": n, "avg_us": 1e3 * ms / n} for (r, l), (n, ms) in prof.items()}
-        dom = max(prof.items(), key=lambda kv: kv[1][1])
+        # dominant iteration kernel (by time over the solve) and its
+        # algorithmic bytes, launch by launch with the mask count of that
+        # iteration (Big-M iterations first, K = 0)
+        iter_prof = {key: v for key, v in prof.items() if key[0] in ("forward", "backward")}
+        dom = max(iter_prof.items(), key=lambda kv: kv[1][1])
         (role, layer), (n_launch, tot_ms) = dom
-        # algorithmic bytes of the dominant kernel over the solve: the forward
-        # (update) kernel of layer k moves its layer's state; every other
-        # kernel is charged the same layer state it reads
-        n_k = sizes[layer] if layer < len(sizes) else sizes[-1]
-        n_prev = sizes[layer - 1] if layer >= 1 else 0
-        per_iter = [per_layer_state_bytes(n_k, n_prev, masks_at(t, sched)) for t in range(sched.as_iters)]
-        K_bigm = [0] * sched.bigm_iters
-        per_iter = [per_layer_state_bytes(n_k, n_prev, K) for K in K_bigm] + per_iter
-        tot_bytes = S * sum(per_iter[:n_launch]) if n_launch <= len(per_iter) else None
-        if tot_bytes:
-            achieved = tot_bytes / (tot_ms / 1e3) / 1e9
+        # the forward pass of iteration t sees the masks added in t, the
+        # backward pass the ones before
+        Ks_all = [0] * sched.bigm_iters + (Ks if role == "forward" else [0] + Ks[:-1])
+        if n_launch == len(Ks_all):
+            tot_bytes = S * sum(kernel_unit_bytes(role, layer, sizes, K) for K in Ks_all)
+            avg_s = tot_ms / 1e3 / n_launch
+            achieved = tot_bytes / n_launch / avg_s / 1e9
+            traffic = committed_traffic(f"{role}:{layer}")
             roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                        "kernel": f"{role} layer {layer}", "avg_launch_us": round(1e3 * tot_ms / n_launch, 2)}
+                        "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "traffic": None if traffic is None else round(traffic / avg_s / 1e9, 1),
+                        "kernel": f"{role} layer {layer}", "avg_launch_us": round(1e6 * avg_s, 2),
+                        "alg_bytes_per_launch": round(tot_bytes / n_launch),
+                        "hbm_bytes_per_launch": None if traffic is None else round(traffic)}
     whole_as_gbs = alg_as / (as_ms / args.steps / 1e3) / 1e9
     cpu = None
     if not args.no_cpu_baseline:

@@ -587,9 +587,11 @@ asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
         }
     }
     if (g.kind == ASD_LAYER_CONV2D) {
+        // column kernel, the taps split over KS waves
         const int CB = (sizeof(T) == 4 && L.C > 4) ? 8 : 4;
+        const int ksp = KS;
         const size_t dyn = (size_t)g.out.C * g.ksz * g.ksz * CB * sizeof(float);
-        const size_t stat = (size_t)KS * CB * kWave * sizeof(T);
+        const size_t stat = (size_t)ksp * CB * kWave * sizeof(T);
         if (dyn + stat > 64 * 1024) return launch_backward<T, T>(P, k, 0, ASD_K_BACKWARD, st);
         ProfScope ps(P, st, ASD_K_BACKWARD, k);
         dim3 grid((unsigned)(L.colpad / kWave), (unsigned)((L.C + CB - 1) / CB));
@@ -597,17 +599,17 @@ asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
         if constexpr (sizeof(T) == 4) {
             if (CB == 8) {
                 if (k4s2)
-                    hipLaunchKernelGGL((k_bwd_conv<T, NM, 8, 4, 2>), grid, dim3(kWave, KS), dyn, st, a);
+                    hipLaunchKernelGGL((k_bwd_conv<T, NM, 8, 4, 2, KS>), grid, dim3(kWave, KS), dyn, st, a);
                 else
-                    hipLaunchKernelGGL((k_bwd_conv<T, NM, 8, 0, 0>), grid, dim3(kWave, KS), dyn, st, a);
+                    hipLaunchKernelGGL((k_bwd_conv<T, NM, 8, 0, 0, KS>), grid, dim3(kWave, KS), dyn, st, a);
                 LAUNCH_CHECK();
                 return ASD_OK;
             }
         }
         if (k4s2)
-            hipLaunchKernelGGL((k_bwd_conv<T, NM, 4, 4, 2>), grid, dim3(kWave, KS), dyn, st, a);
+            hipLaunchKernelGGL((k_bwd_conv<T, NM, 4, 4, 2, KS>), grid, dim3(kWave, KS), dyn, st, a);
         else
-            hipLaunchKernelGGL((k_bwd_conv<T, NM, 4, 0, 0>), grid, dim3(kWave, KS), dyn, st, a);
+            hipLaunchKernelGGL((k_bwd_conv<T, NM, 4, 0, 0, KS>), grid, dim3(kWave, KS), dyn, st, a);
         LAUNCH_CHECK();
         return ASD_OK;
     }

@@ -731,8 +731,9 @@ __device__ __forceinline__ void bwd_store(const FastBwdArgs<T>& A, bool ok, uint
 // (colpad_k / 64, ceil(C_k / CB)), block (64, KS); dynamic LDS holds the
 // block's weights as [C_{k+1}][ks][ks][CB].  KSZ, STR > 0 fix the kernel
 // size and stride (taps of one output channel unrolled), 0 = any.
-template <typename T, int NM, int CB, int KSZ, int STR>
-__global__ void __launch_bounds__(kWave * KS) k_bwd_conv(FastBwdArgs<T> A) {
+template <typename T, int NM, int CB, int KSZ, int STR, int KSP>
+__global__ void __launch_bounds__(kWave * KSP) k_bwd_conv(FastBwdArgs<T> A) {
+    constexpr int KS = KSP;  // waves splitting the reduction (1: a wave owns all taps of its columns)
     static_assert(CB % KS == 0, "CB must be a multiple of KS");
     constexpr int EPW = CB / KS;
     constexpr int NA = NM > 0 ? NM : 1;
@@ -774,45 +775,62 @@ __global__ void __launch_bounds__(kWave * KS) k_bwd_conv(FastBwdArgs<T> A) {
         for (int q = 0; q < NA; ++q) au[q][e] = 0;
     }
     const int co0 = O.C * wave / KS, co1 = O.C * (wave + 1) / KS;
+    // this lane's packed x-bits, loaded before the products
+    unsigned hb[CB];
+#pragma unroll
+    for (int e = 0; e < CB; ++e)
+        hb[e] = NM > 0 && colok ? (unsigned)A.xpk[((long)min(c0 + e, L.C - 1) * S + s) * L.P + p] : 0u;
     // taps per axis: ky = ry + st * jy receives output row qy - jy
     const int JT = (ks + st - 1) / st;
     constexpr int J = (KSZ > 0 && STR > 0) ? (KSZ + STR - 1) / STR : 1;
+    // UC output channels per trip: all their gathers are issued before the
+    // first product of the trip (1: larger trips cost occupancy, measured
+    // slower on the benchmark shapes)
+    constexpr int UC = 1;
     if (colok) {
-        for (int co = co0; co < co1; ++co) {
-            const long obase = ((long)co * S + s) * O.P;
-            const int wco = co * ks * ks;
+        for (int cu = co0; cu < co1; cu += UC) {
             for (int jy0 = 0; jy0 < JT; jy0 += J) {
                 for (int jx0 = 0; jx0 < JT; jx0 += J) {
-                    T vv[J][J], uu[NA][J][J];
-                    int kk[J][J];
+                    T vv[UC][J][J], uu[UC][NA][J][J];
+                    int kk[UC][J][J];
+                    bool okk[UC][J][J];
 #pragma unroll
-                    for (int jy = 0; jy < J; ++jy) {
+                    for (int uc = 0; uc < UC; ++uc) {
+                        const int co = min(cu + uc, co1 - 1);
+                        const long obase = ((long)co * S + s) * O.P;
 #pragma unroll
-                        for (int jx = 0; jx < J; ++jx) {
-                            const int ky = ry + st * (jy0 + jy), kx = rx + st * (jx0 + jx);
-                            const int oy = qy - (jy0 + jy), ox = qx - (jx0 + jx);
-                            const bool ok = ky < ks && kx < ks && oy >= 0 && oy < O.H && ox >= 0 && ox < O.W;
-                            const long a = ok ? obase + (long)oy * O.W + ox : 0;
-                            const T vl = A.vs[a];
-                            vv[jy][jx] = ok ? vl : (T)0;
+                        for (int jy = 0; jy < J; ++jy) {
 #pragma unroll
-                            for (int q = 0; q < NM; ++q) {
-                                const T ul = A.u[q][a];
-                                uu[q][jy][jx] = ok ? ul : (T)0;
+                            for (int jx = 0; jx < J; ++jx) {
+                                const int ky = ry + st * (jy0 + jy), kx = rx + st * (jx0 + jx);
+                                const int oy = qy - (jy0 + jy), ox = qx - (jx0 + jx);
+                                const bool ok = cu + uc < co1 && ky < ks && kx < ks && oy >= 0 && oy < O.H &&
+                                                ox >= 0 && ox < O.W;
+                                const long a = ok ? obase + (long)oy * O.W + ox : 0;
+                                vv[uc][jy][jx] = A.vs[a];
+#pragma unroll
+                                for (int q = 0; q < NM; ++q) uu[uc][q][jy][jx] = A.u[q][a];
+                                kk[uc][jy][jx] = (co * ks + (ok ? ky : 0)) * ks + (ok ? kx : 0);
+                                okk[uc][jy][jx] = ok;
                             }
-                            kk[jy][jx] = ok ? ky * ks + kx : 0;
                         }
                     }
 #pragma unroll
-                    for (int jy = 0; jy < J; ++jy) {
+                    for (int uc = 0; uc < UC; ++uc) {
 #pragma unroll
-                        for (int jx = 0; jx < J; ++jx) {
-                            const float* wp = &wl[(wco + kk[jy][jx]) * CB];
+                        for (int jy = 0; jy < J; ++jy) {
 #pragma unroll
-                            for (int e = 0; e < CB; ++e) {
-                                acc[e] += (T)wp[e] * vv[jy][jx];
+                            for (int jx = 0; jx < J; ++jx) {
+                                const bool ok = okk[uc][jy][jx];
+                                const T v = ok ? vv[uc][jy][jx] : (T)0;
+                                const float* wp = &wl[kk[uc][jy][jx] * CB];
 #pragma unroll
-                                for (int q = 0; q < NM; ++q) au[q][e] += (T)fabsf(wp[e]) * uu[q][jy][jx];
+                                for (int e = 0; e < CB; ++e) {
+                                    acc[e] += (T)wp[e] * v;
+#pragma unroll
+                                    for (int q = 0; q < NM; ++q)
+                                        au[q][e] += (T)fabsf(wp[e]) * (ok ? uu[uc][q][jy][jx] : (T)0);
+                                }
                             }
                         }
                     }
@@ -824,11 +842,8 @@ __global__ void __launch_bounds__(kWave * KS) k_bwd_conv(FastBwdArgs<T> A) {
 #pragma unroll
     for (int e = 0; e < CB; ++e) {
         T part = acc[e];
-        if (NM > 0 && colok && c0 + e < L.C) {
-            const unsigned h = A.xpk[((long)(c0 + e) * S + s) * L.P + p];
 #pragma unroll
-            for (int q = 0; q < NM; ++q) part += (T)0.5 * flip(au[q][e], (h >> q) & 1u);
-        }
+        for (int q = 0; q < NM; ++q) part += (T)0.5 * flip(au[q][e], (hb[e] >> q) & 1u);
         red[wave][e][lane] = part;
     }
     __syncthreads();
@@ -874,6 +889,77 @@ struct BwdConvShape {
     int items, NW;        // work items, waves per block
     FastDiv dimg, dWp;    // divisions by Hp Wp and by Wp
 };
+
+// Stages the operand images of one subproblem for output channels
+// [cb, cb + cc) of layer k+1 (v and every u_q) into opnd
+// [1 + NM][CC][Hp][Wp], zero outside the layer; 16 loads per thread in
+// flight, then their LDS stores.
+template <int NM>
+__device__ __forceinline__ void stage_operands(const FastBwdArgs<float>& A, const BwdConvShape& B, float* opnd,
+                                               int cb, int cc, long obase, long ostride, int tid, int nthr) {
+    const NeuronLayout& O = A.gn.out;
+    const int img = B.Hp * B.Wp, Wp = B.Wp, off = B.off, CC = B.CC;
+    constexpr int UL = 16;
+    const int total = (1 + NM) * cc * img;
+    for (int e0 = tid; e0 < total; e0 += UL * nthr) {
+        float v[UL];
+        int dst[UL];
+#pragma unroll
+        for (int u = 0; u < UL; ++u) {
+            const int e = e0 + u * nthr;
+            const int ee = e < total ? e : 0;
+            const int row = fdiv(ee, B.dimg);  // r * cc + col
+            const int pix = ee - row * img;
+            int r = 0;
+#pragma unroll
+            for (int i = 1; i <= NM; ++i) r += row >= i * cc ? 1 : 0;
+            const int col = row - r * cc;
+            const int py = fdiv(pix, B.dWp);
+            const int oy = py - off, ox = pix - py * Wp - off;
+            const bool ok = e < total && oy >= 0 && oy < O.H && ox >= 0 && ox < O.W;
+            const long a = ok ? (long)(cb + col) * ostride + obase + (long)oy * O.W + ox : 0;
+            const float* src = r == 0 ? A.vs : A.u[r - 1];
+            const float vl = src[a];
+            v[u] = ok ? vl : 0.f;
+            dst[u] = e < total ? (r * CC + col) * img + pix : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < UL; ++u)
+            if (dst[u] >= 0) opnd[dst[u]] = v[u];
+    }
+}
+
+// Finishes rows x P_k neurons of subproblem s, channels c0 .. c0 + rows - 1,
+// from f parked in fbuf [rows][P_k] (natural order), in 64-position runs
+// (P_k % 64 == 0), NB runs' loads in flight together.
+__device__ __forceinline__ void finish_runs(const FastBwdArgs<float>& A, const float* fbuf, int s, int c0, int rows,
+                                            int wave, int nw, int lane) {
+    const NeuronLayout& L = A.gn.in;
+    const int S = A.S;
+    constexpr int NB = 8;
+    const int runs = L.P / kWave;
+    const int nrun = rows * runs;
+    for (int ch0 = wave * NB; ch0 < nrun; ch0 += nw * NB) {
+        BwdIn<float> in[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int ch = min(ch0 + b, nrun - 1);
+            const int c = ch / runs;
+            const int p = (ch - c * runs) * kWave + lane;
+            bwd_load<float>(A, c0 + c, (long)s * L.P + p, true, ((long)(c0 + c) * S + s) * L.P + p, in[b]);
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int ch = ch0 + b;
+            if (ch >= nrun) break;  // uniform
+            const int c = ch / runs;
+            const int p = (ch - c * runs) * kWave + lane;
+            const long col = (long)s * L.P + p;
+            bwd_store<float>(A, true, ((long)(c0 + c) * S + s) * L.P + p, fbuf[c * L.P + p], in[b],
+                             (long)(c0 + c) * L.colpad + col - lane, lane);
+        }
+    }
+}
 
 template <int NM, int KSZ, int STR>
 __global__ void __launch_bounds__(kWave * 8) k_bwd_conv_mfma(FastBwdArgs<float> A, BwdConvShape B) {
@@ -962,37 +1048,7 @@ __global__ void __launch_bounds__(kWave * 8) k_bwd_conv_mfma(FastBwdArgs<float> 
         for (int cb = 0; cb < O.C; cb += CC) {
             const int cc = min(CC, O.C - cb);
             __syncthreads();  // the previous chunk's reads are done
-            // rows (component r, channel col) of img pixels; 16 loads per
-            // thread in flight, then their LDS stores
-            constexpr int UL = 16;
-            const int total = (1 + NM) * cc * img;
-            const int nthr = kWave * NW;
-            for (int e0 = tid; e0 < total; e0 += UL * nthr) {
-                float v[UL];
-                int dst[UL];
-#pragma unroll
-                for (int u = 0; u < UL; ++u) {
-                    const int e = e0 + u * nthr;
-                    const int ee = e < total ? e : 0;
-                    const int row = fdiv(ee, B.dimg);  // r * cc + col
-                    const int pix = ee - row * img;
-                    int r = 0;
-#pragma unroll
-                    for (int i = 1; i <= NM; ++i) r += row >= i * cc ? 1 : 0;
-                    const int col = row - r * cc;
-                    const int py = fdiv(pix, B.dWp);
-                    const int oy = py - off, ox = pix - py * Wp - off;
-                    const bool ok = e < total && oy >= 0 && oy < O.H && ox >= 0 && ox < O.W;
-                    const long a = ok ? (long)(cb + col) * ostride + obase + (long)oy * O.W + ox : 0;
-                    const float* src = r == 0 ? A.vs : A.u[r - 1];
-                    const float vl = src[a];
-                    v[u] = ok ? vl : 0.f;
-                    dst[u] = e < total ? (r * CC + col) * img + pix : -1;
-                }
-#pragma unroll
-                for (int u = 0; u < UL; ++u)
-                    if (dst[u] >= 0) opnd[dst[u]] = v[u];
-            }
+            stage_operands<NM>(A, B, opnd, cb, cc, obase, ostride, tid, kWave * NW);
             __syncthreads();
             if (!has) continue;
             // steps of 4 taps; the weights of the next U steps are loaded
@@ -1055,30 +1111,7 @@ __global__ void __launch_bounds__(kWave * 8) k_bwd_conv_mfma(FastBwdArgs<float> 
         }
     }
     __syncthreads();
-    // finish 64-position runs, NB runs' loads in flight together
-    constexpr int NB = 8;
-    const int runs = L.P / kWave;
-    const int nrun = rows * runs;
-    for (int ch0 = wave * NB; ch0 < nrun; ch0 += NW * NB) {
-        BwdIn<float> in[NB];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const int ch = min(ch0 + b, nrun - 1);
-            const int c = ch / runs;
-            const int p = (ch - c * runs) * kWave + lane;
-            bwd_load<float>(A, c0 + c, (long)s * L.P + p, true, ((long)(c0 + c) * S + s) * L.P + p, in[b]);
-        }
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const int ch = ch0 + b;
-            if (ch >= nrun) break;  // uniform
-            const int c = ch / runs;
-            const int p = (ch - c * runs) * kWave + lane;
-            const long col = (long)s * L.P + p;
-            bwd_store<float>(A, true, ((long)(c0 + c) * S + s) * L.P + p, fbuf[c * L.P + p], in[b],
-                             (long)(c0 + c) * L.colpad + col - lane, lane);
-        }
-    }
+    finish_runs(A, fbuf, s, c0, rows, wave, NW, lane);
 }
 
 // Class weights for k_bwd_conv_mfma: Wb[grp][cls][k][c] = W[co][16 grp + c][ky][kx]

@@ -72,6 +72,8 @@ import scipy.sparse as sp
 class LinearOp:
     W: sp.csr_matrix      # [n_out, n_in], float64, explicit receptive-field pattern
     b: np.ndarray         # [n_out] float64
+    widx: Optional[np.ndarray] = None   # per stored entry: flat index into the layer's weight tensor
+    bidx: Optional[np.ndarray] = None   # per output neuron: index into the layer's bias vector
 
     @property
     def n_out(self) -> int:
@@ -105,7 +107,8 @@ def dense_op(W: np.ndarray, b: np.ndarray) -> LinearOp:
     indptr = np.arange(n_out + 1, dtype=np.int64) * n_in
     indices = np.tile(np.arange(n_in, dtype=np.int64), n_out)
     M = sp.csr_matrix((W.reshape(-1).copy(), indices, indptr), shape=(n_out, n_in))
-    return LinearOp(M, np.asarray(b, dtype=np.float64).copy())
+    return LinearOp(M, np.asarray(b, dtype=np.float64).copy(), widx=np.arange(n_out * n_in, dtype=np.int64),
+                    bidx=np.arange(n_out, dtype=np.int64))
 
 
 def conv_op(weight: np.ndarray, bias: np.ndarray, c_in: int, h_in: int, w_in: int,
@@ -121,7 +124,7 @@ def conv_op(weight: np.ndarray, bias: np.ndarray, c_in: int, h_in: int, w_in: in
     assert c_in_w == c_in
     h_out = (h_in + 2 * pad - kh) // stride + 1
     w_out = (w_in + 2 * pad - kw) // stride + 1
-    rows, cols, vals = [], [], []
+    rows, cols, vals, widx = [], [], [], []
     for co in range(c_out):
         for oy in range(h_out):
             for ox in range(w_out):
@@ -138,6 +141,7 @@ def conv_op(weight: np.ndarray, bias: np.ndarray, c_in: int, h_in: int, w_in: in
                             rows.append(r)
                             cols.append((ci * h_in + iy) * w_in + ix)
                             vals.append(weight[co, ci, ky, kx])
+                            widx.append(((co * c_in + ci) * kh + ky) * kw + kx)
     rows = np.asarray(rows, dtype=np.int64)
     cols = np.asarray(cols, dtype=np.int64)
     vals = np.asarray(vals, dtype=np.float64)
@@ -148,7 +152,8 @@ def conv_op(weight: np.ndarray, bias: np.ndarray, c_in: int, h_in: int, w_in: in
     indptr = np.cumsum(indptr)
     M = sp.csr_matrix((vals, cols, indptr), shape=(n_out, c_in * h_in * w_in))
     b = np.repeat(np.asarray(bias, dtype=np.float64), h_out * w_out)
-    return LinearOp(M, b)
+    return LinearOp(M, b, widx=np.asarray(widx, dtype=np.int64),
+                    bidx=np.repeat(np.arange(c_out, dtype=np.int64), h_out * w_out))
 
 
 def ops_from_workload_layers(layers) -> List[LinearOp]:
@@ -630,3 +635,73 @@ def lagrangian_constraint_form(p: Problem, st: DualState, x, z) -> float:
             L += float(M.beta @ (M.LI * (1.0 - zk) - M.WI @ x[k - 1] - op.b * zk
                                  - M.UI * zk + xk))
     return L
+
+
+# ----------------------------------------------------------------------------
+# Gradient of the bound at fixed duals (the adjoint)
+# ----------------------------------------------------------------------------
+
+
+def bound_gradient(p: Problem, st: DualState):
+    """Gradient of d_B with respect to every weight, bias and the input box,
+    at fixed duals and fixed active sets, the pre-activation bounds l_hat,
+    u_hat of layers 1..n-1 held as given inputs.
+
+    d_B = min over the primal box of the Lagrangian (constraint form, App. D);
+    it is linear in (x, z) and the minimiser (x*, z*) is a box vertex, so
+    (Danskin) its gradient is the Lagrangian's partial derivative at
+    (x*, z*) wherever the minimiser is unique:
+      dd/dW_k[i,j] = x*_{k-1}[j] (alpha_k[i] - beta_{k,1}[i] - sum_I I[i,j] beta_I[i])
+                     + sum_I beta_I[i] ((1 - z*_k[i]) I[i,j] Lchk[i,j]
+                                        - z*_k[i] (1 - I[i,j]) Uchk[i,j]),
+      dd/db_k[i]   = alpha_k[i] - beta_{k,1}[i] - z*_k[i] sum_I beta_I[i],
+    for k = 1..n-1 (LI and UI are the row sums of W . I . Lchk and
+    W . (1 - I) . Uchk, Sec. 2.2, with the check entries chosen by the sign
+    of W); for the last layer dd/dW_n = c x*_{n-1}^T, dd/db_n = c.  The input
+    box enters through x*_0 (dd/du_0 = -f_0 where f_0 >= 0, dd/dl_0 = -f_0
+    where f_0 < 0) and through the check entries of layer 1's mask
+    constants.  Returns (dW, db, dl0, du0): dW[k-1] and db[k-1] in the shapes
+    of layer k's weight tensor and bias (entries of a convolution summed over
+    positions)."""
+    d, x, z, f, g = evaluate(p, st)
+    n = p.n
+    dW, db = [], []
+    dl0 = np.zeros_like(p.l0)
+    du0 = np.zeros_like(p.u0)
+    for k in range(1, n + 1):
+        op = p.W(k)
+        rows, cols, w = op.rows, op.cols, op.w
+        xprev = x[k - 1]
+        nw = int(op.widx.max()) + 1
+        nb = int(op.bidx.max()) + 1
+        if k == n:
+            ge = p.c[rows] * xprev[cols]
+            gb = p.c.copy()
+        else:
+            a = st.alpha[k - 1] - st.beta1[k - 1]
+            ge = a[rows] * xprev[cols]
+            zk = z[k - 1]
+            gb = a - zk * sum((M.beta for M in st.masks[k - 1]), np.zeros(op.n_out))
+            lp, up = p.lu(k - 1)
+            Lchk, Uchk = check_matrices(op, lp, up)
+            for M in st.masks[k - 1]:
+                If = M.I.astype(np.float64)
+                br, zr = M.beta[rows], zk[rows]
+                ge = ge - If * br * xprev[cols]
+                ge = ge + br * ((1.0 - zr) * If * Lchk - zr * (1.0 - If) * Uchk)
+                if k == 1:
+                    # check entries of the input box: Lchk = l0 (W >= 0) or u0, Uchk = u0 (W >= 0) or l0
+                    pos = w >= 0
+                    cl = br * ((1.0 - zr) * If * w * pos - zr * (1.0 - If) * w * (~pos))
+                    cu = br * ((1.0 - zr) * If * w * (~pos) - zr * (1.0 - If) * w * pos)
+                    np.add.at(dl0, cols, cl)
+                    np.add.at(du0, cols, cu)
+        gw = np.zeros(nw)
+        np.add.at(gw, op.widx, ge)
+        gbb = np.zeros(nb)
+        np.add.at(gbb, op.bidx, gb)
+        dW.append(gw)
+        db.append(gbb)
+    dl0 += np.where(f[0] < 0, -f[0], 0.0)
+    du0 += np.where(f[0] >= 0, -f[0], 0.0)
+    return dW, db, dl0, du0

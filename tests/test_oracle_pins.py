@@ -449,3 +449,76 @@ def test_adam_ascent_matches_library_adam():
     for s, (g, lr) in enumerate(zip(grads, lrs), start=1):
         t, m, v = O.adam_ascent(t, m, v, g, s, lr, c)
     assert np.allclose(t, th.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+# ----------------------------------------------------------------------------
+# Adjoint: gradient of the bound at fixed duals and fixed active sets
+# ----------------------------------------------------------------------------
+
+
+def _adjoint_problem(kind):
+    if kind == "dense":
+        specs = [WL.DenseSpec(6, 7), WL.DenseSpec(7, 5), WL.DenseSpec(5, 3)]
+    else:
+        specs = [WL.ConvSpec(2, 5, 5, 3, 3, 2, 1), WL.DenseSpec(3 * 3 * 3, 4), WL.DenseSpec(4, 2)]
+    w = WL.custom_config(specs, S=1, seed=77, eps=0.2)
+    layers = [WL.Layer(L.spec, L.W.astype(np.float64), L.b.astype(np.float64)) for L in w.layers]
+    ops = O.ops_from_workload_layers(layers)
+    lh, uh = O.interval_bounds(ops, w.l0[0].astype(float), w.u0[0].astype(float))
+    return layers, lh[:-1], uh[:-1], w.l0[0].astype(float), w.u0[0].astype(float), w.c[0].astype(float)
+
+
+def _bound_at(layers, lh, uh, l0, u0, c, st):
+    """d_B for the given parameters with the duals and active sets of st
+    (each mask keeps its entries I; W . I, LI and UI follow the parameters)."""
+    ops = O.ops_from_workload_layers(layers)
+    p = O.make_problem(ops, l0, u0, lh, uh, c)
+    st2 = st.copy()
+    for k in range(1, p.n):
+        lp_, up_ = p.lu(k - 1)
+        for qi, M in enumerate(st.masks[k - 1]):
+            M2 = O.new_mask(p.W(k), M.I, lp_, up_, M.x_prev, M.z)
+            M2.beta = M.beta.copy()
+            st2.masks[k - 1][qi] = M2
+    return O.evaluate(p, st2)[0], p, st2
+
+
+@pytest.mark.parametrize("kind", ["dense", "conv"])
+def test_bound_gradient_matches_finite_differences(kind):
+    """bound_gradient against central differences of d_B in every weight,
+    bias and input-box coordinate (random duals and masks; the primal
+    minimiser is unique at such points)."""
+    layers, lh, uh, l0, u0, c = _adjoint_problem(kind)
+    rng = np.random.default_rng(5)
+    ops = O.ops_from_workload_layers(layers)
+    p = O.make_problem(ops, l0, u0, lh, uh, c)
+    st = random_state(p, rng, n_masks=2)
+    dW, db, dl0, du0 = O.bound_gradient(p, st)
+    h = 1e-6
+
+    def fd(mutate):
+        lp_, lm_ = [WL.Layer(L.spec, L.W.copy(), L.b.copy()) for L in layers], \
+            [WL.Layer(L.spec, L.W.copy(), L.b.copy()) for L in layers]
+        bp, bm = [l0.copy(), u0.copy()], [l0.copy(), u0.copy()]
+        mutate(lp_, bp, +h)
+        mutate(lm_, bm, -h)
+        dp = _bound_at(lp_, lh, uh, bp[0], bp[1], c, st)[0]
+        dm = _bound_at(lm_, lh, uh, bm[0], bm[1], c, st)[0]
+        return (dp - dm) / (2 * h)
+
+    for k, L in enumerate(layers):
+        for flat in range(L.W.size):
+            def mut(ls, box, e, k=k, flat=flat):
+                ls[k].W.reshape(-1)[flat] += e
+            assert fd(mut) == pytest.approx(dW[k][flat], rel=1e-5, abs=1e-7), ("W", k, flat)
+        for i in range(L.b.size):
+            def mut(ls, box, e, k=k, i=i):
+                ls[k].b[i] += e
+            assert fd(mut) == pytest.approx(db[k][i], rel=1e-5, abs=1e-7), ("b", k, i)
+    for j in range(l0.size):
+        def mutl(ls, box, e, j=j):
+            box[0][j] += e
+        def mutu(ls, box, e, j=j):
+            box[1][j] += e
+        assert fd(mutl) == pytest.approx(dl0[j], rel=1e-5, abs=1e-7), ("l0", j)
+        assert fd(mutu) == pytest.approx(du0[j], rel=1e-5, abs=1e-7), ("u0", j)

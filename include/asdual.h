@@ -246,6 +246,31 @@ asd_status asd_eval(asd_plan* plan, const asd_eval_out* out /* host */, hipStrea
 asd_status asd_oracle(asd_plan* plan, int32_t k, const void* x_prev, const void* z,
                       uint32_t* mask_bits, void* LI, void* UI, hipStream_t stream);
 
+/* ---- Gradient of the bound (adjoint) ---- */
+
+/* Gradient of sum_s g[s] d_B(s) with respect to the network's weights and
+ * biases and each subproblem's input box, at the plan's current duals and
+ * active sets (the values asd_bound evaluates; the pre-activation bounds of
+ * layers 1..n-1 are held fixed).  d_B is the minimum over the primal box of a
+ * Lagrangian linear in (x, z) (constraint form of the relaxation, App. D), so
+ * by Danskin's theorem its gradient is the Lagrangian's partial derivative at
+ * the minimiser (x*, z*) wherever that is unique; at ties it is one
+ * supergradient, with the tie rules of the minimiser (x* = u where f = 0,
+ * z* = 1 where g = 0).  All sums run in FP64 (for an FP32 plan from the FP32
+ * duals) in a fixed order: results are reproducible bit for bit.
+ *   g      [S] (device, double): per-subproblem factors (the upstream
+ *          gradient of a loss of the bounds); required.
+ *   dW, db host arrays [n_layers] of device pointers (double), or NULL;
+ *          any entry may be NULL to skip it.  dW[k] has the element count and
+ *          order of layer k+1's W ([out_c][in_c] or [out_c][in_c][k][k]),
+ *          db[k] has out_c entries; both are summed over the subproblems.
+ *   dl0, du0 [S][n_0] (device, double, may be NULL): g[s] times the
+ *          gradient of d_B(s) with respect to l0 and u0.
+ * Overwrites the plan's minimiser buffers (as asd_bound does); the duals are
+ * unchanged.  Errors: ASD_EINVAL for a NULL plan or g, or before asd_init. */
+asd_status asd_bound_grad(asd_plan* plan, const double* g, double* const* dW /* host */,
+                          double* const* db /* host */, double* dl0, double* du0, hipStream_t stream);
+
 /* ---- Intermediate bounds (App. E; interval propagation) ---- */
 
 /* Pre-activation bounds of layers 1..n (FP64 arithmetic on the FP32 weights,

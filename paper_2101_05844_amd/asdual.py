@@ -85,7 +85,7 @@ _lib = None
 EXPORTED = ["asd_net_create", "asd_net_destroy", "asd_params_default", "asd_plan_workspace_size",
             "asd_plan_create", "asd_plan_destroy", "asd_init", "asd_run", "asd_bound", "asd_solve",
             "asd_state_get", "asd_state_set", "asd_state_get_counts", "asd_state_set_counts",
-            "asd_eval", "asd_oracle", "asd_interval_bounds", "asd_profile_enable", "asd_profile_read",
+            "asd_eval", "asd_oracle", "asd_bound_grad", "asd_interval_bounds", "asd_profile_enable", "asd_profile_read",
             "asd_last_error", "asd_abi_version"]
 
 
@@ -118,6 +118,7 @@ def lib():
     L.asd_state_set_counts.argtypes = [vp, C.POINTER(Counts), i32, vp]
     L.asd_eval.argtypes = [vp, C.POINTER(EvalOut), vp]
     L.asd_oracle.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+    L.asd_bound_grad.argtypes = [vp, vp, C.POINTER(vp), C.POINTER(vp), vp, vp, vp]
     L.asd_interval_bounds.argtypes = [vp, i32, vp, vp, C.POINTER(vp), C.POINTER(vp), vp]
     L.asd_profile_enable.argtypes = [vp, i32]
     L.asd_profile_read.argtypes = [vp, C.POINTER(KernelTime), i32, C.POINTER(i32)]
@@ -316,6 +317,29 @@ class Plan:
         _check(lib().asd_eval(self.handle, C.byref(out), _stream(stream)))
         return res
 
+    def bound_grad(self, g: torch.Tensor, weights: bool = True, box: bool = True, stream=None):
+        """asd_bound_grad: gradient of sum_s g[s] d_B(s) at the current duals.
+
+        Returns (dW, db, dl0, du0): dW[k], db[k] float64 tensors shaped like
+        layer k+1's weight and bias (None when weights is False), dl0, du0
+        [S][n_0] float64 (None when box is False)."""
+        n = self.net.n
+        g = g.to(device="cuda", dtype=torch.float64).contiguous()
+        assert tuple(g.shape) == (self.S,)
+        dW = [torch.empty(tuple(W.shape), dtype=torch.float64, device="cuda") for W in self.net.W] \
+            if weights else None
+        db = [torch.empty(tuple(b.shape), dtype=torch.float64, device="cuda") for b in self.net.b] \
+            if weights else None
+        dl0 = torch.empty(self.S, self.net.sizes[0], dtype=torch.float64, device="cuda") if box else None
+        du0 = torch.empty_like(dl0) if box else None
+        pw = (C.c_void_p * n)(*[t.data_ptr() for t in dW]) if weights else None
+        pb = (C.c_void_p * n)(*[t.data_ptr() for t in db]) if weights else None
+        _check(lib().asd_bound_grad(self.handle, g.data_ptr(),
+                                    C.cast(pw, C.POINTER(C.c_void_p)) if pw is not None else None,
+                                    C.cast(pb, C.POINTER(C.c_void_p)) if pb is not None else None,
+                                    _ptr(dl0), _ptr(du0), _stream(stream)))
+        return dW, db, dl0, du0
+
     def profile(self, enable: bool):
         """asd_profile_enable: HIP-event pairs around every launch of this plan."""
         _check(lib().asd_profile_enable(self.handle, int(enable)))
@@ -351,3 +375,33 @@ def unpack_bits(bits: np.ndarray, fan: int) -> np.ndarray:
     shifts = np.arange(32, dtype=np.uint32)
     out = ((b[..., :, None] >> shifts) & 1).astype(bool)
     return out.reshape(*b.shape[:-1], -1)[..., :fan]
+
+
+class BoundFunction(torch.autograd.Function):
+    """Solves the batch and returns the FP64 bounds [S]; the backward pass is
+    the gradient of the bound at the final duals and active sets (Danskin,
+    asd_bound_grad) with respect to the net's weights and biases and the
+    input box, the pre-activation bounds held fixed.
+
+    Usage: BoundFunction.apply(plan, l0, u0, lhat, uhat, c, *plan.net.W, *plan.net.b)
+    with lhat/uhat tuples; set requires_grad on the tensors whose gradient is
+    wanted (the net's W/b tensors are the ones the library reads)."""
+
+    @staticmethod
+    def forward(ctx, plan, l0, u0, lhat, uhat, c, *params):
+        ctx.plan = plan
+        ctx.n = plan.net.n
+        return plan.solve(l0, u0, list(lhat), list(uhat), c)
+
+    @staticmethod
+    def backward(ctx, glb):
+        plan = ctx.plan
+        need_w = any(ctx.needs_input_grad[6:])
+        need_box = ctx.needs_input_grad[1] or ctx.needs_input_grad[2]
+        dW, db, dl0, du0 = plan.bound_grad(glb, weights=need_w, box=need_box)
+        n = ctx.n
+        gw = [None] * n if dW is None else [t.to(torch.float32) for t in dW]
+        gb = [None] * n if db is None else [t.to(torch.float32) for t in db]
+        gl = dl0.to(torch.float32) if dl0 is not None else None
+        gu = du0.to(torch.float32) if du0 is not None else None
+        return (None, gl, gu, None, None, None, *gw, *gb)

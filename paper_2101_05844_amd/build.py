@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libasdual.so")
 SOURCES = [os.path.join(HERE, "csrc", "asd_api.hip")]
 HEADERS = [os.path.join(HERE, "csrc", "asd_internal.h"), os.path.join(HERE, "csrc", "asd_kernels.h"),
-           os.path.join(HERE, "csrc", "asd_fast.h"),
+           os.path.join(HERE, "csrc", "asd_fast.h"), os.path.join(HERE, "csrc", "asd_adjoint.h"),
            os.path.join(ROOT, "include", "asdual.h")]
 
 

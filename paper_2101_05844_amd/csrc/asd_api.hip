@@ -15,6 +15,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "asd_adjoint.h"
 #include "asd_fast.h"
 
 using namespace asd;
@@ -103,6 +104,7 @@ struct asd_plan {
     void* part;                       // dense forward partial products
     int* pointflag;                   // [kMaxLayers]: point box away from zero in layer k
     void* Rdev;                       // device copy of the ReluLayerT array (update kernels)
+    double* f0;                       // f_0 of the last bound-gradient evaluation
     // scalar state
     int n_masks;
     int step;
@@ -240,6 +242,7 @@ void carve_t(asd_plan* P, Carver& cv) {
     }
     P->part = cv.take<T>(part);
     P->pointflag = cv.take<int>(kMaxLayers);
+    P->f0 = cv.take<double>((size_t)P->nl[0].N * S);
     P->Rdev = cv.take<ReluLayerT<T>>(kMaxLayers);
 }
 
@@ -516,7 +519,7 @@ asd_status fwd_fast(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t st) 
 }
 
 template <typename Tc, typename Ts>
-asd_status launch_backward(asd_plan* P, int k, int want_obj, int role, hipStream_t st);
+asd_status launch_backward(asd_plan* P, int k, int want_obj, int role, hipStream_t st, double* fout = nullptr);
 
 // Iteration backward pass into neuron layer k; NM = masks of layer k+1.
 template <typename T, int NM>
@@ -640,7 +643,7 @@ asd_status bwd_fast(asd_plan* P, int k, hipStream_t st) {
 
 // Backward pass for neuron layer k (f_k, inner minimisation, terms).
 template <typename Tc, typename Ts>
-asd_status launch_backward(asd_plan* P, int k, int want_obj, int role, hipStream_t st) {
+asd_status launch_backward(asd_plan* P, int k, int want_obj, int role, hipStream_t st, double* fout) {
     BwdArgs<Ts> a;
     memset(&a, 0, sizeof(a));
     a.gn = P->geo[k + 1];
@@ -657,6 +660,7 @@ asd_status launch_backward(asd_plan* P, int k, int want_obj, int role, hipStream
     }
     a.nk = NA<Ts>(P)[k];
     a.want_obj = want_obj;
+    a.fout = fout;
     const size_t lds = (size_t)KS * CB * kWave * sizeof(Tc);
     ProfScope ps(P, st, role, k);
     hipLaunchKernelGGL((k_backward<Tc, Ts>), grid_cols(P->nl[k], CB), dim3(kWave, KS), lds, st, a);
@@ -894,6 +898,66 @@ asd_status bound_f64(asd_plan* P, double* out_lb, float* x0, hipStream_t st) {
     for (int k = P->n - 1; k >= 0; --k) TRY((launch_backward<double, double>(P, k, 1, ASD_K_FINAL, st)));
     TRY(reduce_objective<double>(P, out_lb, st));
     if (x0) TRY((launch_layout<double, float>(P->nad[0].xstar, x0, P->nl[0], P->S, 2, st)));
+    return ASD_OK;
+}
+
+// Gradient of sum_s g_s d_B(s) at the current duals and active sets.  The
+// minimiser is recomputed exactly as asd_bound evaluates it (FP64 sums; for an
+// FP32 plan from the FP32 duals), then each gradient is a fixed-order FP64
+// reduction over the subproblems.
+template <typename Ts>
+asd_status bound_grad_t(asd_plan* P, const double* gs, double* const* dW, double* const* db, double* dl0,
+                        double* du0, hipStream_t st) {
+    if constexpr (sizeof(Ts) == 4)
+        for (int k = 1; k < P->n; ++k) TRY(launch_final_sums(P, k, st));
+    for (int k = P->n - 1; k >= 0; --k)
+        TRY((launch_backward<double, Ts>(P, k, 0, ASD_K_OTHER, st, k == 0 ? P->f0 : nullptr)));
+    auto base_args = [&](int k) {
+        GradArgs<Ts> a;
+        memset(&a, 0, sizeof(a));
+        a.g = P->geo[k];
+        a.S = P->S;
+        a.last = (k == P->n);
+        a.nm = a.last ? 0 : P->n_masks;
+        a.gs = gs;
+        a.xin = NA<Ts>(P)[k - 1].xstar;
+        a.lo_in = NA<Ts>(P)[k - 1].lo;
+        a.hi_in = NA<Ts>(P)[k - 1].hi;
+        a.deg_in = NA<Ts>(P)[k - 1].deg;
+        a.cvec = CV<Ts>(P);
+        if (!a.last) a.R = RL<Ts>(P)[k];
+        return a;
+    };
+    for (int k = 1; k <= P->n; ++k) {
+        const LayerGeo& g = P->geo[k];
+        if (dW && dW[k - 1]) {
+            GradArgs<Ts> a = base_args(k);
+            a.out = dW[k - 1];
+            const long entries = g.kind == ASD_LAYER_DENSE ? (long)g.out.C * g.fan
+                                                           : (long)g.out.C * g.in.C * g.ksz * g.ksz;
+            ProfScope ps(P, st, ASD_K_OTHER, k);
+            hipLaunchKernelGGL(k_grad_weight<Ts>, dim3((unsigned)entries), dim3(kGradThreads), 0, st, a);
+            LAUNCH_CHECK();
+        }
+        if (db && db[k - 1]) {
+            GradArgs<Ts> a = base_args(k);
+            a.out = db[k - 1];
+            ProfScope ps(P, st, ASD_K_OTHER, k);
+            hipLaunchKernelGGL(k_grad_bias<Ts>, dim3((unsigned)g.out.C), dim3(kGradThreads), 0, st, a);
+            LAUNCH_CHECK();
+        }
+    }
+    if (dl0 || du0) {
+        GradArgs<Ts> a = base_args(1);
+        a.f0 = P->f0;
+        a.dl0 = dl0;
+        a.du0 = du0;
+        const long n = (long)P->nl[0].C * P->nl[0].cols;
+        ProfScope ps(P, st, ASD_K_OTHER, 0);
+        hipLaunchKernelGGL(k_grad_box<Ts>, dim3((unsigned)((n + kGradThreads - 1) / kGradThreads)),
+                           dim3(kGradThreads), 0, st, a);
+        LAUNCH_CHECK();
+    }
     return ASD_OK;
 }
 
@@ -1200,6 +1264,14 @@ asd_status asd_bound(asd_plan* P, double* out_lb, float* x0, hipStream_t st) {
     if (!P || !out_lb) return fail(ASD_EINVAL, "NULL argument");
     if (!P->loaded) return fail(ASD_EINVAL, "asd_init has not been called");
     return is64(P) ? bound_f64(P, out_lb, x0, st) : bound_f32(P, out_lb, x0, st);
+}
+
+asd_status asd_bound_grad(asd_plan* P, const double* gs, double* const* dW, double* const* db, double* dl0,
+                          double* du0, hipStream_t st) {
+    if (!P || !gs) return fail(ASD_EINVAL, "NULL argument");
+    if (!P->loaded) return fail(ASD_EINVAL, "asd_init has not been called");
+    return is64(P) ? bound_grad_t<double>(P, gs, dW, db, dl0, du0, st)
+                   : bound_grad_t<float>(P, gs, dW, db, dl0, du0, st);
 }
 
 asd_status asd_solve(asd_plan* P, const asd_batch* b, double* out_lb, float* x0, hipStream_t st) {

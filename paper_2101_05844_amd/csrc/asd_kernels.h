@@ -271,6 +271,7 @@ struct BwdArgs {
     NeuronArraysT<Ts> nk;       // layer k box, outputs
     const float* bk;            // bias of layer k (k >= 1), per channel
     int want_obj;
+    double* fout;               // if set: f_k per neuron (internal layout)
 };
 
 template <typename Tc, typename Ts>
@@ -425,6 +426,7 @@ __global__ void __launch_bounds__(kWave * KS) k_backward(BwdArgs<Ts> A) {
         for (int w = 0; w < KS; ++w) f += red[(w * CB + e) * kWave + lane];
         const int nmo = A.nm_own;
         if (A.k >= 1) f += kFinal64 ? (Tc)A.Rk.own64[idx] : (Tc)A.Rk.own[idx];
+        if (A.fout) A.fout[idx] = (double)f;
         // x-bit "x* = upper end"; a point box counts as both ends and keeps the bit set
         xb = f >= 0 || ((dg4 >> e) & 1u);
         const Tc xv = xb ? (Tc)A.nk.hi[idx] : (Tc)A.nk.lo[idx];

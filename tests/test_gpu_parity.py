@@ -368,3 +368,62 @@ def test_deterministic_repeat():
     a = plan.solve(*batch).cpu().numpy()
     b = plan.solve(*batch).cpu().numpy()
     assert np.array_equal(a, b)
+
+
+def _check_grad(got, ref, mag, tol, what):
+    bad = np.abs(got - ref) > tol * (1 + mag)
+    assert not bad.any(), (what, np.flatnonzero(bad)[:5], got[bad][:5], ref[bad][:5])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("wi", [0, 1, 2])
+@pytest.mark.parametrize("n_masks", [0, 3])
+def test_bound_gradient_matches_oracle(wi, n_masks, prec):
+    """asd_bound_grad at imported duals and masks against the oracle's Danskin
+    gradient (pinned by central differences): weight and bias gradients
+    summed over the subproblems with mixed-sign factors, box gradients per
+    subproblem.  Both sides sum in FP64 from the same FP32-valued duals, so
+    the tolerance (1e-9 of the summed magnitudes) covers summation order."""
+    w = workloads_small()[wi]
+    A, ops, probs, net, plan, _ = _setup(w, prec=prec)
+    rng = np.random.default_rng(300 + 10 * wi + n_masks)
+    states = [H.random_integral_state(p, rng, n_masks, scale=0.5) for p in probs]
+    H.import_states(plan, probs, states)
+    gs = rng.uniform(-1.0, 2.0, w.S)
+    dW, db, dl0, du0 = plan.bound_grad(torch.as_tensor(gs))
+    torch.cuda.synchronize()
+    ora = [O.bound_gradient(p, st) for p, st in zip(probs, states)]
+    for k in range(len(ops)):
+        for i, got in ((0, dW[k]), (1, db[k])):
+            ref = sum(gs[s] * ora[s][i][k] for s in range(w.S))
+            mag = sum(abs(gs[s]) * np.abs(ora[s][i][k]) for s in range(w.S))
+            _check_grad(got.cpu().numpy().reshape(-1), ref, mag, 1e-9, ("dW" if i == 0 else "db", k))
+    for i, got in ((2, dl0), (3, du0)):
+        g = got.cpu().numpy()
+        for s in range(w.S):
+            ref = gs[s] * ora[s][i]
+            _check_grad(g[s], ref, np.abs(ref), 1e-9, ("dl0" if i == 2 else "du0", s))
+
+
+def test_bound_function_autograd():
+    """BoundFunction: the solve's bounds in the forward pass, asd_bound_grad
+    in the backward pass (same values as a direct call at the final duals),
+    gradients routed to the net's weights and the input box."""
+    w = workloads_small()[1]
+    A, ops, probs, net, plan, batch = _setup(w, prec="fp64")
+    l0, u0, lht, uht, c = batch
+    l0 = l0.clone().requires_grad_(True)
+    u0 = u0.clone().requires_grad_(True)
+    params = [t.requires_grad_(True) for t in net.W + net.b]
+    lb = A.BoundFunction.apply(plan, l0, u0, tuple(lht), tuple(uht), c, *params)
+    ref_lb = plan.bound()
+    assert torch.equal(lb, ref_lb)
+    gs = torch.linspace(-1.0, 1.0, w.S, dtype=torch.float64, device="cuda")
+    (lb * gs).sum().backward()
+    dW, db, dl0, du0 = plan.bound_grad(gs)
+    for t, ref in zip(net.W + net.b, dW + db):
+        assert torch.equal(t.grad, ref.to(torch.float32))
+    assert torch.equal(l0.grad, dl0.to(torch.float32)) and torch.equal(u0.grad, du0.to(torch.float32))
+    # repeated evaluation is bit-identical (fixed-order sums)
+    dW2, _, dl02, _ = plan.bound_grad(gs)
+    assert all(torch.equal(a, b) for a, b in zip(dW, dW2)) and torch.equal(dl0, dl02)

@@ -103,6 +103,69 @@ def masks_at(t, sched):
     return K
 
 
+def adjoint_weight_bytes(layer, sizes, n_weights, K, S):
+    """Algorithmic bytes of one weight-gradient launch of layer `layer` over S
+    subproblems: per subproblem the multipliers the gradient reads (alpha,
+    beta_1 and the K mask multipliers of the layer, 4 B each), the z bits of
+    the layer and of its K masks, x*, l, u of the layer below (4 B each) with
+    its point-box and K mask x bits; the last layer reads the objective row
+    and x*.  The FP64 gradient is written once (8 B per weight)."""
+    n, m = sizes[layer], sizes[layer - 1]
+    if layer == len(sizes) - 1:
+        per = 4 * n + 4 * m
+    else:
+        per = 4 * (2 + K) * n + (1 + K) * n / 8.0 + 12 * m + (1 + K) * m / 8.0
+    return S * per + 8 * n_weights
+
+
+def adjoint_leg(A, np, torch, WL, reps=3):
+    """Bound gradient on its own workload: converged duals first (the
+    workload's full schedule), then asd_bound_grad timed by HIP events."""
+    w = WL.adjoint_config()
+    S = w.S
+    dev = "cuda:0"
+    t32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=dev)
+    net = A.Net(w.layers, device=dev)
+    l0, u0, c = t32(w.l0), t32(w.u0), t32(w.c)
+    lh, uh = net.interval_bounds(l0, u0)
+    plan = A.Plan(net, S, A.params_from_schedule(w.schedule))
+    lb = plan.solve(l0, u0, lh[:-1], uh[:-1], c)
+    gs = torch.ones(S, dtype=torch.float64, device=dev)
+    plan.bound_grad(gs)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    for _ in range(reps):
+        plan.bound_grad(gs)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    plan.profile(True)
+    plan.bound_grad(gs)
+    torch.cuda.synchronize()
+    prof = plan.profile_read()
+    plan.profile(False)
+    kernels = {f"{r}:{l}": round(1e3 * t / n, 2) for (r, l), (n, t) in prof.items()}
+    sizes = [w.layers[0].n_in] + [Lr.n_out for Lr in w.layers]
+    K = plan.counts().n_masks
+    wk = {key: v for key, v in prof.items() if key[0] == "grad_weight"}
+    (role, layer), (n_launch, tot_ms) = max(wk.items(), key=lambda kv: kv[1][1])
+    avg_s = tot_ms / 1e3 / n_launch
+    nw = int(np.prod(net.W[layer - 1].shape))
+    ab = adjoint_weight_bytes(layer, sizes, nw, K, S)
+    achieved = ab / avg_s / 1e9
+    return {"workload": f"{w.name}: the CIFAR Wide net, {S // 9} inputs x 9 logit differences, eps 2/255, "
+                        "root boxes, gradient at the duals of a full solve",
+            "subproblems": S, "masks": K, "ms": round(ms, 3), "rate": round(S / (ms / 1e3), 1),
+            "unit": "subproblem-gradients/s", "bound_mean": float(lb.mean().item()),
+            "kernels_avg_us": kernels,
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                         "kernel": f"weight gradient layer {layer}", "avg_launch_us": round(1e6 * avg_s, 2),
+                         "alg_bytes_per_launch": round(ab)}}
+
+
 def cpu_baseline(w, n_sub=2):
     """The FP64 oracle on a bounded sample: the first n_sub subdomains, full
     schedule; rate = Active Set subproblem-iterations per second."""
@@ -143,6 +206,7 @@ def main():
     ap.add_argument("--subproblems", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-profile", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the bound-gradient leg")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 3 device-to-device copies of MIB MiB (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
@@ -251,6 +315,11 @@ def main():
                         "alg_bytes_per_launch": round(tot_bytes / n_launch),
                         "hbm_bytes_per_launch": None if traffic is None else round(traffic)}
     whole_as_gbs = alg_as / (as_ms / args.steps / 1e3) / 1e9
+    adjoint = None
+    if not args.no_adjoint:
+        print("[bench] bound-gradient leg", file=sys.stderr, flush=True)
+        del plan
+        adjoint = adjoint_leg(A, np, torch, WL)
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
@@ -279,6 +348,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,
+        "adjoint": adjoint,
         "bound_mean": float(np.mean(lb_np)),
         "verified_fraction": float(np.mean(lb_np > 0)),
     }

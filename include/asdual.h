@@ -288,7 +288,10 @@ typedef enum {
     ASD_K_MASK = 2,       /* active-set extension */
     ASD_K_FINAL = 3,      /* FP64 final bound (all its kernels) */
     ASD_K_OTHER = 4,
-    ASD_K_COUNT = 5
+    ASD_K_GRAD_WEIGHT = 5, /* asd_bound_grad: weight gradients */
+    ASD_K_GRAD_BIAS = 6,   /* asd_bound_grad: bias gradients */
+    ASD_K_GRAD_BOX = 7,    /* asd_bound_grad: input-box gradients */
+    ASD_K_COUNT = 8
 } asd_kernel_role;
 
 typedef struct {

@@ -67,7 +67,8 @@ class KernelTime(C.Structure):
 
 
 ASD_K_BACKWARD, ASD_K_FORWARD, ASD_K_MASK, ASD_K_FINAL, ASD_K_OTHER = range(5)
-ROLE_NAMES = {0: "backward", 1: "forward", 2: "mask", 3: "final", 4: "other"}
+ROLE_NAMES = {0: "backward", 1: "forward", 2: "mask", 3: "final", 4: "other", 5: "grad_weight",
+              6: "grad_bias", 7: "grad_box"}
 
 
 class EvalOut(C.Structure):

@@ -911,7 +911,7 @@ asd_status bound_grad_t(asd_plan* P, const double* gs, double* const* dW, double
     if constexpr (sizeof(Ts) == 4)
         for (int k = 1; k < P->n; ++k) TRY(launch_final_sums(P, k, st));
     for (int k = P->n - 1; k >= 0; --k)
-        TRY((launch_backward<double, Ts>(P, k, 0, ASD_K_OTHER, st, k == 0 ? P->f0 : nullptr)));
+        TRY((launch_backward<double, Ts>(P, k, 0, ASD_K_FINAL, st, k == 0 ? P->f0 : nullptr)));
     auto base_args = [&](int k) {
         GradArgs<Ts> a;
         memset(&a, 0, sizeof(a));
@@ -935,14 +935,14 @@ asd_status bound_grad_t(asd_plan* P, const double* gs, double* const* dW, double
             a.out = dW[k - 1];
             const long entries = g.kind == ASD_LAYER_DENSE ? (long)g.out.C * g.fan
                                                            : (long)g.out.C * g.in.C * g.ksz * g.ksz;
-            ProfScope ps(P, st, ASD_K_OTHER, k);
+            ProfScope ps(P, st, ASD_K_GRAD_WEIGHT, k);
             hipLaunchKernelGGL(k_grad_weight<Ts>, dim3((unsigned)entries), dim3(kGradThreads), 0, st, a);
             LAUNCH_CHECK();
         }
         if (db && db[k - 1]) {
             GradArgs<Ts> a = base_args(k);
             a.out = db[k - 1];
-            ProfScope ps(P, st, ASD_K_OTHER, k);
+            ProfScope ps(P, st, ASD_K_GRAD_BIAS, k);
             hipLaunchKernelGGL(k_grad_bias<Ts>, dim3((unsigned)g.out.C), dim3(kGradThreads), 0, st, a);
             LAUNCH_CHECK();
         }
@@ -953,7 +953,7 @@ asd_status bound_grad_t(asd_plan* P, const double* gs, double* const* dW, double
         a.dl0 = dl0;
         a.du0 = du0;
         const long n = (long)P->nl[0].C * P->nl[0].cols;
-        ProfScope ps(P, st, ASD_K_OTHER, 0);
+        ProfScope ps(P, st, ASD_K_GRAD_BOX, 0);
         hipLaunchKernelGGL(k_grad_box<Ts>, dim3((unsigned)((n + kGradThreads - 1) / kGradThreads)),
                            dim3(kGradThreads), 0, st, a);
         LAUNCH_CHECK();

@@ -305,6 +305,26 @@ def cifar_conv_config(seed: int = 1002, S: int = 512, specs=None, max_fixed: int
                     meta={"seed": seed, "eps": eps, "true_class": t, "target": j})
 
 
+def adjoint_config(seed: int = 1004, n_inputs: int = 256, net_seed: int = 1002) -> Workload:
+    """Bound-gradient workload: the CIFAR "Wide" net of cifar_conv_config
+    (same weights), n_inputs centres U[0,1]^3072 with eps 2/255 clipped to
+    [0, 1], and for each input its 9 logit differences (true class from the
+    seed): S = 9 n_inputs root subproblems, input-major.  Pre-activation
+    bounds come from interval propagation per input (no fixed ReLUs)."""
+    layers = draw_layers(CIFAR_WIDE_SPECS, np.random.default_rng(net_seed))
+    rng = np.random.default_rng(seed)
+    centre = rng.uniform(0.0, 1.0, size=(n_inputs, 3 * 32 * 32))
+    eps = 2.0 / 255.0
+    l0, u0 = linf_box(centre, eps, (0.0, 1.0))
+    true = rng.integers(0, 10, size=n_inputs)
+    rows = [logit_difference_rows(10, int(t), [j for j in range(10) if j != t]) for t in true]
+    c = np.concatenate(rows, axis=0)
+    sched = Schedule(bigm_iters=180, as_iters=500, add_every=450, add_count=2, max_masks=7)
+    return Workload("cifar-wide-adjoint", layers, np.repeat(l0, 9, 0), np.repeat(u0, 9, 0), c, sched,
+                    meta={"seed": seed, "net_seed": net_seed, "eps": eps, "centre": centre.astype(np.float32),
+                          "true_class": true})
+
+
 def custom_config(specs: Sequence, S: int, seed: int, eps: float = 0.05,
                   centre_range=(0.0, 1.0), n_props: Optional[int] = None,
                   max_fixed: int = 0, schedule: Optional[Schedule] = None,

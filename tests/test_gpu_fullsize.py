@@ -216,3 +216,143 @@ def test_fullsize_bound_gradient_fp32(cifar):
         for s in SAMPLED:
             ref = gs[s] * ora[s][i]
             assert np.all(np.abs(g[s] - ref) <= 1e-9 * (1 + np.abs(ref))), (i, s)
+
+
+@pytest.fixture(scope="module")
+def adjoint_solved():
+    """The bound-gradient workload (CIFAR Wide net, 256 inputs x 9 logit
+    differences) solved with its full schedule in an FP32 plan; interval
+    bounds from the library, shared with the oracle."""
+    from paper_2101_05844_amd import asdual as A
+    A.lib()
+    w = WL.adjoint_config()
+    dev = "cuda"
+    t32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=dev)
+    net = A.Net(w.layers)
+    l0, u0, c = t32(w.l0), t32(w.u0), t32(w.c)
+    lh, uh = net.interval_bounds(l0, u0)
+    lh, uh = lh[:-1], uh[:-1]
+    plan = A.Plan(net, w.S, A.params_from_schedule(w.schedule))
+    lb = plan.solve(l0, u0, lh, uh, c)
+    torch.cuda.synchronize()
+    return A, w, net, plan, lb, [a.cpu().numpy() for a in lh], [a.cpu().numpy() for a in uh]
+
+
+def test_adjoint_supergradient_inequalities(adjoint_solved):
+    """At the converged duals each bound d_s is a minimum of functions affine
+    in the weights (masks and intermediate bounds fixed), hence concave, and
+    asd_bound_grad returns a supergradient: for steps h = 1e-3 (in FP32) on
+    sampled weights of every layer, d(W + h e) <= d(W) + h g_e on both sides,
+    for the sum over all subproblems (factors 1) and for single sampled
+    subproblems.  At converged duals many primal choices sit at near-ties,
+    so a step of 1e-3 often flips one and a central difference then lies
+    strictly between the one-sided slopes; the supergradient inequalities
+    are the form of the finite-difference check that holds regardless, and
+    the number of exact central differences is printed."""
+    A, w, net, plan, lb, _, _ = adjoint_solved
+    S = w.S
+    single = [5, 1000, 2303]
+    grads = {}
+    for key in ["all"] + single:
+        gs = torch.zeros(S, dtype=torch.float64, device="cuda")
+        if key == "all":
+            gs += 1.0
+        else:
+            gs[key] = 1.0
+        grads[key] = [t.view(-1).cpu().numpy() for t in plan.bound_grad(gs, box=False)[0]]
+    d0 = plan.bound().cpu().numpy()
+    tol_all = 1e-9 * (1.0 + np.abs(d0).sum())
+    rng = np.random.default_rng(41)
+    n_exact = n_all = 0
+    for k, Wt in enumerate(net.W):
+        flat = Wt.view(-1)
+        Wc = flat.cpu().numpy()
+        g = grads["all"][k]
+        cand = np.flatnonzero(np.abs(Wc) > 4e-3)
+        picks = list(rng.choice(cand, size=4, replace=False)) + list(cand[np.argsort(-np.abs(g[cand]))[:2]])
+        for e in picks:
+            w0 = np.float32(Wc[e])
+            dv, steps = [], []
+            for sgn in (1.0, -1.0):
+                wp = np.float32(w0 + np.float32(sgn * 1e-3))
+                flat[e] = float(wp)
+                dv.append(plan.bound().cpu().numpy())
+                flat[e] = float(w0)
+                steps.append(float(wp) - float(w0))
+            for dp, step in zip(dv, steps):
+                assert dp.sum() <= d0.sum() + step * g[e] + tol_all, (k, e, step, dp.sum() - d0.sum(), step * g[e])
+                for s in single:
+                    gse = grads[s][k][e]
+                    assert dp[s] <= d0[s] + step * gse + 1e-9 * (1 + abs(d0[s])), (k, e, s, step)
+            for s in single:
+                gse = grads[s][k][e]
+                fd = (dv[0][s] - dv[1][s]) / (steps[0] - steps[1])
+                n_all += 1
+                n_exact += abs(fd - gse) <= 1e-6 * (1 + abs(gse))
+    assert np.array_equal(plan.bound().cpu().numpy(), d0)
+    print(f"central differences equal to the gradient: {n_exact} of {n_all}", flush=True)
+
+
+def test_adjoint_sampled_oracle(adjoint_solved):
+    """Sampled subproblems of the bound-gradient workload at the converged
+    duals: the GPU's gradient with factors on those subproblems only matches
+    the oracle's Danskin gradient at the same duals and masks (exported from
+    the plan), wherever the oracle's minimiser is unique by a clear margin."""
+    A, w, net, plan, lb, LH, UH = adjoint_solved
+    ops = O.ops_from_workload_layers(w.layers)
+    K = plan.counts().n_masks
+    n = len(ops)
+    samples = [5, 1000, 2303]
+    fields = {}
+    for k in range(1, n):
+        for name, f in (("alpha", A.ASD_F_ALPHA), ("beta0", A.ASD_F_BETA0), ("beta1", A.ASD_F_BETA1)):
+            fields[(name, k)] = plan.get(f, k).cpu().numpy()
+        for q in range(K):
+            fields[("beta", k, q)] = plan.get(A.ASD_F_MASK_BETA, k, q).cpu().numpy()
+            fields[("z", k, q)] = plan.get(A.ASD_F_MASK_Z, k, q).cpu().numpy()
+            fields[("x", k, q)] = plan.get(A.ASD_F_MASK_XPREV, k, q).cpu().numpy()
+    gs = np.zeros(w.S)
+    used = []
+    ora = {}
+    for s, v in zip(samples, (1.0, -0.75, 1.5)):
+        p = O.make_problem(ops, w.l0[s], w.u0[s], [a[s] for a in LH], [a[s] for a in UH], w.c[s])
+        st = O.zero_state(p)
+        for k in range(1, n):
+            st.alpha[k - 1] = fields[("alpha", k)][s].astype(np.float64)
+            st.beta0[k - 1] = fields[("beta0", k)][s].astype(np.float64)
+            st.beta1[k - 1] = fields[("beta1", k)][s].astype(np.float64)
+            lp_, up_ = p.lu(k - 1)
+            for q in range(K):
+                xp = fields[("x", k, q)][s].astype(np.float64)
+                zz = fields[("z", k, q)][s].astype(np.float64)
+                M = O.new_mask(p.W(k), O.oracle_mask(p.W(k), lp_, up_, xp, zz), lp_, up_, xp, zz)
+                M.beta = fields[("beta", k, q)][s].astype(np.float64)
+                st.masks[k - 1].append(M)
+        f, g, _ = O.dual_functions(p, st)
+        # x choices matter where the box is not a point; an exact zero is
+        # a sum of zero terms on both sides and takes the same tie rule
+        def rel_margin(v, keep):
+            a = np.abs(v[keep & (v != 0)])
+            return a.min(initial=np.inf) / (1 + np.abs(v).max())
+        margin = min(rel_margin(fk, p.lu(k)[1] > p.lu(k)[0]) for k, fk in enumerate(f))
+        margin = min(margin, min(rel_margin(gk, np.ones(gk.shape, bool)) for gk in g))
+        print(f"subproblem {s}: smallest relative margin of the minimiser {margin:.3e}", flush=True)
+        if margin <= 1e-11:
+            continue
+        gs[s] = v
+        used.append(s)
+        ora[s] = O.bound_gradient(p, st)
+    assert used, "every sampled subproblem has a near-tie in its minimiser"
+    dW, db, dl0, du0 = plan.bound_grad(torch.as_tensor(gs))
+    torch.cuda.synchronize()
+    for k in range(n):
+        for i, got in ((0, dW[k]), (1, db[k])):
+            ref = sum(gs[s] * ora[s][i][k] for s in used)
+            mag = sum(abs(gs[s]) * np.abs(ora[s][i][k]) for s in used)
+            gg = got.cpu().numpy().reshape(-1)
+            assert np.all(np.abs(gg - ref) <= 1e-9 * (1 + mag)), (i, k)
+    for i, got in ((2, dl0), (3, du0)):
+        gg = got.cpu().numpy()
+        for s in used:
+            ref = gs[s] * ora[s][i]
+            assert np.all(np.abs(gg[s] - ref) <= 1e-9 * (1 + np.abs(ref))), (i, s)

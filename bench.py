@@ -166,6 +166,51 @@ def adjoint_leg(A, np, torch, WL, reps=3):
                          "alg_bytes_per_launch": round(ab)}}
 
 
+def ragged_leg(A, np, torch, WL):
+    """Ragged batch: 2048 subdomains on the Wide net and 2048 on its wider
+    variant, 0-50 fixed ReLUs and an Active Set budget U{100..1000} each,
+    solved together (asd_solve_group: one stream per net, per-subproblem
+    budgets), timed by HIP events; then the same plans one after the other
+    on one stream for comparison."""
+    ws = WL.ragged_config()
+    dev = "cuda:0"
+    t32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=dev)
+    plans, batches, iters = [], [], 0
+    for w in ws:
+        net = A.Net(w.layers, device=dev)
+        lh0, uh0 = net.interval_bounds(t32(w.l0[:1]), t32(w.u0[:1]))
+        L, U = WL.subdomain_bounds([a[0].cpu().numpy() for a in lh0[:-1]], [a[0].cpu().numpy() for a in uh0[:-1]],
+                                   w.fix_draws, w.S)
+        plan = A.Plan(net, w.S, A.params_from_schedule(w.schedule))
+        plan.set_budgets(w.meta["budgets"])
+        plans.append(plan)
+        batches.append((t32(w.l0), t32(w.u0), [t32(a) for a in L], [t32(a) for a in U], t32(w.c)))
+        iters += sum(w.meta["budgets"])
+    stream = torch.cuda.current_stream()
+    A.solve_group(plans, batches)            # warm-up
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record(stream)
+    outs = A.solve_group(plans, batches)
+    ev[1].record(stream)
+    for P, b in zip(plans, batches):
+        P.solve(*b)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    ms_group = ev[0].elapsed_time(ev[1])
+    ms_seq = ev[1].elapsed_time(ev[2])
+    bm = sum(w.S * w.schedule.bigm_iters for w in ws)
+    lbs = [o.cpu().numpy() for o in outs]
+    return {"workload": "4096 subdomains: 2048 on the Table 1 Wide CIFAR net and 2048 on its wider variant "
+                        "(conv 3->32, 32->64, FC 4096->512->10), 0-50 fixed ReLUs and an Active Set budget "
+                        "U{100..1000} each, 180 Big-M iterations",
+            "subproblems": sum(w.S for w in ws), "as_iterations": iters, "bigm_iterations": bm,
+            "ms": round(ms_group, 3), "ms_one_stream": round(ms_seq, 3),
+            "rate": round((iters + bm) / (ms_group / 1e3), 1), "unit": "subproblem-iterations/s (whole solve)",
+            "bound_mean": [float(np.mean(l)) for l in lbs],
+            "verified": [int(np.sum(l > 0)) for l in lbs]}
+
+
 def cpu_baseline(w, n_sub=2):
     """The FP64 oracle on a bounded sample: the first n_sub subdomains, full
     schedule; rate = Active Set subproblem-iterations per second."""
@@ -207,6 +252,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-profile", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the bound-gradient leg")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the BF16-moment form")
+    ap.add_argument("--no-ragged", action="store_true", help="skip the ragged two-net batch")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 3 device-to-device copies of MIB MiB (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
@@ -315,10 +362,45 @@ def main():
                         "alg_bytes_per_launch": round(tot_bytes / n_launch),
                         "hbm_bytes_per_launch": None if traffic is None else round(traffic)}
     whole_as_gbs = alg_as / (as_ms / args.steps / 1e3) / 1e9
+    mixed = None
+    if not args.no_mixed:
+        # the same solves with Adam moments stored in BF16 (ASD_PREC_MIXED):
+        # rate, and bound accuracy against the FP32 form on every subdomain
+        print("[bench] mixed-precision form", file=sys.stderr, flush=True)
+        del plan
+        prm_mixed = A.params_from_schedule(sched, A.ASD_PREC_MIXED)
+        plan = A.Plan(net, S, prm_mixed)
+        for _ in range(args.warmup):
+            lb_m = step()
+        torch.cuda.synchronize()
+        evm = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+        for i in range(args.steps):
+            lb_m = step(evm[i])
+        torch.cuda.synchronize()
+        as_m = sum(e[1].elapsed_time(e[2]) for e in evm)
+        lbm = lb_m.cpu().numpy()
+        diff = lb_np - lbm
+        scale = float(np.mean(np.abs(lb_np)))
+        mixed = {"value": round(S * sched.as_iters * args.steps / (as_m / 1e3), 1),
+                 "unit": "subproblem-iterations/s", "as_phase_ms": round(as_m / args.steps, 3),
+                 "speedup_vs_fp32": round(as_ms / as_m, 4),
+                 "bound_mean": float(np.mean(lbm)),
+                 "mean_fp32_minus_mixed": float(np.mean(diff)),
+                 "max_abs_diff": float(np.max(np.abs(diff))),
+                 "accuracy_scale": scale,
+                 "equal_accuracy": bool(np.mean(diff) <= 1e-4 * scale
+                                        and int(np.sum(lbm > 0)) >= int(np.sum(lb_np > 0))),
+                 "verified": [int(np.sum(lb_np > 0)), int(np.sum(lbm > 0))],
+                 "dtype": "f32 duals and arithmetic, bf16 Adam moments, f64 final bound"}
+    ragged = None
+    if not args.no_ragged:
+        print("[bench] ragged two-net batch", file=sys.stderr, flush=True)
+        plan = None
+        ragged = ragged_leg(A, np, torch, WL)
     adjoint = None
     if not args.no_adjoint:
         print("[bench] bound-gradient leg", file=sys.stderr, flush=True)
-        del plan
+        plan = None
         adjoint = adjoint_leg(A, np, torch, WL)
     cpu = None
     if not args.no_cpu_baseline:
@@ -348,6 +430,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,
+        "mixed": mixed,
+        "ragged": ragged,
         "adjoint": adjoint,
         "bound_mean": float(np.mean(lb_np)),
         "verified_fraction": float(np.mean(lb_np > 0)),

@@ -90,8 +90,15 @@ typedef enum { ASD_RULE_ADAM = 0, ASD_RULE_SUPERGRADIENT = 1 } asd_rule;
  * production form (FP32 duals, moments and sums; the final bound is
  * re-evaluated in FP64).  ASD_PREC_FP64 keeps everything in FP64 (twice the
  * memory and traffic); it exists to compare whole runs with an FP64
- * reference.  Network weights and batch inputs are FP32 in both. */
-typedef enum { ASD_PREC_FP32 = 0, ASD_PREC_FP64 = 1 } asd_precision;
+ * reference.  ASD_PREC_MIXED is ASD_PREC_FP32 with the Adam moments stored
+ * in BF16 between iterations (round to nearest even; each update is computed
+ * in FP32 from the stored value and steps with the unrounded result): a
+ * third less state traffic per multiplier.  The duals, the products and the
+ * FP64 final bound are those of ASD_PREC_FP32, so the bound stays valid;
+ * only the trajectory of the ascent changes.  The state calls exchange the
+ * moments as float in every FP32-duals mode.  Network weights and batch
+ * inputs are FP32 in all modes. */
+typedef enum { ASD_PREC_FP32 = 0, ASD_PREC_FP64 = 1, ASD_PREC_MIXED = 2 } asd_precision;
 
 /* Solver schedule (Sec. 7.1; readings: additions at Active Set iterations t
  * with t mod add_every < add_count while fewer than max_masks masks are
@@ -169,10 +176,38 @@ asd_status asd_run(asd_plan* plan, int32_t phase /* asd_phase */, int32_t t_begi
  * (Sec. 6.2 footnote). */
 asd_status asd_bound(asd_plan* plan, double* out_lb, float* x0, hipStream_t stream);
 
-/* Whole solve: asd_init, T_M Big-M iterations, T Active Set iterations,
- * asd_bound.  out_lb [S] device doubles. */
+/* Per-subproblem Active Set budgets (ragged batches of branch-and-bound
+ * subdomains, each with its own iteration budget): budgets [S] (host),
+ * each >= 1 and non-increasing in s (order the batch by budget).  Subproblem
+ * s then runs Active Set iterations 0 .. budgets[s]-1 with its own linear
+ * learning-rate schedule over budgets[s] (as a plan with T = budgets[s]
+ * would), and its duals stay fixed afterwards; mask additions follow the
+ * shared iteration count.  Iterations only touch the subproblems still
+ * within budget (a prefix of the batch), so the work shrinks as budgets
+ * run out.  The Active Set phase then has T = budgets[0] iterations.  NULL
+ * clears the budgets.  Synchronises `stream` (the budgets are copied to the
+ * plan's workspace).  Errors: ASD_EINVAL for a NULL plan or budgets that
+ * are < 1 or increasing. */
+asd_status asd_set_budgets(asd_plan* plan, const int32_t* budgets /* host */, hipStream_t stream);
+
+/* Whole solve: asd_init, T_M Big-M iterations, T Active Set iterations
+ * (T = budgets[0] with per-subproblem budgets), asd_bound.  out_lb [S]
+ * device doubles. */
 asd_status asd_solve(asd_plan* plan, const asd_batch* batch, double* out_lb, float* x0,
                      hipStream_t stream);
+
+/* Solves several plans (for instance one per network of a mixed batch of
+ * branch-and-bound subdomains, each plan with its own budgets) together:
+ * asd_init of batches[i] into plans[i], then the Big-M and Active Set
+ * iterations of all plans interleaved one iteration at a time, plan i's
+ * kernels on streams[i] (host array of n_plans streams; distinct streams let
+ * the plans' kernels overlap), then asd_bound into out_lb[i] (device [S_i]).
+ * Each plan's result is the result of asd_solve on it alone.  Returns once
+ * every launch is queued.  Errors: ASD_EINVAL for NULL entries, a repeated
+ * plan, or any error of the calls above (launches already queued stay
+ * queued). */
+asd_status asd_solve_group(asd_plan* const* plans /* host */, const asd_batch* const* batches /* host */,
+                           double* const* out_lb /* host */, int32_t n_plans, const hipStream_t* streams /* host */);
 
 /* ---- Inspection and warm start (duals are the whole solver state) ---- */
 

@@ -454,6 +454,24 @@ class AdamConsts:
     beta1: float = 0.9
     beta2: float = 0.999
     eps: float = 1e-8
+    # "exact": moments kept at full precision; "bf16": moments stored between
+    # steps as bfloat16 (each step uses the unrounded update, then stores it
+    # rounded); a storage choice of the implementation, not of the paper
+    moments: str = "exact"
+
+
+def round_bf16(a):
+    """Nearest bfloat16 value (8 significant bits, float32's exponent range,
+    ties to even) of each entry, returned as float64.  Written from the
+    format's definition: the spacing of representable values in [2^e, 2^(e+1))
+    is 2^(e-7), with e clamped at float32's smallest normal exponent -126."""
+    a = np.asarray(a, dtype=np.float64)
+    out = np.zeros_like(a)
+    nz = a != 0
+    _, e = np.frexp(a[nz])                  # a = f 2^e with 0.5 <= |f| < 1
+    q = np.ldexp(1.0, np.maximum(e - 1, -126) - 7)
+    out[nz] = np.rint(a[nz] / q) * q        # rint rounds halves to even
+    return out
 
 
 def adam_ascent(theta, m, v, grad, step, lr, c: AdamConsts):
@@ -461,12 +479,16 @@ def adam_ascent(theta, m, v, grad, step, lr, c: AdamConsts):
 
     m <- b1 m + (1-b1) g;  v <- b2 v + (1-b2) g^2;
     theta <- max(0, theta + lr * (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps)).
+    With c.moments == "bf16" the returned (stored) moments are rounded to
+    bfloat16.
     """
     m = c.beta1 * m + (1.0 - c.beta1) * grad
     v = c.beta2 * v + (1.0 - c.beta2) * grad * grad
     mhat = m / (1.0 - c.beta1 ** step)
     vhat = v / (1.0 - c.beta2 ** step)
     theta = np.maximum(theta + lr * mhat / (np.sqrt(vhat) + c.eps), 0.0)
+    if c.moments == "bf16":
+        m, v = round_bf16(m), round_bf16(v)
     return theta, m, v
 
 

@@ -22,7 +22,7 @@ ASD_MAX_LAYERS = 16
 ASD_MAX_MASKS = 8
 ASD_LAYER_DENSE, ASD_LAYER_CONV2D = 0, 1
 ASD_RULE_ADAM, ASD_RULE_SUPERGRADIENT = 0, 1
-ASD_PREC_FP32, ASD_PREC_FP64 = 0, 1
+ASD_PREC_FP32, ASD_PREC_FP64, ASD_PREC_MIXED = 0, 1, 2
 ASD_PHASE_BIGM, ASD_PHASE_AS = 0, 1
 (ASD_F_ALPHA, ASD_F_BETA0, ASD_F_BETA1, ASD_F_ALPHA_M, ASD_F_ALPHA_V, ASD_F_BETA0_M, ASD_F_BETA0_V,
  ASD_F_BETA1_M, ASD_F_BETA1_V, ASD_F_MASK_BETA, ASD_F_MASK_M, ASD_F_MASK_V, ASD_F_MASK_LI,
@@ -86,7 +86,7 @@ _lib = None
 EXPORTED = ["asd_net_create", "asd_net_destroy", "asd_params_default", "asd_plan_workspace_size",
             "asd_plan_create", "asd_plan_destroy", "asd_init", "asd_run", "asd_bound", "asd_solve",
             "asd_state_get", "asd_state_set", "asd_state_get_counts", "asd_state_set_counts",
-            "asd_eval", "asd_oracle", "asd_bound_grad", "asd_interval_bounds", "asd_profile_enable", "asd_profile_read",
+            "asd_eval", "asd_oracle", "asd_bound_grad", "asd_set_budgets", "asd_solve_group", "asd_interval_bounds", "asd_profile_enable", "asd_profile_read",
             "asd_last_error", "asd_abi_version"]
 
 
@@ -120,6 +120,8 @@ def lib():
     L.asd_eval.argtypes = [vp, C.POINTER(EvalOut), vp]
     L.asd_oracle.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
     L.asd_bound_grad.argtypes = [vp, vp, C.POINTER(vp), C.POINTER(vp), vp, vp, vp]
+    L.asd_set_budgets.argtypes = [vp, C.POINTER(i32), vp]
+    L.asd_solve_group.argtypes = [C.POINTER(vp), C.POINTER(C.POINTER(Batch)), C.POINTER(vp), i32, C.POINTER(vp)]
     L.asd_interval_bounds.argtypes = [vp, i32, vp, vp, C.POINTER(vp), C.POINTER(vp), vp]
     L.asd_profile_enable.argtypes = [vp, i32]
     L.asd_profile_read.argtypes = [vp, C.POINTER(KernelTime), i32, C.POINTER(i32)]
@@ -257,10 +259,24 @@ class Plan:
         _check(lib().asd_bound(self.handle, out.data_ptr(), _ptr(x0), _stream(stream)))
         return (out, x0) if want_x0 else out
 
+    def set_budgets(self, budgets: Optional[Sequence[int]], stream=None):
+        """asd_set_budgets: per-subproblem Active Set budgets (non-increasing), or None."""
+        if budgets is None:
+            _check(lib().asd_set_budgets(self.handle, None, _stream(stream)))
+            self.budgets = None
+            return
+        arr = (C.c_int32 * self.S)(*[int(b) for b in budgets])
+        _check(lib().asd_set_budgets(self.handle, arr, _stream(stream)))
+        self.budgets = [int(b) for b in budgets]
+
+    def as_iters(self) -> int:
+        b = getattr(self, "budgets", None)
+        return b[0] if b else self.params.as_iters
+
     def solve(self, l0, u0, lhat, uhat, c, want_x0: bool = False, stream=None):
         self.init(l0, u0, lhat, uhat, c, stream)
         self.run(ASD_PHASE_BIGM, 0, self.params.bigm_iters, stream)
-        self.run(ASD_PHASE_AS, 0, self.params.as_iters, stream)
+        self.run(ASD_PHASE_AS, 0, self.as_iters(), stream)
         return self.bound(want_x0, stream)
 
     # -- state ---------------------------------------------------------------
@@ -376,6 +392,36 @@ def unpack_bits(bits: np.ndarray, fan: int) -> np.ndarray:
     shifts = np.arange(32, dtype=np.uint32)
     out = ((b[..., :, None] >> shifts) & 1).astype(bool)
     return out.reshape(*b.shape[:-1], -1)[..., :fan]
+
+
+def solve_group(plans: Sequence["Plan"], batches, streams=None):
+    """asd_solve_group: batches[i] = (l0, u0, lhat, uhat, c) for plans[i];
+    each plan on its own stream (new streams at default priority unless
+    given).  Returns the bounds [S_i] per plan (float64 tensors)."""
+    n = len(plans)
+    if streams is None:
+        streams = [torch.cuda.Stream() for _ in range(n)]
+    cur = torch.cuda.current_stream()
+    for s_ in streams:
+        s_.wait_stream(cur)
+    keep, bs = [], []
+    for P, (l0, u0, lhat, uhat, c) in zip(plans, batches):
+        lh = (C.c_void_p * max(1, len(lhat)))(*[_ptr(t) for t in lhat])
+        uh = (C.c_void_p * max(1, len(uhat)))(*[_ptr(t) for t in uhat])
+        b = Batch(P.S, _ptr(l0), _ptr(u0), C.cast(lh, C.POINTER(C.c_void_p)), C.cast(uh, C.POINTER(C.c_void_p)),
+                  _ptr(c))
+        keep.append((lh, uh, l0, u0, lhat, uhat, c))
+        P._keep = (l0, u0, list(lhat), list(uhat), c)
+        bs.append(b)
+    outs = [torch.empty(P.S, dtype=torch.float64, device="cuda") for P in plans]
+    parr = (C.c_void_p * n)(*[P.handle.value for P in plans])
+    barr = (C.POINTER(Batch) * n)(*[C.pointer(b) for b in bs])
+    oarr = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+    sarr = (C.c_void_p * n)(*[s_.cuda_stream for s_ in streams])
+    _check(lib().asd_solve_group(parr, barr, oarr, n, sarr))
+    for s_ in streams:
+        cur.wait_stream(s_)
+    return outs
 
 
 class BoundFunction(torch.autograd.Function):

@@ -105,6 +105,20 @@ struct asd_plan {
     int* pointflag;                   // [kMaxLayers]: point box away from zero in layer k
     void* Rdev;                       // device copy of the ReluLayerT array (update kernels)
     double* f0;                       // f_0 of the last bound-gradient evaluation
+    // bound gradient: chunks of the two-stage reductions per layer and the
+    // partial sums they write
+    int gw_chunks[kMaxLayers + 1];
+    long gw_rchunk[kMaxLayers + 1];
+    int gb_chunks[kMaxLayers + 1];
+    long gb_rchunk[kMaxLayers + 1];
+    size_t gpart_w, gpart_b;          // doubles
+    double* gpart;
+    // per-subproblem Active Set budgets (non-increasing in s), or none
+    bool ragged;
+    std::vector<int> budgets;
+    int* budgets_dev;                 // [S]
+    void* lrs;                        // [S] learning rates of the current iteration (T)
+    int Sa;                           // subproblems the current iteration updates (a prefix)
     // scalar state
     int n_masks;
     int step;
@@ -243,6 +257,9 @@ void carve_t(asd_plan* P, Carver& cv) {
     P->part = cv.take<T>(part);
     P->pointflag = cv.take<int>(kMaxLayers);
     P->f0 = cv.take<double>((size_t)P->nl[0].N * S);
+    P->gpart = cv.take<double>(P->gpart_w + P->gpart_b);
+    P->budgets_dev = cv.take<int>(S);
+    P->lrs = cv.take<T>(S);
     P->Rdev = cv.take<ReluLayerT<T>>(kMaxLayers);
 }
 
@@ -259,7 +276,7 @@ asd_status check_params(const asd_params* p) {
     if (p->max_masks < 0 || p->max_masks > ASD_MAX_MASKS)
         return fail(ASD_EINVAL, "max_masks must be in [0, %d]", ASD_MAX_MASKS);
     if (p->rule != ASD_RULE_ADAM && p->rule != ASD_RULE_SUPERGRADIENT) return fail(ASD_EINVAL, "unknown rule");
-    if (p->precision != ASD_PREC_FP32 && p->precision != ASD_PREC_FP64)
+    if (p->precision != ASD_PREC_FP32 && p->precision != ASD_PREC_FP64 && p->precision != ASD_PREC_MIXED)
         return fail(ASD_EINVAL, "unknown precision %d", p->precision);
     if (!(p->adam_beta1 >= 0.0 && p->adam_beta1 < 1.0 && p->adam_beta2 >= 0.0 && p->adam_beta2 < 1.0))
         return fail(ASD_EINVAL, "Adam betas must be in [0, 1)");
@@ -270,6 +287,7 @@ asd_status check_params(const asd_params* p) {
 void setup_plan_geometry(asd_plan* P) {
     const asd_net* net = P->net;
     const int S = P->S;
+    P->gpart_w = P->gpart_b = 0;
     const asd_layer_desc& d0 = net->L[0];
     P->nl[0] = make_layout(d0.in_c, d0.kind == ASD_LAYER_DENSE ? 1 : d0.in_h,
                            d0.kind == ASD_LAYER_DENSE ? 1 : d0.in_w, S);
@@ -300,6 +318,27 @@ void setup_plan_geometry(asd_plan* P) {
             P->nkp[L] = (g.out.C * J * J + 3) / 4 * 4;
         }
         P->fanpad[L] = (g.in.C + 7) / 8 * 8 * g.in.P;
+        {
+            // bound gradient: about 2048 blocks for the weights and 1024 for
+            // the biases, at most 64 chunks, at least 16 subproblems (dense)
+            // or 2048 terms (convolution, biases) per chunk
+            auto split = [](long groups, long terms, long want_blocks, long min_terms, int* chunks, long* rchunk) {
+                long c = (want_blocks + groups - 1) / groups;
+                c = std::max(1L, std::min(c, std::min(64L, std::max(1L, terms / min_terms))));
+                *rchunk = (terms + c - 1) / c;
+                *chunks = (int)((terms + *rchunk - 1) / *rchunk);
+            };
+            const long entries = (long)g.out.C * g.fan;
+            if (d.kind == ASD_LAYER_DENSE)
+                split((long)((g.fan + kGradThreads - 1) / kGradThreads) * ((g.out.C + kGdTO - 1) / kGdTO), S, 2048,
+                      16, &P->gw_chunks[L], &P->gw_rchunk[L]);
+            else
+                split((long)((g.out.C + kGcTO - 1) / kGcTO) * ((g.fan + kGcTT - 1) / kGcTT), (long)S * g.out.P, 2048,
+                      2048, &P->gw_chunks[L], &P->gw_rchunk[L]);
+            split(g.out.C, (long)S * g.out.P, 1024, 2048, &P->gb_chunks[L], &P->gb_rchunk[L]);
+            P->gpart_w = std::max(P->gpart_w, (size_t)P->gw_chunks[L] * entries);
+            P->gpart_b = std::max(P->gpart_b, (size_t)P->gb_chunks[L] * g.out.C);
+        }
         P->ksplit[L] = 1;
         if (d.kind == ASD_LAYER_DENSE) {
             // about two waves per SIMD (2048 waves of KS per 32 x 32 tile), at
@@ -313,7 +352,17 @@ void setup_plan_geometry(asd_plan* P) {
 }
 
 inline dim3 grid_cols(const NeuronLayout& nl, int chan_per_block) {
-    return dim3((unsigned)(nl.colpad / 64), (unsigned)((nl.C + chan_per_block - 1) / chan_per_block));
+    return dim3((unsigned)((nl.cols + 63) / 64), (unsigned)((nl.C + chan_per_block - 1) / chan_per_block));
+}
+
+// Geometry of layer L restricted to the subproblems the current iteration
+// updates (s < Sa): column counts cover that prefix; strides, bit strides and
+// arrays are unchanged.
+LayerGeo gview(const asd_plan* P, int L) {
+    LayerGeo g = P->geo[L];
+    g.in.cols = (long)P->Sa * g.in.P;
+    g.out.cols = (long)P->Sa * g.out.P;
+    return g;
 }
 
 asd_status zero_words(void* p, long n, hipStream_t st) {
@@ -465,8 +514,9 @@ template <typename T, int NM>
 asd_status fwd_fast_nm(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t st) {
     FastFwdArgs<T> a;
     memset(&a, 0, sizeof(a));
-    a.g = P->geo[k];
+    a.g = gview(P, k);
     a.S = P->S;
+    a.Sa = P->Sa;
     a.nm = NM;
     a.Cpad = P->Cpad[k];
     a.ksplit = P->ksplit[k];
@@ -484,7 +534,7 @@ asd_status fwd_fast_nm(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t s
     if (g.kind == ASD_LAYER_CONV2D && g.out.C < 32) {
         // narrow layer: a 32-row matrix tile would be half empty, and the
         // update's memory traffic bounds it anyway
-        dim3 grid((unsigned)(g.out.colpad / kWave), (unsigned)((g.out.C + CB - 1) / CB));
+        dim3 grid((unsigned)((g.out.cols + kWave - 1) / kWave), (unsigned)((g.out.C + CB - 1) / CB));
         if (g.ksz == 4)
             hipLaunchKernelGGL((k_fwd_conv<T, NM, CB, 4>), grid, dim3(kWave, KS), 0, st, a);
         else
@@ -502,10 +552,10 @@ asd_status fwd_fast_nm(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t s
         LAUNCH_CHECK();
         return ASD_OK;
     }
-    dim3 grid((unsigned)((P->S + 31) / 32), (unsigned)(a.Cpad / 32), (unsigned)a.ksplit);
+    dim3 grid((unsigned)((P->Sa + 31) / 32), (unsigned)(a.Cpad / 32), (unsigned)a.ksplit);
     hipLaunchKernelGGL((k_fwd_dense_mfma<NM>), grid, dim3(kWave, KS), 0, st, a);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_fwd_dense_epi<T, NM>), dim3((unsigned)((P->S + 255) / 256), (unsigned)g.out.C), dim3(256),
+    hipLaunchKernelGGL((k_fwd_dense_epi<T, NM>), dim3((unsigned)((P->Sa + 255) / 256), (unsigned)g.out.C), dim3(256),
                        0, st, a);
     LAUNCH_CHECK();
     return ASD_OK;
@@ -526,7 +576,7 @@ template <typename T, int NM>
 asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
     FastBwdArgs<T> a;
     memset(&a, 0, sizeof(a));
-    a.gn = P->geo[k + 1];
+    a.gn = gview(P, k + 1);
     a.S = P->S;
     a.k = k;
     a.last = (k + 1 == P->n);
@@ -580,7 +630,7 @@ asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
             sh.CC = (int)std::min<size_t>((size_t)g.out.C, budget / per_ch);
             const size_t dyn = std::max(fbytes, (size_t)sh.CC * per_ch);
             ProfScope ps(P, st, ASD_K_BACKWARD, k);
-            dim3 grid((unsigned)P->S, (unsigned)((L.C + 15) / 16));
+            dim3 grid((unsigned)P->Sa, (unsigned)((L.C + 15) / 16));
             if (g.ksz == 4 && g.stride == 2)
                 hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 4, 2>), grid, dim3(kWave, sh.NW), dyn, st, a, sh);
             else
@@ -597,7 +647,7 @@ asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
         const size_t stat = (size_t)ksp * CB * kWave * sizeof(T);
         if (dyn + stat > 64 * 1024) return launch_backward<T, T>(P, k, 0, ASD_K_BACKWARD, st);
         ProfScope ps(P, st, ASD_K_BACKWARD, k);
-        dim3 grid((unsigned)(L.colpad / kWave), (unsigned)((L.C + CB - 1) / CB));
+        dim3 grid((unsigned)((L.cols + kWave - 1) / kWave), (unsigned)((L.C + CB - 1) / CB));
         const bool k4s2 = g.ksz == 4 && g.stride == 2;
         if constexpr (sizeof(T) == 4) {
             if (CB == 8) {
@@ -619,11 +669,11 @@ asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
     ProfScope ps(P, st, ASD_K_BACKWARD, k);
     constexpr int SB = sizeof(T) == 4 ? 8 : 4;
     if (L.P % kWave == 0 && P->S >= SB) {
-        dim3 grid((unsigned)(L.C * (L.P / kWave)), (unsigned)((P->S + SB - 1) / SB));
+        dim3 grid((unsigned)(L.C * (L.P / kWave)), (unsigned)((P->Sa + SB - 1) / SB));
         hipLaunchKernelGGL((k_bwd_dense_pos<T, NM, SB>), grid, dim3(kWave, KS), 0, st, a);
     } else {
         constexpr int CB = sizeof(T) == 4 ? 8 : 4;
-        dim3 grid((unsigned)(L.colpad / kWave), (unsigned)((L.C + CB - 1) / CB));
+        dim3 grid((unsigned)((L.cols + kWave - 1) / kWave), (unsigned)((L.C + CB - 1) / CB));
         if (L.P == 1)
             hipLaunchKernelGGL((k_bwd_dense<T, NM, CB, true>), grid, dim3(kWave, KS), 0, st, a);
         else
@@ -646,7 +696,7 @@ template <typename Tc, typename Ts>
 asd_status launch_backward(asd_plan* P, int k, int want_obj, int role, hipStream_t st, double* fout) {
     BwdArgs<Ts> a;
     memset(&a, 0, sizeof(a));
-    a.gn = P->geo[k + 1];
+    a.gn = gview(P, k + 1);
     a.S = P->S;
     a.k = k;
     a.last = (k + 1 == P->n);
@@ -663,7 +713,7 @@ asd_status launch_backward(asd_plan* P, int k, int want_obj, int role, hipStream
     a.fout = fout;
     const size_t lds = (size_t)KS * CB * kWave * sizeof(Tc);
     ProfScope ps(P, st, role, k);
-    hipLaunchKernelGGL((k_backward<Tc, Ts>), grid_cols(P->nl[k], CB), dim3(kWave, KS), lds, st, a);
+    hipLaunchKernelGGL((k_backward<Tc, Ts>), grid_cols(a.gn.in, CB), dim3(kWave, KS), lds, st, a);
     LAUNCH_CHECK();
     return ASD_OK;
 }
@@ -673,7 +723,7 @@ asd_status launch_forward(asd_plan* P, int k, const StepArgsT<T>& sa, int mode, 
                           hipStream_t st) {
     FwdArgs<T> a;
     memset(&a, 0, sizeof(a));
-    a.g = P->geo[k];
+    a.g = gview(P, k);
     a.S = P->S;
     a.nm = P->n_masks;
     a.xin = NA<T>(P)[k - 1].xstar;
@@ -687,7 +737,7 @@ asd_status launch_forward(asd_plan* P, int k, const StepArgsT<T>& sa, int mode, 
         for (int i = 0; i < 3 + kMaxMasks; ++i) a.gout[i] = reinterpret_cast<T*>(gout[i]);
     const size_t lds = (size_t)KS * CB * (1 + a.nm) * kWave * sizeof(T);
     ProfScope ps(P, st, mode == 0 ? ASD_K_FORWARD : ASD_K_OTHER, k);
-    hipLaunchKernelGGL(k_forward<T>, grid_cols(P->nl[k], CB), dim3(kWave, KS), lds, st, a);
+    hipLaunchKernelGGL(k_forward<T>, grid_cols(a.g.out, CB), dim3(kWave, KS), lds, st, a);
     LAUNCH_CHECK();
     return ASD_OK;
 }
@@ -776,6 +826,7 @@ StepArgsT<T> make_step_args(const asd_plan* P, double lr) {
     };
     bc(P->step, &sa.bc1[0], &sa.bc2[0]);
     for (int q = 0; q < kMaxMasks; ++q) bc(q < P->n_masks ? P->mask_step[q] : 1, &sa.bc1[1 + q], &sa.bc2[1 + q]);
+    sa.mbf16 = P->prm.precision == ASD_PREC_MIXED;
     for (int g = 0; g < 1 + kMaxMasks; ++g) {
         const int stp = g == 0 ? P->step : (g - 1 < P->n_masks ? P->mask_step[g - 1] : 1);
         const int s1 = stp > 0 ? stp : 1;
@@ -808,6 +859,23 @@ asd_status reset_group_moments(asd_plan* P, hipStream_t st) {
 template <typename T>
 asd_status iteration(asd_plan* P, bool as_phase, int t, double lr, hipStream_t st) {
     constexpr bool kGeneral = sizeof(T) == 8;
+    // per-subproblem budgets: the subproblems whose budget exceeds t (a
+    // prefix, budgets being non-increasing) are updated, each with the
+    // learning rate of its own schedule
+    const bool rag = as_phase && P->ragged;
+    if (rag) {
+        int sa = 0;
+        while (sa < P->S && P->budgets[sa] > t) ++sa;
+        P->Sa = sa;
+        hipLaunchKernelGGL(k_lr_schedule<T>, dim3((unsigned)((sa + 255) / 256)), dim3(256), 0, st,
+                           (const int*)P->budgets_dev, sa, t, P->prm.as_lr0, P->prm.as_lr1,
+                           reinterpret_cast<T*>(P->lrs));
+        LAUNCH_CHECK();
+    }
+    struct RestoreSa {
+        asd_plan* P;
+        ~RestoreSa() { P->Sa = P->S; }
+    } restore{P};
     for (int k = P->n - 1; k >= 0; --k) {
         if constexpr (kGeneral) TRY((launch_backward<T, T>(P, k, 0, ASD_K_BACKWARD, st)));
         else TRY(bwd_fast<T>(P, k, st));
@@ -829,7 +897,14 @@ asd_status iteration(asd_plan* P, bool as_phase, int t, double lr, hipStream_t s
         P->step += 1;
         for (int q = 0; q < P->n_masks; ++q) P->mask_step[q] += 1;
     }
-    const StepArgsT<T> sa = make_step_args<T>(P, lr);
+    StepArgsT<T> sa = make_step_args<T>(P, lr);
+    if (rag) {
+        sa.lrs = reinterpret_cast<const T*>(P->lrs);
+        for (int g = 0; g < 1 + kMaxMasks; ++g) {
+            const int stp = g == 0 ? P->step : (g - 1 < P->n_masks ? P->mask_step[g - 1] : 1);
+            sa.ib1[g] = (T)(1.0 / (1.0 - pow(P->prm.adam_beta1, (double)(stp > 0 ? stp : 1))));
+        }
+    }
     for (int k = 1; k < P->n; ++k) {
         if constexpr (kGeneral) TRY(launch_forward<T>(P, k, sa, 0, nullptr, st));
         else TRY(fwd_fast<T>(P, k, sa, st));
@@ -925,25 +1000,47 @@ asd_status bound_grad_t(asd_plan* P, const double* gs, double* const* dW, double
         a.hi_in = NA<Ts>(P)[k - 1].hi;
         a.deg_in = NA<Ts>(P)[k - 1].deg;
         a.cvec = CV<Ts>(P);
-        if (!a.last) a.R = RL<Ts>(P)[k];
+        a.R = a.last ? nullptr : RdevT<Ts>(P) + k;
         return a;
     };
     for (int k = 1; k <= P->n; ++k) {
         const LayerGeo& g = P->geo[k];
         if (dW && dW[k - 1]) {
             GradArgs<Ts> a = base_args(k);
-            a.out = dW[k - 1];
-            const long entries = g.kind == ASD_LAYER_DENSE ? (long)g.out.C * g.fan
-                                                           : (long)g.out.C * g.in.C * g.ksz * g.ksz;
-            ProfScope ps(P, st, ASD_K_GRAD_WEIGHT, k);
-            hipLaunchKernelGGL(k_grad_weight<Ts>, dim3((unsigned)entries), dim3(kGradThreads), 0, st, a);
-            LAUNCH_CHECK();
+            a.r_chunk = P->gw_rchunk[k];
+            a.entries = (long)g.out.C * g.fan;
+            a.part = P->gpart;
+            {
+                ProfScope ps(P, st, ASD_K_GRAD_WEIGHT, k);
+                if (g.kind == ASD_LAYER_DENSE)
+                    hipLaunchKernelGGL(k_gw_dense<Ts>,
+                                       dim3((unsigned)((g.fan + kGradThreads - 1) / kGradThreads),
+                                            (unsigned)((g.out.C + kGdTO - 1) / kGdTO), (unsigned)P->gw_chunks[k]),
+                                       dim3(kGradThreads), 0, st, a);
+                else
+                    hipLaunchKernelGGL(k_gw_conv<Ts>,
+                                       dim3((unsigned)P->gw_chunks[k], (unsigned)((g.fan + kGcTT - 1) / kGcTT),
+                                            (unsigned)((g.out.C + kGcTO - 1) / kGcTO)),
+                                       dim3(kGradThreads), 0, st, a);
+                LAUNCH_CHECK();
+                hipLaunchKernelGGL(k_gsum, dim3((unsigned)((a.entries + kGradThreads - 1) / kGradThreads)),
+                                   dim3(kGradThreads), 0, st, (const double*)P->gpart, a.entries, P->gw_chunks[k],
+                                   dW[k - 1]);
+                LAUNCH_CHECK();
+            }
         }
         if (db && db[k - 1]) {
             GradArgs<Ts> a = base_args(k);
-            a.out = db[k - 1];
+            a.r_chunk = P->gb_rchunk[k];
+            a.entries = g.out.C;
+            a.part = P->gpart + P->gpart_w;
             ProfScope ps(P, st, ASD_K_GRAD_BIAS, k);
-            hipLaunchKernelGGL(k_grad_bias<Ts>, dim3((unsigned)g.out.C), dim3(kGradThreads), 0, st, a);
+            hipLaunchKernelGGL(k_gb_part<Ts>, dim3((unsigned)P->gb_chunks[k], (unsigned)g.out.C), dim3(kGradThreads), 0,
+                               st, a);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_gsum, dim3((unsigned)((g.out.C + kGradThreads - 1) / kGradThreads)),
+                               dim3(kGradThreads), 0, st, (const double*)a.part, (long)g.out.C, P->gb_chunks[k],
+                               db[k - 1]);
             LAUNCH_CHECK();
         }
     }
@@ -993,9 +1090,26 @@ asd_status check_field(asd_plan* P, int field, int k, int q) {
     return ASD_OK;
 }
 
+bool is_moment(int field) {
+    return field == ASD_F_ALPHA_M || field == ASD_F_ALPHA_V || field == ASD_F_BETA0_M || field == ASD_F_BETA0_V ||
+           field == ASD_F_BETA1_M || field == ASD_F_BETA1_V || field == ASD_F_MASK_M || field == ASD_F_MASK_V;
+}
+
+// Moment fields of a mixed-mode plan: BF16 in the plan, float for the caller.
+asd_status moment_bf16(asd_plan* P, int field, int k, int q, float* ext, int mode, hipStream_t st) {
+    uint16_t* arr = reinterpret_cast<uint16_t*>(field_ptr<float>(P, field, k, q));
+    const NeuronLayout& nl = P->nl[k];
+    dim3 grid((unsigned)((nl.cols + 255) / 256), (unsigned)nl.C);
+    hipLaunchKernelGGL(k_layout_bf16, grid, dim3(256), 0, st, arr, ext, nl, P->S, mode);
+    LAUNCH_CHECK();
+    return ASD_OK;
+}
+
 template <typename T>
 asd_status state_get_t(asd_plan* P, int field, int k, int q, T* dst, hipStream_t st) {
     ReluLayerT<T>& r = RL<T>(P)[k];
+    if constexpr (sizeof(T) == 4)
+        if (P->prm.precision == ASD_PREC_MIXED && is_moment(field)) return moment_bf16(P, field, k, q, dst, 2, st);
     if (field == ASD_F_MASK_Z)
         return launch_bits<T, T>(P->nl[k], P->S, 0, r.slot[q].zbits, dst, nullptr, nullptr, st);
     if (field == ASD_F_MASK_XPREV)
@@ -1008,6 +1122,8 @@ template <typename T>
 asd_status state_set_t(asd_plan* P, int field, int k, int q, const T* src, hipStream_t st) {
     ReluLayerT<T>& r = RL<T>(P)[k];
     T* s = const_cast<T*>(src);
+    if constexpr (sizeof(T) == 4)
+        if (P->prm.precision == ASD_PREC_MIXED && is_moment(field)) return moment_bf16(P, field, k, q, s, 0, st);
     if (field == ASD_F_MASK_Z) {
         TRY((launch_bits<T, T>(P->nl[k], P->S, 2, r.slot[q].zbits, s, nullptr, nullptr, st)));
     } else if (field == ASD_F_MASK_XPREV) {
@@ -1076,6 +1192,9 @@ asd_status oracle_t(asd_plan* P, int k, const T* x_prev, const T* z, uint32_t* b
     LAUNCH_CHECK();
     return ASD_OK;
 }
+
+// Active Set iterations of the plan: the largest budget, or the schedule's T.
+int as_iters_of(const asd_plan* P) { return P->ragged ? P->budgets[0] : P->prm.as_iters; }
 
 }  // namespace
 
@@ -1190,6 +1309,8 @@ asd_status asd_plan_create(const asd_net* net, int32_t S, const asd_params* para
     setup_plan_geometry(P);
     Carver cv{reinterpret_cast<char*>(workspace), 0};
     carve(P, cv);
+    P->Sa = S;
+    P->ragged = false;
     *out = P;
     return ASD_OK;
 }
@@ -1252,7 +1373,7 @@ asd_status asd_run(asd_plan* P, int32_t phase, int32_t t_begin, int32_t n_iters,
     if (!P) return fail(ASD_EINVAL, "NULL plan");
     if (!P->loaded) return fail(ASD_EINVAL, "asd_init has not been called");
     if (phase != ASD_PHASE_BIGM && phase != ASD_PHASE_AS) return fail(ASD_EINVAL, "unknown phase");
-    const int T = phase == ASD_PHASE_BIGM ? P->prm.bigm_iters : P->prm.as_iters;
+    const int T = phase == ASD_PHASE_BIGM ? P->prm.bigm_iters : as_iters_of(P);
     if (t_begin < 0 || n_iters < 0 || t_begin + n_iters > T)
         return fail(ASD_EINVAL, "iterations [%d, %d) outside [0, %d)", t_begin, t_begin + n_iters, T);
     const bool as = phase == ASD_PHASE_AS;
@@ -1274,11 +1395,58 @@ asd_status asd_bound_grad(asd_plan* P, const double* gs, double* const* dW, doub
                    : bound_grad_t<float>(P, gs, dW, db, dl0, du0, st);
 }
 
+asd_status asd_set_budgets(asd_plan* P, const int32_t* budgets, hipStream_t st) {
+    if (!P) return fail(ASD_EINVAL, "NULL plan");
+    if (!budgets) {
+        P->ragged = false;
+        P->budgets.clear();
+        return ASD_OK;
+    }
+    for (int s = 0; s < P->S; ++s) {
+        if (budgets[s] < 1) return fail(ASD_EINVAL, "budget of subproblem %d is %d; budgets must be >= 1", s, budgets[s]);
+        if (s > 0 && budgets[s] > budgets[s - 1])
+            return fail(ASD_EINVAL, "budgets must be non-increasing (subproblem %d: %d after %d)", s, budgets[s],
+                        budgets[s - 1]);
+    }
+    P->budgets.assign(budgets, budgets + P->S);
+    HIP_TRY(hipMemcpyAsync(P->budgets_dev, P->budgets.data(), sizeof(int) * P->S, hipMemcpyHostToDevice, st));
+    // a later call may replace the host copy: finish this one first
+    HIP_TRY(hipStreamSynchronize(st));
+    P->ragged = true;
+    return ASD_OK;
+}
+
 asd_status asd_solve(asd_plan* P, const asd_batch* b, double* out_lb, float* x0, hipStream_t st) {
     TRY(asd_init(P, b, st));
     TRY(asd_run(P, ASD_PHASE_BIGM, 0, P->prm.bigm_iters, st));
-    TRY(asd_run(P, ASD_PHASE_AS, 0, P->prm.as_iters, st));
+    TRY(asd_run(P, ASD_PHASE_AS, 0, as_iters_of(P), st));
     return asd_bound(P, out_lb, x0, st);
+}
+
+asd_status asd_solve_group(asd_plan* const* plans, const asd_batch* const* batches, double* const* out_lb,
+                           int32_t n_plans, const hipStream_t* streams) {
+    if (!plans || !batches || !out_lb || !streams || n_plans < 1) return fail(ASD_EINVAL, "NULL argument");
+    for (int i = 0; i < n_plans; ++i) {
+        if (!plans[i] || !batches[i] || !out_lb[i]) return fail(ASD_EINVAL, "NULL entry %d", i);
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == plans[i]) return fail(ASD_EINVAL, "plan %d appears twice", i);
+    }
+    int tm = 0, ta = 0;
+    for (int i = 0; i < n_plans; ++i) {
+        TRY(asd_init(plans[i], batches[i], streams[i]));
+        tm = std::max(tm, plans[i]->prm.bigm_iters);
+        ta = std::max(ta, as_iters_of(plans[i]));
+    }
+    // one iteration of every plan in turn, each on its own stream, so the
+    // kernels of different plans overlap on the device
+    for (int t = 0; t < tm; ++t)
+        for (int i = 0; i < n_plans; ++i)
+            if (t < plans[i]->prm.bigm_iters) TRY(asd_run(plans[i], ASD_PHASE_BIGM, t, 1, streams[i]));
+    for (int t = 0; t < ta; ++t)
+        for (int i = 0; i < n_plans; ++i)
+            if (t < as_iters_of(plans[i])) TRY(asd_run(plans[i], ASD_PHASE_AS, t, 1, streams[i]));
+    for (int i = 0; i < n_plans; ++i) TRY(asd_bound(plans[i], out_lb[i], nullptr, streams[i]));
+    return ASD_OK;
 }
 
 asd_status asd_state_get(asd_plan* P, int32_t field, int32_t k, int32_t q, void* dst, hipStream_t st) {

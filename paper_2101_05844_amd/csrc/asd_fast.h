@@ -108,6 +108,8 @@ struct FastFwdArgs {
     const ReluLayerT<T>* R;     // layer k arrays, a copy in device memory (read
                                 // in the update only, through the scalar cache)
     StepArgsT<T> st;
+    int Sa;                     // subproblems updated: s < Sa (the geometry's
+                                // column counts cover the same prefix)
     T* part;                    // dense: partial products [ksplit][1 + nm][Cpad][S]
 };
 
@@ -121,6 +123,45 @@ struct FwdIn {
     unsigned zq;
     T LI[NM > 0 ? NM : 1], UI[NM > 0 ? NM : 1], bq[NM > 0 ? NM : 1], mq[NM > 0 ? NM : 1], vq[NM > 0 ? NM : 1];
 };
+
+// BF16 storage of Adam moments: round to nearest even on the FP32 bits, and
+// back by placing the 16 stored bits on top (moments are finite).
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_val(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+template <typename T>
+__device__ __forceinline__ T load_moment(const T* p, uint32_t idx, bool bf16) {
+    if constexpr (sizeof(T) == 4) {
+        if (bf16) return bf16_val(reinterpret_cast<const uint16_t*>(p)[idx]);
+    }
+    return p[idx];
+}
+template <typename T>
+__device__ __forceinline__ void store_moment(T* p, uint32_t idx, T v, bool bf16) {
+    if constexpr (sizeof(T) == 4) {
+        if (bf16) {
+            reinterpret_cast<uint16_t*>(p)[idx] = bf16_rne(v);
+            return;
+        }
+    }
+    p[idx] = v;
+}
+
+// Moment arrays of the mixed mode <-> caller [S][N] floats (mode 0: set,
+// rounding to BF16; mode 2: get).
+__global__ void k_layout_bf16(uint16_t* in_arr, float* ex_arr, NeuronLayout nl, int S, int mode) {
+    const long col = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (col >= nl.cols) return;
+    const int s = (int)(col / nl.P), p = (int)(col - (long)s * nl.P);
+    const long in_ = ((long)c * S + s) * nl.P + p;
+    const long ex = (long)s * nl.N + (long)c * nl.P + p;
+    if (mode == 0) in_arr[in_] = bf16_rne(ex_arr[ex]);
+    else ex_arr[ex] = bf16_val(in_arr[in_]);
+}
 
 template <typename T, int NM>
 __device__ __forceinline__ void fwd_load(const FastFwdArgs<T>& A, int c, uint32_t idx, uint32_t bi, FwdIn<T, NM>& in) {
@@ -138,13 +179,14 @@ __device__ __forceinline__ void fwd_load(const FastFwdArgs<T>& A, int c, uint32_
     for (int j = 0; j < 3; ++j) in.m[j] = in.v[j] = (T)0;
 #pragma unroll
     for (int q = 0; q < (NM > 0 ? NM : 1); ++q) in.mq[q] = in.vq[q] = (T)0;
+    const bool hb = A.st.mbf16 != 0;
     if (adam) {
-        in.m[0] = R->alpha_m[idx];
-        in.v[0] = R->alpha_v[idx];
-        in.m[1] = R->beta0_m[idx];
-        in.v[1] = R->beta0_v[idx];
-        in.m[2] = R->beta1_m[idx];
-        in.v[2] = R->beta1_v[idx];
+        in.m[0] = load_moment(R->alpha_m, idx, hb);
+        in.v[0] = load_moment(R->alpha_v, idx, hb);
+        in.m[1] = load_moment(R->beta0_m, idx, hb);
+        in.v[1] = load_moment(R->beta0_v, idx, hb);
+        in.m[2] = load_moment(R->beta1_m, idx, hb);
+        in.v[2] = load_moment(R->beta1_v, idx, hb);
     }
     in.zq = NM > 0 ? (unsigned)R->zpk[idx] : 0u;
 #pragma unroll
@@ -154,8 +196,8 @@ __device__ __forceinline__ void fwd_load(const FastFwdArgs<T>& A, int c, uint32_
         in.UI[q] = M->UI[idx];
         in.bq[q] = M->beta[idx];
         if (adam) {
-            in.mq[q] = M->m[idx];
-            in.vq[q] = M->v[idx];
+            in.mq[q] = load_moment(M->m, idx, hb);
+            in.vq[q] = load_moment(M->v, idx, hb);
         }
     }
 }
@@ -164,7 +206,7 @@ __device__ __forceinline__ void fwd_load(const FastFwdArgs<T>& A, int c, uint32_
 // ym[q] = (|W| (sigma_q . x))[i] + 2 (W+ x_point)[i], the projected step, the
 // derived sums own, g, vs, u_q; stores only.
 template <typename T, int NM>
-__device__ __forceinline__ void fwd_store(const FastFwdArgs<T>& A, uint32_t idx, const FwdIn<T, NM>& in, T yd,
+__device__ __forceinline__ void fwd_store(const FastFwdArgs<T>& A, uint32_t idx, int s, const FwdIn<T, NM>& in, T yd,
                                           const T* ym) {
     __builtin_assume(idx < (1u << 30));
     const cptr_t<ReluLayerT<T>> R = kconst_t(A.R);
@@ -178,17 +220,19 @@ __device__ __forceinline__ void fwd_store(const FastFwdArgs<T>& A, uint32_t idx,
     gr[2] = x - xhat + ((T)1 - z) * lh;
     // Adam: theta + (lr / (1 - b1^t)) m / (sqrt(v / (1 - b2^t)) + eps), with
     // the hardware square root and reciprocal (a few ulps in FP32)
+    const T lr_s = st.lrs ? st.lrs[s] : st.lr;
     auto step = [&](T th, T m, T v, T g, int grp, T* mo, T* vo) -> T {
-        if (!adam) return tmax0(th + st.lr * g);
+        if (!adam) return tmax0(th + lr_s * g);
+        const T c1 = st.lrs ? lr_s * st.ib1[grp] : st.c1[grp];
         const T mm = st.b1 * m + ((T)1 - st.b1) * g;
         const T vv = st.b2 * v + ((T)1 - st.b2) * g * g;
-        mo[idx] = mm;
-        vo[idx] = vv;
+        store_moment(mo, idx, mm, st.mbf16 != 0);
+        store_moment(vo, idx, vv, st.mbf16 != 0);
         if constexpr (sizeof(T) == 4) {
             const float den = __builtin_amdgcn_sqrtf(vv * st.ib2[grp]) + st.eps;
-            return tmax0(th + st.c1[grp] * mm * __builtin_amdgcn_rcpf(den));
+            return tmax0(th + c1 * mm * __builtin_amdgcn_rcpf(den));
         } else {
-            return tmax0(th + st.c1[grp] * mm / (tsqrt(vv * st.ib2[grp]) + st.eps));
+            return tmax0(th + c1 * mm / (tsqrt(vv * st.ib2[grp]) + st.eps));
         }
     };
     const T al = step(in.th[0], in.m[0], in.v[0], gr[0], 0, R->alpha_m, R->alpha_v);
@@ -219,11 +263,11 @@ __device__ __forceinline__ void fwd_store(const FastFwdArgs<T>& A, uint32_t idx,
 }
 
 template <typename T, int NM>
-__device__ __forceinline__ void fwd_update(const FastFwdArgs<T>& A, int c, uint32_t idx, uint32_t bi, T yd,
+__device__ __forceinline__ void fwd_update(const FastFwdArgs<T>& A, int c, uint32_t idx, int s, uint32_t bi, T yd,
                                            const T* ym) {
     FwdIn<T, NM> in;
     fwd_load<T, NM>(A, c, idx, bi, in);
-    fwd_store<T, NM>(A, idx, in, yd, ym);
+    fwd_store<T, NM>(A, idx, s, in, yd, ym);
 }
 
 // ---------------------------------------------------------------------------
@@ -364,7 +408,7 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_conv(FastFwdArgs<T> A) {
         T ymj[NA];
 #pragma unroll
         for (int q = 0; q < NM; ++q) ymj[q] = tot[1 + q][j];
-        fwd_store<T, NM>(A, ((long)c * S + s) * g.out.P + p, in[j], tot[0][j], ymj);
+        fwd_store<T, NM>(A, ((long)c * S + s) * g.out.P + p, s, in[j], tot[0][j], ymj);
     }
 }
 
@@ -619,7 +663,7 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_conv_mfma(FastFwdArgs<float>
             const int ii = b0 + jb;
             const int i = SPLITK ? wave * NR + ii : ii;
             const int c = min(m0 + 8 * (i / 4) + 4 * half + (i % 4), g.out.C - 1);
-            fwd_load<float, NM>(A, c, (long)c * g.out.cols + col, (long)c * g.out.colpad + col, in[jb]);
+            fwd_load<float, NM>(A, c, (long)c * S * g.out.P + col, (long)c * g.out.colpad + col, in[jb]);
         }
 #pragma unroll
         for (int jb = 0; jb < NB; ++jb) {
@@ -630,7 +674,7 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_conv_mfma(FastFwdArgs<float>
             float ym[NM > 0 ? NM : 1];
 #pragma unroll
             for (int q = 0; q < NM; ++q) ym[q] = tot[1 + q][ii];
-            fwd_store<float, NM>(A, (long)c * g.out.cols + col, in[jb], tot[0][ii], ym);
+            fwd_store<float, NM>(A, (long)c * S * g.out.P + col, s, in[jb], tot[0][ii], ym);
         }
     }
 }
@@ -643,7 +687,7 @@ __global__ void __launch_bounds__(256) k_fwd_dense_epi(FastFwdArgs<T> A) {
     const int s = blockIdx.x * 256 + threadIdx.x;
     const int c = blockIdx.y;
     const int S = A.S;
-    if (s >= S) return;
+    if (s >= A.Sa) return;
     const int Cp = A.Cpad;
     T yd = 0, ym[NA];
 #pragma unroll
@@ -656,7 +700,7 @@ __global__ void __launch_bounds__(256) k_fwd_dense_epi(FastFwdArgs<T> A) {
     }
     const long idx = (long)c * S + s;  // dense layout, P = 1
     const long bi = (long)c * A.g.out.colpad + s;
-    fwd_update<T, NM>(A, c, idx, bi, yd, ym);
+    fwd_update<T, NM>(A, c, idx, s, bi, yd, ym);
 }
 
 // ---------------------------------------------------------------------------

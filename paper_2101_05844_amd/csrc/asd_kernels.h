@@ -214,15 +214,16 @@ __global__ void __launch_bounds__(kWave * KS) k_forward(FwdArgs<T> A) {
         return;
     }
     const StepArgsT<T>& st = A.st;
+    const T lr_s = st.lrs ? st.lrs[s] : st.lr;
     auto step = [&](T th, T* m, T* v, T gr, int grp) -> T {
-        if (st.rule == ASD_RULE_SUPERGRADIENT) return tmax0(th + st.lr * gr);
+        if (st.rule == ASD_RULE_SUPERGRADIENT) return tmax0(th + lr_s * gr);
         const T mm = st.b1 * m[idx] + ((T)1 - st.b1) * gr;
         const T vv = st.b2 * v[idx] + ((T)1 - st.b2) * gr * gr;
         m[idx] = mm;
         v[idx] = vv;
         const T mh = mm / st.bc1[grp];
         const T vh = vv / st.bc2[grp];
-        return tmax0(th + st.lr * mh / (tsqrt(vh) + st.eps));
+        return tmax0(th + lr_s * mh / (tsqrt(vh) + st.eps));
     };
     const T al = step(A.R.alpha[idx], A.R.alpha_m, A.R.alpha_v, ga, 0);
     const T b0 = step(A.R.beta0[idx], A.R.beta0_m, A.R.beta0_v, gb0, 0);
@@ -722,6 +723,17 @@ struct ReduceArgs {
     int n_last;
     double* out;
 };
+
+// Learning rate of Active Set iteration t for each updated subproblem on its
+// own linear schedule over its budget (the same expression as the shared
+// schedule, in FP64).
+template <typename T>
+__global__ void __launch_bounds__(256) k_lr_schedule(const int* budgets, int Sa, int t, double lr0, double lr1, T* lrs) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= Sa) return;
+    const int Ts = budgets[s];
+    lrs[s] = (T)(Ts <= 1 ? lr0 : lr0 + (lr1 - lr0) * (double)t / (double)(Ts - 1));
+}
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_reduce_obj(ReduceArgs<T> A) {

@@ -325,6 +325,37 @@ def adjoint_config(seed: int = 1004, n_inputs: int = 256, net_seed: int = 1002) 
                           "true_class": true})
 
 
+def ragged_config(seed: int = 1003, S: int = 4096, net_seeds=(1002, 1005), max_fixed: int = 50,
+                  budget_range=(100, 1000)):
+    """Ragged batch of branch-and-bound subdomains: S/2 on the CIFAR "Wide"
+    net of cifar_conv_config (same weights) and S/2 on its wider variant
+    (conv 3->32 and 32->64, FC 4096->512->10), one input box and property
+    per net (3x32x32 U[0,1], eps 2/255), each subdomain fixing U{0..max_fixed}
+    ambiguous ReLUs and carrying its own Active Set budget U{budget_range}.
+    Returns one Workload per net (subdomains ordered by non-increasing
+    budget, budgets in meta["budgets"])."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i, (specs, nseed) in enumerate(((CIFAR_WIDE_SPECS, net_seeds[0]), (CIFAR_WIDER_SPECS, net_seeds[1]))):
+        layers = draw_layers(specs, np.random.default_rng(nseed))
+        Sn = S // 2 if i == 0 else S - S // 2
+        centre = rng.uniform(0.0, 1.0, size=3 * 32 * 32)
+        eps = 2.0 / 255.0
+        l0, u0 = linf_box(centre, eps, (0.0, 1.0))
+        t = int(rng.integers(0, 10))
+        j = int(rng.choice([k for k in range(10) if k != t]))
+        c = logit_difference_rows(10, t, [j])
+        n_relu = sum(spec_sizes(sp)[1] for sp in specs[:-1])
+        draws = draw_fixes(rng, Sn, n_relu, max_fixed)
+        budgets = np.sort(rng.integers(budget_range[0], budget_range[1] + 1, size=Sn))[::-1].copy()
+        sched = Schedule(bigm_iters=180, as_iters=int(budgets[0]), add_every=450, add_count=2, max_masks=7)
+        out.append(Workload(f"ragged-{'wide' if i == 0 else 'wider'}", layers, np.repeat(l0[None], Sn, 0),
+                            np.repeat(u0[None], Sn, 0), np.repeat(c, Sn, 0), sched, fix_draws=draws,
+                            meta={"seed": seed, "net_seed": nseed, "eps": eps, "true_class": t, "target": j,
+                                  "budgets": [int(b) for b in budgets]}))
+    return out
+
+
 def custom_config(specs: Sequence, S: int, seed: int, eps: float = 0.05,
                   centre_range=(0.0, 1.0), n_props: Optional[int] = None,
                   max_fixed: int = 0, schedule: Optional[Schedule] = None,

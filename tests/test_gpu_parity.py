@@ -34,6 +34,11 @@ SMALL_DENSE = [WL.DenseSpec(37, 53), WL.DenseSpec(53, 29), WL.DenseSpec(29, 4)]
 # channels (forward on matrix cores, backward with positions on lanes)
 MFMA_CONV = [WL.ConvSpec(2, 16, 16, 16, 3, 1, 1), WL.ConvSpec(16, 16, 16, 32, 4, 2, 1),
              WL.DenseSpec(32 * 8 * 8, 20), WL.DenseSpec(20, 3)]
+# the convolutions of the wider CIFAR variant (32 and 64 channels) with a
+# narrow dense head: transposed convolutions from 64 channels on the matrix
+# cores, the dense backward with positions on lanes into 64 x 8 x 8
+WIDER_CONV = [WL.ConvSpec(3, 32, 32, 32, 4, 2, 1), WL.ConvSpec(32, 16, 16, 64, 4, 2, 1),
+              WL.DenseSpec(64 * 8 * 8, 24), WL.DenseSpec(24, 3)]
 
 
 def _A():
@@ -66,6 +71,8 @@ def workloads_small():
                          name="conv-2x7x9"),
         WL.custom_config(MFMA_CONV, S=9, seed=23, eps=0.03, schedule=sched, max_fixed=6,
                          name="conv-2x16x16"),
+        WL.custom_config(WIDER_CONV, S=4, seed=24, eps=0.01, schedule=sched, max_fixed=8,
+                         name="conv-3x32x32-wider"),
     ]
 
 
@@ -89,7 +96,7 @@ def test_interval_bounds_match_oracle(wi):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-@pytest.mark.parametrize("wi", [0, 1])
+@pytest.mark.parametrize("wi", [0, 1, 3])
 @pytest.mark.parametrize("n_masks", [0, 3])
 def test_fixed_dual_evaluation(wi, n_masks, prec):
     w = workloads_small()[wi]
@@ -220,20 +227,31 @@ def _window_plan(prec, rule):
     return [("bigm", 3), ("bigm", 6), ("as", 4), ("as", 9)], 1, 2e-5
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "mixed"])
 @pytest.mark.parametrize("rule", ["supergradient", "adam"])
-@pytest.mark.parametrize("wi", [0, 1, 2])
+@pytest.mark.parametrize("wi", [0, 1, 2, 3])
 def test_iteration_windows_match_oracle(wi, rule, prec):
     """Import the oracle's state at points of its run (the Big-M start, mid
     Big-M, the Active Set start with its mask additions, and later), advance
     the GPU, and compare every subproblem's duals and bound with the
-    oracle's state at the end of the same window (see _window_plan)."""
+    oracle's state at the end of the same window (see _window_plan).  The
+    mixed mode (BF16-stored Adam moments) is compared with the oracle run
+    whose Adam step stores its moments rounded to bfloat16; its moments must
+    also agree, within one bfloat16 spacing (the GPU rounds the FP32 update,
+    the oracle the FP64 one)."""
+    if prec == "mixed" and rule != "adam":
+        pytest.skip("the plain rule keeps no moments: the mixed mode is the FP32 mode")
+    if wi == 3 and prec == "mixed":
+        pytest.skip("the mixed mode's moments are covered on the other shapes")
     w = workloads_small()[wi]
     A = _A()
-    starts, win, tol = _window_plan(prec, rule)
-    eps = EPS[prec]
+    starts, win, tol = _window_plan("fp32" if prec == "mixed" else prec, rule)
+    eps = EPS["fp32" if prec == "mixed" else prec]
     prm = O.params_from_schedule(w.schedule)
-    params = A.params_from_schedule(w.schedule, A.ASD_PREC_FP64 if prec == "fp64" else A.ASD_PREC_FP32)
+    if prec == "mixed":
+        prm.adam = O.AdamConsts(prm.adam.beta1, prm.adam.beta2, prm.adam.eps, moments="bf16")
+    params = A.params_from_schedule(w.schedule, {"fp32": A.ASD_PREC_FP32, "fp64": A.ASD_PREC_FP64,
+                                                 "mixed": A.ASD_PREC_MIXED}[prec])
     if rule == "supergradient":
         prm.rule = "sgd"
         params.rule = A.ASD_RULE_SUPERGRADIENT
@@ -250,7 +268,7 @@ def test_iteration_windows_match_oracle(wi, rule, prec):
     # may differ, by at most 2.5 step sizes, only where the oracle's
     # supergradient at the window start is within rounding of zero; every
     # other entry must match.
-    loose = prec == "fp32" and rule == "adam"
+    loose = prec in ("fp32", "mixed") and rule == "adam"
     lr_max = max(prm.bigm_lr[0], prm.as_lr[0])
     n_ent = n_bad = 0
     for ph, t in starts:
@@ -264,6 +282,15 @@ def test_iteration_windows_match_oracle(wi, rule, prec):
         K = plan.counts().n_masks
         assert K == len(ends[0].masks[0])
         duals = H.export_duals(plan, len(ops), K)
+        moments = {}
+        if prec == "mixed":
+            for k in range(1, len(ops)):
+                for fld in (A.ASD_F_ALPHA_M, A.ASD_F_ALPHA_V, A.ASD_F_BETA0_M, A.ASD_F_BETA0_V,
+                            A.ASD_F_BETA1_M, A.ASD_F_BETA1_V):
+                    moments[(fld, k, 0)] = plan.get(fld, k).cpu().numpy().astype(np.float64)
+                for q in range(K):
+                    for fld in (A.ASD_F_MASK_M, A.ASD_F_MASK_V):
+                        moments[(fld, k, q)] = plan.get(fld, k, q).cpu().numpy().astype(np.float64)
         lb = out.cpu().numpy()
         for s, (p, e) in enumerate(zip(probs, ends)):
             d_ora = O.evaluate(p, e)[0]
@@ -296,6 +323,20 @@ def test_iteration_windows_match_oracle(wi, rule, prec):
                         assert np.all(np.abs(a - b) <= 2.5 * lr_max + eps * (1 + np.abs(b))), (ph, t, s, k, name)
                     else:
                         assert ok.all(), (ph, t, s, k, name, np.flatnonzero(~ok)[:5])
+                    if prec == "mixed":
+                        # moments where the dual matched
+                        if j < 3:
+                            fm, fv = [(A.ASD_F_ALPHA_M, A.ASD_F_ALPHA_V), (A.ASD_F_BETA0_M, A.ASD_F_BETA0_V),
+                                      (A.ASD_F_BETA1_M, A.ASD_F_BETA1_V)][j]
+                            om, ov = e.m[name][k - 1], e.v[name][k - 1]
+                            q = 0
+                        else:
+                            fm, fv, q = A.ASD_F_MASK_M, A.ASD_F_MASK_V, j - 3
+                            om, ov = e.masks[k - 1][q].m, e.masks[k - 1][q].v
+                        for fld, ref in ((fm, om), (fv, ov)):
+                            got = moments[(fld, k, q)][s]
+                            close = np.abs(got - ref) <= 2.0 ** -7 * np.abs(ref) + 1e-30
+                            assert np.all(close | ~ok), (ph, t, s, k, name, fld)
     print(f"{n_bad} of {n_ent} entries differ (ties under Adam's normalised step)" if loose else "", flush=True)
 
 
@@ -360,6 +401,27 @@ def test_end_to_end_fp32(wi):
     ora = np.array(ora)
     n = len(ora)
     assert abs(lb[:n].mean() - ora.mean()) <= 2e-2 * max(1.0, abs(ora.mean()))
+
+
+@pytest.mark.parametrize("wi", [0, 1, 2, 3])
+def test_end_to_end_mixed(wi):
+    """Whole runs with BF16-stored Adam moments: the final bound is the FP64
+    evaluation of valid duals, so it never exceeds a sampled output and
+    never falls below the interval bound; it stays within the FP32 form's
+    sensitivity band of the FP32 run (5e-2 per subproblem, 2e-2 on the
+    mean)."""
+    w = e2e_workloads()[wi]
+    A, ops, probs, net, plan, batch = _setup(w, prec="fp32")
+    lb32 = plan.solve(*batch).cpu().numpy()
+    prm = A.params_from_schedule(w.schedule, A.ASD_PREC_MIXED)
+    plan_m = A.Plan(net, w.S, prm)
+    lbm = plan_m.solve(*batch).cpu().numpy()
+    for s, p in enumerate(probs[:12]):
+        assert lbm[s] <= _sampled_min(ops, p, w.l0[s], w.u0[s], s) + 1e-6
+        assert lbm[s] >= O.evaluate(p, O.zero_state(p))[0] - 1e-5 * max(1.0, abs(lbm[s]))
+    assert np.all(np.abs(lbm - lb32) <= 5e-2 * np.maximum(1.0, np.abs(lb32)))
+    assert abs(np.mean(lbm - lb32)) <= 2e-2 * max(1.0, float(np.mean(np.abs(lb32))))
+    print(f"mean fp32 - mixed {np.mean(lb32 - lbm):.3e}, max |diff| {np.max(np.abs(lb32 - lbm)):.3e}", flush=True)
 
 
 def test_deterministic_repeat():
@@ -427,3 +489,77 @@ def test_bound_function_autograd():
     # repeated evaluation is bit-identical (fixed-order sums)
     dW2, _, dl02, _ = plan.bound_grad(gs)
     assert all(torch.equal(a, b) for a, b in zip(dW, dW2)) and torch.equal(dl0, dl02)
+
+
+def _ragged_budgets(w, seed):
+    rng = np.random.default_rng(seed)
+    T = w.schedule.as_iters
+    b = np.sort(rng.integers(2, T + 1, size=w.S))[::-1].copy()
+    b[0] = T
+    return [int(v) for v in b]
+
+
+@pytest.mark.parametrize("wi", [0, 1])
+def test_ragged_budgets_match_plain_solves_fp64(wi):
+    """Per-subproblem Active Set budgets (FP64 plan): subproblem s of a ragged
+    batch ends with the bound of a plain solve whose Active Set phase has
+    T = budget[s] iterations (own learning-rate schedule, same additions)."""
+    w = workloads_small()[wi]
+    A, ops, probs, net, plan, batch = _setup(w, prec="fp64")
+    budgets = _ragged_budgets(w, 60 + wi)
+    plan.set_budgets(budgets)
+    lb = plan.solve(*batch).cpu().numpy()
+    for T in sorted(set(budgets)):
+        prm = A.params_from_schedule(w.schedule, A.ASD_PREC_FP64)
+        prm.as_iters = T
+        ref_plan = A.Plan(net, w.S, prm)
+        ref = ref_plan.solve(*batch).cpu().numpy()
+        rows = [s for s in range(w.S) if budgets[s] == T]
+        for s in rows:
+            assert abs(lb[s] - ref[s]) <= 1e-12 * max(1.0, abs(ref[s])), (T, s, lb[s], ref[s])
+    # and against the oracle's solve with the subproblem's own T
+    prm_o = O.params_from_schedule(w.schedule)
+    for s in (0, w.S // 2, w.S - 1):
+        prm_o.as_iters = budgets[s]
+        r = O.solve(probs[s], prm_o)
+        assert abs(lb[s] - r.bound) <= 1e-8 * max(1.0, abs(r.bound)), (s, lb[s], r.bound)
+
+
+@pytest.mark.parametrize("wi", [1, 2])
+def test_ragged_budgets_independent_fp32(wi):
+    """FP32 plan (matrix-core and column kernels): subproblem s of a ragged
+    batch is bit-identical to the same subproblem in a batch where every
+    budget equals budget[s]: updating only the prefix within budget changes
+    nothing for the others."""
+    w = workloads_small()[wi]
+    A, ops, probs, net, plan, batch = _setup(w, prec="fp32")
+    budgets = _ragged_budgets(w, 70 + wi)
+    plan.set_budgets(budgets)
+    lb = plan.solve(*batch).cpu().numpy()
+    ref_plan = A.Plan(net, w.S, A.params_from_schedule(w.schedule, A.ASD_PREC_FP32))
+    for T in sorted(set(budgets)):
+        ref_plan.set_budgets([T] * w.S)
+        ref = ref_plan.solve(*batch).cpu().numpy()
+        rows = [s for s in range(w.S) if budgets[s] == T]
+        assert np.array_equal(lb[rows], ref[rows]), (T, rows, lb[rows], ref[rows])
+    with pytest.raises(A.AsdError):
+        plan.set_budgets(sorted(budgets))  # increasing: rejected
+
+
+def test_solve_group_matches_separate_solves():
+    """asd_solve_group over two plans on different nets (one with budgets),
+    each on its own stream: every bound equals that plan's own asd_solve."""
+    A = _A()
+    outs_sep, plans, batches = [], [], []
+    for wi, budgets in ((1, True), (2, False)):
+        w = workloads_small()[wi]
+        A, ops, probs, net, plan, batch = _setup(w, prec="fp32")
+        if budgets:
+            plan.set_budgets(_ragged_budgets(w, 80))
+        outs_sep.append(plan.solve(*batch).cpu().numpy())
+        plans.append(plan)
+        batches.append(batch)
+    outs = A.solve_group(plans, batches)
+    torch.cuda.synchronize()
+    for a, b in zip(outs, outs_sep):
+        assert np.array_equal(a.cpu().numpy(), b)

@@ -451,6 +451,32 @@ def test_adam_ascent_matches_library_adam():
     assert np.allclose(t, th.detach().numpy(), rtol=1e-12, atol=1e-14)
 
 
+def test_round_bf16_matches_library_conversion():
+    """round_bf16 (the stored form of Adam moments in the mixed mode) against
+    the library's float32 -> bfloat16 conversion, on values spanning the
+    exponent range, exact halfway cases (ties to even) and float32
+    subnormals."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(12)
+    vals = [rng.normal(size=4000) * 10.0 ** rng.uniform(-30, 30, 4000)]
+    # halfway between consecutive bfloat16 values: 1 + k/128 + 1/256
+    k = np.arange(128)
+    vals.append(np.concatenate([(1 + k / 128 + 1 / 256) * 2.0 ** e for e in (-100, -3, 0, 7, 90)]))
+    vals.append(-vals[-1])
+    vals.append(rng.uniform(-1, 1, 500) * 2.0 ** -128)   # subnormal in float32
+    a = np.concatenate(vals).astype(np.float32).astype(np.float64)
+    ref = torch.tensor(a, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    got = O.round_bf16(a)
+    assert np.array_equal(got, ref)
+    # the Adam step of the mixed mode steps with the unrounded moments and
+    # stores them rounded
+    g, m_in, v_in = rng.normal(size=50), O.round_bf16(rng.normal(size=50)), O.round_bf16(rng.uniform(0, 1, 50))
+    th_b, m_b, v_b = O.adam_ascent(np.full(50, 0.3), m_in, v_in, g, 3, 1e-3, O.AdamConsts(moments="bf16"))
+    th_e, m_e, v_e = O.adam_ascent(np.full(50, 0.3), m_in, v_in, g, 3, 1e-3, O.AdamConsts())
+    assert np.array_equal(th_b, th_e)
+    assert np.array_equal(m_b, O.round_bf16(m_e)) and np.array_equal(v_b, O.round_bf16(v_e))
+
+
 # ----------------------------------------------------------------------------
 # Adjoint: gradient of the bound at fixed duals and fixed active sets
 # ----------------------------------------------------------------------------

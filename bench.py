@@ -175,7 +175,7 @@ def ragged_leg(A, np, torch, WL):
     ws = WL.ragged_config()
     dev = "cuda:0"
     t32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=dev)
-    plans, batches, iters = [], [], 0
+    plans, batches, iters, tunings = [], [], 0, []
     for w in ws:
         net = A.Net(w.layers, device=dev)
         lh0, uh0 = net.interval_bounds(t32(w.l0[:1]), t32(w.u0[:1]))
@@ -183,8 +183,11 @@ def ragged_leg(A, np, torch, WL):
                                    w.fix_draws, w.S)
         plan = A.Plan(net, w.S, A.params_from_schedule(w.schedule))
         plan.set_budgets(w.meta["budgets"])
+        b = (t32(w.l0), t32(w.u0), [t32(a) for a in L], [t32(a) for a in U], t32(w.c))
+        plan.init(*b)
+        tunings.append(plan.autotune(ktune=2, reps=3))
         plans.append(plan)
-        batches.append((t32(w.l0), t32(w.u0), [t32(a) for a in L], [t32(a) for a in U], t32(w.c)))
+        batches.append(b)
         iters += sum(w.meta["budgets"])
     stream = torch.cuda.current_stream()
     A.solve_group(plans, batches)            # warm-up
@@ -208,7 +211,7 @@ def ragged_leg(A, np, torch, WL):
             "ms": round(ms_group, 3), "ms_one_stream": round(ms_seq, 3),
             "rate": round((iters + bm) / (ms_group / 1e3), 1), "unit": "subproblem-iterations/s (whole solve)",
             "bound_mean": [float(np.mean(l)) for l in lbs],
-            "verified": [int(np.sum(l > 0)) for l in lbs]}
+            "verified": [int(np.sum(l > 0)) for l in lbs], "tuning": tunings}
 
 
 def cpu_baseline(w, n_sub=2):
@@ -254,6 +257,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the bound-gradient leg")
     ap.add_argument("--no-mixed", action="store_true", help="skip the BF16-moment form")
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged two-net batch")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the heuristic kernel choices")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 3 device-to-device copies of MIB MiB (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
@@ -298,6 +302,12 @@ def main():
     lh, uh = [t32(a) for a in L], [t32(a) for a in U]
     plan = A.Plan(net, S, A.params_from_schedule(sched))
     stream = torch.cuda.current_stream()
+    tuning = None
+    if not args.no_autotune:
+        # kernel choices timed on this batch (two empty mask slots active)
+        plan.init(l0, u0, lh, uh, c)
+        tuning = plan.autotune(ktune=2, reps=3)
+        print(f"[bench] autotuned kernel choices {tuning}", file=sys.stderr, flush=True)
 
     def step(ev=None):
         plan.init(l0, u0, lh, uh, c)
@@ -370,6 +380,8 @@ def main():
         del plan
         prm_mixed = A.params_from_schedule(sched, A.ASD_PREC_MIXED)
         plan = A.Plan(net, S, prm_mixed)
+        if tuning is not None:
+            plan.set_tuning(tuning)
         for _ in range(args.warmup):
             lb_m = step()
         torch.cuda.synchronize()
@@ -430,6 +442,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,
+        "tuning": tuning,
         "mixed": mixed,
         "ragged": ragged,
         "adjoint": adjoint,

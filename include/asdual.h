@@ -90,10 +90,12 @@ typedef enum { ASD_RULE_ADAM = 0, ASD_RULE_SUPERGRADIENT = 1 } asd_rule;
  * production form (FP32 duals, moments and sums; the final bound is
  * re-evaluated in FP64).  ASD_PREC_FP64 keeps everything in FP64 (twice the
  * memory and traffic); it exists to compare whole runs with an FP64
- * reference.  ASD_PREC_MIXED is ASD_PREC_FP32 with the Adam moments stored
- * in BF16 between iterations (round to nearest even; each update is computed
- * in FP32 from the stored value and steps with the unrounded result): a
- * third less state traffic per multiplier.  The duals, the products and the
+ * reference.  ASD_PREC_MIXED is ASD_PREC_FP32 with the two Adam moments of
+ * each multiplier stored together in one 32-bit word as BF16 between
+ * iterations (round to nearest even; each update is computed in FP32 from
+ * the stored values and steps with the unrounded result): one load and one
+ * store of 4 bytes instead of two of 8, a third less state traffic per
+ * multiplier.  The duals, the products and the
  * FP64 final bound are those of ASD_PREC_FP32, so the bound stays valid;
  * only the trajectory of the ascent changes.  The state calls exchange the
  * moments as float in every FP32-duals mode.  Network weights and batch
@@ -195,6 +197,17 @@ asd_status asd_set_budgets(asd_plan* plan, const int32_t* budgets /* host */, hi
  * device doubles. */
 asd_status asd_solve(asd_plan* plan, const asd_batch* batch, double* out_lb, float* x0,
                      hipStream_t stream);
+
+/* asd_solve with the iterations replayed from a HIP graph: the first call
+ * (and the first after asd_set_budgets, asd_plan_set_tuning or
+ * asd_plan_autotune) captures the Big-M and Active Set iterations of the
+ * plan's schedule from `stream` into a graph and instantiates it; every call
+ * runs asd_init (eager), launches the graph, then asd_bound (eager).  The
+ * graph reads only the plan's workspace, so it serves any batch of the
+ * plan's size.  Results equal asd_solve's.  Errors: those of asd_solve;
+ * ASD_EINVAL while kernel profiling is on; ASD_EDEVICE if capture or
+ * instantiation fails. */
+asd_status asd_solve_graph(asd_plan* plan, const asd_batch* batch, double* out_lb, hipStream_t stream);
 
 /* Solves several plans (for instance one per network of a mixed batch of
  * branch-and-bound subdomains, each plan with its own budgets) together:
@@ -313,6 +326,40 @@ asd_status asd_bound_grad(asd_plan* plan, const double* g, double* const* dW /* 
  * floats, host array of device pointers.  l0, u0 [S][n_0]. */
 asd_status asd_interval_bounds(const asd_net* net, int32_t S, const float* l0, const float* u0,
                                float* const* lhat, float* const* uhat, hipStream_t stream);
+
+/* ---- Autotuning of the iteration kernels ---- */
+
+/* Kernel choices of an FP32-duals plan, per layer (index L-1 for layer L;
+ * the backward entries are indexed by the neuron layer k they write):
+ *   ksplit[L-1]   dense ReLU layer L: partial sums over the fan-in (1..8),
+ *   fwd_mfma[L-1] convolutional ReLU layer L with < 32 channels: forward on
+ *                 the matrix cores (1) or the VALU column kernel (0),
+ *   bwd_cb[k]     transposed convolution into layer k on the column kernel:
+ *                 channels per thread (4 or 8; 0 = default),
+ *   bwd_pos[k]    dense backward into layer k: positions on lanes (1) or
+ *                 the column kernel (0). */
+typedef struct {
+    int32_t ksplit[ASD_MAX_LAYERS];
+    int32_t fwd_mfma[ASD_MAX_LAYERS];
+    int32_t bwd_cb[ASD_MAX_LAYERS];
+    int32_t bwd_pos[ASD_MAX_LAYERS];
+} asd_tuning;
+
+/* Times every alternative of the choices above on the loaded batch (each
+ * kernel alone, `reps` launches after one warm-up, HIP events on `stream`)
+ * with `ktune` mask slots active, and keeps the fastest.  The plan's state is
+ * unchanged: the kernels run with the plain rule at step size 0 and the
+ * slots beyond the active ones hold zero multipliers.  Call after asd_init
+ * (before masks are added).  FP64 plans run the general kernels only: no-op.
+ * Synchronises `stream`.  Errors: ASD_EINVAL before asd_init, for ktune
+ * outside [0, max_masks] or below the active mask count, reps < 1. */
+asd_status asd_plan_autotune(asd_plan* plan, int32_t ktune, int32_t reps, hipStream_t stream);
+asd_status asd_plan_get_tuning(const asd_plan* plan, asd_tuning* out /* host */);
+/* Sets the choices (entries of layers beyond the net are ignored).  Every
+ * choice is valid for every shape: one a shape cannot take falls back to the
+ * kernel it would use anyway.  Errors: ASD_EINVAL for values outside the
+ * ranges above. */
+asd_status asd_plan_set_tuning(asd_plan* plan, const asd_tuning* in /* host */);
 
 /* ---- Kernel timing (for the benchmark's roofline figures) ---- */
 

@@ -71,6 +71,11 @@ ROLE_NAMES = {0: "backward", 1: "forward", 2: "mask", 3: "final", 4: "other", 5:
               6: "grad_bias", 7: "grad_box"}
 
 
+class Tuning(C.Structure):
+    _fields_ = [("ksplit", C.c_int32 * 16), ("fwd_mfma", C.c_int32 * 16), ("bwd_cb", C.c_int32 * 16),
+                ("bwd_pos", C.c_int32 * 16)]
+
+
 class EvalOut(C.Structure):
     _fields_ = [("obj", C.c_void_p),
                 ("xstar", C.c_void_p * ASD_MAX_LAYERS),
@@ -86,7 +91,8 @@ _lib = None
 EXPORTED = ["asd_net_create", "asd_net_destroy", "asd_params_default", "asd_plan_workspace_size",
             "asd_plan_create", "asd_plan_destroy", "asd_init", "asd_run", "asd_bound", "asd_solve",
             "asd_state_get", "asd_state_set", "asd_state_get_counts", "asd_state_set_counts",
-            "asd_eval", "asd_oracle", "asd_bound_grad", "asd_set_budgets", "asd_solve_group", "asd_interval_bounds", "asd_profile_enable", "asd_profile_read",
+            "asd_eval", "asd_oracle", "asd_bound_grad", "asd_set_budgets", "asd_solve_group", "asd_solve_graph",
+            "asd_plan_autotune", "asd_plan_get_tuning", "asd_plan_set_tuning", "asd_interval_bounds", "asd_profile_enable", "asd_profile_read",
             "asd_last_error", "asd_abi_version"]
 
 
@@ -121,6 +127,10 @@ def lib():
     L.asd_oracle.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
     L.asd_bound_grad.argtypes = [vp, vp, C.POINTER(vp), C.POINTER(vp), vp, vp, vp]
     L.asd_set_budgets.argtypes = [vp, C.POINTER(i32), vp]
+    L.asd_solve_graph.argtypes = [vp, C.POINTER(Batch), vp, vp]
+    L.asd_plan_autotune.argtypes = [vp, i32, i32, vp]
+    L.asd_plan_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
+    L.asd_plan_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
     L.asd_solve_group.argtypes = [C.POINTER(vp), C.POINTER(C.POINTER(Batch)), C.POINTER(vp), i32, C.POINTER(vp)]
     L.asd_interval_bounds.argtypes = [vp, i32, vp, vp, C.POINTER(vp), C.POINTER(vp), vp]
     L.asd_profile_enable.argtypes = [vp, i32]
@@ -269,6 +279,26 @@ class Plan:
         _check(lib().asd_set_budgets(self.handle, arr, _stream(stream)))
         self.budgets = [int(b) for b in budgets]
 
+    def autotune(self, ktune: int = 2, reps: int = 5, stream=None):
+        """asd_plan_autotune (after init); returns the chosen tuning."""
+        _check(lib().asd_plan_autotune(self.handle, ktune, reps, _stream(stream)))
+        return self.tuning()
+
+    def tuning(self) -> Dict:
+        t = Tuning()
+        _check(lib().asd_plan_get_tuning(self.handle, C.byref(t)))
+        n = self.net.n
+        return {f: list(getattr(t, f))[:n] for f in ("ksplit", "fwd_mfma", "bwd_cb", "bwd_pos")}
+
+    def set_tuning(self, d: Dict):
+        t = Tuning()
+        _check(lib().asd_plan_get_tuning(self.handle, C.byref(t)))
+        for f, vals in d.items():
+            arr = getattr(t, f)
+            for i, v in enumerate(vals):
+                arr[i] = int(v)
+        _check(lib().asd_plan_set_tuning(self.handle, C.byref(t)))
+
     def as_iters(self) -> int:
         b = getattr(self, "budgets", None)
         return b[0] if b else self.params.as_iters
@@ -278,6 +308,24 @@ class Plan:
         self.run(ASD_PHASE_BIGM, 0, self.params.bigm_iters, stream)
         self.run(ASD_PHASE_AS, 0, self.as_iters(), stream)
         return self.bound(want_x0, stream)
+
+    def solve_graph(self, l0, u0, lhat, uhat, c, stream=None):
+        """asd_solve_graph: asd_solve with the iterations replayed from a HIP graph."""
+        lh = (C.c_void_p * max(1, len(lhat)))(*[_ptr(t) for t in lhat])
+        uh = (C.c_void_p * max(1, len(uhat)))(*[_ptr(t) for t in uhat])
+        b = Batch(self.S, _ptr(l0), _ptr(u0), C.cast(lh, C.POINTER(C.c_void_p)),
+                  C.cast(uh, C.POINTER(C.c_void_p)), _ptr(c))
+        self._keep = (l0, u0, list(lhat), list(uhat), c)
+        out = torch.empty(self.S, dtype=torch.float64, device="cuda")
+        # a graph is captured from a stream of its own (not the default stream)
+        cur = torch.cuda.current_stream() if stream is None else stream
+        if getattr(self, "_graph_stream", None) is None:
+            self._graph_stream = torch.cuda.Stream()
+        gs = self._graph_stream
+        gs.wait_stream(cur)
+        _check(lib().asd_solve_graph(self.handle, C.byref(b), out.data_ptr(), gs.cuda_stream))
+        cur.wait_stream(gs)
+        return out
 
     # -- state ---------------------------------------------------------------
     def _n(self, field, k):

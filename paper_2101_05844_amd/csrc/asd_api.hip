@@ -99,6 +99,10 @@ struct asd_plan {
     float* Wr[kMaxLayers + 1];        // [n_out][fanpad] (dense layers)
     int fanpad[kMaxLayers + 1];
     int ksplit[kMaxLayers + 1];       // dense forward: blocks over the fan-in
+    // kernel choices per layer (heuristic defaults, or asd_plan_autotune)
+    int fwd_mfma[kMaxLayers + 1];     // convolution forward with < 32 channels on the matrix cores
+    int bwd_cb[kMaxLayers + 1];       // column transposed convolution into layer k: channels per thread
+    int bwd_pos[kMaxLayers + 1];      // dense backward into layer k: positions on lanes
     float* Wb[kMaxLayers + 1];        // convolution: class weights of the transposed product
     int nkp[kMaxLayers + 1];
     void* part;                       // dense forward partial products
@@ -119,6 +123,10 @@ struct asd_plan {
     int* budgets_dev;                 // [S]
     void* lrs;                        // [S] learning rates of the current iteration (T)
     int Sa;                           // subproblems the current iteration updates (a prefix)
+    // captured iteration schedule (asd_solve_graph) and the host state it ends in
+    hipGraphExec_t graph_exec;
+    bool graph_valid;
+    int graph_end_masks, graph_end_step, graph_end_mask_step[kMaxMasks];
     // scalar state
     int n_masks;
     int step;
@@ -174,6 +182,8 @@ struct ProfScope {
 // ---------------------------------------------------------------------------
 // Workspace carving (two passes: measure, then assign).
 // ---------------------------------------------------------------------------
+constexpr int kMaxKsplit = 8;  // dense forward partial sums per output (the partial-sum buffer's size)
+
 struct Carver {
     char* base;
     size_t off;
@@ -251,7 +261,7 @@ void carve_t(asd_plan* P, Carver& cv) {
         if (g.kind == ASD_LAYER_DENSE) {
             P->Wr[L] = cv.take<float>((size_t)g.out.C * P->fanpad[L]);
             if (L < P->n)
-                part = std::max(part, (size_t)P->ksplit[L] * (1 + P->prm.max_masks) * P->Cpad[L] * S);
+                part = std::max(part, (size_t)kMaxKsplit * (1 + P->prm.max_masks) * P->Cpad[L] * S);
         }
     }
     P->part = cv.take<T>(part);
@@ -340,13 +350,16 @@ void setup_plan_geometry(asd_plan* P) {
             P->gpart_b = std::max(P->gpart_b, (size_t)P->gb_chunks[L] * g.out.C);
         }
         P->ksplit[L] = 1;
+        P->fwd_mfma[L] = 0;
+        P->bwd_cb[L - 1] = 0;
+        P->bwd_pos[L - 1] = 1;
         if (d.kind == ASD_LAYER_DENSE) {
             // about two waves per SIMD (2048 waves of KS per 32 x 32 tile), at
             // least 32 taps per wave, at most 8 partial sums per output
             const long tiles = (long)((S + 31) / 32) * (P->Cpad[L] / 32);
             const long want = (2048 / KS + tiles - 1) / tiles;
             const long cap = std::max(1L, std::min(8L, (long)(g.fan / (32 * KS))));
-            P->ksplit[L] = (int)std::max(1L, std::min(want, cap));
+            P->ksplit[L] = (int)std::max(1L, std::min(std::min(want, cap), (long)kMaxKsplit));
         }
     }
 }
@@ -510,7 +523,7 @@ asd_status prepare_weights(asd_plan* P, hipStream_t st) {
     }
 
 // Iteration forward pass of ReLU layer k with NM active masks.
-template <typename T, int NM>
+template <typename T, int NM, bool MB>
 asd_status fwd_fast_nm(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t st) {
     FastFwdArgs<T> a;
     memset(&a, 0, sizeof(a));
@@ -531,14 +544,14 @@ asd_status fwd_fast_nm(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t s
     const LayerGeo& g = a.g;
     constexpr int CB = sizeof(T) == 4 ? 8 : 4;
     ProfScope ps(P, st, ASD_K_FORWARD, k);
-    if (g.kind == ASD_LAYER_CONV2D && g.out.C < 32) {
+    if (g.kind == ASD_LAYER_CONV2D && g.out.C < 32 && !P->fwd_mfma[k]) {
         // narrow layer: a 32-row matrix tile would be half empty, and the
         // update's memory traffic bounds it anyway
         dim3 grid((unsigned)((g.out.cols + kWave - 1) / kWave), (unsigned)((g.out.C + CB - 1) / CB));
         if (g.ksz == 4)
-            hipLaunchKernelGGL((k_fwd_conv<T, NM, CB, 4>), grid, dim3(kWave, KS), 0, st, a);
+            hipLaunchKernelGGL((k_fwd_conv<T, NM, CB, 4, MB>), grid, dim3(kWave, KS), 0, st, a);
         else
-            hipLaunchKernelGGL((k_fwd_conv<T, NM, CB, 0>), grid, dim3(kWave, KS), 0, st, a);
+            hipLaunchKernelGGL((k_fwd_conv<T, NM, CB, 0, MB>), grid, dim3(kWave, KS), 0, st, a);
         LAUNCH_CHECK();
         return ASD_OK;
     }
@@ -546,8 +559,8 @@ asd_status fwd_fast_nm(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t s
         // one 32-column tile per block, its waves splitting the taps
         const long ntiles = (g.out.cols + 31) / 32;
         dim3 grid((unsigned)ntiles, (unsigned)(a.Cpad / 32));
-        if (g.ksz == 4) hipLaunchKernelGGL((k_fwd_conv_mfma<NM, true, 4>), grid, dim3(kWave, KS), 0, st, a);
-        else hipLaunchKernelGGL((k_fwd_conv_mfma<NM, true, 0>), grid, dim3(kWave, KS), 0, st, a);
+        if (g.ksz == 4) hipLaunchKernelGGL((k_fwd_conv_mfma<NM, true, 4, MB>), grid, dim3(kWave, KS), 0, st, a);
+        else hipLaunchKernelGGL((k_fwd_conv_mfma<NM, true, 0, MB>), grid, dim3(kWave, KS), 0, st, a);
         (void)CB;
         LAUNCH_CHECK();
         return ASD_OK;
@@ -555,7 +568,7 @@ asd_status fwd_fast_nm(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t s
     dim3 grid((unsigned)((P->Sa + 31) / 32), (unsigned)(a.Cpad / 32), (unsigned)a.ksplit);
     hipLaunchKernelGGL((k_fwd_dense_mfma<NM>), grid, dim3(kWave, KS), 0, st, a);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_fwd_dense_epi<T, NM>), dim3((unsigned)((P->Sa + 255) / 256), (unsigned)g.out.C), dim3(256),
+    hipLaunchKernelGGL((k_fwd_dense_epi<T, NM, MB>), dim3((unsigned)((P->Sa + 255) / 256), (unsigned)g.out.C), dim3(256),
                        0, st, a);
     LAUNCH_CHECK();
     return ASD_OK;
@@ -563,7 +576,14 @@ asd_status fwd_fast_nm(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t s
 
 template <typename T>
 asd_status fwd_fast(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t st) {
-#define ASD_FWD_CALL(N) return fwd_fast_nm<T, N>(P, k, sa, st)
+    if constexpr (sizeof(T) == 4) {
+        if (P->prm.precision == ASD_PREC_MIXED) {
+#define ASD_FWD_CALL(N) return fwd_fast_nm<T, N, true>(P, k, sa, st)
+            ASD_NM_DISPATCH(P->n_masks, ASD_FWD_CALL)
+#undef ASD_FWD_CALL
+        }
+    }
+#define ASD_FWD_CALL(N) return fwd_fast_nm<T, N, false>(P, k, sa, st)
     ASD_NM_DISPATCH(P->n_masks, ASD_FWD_CALL)
 #undef ASD_FWD_CALL
 }
@@ -641,7 +661,7 @@ asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
     }
     if (g.kind == ASD_LAYER_CONV2D) {
         // column kernel, the taps split over KS waves
-        const int CB = (sizeof(T) == 4 && L.C > 4) ? 8 : 4;
+        const int CB = (sizeof(T) == 4 && L.C > 4 && P->bwd_cb[k] != 4) ? 8 : 4;
         const int ksp = KS;
         const size_t dyn = (size_t)g.out.C * g.ksz * g.ksz * CB * sizeof(float);
         const size_t stat = (size_t)ksp * CB * kWave * sizeof(T);
@@ -668,7 +688,7 @@ asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
     }
     ProfScope ps(P, st, ASD_K_BACKWARD, k);
     constexpr int SB = sizeof(T) == 4 ? 8 : 4;
-    if (L.P % kWave == 0 && P->S >= SB) {
+    if (L.P % kWave == 0 && P->S >= SB && P->bwd_pos[k]) {
         dim3 grid((unsigned)(L.C * (L.P / kWave)), (unsigned)((P->Sa + SB - 1) / SB));
         hipLaunchKernelGGL((k_bwd_dense_pos<T, NM, SB>), grid, dim3(kWave, KS), 0, st, a);
     } else {
@@ -826,7 +846,6 @@ StepArgsT<T> make_step_args(const asd_plan* P, double lr) {
     };
     bc(P->step, &sa.bc1[0], &sa.bc2[0]);
     for (int q = 0; q < kMaxMasks; ++q) bc(q < P->n_masks ? P->mask_step[q] : 1, &sa.bc1[1 + q], &sa.bc2[1 + q]);
-    sa.mbf16 = P->prm.precision == ASD_PREC_MIXED;
     for (int g = 0; g < 1 + kMaxMasks; ++g) {
         const int stp = g == 0 ? P->step : (g - 1 < P->n_masks ? P->mask_step[g - 1] : 1);
         const int s1 = stp > 0 ? stp : 1;
@@ -1097,10 +1116,19 @@ bool is_moment(int field) {
 
 // Moment fields of a mixed-mode plan: BF16 in the plan, float for the caller.
 asd_status moment_bf16(asd_plan* P, int field, int k, int q, float* ext, int mode, hipStream_t st) {
-    uint16_t* arr = reinterpret_cast<uint16_t*>(field_ptr<float>(P, field, k, q));
+    // both moments live in the m array: m in the high half, v in the low half
+    int mfield = field, hi = 1;
+    switch (field) {
+        case ASD_F_ALPHA_V: mfield = ASD_F_ALPHA_M; hi = 0; break;
+        case ASD_F_BETA0_V: mfield = ASD_F_BETA0_M; hi = 0; break;
+        case ASD_F_BETA1_V: mfield = ASD_F_BETA1_M; hi = 0; break;
+        case ASD_F_MASK_V: mfield = ASD_F_MASK_M; hi = 0; break;
+        default: break;
+    }
+    uint32_t* arr = reinterpret_cast<uint32_t*>(field_ptr<float>(P, mfield, k, q));
     const NeuronLayout& nl = P->nl[k];
     dim3 grid((unsigned)((nl.cols + 255) / 256), (unsigned)nl.C);
-    hipLaunchKernelGGL(k_layout_bf16, grid, dim3(256), 0, st, arr, ext, nl, P->S, mode);
+    hipLaunchKernelGGL(k_layout_bf16, grid, dim3(256), 0, st, arr, ext, nl, P->S, mode, hi);
     LAUNCH_CHECK();
     return ASD_OK;
 }
@@ -1191,6 +1219,97 @@ asd_status oracle_t(asd_plan* P, int k, const T* x_prev, const T* z, uint32_t* b
     hipLaunchKernelGGL(k_oracle<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
     LAUNCH_CHECK();
     return ASD_OK;
+}
+
+// Autotuning: each kernel choice of the FP32 iteration is timed alone on the
+// loaded batch, with the plain rule at step size 0 so that no dual or moment
+// changes (the backward kernels rewrite x* and its bits, which every
+// iteration recomputes), and with `ktune` empty mask slots active (their
+// multipliers are zero, so the products are those of K masks).
+template <typename T>
+asd_status autotune_t(asd_plan* P, int ktune, int reps, hipStream_t st) {
+    const int nm0 = P->n_masks;
+    const int rule0 = P->prm.rule;
+    P->n_masks = ktune;
+    P->prm.rule = ASD_RULE_SUPERGRADIENT;
+    StepArgsT<T> sa = make_step_args<T>(P, 0.0);
+    struct Restore {
+        asd_plan* P;
+        int nm, rule;
+        ~Restore() {
+            P->n_masks = nm;
+            P->prm.rule = rule;
+        }
+    } restore{P, nm0, rule0};
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    asd_status err = ASD_OK;
+    auto timed = [&](auto&& launch) -> float {
+        if (err != ASD_OK) return 1e30f;
+        asd_status r = launch();  // warm
+        for (int i = 0; i < reps && r == ASD_OK; ++i) {
+            if (i == 0 && hipEventRecord(e0, st) != hipSuccess) r = fail(ASD_EDEVICE, "hipEventRecord failed");
+            if (r == ASD_OK) r = launch();
+        }
+        float ms = 1e30f;
+        if (r == ASD_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            r = fail(ASD_EDEVICE, "event timing failed");
+        if (r != ASD_OK) err = r;
+        return ms;
+    };
+    // every iterate's x* must exist before the forward kernels run
+    for (int k = P->n - 1; k >= 0 && err == ASD_OK; --k) err = bwd_fast<T>(P, k, st);
+    for (int L = 1; L <= P->n && err == ASD_OK; ++L) {
+        const LayerGeo& g = P->geo[L];
+        if (L < P->n && g.kind == ASD_LAYER_DENSE) {
+            const long cap = std::max(1L, std::min((long)kMaxKsplit, (long)(g.fan / (32 * KS))));
+            int best = P->ksplit[L];
+            float tbest = 1e30f;
+            for (int ks = 1; ks <= cap; ks *= 2) {
+                P->ksplit[L] = ks;
+                const float t = timed([&] { return fwd_fast<T>(P, L, sa, st); });
+                if (t < tbest) tbest = t, best = ks;
+            }
+            P->ksplit[L] = best;
+        }
+        if (L < P->n && g.kind == ASD_LAYER_CONV2D && g.out.C < 32) {
+            float tb[2];
+            for (int m = 0; m < 2; ++m) {
+                P->fwd_mfma[L] = m;
+                tb[m] = timed([&] { return fwd_fast<T>(P, L, sa, st); });
+            }
+            P->fwd_mfma[L] = tb[1] < tb[0];
+        }
+        const int k = L - 1;  // backward into neuron layer k through layer L
+        const NeuronLayout& In = g.in;
+        if (g.kind == ASD_LAYER_CONV2D && !(In.P % kWave == 0 && In.C >= 16) && In.C > 4) {
+            float tb[2];
+            const int cand[2] = {4, 8};
+            for (int m = 0; m < 2; ++m) {
+                P->bwd_cb[k] = cand[m];
+                tb[m] = timed([&] { return bwd_fast<T>(P, k, st); });
+            }
+            P->bwd_cb[k] = tb[0] < tb[1] ? 4 : 8;
+        }
+        if (g.kind == ASD_LAYER_DENSE && In.P % kWave == 0 && P->S >= 8) {
+            float tb[2];
+            for (int m = 0; m < 2; ++m) {
+                P->bwd_pos[k] = m;
+                tb[m] = timed([&] { return bwd_fast<T>(P, k, st); });
+            }
+            P->bwd_pos[k] = tb[1] <= tb[0];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return err;
+}
+
+void invalidate_graph(asd_plan* P) {
+    if (P->graph_valid) (void)hipGraphExecDestroy(P->graph_exec);
+    P->graph_valid = false;
 }
 
 // Active Set iterations of the plan: the largest budget, or the schedule's T.
@@ -1317,8 +1436,52 @@ asd_status asd_plan_create(const asd_net* net, int32_t S, const asd_params* para
 
 void asd_plan_destroy(asd_plan* plan) {
     if (!plan) return;
+    invalidate_graph(plan);
     for (hipEvent_t e : plan->prof_pool) (void)hipEventDestroy(e);
     delete plan;
+}
+
+asd_status asd_plan_autotune(asd_plan* P, int32_t ktune, int32_t reps, hipStream_t st) {
+    if (!P) return fail(ASD_EINVAL, "NULL plan");
+    if (!P->loaded) return fail(ASD_EINVAL, "asd_init has not been called");
+    if (ktune < 0 || ktune > P->prm.max_masks) return fail(ASD_EINVAL, "ktune %d outside [0, %d]", ktune, P->prm.max_masks);
+    if (reps < 1) return fail(ASD_EINVAL, "reps must be >= 1");
+    if (is64(P)) return ASD_OK;  // FP64 plans run the general kernels only
+    if (P->n_masks > ktune) return fail(ASD_EINVAL, "the plan already has %d masks (> ktune)", P->n_masks);
+    invalidate_graph(P);
+    return autotune_t<float>(P, ktune, reps, st);
+}
+
+asd_status asd_plan_get_tuning(const asd_plan* P, asd_tuning* out) {
+    if (!P || !out) return fail(ASD_EINVAL, "NULL argument");
+    memset(out, 0, sizeof(*out));
+    for (int L = 1; L <= P->n; ++L) {
+        out->ksplit[L - 1] = P->ksplit[L];
+        out->fwd_mfma[L - 1] = P->fwd_mfma[L];
+        out->bwd_cb[L - 1] = P->bwd_cb[L - 1];
+        out->bwd_pos[L - 1] = P->bwd_pos[L - 1];
+    }
+    return ASD_OK;
+}
+
+asd_status asd_plan_set_tuning(asd_plan* P, const asd_tuning* in) {
+    if (!P || !in) return fail(ASD_EINVAL, "NULL argument");
+    for (int L = 1; L <= P->n; ++L) {
+        if (in->ksplit[L - 1] < 1 || in->ksplit[L - 1] > kMaxKsplit)
+            return fail(ASD_EINVAL, "ksplit of layer %d is %d, outside [1, %d]", L, in->ksplit[L - 1], kMaxKsplit);
+        if (in->fwd_mfma[L - 1] != 0 && in->fwd_mfma[L - 1] != 1) return fail(ASD_EINVAL, "fwd_mfma must be 0 or 1");
+        const int cb = in->bwd_cb[L - 1];
+        if (cb != 0 && cb != 4 && cb != 8) return fail(ASD_EINVAL, "bwd_cb must be 0, 4 or 8");
+        if (in->bwd_pos[L - 1] != 0 && in->bwd_pos[L - 1] != 1) return fail(ASD_EINVAL, "bwd_pos must be 0 or 1");
+    }
+    invalidate_graph(P);
+    for (int L = 1; L <= P->n; ++L) {
+        P->ksplit[L] = in->ksplit[L - 1];
+        P->fwd_mfma[L] = in->fwd_mfma[L - 1];
+        P->bwd_cb[L - 1] = in->bwd_cb[L - 1];
+        P->bwd_pos[L - 1] = in->bwd_pos[L - 1];
+    }
+    return ASD_OK;
 }
 
 asd_status asd_profile_enable(asd_plan* P, int32_t enable) {
@@ -1398,6 +1561,7 @@ asd_status asd_bound_grad(asd_plan* P, const double* gs, double* const* dW, doub
 asd_status asd_set_budgets(asd_plan* P, const int32_t* budgets, hipStream_t st) {
     if (!P) return fail(ASD_EINVAL, "NULL plan");
     if (!budgets) {
+        invalidate_graph(P);
         P->ragged = false;
         P->budgets.clear();
         return ASD_OK;
@@ -1408,6 +1572,7 @@ asd_status asd_set_budgets(asd_plan* P, const int32_t* budgets, hipStream_t st) 
             return fail(ASD_EINVAL, "budgets must be non-increasing (subproblem %d: %d after %d)", s, budgets[s],
                         budgets[s - 1]);
     }
+    invalidate_graph(P);
     P->budgets.assign(budgets, budgets + P->S);
     HIP_TRY(hipMemcpyAsync(P->budgets_dev, P->budgets.data(), sizeof(int) * P->S, hipMemcpyHostToDevice, st));
     // a later call may replace the host copy: finish this one first
@@ -1421,6 +1586,38 @@ asd_status asd_solve(asd_plan* P, const asd_batch* b, double* out_lb, float* x0,
     TRY(asd_run(P, ASD_PHASE_BIGM, 0, P->prm.bigm_iters, st));
     TRY(asd_run(P, ASD_PHASE_AS, 0, as_iters_of(P), st));
     return asd_bound(P, out_lb, x0, st);
+}
+
+asd_status asd_solve_graph(asd_plan* P, const asd_batch* b, double* out_lb, hipStream_t st) {
+    if (!P || !b || !out_lb) return fail(ASD_EINVAL, "NULL argument");
+    if (P->prof) return fail(ASD_EINVAL, "kernel profiling is on; it cannot run inside a captured graph");
+    TRY(asd_init(P, b, st));
+    if (!P->graph_valid) {
+        // capture the iterations (kernels only: fills and copies inside them
+        // are kernels too); the host state advances as the capture proceeds
+        HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        asd_status r = asd_run(P, ASD_PHASE_BIGM, 0, P->prm.bigm_iters, st);
+        if (r == ASD_OK) r = asd_run(P, ASD_PHASE_AS, 0, as_iters_of(P), st);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(st, &graph);
+        if (r != ASD_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return r;
+        }
+        if (e != hipSuccess) return fail(ASD_EDEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+        const hipError_t ei = hipGraphInstantiate(&P->graph_exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) return fail(ASD_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(ei));
+        P->graph_valid = true;
+        P->graph_end_masks = P->n_masks;
+        P->graph_end_step = P->step;
+        for (int q = 0; q < kMaxMasks; ++q) P->graph_end_mask_step[q] = P->mask_step[q];
+    }
+    HIP_TRY(hipGraphLaunch(P->graph_exec, st));
+    P->n_masks = P->graph_end_masks;
+    P->step = P->graph_end_step;
+    for (int q = 0; q < kMaxMasks; ++q) P->mask_step[q] = P->graph_end_mask_step[q];
+    return asd_bound(P, out_lb, nullptr, st);
 }
 
 asd_status asd_solve_group(asd_plan* const* plans, const asd_batch* const* batches, double* const* out_lb,

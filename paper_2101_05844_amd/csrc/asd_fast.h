@@ -132,39 +132,40 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
 }
 __device__ __forceinline__ float bf16_val(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-template <typename T>
-__device__ __forceinline__ T load_moment(const T* p, uint32_t idx, bool bf16) {
-    if constexpr (sizeof(T) == 4) {
-        if (bf16) return bf16_val(reinterpret_cast<const uint16_t*>(p)[idx]);
-    }
-    return p[idx];
+// Mixed mode (MB): the two Adam moments of a multiplier share one 32-bit
+// word of the m array, m in the high and v in the low 16 bits, each BF16;
+// the v array is unused.
+__device__ __forceinline__ void load_moments_bf16(const float* pm, uint32_t idx, float& m, float& v) {
+    const uint32_t w = reinterpret_cast<const uint32_t*>(pm)[idx];
+    m = __uint_as_float(w & 0xffff0000u);
+    v = __uint_as_float(w << 16);
 }
-template <typename T>
-__device__ __forceinline__ void store_moment(T* p, uint32_t idx, T v, bool bf16) {
-    if constexpr (sizeof(T) == 4) {
-        if (bf16) {
-            reinterpret_cast<uint16_t*>(p)[idx] = bf16_rne(v);
-            return;
-        }
-    }
-    p[idx] = v;
+__device__ __forceinline__ void store_moments_bf16(float* pm, uint32_t idx, float m, float v) {
+    reinterpret_cast<uint32_t*>(pm)[idx] = ((uint32_t)bf16_rne(m) << 16) | (uint32_t)bf16_rne(v);
 }
 
-// Moment arrays of the mixed mode <-> caller [S][N] floats (mode 0: set,
-// rounding to BF16; mode 2: get).
-__global__ void k_layout_bf16(uint16_t* in_arr, float* ex_arr, NeuronLayout nl, int S, int mode) {
+// One moment of the mixed mode (the high half of each packed word for m,
+// hi = 1; the low half for v) <-> caller [S][N] floats (mode 0: set, rounding
+// to BF16 and keeping the other half; mode 2: get).
+__global__ void k_layout_bf16(uint32_t* in_arr, float* ex_arr, NeuronLayout nl, int S, int mode, int hi) {
     const long col = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
     if (col >= nl.cols) return;
     const int s = (int)(col / nl.P), p = (int)(col - (long)s * nl.P);
     const long in_ = ((long)c * S + s) * nl.P + p;
     const long ex = (long)s * nl.N + (long)c * nl.P + p;
-    if (mode == 0) in_arr[in_] = bf16_rne(ex_arr[ex]);
-    else ex_arr[ex] = bf16_val(in_arr[in_]);
+    const uint32_t w = in_arr[in_];
+    if (mode == 0) {
+        const uint32_t h = bf16_rne(ex_arr[ex]);
+        in_arr[in_] = hi ? ((w & 0x0000ffffu) | (h << 16)) : ((w & 0xffff0000u) | h);
+    } else {
+        ex_arr[ex] = bf16_val((uint16_t)(hi ? (w >> 16) : (w & 0xffffu)));
+    }
 }
 
-template <typename T, int NM>
+template <typename T, int NM, bool MB>
 __device__ __forceinline__ void fwd_load(const FastFwdArgs<T>& A, int c, uint32_t idx, uint32_t bi, FwdIn<T, NM>& in) {
+    static_assert(!MB || sizeof(T) == 4, "BF16 moments go with FP32 duals");
     __builtin_assume(idx < (1u << 30));  // byte offsets fit 32 bits (checked at plan creation)
     const cptr_t<ReluLayerT<T>> R = kconst_t(A.R);
     const bool adam = A.st.rule != ASD_RULE_SUPERGRADIENT;
@@ -179,14 +180,19 @@ __device__ __forceinline__ void fwd_load(const FastFwdArgs<T>& A, int c, uint32_
     for (int j = 0; j < 3; ++j) in.m[j] = in.v[j] = (T)0;
 #pragma unroll
     for (int q = 0; q < (NM > 0 ? NM : 1); ++q) in.mq[q] = in.vq[q] = (T)0;
-    const bool hb = A.st.mbf16 != 0;
     if (adam) {
-        in.m[0] = load_moment(R->alpha_m, idx, hb);
-        in.v[0] = load_moment(R->alpha_v, idx, hb);
-        in.m[1] = load_moment(R->beta0_m, idx, hb);
-        in.v[1] = load_moment(R->beta0_v, idx, hb);
-        in.m[2] = load_moment(R->beta1_m, idx, hb);
-        in.v[2] = load_moment(R->beta1_v, idx, hb);
+        if constexpr (MB) {
+            load_moments_bf16(R->alpha_m, idx, in.m[0], in.v[0]);
+            load_moments_bf16(R->beta0_m, idx, in.m[1], in.v[1]);
+            load_moments_bf16(R->beta1_m, idx, in.m[2], in.v[2]);
+        } else {
+            in.m[0] = R->alpha_m[idx];
+            in.v[0] = R->alpha_v[idx];
+            in.m[1] = R->beta0_m[idx];
+            in.v[1] = R->beta0_v[idx];
+            in.m[2] = R->beta1_m[idx];
+            in.v[2] = R->beta1_v[idx];
+        }
     }
     in.zq = NM > 0 ? (unsigned)R->zpk[idx] : 0u;
 #pragma unroll
@@ -196,8 +202,12 @@ __device__ __forceinline__ void fwd_load(const FastFwdArgs<T>& A, int c, uint32_
         in.UI[q] = M->UI[idx];
         in.bq[q] = M->beta[idx];
         if (adam) {
-            in.mq[q] = load_moment(M->m, idx, hb);
-            in.vq[q] = load_moment(M->v, idx, hb);
+            if constexpr (MB) {
+                load_moments_bf16(M->m, idx, in.mq[q], in.vq[q]);
+            } else {
+                in.mq[q] = M->m[idx];
+                in.vq[q] = M->v[idx];
+            }
         }
     }
 }
@@ -205,7 +215,7 @@ __device__ __forceinline__ void fwd_load(const FastFwdArgs<T>& A, int c, uint32_
 // Supergradient eq:as-supergradient from the products yd = (W x)[i] and
 // ym[q] = (|W| (sigma_q . x))[i] + 2 (W+ x_point)[i], the projected step, the
 // derived sums own, g, vs, u_q; stores only.
-template <typename T, int NM>
+template <typename T, int NM, bool MB>
 __device__ __forceinline__ void fwd_store(const FastFwdArgs<T>& A, uint32_t idx, int s, const FwdIn<T, NM>& in, T yd,
                                           const T* ym) {
     __builtin_assume(idx < (1u << 30));
@@ -226,8 +236,12 @@ __device__ __forceinline__ void fwd_store(const FastFwdArgs<T>& A, uint32_t idx,
         const T c1 = st.lrs ? lr_s * st.ib1[grp] : st.c1[grp];
         const T mm = st.b1 * m + ((T)1 - st.b1) * g;
         const T vv = st.b2 * v + ((T)1 - st.b2) * g * g;
-        store_moment(mo, idx, mm, st.mbf16 != 0);
-        store_moment(vo, idx, vv, st.mbf16 != 0);
+        if constexpr (MB) {
+            store_moments_bf16(mo, idx, mm, vv);
+        } else {
+            mo[idx] = mm;
+            vo[idx] = vv;
+        }
         if constexpr (sizeof(T) == 4) {
             const float den = __builtin_amdgcn_sqrtf(vv * st.ib2[grp]) + st.eps;
             return tmax0(th + c1 * mm * __builtin_amdgcn_rcpf(den));
@@ -262,19 +276,19 @@ __device__ __forceinline__ void fwd_store(const FastFwdArgs<T>& A, uint32_t idx,
     R->vs[idx] = vs;
 }
 
-template <typename T, int NM>
+template <typename T, int NM, bool MB>
 __device__ __forceinline__ void fwd_update(const FastFwdArgs<T>& A, int c, uint32_t idx, int s, uint32_t bi, T yd,
                                            const T* ym) {
     FwdIn<T, NM> in;
-    fwd_load<T, NM>(A, c, idx, bi, in);
-    fwd_store<T, NM>(A, idx, s, in, yd, ym);
+    fwd_load<T, NM, MB>(A, c, idx, bi, in);
+    fwd_store<T, NM, MB>(A, idx, s, in, yd, ym);
 }
 
 // ---------------------------------------------------------------------------
 // Forward pass of a convolutional ReLU layer k (column mapping).
 // Grid (colpad_k / 64, ceil(C_k / CB)), block (64, KS).
 // ---------------------------------------------------------------------------
-template <typename T, int NM, int CB, int KSZ>
+template <typename T, int NM, int CB, int KSZ, bool MB>
 __global__ void __launch_bounds__(kWave * KS) k_fwd_conv(FastFwdArgs<T> A) {
     static_assert(CB % KS == 0, "CB must be a multiple of KS");
     constexpr int EPW = CB / KS;  // epilogue channels per wave
@@ -399,7 +413,7 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_conv(FastFwdArgs<T> A) {
 #pragma unroll
     for (int j = 0; j < EPW; ++j) {  // loads of every neuron first
         const int c = min(c0 + wave * EPW + j, g.out.C - 1);
-        fwd_load<T, NM>(A, c, ((long)c * S + s) * g.out.P + p, (long)c * g.out.colpad + col, in[j]);
+        fwd_load<T, NM, MB>(A, c, ((long)c * S + s) * g.out.P + p, (long)c * g.out.colpad + col, in[j]);
     }
 #pragma unroll
     for (int j = 0; j < EPW; ++j) {
@@ -408,7 +422,7 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_conv(FastFwdArgs<T> A) {
         T ymj[NA];
 #pragma unroll
         for (int q = 0; q < NM; ++q) ymj[q] = tot[1 + q][j];
-        fwd_store<T, NM>(A, ((long)c * S + s) * g.out.P + p, s, in[j], tot[0][j], ymj);
+        fwd_store<T, NM, MB>(A, ((long)c * S + s) * g.out.P + p, s, in[j], tot[0][j], ymj);
     }
 }
 
@@ -538,7 +552,7 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_dense_mfma(FastFwdArgs<float
 // register's state access is two 128-byte runs.
 // Grid (column tiles / (SPLITK ? 1 : KS), Cpad / 32), block (64, KS).
 // ---------------------------------------------------------------------------
-template <int NM, bool SPLITK, int KSZ>
+template <int NM, bool SPLITK, int KSZ, bool MB>
 __global__ void __launch_bounds__(kWave * KS) k_fwd_conv_mfma(FastFwdArgs<float> A) {
     constexpr int U = 4;  // steps of 2 taps per trip
     __shared__ float red[SPLITK ? KS : 1][16][kWave];
@@ -663,7 +677,7 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_conv_mfma(FastFwdArgs<float>
             const int ii = b0 + jb;
             const int i = SPLITK ? wave * NR + ii : ii;
             const int c = min(m0 + 8 * (i / 4) + 4 * half + (i % 4), g.out.C - 1);
-            fwd_load<float, NM>(A, c, (long)c * S * g.out.P + col, (long)c * g.out.colpad + col, in[jb]);
+            fwd_load<float, NM, MB>(A, c, (long)c * S * g.out.P + col, (long)c * g.out.colpad + col, in[jb]);
         }
 #pragma unroll
         for (int jb = 0; jb < NB; ++jb) {
@@ -674,14 +688,14 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_conv_mfma(FastFwdArgs<float>
             float ym[NM > 0 ? NM : 1];
 #pragma unroll
             for (int q = 0; q < NM; ++q) ym[q] = tot[1 + q][ii];
-            fwd_store<float, NM>(A, (long)c * S * g.out.P + col, s, in[jb], tot[0][ii], ym);
+            fwd_store<float, NM, MB>(A, (long)c * S * g.out.P + col, s, in[jb], tot[0][ii], ym);
         }
     }
 }
 
 // Sums the partial products in a fixed order and updates.  Grid
 // (ceil(S / 256), C_k), block 256.
-template <typename T, int NM>
+template <typename T, int NM, bool MB>
 __global__ void __launch_bounds__(256) k_fwd_dense_epi(FastFwdArgs<T> A) {
     constexpr int NA = NM > 0 ? NM : 1;
     const int s = blockIdx.x * 256 + threadIdx.x;
@@ -700,7 +714,7 @@ __global__ void __launch_bounds__(256) k_fwd_dense_epi(FastFwdArgs<T> A) {
     }
     const long idx = (long)c * S + s;  // dense layout, P = 1
     const long bi = (long)c * A.g.out.colpad + s;
-    fwd_update<T, NM>(A, c, idx, s, bi, yd, ym);
+    fwd_update<T, NM, MB>(A, c, idx, s, bi, yd, ym);
 }
 
 // ---------------------------------------------------------------------------

@@ -65,7 +65,7 @@ template <typename T>
 struct ReluLayerT {
     T* lhat; T* uhat;             // pre-activation bounds
     T* alpha; T* beta0; T* beta1;
-    T* alpha_m; T* alpha_v;       // Adam moments (BF16 in the low half in the mixed mode)
+    T* alpha_m; T* alpha_v;       // Adam moments (mixed mode: both as BF16 in one word of the m array)
     T* beta0_m; T* beta0_v;
     T* beta1_m; T* beta1_v;
     T* own;   // derived: alpha - beta0 - beta1 - sum_I beta_I
@@ -100,7 +100,6 @@ struct StepArgsT {
     T bc2[1 + kMaxMasks];
     T c1[1 + kMaxMasks];    // lr / (1 - b1^step)  (rounded once, on the host)
     T ib2[1 + kMaxMasks];   // 1 / (1 - b2^step)
-    int mbf16;              // moments stored as BF16 (the low half of each moment array)
     // per-subproblem learning rates (subproblems with their own iteration
     // budget, each on its own schedule), or null: then lr / c1 apply to all
     const T* lrs;

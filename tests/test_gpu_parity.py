@@ -294,7 +294,7 @@ def test_iteration_windows_match_oracle(wi, rule, prec):
         lb = out.cpu().numpy()
         for s, (p, e) in enumerate(zip(probs, ends)):
             d_ora = O.evaluate(p, e)[0]
-            assert abs(lb[s] - d_ora) <= tol * max(1.0, abs(d_ora)), (ph, t, s, lb[s], d_ora)
+            bad_before = n_bad
             if loose:
                 st0 = sts[s]
                 _, x0, z0, _, _ = O.evaluate(p, st0)
@@ -333,10 +333,20 @@ def test_iteration_windows_match_oracle(wi, rule, prec):
                         else:
                             fm, fv, q = A.ASD_F_MASK_M, A.ASD_F_MASK_V, j - 3
                             om, ov = e.masks[k - 1][q].m, e.masks[k - 1][q].v
-                        for fld, ref in ((fm, om), (fv, ov)):
+                        # one bfloat16 spacing, plus what the FP32 rounding of the
+                        # supergradient (eps * scale) moves the updated moment by
+                        dg = eps * scale
+                        b1, b2 = prm.adam.beta1, prm.adam.beta2
+                        for fld, ref, extra in ((fm, om, (1 - b1) * dg),
+                                                (fv, ov, (1 - b2) * (2 * np.abs(grads[j]) + dg) * dg)):
                             got = moments[(fld, k, q)][s]
-                            close = np.abs(got - ref) <= 2.0 ** -7 * np.abs(ref) + 1e-30
-                            assert np.all(close | ~ok), (ph, t, s, k, name, fld)
+                            close = np.abs(got - ref) <= 2.0 ** -7 * np.abs(ref) + extra
+                            assert np.all(close | ~ok), (ph, t, s, k, name, fld,
+                                                         np.flatnonzero(~(close | ~ok))[:3])
+            # the bound is a function of the duals: compared where every dual
+            # matched (a tie entry allowed to differ above moves it further)
+            if n_bad == bad_before:
+                assert abs(lb[s] - d_ora) <= tol * max(1.0, abs(d_ora)), (ph, t, s, lb[s], d_ora)
     print(f"{n_bad} of {n_ent} entries differ (ties under Adam's normalised step)" if loose else "", flush=True)
 
 
@@ -563,3 +573,127 @@ def test_solve_group_matches_separate_solves():
     torch.cuda.synchronize()
     for a, b in zip(outs, outs_sep):
         assert np.array_equal(a.cpu().numpy(), b)
+
+
+def _tuning_alternatives(A, plan):
+    """Every single-choice deviation from the plan's default tuning that
+    changes a kernel for this net."""
+    base = plan.tuning()
+    alts = []
+    n = plan.net.n
+    for L in range(1, n):
+        Ly = plan.net.layers[L - 1]
+        if Ly.kind == "dense":
+            cap = max(1, min(8, Ly.spec.n_in // 128))
+            ks = 1
+            while ks <= cap:
+                if ks != base["ksplit"][L - 1]:
+                    alts.append(("ksplit", L - 1, ks))
+                ks *= 2
+        elif Ly.spec.c_out < 32:
+            alts.append(("fwd_mfma", L - 1, 1 - base["fwd_mfma"][L - 1]))
+    for L in range(1, n + 1):
+        Ly = plan.net.layers[L - 1]
+        k = L - 1
+        if Ly.kind == "conv":
+            sp = Ly.spec
+            if not ((sp.h_in * sp.w_in) % 64 == 0 and sp.c_in >= 16) and sp.c_in > 4:
+                alts.append(("bwd_cb", k, 4 if base["bwd_cb"][k] != 4 else 8))
+        else:
+            n_in = Ly.spec.n_in
+            prev = plan.net.layers[L - 2] if L >= 2 else None
+            P_in = prev.spec.h_out * prev.spec.w_out if prev is not None and prev.kind == "conv" else 1
+            if P_in % 64 == 0:
+                alts.append(("bwd_pos", k, 1 - base["bwd_pos"][k]))
+    return base, alts
+
+
+@pytest.mark.parametrize("wi", [1, 2])
+def test_tuning_alternatives_match_oracle(wi):
+    """Each kernel alternative the autotuner may pick (dense forward split
+    counts, narrow convolution forward on the matrix cores, channels per
+    thread of the column transposed convolution, dense backward with
+    positions on lanes), one FP32 iteration under the plain rule from two
+    oracle snapshots (with and without masks): duals within 1e-5."""
+    w = workloads_small()[wi]
+    A = _A()
+    prm = O.params_from_schedule(w.schedule)
+    prm.rule = "sgd"
+    prm.bigm_lr, prm.as_lr = (1e-3, 1e-4), (1e-4, 1e-5)
+    params = A.params_from_schedule(w.schedule, A.ASD_PREC_FP32)
+    params.rule = A.ASD_RULE_SUPERGRADIENT
+    params.bigm_lr0, params.bigm_lr1, params.as_lr0, params.as_lr1 = 1e-3, 1e-4, 1e-4, 1e-5
+    A, ops, probs, net, plan, _ = _setup(w, params)
+    base, alts = _tuning_alternatives(A, plan)
+    assert alts, "no kernel alternative on this net"
+    starts = [("bigm", 3), ("as", 4)]
+    want = set(starts) | {(ph, t + 1) for ph, t in starts}
+    runs = [O.solve(p, prm, snapshot_at=sorted(want, key=str)) for p in probs]
+    for field, idx, val in alts:
+        tun = {f: list(v) for f, v in base.items()}
+        tun[field][idx] = val
+        plan.set_tuning(tun)
+        for ph, t in starts:
+            H.import_states(plan, probs, [r.snapshots[(ph, t)] for r in runs])
+            plan.run(A.ASD_PHASE_BIGM if ph == "bigm" else A.ASD_PHASE_AS, t, 1)
+            torch.cuda.synchronize()
+            K = plan.counts().n_masks
+            duals = H.export_duals(plan, len(ops), K)
+            for s, r in enumerate(runs):
+                e = r.snapshots[(ph, t + 1)]
+                for k in range(1, len(ops)):
+                    pairs = [(duals[("alpha", k)][s], e.alpha[k - 1]), (duals[("beta1", k)][s], e.beta1[k - 1])]
+                    pairs += [(duals[("mask", k, q)][s], e.masks[k - 1][q].beta) for q in range(K)]
+                    for a, b in pairs:
+                        assert np.all(np.abs(a - b) <= 1e-5 * (1 + np.abs(b))), (field, idx, val, ph, t, s, k)
+    plan.set_tuning(base)
+
+
+def test_autotune_keeps_state():
+    """asd_plan_autotune times the kernels without changing the state: the
+    bound and every dual and moment are bit-identical before and after, and
+    the chosen tuning is one of the valid ones."""
+    w = workloads_small()[2]
+    A, ops, probs, net, plan, _ = _setup(w, prec="fp32")
+    rng = np.random.default_rng(90)
+    states = [H.random_integral_state(p, rng, 2, scale=0.5) for p in probs]
+    H.import_states(plan, probs, states)
+    before = plan.bound().cpu().numpy()
+    d0 = H.export_duals(plan, len(ops), 2)
+    m0 = plan.get(A.ASD_F_ALPHA_M, 1).cpu().numpy()
+    tun = plan.autotune(ktune=2, reps=2)
+    after = plan.bound().cpu().numpy()
+    d1 = H.export_duals(plan, len(ops), 2)
+    assert np.array_equal(before, after)
+    assert all(np.array_equal(d0[key], d1[key]) for key in d0)
+    assert np.array_equal(m0, plan.get(A.ASD_F_ALPHA_M, 1).cpu().numpy())
+    assert plan.counts().n_masks == 2
+    assert all(1 <= v <= 8 for v in tun["ksplit"])
+    print("tuning", tun, flush=True)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_solve_graph_replays_match_eager(prec):
+    """asd_solve_graph: the captured iteration schedule, replayed three times
+    with eager work between the replays, on the batch it was captured with
+    and on another batch of the same size, and recaptured after budgets are
+    set: every result equals the eager asd_solve bit for bit."""
+    w = workloads_small()[2]
+    A, ops, probs, net, plan, batch = _setup(w, prec=prec)
+    lb_e = plan.solve(*batch).cpu().numpy()
+    for rep in range(3):
+        lb_g = plan.solve_graph(*batch)
+        torch.cuda.synchronize()
+        assert np.array_equal(lb_g.cpu().numpy(), lb_e), rep
+        plan.eval()                       # eager work between replays
+        torch.cuda.synchronize()
+    l0, u0, lht, uht, c = batch
+    mid, rad = (l0 + u0) / 2, (u0 - l0) / 4   # a smaller box: the bounds stay valid
+    batch2 = ((mid - rad).contiguous(), (mid + rad).contiguous(), lht, uht, c)
+    lb2_e = plan.solve(*batch2).cpu().numpy()
+    lb2_g = plan.solve_graph(*batch2).cpu().numpy()
+    assert np.array_equal(lb2_g, lb2_e)
+    plan.set_budgets(_ragged_budgets(w, 81))
+    lb3_e = plan.solve(*batch).cpu().numpy()
+    lb3_g = plan.solve_graph(*batch).cpu().numpy()
+    assert np.array_equal(lb3_g, lb3_e)

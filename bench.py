@@ -24,15 +24,17 @@ METRIC = "subproblem-iterations/sec, Active Set dual on CIFAR conv net; % HBM ro
 HBM_PEAK_GBS = 8000.0
 
 
-def per_layer_state_bytes(n_k, n_prev, K):
+def per_layer_state_bytes(n_k, n_prev, K, mixed=False):
     """Algorithmic bytes the update of one ReLU layer must move per
     subproblem-iteration: duals and Adam moments read and written (24 B per
-    multiplier), pre-activation bounds (8 B), LI/UI per mask (8 B), compact
-    mask bits (z bits of the layer, x bits of the layer before)."""
-    return 24 * (3 + K) * n_k + 8 * n_k + 8 * K * n_k + K * (n_k + n_prev) / 8.0
+    multiplier; 16 B with both moments in one BF16 word), pre-activation
+    bounds (8 B), LI/UI per mask (8 B), compact mask bits (z bits of the
+    layer, x bits of the layer before)."""
+    per_mult = 16 if mixed else 24
+    return per_mult * (3 + K) * n_k + 8 * n_k + 8 * K * n_k + K * (n_k + n_prev) / 8.0
 
 
-def kernel_unit_bytes(role, layer, sizes, K):
+def kernel_unit_bytes(role, layer, sizes, K, mixed=False):
     """Algorithmic bytes per subproblem of one launch of an iteration kernel.
 
     forward k (update of ReLU layer k): the layer's state (per_layer_state_bytes)
@@ -42,7 +44,7 @@ def kernel_unit_bytes(role, layer, sizes, K):
     inputs, whose operand is the objective row), the box of layer k (8 B) and
     x*_k written (4 B)."""
     if role == "forward":
-        return per_layer_state_bytes(sizes[layer], sizes[layer - 1], K) + 4 * (sizes[layer] + sizes[layer - 1])
+        return per_layer_state_bytes(sizes[layer], sizes[layer - 1], K, mixed) + 4 * (sizes[layer] + sizes[layer - 1])
     if role == "backward":
         nxt = sizes[layer + 1]
         kk = K if layer + 1 < len(sizes) - 1 else 0
@@ -101,6 +103,30 @@ def masks_at(t, sched):
         if (tt % sched.add_every) < sched.add_count and K < sched.max_masks:
             K += 1
     return K
+
+
+def roofline_of(prof, sched, S, sizes, Ks, mixed=False):
+    """Roofline entry of the dominant iteration kernel (by time over the
+    solve): its algorithmic bytes summed launch by launch with the mask
+    count of that iteration (Big-M iterations first, K = 0), over its
+    HIP-event time; HBM traffic from the committed counter summary."""
+    iter_prof = {key: v for key, v in prof.items() if key[0] in ("forward", "backward")}
+    (role, layer), (n_launch, tot_ms) = max(iter_prof.items(), key=lambda kv: kv[1][1])
+    # the forward pass of iteration t sees the masks added in t, the
+    # backward pass the ones before
+    Ks_all = [0] * sched.bigm_iters + (Ks if role == "forward" else [0] + Ks[:-1])
+    if n_launch != len(Ks_all):
+        return None
+    tot_bytes = S * sum(kernel_unit_bytes(role, layer, sizes, K, mixed) for K in Ks_all)
+    avg_s = tot_ms / 1e3 / n_launch
+    achieved = tot_bytes / n_launch / avg_s / 1e9
+    traffic = committed_traffic(f"{role}:{layer}" + (":mixed" if mixed and role == "forward" else ""))
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None if traffic is None else round(traffic / avg_s / 1e9, 1),
+            "kernel": f"{role} layer {layer}", "avg_launch_us": round(1e6 * avg_s, 2),
+            "alg_bytes_per_launch": round(tot_bytes / n_launch),
+            "hbm_bytes_per_launch": None if traffic is None else round(traffic)}
 
 
 def adjoint_weight_bytes(layer, sizes, n_weights, K, S):
@@ -351,26 +377,7 @@ def main():
         prof = plan.profile_read()
         plan.profile(False)
         kernels = {f"{r}:{l}": {"launches": n, "avg_us": 1e3 * ms / n} for (r, l), (n, ms) in prof.items()}
-        # dominant iteration kernel (by time over the solve) and its
-        # algorithmic bytes, launch by launch with the mask count of that
-        # iteration (Big-M iterations first, K = 0)
-        iter_prof = {key: v for key, v in prof.items() if key[0] in ("forward", "backward")}
-        dom = max(iter_prof.items(), key=lambda kv: kv[1][1])
-        (role, layer), (n_launch, tot_ms) = dom
-        # the forward pass of iteration t sees the masks added in t, the
-        # backward pass the ones before
-        Ks_all = [0] * sched.bigm_iters + (Ks if role == "forward" else [0] + Ks[:-1])
-        if n_launch == len(Ks_all):
-            tot_bytes = S * sum(kernel_unit_bytes(role, layer, sizes, K) for K in Ks_all)
-            avg_s = tot_ms / 1e3 / n_launch
-            achieved = tot_bytes / n_launch / avg_s / 1e9
-            traffic = committed_traffic(f"{role}:{layer}")
-            roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBS, 4),
-                        "traffic": None if traffic is None else round(traffic / avg_s / 1e9, 1),
-                        "kernel": f"{role} layer {layer}", "avg_launch_us": round(1e6 * avg_s, 2),
-                        "alg_bytes_per_launch": round(tot_bytes / n_launch),
-                        "hbm_bytes_per_launch": None if traffic is None else round(traffic)}
+        roofline = roofline_of(prof, sched, S, sizes, Ks)
     whole_as_gbs = alg_as / (as_ms / args.steps / 1e3) / 1e9
     mixed = None
     if not args.no_mixed:
@@ -391,6 +398,14 @@ def main():
         torch.cuda.synchronize()
         as_m = sum(e[1].elapsed_time(e[2]) for e in evm)
         lbm = lb_m.cpu().numpy()
+        roof_m = None
+        if not args.no_kernel_profile:
+            plan.profile(True)
+            step()
+            torch.cuda.synchronize()
+            prof_m = plan.profile_read()
+            plan.profile(False)
+            roof_m = roofline_of(prof_m, sched, S, sizes, Ks, mixed=True)
         diff = lb_np - lbm
         scale = float(np.mean(np.abs(lb_np)))
         mixed = {"value": round(S * sched.as_iters * args.steps / (as_m / 1e3), 1),
@@ -403,6 +418,7 @@ def main():
                  "equal_accuracy": bool(np.mean(diff) <= 1e-4 * scale
                                         and int(np.sum(lbm > 0)) >= int(np.sum(lb_np > 0))),
                  "verified": [int(np.sum(lb_np > 0)), int(np.sum(lbm > 0))],
+                 "roofline": roof_m,
                  "dtype": "f32 duals and arithmetic, bf16 Adam moments, f64 final bound"}
     ragged = None
     if not args.no_ragged:

@@ -663,7 +663,7 @@ asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
         // column kernel, the taps split over KS waves
         const int CB = (sizeof(T) == 4 && L.C > 4 && P->bwd_cb[k] != 4) ? 8 : 4;
         const int ksp = KS;
-        const size_t dyn = (size_t)g.out.C * g.ksz * g.ksz * CB * sizeof(float);
+        const size_t dyn = ((size_t)g.out.C * g.ksz * g.ksz + 1) * CB * sizeof(float);  // + a zero row
         const size_t stat = (size_t)ksp * CB * kWave * sizeof(T);
         if (dyn + stat > 64 * 1024) return launch_backward<T, T>(P, k, 0, ASD_K_BACKWARD, st);
         ProfScope ps(P, st, ASD_K_BACKWARD, k);

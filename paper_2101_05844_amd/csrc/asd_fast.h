@@ -808,15 +808,20 @@ __global__ void __launch_bounds__(kWave * KSP) k_bwd_conv(FastBwdArgs<T> A) {
     const long col = (long)tile * kWave + lane;
     const int c0 = group * CB;
     const int S = A.S;
-    const int ks = g.ksz, st = g.stride;
-    const int nw = O.C * ks * ks * CB;
-    for (int i = tid; i < nw; i += kWave * KS) {
+    const int ks = KSZ > 0 ? KSZ : g.ksz, st = STR > 0 ? STR : g.stride;
+    const int kk2 = ks * ks;  // a constant when the kernel size is fixed
+    const int nrow = O.C * kk2;
+    const int nw = nrow * CB;
+    // weights [(co * ks + ky) * ks + kx][e], then one zero row that taps
+    // outside the output map point at (their operands are then read from a
+    // valid address and multiplied by zero)
+    for (int i = tid; i < nw + CB; i += kWave * KS) {
         const int e = i % CB;
-        const int rest = i / CB;  // (co * ks + ky) * ks + kx
-        const int co = rest / (ks * ks);
-        const int kk = rest - co * ks * ks;
+        const int rest = i / CB;
+        const int co = rest / kk2;
+        const int kk = rest - co * kk2;
         const int c = c0 + e;
-        wl[i] = c < L.C ? g.W[((long)co * L.C + c) * ks * ks + kk] : 0.f;
+        wl[i] = (c < L.C && rest < nrow) ? g.W[(co * L.C + c) * kk2 + kk] : 0.f;
     }
     __syncthreads();
     const bool colok = col < L.cols;
@@ -851,11 +856,12 @@ __global__ void __launch_bounds__(kWave * KSP) k_bwd_conv(FastBwdArgs<T> A) {
                 for (int jx0 = 0; jx0 < JT; jx0 += J) {
                     T vv[UC][J][J], uu[UC][NA][J][J];
                     int kk[UC][J][J];
-                    bool okk[UC][J][J];
 #pragma unroll
                     for (int uc = 0; uc < UC; ++uc) {
                         const int co = min(cu + uc, co1 - 1);
-                        const long obase = ((long)co * S + s) * O.P;
+                        // neuron indices fit 31 bits (checked when the
+                        // workspace is sized): 32-bit offsets from the bases
+                        const uint32_t obase = ((uint32_t)co * (uint32_t)S + (uint32_t)s) * (uint32_t)O.P;
 #pragma unroll
                         for (int jy = 0; jy < J; ++jy) {
 #pragma unroll
@@ -864,12 +870,12 @@ __global__ void __launch_bounds__(kWave * KSP) k_bwd_conv(FastBwdArgs<T> A) {
                                 const int oy = qy - (jy0 + jy), ox = qx - (jx0 + jx);
                                 const bool ok = cu + uc < co1 && ky < ks && kx < ks && oy >= 0 && oy < O.H &&
                                                 ox >= 0 && ox < O.W;
-                                const long a = ok ? obase + (long)oy * O.W + ox : 0;
+                                const uint32_t a = ok ? obase + (uint32_t)(oy * O.W + ox) : 0u;
+                                __builtin_assume(a < (1u << 30));
                                 vv[uc][jy][jx] = A.vs[a];
 #pragma unroll
                                 for (int q = 0; q < NM; ++q) uu[uc][q][jy][jx] = A.u[q][a];
-                                kk[uc][jy][jx] = (co * ks + (ok ? ky : 0)) * ks + (ok ? kx : 0);
-                                okk[uc][jy][jx] = ok;
+                                kk[uc][jy][jx] = ok ? (co * ks + ky) * ks + kx : nrow;  // zero row
                             }
                         }
                     }
@@ -879,15 +885,13 @@ __global__ void __launch_bounds__(kWave * KSP) k_bwd_conv(FastBwdArgs<T> A) {
                         for (int jy = 0; jy < J; ++jy) {
 #pragma unroll
                             for (int jx = 0; jx < J; ++jx) {
-                                const bool ok = okk[uc][jy][jx];
-                                const T v = ok ? vv[uc][jy][jx] : (T)0;
+                                const T v = vv[uc][jy][jx];
                                 const float* wp = &wl[kk[uc][jy][jx] * CB];
 #pragma unroll
                                 for (int e = 0; e < CB; ++e) {
                                     acc[e] += (T)wp[e] * v;
 #pragma unroll
-                                    for (int q = 0; q < NM; ++q)
-                                        au[q][e] += (T)fabsf(wp[e]) * (ok ? uu[uc][q][jy][jx] : (T)0);
+                                    for (int q = 0; q < NM; ++q) au[q][e] += (T)fabsf(wp[e]) * uu[uc][q][jy][jx];
                                 }
                             }
                         }

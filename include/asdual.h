@@ -337,12 +337,16 @@ asd_status asd_interval_bounds(const asd_net* net, int32_t S, const float* l0, c
  *   bwd_cb[k]     transposed convolution into layer k on the column kernel:
  *                 channels per thread (4 or 8; 0 = default),
  *   bwd_pos[k]    dense backward into layer k: positions on lanes (1) or
- *                 the column kernel (0). */
+ *                 the column kernel (0),
+ *   bwd_nt[k]     transposed convolution into layer k on the matrix cores:
+ *                 16-position column tiles per wave (2 or 4; 0 = 2 where a
+ *                 block's waves still cover every parity class at once). */
 typedef struct {
     int32_t ksplit[ASD_MAX_LAYERS];
     int32_t fwd_mfma[ASD_MAX_LAYERS];
     int32_t bwd_cb[ASD_MAX_LAYERS];
     int32_t bwd_pos[ASD_MAX_LAYERS];
+    int32_t bwd_nt[ASD_MAX_LAYERS];
 } asd_tuning;
 
 /* Times every alternative of the choices above on the loaded batch (each

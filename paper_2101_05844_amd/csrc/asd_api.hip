@@ -103,6 +103,7 @@ struct asd_plan {
     int fwd_mfma[kMaxLayers + 1];     // convolution forward with < 32 channels on the matrix cores
     int bwd_cb[kMaxLayers + 1];       // column transposed convolution into layer k: channels per thread
     int bwd_pos[kMaxLayers + 1];      // dense backward into layer k: positions on lanes
+    int bwd_nt[kMaxLayers + 1];       // matrix-core transposed convolution into layer k: tiles per item (0 = 2 where it fits)
     float* Wb[kMaxLayers + 1];        // convolution: class weights of the transposed product
     int nkp[kMaxLayers + 1];
     void* part;                       // dense forward partial products
@@ -353,6 +354,7 @@ void setup_plan_geometry(asd_plan* P) {
         P->fwd_mfma[L] = 0;
         P->bwd_cb[L - 1] = 0;
         P->bwd_pos[L - 1] = 1;
+        P->bwd_nt[L - 1] = 0;
         if (d.kind == ASD_LAYER_DENSE) {
             // about two waves per SIMD (2048 waves of KS per 32 x 32 tile), at
             // least 32 taps per wave, at most 8 partial sums per output
@@ -632,14 +634,21 @@ asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
         const int qymax = (L.H - 1 + pd) / st_, qxmax = (L.W - 1 + pd) / st_;
         sh.Hp = std::max(g.out.H, qymax + 1) + sh.off;
         sh.Wp = std::max(g.out.W, qxmax + 1) + sh.off;
-        sh.items = 0;
-        for (int c = 0; c < st_ * st_; ++c) {
-            const int ry = c / st_, rx = c % st_;
-            const int yf = ((ry - pd) % st_ + st_) % st_, xf = ((rx - pd) % st_ + st_) % st_;
-            const int ny = yf < L.H ? (L.H - 1 - yf) / st_ + 1 : 0;
-            const int nx = xf < L.W ? (L.W - 1 - xf) / st_ + 1 : 0;
-            sh.items += (ny * nx + 63) / 64;
-        }
+        // items of NT column tiles of 16 positions of one parity class; one
+        // wave per item, at most 8: two tiles per item where that fits
+        auto count_items = [&](int nt) {
+            int items = 0;
+            for (int c = 0; c < st_ * st_; ++c) {
+                const int ry = c / st_, rx = c % st_;
+                const int yf = ((ry - pd) % st_ + st_) % st_, xf = ((rx - pd) % st_ + st_) % st_;
+                const int ny = yf < L.H ? (L.H - 1 - yf) / st_ + 1 : 0;
+                const int nx = xf < L.W ? (L.W - 1 - xf) / st_ + 1 : 0;
+                items += (ny * nx + 16 * nt - 1) / (16 * nt);
+            }
+            return items;
+        };
+        const int NT = (count_items(2) <= 8 && P->bwd_nt[k] != 4) ? 2 : 4;
+        sh.items = count_items(NT);
         sh.NW = std::min(sh.items, 8);
         sh.dimg = FastDiv{sh.Hp * sh.Wp, 1.0f / (float)(sh.Hp * sh.Wp)};
         sh.dWp = FastDiv{sh.Wp, 1.0f / (float)sh.Wp};
@@ -651,10 +660,13 @@ asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
             const size_t dyn = std::max(fbytes, (size_t)sh.CC * per_ch);
             ProfScope ps(P, st, ASD_K_BACKWARD, k);
             dim3 grid((unsigned)P->Sa, (unsigned)((L.C + 15) / 16));
-            if (g.ksz == 4 && g.stride == 2)
-                hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 4, 2>), grid, dim3(kWave, sh.NW), dyn, st, a, sh);
-            else
-                hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 0, 0>), grid, dim3(kWave, sh.NW), dyn, st, a, sh);
+            if (g.ksz == 4 && g.stride == 2) {
+                if (NT == 2) hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 4, 2, 2>), grid, dim3(kWave, sh.NW), dyn, st, a, sh);
+                else hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 4, 2, 4>), grid, dim3(kWave, sh.NW), dyn, st, a, sh);
+            } else {
+                if (NT == 2) hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 0, 0, 2>), grid, dim3(kWave, sh.NW), dyn, st, a, sh);
+                else hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 0, 0, 4>), grid, dim3(kWave, sh.NW), dyn, st, a, sh);
+            }
             LAUNCH_CHECK();
             return ASD_OK;
         }
@@ -1293,6 +1305,15 @@ asd_status autotune_t(asd_plan* P, int ktune, int reps, hipStream_t st) {
             }
             P->bwd_cb[k] = tb[0] < tb[1] ? 4 : 8;
         }
+        if (g.kind == ASD_LAYER_CONV2D && In.P % kWave == 0 && In.C >= 16) {
+            float tb[2];
+            const int cand[2] = {2, 4};
+            for (int m = 0; m < 2; ++m) {
+                P->bwd_nt[k] = cand[m];
+                tb[m] = timed([&] { return bwd_fast<T>(P, k, st); });
+            }
+            P->bwd_nt[k] = tb[0] <= tb[1] ? 2 : 4;
+        }
         if (g.kind == ASD_LAYER_DENSE && In.P % kWave == 0 && P->S >= 8) {
             float tb[2];
             for (int m = 0; m < 2; ++m) {
@@ -1460,6 +1481,7 @@ asd_status asd_plan_get_tuning(const asd_plan* P, asd_tuning* out) {
         out->fwd_mfma[L - 1] = P->fwd_mfma[L];
         out->bwd_cb[L - 1] = P->bwd_cb[L - 1];
         out->bwd_pos[L - 1] = P->bwd_pos[L - 1];
+        out->bwd_nt[L - 1] = P->bwd_nt[L - 1];
     }
     return ASD_OK;
 }
@@ -1473,6 +1495,8 @@ asd_status asd_plan_set_tuning(asd_plan* P, const asd_tuning* in) {
         const int cb = in->bwd_cb[L - 1];
         if (cb != 0 && cb != 4 && cb != 8) return fail(ASD_EINVAL, "bwd_cb must be 0, 4 or 8");
         if (in->bwd_pos[L - 1] != 0 && in->bwd_pos[L - 1] != 1) return fail(ASD_EINVAL, "bwd_pos must be 0 or 1");
+        const int nt = in->bwd_nt[L - 1];
+        if (nt != 0 && nt != 2 && nt != 4) return fail(ASD_EINVAL, "bwd_nt must be 0, 2 or 4");
     }
     invalidate_graph(P);
     for (int L = 1; L <= P->n; ++L) {
@@ -1480,6 +1504,7 @@ asd_status asd_plan_set_tuning(asd_plan* P, const asd_tuning* in) {
         P->fwd_mfma[L] = in->fwd_mfma[L - 1];
         P->bwd_cb[L - 1] = in->bwd_cb[L - 1];
         P->bwd_pos[L - 1] = in->bwd_pos[L - 1];
+        P->bwd_nt[L - 1] = in->bwd_nt[L - 1];
     }
     return ASD_OK;
 }

@@ -666,8 +666,9 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_conv_mfma(FastFwdArgs<float>
             for (int i = 0; i < 16; ++i) tot[r][i] = acc[r][i];
     }
     if (!colok) return;
-    // update in batches of NB neurons, each batch's loads issued together
-    constexpr int NB = NM <= 2 ? 4 : (NM <= 4 ? 2 : 1);
+    // update neuron by neuron: batching the loads of several neurons costs
+    // registers (two waves per SIMD instead of three) and measured slower
+    constexpr int NB = 1;
     static_assert(NR % NB == 0, "batch size");
 #pragma unroll
     for (int b0 = 0; b0 < NR; b0 += NB) {
@@ -1023,10 +1024,9 @@ __device__ __forceinline__ void finish_runs(const FastBwdArgs<float>& A, const f
     }
 }
 
-template <int NM, int KSZ, int STR>
+template <int NM, int KSZ, int STR, int NT>  // NT: column tiles of 16 per item
 __global__ void __launch_bounds__(kWave * 8) k_bwd_conv_mfma(FastBwdArgs<float> A, BwdConvShape B) {
     typedef float floatx4 __attribute__((ext_vector_type(4)));
-    constexpr int NT = 4;  // column tiles of 16 per item
     extern __shared__ float lds[];
     const LayerGeo& g = A.gn;
     const NeuronLayout& L = g.in;

@@ -599,6 +599,8 @@ def _tuning_alternatives(A, plan):
             sp = Ly.spec
             if not ((sp.h_in * sp.w_in) % 64 == 0 and sp.c_in >= 16) and sp.c_in > 4:
                 alts.append(("bwd_cb", k, 4 if base["bwd_cb"][k] != 4 else 8))
+            if (sp.h_in * sp.w_in) % 64 == 0 and sp.c_in >= 16:
+                alts.append(("bwd_nt", k, 4 if base["bwd_nt"][k] != 4 else 2))
         else:
             n_in = Ly.spec.n_in
             prev = plan.net.layers[L - 2] if L >= 2 else None

@@ -105,6 +105,8 @@ struct asd_plan {
     int bwd_pos[kMaxLayers + 1];      // dense backward into layer k: positions on lanes
     int bwd_nt[kMaxLayers + 1];       // matrix-core transposed convolution into layer k: tiles per item (0 = 2 where it fits)
     float* Wb[kMaxLayers + 1];        // convolution: class weights of the transposed product
+    float* Wl4[kMaxLayers + 1];       // convolution: weights in the column kernel's LDS layout, 4 and
+    float* Wl8[kMaxLayers + 1];       // 8 channels per group (k_col_weights)
     int nkp[kMaxLayers + 1];
     void* part;                       // dense forward partial products
     int* pointflag;                   // [kMaxLayers]: point box away from zero in layer k
@@ -258,7 +260,12 @@ void carve_t(asd_plan* P, Carver& cv) {
         const LayerGeo& g = P->geo[L];
         if (L < P->n) P->Wt[L] = cv.take<float>((size_t)g.fan * P->Cpad[L]);
         if (g.kind == ASD_LAYER_CONV2D)
+        {
             P->Wb[L] = cv.take<float>((size_t)((g.in.C + 15) / 16) * g.stride * g.stride * P->nkp[L] * 16);
+            const size_t rows = (size_t)g.out.C * g.ksz * g.ksz + 1;
+            P->Wl4[L] = cv.take<float>((size_t)((g.in.C + 3) / 4) * rows * 4);
+            P->Wl8[L] = cv.take<float>((size_t)((g.in.C + 7) / 8) * rows * 8);
+        }
         if (g.kind == ASD_LAYER_DENSE) {
             P->Wr[L] = cv.take<float>((size_t)g.out.C * P->fanpad[L]);
             if (L < P->n)
@@ -499,6 +506,13 @@ asd_status prepare_weights(asd_plan* P, hipStream_t st) {
             hipLaunchKernelGGL(k_class_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g.W, P->Wb[L],
                                g.in.C, g.out.C, g.ksz, g.stride, P->nkp[L], n);
             LAUNCH_CHECK();
+            for (int cb = 4; cb <= 8; cb += 4) {
+                const long rows = (long)g.out.C * g.ksz * g.ksz + 1;
+                const long nl = (long)((g.in.C + cb - 1) / cb) * rows * cb;
+                hipLaunchKernelGGL(k_col_weights, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, g.W,
+                                   cb == 4 ? P->Wl4[L] : P->Wl8[L], g.in.C, g.out.C, g.ksz * g.ksz, cb, nl);
+                LAUNCH_CHECK();
+            }
         }
         if (g.kind == ASD_LAYER_DENSE) {
             const long n = (long)g.out.C * P->fanpad[L];
@@ -622,6 +636,8 @@ asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
     const LayerGeo& g = a.gn;
     const NeuronLayout& L = g.in;
     a.Wb = P->Wb[k + 1];
+    a.Wl4 = P->Wl4[k + 1];
+    a.Wl8 = P->Wl8[k + 1];
     a.nkp = P->nkp[k + 1];
     if (g.kind == ASD_LAYER_CONV2D && L.P % kWave == 0 && L.C >= 16) {
         // matrix-core transposed convolution over parity classes, operands

@@ -124,6 +124,14 @@ struct FwdIn {
     T LI[NM > 0 ? NM : 1], UI[NM > 0 ? NM : 1], bq[NM > 0 ? NM : 1], mq[NM > 0 ? NM : 1], vq[NM > 0 ? NM : 1];
 };
 
+// Load of element idx (< 2^30, so that its byte offset is a 32-bit value)
+// from a wave-uniform base: base register plus 32-bit offset addressing.
+template <typename T>
+__device__ __forceinline__ T ld32(const T* base, uint32_t idx) {
+    const uint32_t off = idx * (uint32_t)sizeof(T);
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+}
+
 // BF16 storage of Adam moments: round to nearest even on the FP32 bits, and
 // back by placing the 16 stored bits on top (moments are finite).
 __device__ __forceinline__ uint16_t bf16_rne(float f) {
@@ -734,6 +742,8 @@ struct FastBwdArgs {
     const float* Wr;            // dense: W rows padded to fanpad (zeros past layer k)
     int fanpad;
     const float* Wb;            // convolution: class weights [group][class][nkp][16]
+    const float* Wl4;           // convolution: [group][C_{k+1} k k + 1][CB] (last row zero), CB = 4
+    const float* Wl8;           // and CB = 8
     int nkp;                    // taps per class (C_{k+1} J^2) rounded up to 4
     const T* cvec;              // objective rows (layout of layer n)
     const T* vs;                // layer k+1 operand of the W^T product
@@ -796,7 +806,7 @@ __global__ void __launch_bounds__(kWave * KSP) k_bwd_conv(FastBwdArgs<T> A) {
     static_assert(CB % KS == 0, "CB must be a multiple of KS");
     constexpr int EPW = CB / KS;
     constexpr int NA = NM > 0 ? NM : 1;
-    extern __shared__ float wl[];
+    extern __shared__ __attribute__((aligned(16))) float wl[];
     __shared__ T red[KS][CB][kWave];
     const LayerGeo& g = A.gn;
     const NeuronLayout& L = g.in;
@@ -810,19 +820,16 @@ __global__ void __launch_bounds__(kWave * KSP) k_bwd_conv(FastBwdArgs<T> A) {
     const int c0 = group * CB;
     const int S = A.S;
     const int ks = KSZ > 0 ? KSZ : g.ksz, st = STR > 0 ? STR : g.stride;
-    const int kk2 = ks * ks;  // a constant when the kernel size is fixed
-    const int nrow = O.C * kk2;
-    const int nw = nrow * CB;
-    // weights [(co * ks + ky) * ks + kx][e], then one zero row that taps
-    // outside the output map point at (their operands are then read from a
-    // valid address and multiplied by zero)
-    for (int i = tid; i < nw + CB; i += kWave * KS) {
-        const int e = i % CB;
-        const int rest = i / CB;
-        const int co = rest / kk2;
-        const int kk = rest - co * kk2;
-        const int c = c0 + e;
-        wl[i] = (c < L.C && rest < nrow) ? g.W[(co * L.C + c) * kk2 + kk] : 0.f;
+    const int nrow = O.C * ks * ks;
+    // weights [(co * ks + ky) * ks + kx][e] of this channel group, then one
+    // zero row that taps outside the output map point at (their operands are
+    // then read from a valid address and multiplied by zero); laid out once
+    // per plan by k_col_weights, copied here in 16-byte pieces
+    {
+        const float4* src = reinterpret_cast<const float4*>((CB == 4 ? A.Wl4 : A.Wl8) + (long)group * (nrow + 1) * CB);
+        float4* dst = reinterpret_cast<float4*>(wl);
+        const int n4 = (nrow + 1) * CB / 4;
+        for (int i = tid; i < n4; i += kWave * KS) dst[i] = src[i];
     }
     __syncthreads();
     const bool colok = col < L.cols;
@@ -872,10 +879,9 @@ __global__ void __launch_bounds__(kWave * KSP) k_bwd_conv(FastBwdArgs<T> A) {
                                 const bool ok = cu + uc < co1 && ky < ks && kx < ks && oy >= 0 && oy < O.H &&
                                                 ox >= 0 && ox < O.W;
                                 const uint32_t a = ok ? obase + (uint32_t)(oy * O.W + ox) : 0u;
-                                __builtin_assume(a < (1u << 30));
-                                vv[uc][jy][jx] = A.vs[a];
+                                vv[uc][jy][jx] = ld32(A.vs, a);
 #pragma unroll
-                                for (int q = 0; q < NM; ++q) uu[uc][q][jy][jx] = A.u[q][a];
+                                for (int q = 0; q < NM; ++q) uu[uc][q][jy][jx] = ld32(A.u[q], a);
                                 kk[uc][jy][jx] = ok ? (co * ks + ky) * ks + kx : nrow;  // zero row
                             }
                         }
@@ -1179,6 +1185,22 @@ __global__ void __launch_bounds__(kWave * 8) k_bwd_conv_mfma(FastBwdArgs<float> 
 // Class weights for k_bwd_conv_mfma: Wb[grp][cls][k][c] = W[co][16 grp + c][ky][kx]
 // with k = (co J + jy) J + jx, ky = ry + st jy, kx = rx + st jx, zero past
 // the kernel, past C_k or past C_{k+1} J^2.
+// Weights of a convolution in the column transposed kernel's LDS layout:
+// Wl[group][(co * k + ky) * k + kx][e] = W[co][group * cb + e][ky][kx] (zero
+// past C_in), then one zero row per group.
+__global__ void __launch_bounds__(256) k_col_weights(const float* W, float* Wl, int Cin, int Cout, int kk2, int cb,
+                                                     long n) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int rows = Cout * kk2 + 1;
+    const int e = (int)(i % cb);
+    const long rest = i / cb;
+    const int grp = (int)(rest / rows), row = (int)(rest - (long)grp * rows);
+    const int c = grp * cb + e;
+    const int co = row / kk2, kk = row - co * kk2;
+    Wl[i] = (row < rows - 1 && c < Cin) ? W[((long)co * Cin + c) * kk2 + kk] : 0.f;
+}
+
 __global__ void __launch_bounds__(256) k_class_weights(const float* W, float* Wb, int Ck, int C1, int ks, int st,
                                                        int nkp, long n) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;

@@ -379,6 +379,25 @@ def main():
         kernels = {f"{r}:{l}": {"launches": n, "avg_us": 1e3 * ms / n} for (r, l), (n, ms) in prof.items()}
         roofline = roofline_of(prof, sched, S, sizes, Ks)
     whole_as_gbs = alg_as / (as_ms / args.steps / 1e3) / 1e9
+    # what a plain device copy reaches on this GPU (1 GiB read + 1 GiB written,
+    # best of 3, HIP events on the copy's stream): the practical HBM ceiling
+    copy_gbs = None
+    if roofline is not None:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        best = None
+        for _ in range(4):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            dst.copy_(src)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1)
+            best = t if best is None else min(best, t)
+        copy_gbs = 2 * src.numel() * 4 / (best / 1e3) / 1e9
+        del src, dst
+        roofline["copy_GBps"] = round(copy_gbs, 1)
+        roofline["frac_of_copy"] = round(roofline["achieved"] / copy_gbs, 4)
     mixed = None
     if not args.no_mixed:
         # the same solves with Adam moments stored in BF16 (ASD_PREC_MIXED):

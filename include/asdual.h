@@ -332,8 +332,8 @@ asd_status asd_interval_bounds(const asd_net* net, int32_t S, const float* l0, c
 /* Kernel choices of an FP32-duals plan, per layer (index L-1 for layer L;
  * the backward entries are indexed by the neuron layer k they write):
  *   ksplit[L-1]   dense ReLU layer L: partial sums over the fan-in (1..8),
- *   fwd_mfma[L-1] convolutional ReLU layer L with < 32 channels: forward on
- *                 the matrix cores (1) or the VALU column kernel (0),
+ *   fwd_mfma[L-1] convolutional ReLU layer L: forward on the matrix cores
+ *                 (1; default from 32 channels) or the VALU column kernel (0),
  *   bwd_cb[k]     transposed convolution into layer k on the column kernel:
  *                 channels per thread (4 or 8; 0 = default),
  *   bwd_pos[k]    dense backward into layer k: positions on lanes (1) or

@@ -100,7 +100,7 @@ struct asd_plan {
     int fanpad[kMaxLayers + 1];
     int ksplit[kMaxLayers + 1];       // dense forward: blocks over the fan-in
     // kernel choices per layer (heuristic defaults, or asd_plan_autotune)
-    int fwd_mfma[kMaxLayers + 1];     // convolution forward with < 32 channels on the matrix cores
+    int fwd_mfma[kMaxLayers + 1];     // convolution forward on the matrix cores (else the VALU column kernel)
     int bwd_cb[kMaxLayers + 1];       // column transposed convolution into layer k: channels per thread
     int bwd_pos[kMaxLayers + 1];      // dense backward into layer k: positions on lanes
     int bwd_nt[kMaxLayers + 1];       // matrix-core transposed convolution into layer k: tiles per item (0 = 2 where it fits)
@@ -358,7 +358,7 @@ void setup_plan_geometry(asd_plan* P) {
             P->gpart_b = std::max(P->gpart_b, (size_t)P->gb_chunks[L] * g.out.C);
         }
         P->ksplit[L] = 1;
-        P->fwd_mfma[L] = 0;
+        P->fwd_mfma[L] = d.kind == ASD_LAYER_CONV2D && d.out_c >= 32;
         P->bwd_cb[L - 1] = 0;
         P->bwd_pos[L - 1] = 1;
         P->bwd_nt[L - 1] = 0;
@@ -560,7 +560,7 @@ asd_status fwd_fast_nm(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t s
     const LayerGeo& g = a.g;
     constexpr int CB = sizeof(T) == 4 ? 8 : 4;
     ProfScope ps(P, st, ASD_K_FORWARD, k);
-    if (g.kind == ASD_LAYER_CONV2D && g.out.C < 32 && !P->fwd_mfma[k]) {
+    if (g.kind == ASD_LAYER_CONV2D && !P->fwd_mfma[k]) {
         // narrow layer: a 32-row matrix tile would be half empty, and the
         // update's memory traffic bounds it anyway
         dim3 grid((unsigned)((g.out.cols + kWave - 1) / kWave), (unsigned)((g.out.C + CB - 1) / CB));
@@ -1302,7 +1302,7 @@ asd_status autotune_t(asd_plan* P, int ktune, int reps, hipStream_t st) {
             }
             P->ksplit[L] = best;
         }
-        if (L < P->n && g.kind == ASD_LAYER_CONV2D && g.out.C < 32) {
+        if (L < P->n && g.kind == ASD_LAYER_CONV2D) {
             float tb[2];
             for (int m = 0; m < 2; ++m) {
                 P->fwd_mfma[L] = m;

@@ -590,7 +590,7 @@ def _tuning_alternatives(A, plan):
                 if ks != base["ksplit"][L - 1]:
                     alts.append(("ksplit", L - 1, ks))
                 ks *= 2
-        elif Ly.spec.c_out < 32:
+        else:
             alts.append(("fwd_mfma", L - 1, 1 - base["fwd_mfma"][L - 1]))
     for L in range(1, n + 1):
         Ly = plan.net.layers[L - 1]

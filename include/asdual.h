@@ -340,13 +340,16 @@ asd_status asd_interval_bounds(const asd_net* net, int32_t S, const float* l0, c
  *                 the column kernel (0),
  *   bwd_nt[k]     transposed convolution into layer k on the matrix cores:
  *                 16-position column tiles per wave (2 or 4; 0 = 2 where a
- *                 block's waves still cover every parity class at once). */
+ *                 block's waves still cover every parity class at once),
+ *   fwd_kw[L-1]   convolution forward on the matrix cores: waves splitting
+ *                 the taps of one 32 x 32 tile (4 or 8). */
 typedef struct {
     int32_t ksplit[ASD_MAX_LAYERS];
     int32_t fwd_mfma[ASD_MAX_LAYERS];
     int32_t bwd_cb[ASD_MAX_LAYERS];
     int32_t bwd_pos[ASD_MAX_LAYERS];
     int32_t bwd_nt[ASD_MAX_LAYERS];
+    int32_t fwd_kw[ASD_MAX_LAYERS];
 } asd_tuning;
 
 /* Times every alternative of the choices above on the loaded batch (each

@@ -103,6 +103,7 @@ struct asd_plan {
     int fwd_mfma[kMaxLayers + 1];     // convolution forward on the matrix cores (else the VALU column kernel)
     int bwd_cb[kMaxLayers + 1];       // column transposed convolution into layer k: channels per thread
     int bwd_pos[kMaxLayers + 1];      // dense backward into layer k: positions on lanes
+    int fwd_kw[kMaxLayers + 1];       // matrix-core convolution forward: waves per block (4 or 8)
     int bwd_nt[kMaxLayers + 1];       // matrix-core transposed convolution into layer k: tiles per item (0 = 2 where it fits)
     float* Wb[kMaxLayers + 1];        // convolution: class weights of the transposed product
     float* Wl4[kMaxLayers + 1];       // convolution: weights in the column kernel's LDS layout, 4 and
@@ -362,6 +363,7 @@ void setup_plan_geometry(asd_plan* P) {
         P->bwd_cb[L - 1] = 0;
         P->bwd_pos[L - 1] = 1;
         P->bwd_nt[L - 1] = 0;
+        P->fwd_kw[L] = 8;
         if (d.kind == ASD_LAYER_DENSE) {
             // about two waves per SIMD (2048 waves of KS per 32 x 32 tile), at
             // least 32 taps per wave, at most 8 partial sums per output
@@ -575,8 +577,13 @@ asd_status fwd_fast_nm(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t s
         // one 32-column tile per block, its waves splitting the taps
         const long ntiles = (g.out.cols + 31) / 32;
         dim3 grid((unsigned)ntiles, (unsigned)(a.Cpad / 32));
-        if (g.ksz == 4) hipLaunchKernelGGL((k_fwd_conv_mfma<NM, true, 4, MB>), grid, dim3(kWave, KS), 0, st, a);
-        else hipLaunchKernelGGL((k_fwd_conv_mfma<NM, true, 0, MB>), grid, dim3(kWave, KS), 0, st, a);
+        if (P->fwd_kw[k] == 8) {
+            if (g.ksz == 4) hipLaunchKernelGGL((k_fwd_conv_mfma<NM, true, 4, MB, 8>), grid, dim3(kWave, 8), 0, st, a);
+            else hipLaunchKernelGGL((k_fwd_conv_mfma<NM, true, 0, MB, 8>), grid, dim3(kWave, 8), 0, st, a);
+        } else {
+            if (g.ksz == 4) hipLaunchKernelGGL((k_fwd_conv_mfma<NM, true, 4, MB, 4>), grid, dim3(kWave, 4), 0, st, a);
+            else hipLaunchKernelGGL((k_fwd_conv_mfma<NM, true, 0, MB, 4>), grid, dim3(kWave, 4), 0, st, a);
+        }
         (void)CB;
         LAUNCH_CHECK();
         return ASD_OK;
@@ -1303,12 +1310,17 @@ asd_status autotune_t(asd_plan* P, int ktune, int reps, hipStream_t st) {
             P->ksplit[L] = best;
         }
         if (L < P->n && g.kind == ASD_LAYER_CONV2D) {
-            float tb[2];
-            for (int m = 0; m < 2; ++m) {
-                P->fwd_mfma[L] = m;
+            // VALU column kernel, or the matrix cores with 4 or 8 waves per tile
+            float tb[3];
+            const int mf[3] = {0, 1, 1}, kw[3] = {8, 4, 8};
+            for (int m = 0; m < 3; ++m) {
+                P->fwd_mfma[L] = mf[m];
+                P->fwd_kw[L] = kw[m];
                 tb[m] = timed([&] { return fwd_fast<T>(P, L, sa, st); });
             }
-            P->fwd_mfma[L] = tb[1] < tb[0];
+            const int b = tb[0] < tb[1] ? (tb[0] < tb[2] ? 0 : 2) : (tb[1] < tb[2] ? 1 : 2);
+            P->fwd_mfma[L] = mf[b];
+            P->fwd_kw[L] = kw[b];
         }
         const int k = L - 1;  // backward into neuron layer k through layer L
         const NeuronLayout& In = g.in;
@@ -1498,6 +1510,7 @@ asd_status asd_plan_get_tuning(const asd_plan* P, asd_tuning* out) {
         out->bwd_cb[L - 1] = P->bwd_cb[L - 1];
         out->bwd_pos[L - 1] = P->bwd_pos[L - 1];
         out->bwd_nt[L - 1] = P->bwd_nt[L - 1];
+        out->fwd_kw[L - 1] = P->fwd_kw[L];
     }
     return ASD_OK;
 }
@@ -1513,6 +1526,7 @@ asd_status asd_plan_set_tuning(asd_plan* P, const asd_tuning* in) {
         if (in->bwd_pos[L - 1] != 0 && in->bwd_pos[L - 1] != 1) return fail(ASD_EINVAL, "bwd_pos must be 0 or 1");
         const int nt = in->bwd_nt[L - 1];
         if (nt != 0 && nt != 2 && nt != 4) return fail(ASD_EINVAL, "bwd_nt must be 0, 2 or 4");
+        if (in->fwd_kw[L - 1] != 4 && in->fwd_kw[L - 1] != 8) return fail(ASD_EINVAL, "fwd_kw must be 4 or 8");
     }
     invalidate_graph(P);
     for (int L = 1; L <= P->n; ++L) {
@@ -1521,6 +1535,7 @@ asd_status asd_plan_set_tuning(asd_plan* P, const asd_tuning* in) {
         P->bwd_cb[L - 1] = in->bwd_cb[L - 1];
         P->bwd_pos[L - 1] = in->bwd_pos[L - 1];
         P->bwd_nt[L - 1] = in->bwd_nt[L - 1];
+        P->fwd_kw[L] = in->fwd_kw[L - 1];
     }
     return ASD_OK;
 }

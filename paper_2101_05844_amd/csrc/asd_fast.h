@@ -560,16 +560,16 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_dense_mfma(FastFwdArgs<float
 // register's state access is two 128-byte runs.
 // Grid (column tiles / (SPLITK ? 1 : KS), Cpad / 32), block (64, KS).
 // ---------------------------------------------------------------------------
-template <int NM, bool SPLITK, int KSZ, bool MB>
-__global__ void __launch_bounds__(kWave * KS) k_fwd_conv_mfma(FastFwdArgs<float> A) {
+template <int NM, bool SPLITK, int KSZ, bool MB, int KW>  // KW: waves per block
+__global__ void __launch_bounds__(kWave * KW) k_fwd_conv_mfma(FastFwdArgs<float> A) {
     constexpr int U = 4;  // steps of 2 taps per trip
-    __shared__ float red[SPLITK ? KS : 1][16][kWave];
+    __shared__ float red[SPLITK ? KW : 1][16][kWave];
     const LayerGeo& g = A.g;
     const int lane = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
     int tile, group;
     xcd_tile(tile, group);
-    const long ntile = SPLITK ? tile : (long)tile * KS + wave;
+    const long ntile = SPLITK ? tile : (long)tile * KW + wave;
     const int m0 = group * 32;
     const long n0 = ntile * 32;
     if (!SPLITK && n0 >= g.out.cols) return;  // whole wave, no barrier below
@@ -588,7 +588,7 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_conv_mfma(FastFwdArgs<float>
     const long xbase = (long)s * g.in.P;
     const long cstride = (long)S * g.in.P;
     const int F = g.fan;
-    const int t0 = SPLITK ? F * wave / KS : 0, t1 = SPLITK ? F * (wave + 1) / KS : F;
+    const int t0 = SPLITK ? F * wave / KW : 0, t1 = SPLITK ? F * (wave + 1) / KW : F;
     const bool pointin = NM > 0 && *kconst_t<int>(A.pointflag) != 0;
     floatx16 acc[1 + NM], accp;
 #pragma unroll
@@ -650,7 +650,7 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_conv_mfma(FastFwdArgs<float>
     for (int q = 0; q < NM; ++q)
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[1 + q][i] += 2.f * accp[i];
-    constexpr int NR = SPLITK ? 16 / KS : 16;  // accumulator registers this wave updates
+    constexpr int NR = SPLITK ? 16 / KW : 16;  // accumulator registers this wave updates
     float tot[1 + NM][NR];
     if constexpr (SPLITK) {
 #pragma unroll
@@ -662,7 +662,7 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_conv_mfma(FastFwdArgs<float>
             for (int ii = 0; ii < NR; ++ii) {
                 float v = 0.f;
 #pragma unroll
-                for (int w = 0; w < KS; ++w) v += red[w][wave * NR + ii][lane];
+                for (int w = 0; w < KW; ++w) v += red[w][wave * NR + ii][lane];
                 tot[r][ii] = v;
             }
             __syncthreads();

@@ -592,6 +592,7 @@ def _tuning_alternatives(A, plan):
                 ks *= 2
         else:
             alts.append(("fwd_mfma", L - 1, 1 - base["fwd_mfma"][L - 1]))
+            alts.append(("fwd_kw", L - 1, 4 if base["fwd_kw"][L - 1] == 8 else 8))
     for L in range(1, n + 1):
         Ly = plan.net.layers[L - 1]
         k = L - 1

@@ -341,8 +341,10 @@ asd_status asd_interval_bounds(const asd_net* net, int32_t S, const float* l0, c
  *   bwd_nt[k]     transposed convolution into layer k on the matrix cores:
  *                 16-position column tiles per wave (2 or 4; 0 = 2 where a
  *                 block's waves still cover every parity class at once),
- *   fwd_kw[L-1]   convolution forward on the matrix cores: waves splitting
- *                 the taps of one 32 x 32 tile (4 or 8). */
+ *   fwd_kw[L-1]   forward on the matrix cores: waves splitting the taps of
+ *                 one 32 x 32 tile (convolution) or of one split (dense), 4 or 8,
+ *   bwd_kw[k]     dense backward into layer k with positions on lanes: waves
+ *                 splitting the outputs of layer k+1 (4 or 8; FP32 only). */
 typedef struct {
     int32_t ksplit[ASD_MAX_LAYERS];
     int32_t fwd_mfma[ASD_MAX_LAYERS];
@@ -350,6 +352,7 @@ typedef struct {
     int32_t bwd_pos[ASD_MAX_LAYERS];
     int32_t bwd_nt[ASD_MAX_LAYERS];
     int32_t fwd_kw[ASD_MAX_LAYERS];
+    int32_t bwd_kw[ASD_MAX_LAYERS];
 } asd_tuning;
 
 /* Times every alternative of the choices above on the loaded batch (each

@@ -73,7 +73,8 @@ ROLE_NAMES = {0: "backward", 1: "forward", 2: "mask", 3: "final", 4: "other", 5:
 
 class Tuning(C.Structure):
     _fields_ = [("ksplit", C.c_int32 * 16), ("fwd_mfma", C.c_int32 * 16), ("bwd_cb", C.c_int32 * 16),
-                ("bwd_pos", C.c_int32 * 16), ("bwd_nt", C.c_int32 * 16), ("fwd_kw", C.c_int32 * 16)]
+                ("bwd_pos", C.c_int32 * 16), ("bwd_nt", C.c_int32 * 16), ("fwd_kw", C.c_int32 * 16),
+                ("bwd_kw", C.c_int32 * 16)]
 
 
 class EvalOut(C.Structure):
@@ -288,7 +289,7 @@ class Plan:
         t = Tuning()
         _check(lib().asd_plan_get_tuning(self.handle, C.byref(t)))
         n = self.net.n
-        return {f: list(getattr(t, f))[:n] for f in ("ksplit", "fwd_mfma", "bwd_cb", "bwd_pos", "bwd_nt", "fwd_kw")}
+        return {f: list(getattr(t, f))[:n] for f in ("ksplit", "fwd_mfma", "bwd_cb", "bwd_pos", "bwd_nt", "fwd_kw", "bwd_kw")}
 
     def set_tuning(self, d: Dict):
         t = Tuning()

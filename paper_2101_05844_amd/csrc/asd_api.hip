@@ -103,6 +103,7 @@ struct asd_plan {
     int fwd_mfma[kMaxLayers + 1];     // convolution forward on the matrix cores (else the VALU column kernel)
     int bwd_cb[kMaxLayers + 1];       // column transposed convolution into layer k: channels per thread
     int bwd_pos[kMaxLayers + 1];      // dense backward into layer k: positions on lanes
+    int bwd_kw[kMaxLayers + 1];       // dense backward with positions on lanes: waves per block (4 or 8)
     int fwd_kw[kMaxLayers + 1];       // matrix-core convolution forward: waves per block (4 or 8)
     int bwd_nt[kMaxLayers + 1];       // matrix-core transposed convolution into layer k: tiles per item (0 = 2 where it fits)
     float* Wb[kMaxLayers + 1];        // convolution: class weights of the transposed product
@@ -364,6 +365,7 @@ void setup_plan_geometry(asd_plan* P) {
         P->bwd_pos[L - 1] = 1;
         P->bwd_nt[L - 1] = 0;
         P->fwd_kw[L] = 8;
+        P->bwd_kw[L - 1] = 8;
         if (d.kind == ASD_LAYER_DENSE) {
             // about two waves per SIMD (2048 waves of KS per 32 x 32 tile), at
             // least 32 taps per wave, at most 8 partial sums per output
@@ -589,7 +591,8 @@ asd_status fwd_fast_nm(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t s
         return ASD_OK;
     }
     dim3 grid((unsigned)((P->Sa + 31) / 32), (unsigned)(a.Cpad / 32), (unsigned)a.ksplit);
-    hipLaunchKernelGGL((k_fwd_dense_mfma<NM>), grid, dim3(kWave, KS), 0, st, a);
+    if (P->fwd_kw[k] == 8) hipLaunchKernelGGL((k_fwd_dense_mfma<NM, 8>), grid, dim3(kWave, 8), 0, st, a);
+    else hipLaunchKernelGGL((k_fwd_dense_mfma<NM, 4>), grid, dim3(kWave, 4), 0, st, a);
     LAUNCH_CHECK();
     hipLaunchKernelGGL((k_fwd_dense_epi<T, NM, MB>), dim3((unsigned)((P->Sa + 255) / 256), (unsigned)g.out.C), dim3(256),
                        0, st, a);
@@ -725,7 +728,14 @@ asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
     constexpr int SB = sizeof(T) == 4 ? 8 : 4;
     if (L.P % kWave == 0 && P->S >= SB && P->bwd_pos[k]) {
         dim3 grid((unsigned)(L.C * (L.P / kWave)), (unsigned)((P->Sa + SB - 1) / SB));
-        hipLaunchKernelGGL((k_bwd_dense_pos<T, NM, SB>), grid, dim3(kWave, KS), 0, st, a);
+        bool done = false;
+        if constexpr (SB % 8 == 0) {
+            if (P->bwd_kw[k] == 8) {
+                hipLaunchKernelGGL((k_bwd_dense_pos<T, NM, SB, 8>), grid, dim3(kWave, 8), 0, st, a);
+                done = true;
+            }
+        }
+        if (!done) hipLaunchKernelGGL((k_bwd_dense_pos<T, NM, SB, 4>), grid, dim3(kWave, 4), 0, st, a);
     } else {
         constexpr int CB = sizeof(T) == 4 ? 8 : 4;
         dim3 grid((unsigned)((L.cols + kWave - 1) / kWave), (unsigned)((L.C + CB - 1) / CB));
@@ -1300,14 +1310,17 @@ asd_status autotune_t(asd_plan* P, int ktune, int reps, hipStream_t st) {
         const LayerGeo& g = P->geo[L];
         if (L < P->n && g.kind == ASD_LAYER_DENSE) {
             const long cap = std::max(1L, std::min((long)kMaxKsplit, (long)(g.fan / (32 * KS))));
-            int best = P->ksplit[L];
+            int best = P->ksplit[L], bestkw = P->fwd_kw[L];
             float tbest = 1e30f;
-            for (int ks = 1; ks <= cap; ks *= 2) {
-                P->ksplit[L] = ks;
-                const float t = timed([&] { return fwd_fast<T>(P, L, sa, st); });
-                if (t < tbest) tbest = t, best = ks;
-            }
+            for (int kw = 4; kw <= 8; kw += 4)
+                for (int ks = 1; ks <= cap; ks *= 2) {
+                    P->ksplit[L] = ks;
+                    P->fwd_kw[L] = kw;
+                    const float t = timed([&] { return fwd_fast<T>(P, L, sa, st); });
+                    if (t < tbest) tbest = t, best = ks, bestkw = kw;
+                }
             P->ksplit[L] = best;
+            P->fwd_kw[L] = bestkw;
         }
         if (L < P->n && g.kind == ASD_LAYER_CONV2D) {
             // VALU column kernel, or the matrix cores with 4 or 8 waves per tile
@@ -1343,12 +1356,17 @@ asd_status autotune_t(asd_plan* P, int ktune, int reps, hipStream_t st) {
             P->bwd_nt[k] = tb[0] <= tb[1] ? 2 : 4;
         }
         if (g.kind == ASD_LAYER_DENSE && In.P % kWave == 0 && P->S >= 8) {
-            float tb[2];
-            for (int m = 0; m < 2; ++m) {
-                P->bwd_pos[k] = m;
+            // column kernel, or positions on lanes with 4 or 8 waves
+            float tb[3];
+            const int pos[3] = {0, 1, 1}, kw[3] = {8, 4, 8};
+            for (int m = 0; m < 3; ++m) {
+                P->bwd_pos[k] = pos[m];
+                P->bwd_kw[k] = kw[m];
                 tb[m] = timed([&] { return bwd_fast<T>(P, k, st); });
             }
-            P->bwd_pos[k] = tb[1] <= tb[0];
+            const int b = tb[0] < tb[1] ? (tb[0] < tb[2] ? 0 : 2) : (tb[1] < tb[2] ? 1 : 2);
+            P->bwd_pos[k] = pos[b];
+            P->bwd_kw[k] = kw[b];
         }
     }
     (void)hipEventDestroy(e0);
@@ -1511,6 +1529,7 @@ asd_status asd_plan_get_tuning(const asd_plan* P, asd_tuning* out) {
         out->bwd_pos[L - 1] = P->bwd_pos[L - 1];
         out->bwd_nt[L - 1] = P->bwd_nt[L - 1];
         out->fwd_kw[L - 1] = P->fwd_kw[L];
+        out->bwd_kw[L - 1] = P->bwd_kw[L - 1];
     }
     return ASD_OK;
 }
@@ -1527,6 +1546,7 @@ asd_status asd_plan_set_tuning(asd_plan* P, const asd_tuning* in) {
         const int nt = in->bwd_nt[L - 1];
         if (nt != 0 && nt != 2 && nt != 4) return fail(ASD_EINVAL, "bwd_nt must be 0, 2 or 4");
         if (in->fwd_kw[L - 1] != 4 && in->fwd_kw[L - 1] != 8) return fail(ASD_EINVAL, "fwd_kw must be 4 or 8");
+        if (in->bwd_kw[L - 1] != 4 && in->bwd_kw[L - 1] != 8) return fail(ASD_EINVAL, "bwd_kw must be 4 or 8");
     }
     invalidate_graph(P);
     for (int L = 1; L <= P->n; ++L) {
@@ -1536,6 +1556,7 @@ asd_status asd_plan_set_tuning(asd_plan* P, const asd_tuning* in) {
         P->bwd_pos[L - 1] = in->bwd_pos[L - 1];
         P->bwd_nt[L - 1] = in->bwd_nt[L - 1];
         P->fwd_kw[L] = in->fwd_kw[L - 1];
+        P->bwd_kw[L - 1] = in->bwd_kw[L - 1];
     }
     return ASD_OK;
 }

@@ -448,10 +448,10 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_conv(FastFwdArgs<T> A) {
 // ---------------------------------------------------------------------------
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-template <int NM>
-__global__ void __launch_bounds__(kWave * KS) k_fwd_dense_mfma(FastFwdArgs<float> A) {
+template <int NM, int KW>  // KW: waves splitting the block's fan-in range
+__global__ void __launch_bounds__(kWave * KW) k_fwd_dense_mfma(FastFwdArgs<float> A) {
     constexpr int U = 4;  // steps of 2 taps per trip
-    __shared__ float red[KS][16][kWave];
+    __shared__ float red[KW][16][kWave];
     const LayerGeo& g = A.g;
     const int lane = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
@@ -460,7 +460,7 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_dense_mfma(FastFwdArgs<float
     const int m0 = blockIdx.y * 32;
     const int n0 = blockIdx.x * 32;
     const int F = g.fan;
-    const long zr = (long)blockIdx.z * KS + wave, nz = (long)A.ksplit * KS;
+    const long zr = (long)blockIdx.z * KW + wave, nz = (long)A.ksplit * KW;
     const int t0 = (int)(F * zr / nz), t1 = (int)(F * (zr + 1) / nz);
     const int Pin = g.in.P;
     const int half = lane >> 5;          // k offset of this lane within a step
@@ -535,11 +535,11 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_dense_mfma(FastFwdArgs<float
         for (int i = 0; i < 16; ++i) red[wave][i][lane] = r == 0 ? acc[0][i] : acc[r][i] + 2.f * accp[i];
         __syncthreads();
 #pragma unroll
-        for (int ii = 0; ii < 16 / KS; ++ii) {
-            const int i = wave * (16 / KS) + ii;
+        for (int ii = 0; ii < 16 / KW; ++ii) {
+            const int i = wave * (16 / KW) + ii;
             float v = 0.f;
 #pragma unroll
-            for (int w = 0; w < KS; ++w) v += red[w][i][lane];
+            for (int w = 0; w < KW; ++w) v += red[w][i][lane];
             const int m = m0 + 8 * (i / 4) + 4 * half + (i % 4);
             if (sw < S && m < g.out.C) A.part[((zs + r) * Cp + m) * S + sw] = v;
         }
@@ -1306,12 +1306,12 @@ __global__ void __launch_bounds__(kWave * KS) k_bwd_dense(FastBwdArgs<T> A) {
 // last tile is shifted back to end at S, so S >= SB).  Grid
 // (C_k * P_k / 64, ceil(S / SB)), block (64, KS), the outputs of layer k+1
 // split over waves.
-template <typename T, int NM, int SB>
-__global__ void __launch_bounds__(kWave * KS) k_bwd_dense_pos(FastBwdArgs<T> A) {
-    static_assert(SB % KS == 0, "SB must be a multiple of KS");
-    constexpr int EPW = SB / KS;
+template <typename T, int NM, int SB, int KW>  // KW: waves splitting the outputs of layer k+1
+__global__ void __launch_bounds__(kWave * KW) k_bwd_dense_pos(FastBwdArgs<T> A) {
+    static_assert(SB % KW == 0, "SB must be a multiple of KW");
+    constexpr int EPW = SB / KW;
     constexpr int NA = NM > 0 ? NM : 1;
-    __shared__ T red[KS][SB][kWave];
+    __shared__ T red[KW][SB][kWave];
     const LayerGeo& g = A.gn;
     const NeuronLayout& L = g.in;
     const int lane = threadIdx.x;
@@ -1323,7 +1323,7 @@ __global__ void __launch_bounds__(kWave * KS) k_bwd_dense_pos(FastBwdArgs<T> A) 
     const int s0 = blockIdx.y * SB;
     const int sb = min(s0, S - SB);
     const int n1 = g.out.C;
-    const int i0 = n1 * wave / KS, i1 = n1 * (wave + 1) / KS;
+    const int i0 = n1 * wave / KW, i1 = n1 * (wave + 1) / KW;
     const long F = g.fan;
     const cptr_t<T> vs = kconst_t<T>(A.last ? A.cvec : A.vs);
     const T vsign = A.last ? (T)-1 : (T)1;
@@ -1372,7 +1372,7 @@ __global__ void __launch_bounds__(kWave * KS) k_bwd_dense_pos(FastBwdArgs<T> A) 
         if (s < s0) continue;  // uniform: computed by the previous tile
         T f = 0;
 #pragma unroll
-        for (int w = 0; w < KS; ++w) f += red[w][j][lane];
+        for (int w = 0; w < KW; ++w) f += red[w][j][lane];
         const long idx = ((long)c * S + s) * L.P + p;
         bwd_store<T>(A, true, idx, f, in[jj], (long)c * L.colpad + (long)s * L.P + (p - lane), lane);
     }

@@ -590,6 +590,7 @@ def _tuning_alternatives(A, plan):
                 if ks != base["ksplit"][L - 1]:
                     alts.append(("ksplit", L - 1, ks))
                 ks *= 2
+            alts.append(("fwd_kw", L - 1, 4 if base["fwd_kw"][L - 1] == 8 else 8))
         else:
             alts.append(("fwd_mfma", L - 1, 1 - base["fwd_mfma"][L - 1]))
             alts.append(("fwd_kw", L - 1, 4 if base["fwd_kw"][L - 1] == 8 else 8))
@@ -608,6 +609,7 @@ def _tuning_alternatives(A, plan):
             P_in = prev.spec.h_out * prev.spec.w_out if prev is not None and prev.kind == "conv" else 1
             if P_in % 64 == 0:
                 alts.append(("bwd_pos", k, 1 - base["bwd_pos"][k]))
+                alts.append(("bwd_kw", k, 4 if base["bwd_kw"][k] == 8 else 8))
     return base, alts
 
 

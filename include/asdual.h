@@ -314,10 +314,16 @@ asd_status asd_oracle(asd_plan* plan, int32_t k, const void* x_prev, const void*
  *          db[k] has out_c entries; both are summed over the subproblems.
  *   dl0, du0 [S][n_0] (device, double, may be NULL): g[s] times the
  *          gradient of d_B(s) with respect to l0 and u0.
+ *   reuse  nonzero: if asd_bound (or asd_bound_grad) ran last on this plan
+ *          and no call has changed its state since, take the minimiser it
+ *          left (the same values a recomputation gives); the caller
+ *          guarantees that the network weights and the batch were not
+ *          changed in place in between.  0: always recompute.
  * Overwrites the plan's minimiser buffers (as asd_bound does); the duals are
  * unchanged.  Errors: ASD_EINVAL for a NULL plan or g, or before asd_init. */
 asd_status asd_bound_grad(asd_plan* plan, const double* g, double* const* dW /* host */,
-                          double* const* db /* host */, double* dl0, double* du0, hipStream_t stream);
+                          double* const* db /* host */, double* dl0, double* du0, int32_t reuse,
+                          hipStream_t stream);
 
 /* ---- Intermediate bounds (App. E; interval propagation) ---- */
 

@@ -126,7 +126,7 @@ def lib():
     L.asd_state_set_counts.argtypes = [vp, C.POINTER(Counts), i32, vp]
     L.asd_eval.argtypes = [vp, C.POINTER(EvalOut), vp]
     L.asd_oracle.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
-    L.asd_bound_grad.argtypes = [vp, vp, C.POINTER(vp), C.POINTER(vp), vp, vp, vp]
+    L.asd_bound_grad.argtypes = [vp, vp, C.POINTER(vp), C.POINTER(vp), vp, vp, i32, vp]
     L.asd_set_budgets.argtypes = [vp, C.POINTER(i32), vp]
     L.asd_solve_graph.argtypes = [vp, C.POINTER(Batch), vp, vp]
     L.asd_plan_autotune.argtypes = [vp, i32, i32, vp]
@@ -383,12 +383,15 @@ class Plan:
         _check(lib().asd_eval(self.handle, C.byref(out), _stream(stream)))
         return res
 
-    def bound_grad(self, g: torch.Tensor, weights: bool = True, box: bool = True, stream=None):
+    def bound_grad(self, g: torch.Tensor, weights: bool = True, box: bool = True, reuse: bool = False,
+                   stream=None):
         """asd_bound_grad: gradient of sum_s g[s] d_B(s) at the current duals.
 
         Returns (dW, db, dl0, du0): dW[k], db[k] float64 tensors shaped like
         layer k+1's weight and bias (None when weights is False), dl0, du0
-        [S][n_0] float64 (None when box is False)."""
+        [S][n_0] float64 (None when box is False).  reuse: take the minimiser
+        of the last asd_bound if the plan's state is unchanged since (the
+        weights and the batch must not have been changed in place)."""
         n = self.net.n
         g = g.to(device="cuda", dtype=torch.float64).contiguous()
         assert tuple(g.shape) == (self.S,)
@@ -403,7 +406,7 @@ class Plan:
         _check(lib().asd_bound_grad(self.handle, g.data_ptr(),
                                     C.cast(pw, C.POINTER(C.c_void_p)) if pw is not None else None,
                                     C.cast(pb, C.POINTER(C.c_void_p)) if pb is not None else None,
-                                    _ptr(dl0), _ptr(du0), _stream(stream)))
+                                    _ptr(dl0), _ptr(du0), int(reuse), _stream(stream)))
         return dW, db, dl0, du0
 
     def profile(self, enable: bool):
@@ -494,7 +497,9 @@ class BoundFunction(torch.autograd.Function):
         plan = ctx.plan
         need_w = any(ctx.needs_input_grad[6:])
         need_box = ctx.needs_input_grad[1] or ctx.needs_input_grad[2]
-        dW, db, dl0, du0 = plan.bound_grad(glb, weights=need_w, box=need_box)
+        # the forward pass ended with asd_bound on this plan; autograd runs
+        # the backward pass before any optimiser step touches the weights
+        dW, db, dl0, du0 = plan.bound_grad(glb, weights=need_w, box=need_box, reuse=True)
         n = ctx.n
         gw = [None] * n if dW is None else [t.to(torch.float32) for t in dW]
         gb = [None] * n if db is None else [t.to(torch.float32) for t in db]

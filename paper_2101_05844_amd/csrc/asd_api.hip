@@ -113,7 +113,8 @@ struct asd_plan {
     void* part;                       // dense forward partial products
     int* pointflag;                   // [kMaxLayers]: point box away from zero in layer k
     void* Rdev;                       // device copy of the ReluLayerT array (update kernels)
-    double* f0;                       // f_0 of the last bound-gradient evaluation
+    double* f0;                       // f_0 of the last bound evaluation
+    bool min_valid;                   // x*, z* bits and f0 are those of the current state, in FP64
     // bound gradient: chunks of the two-stage reductions per layer and the
     // partial sums they write
     int gw_chunks[kMaxLayers + 1];
@@ -1026,17 +1027,23 @@ asd_status run_t(asd_plan* P, bool as, int t_begin, int n_iters, int T_, hipStre
 }
 
 asd_status bound_f32(asd_plan* P, double* out_lb, float* x0, hipStream_t st) {
+    P->min_valid = false;
     for (int k = 1; k < P->n; ++k) TRY(launch_final_sums(P, k, st));
-    for (int k = P->n - 1; k >= 0; --k) TRY((launch_backward<double, float>(P, k, 1, ASD_K_FINAL, st)));
+    for (int k = P->n - 1; k >= 0; --k)
+        TRY((launch_backward<double, float>(P, k, 1, ASD_K_FINAL, st, k == 0 ? P->f0 : nullptr)));
     TRY(reduce_objective<float>(P, out_lb, st));
     if (x0) TRY((launch_layout<float, float>(P->naf[0].xstar, x0, P->nl[0], P->S, 2, st)));
+    P->min_valid = true;
     return ASD_OK;
 }
 
 asd_status bound_f64(asd_plan* P, double* out_lb, float* x0, hipStream_t st) {
-    for (int k = P->n - 1; k >= 0; --k) TRY((launch_backward<double, double>(P, k, 1, ASD_K_FINAL, st)));
+    P->min_valid = false;
+    for (int k = P->n - 1; k >= 0; --k)
+        TRY((launch_backward<double, double>(P, k, 1, ASD_K_FINAL, st, k == 0 ? P->f0 : nullptr)));
     TRY(reduce_objective<double>(P, out_lb, st));
     if (x0) TRY((launch_layout<double, float>(P->nad[0].xstar, x0, P->nl[0], P->S, 2, st)));
+    P->min_valid = true;
     return ASD_OK;
 }
 
@@ -1046,11 +1053,15 @@ asd_status bound_f64(asd_plan* P, double* out_lb, float* x0, hipStream_t st) {
 // reduction over the subproblems.
 template <typename Ts>
 asd_status bound_grad_t(asd_plan* P, const double* gs, double* const* dW, double* const* db, double* dl0,
-                        double* du0, hipStream_t st) {
-    if constexpr (sizeof(Ts) == 4)
-        for (int k = 1; k < P->n; ++k) TRY(launch_final_sums(P, k, st));
-    for (int k = P->n - 1; k >= 0; --k)
-        TRY((launch_backward<double, Ts>(P, k, 0, ASD_K_FINAL, st, k == 0 ? P->f0 : nullptr)));
+                        double* du0, int reuse, hipStream_t st) {
+    if (!(reuse && P->min_valid)) {
+        P->min_valid = false;
+        if constexpr (sizeof(Ts) == 4)
+            for (int k = 1; k < P->n; ++k) TRY(launch_final_sums(P, k, st));
+        for (int k = P->n - 1; k >= 0; --k)
+            TRY((launch_backward<double, Ts>(P, k, 0, ASD_K_FINAL, st, k == 0 ? P->f0 : nullptr)));
+        P->min_valid = true;
+    }
     auto base_args = [&](int k) {
         GradArgs<Ts> a;
         memset(&a, 0, sizeof(a));
@@ -1497,6 +1508,7 @@ asd_status asd_plan_create(const asd_net* net, int32_t S, const asd_params* para
     carve(P, cv);
     P->Sa = S;
     P->ragged = false;
+    P->min_valid = false;
     *out = P;
     return ASD_OK;
 }
@@ -1516,6 +1528,7 @@ asd_status asd_plan_autotune(asd_plan* P, int32_t ktune, int32_t reps, hipStream
     if (is64(P)) return ASD_OK;  // FP64 plans run the general kernels only
     if (P->n_masks > ktune) return fail(ASD_EINVAL, "the plan already has %d masks (> ktune)", P->n_masks);
     invalidate_graph(P);
+    P->min_valid = false;
     return autotune_t<float>(P, ktune, reps, st);
 }
 
@@ -1595,6 +1608,7 @@ asd_status asd_profile_read(asd_plan* P, asd_kernel_time* out, int32_t cap, int3
 
 asd_status asd_init(asd_plan* P, const asd_batch* b, hipStream_t st) {
     if (!P || !b) return fail(ASD_EINVAL, "NULL argument");
+    P->min_valid = false;
     if (b->S != P->S) return fail(ASD_EINVAL, "batch has S = %d, plan has %d", b->S, P->S);
     if (!b->l0 || !b->u0 || !b->c) return fail(ASD_EINVAL, "NULL l0/u0/c");
     if (P->n > 1 && (!b->lhat || !b->uhat)) return fail(ASD_EINVAL, "NULL lhat/uhat");
@@ -1611,6 +1625,7 @@ asd_status asd_init(asd_plan* P, const asd_batch* b, hipStream_t st) {
 
 asd_status asd_run(asd_plan* P, int32_t phase, int32_t t_begin, int32_t n_iters, hipStream_t st) {
     if (!P) return fail(ASD_EINVAL, "NULL plan");
+    P->min_valid = false;
     if (!P->loaded) return fail(ASD_EINVAL, "asd_init has not been called");
     if (phase != ASD_PHASE_BIGM && phase != ASD_PHASE_AS) return fail(ASD_EINVAL, "unknown phase");
     const int T = phase == ASD_PHASE_BIGM ? P->prm.bigm_iters : as_iters_of(P);
@@ -1628,11 +1643,11 @@ asd_status asd_bound(asd_plan* P, double* out_lb, float* x0, hipStream_t st) {
 }
 
 asd_status asd_bound_grad(asd_plan* P, const double* gs, double* const* dW, double* const* db, double* dl0,
-                          double* du0, hipStream_t st) {
+                          double* du0, int32_t reuse, hipStream_t st) {
     if (!P || !gs) return fail(ASD_EINVAL, "NULL argument");
     if (!P->loaded) return fail(ASD_EINVAL, "asd_init has not been called");
-    return is64(P) ? bound_grad_t<double>(P, gs, dW, db, dl0, du0, st)
-                   : bound_grad_t<float>(P, gs, dW, db, dl0, du0, st);
+    return is64(P) ? bound_grad_t<double>(P, gs, dW, db, dl0, du0, reuse, st)
+                   : bound_grad_t<float>(P, gs, dW, db, dl0, du0, reuse, st);
 }
 
 asd_status asd_set_budgets(asd_plan* P, const int32_t* budgets, hipStream_t st) {
@@ -1732,6 +1747,7 @@ asd_status asd_state_get(asd_plan* P, int32_t field, int32_t k, int32_t q, void*
 
 asd_status asd_state_set(asd_plan* P, int32_t field, int32_t k, int32_t q, const void* src, hipStream_t st) {
     TRY(check_field(P, field, k, q));
+    P->min_valid = false;
     if (!src) return fail(ASD_EINVAL, "NULL source");
     if (is64(P)) return state_set_t<double>(P, field, k, q, reinterpret_cast<const double*>(src), st);
     return state_set_t<float>(P, field, k, q, reinterpret_cast<const float*>(src), st);
@@ -1748,6 +1764,7 @@ asd_status asd_state_get_counts(const asd_plan* P, asd_counts* out) {
 
 asd_status asd_state_set_counts(asd_plan* P, const asd_counts* in, int32_t recompute, hipStream_t st) {
     if (!P || !in) return fail(ASD_EINVAL, "NULL argument");
+    P->min_valid = false;
     if (!P->loaded) return fail(ASD_EINVAL, "asd_init has not been called");
     if (in->n_masks < 0 || in->n_masks > P->prm.max_masks)
         return fail(ASD_EINVAL, "n_masks %d outside [0, %d]", in->n_masks, P->prm.max_masks);
@@ -1762,6 +1779,7 @@ asd_status asd_state_set_counts(asd_plan* P, const asd_counts* in, int32_t recom
 
 asd_status asd_eval(asd_plan* P, const asd_eval_out* out, hipStream_t st) {
     if (!P || !out) return fail(ASD_EINVAL, "NULL argument");
+    P->min_valid = false;
     if (!P->loaded) return fail(ASD_EINVAL, "asd_init has not been called");
     return is64(P) ? eval_t<double>(P, out, st) : eval_t<float>(P, out, st);
 }

@@ -499,6 +499,13 @@ def test_bound_function_autograd():
     # repeated evaluation is bit-identical (fixed-order sums)
     dW2, _, dl02, _ = plan.bound_grad(gs)
     assert all(torch.equal(a, b) for a, b in zip(dW, dW2)) and torch.equal(dl0, dl02)
+    # after the duals change, a call asking to reuse the minimiser of the last
+    # bound recomputes it (the state changed since): same as a fresh call
+    plan.run(A.ASD_PHASE_AS, 0, 2)
+    dW3, _, dl03, _ = plan.bound_grad(gs, reuse=True)
+    dW4, _, dl04, _ = plan.bound_grad(gs)
+    assert all(torch.equal(a, b) for a, b in zip(dW3, dW4)) and torch.equal(dl03, dl04)
+    assert not all(torch.equal(a, b) for a, b in zip(dW3, dW))
 
 
 def _ragged_budgets(w, seed):

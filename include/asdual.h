@@ -209,6 +209,14 @@ asd_status asd_solve(asd_plan* plan, const asd_batch* batch, double* out_lb, flo
  * instantiation fails. */
 asd_status asd_solve_graph(asd_plan* plan, const asd_batch* batch, double* out_lb, hipStream_t stream);
 
+/* Per-subproblem health of a solve: flags [S] (device, int32) receives, for
+ * each subproblem s, bit 0 set if lb[s] (device [S], as written by asd_bound)
+ * is not finite and bit 1 set if any multiplier of s (alpha, beta_0, beta_1,
+ * the active masks' beta) is not finite; 0 for a healthy subproblem.  A
+ * non-finite bound is no bound: callers should treat such subproblems as
+ * unverified.  Errors: ASD_EINVAL for NULL arguments or before asd_init. */
+asd_status asd_check_finite(asd_plan* plan, const double* lb, int32_t* flags, hipStream_t stream);
+
 /* Solves several plans (for instance one per network of a mixed batch of
  * branch-and-bound subdomains, each plan with its own budgets) together:
  * asd_init of batches[i] into plans[i], then the Big-M and Active Set

@@ -92,7 +92,7 @@ _lib = None
 EXPORTED = ["asd_net_create", "asd_net_destroy", "asd_params_default", "asd_plan_workspace_size",
             "asd_plan_create", "asd_plan_destroy", "asd_init", "asd_run", "asd_bound", "asd_solve",
             "asd_state_get", "asd_state_set", "asd_state_get_counts", "asd_state_set_counts",
-            "asd_eval", "asd_oracle", "asd_bound_grad", "asd_set_budgets", "asd_solve_group", "asd_solve_graph",
+            "asd_eval", "asd_oracle", "asd_bound_grad", "asd_set_budgets", "asd_solve_group", "asd_solve_graph", "asd_check_finite",
             "asd_plan_autotune", "asd_plan_get_tuning", "asd_plan_set_tuning", "asd_interval_bounds", "asd_profile_enable", "asd_profile_read",
             "asd_last_error", "asd_abi_version"]
 
@@ -129,6 +129,7 @@ def lib():
     L.asd_bound_grad.argtypes = [vp, vp, C.POINTER(vp), C.POINTER(vp), vp, vp, i32, vp]
     L.asd_set_budgets.argtypes = [vp, C.POINTER(i32), vp]
     L.asd_solve_graph.argtypes = [vp, C.POINTER(Batch), vp, vp]
+    L.asd_check_finite.argtypes = [vp, vp, vp, vp]
     L.asd_plan_autotune.argtypes = [vp, i32, i32, vp]
     L.asd_plan_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
     L.asd_plan_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
@@ -309,6 +310,13 @@ class Plan:
         self.run(ASD_PHASE_BIGM, 0, self.params.bigm_iters, stream)
         self.run(ASD_PHASE_AS, 0, self.as_iters(), stream)
         return self.bound(want_x0, stream)
+
+    def check_finite(self, lb: torch.Tensor, stream=None) -> torch.Tensor:
+        """asd_check_finite: int32 flags [S] (bit 0: bound not finite, bit 1: a multiplier not finite)."""
+        lb = lb.to(device="cuda", dtype=torch.float64).contiguous()
+        flags = torch.empty(self.S, dtype=torch.int32, device="cuda")
+        _check(lib().asd_check_finite(self.handle, lb.data_ptr(), flags.data_ptr(), _stream(stream)))
+        return flags
 
     def solve_graph(self, l0, u0, lhat, uhat, c, stream=None):
         """asd_solve_graph: asd_solve with the iterations replayed from a HIP graph."""

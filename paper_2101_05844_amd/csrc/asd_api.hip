@@ -1385,6 +1385,17 @@ asd_status autotune_t(asd_plan* P, int ktune, int reps, hipStream_t st) {
     return err;
 }
 
+template <typename T>
+asd_status check_finite_t(asd_plan* P, int32_t* flags, hipStream_t st) {
+    for (int k = 1; k < P->n; ++k) {
+        const NeuronLayout& nl = P->nl[k];
+        hipLaunchKernelGGL(k_flags_duals<T>, dim3((unsigned)((nl.cols + 255) / 256), (unsigned)nl.C), dim3(256), 0,
+                           st, RL<T>(P)[k], nl, P->S, P->n_masks, flags);
+        LAUNCH_CHECK();
+    }
+    return ASD_OK;
+}
+
 void invalidate_graph(asd_plan* P) {
     if (P->graph_valid) (void)hipGraphExecDestroy(P->graph_exec);
     P->graph_valid = false;
@@ -1678,6 +1689,14 @@ asd_status asd_solve(asd_plan* P, const asd_batch* b, double* out_lb, float* x0,
     TRY(asd_run(P, ASD_PHASE_BIGM, 0, P->prm.bigm_iters, st));
     TRY(asd_run(P, ASD_PHASE_AS, 0, as_iters_of(P), st));
     return asd_bound(P, out_lb, x0, st);
+}
+
+asd_status asd_check_finite(asd_plan* P, const double* lb, int32_t* flags, hipStream_t st) {
+    if (!P || !lb || !flags) return fail(ASD_EINVAL, "NULL argument");
+    if (!P->loaded) return fail(ASD_EINVAL, "asd_init has not been called");
+    hipLaunchKernelGGL(k_flags_bound, dim3((unsigned)((P->S + 255) / 256)), dim3(256), 0, st, lb, flags, P->S);
+    LAUNCH_CHECK();
+    return is64(P) ? check_finite_t<double>(P, flags, st) : check_finite_t<float>(P, flags, st);
 }
 
 asd_status asd_solve_graph(asd_plan* P, const asd_batch* b, double* out_lb, hipStream_t st) {

@@ -724,6 +724,27 @@ struct ReduceArgs {
     double* out;
 };
 
+// Per-subproblem finiteness flags: bit 0 = the bound is not finite (first
+// kernel, one thread per subproblem), bit 1 = some multiplier of the
+// subproblem is not finite (second kernel, one thread per neuron of a ReLU
+// layer, flags OR-ed in with vector atomics).
+__global__ void __launch_bounds__(256) k_flags_bound(const double* lb, int32_t* flags, int S) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s < S) flags[s] = isfinite(lb[s]) ? 0 : 1;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_flags_duals(ReluLayerT<T> R, NeuronLayout nl, int S, int nm, int32_t* flags) {
+    const long col = (long)blockIdx.x * 256 + threadIdx.x;
+    const int c = blockIdx.y;
+    if (col >= nl.cols) return;
+    const int s = (int)(col / nl.P);
+    const long idx = (long)c * nl.cols + col;
+    bool ok = isfinite(R.alpha[idx]) && isfinite(R.beta0[idx]) && isfinite(R.beta1[idx]);
+    for (int q = 0; q < nm; ++q) ok = ok && isfinite(R.slot[q].beta[idx]);
+    if (!ok) atomicOr(&flags[s], 2);
+}
+
 // Learning rate of Active Set iteration t for each updated subproblem on its
 // own linear schedule over its budget (the same expression as the shared
 // schedule, in FP64).

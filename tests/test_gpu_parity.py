@@ -709,3 +709,22 @@ def test_solve_graph_replays_match_eager(prec):
     lb3_e = plan.solve(*batch).cpu().numpy()
     lb3_g = plan.solve_graph(*batch).cpu().numpy()
     assert np.array_equal(lb3_g, lb3_e)
+
+
+def test_check_finite_flags():
+    """asd_check_finite: all zero after a normal solve; a non-finite bound sets
+    bit 0 and a non-finite multiplier bit 1 of its subproblem only."""
+    w = workloads_small()[1]
+    A, ops, probs, net, plan, batch = _setup(w, prec="fp32")
+    lb = plan.solve(*batch)
+    assert int(plan.check_finite(lb).abs().sum().item()) == 0
+    alpha = plan.get(A.ASD_F_ALPHA, 1)
+    alpha[3, 2] = float("nan")
+    plan.set(A.ASD_F_ALPHA, 1, alpha)
+    lb2 = lb.clone()
+    lb2[5] = float("inf")
+    flags = plan.check_finite(lb2).cpu().numpy()
+    want = np.zeros(w.S, dtype=np.int32)
+    want[3] |= 2
+    want[5] |= 1
+    assert np.array_equal(flags, want), flags

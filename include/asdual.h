@@ -349,7 +349,9 @@ asd_status asd_interval_bounds(const asd_net* net, int32_t S, const float* l0, c
  *   fwd_mfma[L-1] convolutional ReLU layer L: forward on the matrix cores
  *                 (1; default from 32 channels) or the VALU column kernel (0),
  *   bwd_cb[k]     transposed convolution into layer k on the column kernel:
- *                 channels per thread (4 or 8; 0 = default),
+ *                 channels per thread (4 or 8; 0 = default); into a layer of
+ *                 at most 4 channels (stride 2, rows of 8k positions): the
+ *                 matrix-core kernel (0, default) or the VALU one (4),
  *   bwd_pos[k]    dense backward into layer k: positions on lanes (1) or
  *                 the column kernel (0),
  *   bwd_nt[k]     transposed convolution into layer k on the matrix cores:

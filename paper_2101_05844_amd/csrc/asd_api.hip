@@ -618,6 +618,39 @@ asd_status fwd_fast(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t st) 
 template <typename Tc, typename Ts>
 asd_status launch_backward(asd_plan* P, int k, int want_obj, int role, hipStream_t st, double* fout = nullptr);
 
+// Staged operand images of the transposed convolution through layer k+1
+// (k_bwd_conv_mfma, k_bwd_conv_m4): taps per axis, zero border, image size.
+BwdConvShape conv_shape(const LayerGeo& g) {
+    BwdConvShape sh;
+    memset(&sh, 0, sizeof(sh));
+    const int st_ = g.stride, pd = g.pad;
+    sh.J = (g.ksz + st_ - 1) / st_;
+    sh.off = sh.J - 1;
+    const int qymax = (g.in.H - 1 + pd) / st_, qxmax = (g.in.W - 1 + pd) / st_;
+    sh.Hp = std::max(g.out.H, qymax + 1) + sh.off;
+    sh.Wp = std::max(g.out.W, qxmax + 1) + sh.off;
+    sh.dimg = FastDiv{sh.Hp * sh.Wp, 1.0f / (float)(sh.Hp * sh.Wp)};
+    sh.dWp = FastDiv{sh.Wp, 1.0f / (float)sh.Wp};
+    sh.dOP = FastDiv{g.out.P, 1.0f / (float)g.out.P};
+    sh.dOW = FastDiv{g.out.W, 1.0f / (float)g.out.W};
+    return sh;
+}
+
+// The transposed convolution into layer k fits k_bwd_conv_m4: stride 2, at
+// most 4 channels, every 64-position run whole rows of layer k or part of
+// one with an even number of columns per parity, at most 16 such runs per
+// subproblem, and the staged images of one output channel within the LDS
+// share of a product at any mask count.
+bool bwd_m4_fits(const asd_plan* P, int k) {
+    const LayerGeo& g = P->geo[k + 1];
+    const NeuronLayout& L = g.in;
+    if (g.kind != ASD_LAYER_CONV2D || g.stride != 2 || L.C > 4 || k + 1 == P->n) return false;
+    if (L.P % kWave != 0 || L.P > 16 * kWave || L.W % 8 != 0 || !(L.W % kWave == 0 || kWave % L.W == 0))
+        return false;
+    const BwdConvShape sh = conv_shape(g);
+    return sh.Hp * sh.Wp <= bwd_mfma_rs<kMaxMasks>();
+}
+
 // Iteration backward pass into neuron layer k; NM = masks of layer k+1.
 template <typename T, int NM>
 asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
@@ -654,13 +687,8 @@ asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
         // matrix-core transposed convolution over parity classes, operands
         // staged in LDS (see k_bwd_conv_mfma); shapes it cannot hold fall
         // through to the column kernel
-        BwdConvShape sh;
+        BwdConvShape sh = conv_shape(g);
         const int st_ = g.stride, pd = g.pad;
-        sh.J = (g.ksz + st_ - 1) / st_;
-        sh.off = sh.J - 1;
-        const int qymax = (L.H - 1 + pd) / st_, qxmax = (L.W - 1 + pd) / st_;
-        sh.Hp = std::max(g.out.H, qymax + 1) + sh.off;
-        sh.Wp = std::max(g.out.W, qxmax + 1) + sh.off;
         // items of NT column tiles of 16 positions of one parity class; one
         // wave per item, at most 8: two tiles per item where that fits
         auto count_items = [&](int nt) {
@@ -677,14 +705,14 @@ asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
         const int NT = (count_items(2) <= 8 && P->bwd_nt[k] != 4) ? 2 : 4;
         sh.items = count_items(NT);
         sh.NW = std::min(sh.items, 8);
-        sh.dimg = FastDiv{sh.Hp * sh.Wp, 1.0f / (float)(sh.Hp * sh.Wp)};
-        sh.dWp = FastDiv{sh.Wp, 1.0f / (float)sh.Wp};
         const size_t fbytes = (size_t)std::min(16, L.C) * L.P * sizeof(float);
-        const size_t per_ch = (size_t)(1 + NM) * sh.Hp * sh.Wp * sizeof(float);
-        const size_t budget = 48 * 1024;
-        if (sh.items <= sh.NW && fbytes <= budget && per_ch <= budget) {
-            sh.CC = (int)std::min<size_t>((size_t)g.out.C, budget / per_ch);
-            const size_t dyn = std::max(fbytes, (size_t)sh.CC * per_ch);
+        constexpr int RS = bwd_mfma_rs<NM>();
+        const int img = sh.Hp * sh.Wp;
+        if (sh.items <= sh.NW && fbytes <= 32 * 1024 && img <= RS) {
+            sh.CC = std::min(g.out.C, RS / img);
+            // product r's images at float r RS, the parked f after the last
+            sh.fboff = NM * RS + sh.CC * img;
+            const size_t dyn = (size_t)sh.fboff * sizeof(float) + fbytes;
             ProfScope ps(P, st, ASD_K_BACKWARD, k);
             dim3 grid((unsigned)P->Sa, (unsigned)((L.C + 15) / 16));
             if (g.ksz == 4 && g.stride == 2) {
@@ -709,6 +737,23 @@ asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
         dim3 grid((unsigned)((L.cols + kWave - 1) / kWave), (unsigned)((L.C + CB - 1) / CB));
         const bool k4s2 = g.ksz == 4 && g.stride == 2;
         if constexpr (sizeof(T) == 4) {
+            if (bwd_m4_fits(P, k) && P->bwd_cb[k] != 4) {
+                // at most 4 channels, stride 2: the matrix-core variant, a
+                // block per subproblem
+                BwdConvShape sh = conv_shape(g);
+                constexpr int RS = bwd_mfma_rs<NM>();
+                const int img = sh.Hp * sh.Wp;
+                sh.CC = std::min(g.out.C, RS / img);
+                sh.fboff = (NM * RS + sh.CC * img + 3) / 4 * 4;
+                const size_t dm4 = ((size_t)sh.fboff + (size_t)(g.out.C * g.ksz * g.ksz + 1) * 4) * sizeof(float);
+                if (dm4 <= 64 * 1024) {
+                    const dim3 bm4(kWave, L.P / kWave);
+                    if (g.ksz == 4) hipLaunchKernelGGL((k_bwd_conv_m4<NM, 4>), dim3((unsigned)P->Sa), bm4, dm4, st, a, sh);
+                    else hipLaunchKernelGGL((k_bwd_conv_m4<NM, 0>), dim3((unsigned)P->Sa), bm4, dm4, st, a, sh);
+                    LAUNCH_CHECK();
+                    return ASD_OK;
+                }
+            }
             if (CB == 8) {
                 if (k4s2)
                     hipLaunchKernelGGL((k_bwd_conv<T, NM, 8, 4, 2, KS>), grid, dim3(kWave, KS), dyn, st, a);
@@ -1348,6 +1393,16 @@ asd_status autotune_t(asd_plan* P, int ktune, int reps, hipStream_t st) {
         }
         const int k = L - 1;  // backward into neuron layer k through layer L
         const NeuronLayout& In = g.in;
+        if (bwd_m4_fits(P, k)) {
+            // matrix-core 4-channel kernel (0) or the VALU column kernel (4)
+            float tb[2];
+            const int cand[2] = {0, 4};
+            for (int m = 0; m < 2; ++m) {
+                P->bwd_cb[k] = cand[m];
+                tb[m] = timed([&] { return bwd_fast<T>(P, k, st); });
+            }
+            P->bwd_cb[k] = tb[0] <= tb[1] ? 0 : 4;
+        }
         if (g.kind == ASD_LAYER_CONV2D && !(In.P % kWave == 0 && In.C >= 16) && In.C > 4) {
             float tb[2];
             const int cand[2] = {4, 8};

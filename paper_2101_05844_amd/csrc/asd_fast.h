@@ -78,6 +78,10 @@ __device__ __forceinline__ int fdiv(int n, FastDiv f) {
     return q;
 }
 
+// Subproblem and position of column col = s P + p, in 32-bit arithmetic
+// (column counts fit 31 bits: checked when the workspace is sized)
+__device__ __forceinline__ int col_sub(long col, int P) { return (int)((uint32_t)col / (uint32_t)P); }
+
 __device__ __forceinline__ void xcd_tile(int& tile, int& group) {
     const unsigned gx = gridDim.x, gy = gridDim.y, n = gx * gy;
     const unsigned lin = blockIdx.y * gx + blockIdx.x;
@@ -159,7 +163,7 @@ __global__ void k_layout_bf16(uint32_t* in_arr, float* ex_arr, NeuronLayout nl, 
     const long col = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
     if (col >= nl.cols) return;
-    const int s = (int)(col / nl.P), p = (int)(col - (long)s * nl.P);
+    const int s = col_sub(col, nl.P), p = (int)col - s * nl.P;
     const long in_ = ((long)c * S + s) * nl.P + p;
     const long ex = (long)s * nl.N + (long)c * nl.P + p;
     const uint32_t w = in_arr[in_];
@@ -311,8 +315,8 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_conv(FastFwdArgs<T> A) {
     const int c0 = group * CB;
     const int S = A.S;
     const bool colok = col < g.out.cols;
-    const int s = colok ? (int)(col / g.out.P) : 0;
-    const int p = colok ? (int)(col - (long)s * g.out.P) : 0;
+    const int s = colok ? col_sub(col, g.out.P) : 0;
+    const int p = colok ? (int)col - s * g.out.P : 0;
     const int oy = p / g.out.W, ox = p - (p / g.out.W) * g.out.W;
     const int ks = KSZ > 0 ? KSZ : g.ksz;
     const int iy0 = oy * g.stride - g.pad, ix0 = ox * g.stride - g.pad;
@@ -579,8 +583,8 @@ __global__ void __launch_bounds__(kWave * KW) k_fwd_conv_mfma(FastFwdArgs<float>
     const long col = n0 + cl;
     const bool colok = col < g.out.cols;
     const long cc = colok ? col : g.out.cols - 1;  // clamped column for the gathers
-    const int s = (int)(cc / g.out.P);
-    const int p = (int)(cc - (long)s * g.out.P);
+    const int s = col_sub(cc, g.out.P);
+    const int p = (int)cc - s * g.out.P;
     const int oy = p / g.out.W, ox = p - (p / g.out.W) * g.out.W;
     const int ks = KSZ > 0 ? KSZ : g.ksz;
     const int ks2 = ks * ks;
@@ -833,8 +837,8 @@ __global__ void __launch_bounds__(kWave * KSP) k_bwd_conv(FastBwdArgs<T> A) {
     }
     __syncthreads();
     const bool colok = col < L.cols;
-    const int s = colok ? (int)(col / L.P) : 0;
-    const int p = colok ? (int)(col - (long)s * L.P) : 0;
+    const int s = colok ? col_sub(col, L.P) : 0;
+    const int p = colok ? (int)col - s * L.P : 0;
     const int y = p / L.W, x = p - (p / L.W) * L.W;
     const int ry = (y + g.pad) % st, qy = (y + g.pad) / st;
     const int rx = (x + g.pad) % st, qx = (x + g.pad) / st;
@@ -949,52 +953,192 @@ __global__ void __launch_bounds__(kWave * KSP) k_bwd_conv(FastBwdArgs<T> A) {
 // r wave w takes item r NW + w (one round: items <= NW).  The operand images
 // of the subproblem (v and every u_q, with a zero border of J - 1 outputs)
 // are staged in LDS in chunks of CC output channels, so the B gathers are LDS
-// reads.  Partial f (sigma_q folded) is then parked in the same LDS in
-// natural position order, and the waves finish 64-position runs
+// reads; product r's images start at float r * RS (RS fixed per mask count,
+// so the 1 + NM reads of one tap differ only in their immediate offsets).
+// Partial f (sigma_q folded) is then parked in natural position order in a
+// region of its own (float fboff on), and the waves finish 64-position runs
 // (P_k % 64 == 0).
 struct BwdConvShape {
     int J, off, Hp, Wp;   // taps per axis, border, staged image size
     int CC;               // output channels per staged chunk
     int items, NW;        // work items, waves per block
+    int fboff;            // LDS float offset of the parked f
     FastDiv dimg, dWp;    // divisions by Hp Wp and by Wp
+    FastDiv dOP, dOW;     // divisions by P_{k+1} and by W_{k+1}
 };
 
+// LDS floats reserved per product for the staged images (48 KB over the
+// 1 + NM products)
+template <int NM>
+__host__ __device__ constexpr int bwd_mfma_rs() {
+    return (12288 / (1 + NM)) & ~3;
+}
+
 // Stages the operand images of one subproblem for output channels
-// [cb, cb + cc) of layer k+1 (v and every u_q) into opnd
-// [1 + NM][CC][Hp][Wp], zero outside the layer; 16 loads per thread in
-// flight, then their LDS stores.
+// [cb, cb + cc) of layer k+1 (v and every u_q) into the interiors of the
+// images at opnd + r RS (the borders were zeroed once); UL elements per
+// thread, the loads of every product in flight before the LDS stores.
 template <int NM>
 __device__ __forceinline__ void stage_operands(const FastBwdArgs<float>& A, const BwdConvShape& B, float* opnd,
-                                               int cb, int cc, long obase, long ostride, int tid, int nthr) {
+                                               int cb, int cc, uint32_t obase, uint32_t ostride, int tid, int nthr) {
+    constexpr int RS = bwd_mfma_rs<NM>();
+    constexpr int UL = 4;
     const NeuronLayout& O = A.gn.out;
-    const int img = B.Hp * B.Wp, Wp = B.Wp, off = B.off, CC = B.CC;
-    constexpr int UL = 16;
-    const int total = (1 + NM) * cc * img;
+    const int img = B.Hp * B.Wp, Wp = B.Wp, off = B.off;
+    const int total = cc * O.P;
     for (int e0 = tid; e0 < total; e0 += UL * nthr) {
-        float v[UL];
+        uint32_t src[UL];
         int dst[UL];
 #pragma unroll
         for (int u = 0; u < UL; ++u) {
             const int e = e0 + u * nthr;
             const int ee = e < total ? e : 0;
-            const int row = fdiv(ee, B.dimg);  // r * cc + col
-            const int pix = ee - row * img;
-            int r = 0;
+            const int col = fdiv(ee, B.dOP);
+            const int pix = ee - col * O.P;
+            const int oy = fdiv(pix, B.dOW), ox = pix - oy * O.W;
+            // neuron indices fit 31 bits (checked when the workspace is sized)
+            src[u] = (uint32_t)(cb + col) * ostride + obase + (uint32_t)pix;
+            dst[u] = e < total ? col * img + (oy + off) * Wp + ox + off : -1;
+        }
+        float v[1 + NM][UL];
 #pragma unroll
-            for (int i = 1; i <= NM; ++i) r += row >= i * cc ? 1 : 0;
-            const int col = row - r * cc;
-            const int py = fdiv(pix, B.dWp);
-            const int oy = py - off, ox = pix - py * Wp - off;
-            const bool ok = e < total && oy >= 0 && oy < O.H && ox >= 0 && ox < O.W;
-            const long a = ok ? (long)(cb + col) * ostride + obase + (long)oy * O.W + ox : 0;
-            const float* src = r == 0 ? A.vs : A.u[r - 1];
-            const float vl = src[a];
-            v[u] = ok ? vl : 0.f;
-            dst[u] = e < total ? (r * CC + col) * img + pix : -1;
+        for (int r = 0; r <= NM; ++r) {
+            const float* base = r == 0 ? A.vs : A.u[r > 0 ? r - 1 : 0];
+#pragma unroll
+            for (int u = 0; u < UL; ++u) v[r][u] = ld32(base, src[u]);
         }
 #pragma unroll
-        for (int u = 0; u < UL; ++u)
-            if (dst[u] >= 0) opnd[dst[u]] = v[u];
+        for (int u = 0; u < UL; ++u) {
+            if (dst[u] < 0) continue;
+#pragma unroll
+            for (int r = 0; r <= NM; ++r) opnd[r * RS + dst[u]] = v[r][u];
+        }
+    }
+}
+
+// Transposed convolution of stride 2 into a layer of at most 4 channels on
+// the matrix cores (v_mfma_f32_4x4x1_16b_f32: in each block b of 4 lanes,
+// lane 4b + i supplies row i of A, lane 4b + j column j of B, and register
+// r of lane 4b + j receives D[r][j]).  A = the 4 channels' weights at one
+// tap, B = the operand of each lane's position at that tap, so register e
+// of a lane accumulates channel e of its own position.  The lanes of a
+// block must share the tap, hence the parity class: within each run of
+// SW = min(W_k, 64) positions of a row the lanes take the even columns
+// first, then the odd ones (W_k % 8 == 0, W_k divides 64 or 64 divides W_k).
+// Grid (S), block (64, P_k / 64): a block owns one subproblem, wave w its
+// positions [64 w, 64 w + 64).  The operand images of the subproblem are
+// staged in LDS as for k_bwd_conv_mfma (zero borders, chunks of CC output
+// channels, product r at float r RS), the weights [C_{k+1}][ks][ks][4] (then
+// one zero row) after them at float fboff; the sums go back to natural
+// order through lane shuffles before the finishing stores.
+template <int NM, int KSZ>
+__global__ void __launch_bounds__(kWave * 16) k_bwd_conv_m4(FastBwdArgs<float> A, BwdConvShape B) {
+    typedef float floatx4 __attribute__((ext_vector_type(4)));
+    constexpr int CB = 4;
+    constexpr int NA = NM > 0 ? NM : 1;
+    constexpr int st = 2;
+    constexpr int RS = bwd_mfma_rs<NM>();
+    extern __shared__ __attribute__((aligned(16))) float lds[];
+    const LayerGeo& g = A.gn;
+    const NeuronLayout& L = g.in;
+    const NeuronLayout& O = g.out;
+    const int lane = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    const int nw = L.P / kWave;
+    const int tid = wave * kWave + lane, nthr = kWave * nw;
+    const int s = blockIdx.x;
+    const int S = A.S;
+    const int ks = KSZ > 0 ? KSZ : g.ksz;
+    const int nrow = O.C * ks * ks;
+    const int CC = B.CC, off = B.off, Wp = B.Wp, img = B.Hp * B.Wp;
+    float* opnd = lds;
+    float* wl = lds + B.fboff;
+    {
+        const float4* src = reinterpret_cast<const float4*>(A.Wl4);
+        float4* dst = reinterpret_cast<float4*>(wl);
+        const int n4 = (nrow + 1) * CB / 4;
+        for (int i = tid; i < n4; i += nthr) dst[i] = src[i];
+    }
+    // zero borders: the interiors are overwritten by every chunk
+#pragma unroll
+    for (int r = 0; r <= NM; ++r)
+        for (int i = tid; i < CC * img; i += nthr) opnd[r * RS + i] = 0.f;
+    // this lane's position
+    const int SW = min(L.W, kWave), half = SW >> 1;
+    const int seg = lane / SW, li = lane - seg * SW;
+    const int p = wave * kWave + seg * SW + (li < half ? 2 * li : 2 * (li - half) + 1);
+    const int y = p / L.W, x = p - (p / L.W) * L.W;
+    const int ry = (y + g.pad) % st, qy = (y + g.pad) / st;
+    const int rx = (x + g.pad) % st, qx = (x + g.pad) / st;
+    const int lb = (qy + off) * Wp + qx + off;  // staged image offset of tap (0, 0)
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    floatx4 au[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) au[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // this lane's packed x-bits (channels past C_k read channel C_k - 1)
+    const uint32_t nidx = (uint32_t)s * (uint32_t)L.P + (uint32_t)p, cstride = (uint32_t)S * (uint32_t)L.P;
+    unsigned hb[CB];
+#pragma unroll
+    for (int e = 0; e < CB; ++e)
+        hb[e] = NM > 0 ? (unsigned)ld32(A.xpk, (uint32_t)min(e, L.C - 1) * cstride + nidx) : 0u;
+    constexpr int JC = KSZ > 0 ? (KSZ + st - 1) / st : 0;
+    const int J = JC > 0 ? JC : (ks + st - 1) / st;
+    for (int cb = 0; cb < O.C; cb += CC) {
+        const int cc = min(CC, O.C - cb);
+        __syncthreads();  // the previous chunk's reads are done (and the borders zeroed)
+        stage_operands<NM>(A, B, opnd, cb, cc, (uint32_t)s * (uint32_t)O.P, (uint32_t)S * (uint32_t)O.P, tid, nthr);
+        __syncthreads();
+        for (int c = 0; c < cc; ++c) {
+            const int co = cb + c;
+#pragma unroll
+            for (int jy = 0; jy < (JC > 0 ? JC : 1); ++jy) {
+#pragma unroll
+                for (int jx = 0; jx < (JC > 0 ? JC : 1); ++jx) {
+                    // fixed kernel size: the J x J taps unrolled; any size: one
+                    // tap per trip of the loops below
+                    for (int jy2 = 0; jy2 < (JC > 0 ? 1 : J); ++jy2) {
+                        for (int jx2 = 0; jx2 < (JC > 0 ? 1 : J); ++jx2) {
+                            const int ty = jy + jy2, tx = jx + jx2;
+                            const int ky = ry + st * ty, kx = rx + st * tx;
+                            const bool tap = ky < ks && kx < ks;  // shared by the lanes of a block
+                            const int kk = tap ? (co * ks + ky) * ks + kx : nrow;  // zero row
+                            const float w = wl[kk * CB + (lane & 3)];
+                            const float wabs = fabsf(w);
+                            const float* o = opnd + c * img + lb - ty * Wp - tx;
+                            acc = __builtin_amdgcn_mfma_f32_4x4x1f32(w, o[0], acc, 0, 0, 0);
+#pragma unroll
+                            for (int q = 0; q < NM; ++q)
+                                au[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(wabs, o[(1 + q) * RS], au[q], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    // fold sigma_q (this lane's packed x-bits), then fetch each channel's
+    // sum from the lane that computed the natural position of this lane
+    const int ns = lane / SW, ni = lane - ns * SW;
+    const int from = ns * SW + ((ni & 1) ? half + (ni >> 1) : (ni >> 1));
+    float f[CB];
+#pragma unroll
+    for (int e = 0; e < CB; ++e) {
+        float part = acc[e];
+#pragma unroll
+        for (int q = 0; q < NM; ++q) part += 0.5f * flip(au[q][e], (hb[e] >> q) & 1u);
+        f[e] = __shfl(part, from);
+    }
+    const int p2 = wave * kWave + lane;
+    const long ncol = (long)s * L.P + p2;
+    BwdIn<float> in[CB];
+#pragma unroll
+    for (int e = 0; e < CB; ++e) {
+        const int c = min(e, L.C - 1);
+        bwd_load<float>(A, c, ncol, true, ((long)c * S + s) * L.P + p2, in[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < CB; ++e) {
+        if (e >= L.C) break;  // uniform
+        bwd_store<float>(A, true, ((long)e * S + s) * L.P + p2, f[e], in[e], (long)e * L.colpad + ncol - lane, lane);
     }
 }
 
@@ -1054,11 +1198,16 @@ __global__ void __launch_bounds__(kWave * 8) k_bwd_conv_mfma(FastBwdArgs<float> 
     const int nkp = A.nkp;
     const int r4 = lane >> 4, cl = lane & 15;
     const int CC = B.CC;
-    float* opnd = lds;  // [1 + NM][CC][Hp][Wp] while products run
-    float* fbuf = lds;  // [rows][P_k] afterwards (same storage)
-    const long obase = (long)s * O.P;
-    const long ostride = (long)S * O.P;
+    constexpr int RS = bwd_mfma_rs<NM>();
+    float* opnd = lds;             // product r: [CC][Hp][Wp] at float r RS
+    float* fbuf = lds + B.fboff;   // [rows][P_k]
+    const uint32_t obase = (uint32_t)s * (uint32_t)O.P;
+    const uint32_t ostride = (uint32_t)S * (uint32_t)O.P;
     const int rounds = (B.items + NW - 1) / NW;
+    // zero borders: the interiors are overwritten by every chunk
+#pragma unroll
+    for (int r = 0; r <= NM; ++r)
+        for (int i = tid; i < CC * img; i += kWave * NW) opnd[r * RS + i] = 0.f;
     for (int rd = 0; rd < rounds; ++rd) {
         // find this wave's item: class cls, first position n0 within the class
         const int item = rd * NW + wave;
@@ -1119,8 +1268,47 @@ __global__ void __launch_bounds__(kWave * 8) k_bwd_conv_mfma(FastBwdArgs<float> 
             stage_operands<NM>(A, B, opnd, cb, cc, obase, ostride, tid, kWave * NW);
             __syncthreads();
             if (!has) continue;
-            // steps of 4 taps; the weights of the next U steps are loaded
-            // while this trip's products run
+            if constexpr (JC == 2) {
+                // J = 2: a step of 4 taps is one output channel; lane r4
+                // takes tap (jy, jx) = (r4 / 2, r4 % 2) of every channel, so
+                // its B reads sit at a fixed offset from the channel's image
+                int lb[NT];
+#pragma unroll
+                for (int j = 0; j < NT; ++j) lb[j] = (qy[j] - (r4 >> 1)) * Wp + qx[j] - (r4 & 1);
+                const float* wp = Wc + ((long)cb * 4 + r4) * 16 + cl;  // + 64 per output channel
+                constexpr int U = 8;
+                float wq[U];
+                auto wload = [&](int c) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) wq[u] = wp[(long)min(c + u, cc - 1) * 64];
+                };
+                wload(0);
+                for (int c = 0; c < cc; c += U) {
+                    float w2[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) w2[u] = wq[u];
+                    if (c + U < cc) wload(c + U);
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        if (c + u >= cc) break;  // uniform
+                        const float wa = w2[u];
+                        const float wabs = fabsf(wa);
+                        const int cofs = (c + u) * img;
+#pragma unroll
+                        for (int j = 0; j < NT; ++j) {
+                            const float* o = opnd + lb[j] + cofs;
+                            acc[j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa, o[0], acc[j][0], 0, 0, 0);
+#pragma unroll
+                            for (int q = 0; q < NM; ++q)
+                                acc[j][1 + q] = __builtin_amdgcn_mfma_f32_16x16x4f32(wabs, o[(1 + q) * RS],
+                                                                                     acc[j][1 + q], 0, 0, 0);
+                        }
+                    }
+                }
+                continue;
+            }
+            // any J: steps of 4 taps; the weights of the next U steps are
+            // loaded while this trip's products run
             const int kbeg = cb * J2, kend = (cb + cc) * J2;
             constexpr int U = 8;
             float wq[U];
@@ -1153,15 +1341,13 @@ __global__ void __launch_bounds__(kWave * 8) k_bwd_conv_mfma(FastBwdArgs<float> 
                         acc[j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa, opnd[li], acc[j][0], 0, 0, 0);
 #pragma unroll
                         for (int q = 0; q < NM; ++q)
-                            acc[j][1 + q] = __builtin_amdgcn_mfma_f32_16x16x4f32(wabs, opnd[(1 + q) * CC * img + li],
+                            acc[j][1 + q] = __builtin_amdgcn_mfma_f32_16x16x4f32(wabs, opnd[(1 + q) * RS + li],
                                                                                  acc[j][1 + q], 0, 0, 0);
                     }
                 }
             }
         }
-        // fold sigma_q of each neuron and park f in natural order (the
-        // storage of the staged operands: every wave is past its products)
-        __syncthreads();
+        // fold sigma_q of each neuron and park f in natural order
         if (has) {
 #pragma unroll
             for (int j = 0; j < NT; ++j) {
@@ -1240,8 +1426,8 @@ __global__ void __launch_bounds__(kWave * KS) k_bwd_dense(FastBwdArgs<T> A) {
     const int c0 = group * CB;
     const int S = A.S;
     const bool colok = col < L.cols;
-    const int s = colok ? (int)(col / L.P) : 0;
-    const int p = colok ? (int)(col - (long)s * L.P) : 0;
+    const int s = colok ? col_sub(col, L.P) : 0;
+    const int p = colok ? (int)col - s * L.P : 0;
     const int n1 = g.out.C;
     const int i0 = n1 * wave / KS, i1 = n1 * (wave + 1) / KS;
     const cfloat_p Wr = kconst(A.Wr);
@@ -1403,7 +1589,7 @@ __global__ void __launch_bounds__(256) k_pack(PackArgs<T> A) {
     const int c = blockIdx.y;
     bool point_nz = false;
     if (col < A.nl.cols) {
-        const int s = (int)(col / A.nl.P), p = (int)(col - (long)s * A.nl.P);
+        const int s = col_sub(col, A.nl.P), p = (int)col - s * A.nl.P;
         const long idx = ((long)c * A.S + s) * A.nl.P + p;
         const long bi = (long)c * A.nl.colpad + col;
         unsigned w = 0;

@@ -608,6 +608,10 @@ def _tuning_alternatives(A, plan):
             sp = Ly.spec
             if not ((sp.h_in * sp.w_in) % 64 == 0 and sp.c_in >= 16) and sp.c_in > 4:
                 alts.append(("bwd_cb", k, 4 if base["bwd_cb"][k] != 4 else 8))
+            if (sp.stride == 2 and sp.c_in <= 4 and (sp.h_in * sp.w_in) % 64 == 0 and sp.w_in % 8 == 0
+                    and (sp.w_in % 64 == 0 or 64 % sp.w_in == 0)):
+                # matrix-core 4-channel kernel (0) against the VALU column kernel (4)
+                alts.append(("bwd_cb", k, 4 if base["bwd_cb"][k] != 4 else 0))
             if (sp.h_in * sp.w_in) % 64 == 0 and sp.c_in >= 16:
                 alts.append(("bwd_nt", k, 4 if base["bwd_nt"][k] != 4 else 2))
         else:
@@ -620,12 +624,13 @@ def _tuning_alternatives(A, plan):
     return base, alts
 
 
-@pytest.mark.parametrize("wi", [1, 2])
+@pytest.mark.parametrize("wi", [1, 2, 3])
 def test_tuning_alternatives_match_oracle(wi):
     """Each kernel alternative the autotuner may pick (dense forward split
     counts, narrow convolution forward on the matrix cores, channels per
-    thread of the column transposed convolution, dense backward with
-    positions on lanes), one FP32 iteration under the plain rule from two
+    thread of the column transposed convolution, the matrix-core kernel
+    into a layer of at most 4 channels, dense backward with positions on
+    lanes), one FP32 iteration under the plain rule from two
     oracle snapshots (with and without masks): duals within 1e-5."""
     w = workloads_small()[wi]
     A = _A()

@@ -352,8 +352,9 @@ asd_status asd_interval_bounds(const asd_net* net, int32_t S, const float* l0, c
  *                 channels per thread (4 or 8; 0 = default); into a layer of
  *                 at most 4 channels (stride 2, rows of 8k positions): the
  *                 matrix-core kernel (0, default) or the VALU one (4),
- *   bwd_pos[k]    dense backward into layer k: positions on lanes (1) or
- *                 the column kernel (0),
+ *   bwd_pos[k]    dense backward into layer k: the matrix cores (2, the
+ *                 default; FP32, 64-position runs), positions on lanes (1)
+ *                 or the column kernel (0),
  *   bwd_nt[k]     transposed convolution into layer k on the matrix cores:
  *                 16-position column tiles per wave (2 or 4; 0 = 2 where a
  *                 block's waves still cover every parity class at once),

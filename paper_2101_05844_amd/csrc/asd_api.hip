@@ -363,7 +363,7 @@ void setup_plan_geometry(asd_plan* P) {
         P->ksplit[L] = 1;
         P->fwd_mfma[L] = d.kind == ASD_LAYER_CONV2D && d.out_c >= 32;
         P->bwd_cb[L - 1] = 0;
-        P->bwd_pos[L - 1] = 1;
+        P->bwd_pos[L - 1] = 2;
         P->bwd_nt[L - 1] = 0;
         P->fwd_kw[L] = 8;
         P->bwd_kw[L - 1] = 8;
@@ -772,6 +772,15 @@ asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
     }
     ProfScope ps(P, st, ASD_K_BACKWARD, k);
     constexpr int SB = sizeof(T) == 4 ? 8 : 4;
+    if constexpr (sizeof(T) == 4) {
+        if (L.P % kWave == 0 && P->bwd_pos[k] == 2) {
+            // matrix cores: 16 subproblems x 64 positions per block
+            dim3 grid((unsigned)((P->Sa + 15) / 16), (unsigned)(L.C * (L.P / kWave)));
+            hipLaunchKernelGGL((k_bwd_dense_mfma<NM>), grid, dim3(kWave, 4), 0, st, a);
+            LAUNCH_CHECK();
+            return ASD_OK;
+        }
+    }
     if (L.P % kWave == 0 && P->S >= SB && P->bwd_pos[k]) {
         dim3 grid((unsigned)(L.C * (L.P / kWave)), (unsigned)((P->Sa + SB - 1) / SB));
         bool done = false;
@@ -1422,15 +1431,17 @@ asd_status autotune_t(asd_plan* P, int ktune, int reps, hipStream_t st) {
             P->bwd_nt[k] = tb[0] <= tb[1] ? 2 : 4;
         }
         if (g.kind == ASD_LAYER_DENSE && In.P % kWave == 0 && P->S >= 8) {
-            // column kernel, or positions on lanes with 4 or 8 waves
-            float tb[3];
-            const int pos[3] = {0, 1, 1}, kw[3] = {8, 4, 8};
-            for (int m = 0; m < 3; ++m) {
+            // column kernel, positions on lanes with 4 or 8 waves, or the
+            // matrix cores
+            float tb[4];
+            const int pos[4] = {0, 1, 1, 2}, kw[4] = {8, 4, 8, 4};
+            int b = 0;
+            for (int m = 0; m < 4; ++m) {
                 P->bwd_pos[k] = pos[m];
                 P->bwd_kw[k] = kw[m];
                 tb[m] = timed([&] { return bwd_fast<T>(P, k, st); });
+                if (tb[m] < tb[b]) b = m;
             }
-            const int b = tb[0] < tb[1] ? (tb[0] < tb[2] ? 0 : 2) : (tb[1] < tb[2] ? 1 : 2);
             P->bwd_pos[k] = pos[b];
             P->bwd_kw[k] = kw[b];
         }
@@ -1621,7 +1632,7 @@ asd_status asd_plan_set_tuning(asd_plan* P, const asd_tuning* in) {
         if (in->fwd_mfma[L - 1] != 0 && in->fwd_mfma[L - 1] != 1) return fail(ASD_EINVAL, "fwd_mfma must be 0 or 1");
         const int cb = in->bwd_cb[L - 1];
         if (cb != 0 && cb != 4 && cb != 8) return fail(ASD_EINVAL, "bwd_cb must be 0, 4 or 8");
-        if (in->bwd_pos[L - 1] != 0 && in->bwd_pos[L - 1] != 1) return fail(ASD_EINVAL, "bwd_pos must be 0 or 1");
+        if (in->bwd_pos[L - 1] < 0 || in->bwd_pos[L - 1] > 2) return fail(ASD_EINVAL, "bwd_pos must be 0, 1 or 2");
         const int nt = in->bwd_nt[L - 1];
         if (nt != 0 && nt != 2 && nt != 4) return fail(ASD_EINVAL, "bwd_nt must be 0, 2 or 4");
         if (in->fwd_kw[L - 1] != 4 && in->fwd_kw[L - 1] != 8) return fail(ASD_EINVAL, "fwd_kw must be 4 or 8");

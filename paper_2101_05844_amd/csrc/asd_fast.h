@@ -1564,6 +1564,120 @@ __global__ void __launch_bounds__(kWave * KW) k_bwd_dense_pos(FastBwdArgs<T> A) 
     }
 }
 
+// Dense layer k+1 into a layer k whose positions come in runs of 64 (P_k %
+// 64 == 0) on the matrix cores (v_mfma_f32_16x16x4f32: lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16]; register r is
+// C[4 (l / 16) + r][l % 16]).  A wave owns C = f over 16 subproblems (rows)
+// x 16 positions of one channel (columns) and the whole contraction over
+// the outputs of layer k+1: A = the operands of layer k+1 (v, or -c into
+// the output layer's inputs, and every u_q) at those subproblems, B = W
+// (|W| for the u_q) at those positions.  The x-bits and the finishing
+// inputs of the wave's neurons are loaded before the products, so their
+// latency overlaps them; rows past the active subproblems are computed on
+// clamped operands and dropped.  The bits of one register's 16 positions of
+// one subproblem are one 16-bit piece of the bit array.  Grid
+// (ceil(Sa / 16), C_k P_k / 64), block (64, 4): wave w takes positions
+// [16 w, 16 w + 16) of the block's 64.
+template <int NM>
+__global__ void __launch_bounds__(kWave * 4) k_bwd_dense_mfma(FastBwdArgs<float> A) {
+    typedef float floatx4 __attribute__((ext_vector_type(4)));
+    constexpr int NA = NM > 0 ? NM : 1;
+    const LayerGeo& g = A.gn;
+    const NeuronLayout& L = g.in;
+    const int lane = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    const int S = A.S;
+    const int Sa = (int)(L.cols / L.P);
+    const int tiles = L.P / kWave;
+    const int c = blockIdx.y / tiles;
+    const int p0 = (blockIdx.y - c * tiles) * kWave + wave * 16;
+    const int s0 = blockIdx.x * 16;
+    const int kq = lane >> 4, cl = lane & 15;
+    const int sA = min(s0 + cl, Sa - 1);  // A row of this lane
+    const int p = p0 + cl;                // C column of this lane
+    const int n1 = g.out.C;
+    const long F = g.fan;
+    const float* vsrc = A.last ? A.cvec : A.vs;
+    const float vsign = A.last ? -1.f : 1.f;
+    // this lane's neurons: rows 4 kq + r, column cl
+    unsigned hb[4];
+    BwdIn<float> in[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int sc = min(s0 + 4 * kq + r, Sa - 1);
+        const long idx = ((long)c * S + sc) * L.P + p;
+        hb[r] = NM > 0 ? (unsigned)A.xpk[idx] : 0u;
+        bwd_load<float>(A, c, (long)sc * L.P + p, true, idx, in[r]);
+    }
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    floatx4 au[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) au[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // steps of 4 outputs of layer k+1 (lane group kq takes output i + kq), U
+    // steps per trip, the next trip's loads in flight during this one
+    constexpr int U = 5;
+    float av[U], uv[U][NA], wv[U];
+    const float* wcol = g.W + (long)c * L.P + p;
+    auto load = [&](int i) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int ii = i + 4 * u + kq;
+            const int ic = ii < n1 ? ii : 0;
+            const long a = (long)ic * S + sA;
+            av[u] = vsrc[a];
+#pragma unroll
+            for (int q = 0; q < NM; ++q) uv[u][q] = A.u[q][a];
+            wv[u] = wcol[(long)ic * F];
+        }
+    };
+    load(0);
+    for (int i = 0; i < n1; i += 4 * U) {
+        float a2[U], u2[U][NA], w2[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool ok = i + 4 * u + kq < n1;  // outputs past n1 contribute nothing
+            a2[u] = ok ? av[u] : 0.f;
+#pragma unroll
+            for (int q = 0; q < NM; ++q) u2[u][q] = ok ? uv[u][q] : 0.f;
+            w2[u] = wv[u];
+        }
+        if (i + 4 * U < n1) load(i + 4 * U);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (i + 4 * u >= n1) break;  // uniform
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[u], w2[u], acc, 0, 0, 0);
+            const float wa = fabsf(w2[u]);
+#pragma unroll
+            for (int q = 0; q < NM; ++q)
+                au[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(u2[u][q], wa, au[q], 0, 0, 0);
+        }
+    }
+    uint16_t* xb16 = reinterpret_cast<uint16_t*>(A.nk.xbits);
+    uint16_t* zb16 = reinterpret_cast<uint16_t*>(A.zbits);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int s = s0 + 4 * kq + r;
+        const bool ok = s < Sa;  // uniform over each group of 16 lanes
+        float f = vsign * acc[r];
+#pragma unroll
+        for (int q = 0; q < NM; ++q) f += 0.5f * flip(au[q][r], (hb[r] >> q) & 1u);
+        bool xb = false, zb = false;
+        if (ok) {
+            if (A.k >= 1) f += in[r].own;
+            xb = f >= 0.f || in[r].dg;
+            A.nk.xstar[((long)c * S + s) * L.P + p] = xb ? in[r].hi : in[r].lo;
+            if (A.k >= 1) zb = in[r].g >= 0.f;
+        }
+        const unsigned long long mx = __ballot(xb);
+        const unsigned long long mz = __ballot(zb);
+        if (ok && cl == 0) {
+            const long piece = ((long)c * L.colpad + (long)s * L.P + p0) >> 4;
+            xb16[piece] = (uint16_t)(mx >> (16 * kq));
+            if (A.k >= 1) zb16[piece] = (uint16_t)(mz >> (16 * kq));
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Packed bits.  Grid (ceil(cols / 256), C), block 256.
 // x words of layer k from the x-bit arrays of the nm slots of ReLU layer k+1,

@@ -619,7 +619,8 @@ def _tuning_alternatives(A, plan):
             prev = plan.net.layers[L - 2] if L >= 2 else None
             P_in = prev.spec.h_out * prev.spec.w_out if prev is not None and prev.kind == "conv" else 1
             if P_in % 64 == 0:
-                alts.append(("bwd_pos", k, 1 - base["bwd_pos"][k]))
+                alts.append(("bwd_pos", k, 1 - base["bwd_pos"][k] if base["bwd_pos"][k] < 2 else 1))
+                alts.append(("bwd_pos", k, 2 if base["bwd_pos"][k] != 2 else 0))
                 alts.append(("bwd_kw", k, 4 if base["bwd_kw"][k] == 8 else 8))
     return base, alts
 
@@ -630,7 +631,7 @@ def test_tuning_alternatives_match_oracle(wi):
     counts, narrow convolution forward on the matrix cores, channels per
     thread of the column transposed convolution, the matrix-core kernel
     into a layer of at most 4 channels, dense backward with positions on
-    lanes), one FP32 iteration under the plain rule from two
+    lanes or on the matrix cores), one FP32 iteration under the plain rule from two
     oracle snapshots (with and without masks): duals within 1e-5."""
     w = workloads_small()[wi]
     A = _A()

@@ -455,6 +455,7 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 template <int NM, int KW>  // KW: waves splitting the block's fan-in range
 __global__ void __launch_bounds__(kWave * KW) k_fwd_dense_mfma(FastFwdArgs<float> A) {
     constexpr int U = 4;  // steps of 2 taps per trip
+    static_assert(U == 4, "a lane's 16-byte input load holds its 4 taps of a trip");
     __shared__ float red[KW][16][kWave];
     const LayerGeo& g = A.g;
     const int lane = threadIdx.x;
@@ -464,9 +465,14 @@ __global__ void __launch_bounds__(kWave * KW) k_fwd_dense_mfma(FastFwdArgs<float
     const int m0 = blockIdx.y * 32;
     const int n0 = blockIdx.x * 32;
     const int F = g.fan;
-    const long zr = (long)blockIdx.z * KW + wave, nz = (long)A.ksplit * KW;
-    const int t0 = (int)(F * zr / nz), t1 = (int)(F * (zr + 1) / nz);
     const int Pin = g.in.P;
+    // input channels of a multiple of 8 positions: a lane's 4 taps of a trip
+    // are consecutive positions of one channel (one 16-byte load), the taps
+    // of a wave's range whole groups of 8
+    const bool vec = Pin % 8 == 0 && F % 8 == 0;
+    const long zr = (long)blockIdx.z * KW + wave, nz = (long)A.ksplit * KW;
+    const int t0 = vec ? 8 * (int)((F / 8) * zr / nz) : (int)(F * zr / nz);
+    const int t1 = vec ? 8 * (int)((F / 8) * (zr + 1) / nz) : (int)(F * (zr + 1) / nz);
     const int half = lane >> 5;          // k offset of this lane within a step
     const int col = lane & 31;           // A row / B column of this lane
     const int s = min(n0 + col, S - 1);  // clamped: columns past S are computed and dropped
@@ -480,8 +486,33 @@ __global__ void __launch_bounds__(kWave * KW) k_fwd_dense_mfma(FastFwdArgs<float
     for (int i = 0; i < 16; ++i) accp[i] = 0.f;
     float wv[U], xv[U];
     unsigned hv[U];
-    // loads of the trip starting at tap k (lanes past t1 read tap t0 and get 0)
+    // loads of the trip starting at tap k (lanes past t1 read tap t0 and get
+    // 0): step u takes tap k + 4 half + u (vec), else k + 2 u + half
     auto load = [&](int k) {
+        if (vec) {
+            const int tb = k + 4 * half;
+            const int tt = tb < t1 ? tb : t0;
+            const int ci = tt / Pin, pp = tt - (tt / Pin) * Pin;
+            const long b_idx = ((long)ci * S + s) * Pin + pp;
+            const float4 x4 = *reinterpret_cast<const float4*>(A.xin + b_idx);
+            xv[0] = x4.x;
+            xv[1] = x4.y;
+            xv[2] = x4.z;
+            xv[3] = x4.w;
+            if (NM > 0) {
+                const uint2 h4 = *reinterpret_cast<const uint2*>(A.xpk + b_idx);
+                hv[0] = h4.x & 0xffffu;
+                hv[1] = h4.x >> 16;
+                hv[2] = h4.y & 0xffffu;
+                hv[3] = h4.y >> 16;
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u) hv[u] = 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) wv[u] = A.Wt[(long)(tt + u) * Cp + m0 + col];
+            return;
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int t = k + 2 * u + half;
@@ -507,7 +538,7 @@ __global__ void __launch_bounds__(kWave * KW) k_fwd_dense_mfma(FastFwdArgs<float
         // taps past the range contribute nothing
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const bool tok = k + 2 * u + half < t1;
+            const bool tok = (vec ? k + 4 * half + u : k + 2 * u + half) < t1;
             w2[u] = tok ? w2[u] : 0.f;
             x2[u] = tok ? x2[u] : 0.f;
         }

@@ -879,9 +879,16 @@ asd_status launch_mask_consts(asd_plan* P, int k, int q, const uint32_t* zsrc, c
     a.zero_state = zero_state;
     a.deg_in = NA<T>(P)[k - 1].deg;
     a.R = RL<T>(P)[k];
-    const size_t lds = (size_t)KS * CB * 2 * kWave * sizeof(T);
     ProfScope ps(P, st, ASD_K_MASK, k);
-    hipLaunchKernelGGL((k_mask_consts<T, T>), grid_cols(P->nl[k], CB), dim3(kWave, KS), lds, st, a);
+    if (sizeof(T) == 4 && a.g.fan >= 1024) {
+        // wide fan-in (few columns, long tap loops): 16 waves split it (FP64
+        // plans keep the 4 partial sums of their tested arithmetic order)
+        const size_t lds = (size_t)16 * CB * 2 * kWave * sizeof(T);
+        hipLaunchKernelGGL((k_mask_consts<T, T, 16>), grid_cols(P->nl[k], CB), dim3(kWave, 16), lds, st, a);
+    } else {
+        const size_t lds = (size_t)KS * CB * 2 * kWave * sizeof(T);
+        hipLaunchKernelGGL((k_mask_consts<T, T, KS>), grid_cols(P->nl[k], CB), dim3(kWave, KS), lds, st, a);
+    }
     LAUNCH_CHECK();
     return ASD_OK;
 }
@@ -898,9 +905,14 @@ asd_status launch_final_sums(asd_plan* P, int k, hipStream_t st) {
     a.hi_in = P->naf[k - 1].hi;
     a.deg_in = P->naf[k - 1].deg;
     a.R = P->Rf[k];
-    const size_t lds = (size_t)KS * CB * 2 * kWave * sizeof(double);
     ProfScope ps(P, st, ASD_K_FINAL, k);
-    hipLaunchKernelGGL((k_mask_consts<double, float>), grid_cols(P->nl[k], CB), dim3(kWave, KS), lds, st, a);
+    if (a.g.fan >= 1024) {
+        const size_t lds = (size_t)16 * CB * 2 * kWave * sizeof(double);
+        hipLaunchKernelGGL((k_mask_consts<double, float, 16>), grid_cols(P->nl[k], CB), dim3(kWave, 16), lds, st, a);
+    } else {
+        const size_t lds = (size_t)KS * CB * 2 * kWave * sizeof(double);
+        hipLaunchKernelGGL((k_mask_consts<double, float, KS>), grid_cols(P->nl[k], CB), dim3(kWave, KS), lds, st, a);
+    }
     LAUNCH_CHECK();
     return ASD_OK;
 }

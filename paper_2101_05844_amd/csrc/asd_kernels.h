@@ -66,6 +66,69 @@ struct FwdTap {
     long bi;    // input bit index
 };
 
+// The taps t0, t0 + 1, ... of output column (s, p) in the order of
+// fwd_tap, without a division per tap: (channel, kernel row, kernel column)
+// of a convolution, (channel, position) of a dense layer's input, advanced
+// one tap at a time.
+struct TapWalk {
+    int ci, ky, kx;  // dense: channel ci, input position ky
+    int iy0, ix0;    // convolution: first input row and column of the field
+};
+
+__device__ __forceinline__ TapWalk tap_walk(const LayerGeo& g, int p, int t) {
+    TapWalk w;
+    if (g.kind == ASD_LAYER_DENSE) {
+        w.ci = t / g.in.P;
+        w.ky = t - w.ci * g.in.P;
+        w.kx = 0;
+        w.iy0 = w.ix0 = 0;
+    } else {
+        const int k2 = g.ksz * g.ksz;
+        w.ci = t / k2;
+        const int rem = t - w.ci * k2;
+        w.ky = rem / g.ksz;
+        w.kx = rem - w.ky * g.ksz;
+        const int oy = p / g.out.W, ox = p - oy * g.out.W;
+        w.iy0 = oy * g.stride - g.pad;
+        w.ix0 = ox * g.stride - g.pad;
+    }
+    return w;
+}
+
+__device__ __forceinline__ FwdTap tap_at(const LayerGeo& g, int S, int s, const TapWalk& w) {
+    FwdTap r;
+    if (g.kind == ASD_LAYER_DENSE) {
+        r.a = ((long)w.ci * S + s) * g.in.P + w.ky;
+        r.bi = (long)w.ci * g.in.colpad + (long)s * g.in.P + w.ky;
+    } else {
+        const int iy = w.iy0 + w.ky, ix = w.ix0 + w.kx;
+        if (iy < 0 || iy >= g.in.H || ix < 0 || ix >= g.in.W) {
+            r.a = -1;
+            r.bi = 0;
+        } else {
+            const int pin = iy * g.in.W + ix;
+            r.a = ((long)w.ci * S + s) * g.in.P + pin;
+            r.bi = (long)w.ci * g.in.colpad + (long)s * g.in.P + pin;
+        }
+    }
+    return r;
+}
+
+__device__ __forceinline__ void tap_next(const LayerGeo& g, TapWalk& w) {
+    if (g.kind == ASD_LAYER_DENSE) {
+        if (++w.ky == g.in.P) {
+            w.ky = 0;
+            ++w.ci;
+        }
+    } else if (++w.kx == g.ksz) {
+        w.kx = 0;
+        if (++w.ky == g.ksz) {
+            w.ky = 0;
+            ++w.ci;
+        }
+    }
+}
+
 __device__ __forceinline__ FwdTap fwd_tap(const LayerGeo& g, int S, int s, int p, int t) {
     FwdTap r;
     if (g.kind == ASD_LAYER_DENSE) {
@@ -134,8 +197,9 @@ __global__ void __launch_bounds__(kWave * KS) k_forward(FwdArgs<T> A) {
     const int F = g.fan;
     const int t0 = (int)((long)F * wave / KS), t1 = (int)((long)F * (wave + 1) / KS);
     if (colok) {
-        for (int t = t0; t < t1; ++t) {
-            const FwdTap tp = fwd_tap(g, S, s, p, t);
+        TapWalk tw = tap_walk(g, p, t0);
+        for (int t = t0; t < t1; ++t, tap_next(g, tw)) {
+            const FwdTap tp = tap_at(g, S, s, tw);
             const bool ok = tp.a >= 0;
             const T x = ok ? A.xin[tp.a] : (T)0;
             const unsigned dg = ok ? getbit(A.deg_in, tp.bi) : 0u;
@@ -352,12 +416,15 @@ __global__ void __launch_bounds__(kWave * KS) k_backward(BwdArgs<Ts> A) {
             const int co0 = (int)((long)O.C * wave / KS), co1 = (int)((long)O.C * (wave + 1) / KS);
             const int ks = g.ksz, str = g.stride;
             const int ky0 = (y + g.pad) % str, kx0 = (x + g.pad) % str;
+            // (y + pad - ky) is a multiple of the stride for every ky of the
+            // loop: the output row falls by one per step of ky
+            const int oyf = (y + g.pad - ky0) / str, oxf = (x + g.pad - kx0) / str;
             for (int co = co0; co < co1; ++co) {
-                for (int ky = ky0; ky < ks; ky += str) {
-                    const int oy = (y + g.pad - ky) / str;
+                int oy = oyf;
+                for (int ky = ky0; ky < ks; ky += str, --oy) {
                     if (oy < 0 || oy >= O.H) continue;
-                    for (int kx = kx0; kx < ks; kx += str) {
-                        const int ox = (x + g.pad - kx) / str;
+                    int ox = oxf;
+                    for (int kx = kx0; kx < ks; kx += str, --ox) {
                         if (ox < 0 || ox >= O.W) continue;
                         const int op = oy * O.W + ox;
                         const long a = ((long)co * S + s) * O.P + op;
@@ -475,10 +542,11 @@ struct MaskArgs {
     ReluLayerT<Ts> R;
 };
 
-template <typename Tc, typename Ts>
-__global__ void __launch_bounds__(kWave * KS) k_mask_consts(MaskArgs<Ts> A) {
+template <typename Tc, typename Ts, int NW>  // NW: waves splitting the fan-in
+__global__ void __launch_bounds__(kWave * NW) k_mask_consts(MaskArgs<Ts> A) {
+    static_assert(NW >= CB, "one wave per channel finishes the sums");
     extern __shared__ unsigned char red_raw[];
-    Tc* red = reinterpret_cast<Tc*>(red_raw);  // [KS][CB][2][64]
+    Tc* red = reinterpret_cast<Tc*>(red_raw);  // [NW][CB][2][64]
     constexpr bool kFinal64 = sizeof(Tc) > sizeof(Ts);
     const LayerGeo& g = A.g;
     const int lane = threadIdx.x, wave = threadIdx.y;
@@ -492,82 +560,71 @@ __global__ void __launch_bounds__(kWave * KS) k_mask_consts(MaskArgs<Ts> A) {
     const int p = colok ? (int)(col - (long)s * g.out.P) : 0;
     const long bicol0 = (long)c0 * g.out.colpad + col;
 
-    Tc LI[kMaxMasks][CB], UI[kMaxMasks][CB];
-    unsigned zmask[kMaxMasks];
+    // one slot at a time: its LI and UI over this wave's taps; the final
+    // sums fold each slot with its multiplier as soon as it is done,
+    // sum_q beta_q (LI_q + UI_q) and sum_q beta_q LI_q, in slot order
+    Tc fin0[CB], fin1[CB];
 #pragma unroll
-    for (int j = 0; j < kMaxMasks; ++j) {
-        zmask[j] = 0;
+    for (int e = 0; e < CB; ++e) fin0[e] = fin1[e] = 0;
+    const int F = g.fan;
+    const int t0 = (int)((long)F * wave / NW), t1 = (int)((long)F * (wave + 1) / NW);
+    for (int j = 0; j < (colok ? nsl : 0); ++j) {
+        const uint32_t* zb = kFinal64 ? A.R.slot[q0 + j].zbits : A.zsrc;
+        const uint32_t* xbits = kFinal64 ? A.R.slot[q0 + j].xbits : A.xsrc;
+        unsigned zmask = 0;
 #pragma unroll
-        for (int e = 0; e < CB; ++e) LI[j][e] = UI[j][e] = 0;
-    }
-    if (colok && nsl > 0) {
+        for (int e = 0; e < CB; ++e)
+            if (c0 + e < g.out.C) zmask |= getbit(zb, bicol0 + (long)e * g.out.colpad) << e;
+        Tc LI[CB], UI[CB];
 #pragma unroll
-        for (int j = 0; j < kMaxMasks; ++j) {
-            if (j < nsl) {
-                const uint32_t* zb = kFinal64 ? A.R.slot[q0 + j].zbits : A.zsrc;
-#pragma unroll
-                for (int e = 0; e < CB; ++e)
-                    if (c0 + e < g.out.C) zmask[j] |= getbit(zb, bicol0 + (long)e * g.out.colpad) << e;
-            }
-        }
-        const int F = g.fan;
-        const int t0 = (int)((long)F * wave / KS), t1 = (int)((long)F * (wave + 1) / KS);
-        for (int t = t0; t < t1; ++t) {
-            const FwdTap tp = fwd_tap(g, S, s, p, t);
+        for (int e = 0; e < CB; ++e) LI[e] = UI[e] = 0;
+        TapWalk tw = tap_walk(g, p, t0);
+#pragma unroll 4
+        for (int t = t0; t < t1; ++t, tap_next(g, tw)) {
+            const FwdTap tp = tap_at(g, S, s, tw);
             if (tp.a < 0) continue;
             const Tc lo = (Tc)A.lo_in[tp.a], hi = (Tc)A.hi_in[tp.a];
             const unsigned dg = getbit(A.deg_in, tp.bi);
+            const unsigned xb = getbit(xbits, tp.bi);
+            const bool eL = !xb || dg, eH = xb || dg;
 #pragma unroll
-            for (int j = 0; j < kMaxMasks; ++j) {
-                if (j < nsl) {
-                    const uint32_t* xbits = kFinal64 ? A.R.slot[q0 + j].xbits : A.xsrc;
-                    const unsigned xb = getbit(xbits, tp.bi);
-                    const bool eL = !xb || dg, eH = xb || dg;
+            for (int e = 0; e < CB; ++e) {
+                const int c = c0 + e;
+                const Tc w = c < g.out.C ? (Tc)g.W[(long)c * F + t] : (Tc)0;
+                const Tc wl = w >= 0 ? w * lo : w * hi;   // W . Lcheck
+                const Tc wu = w >= 0 ? w * hi : w * lo;   // W . Ucheck
+                const bool zi = (zmask >> e) & 1u;
+                const bool bit = zi || (w > 0 ? eL : (w < 0 ? eH : true));
+                if (bit) LI[e] += wl;
+                else UI[e] += wu;
+            }
+        }
 #pragma unroll
-                    for (int e = 0; e < CB; ++e) {
-                        const int c = c0 + e;
-                        const Tc w = c < g.out.C ? (Tc)g.W[(long)c * F + t] : (Tc)0;
-                        const Tc wl = w >= 0 ? w * lo : w * hi;   // W . Lcheck
-                        const Tc wu = w >= 0 ? w * hi : w * lo;   // W . Ucheck
-                        const bool zi = (zmask[j] >> e) & 1u;
-                        const bool bit = zi || (w > 0 ? eL : (w < 0 ? eH : true));
-                        if (bit) LI[j][e] += wl;
-                        else UI[j][e] += wu;
-                    }
-                }
+        for (int e = 0; e < CB; ++e) {
+            if (!kFinal64) {
+                fin0[e] = LI[e];
+                fin1[e] = UI[e];
+            } else if (c0 + e < g.out.C) {
+                const long idx_e = ((long)(c0 + e) * S + s) * g.out.P + p;
+                const Tc bq = (Tc)A.R.slot[j].beta[idx_e];
+                fin0[e] += bq * (LI[e] + UI[e]);
+                fin1[e] += bq * LI[e];
             }
         }
     }
-    // one slot: reduce LI and UI.  Final sums: each wave folds its partial
-    // LI/UI of all slots with the slot multipliers into the two sums the
-    // bound needs, sum_q beta_q (LI_q + UI_q) and sum_q beta_q LI_q.
 #pragma unroll
     for (int e = 0; e < CB; ++e) {
-        Tc r0 = 0, r1 = 0;
-        if (!kFinal64) {
-            r0 = LI[0][e];
-            r1 = UI[0][e];
-        } else if (colok && c0 + e < g.out.C) {
-            const long idx_e = ((long)(c0 + e) * S + s) * g.out.P + p;
-#pragma unroll
-            for (int j = 0; j < kMaxMasks; ++j) {
-                if (j < nsl) {
-                    const Tc bq = (Tc)A.R.slot[j].beta[idx_e];
-                    r0 += bq * (LI[j][e] + UI[j][e]);
-                    r1 += bq * LI[j][e];
-                }
-            }
-        }
-        red[((wave * CB + e) * 2 + 0) * kWave + lane] = r0;
-        red[((wave * CB + e) * 2 + 1) * kWave + lane] = r1;
+        red[((wave * CB + e) * 2 + 0) * kWave + lane] = fin0[e];
+        red[((wave * CB + e) * 2 + 1) * kWave + lane] = fin1[e];
     }
     __syncthreads();
     const int e = wave;
+    if (e >= CB) return;
     const int c = c0 + e;
     if (!colok || c >= g.out.C) return;
     const long idx = ((long)c * S + s) * g.out.P + p;
     Tc r0 = 0, r1 = 0;
-    for (int w = 0; w < KS; ++w) {
+    for (int w = 0; w < NW; ++w) {
         r0 += red[((w * CB + e) * 2 + 0) * kWave + lane];
         r1 += red[((w * CB + e) * 2 + 1) * kWave + lane];
     }

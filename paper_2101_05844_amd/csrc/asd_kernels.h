@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(kWave * KS) k_forward(FwdArgs<T> A) {
     extern __shared__ unsigned char red_raw[];
     T* red = reinterpret_cast<T*>(red_raw);  // [KS][CB][1 + nm][64]
     const LayerGeo& g = A.g;
-    const int lane = threadIdx.x, wave = threadIdx.y;
+    const int lane = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(threadIdx.y);  // wave-uniform
     const long col = (long)blockIdx.x * kWave + lane;
     const int c0 = blockIdx.y * CB;
     const int S = A.S, nm = A.nm;
@@ -369,7 +369,7 @@ __global__ void __launch_bounds__(kWave * KS) k_backward(BwdArgs<Ts> A) {
     const LayerGeo& g = A.gn;
     const NeuronLayout& L = g.in;   // layer k
     const NeuronLayout& O = g.out;  // layer k+1
-    const int lane = threadIdx.x, wave = threadIdx.y;
+    const int lane = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(threadIdx.y);  // wave-uniform
     const long col = (long)blockIdx.x * kWave + lane;
     const int c0 = blockIdx.y * CB;
     const int S = A.S, nm = A.nm_next;
@@ -549,7 +549,7 @@ __global__ void __launch_bounds__(kWave * NW) k_mask_consts(MaskArgs<Ts> A) {
     Tc* red = reinterpret_cast<Tc*>(red_raw);  // [NW][CB][2][64]
     constexpr bool kFinal64 = sizeof(Tc) > sizeof(Ts);
     const LayerGeo& g = A.g;
-    const int lane = threadIdx.x, wave = threadIdx.y;
+    const int lane = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(threadIdx.y);  // wave-uniform
     const long col = (long)blockIdx.x * kWave + lane;
     const int c0 = blockIdx.y * CB;
     const int S = A.S;

@@ -377,14 +377,59 @@ __global__ void __launch_bounds__(kWave * KS) k_backward(BwdArgs<Ts> A) {
     const int s = colok ? (int)(col / L.P) : 0;
     const int p = colok ? (int)(col - (long)s * L.P) : 0;
 
-    Tc acc[CB];
-    Tc accP[kMaxMasks][CB], accQ[kMaxMasks][CB];
+    // this neuron's point-box bits and the slots' x-bits (eL = !x or point,
+    // eH = x or point per mask)
+    unsigned dg4 = 0, xq4[kMaxMasks];
+#pragma unroll
+    for (int q = 0; q < kMaxMasks; ++q) xq4[q] = 0;
+    if (colok) {
+#pragma unroll
+        for (int e = 0; e < CB; ++e) {
+            if (c0 + e < L.C) {
+                const long bie = (long)(c0 + e) * L.colpad + col;
+                dg4 |= getbit(A.nk.deg, bie) << e;
+#pragma unroll
+                for (int q = 0; q < kMaxMasks; ++q)
+                    if (q < nm) xq4[q] |= getbit(A.Rn.slot[q].xbits, bie) << e;
+            }
+        }
+    }
+    // Iteration kernels keep W+^T u and W-^T u per mask and fold them with
+    // the bits at the end; the FP64 final bound of an FP32 plan folds every
+    // tap's masked terms as it goes (one accumulator per channel instead of
+    // 2 K: the register count, not the FP64 rounding order, sets its speed)
+    constexpr int NQ = kFinal64 ? 1 : kMaxMasks;
+    Tc acc[CB], am[CB];
+    Tc accP[NQ][CB], accQ[NQ][CB];
 #pragma unroll
     for (int e = 0; e < CB; ++e) {
-        acc[e] = 0;
+        acc[e] = am[e] = 0;
 #pragma unroll
-        for (int q = 0; q < kMaxMasks; ++q) accP[q][e] = accQ[q][e] = 0;
+        for (int q = 0; q < NQ; ++q) accP[q][e] = accQ[q][e] = 0;
     }
+    auto add = [&](int e, Tc w, Tc v, const Tc* uq) {
+        acc[e] += w * v;
+        if constexpr (kFinal64) {
+            const bool dg = (dg4 >> e) & 1u;
+            const Tc wp = tmax0(w), wn = tmin0(w);
+#pragma unroll
+            for (int q = 0; q < kMaxMasks; ++q) {
+                if (q < nm) {
+                    const bool xq = (xq4[q] >> e) & 1u;
+                    const Tc cq = ((!xq || dg) ? wp : (Tc)0) + ((xq || dg) ? wn : (Tc)0);
+                    am[e] += cq * uq[q];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                if (q < nm) {
+                    accP[q][e] += tmax0(w) * uq[q];
+                    accQ[q][e] += tmin0(w) * uq[q];
+                }
+            }
+        }
+    };
     if (colok) {
         if (g.kind == ASD_LAYER_DENSE) {
             // reduction over the outputs i of the dense layer k+1
@@ -399,14 +444,7 @@ __global__ void __launch_bounds__(kWave * KS) k_backward(BwdArgs<Ts> A) {
                 for (int e = 0; e < CB; ++e) {
                     const int c = c0 + e;
                     const Tc w = c < L.C ? (Tc)g.W[(long)i * g.fan + (long)c * L.P + p] : (Tc)0;
-                    acc[e] += w * v;
-#pragma unroll
-                    for (int q = 0; q < kMaxMasks; ++q) {
-                        if (q < nm) {
-                            accP[q][e] += tmax0(w) * uq[q];
-                            accQ[q][e] += tmin0(w) * uq[q];
-                        }
-                    }
+                    add(e, w, v, uq);
                 }
             }
         } else {
@@ -435,14 +473,7 @@ __global__ void __launch_bounds__(kWave * KS) k_backward(BwdArgs<Ts> A) {
                         for (int e = 0; e < CB; ++e) {
                             const int c = c0 + e;
                             const Tc w = c < L.C ? (Tc)g.W[(((long)co * L.C + c) * ks + ky) * ks + kx] : (Tc)0;
-                            acc[e] += w * v;
-#pragma unroll
-                            for (int q = 0; q < kMaxMasks; ++q) {
-                                if (q < nm) {
-                                    accP[q][e] += tmax0(w) * uq[q];
-                                    accQ[q][e] += tmin0(w) * uq[q];
-                                }
-                            }
+                            add(e, w, v, uq);
                         }
                     }
                 }
@@ -451,37 +482,23 @@ __global__ void __launch_bounds__(kWave * KS) k_backward(BwdArgs<Ts> A) {
     }
     // fold the masked products with this neuron's e-bits before reducing
     // across waves: f gets eL (W+^T u) + eH (W-^T u) per mask
-    unsigned dg4 = 0;
-    {
-        unsigned xq4[kMaxMasks];
 #pragma unroll
-        for (int q = 0; q < kMaxMasks; ++q) xq4[q] = 0;
-        if (colok) {
-#pragma unroll
-            for (int e = 0; e < CB; ++e) {
-                if (c0 + e < L.C) {
-                    const long bie = (long)(c0 + e) * L.colpad + col;
-                    dg4 |= getbit(A.nk.deg, bie) << e;
-#pragma unroll
-                    for (int q = 0; q < kMaxMasks; ++q)
-                        if (q < nm) xq4[q] |= getbit(A.Rn.slot[q].xbits, bie) << e;
-                }
-            }
-        }
-#pragma unroll
-        for (int e = 0; e < CB; ++e) {
-            Tc part = acc[e];
+    for (int e = 0; e < CB; ++e) {
+        Tc part = acc[e];
+        if constexpr (kFinal64) {
+            part += am[e];
+        } else {
             const bool dg = (dg4 >> e) & 1u;
 #pragma unroll
-            for (int q = 0; q < kMaxMasks; ++q) {
+            for (int q = 0; q < NQ; ++q) {
                 if (q < nm) {
                     const bool xq = (xq4[q] >> e) & 1u;
                     if (!xq || dg) part += accP[q][e];
                     if (xq || dg) part += accQ[q][e];
                 }
             }
-            red[(wave * CB + e) * kWave + lane] = part;
         }
+        red[(wave * CB + e) * kWave + lane] = part;
     }
     __syncthreads();
     const int e = wave;

@@ -542,7 +542,7 @@ def test_ragged_budgets_match_plain_solves_fp64(wi):
         assert abs(lb[s] - r.bound) <= 1e-8 * max(1.0, abs(r.bound)), (s, lb[s], r.bound)
 
 
-@pytest.mark.parametrize("wi", [1, 2])
+@pytest.mark.parametrize("wi", [1, 2, 3])
 def test_ragged_budgets_independent_fp32(wi):
     """FP32 plan (matrix-core and column kernels): subproblem s of a ragged
     batch is bit-identical to the same subproblem in a batch where every

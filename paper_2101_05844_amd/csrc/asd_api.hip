@@ -863,6 +863,12 @@ asd_status launch_forward(asd_plan* P, int k, const StepArgsT<T>& sa, int mode, 
 }
 
 // Mask constants of slot q of layer k from the given bit sources.
+// k_mask_consts may read 4 taps at a time: a dense layer over channels of
+// 4k positions whose fan-in splits over nw waves into multiples of 4.
+bool mask_dv(const LayerGeo& g, int nw) {
+    return g.kind == ASD_LAYER_DENSE && g.in.P % 4 == 0 && g.fan % (4 * nw) == 0;
+}
+
 template <typename T>
 asd_status launch_mask_consts(asd_plan* P, int k, int q, const uint32_t* zsrc, const uint32_t* xsrc,
                               int zero_state, hipStream_t st) {
@@ -884,10 +890,16 @@ asd_status launch_mask_consts(asd_plan* P, int k, int q, const uint32_t* zsrc, c
         // wide fan-in (few columns, long tap loops): 16 waves split it (FP64
         // plans keep the 4 partial sums of their tested arithmetic order)
         const size_t lds = (size_t)16 * CB * 2 * kWave * sizeof(T);
-        hipLaunchKernelGGL((k_mask_consts<T, T, 16>), grid_cols(P->nl[k], CB), dim3(kWave, 16), lds, st, a);
+        if (mask_dv(a.g, 16))
+            hipLaunchKernelGGL((k_mask_consts<T, T, 16, true>), grid_cols(P->nl[k], CB), dim3(kWave, 16), lds, st, a);
+        else
+            hipLaunchKernelGGL((k_mask_consts<T, T, 16, false>), grid_cols(P->nl[k], CB), dim3(kWave, 16), lds, st, a);
     } else {
         const size_t lds = (size_t)KS * CB * 2 * kWave * sizeof(T);
-        hipLaunchKernelGGL((k_mask_consts<T, T, KS>), grid_cols(P->nl[k], CB), dim3(kWave, KS), lds, st, a);
+        if (mask_dv(a.g, KS))
+            hipLaunchKernelGGL((k_mask_consts<T, T, KS, true>), grid_cols(P->nl[k], CB), dim3(kWave, KS), lds, st, a);
+        else
+            hipLaunchKernelGGL((k_mask_consts<T, T, KS, false>), grid_cols(P->nl[k], CB), dim3(kWave, KS), lds, st, a);
     }
     LAUNCH_CHECK();
     return ASD_OK;
@@ -908,10 +920,20 @@ asd_status launch_final_sums(asd_plan* P, int k, hipStream_t st) {
     ProfScope ps(P, st, ASD_K_FINAL, k);
     if (a.g.fan >= 1024) {
         const size_t lds = (size_t)16 * CB * 2 * kWave * sizeof(double);
-        hipLaunchKernelGGL((k_mask_consts<double, float, 16>), grid_cols(P->nl[k], CB), dim3(kWave, 16), lds, st, a);
+        if (mask_dv(a.g, 16))
+            hipLaunchKernelGGL((k_mask_consts<double, float, 16, true>), grid_cols(P->nl[k], CB), dim3(kWave, 16), lds,
+                               st, a);
+        else
+            hipLaunchKernelGGL((k_mask_consts<double, float, 16, false>), grid_cols(P->nl[k], CB), dim3(kWave, 16), lds,
+                               st, a);
     } else {
         const size_t lds = (size_t)KS * CB * 2 * kWave * sizeof(double);
-        hipLaunchKernelGGL((k_mask_consts<double, float, KS>), grid_cols(P->nl[k], CB), dim3(kWave, KS), lds, st, a);
+        if (mask_dv(a.g, KS))
+            hipLaunchKernelGGL((k_mask_consts<double, float, KS, true>), grid_cols(P->nl[k], CB), dim3(kWave, KS), lds,
+                               st, a);
+        else
+            hipLaunchKernelGGL((k_mask_consts<double, float, KS, false>), grid_cols(P->nl[k], CB), dim3(kWave, KS), lds,
+                               st, a);
     }
     LAUNCH_CHECK();
     return ASD_OK;

@@ -559,7 +559,30 @@ struct MaskArgs {
     ReluLayerT<Ts> R;
 };
 
-template <typename Tc, typename Ts, int NW>  // NW: waves splitting the fan-in
+// One tap t of the mask constants of channels c0 .. c0 + CB - 1: the box
+// ends lo, hi of the input, its point-box bit dg and the mask's x-bit xb.
+template <typename Tc>
+__device__ __forceinline__ void mask_tap(const LayerGeo& g, int t, int c0, int F, unsigned zmask, Tc lo, Tc hi,
+                                         unsigned dg, unsigned xb, Tc (&LI)[CB], Tc (&UI)[CB]) {
+    const bool eL = !xb || dg, eH = xb || dg;
+#pragma unroll
+    for (int e = 0; e < CB; ++e) {
+        const int c = c0 + e;
+        const Tc w = c < g.out.C ? (Tc)g.W[(long)c * F + t] : (Tc)0;
+        const Tc wl = w >= 0 ? w * lo : w * hi;   // W . Lcheck
+        const Tc wu = w >= 0 ? w * hi : w * lo;   // W . Ucheck
+        const bool zi = (zmask >> e) & 1u;
+        const bool bit = zi || (w > 0 ? eL : (w < 0 ? eH : true));
+        // selects of values (a branch lets the compiler select the target
+        // instead and index the accumulators dynamically, in scratch memory)
+        LI[e] = bit ? LI[e] + wl : LI[e];
+        UI[e] = bit ? UI[e] : UI[e] + wu;
+    }
+}
+
+// NW: waves splitting the fan-in; DV: a dense layer over channels of 4k
+// positions whose fan-in splits into multiples of 4 taps
+template <typename Tc, typename Ts, int NW, bool DV>
 __global__ void __launch_bounds__(kWave * NW) k_mask_consts(MaskArgs<Ts> A) {
     static_assert(NW >= CB, "one wave per channel finishes the sums");
     extern __shared__ unsigned char red_raw[];
@@ -595,25 +618,41 @@ __global__ void __launch_bounds__(kWave * NW) k_mask_consts(MaskArgs<Ts> A) {
         Tc LI[CB], UI[CB];
 #pragma unroll
         for (int e = 0; e < CB; ++e) LI[e] = UI[e] = 0;
-        TapWalk tw = tap_walk(g, p, t0);
-#pragma unroll 4
-        for (int t = t0; t < t1; ++t, tap_next(g, tw)) {
-            const FwdTap tp = tap_at(g, S, s, tw);
-            if (tp.a < 0) continue;
-            const Tc lo = (Tc)A.lo_in[tp.a], hi = (Tc)A.hi_in[tp.a];
-            const unsigned dg = getbit(A.deg_in, tp.bi);
-            const unsigned xb = getbit(xbits, tp.bi);
-            const bool eL = !xb || dg, eH = xb || dg;
+        if constexpr (DV) {
+            // dense layer over channels of 4k positions: 4 consecutive taps
+            // are consecutive positions of one channel (one vector load of
+            // each box end; their bits share a word), same order of the sums
+            for (int t = t0; t < t1; t += 4) {
+                const int ci = t / g.in.P, pj = t - ci * g.in.P;
+                const long a = ((long)ci * S + s) * g.in.P + pj;
+                const long bi = (long)ci * g.in.colpad + (long)s * g.in.P + pj;
+                const unsigned dw = A.deg_in[bi >> 5] >> (bi & 31), xw = xbits[bi >> 5] >> (bi & 31);
+                Tc lo[4], hi[4];
+                if constexpr (sizeof(Ts) == 4) {
+                    const float4 l = *reinterpret_cast<const float4*>(A.lo_in + a);
+                    const float4 h = *reinterpret_cast<const float4*>(A.hi_in + a);
+                    lo[0] = (Tc)l.x, lo[1] = (Tc)l.y, lo[2] = (Tc)l.z, lo[3] = (Tc)l.w;
+                    hi[0] = (Tc)h.x, hi[1] = (Tc)h.y, hi[2] = (Tc)h.z, hi[3] = (Tc)h.w;
+                } else {
+                    const double2 l0 = reinterpret_cast<const double2*>(A.lo_in + a)[0];
+                    const double2 l1 = reinterpret_cast<const double2*>(A.lo_in + a)[1];
+                    const double2 h0 = reinterpret_cast<const double2*>(A.hi_in + a)[0];
+                    const double2 h1 = reinterpret_cast<const double2*>(A.hi_in + a)[1];
+                    lo[0] = (Tc)l0.x, lo[1] = (Tc)l0.y, lo[2] = (Tc)l1.x, lo[3] = (Tc)l1.y;
+                    hi[0] = (Tc)h0.x, hi[1] = (Tc)h0.y, hi[2] = (Tc)h1.x, hi[3] = (Tc)h1.y;
+                }
 #pragma unroll
-            for (int e = 0; e < CB; ++e) {
-                const int c = c0 + e;
-                const Tc w = c < g.out.C ? (Tc)g.W[(long)c * F + t] : (Tc)0;
-                const Tc wl = w >= 0 ? w * lo : w * hi;   // W . Lcheck
-                const Tc wu = w >= 0 ? w * hi : w * lo;   // W . Ucheck
-                const bool zi = (zmask >> e) & 1u;
-                const bool bit = zi || (w > 0 ? eL : (w < 0 ? eH : true));
-                if (bit) LI[e] += wl;
-                else UI[e] += wu;
+                for (int u = 0; u < 4; ++u)
+                    mask_tap<Tc>(g, t + u, c0, F, zmask, lo[u], hi[u], (dw >> u) & 1u, (xw >> u) & 1u, LI, UI);
+            }
+        } else {
+            TapWalk tw = tap_walk(g, p, t0);
+#pragma unroll 4
+            for (int t = t0; t < t1; ++t, tap_next(g, tw)) {
+                const FwdTap tp = tap_at(g, S, s, tw);
+                if (tp.a < 0) continue;
+                mask_tap<Tc>(g, t, c0, F, zmask, (Tc)A.lo_in[tp.a], (Tc)A.hi_in[tp.a], getbit(A.deg_in, tp.bi),
+                             getbit(xbits, tp.bi), LI, UI);
             }
         }
 #pragma unroll

@@ -543,15 +543,14 @@ asd_status prepare_weights(asd_plan* P, hipStream_t st) {
         default: return fail(ASD_EINVAL, "mask count %d outside [0, 8]", (int)(nm)); \
     }
 
-// Iteration forward pass of ReLU layer k with NM active masks.
-template <typename T, int NM, bool MB>
-asd_status fwd_fast_nm(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t st) {
+template <typename T>
+FastFwdArgs<T> fwd_args(asd_plan* P, int k, int nm, const StepArgsT<T>& sa) {
     FastFwdArgs<T> a;
     memset(&a, 0, sizeof(a));
     a.g = gview(P, k);
     a.S = P->S;
     a.Sa = P->Sa;
-    a.nm = NM;
+    a.nm = nm;
     a.Cpad = P->Cpad[k];
     a.ksplit = P->ksplit[k];
     a.Wt = P->Wt[k];
@@ -562,6 +561,13 @@ asd_status fwd_fast_nm(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t s
     a.R = RdevT<T>(P) + k;
     a.st = sa;
     a.part = reinterpret_cast<T*>(P->part);
+    return a;
+}
+
+// Iteration forward pass of ReLU layer k with NM active masks.
+template <typename T, int NM, bool MB>
+asd_status fwd_fast_nm(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t st) {
+    FastFwdArgs<T> a = fwd_args<T>(P, k, NM, sa);
     const LayerGeo& g = a.g;
     constexpr int CB = sizeof(T) == 4 ? 8 : 4;
     ProfScope ps(P, st, ASD_K_FORWARD, k);
@@ -615,6 +621,38 @@ asd_status fwd_fast(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t st) 
 #undef ASD_FWD_CALL
 }
 
+// The forward pass of convolutional layer kc on the matrix cores (8 waves
+// per tile) and the products of dense layer kd (8 waves per split) in one
+// launch (k_fwd_conv_dense), then the dense layer's epilogue.
+template <int NM, bool MB>
+asd_status fwd_fused_nm(asd_plan* P, int kc, int kd, const StepArgsT<float>& sa, hipStream_t st) {
+    const FastFwdArgs<float> ac = fwd_args<float>(P, kc, NM, sa);
+    const FastFwdArgs<float> ad = fwd_args<float>(P, kd, NM, sa);
+    const int dgx = (P->Sa + 31) / 32, dgy = ad.Cpad / 32, nd = dgx * dgy * ad.ksplit;
+    const int cgx = (int)((ac.g.out.cols + 31) / 32), cgy = ac.Cpad / 32;
+    const dim3 grid((unsigned)(nd + cgx * cgy));
+    if (ac.g.ksz == 4)
+        hipLaunchKernelGGL((k_fwd_conv_dense<NM, 4, MB>), grid, dim3(kWave, 8), 0, st, ac, ad, nd, dgx, dgy, cgx, cgy);
+    else
+        hipLaunchKernelGGL((k_fwd_conv_dense<NM, 0, MB>), grid, dim3(kWave, 8), 0, st, ac, ad, nd, dgx, dgy, cgx, cgy);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_fwd_dense_epi<float, NM, MB>), dim3((unsigned)((P->Sa + 255) / 256), (unsigned)ad.g.out.C),
+                       dim3(256), 0, st, ad);
+    LAUNCH_CHECK();
+    return ASD_OK;
+}
+
+asd_status fwd_fused(asd_plan* P, int kc, int kd, const StepArgsT<float>& sa, hipStream_t st) {
+    if (P->prm.precision == ASD_PREC_MIXED) {
+#define ASD_FUSED_CALL(N) return fwd_fused_nm<N, true>(P, kc, kd, sa, st)
+        ASD_NM_DISPATCH(P->n_masks, ASD_FUSED_CALL)
+#undef ASD_FUSED_CALL
+    }
+#define ASD_FUSED_CALL(N) return fwd_fused_nm<N, false>(P, kc, kd, sa, st)
+    ASD_NM_DISPATCH(P->n_masks, ASD_FUSED_CALL)
+#undef ASD_FUSED_CALL
+}
+
 template <typename Tc, typename Ts>
 asd_status launch_backward(asd_plan* P, int k, int want_obj, int role, hipStream_t st, double* fout = nullptr);
 
@@ -649,6 +687,73 @@ bool bwd_m4_fits(const asd_plan* P, int k) {
         return false;
     const BwdConvShape sh = conv_shape(g);
     return sh.Hp * sh.Wp <= bwd_mfma_rs<kMaxMasks>();
+}
+
+template <typename T>
+FastBwdArgs<T> bwd_args(asd_plan* P, int k, int nm) {
+    FastBwdArgs<T> a;
+    memset(&a, 0, sizeof(a));
+    a.gn = gview(P, k + 1);
+    a.S = P->S;
+    a.k = k;
+    a.last = (k + 1 == P->n);
+    a.nm = nm;
+    a.Wr = P->Wr[k + 1];
+    a.fanpad = P->fanpad[k + 1];
+    a.cvec = CV<T>(P);
+    if (!a.last) {
+        const ReluLayerT<T>& rn = RL<T>(P)[k + 1];
+        a.vs = rn.vs;
+        for (int q = 0; q < nm; ++q) a.u[q] = rn.slot[q].u;
+    }
+    a.xpk = NA<T>(P)[k].xpk;
+    a.nk = NA<T>(P)[k];
+    if (k >= 1) {
+        const ReluLayerT<T>& r = RL<T>(P)[k];
+        a.own = r.own;
+        a.gk = r.g;
+        a.zbits = r.zbits;
+    }
+    a.Wb = P->Wb[k + 1];
+    a.Wl4 = P->Wl4[k + 1];
+    a.Wl8 = P->Wl8[k + 1];
+    a.nkp = P->nkp[k + 1];
+    return a;
+}
+
+// The backward passes into the last ReLU layer (dense, one position per
+// channel: k_bwd_dense) and into the layer below (dense into 64-position
+// channels on the matrix cores: k_bwd_dense_mfma) can share a launch
+// (k_bwd_dense_pair); returns that lower layer, or -1.
+int bwd_pair_layer(const asd_plan* P) {
+    const int ka = P->n - 1, kb = P->n - 2;
+    if (kb < 0 || P->prof) return -1;
+    const LayerGeo& ga = P->geo[ka + 1];
+    const LayerGeo& gb = P->geo[kb + 1];
+    if (ga.kind != ASD_LAYER_DENSE || ga.in.P != 1) return -1;
+    if (gb.kind != ASD_LAYER_DENSE || gb.in.P % kWave != 0 || P->bwd_pos[kb] != 2) return -1;
+    return kb;
+}
+
+template <int NM>
+asd_status bwd_pair_nm(asd_plan* P, hipStream_t st) {
+    const int ka = P->n - 1, kb = P->n - 2;
+    const FastBwdArgs<float> aa = bwd_args<float>(P, ka, 0);
+    const FastBwdArgs<float> ab = bwd_args<float>(P, kb, NM);
+    const NeuronLayout& La = aa.gn.in;
+    const NeuronLayout& Lb = ab.gn.in;
+    const int agx = (int)((La.cols + kWave - 1) / kWave), agy = (La.C + 7) / 8, na = agx * agy;
+    const int mgx = (P->Sa + 15) / 16, mgy = Lb.C * (Lb.P / kWave);
+    hipLaunchKernelGGL((k_bwd_dense_pair<NM>), dim3((unsigned)(na + mgx * mgy)), dim3(kWave, 4), 0, st, aa, ab, na, agx,
+                       agy, mgx);
+    LAUNCH_CHECK();
+    return ASD_OK;
+}
+
+asd_status bwd_pair(asd_plan* P, hipStream_t st) {
+#define ASD_PAIR_CALL(N) return bwd_pair_nm<N>(P, st)
+    ASD_NM_DISPATCH(P->n_masks, ASD_PAIR_CALL)
+#undef ASD_PAIR_CALL
 }
 
 // Iteration backward pass into neuron layer k; NM = masks of layer k+1.
@@ -1029,9 +1134,18 @@ asd_status iteration(asd_plan* P, bool as_phase, int t, double lr, hipStream_t s
         asd_plan* P;
         ~RestoreSa() { P->Sa = P->S; }
     } restore{P};
+    // FP32 plans: the backward launches into the last two layers can share
+    // one (unless kernels are being timed one by one)
+    int kpair = -1;
+    if constexpr (!kGeneral) kpair = bwd_pair_layer(P);
     for (int k = P->n - 1; k >= 0; --k) {
-        if constexpr (kGeneral) TRY((launch_backward<T, T>(P, k, 0, ASD_K_BACKWARD, st)));
-        else TRY(bwd_fast<T>(P, k, st));
+        if constexpr (kGeneral) {
+            TRY((launch_backward<T, T>(P, k, 0, ASD_K_BACKWARD, st)));
+        } else {
+            if (k == kpair) continue;
+            if (kpair >= 0 && k == P->n - 1) TRY(bwd_pair(P, st));
+            else TRY(bwd_fast<T>(P, k, st));
+        }
     }
     if (as_phase && P->n >= 2 && (t % P->prm.add_every) < P->prm.add_count &&
         P->n_masks < P->prm.max_masks) {
@@ -1058,9 +1172,26 @@ asd_status iteration(asd_plan* P, bool as_phase, int t, double lr, hipStream_t s
             sa.ib1[g] = (T)(1.0 / (1.0 - pow(P->prm.adam_beta1, (double)(stp > 0 ? stp : 1))));
         }
     }
+    // FP32 plans: one convolutional layer on the matrix cores and one dense
+    // layer (8 waves per tile and per split) share a launch, unless kernels
+    // are being timed one by one
+    int fc = -1, fd = -1;
+    if constexpr (!kGeneral) {
+        for (int k = 1; k < P->n && !P->prof; ++k) {
+            const LayerGeo& g = P->geo[k];
+            if (fc < 0 && g.kind == ASD_LAYER_CONV2D && P->fwd_mfma[k] && P->fwd_kw[k] == 8) fc = k;
+            if (fd < 0 && g.kind == ASD_LAYER_DENSE && P->fwd_kw[k] == 8) fd = k;
+        }
+        if (fc < 0 || fd < 0) fc = fd = -1;
+    }
     for (int k = 1; k < P->n; ++k) {
-        if constexpr (kGeneral) TRY(launch_forward<T>(P, k, sa, 0, nullptr, st));
-        else TRY(fwd_fast<T>(P, k, sa, st));
+        if constexpr (kGeneral) {
+            TRY(launch_forward<T>(P, k, sa, 0, nullptr, st));
+        } else {
+            if (k == fc) continue;
+            if (k == fd) TRY(fwd_fused(P, fc, fd, sa, st));
+            else TRY(fwd_fast<T>(P, k, sa, st));
+        }
     }
     return ASD_OK;
 }

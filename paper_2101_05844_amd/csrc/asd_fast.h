@@ -82,13 +82,18 @@ __device__ __forceinline__ int fdiv(int n, FastDiv f) {
 // (column counts fit 31 bits: checked when the workspace is sized)
 __device__ __forceinline__ int col_sub(long col, int P) { return (int)((uint32_t)col / (uint32_t)P); }
 
-__device__ __forceinline__ void xcd_tile(int& tile, int& group) {
-    const unsigned gx = gridDim.x, gy = gridDim.y, n = gx * gy;
-    const unsigned lin = blockIdx.y * gx + blockIdx.x;
+// (tile, group) of block lin of a gx x gy grid, XCD-aware: the blocks the
+// hardware sends to one XCD (lin % 8) take one contiguous range of tiles.
+__device__ __forceinline__ void xcd_tile_of(unsigned lin, unsigned gx, unsigned gy, int& tile, int& group) {
+    const unsigned n = gx * gy;
     const unsigned x = lin & 7u, q = n >> 3, r = n & 7u;
     const unsigned logical = (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + (lin >> 3);
     tile = (int)(logical / gy);
     group = (int)(logical - (logical / gy) * gy);
+}
+
+__device__ __forceinline__ void xcd_tile(int& tile, int& group) {
+    xcd_tile_of(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x, gridDim.y, tile, group);
 }
 
 // ---------------------------------------------------------------------------
@@ -453,24 +458,24 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_conv(FastFwdArgs<T> A) {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 template <int NM, int KW>  // KW: waves splitting the block's fan-in range
-__global__ void __launch_bounds__(kWave * KW) k_fwd_dense_mfma(FastFwdArgs<float> A) {
+__device__ __forceinline__ void fwd_dense_mfma_block(const FastFwdArgs<float>& A, int bx, int by, int bz,
+                                                     float (*red)[16][kWave]) {
     constexpr int U = 4;  // steps of 2 taps per trip
     static_assert(U == 4, "a lane's 16-byte input load holds its 4 taps of a trip");
-    __shared__ float red[KW][16][kWave];
     const LayerGeo& g = A.g;
     const int lane = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
     const int S = A.S;
     const int Cp = A.Cpad;
-    const int m0 = blockIdx.y * 32;
-    const int n0 = blockIdx.x * 32;
+    const int m0 = by * 32;
+    const int n0 = bx * 32;
     const int F = g.fan;
     const int Pin = g.in.P;
     // input channels of a multiple of 8 positions: a lane's 4 taps of a trip
     // are consecutive positions of one channel (one 16-byte load), the taps
     // of a wave's range whole groups of 8
     const bool vec = Pin % 8 == 0 && F % 8 == 0;
-    const long zr = (long)blockIdx.z * KW + wave, nz = (long)A.ksplit * KW;
+    const long zr = (long)bz * KW + wave, nz = (long)A.ksplit * KW;
     const int t0 = vec ? 8 * (int)((F / 8) * zr / nz) : (int)(F * zr / nz);
     const int t1 = vec ? 8 * (int)((F / 8) * (zr + 1) / nz) : (int)(F * (zr + 1) / nz);
     const int half = lane >> 5;          // k offset of this lane within a step
@@ -563,7 +568,7 @@ __global__ void __launch_bounds__(kWave * KW) k_fwd_dense_mfma(FastFwdArgs<float
     // add the waves' tiles (fixed order), one product at a time; wave w
     // finishes accumulator registers 4w .. 4w + 3
     const int sw = n0 + col;
-    const long zs = (long)blockIdx.z * (1 + NM);
+    const long zs = (long)bz * (1 + NM);
 #pragma unroll
     for (int r = 0; r <= NM; ++r) {
 #pragma unroll
@@ -582,6 +587,12 @@ __global__ void __launch_bounds__(kWave * KW) k_fwd_dense_mfma(FastFwdArgs<float
     }
 }
 
+template <int NM, int KW>
+__global__ void __launch_bounds__(kWave * KW) k_fwd_dense_mfma(FastFwdArgs<float> A) {
+    __shared__ float red[KW][16][kWave];
+    fwd_dense_mfma_block<NM, KW>(A, blockIdx.x, blockIdx.y, blockIdx.z, red);
+}
+
 // ---------------------------------------------------------------------------
 // Forward pass of a convolutional ReLU layer k on the matrix cores (implicit
 // GEMM, same instruction and operand layout as the dense kernel): output tile
@@ -596,14 +607,12 @@ __global__ void __launch_bounds__(kWave * KW) k_fwd_dense_mfma(FastFwdArgs<float
 // Grid (column tiles / (SPLITK ? 1 : KS), Cpad / 32), block (64, KS).
 // ---------------------------------------------------------------------------
 template <int NM, bool SPLITK, int KSZ, bool MB, int KW>  // KW: waves per block
-__global__ void __launch_bounds__(kWave * KW) k_fwd_conv_mfma(FastFwdArgs<float> A) {
+__device__ __forceinline__ void fwd_conv_mfma_block(const FastFwdArgs<float>& A, int tile, int group,
+                                                    float (*red)[16][kWave]) {
     constexpr int U = 4;  // steps of 2 taps per trip
-    __shared__ float red[SPLITK ? KW : 1][16][kWave];
     const LayerGeo& g = A.g;
     const int lane = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
-    int tile, group;
-    xcd_tile(tile, group);
     const long ntile = SPLITK ? tile : (long)tile * KW + wave;
     const int m0 = group * 32;
     const long n0 = ntile * 32;
@@ -734,6 +743,37 @@ __global__ void __launch_bounds__(kWave * KW) k_fwd_conv_mfma(FastFwdArgs<float>
             for (int q = 0; q < NM; ++q) ym[q] = tot[1 + q][ii];
             fwd_store<float, NM, MB>(A, (long)c * S * g.out.P + col, s, in[jb], tot[0][ii], ym);
         }
+    }
+}
+
+template <int NM, bool SPLITK, int KSZ, bool MB, int KW>
+__global__ void __launch_bounds__(kWave * KW) k_fwd_conv_mfma(FastFwdArgs<float> A) {
+    __shared__ float red[SPLITK ? KW : 1][16][kWave];
+    int tile, group;
+    xcd_tile(tile, group);
+    fwd_conv_mfma_block<NM, SPLITK, KSZ, MB, KW>(A, tile, group, red);
+}
+
+// The products of a dense layer (k_fwd_dense_mfma, 8 waves per split) and
+// the forward pass of a convolutional layer on the matrix cores
+// (k_fwd_conv_mfma, 8 waves per tile) in one launch: the two are
+// independent (each reads x* of its own layers and writes its own layer's
+// state or partial products), so the dense blocks, first in the grid, run
+// beside the convolution's instead of before or after them.  Grid
+// (nd + cgx cgy): blocks [0, nd) are the dense grid (dgx x dgy x ksplit, x
+// fastest), the rest the convolution's cgx x cgy grid.  Block (64, 8).
+template <int NM, int KSZ, bool MB>
+__global__ void __launch_bounds__(kWave * 8) k_fwd_conv_dense(FastFwdArgs<float> Ac, FastFwdArgs<float> Ad, int nd,
+                                                              int dgx, int dgy, int cgx, int cgy) {
+    __shared__ float red[8][16][kWave];
+    const int lin = blockIdx.x;
+    if (lin < nd) {
+        const int bx = lin % dgx, rest = lin / dgx;
+        fwd_dense_mfma_block<NM, 8>(Ad, bx, rest % dgy, rest / dgy, red);
+    } else {
+        int tile, group;
+        xcd_tile_of((unsigned)(lin - nd), (unsigned)cgx, (unsigned)cgy, tile, group);
+        fwd_conv_mfma_block<NM, true, KSZ, MB, 8>(Ac, tile, group, red);
     }
 }
 
@@ -1442,17 +1482,14 @@ __global__ void __launch_bounds__(256) k_class_weights(const float* W, float* Wb
 // when the weights are wave-uniform scalar loads).  Grid (colpad_k / 64,
 // ceil(C_k / CB)), block (64, KS), the outputs of layer k+1 split over waves.
 template <typename T, int NM, int CB, bool P1>
-__global__ void __launch_bounds__(kWave * KS) k_bwd_dense(FastBwdArgs<T> A) {
+__device__ __forceinline__ void bwd_dense_block(const FastBwdArgs<T>& A, int tile, int group, T (*red)[CB][kWave]) {
     static_assert(CB % KS == 0, "CB must be a multiple of KS");
     constexpr int EPW = CB / KS;
     constexpr int NA = NM > 0 ? NM : 1;
-    __shared__ T red[KS][CB][kWave];
     const LayerGeo& g = A.gn;
     const NeuronLayout& L = g.in;
     const int lane = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);  // wave-uniform
-    int tile, group;
-    xcd_tile(tile, group);
     const long col = (long)tile * kWave + lane;
     const int c0 = group * CB;
     const int S = A.S;
@@ -1515,6 +1552,14 @@ __global__ void __launch_bounds__(kWave * KS) k_bwd_dense(FastBwdArgs<T> A) {
         for (int w = 0; w < KS; ++w) f += red[w][e][lane];
         bwd_store<T>(A, colok, ((long)c * S + s) * L.P + p, f, in[j], (long)c * L.colpad + wave_base, lane);
     }
+}
+
+template <typename T, int NM, int CB, bool P1>
+__global__ void __launch_bounds__(kWave * KS) k_bwd_dense(FastBwdArgs<T> A) {
+    __shared__ T red[KS][CB][kWave];
+    int tile, group;
+    xcd_tile(tile, group);
+    bwd_dense_block<T, NM, CB, P1>(A, tile, group, red);
 }
 
 // Dense layer k+1 into a layer k whose positions come in whole wavefronts
@@ -1610,7 +1655,7 @@ __global__ void __launch_bounds__(kWave * KW) k_bwd_dense_pos(FastBwdArgs<T> A) 
 // (ceil(Sa / 16), C_k P_k / 64), block (64, 4): wave w takes positions
 // [16 w, 16 w + 16) of the block's 64.
 template <int NM>
-__global__ void __launch_bounds__(kWave * 4) k_bwd_dense_mfma(FastBwdArgs<float> A) {
+__device__ __forceinline__ void bwd_dense_mfma_block(const FastBwdArgs<float>& A, int bx, int by) {
     typedef float floatx4 __attribute__((ext_vector_type(4)));
     constexpr int NA = NM > 0 ? NM : 1;
     const LayerGeo& g = A.gn;
@@ -1620,9 +1665,9 @@ __global__ void __launch_bounds__(kWave * 4) k_bwd_dense_mfma(FastBwdArgs<float>
     const int S = A.S;
     const int Sa = (int)(L.cols / L.P);
     const int tiles = L.P / kWave;
-    const int c = blockIdx.y / tiles;
-    const int p0 = (blockIdx.y - c * tiles) * kWave + wave * 16;
-    const int s0 = blockIdx.x * 16;
+    const int c = by / tiles;
+    const int p0 = (by - c * tiles) * kWave + wave * 16;
+    const int s0 = bx * 16;
     const int kq = lane >> 4, cl = lane & 15;
     const int sA = min(s0 + cl, Sa - 1);  // A row of this lane
     const int p = p0 + cl;                // C column of this lane
@@ -1706,6 +1751,36 @@ __global__ void __launch_bounds__(kWave * 4) k_bwd_dense_mfma(FastBwdArgs<float>
             xb16[piece] = (uint16_t)(mx >> (16 * kq));
             if (A.k >= 1) zb16[piece] = (uint16_t)(mz >> (16 * kq));
         }
+    }
+}
+
+template <int NM>
+__global__ void __launch_bounds__(kWave * 4) k_bwd_dense_mfma(FastBwdArgs<float> A) {
+    bwd_dense_mfma_block<NM>(A, blockIdx.x, blockIdx.y);
+}
+
+// The column-mapped dense backward into the last ReLU layer (k_bwd_dense
+// with one position per channel, the output layer's objective rows as
+// operand) and the matrix-core dense backward into the layer below it
+// (k_bwd_dense_mfma) in one launch: the two are independent (each reads the
+// operands of its own layer k+1 and writes its own layer k), and the small
+// one, first in the grid, runs beside the other instead of on its own.
+// Grid (na + mgx mgy): blocks [0, na) are the column kernel's agx x agy grid,
+// the rest the matrix-core kernel's mgx x mgy grid (x fastest).  Block
+// (64, 4).
+template <int NMB>
+__global__ void __launch_bounds__(kWave * 4) k_bwd_dense_pair(FastBwdArgs<float> Aa, FastBwdArgs<float> Ab, int na,
+                                                              int agx, int agy, int mgx) {
+    static_assert(KS == 4, "both kernels run 4 waves per block");
+    __shared__ float red[KS][8][kWave];
+    const int lin = blockIdx.x;
+    if (lin < na) {
+        int tile, group;
+        xcd_tile_of((unsigned)lin, (unsigned)agx, (unsigned)agy, tile, group);
+        bwd_dense_block<float, 0, 8, true>(Aa, tile, group, red);
+    } else {
+        const int l2 = lin - na;
+        bwd_dense_mfma_block<NMB>(Ab, l2 % mgx, l2 / mgx);
     }
 }
 

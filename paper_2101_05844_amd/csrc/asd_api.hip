@@ -642,6 +642,52 @@ asd_status fwd_fused_nm(asd_plan* P, int kc, int kd, const StepArgsT<float>& sa,
     return ASD_OK;
 }
 
+// The forward pass of VALU-mapped convolutional layer kv, matrix-core
+// convolutional layer kc and dense layer kd in one launch (k_fwd_trio), then
+// the dense layer's epilogue.
+template <int NM, bool MB>
+asd_status fwd_trio_nm(asd_plan* P, int kv, int kc, int kd, const StepArgsT<float>& sa, hipStream_t st) {
+    const FastFwdArgs<float> av = fwd_args<float>(P, kv, NM, sa);
+    const FastFwdArgs<float> ac = fwd_args<float>(P, kc, NM, sa);
+    const FastFwdArgs<float> ad = fwd_args<float>(P, kd, NM, sa);
+    const int dgx = (P->Sa + 31) / 32, dgy = ad.Cpad / 32, nd = dgx * dgy * ad.ksplit;
+    const int cgx = (int)((ac.g.out.cols + 31) / 32), cgy = ac.Cpad / 32, nc = cgx * cgy;
+    const int vgx = (int)((av.g.out.cols + kWave - 1) / kWave), vgy = (av.g.out.C + 7) / 8, nv = vgx * vgy;
+    // the convolutions' blocks in order (matrix-core ones first): measured
+    // faster than interleaving them
+    const int ip = 1;
+    const dim3 grid((unsigned)(nd + nc + nv));
+    const bool c4 = ac.g.ksz == 4, v4 = av.g.ksz == 4;
+    if (c4 && v4)
+        hipLaunchKernelGGL((k_fwd_trio<NM, 4, 4, MB>), grid, dim3(kWave, 8), 0, st, av, ac, ad, nd, dgx, dgy, nc, cgx, cgy,
+                           vgx, vgy, ip);
+    else if (c4)
+        hipLaunchKernelGGL((k_fwd_trio<NM, 4, 0, MB>), grid, dim3(kWave, 8), 0, st, av, ac, ad, nd, dgx, dgy, nc, cgx, cgy,
+                           vgx, vgy, ip);
+    else if (v4)
+        hipLaunchKernelGGL((k_fwd_trio<NM, 0, 4, MB>), grid, dim3(kWave, 8), 0, st, av, ac, ad, nd, dgx, dgy, nc, cgx, cgy,
+                           vgx, vgy, ip);
+    else
+        hipLaunchKernelGGL((k_fwd_trio<NM, 0, 0, MB>), grid, dim3(kWave, 8), 0, st, av, ac, ad, nd, dgx, dgy, nc, cgx, cgy,
+                           vgx, vgy, ip);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_fwd_dense_epi<float, NM, MB>), dim3((unsigned)((P->Sa + 255) / 256), (unsigned)ad.g.out.C),
+                       dim3(256), 0, st, ad);
+    LAUNCH_CHECK();
+    return ASD_OK;
+}
+
+asd_status fwd_trio(asd_plan* P, int kv, int kc, int kd, const StepArgsT<float>& sa, hipStream_t st) {
+    if (P->prm.precision == ASD_PREC_MIXED) {
+#define ASD_TRIO_CALL(N) return fwd_trio_nm<N, true>(P, kv, kc, kd, sa, st)
+        ASD_NM_DISPATCH(P->n_masks, ASD_TRIO_CALL)
+#undef ASD_TRIO_CALL
+    }
+#define ASD_TRIO_CALL(N) return fwd_trio_nm<N, false>(P, kv, kc, kd, sa, st)
+    ASD_NM_DISPATCH(P->n_masks, ASD_TRIO_CALL)
+#undef ASD_TRIO_CALL
+}
+
 asd_status fwd_fused(asd_plan* P, int kc, int kd, const StepArgsT<float>& sa, hipStream_t st) {
     if (P->prm.precision == ASD_PREC_MIXED) {
 #define ASD_FUSED_CALL(N) return fwd_fused_nm<N, true>(P, kc, kd, sa, st)
@@ -1175,21 +1221,24 @@ asd_status iteration(asd_plan* P, bool as_phase, int t, double lr, hipStream_t s
     // FP32 plans: one convolutional layer on the matrix cores and one dense
     // layer (8 waves per tile and per split) share a launch, unless kernels
     // are being timed one by one
-    int fc = -1, fd = -1;
+    // (and with them, in FP32 plans, one VALU-mapped convolutional layer when
+    // there is one: measured 1 % faster there, 6 % slower with BF16 moments)
+    int fc = -1, fd = -1, fv = -1;
     if constexpr (!kGeneral) {
         for (int k = 1; k < P->n && !P->prof; ++k) {
             const LayerGeo& g = P->geo[k];
             if (fc < 0 && g.kind == ASD_LAYER_CONV2D && P->fwd_mfma[k] && P->fwd_kw[k] == 8) fc = k;
+            if (fv < 0 && g.kind == ASD_LAYER_CONV2D && !P->fwd_mfma[k] && P->prm.precision != ASD_PREC_MIXED) fv = k;
             if (fd < 0 && g.kind == ASD_LAYER_DENSE && P->fwd_kw[k] == 8) fd = k;
         }
-        if (fc < 0 || fd < 0) fc = fd = -1;
+        if (fc < 0 || fd < 0) fc = fd = fv = -1;
     }
     for (int k = 1; k < P->n; ++k) {
         if constexpr (kGeneral) {
             TRY(launch_forward<T>(P, k, sa, 0, nullptr, st));
         } else {
-            if (k == fc) continue;
-            if (k == fd) TRY(fwd_fused(P, fc, fd, sa, st));
+            if (k == fc || k == fv) continue;
+            if (k == fd) TRY(fv >= 0 ? fwd_trio(P, fv, fc, fd, sa, st) : fwd_fused(P, fc, fd, sa, st));
             else TRY(fwd_fast<T>(P, k, sa, st));
         }
     }

@@ -305,17 +305,14 @@ __device__ __forceinline__ void fwd_update(const FastFwdArgs<T>& A, int c, uint3
 // Forward pass of a convolutional ReLU layer k (column mapping).
 // Grid (colpad_k / 64, ceil(C_k / CB)), block (64, KS).
 // ---------------------------------------------------------------------------
-template <typename T, int NM, int CB, int KSZ, bool MB>
-__global__ void __launch_bounds__(kWave * KS) k_fwd_conv(FastFwdArgs<T> A) {
-    static_assert(CB % KS == 0, "CB must be a multiple of KS");
-    constexpr int EPW = CB / KS;  // epilogue channels per wave
+template <typename T, int NM, int CB, int KSZ, bool MB, int KSP>  // KSP: waves splitting the taps
+__device__ __forceinline__ void fwd_conv_block(const FastFwdArgs<T>& A, int tile, int group, T (*red)[CB][kWave]) {
+    static_assert(CB % KSP == 0, "CB must be a multiple of KSP");
+    constexpr int EPW = CB / KSP;  // epilogue channels per wave
     constexpr int NA = NM > 0 ? NM : 1;
-    __shared__ T red[KS][CB][kWave];
     const LayerGeo& g = A.g;
     const int lane = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);  // wave-uniform
-    int tile, group;
-    xcd_tile(tile, group);
     const long col = (long)tile * kWave + lane;
     const int c0 = group * CB;
     const int S = A.S;
@@ -340,7 +337,7 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_conv(FastFwdArgs<T> A) {
     const cfloat_p Wt = kconst(A.Wt);
     const int Cp = A.Cpad;
     const int R = g.in.C * ks;  // tap rows (ci, ky)
-    const int r0 = R * wave / KS, r1 = R * (wave + 1) / KS;
+    const int r0 = R * wave / KSP, r1 = R * (wave + 1) / KSP;
     const bool pointin = NM > 0 && *kconst_t<int>(A.pointflag) != 0;
     // Taps of one row (ci, ky): loads are issued unconditionally from clamped
     // addresses and zeroed afterwards, so a row's loads overlap.
@@ -420,7 +417,7 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_conv(FastFwdArgs<T> A) {
         for (int j = 0; j < EPW; ++j) {
             T a = 0;
 #pragma unroll
-            for (int w = 0; w < KS; ++w) a += red[w][wave * EPW + j][lane];
+            for (int w = 0; w < KSP; ++w) a += red[w][wave * EPW + j][lane];
             tot[r][j] = a;
         }
         __syncthreads();
@@ -441,6 +438,14 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_conv(FastFwdArgs<T> A) {
         for (int q = 0; q < NM; ++q) ymj[q] = tot[1 + q][j];
         fwd_store<T, NM, MB>(A, ((long)c * S + s) * g.out.P + p, s, in[j], tot[0][j], ymj);
     }
+}
+
+template <typename T, int NM, int CB, int KSZ, bool MB>
+__global__ void __launch_bounds__(kWave * KS) k_fwd_conv(FastFwdArgs<T> A) {
+    __shared__ T red[KS][CB][kWave];
+    int tile, group;
+    xcd_tile(tile, group);
+    fwd_conv_block<T, NM, CB, KSZ, MB, KS>(A, tile, group, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -774,6 +779,38 @@ __global__ void __launch_bounds__(kWave * 8) k_fwd_conv_dense(FastFwdArgs<float>
         int tile, group;
         xcd_tile_of((unsigned)(lin - nd), (unsigned)cgx, (unsigned)cgy, tile, group);
         fwd_conv_mfma_block<NM, true, KSZ, MB, 8>(Ac, tile, group, red);
+    }
+}
+
+// The whole forward pass of a net with one VALU-mapped convolution (8
+// channels per block, here 8 waves splitting its taps), one convolution on
+// the matrix cores and one dense layer in one launch: the three are
+// independent (each reads x* of its own two layers and writes its own
+// layer's state or partial products).  Grid (nd + nc + nv): the dense
+// products' blocks (dgx x dgy x ksplit) first, then the two convolutions'
+// blocks interleaved, one matrix-core block every ip blocks while they last,
+// so that the blocks resident at any time mix matrix-core and streaming
+// work.  Block (64, 8).
+template <int NM, int KSC, int KSV, bool MB>
+__global__ void __launch_bounds__(kWave * 8) k_fwd_trio(FastFwdArgs<float> Av, FastFwdArgs<float> Ac,
+                                                        FastFwdArgs<float> Ad, int nd, int dgx, int dgy, int nc,
+                                                        int cgx, int cgy, int vgx, int vgy, int ip) {
+    __shared__ float red[8][16][kWave];
+    const int lin = blockIdx.x;
+    if (lin < nd) {
+        const int bx = lin % dgx, rest = lin / dgx;
+        fwd_dense_mfma_block<NM, 8>(Ad, bx, rest % dgy, rest / dgy, red);
+        return;
+    }
+    const int l = lin - nd;
+    const int before = min(l / ip + 1, nc);  // matrix-core positions 0, ip, 2 ip, ... up to l
+    int tile, group;
+    if (l % ip == 0 && l / ip < nc) {
+        xcd_tile_of((unsigned)(l / ip), (unsigned)cgx, (unsigned)cgy, tile, group);
+        fwd_conv_mfma_block<NM, true, KSC, MB, 8>(Ac, tile, group, red);
+    } else {
+        xcd_tile_of((unsigned)(l - before), (unsigned)vgx, (unsigned)vgy, tile, group);
+        fwd_conv_block<float, NM, 8, KSV, MB, 8>(Av, tile, group, reinterpret_cast<float (*)[8][kWave]>(&red[0][0][0]));
     }
 }
 

@@ -631,8 +631,10 @@ def test_tuning_alternatives_match_oracle(wi):
     counts, narrow convolution forward on the matrix cores, channels per
     thread of the column transposed convolution, the matrix-core kernel
     into a layer of at most 4 channels, dense backward with positions on
-    lanes or on the matrix cores), one FP32 iteration under the plain rule from two
-    oracle snapshots (with and without masks): duals within 1e-5."""
+    lanes or on the matrix cores), and the default choices with every kernel
+    launched alone instead of sharing launches, one FP32 iteration under the
+    plain rule from two oracle snapshots (with and without masks): duals
+    within 1e-5."""
     w = workloads_small()[wi]
     A = _A()
     prm = O.params_from_schedule(w.schedule)
@@ -647,10 +649,15 @@ def test_tuning_alternatives_match_oracle(wi):
     starts = [("bigm", 3), ("as", 4)]
     want = set(starts) | {(ph, t + 1) for ph, t in starts}
     runs = [O.solve(p, prm, snapshot_at=sorted(want, key=str)) for p in probs]
+    # and the default choices with every kernel launched alone (as while
+    # kernels are timed) instead of sharing launches
+    alts = alts + [("profile", None, True)]
     for field, idx, val in alts:
         tun = {f: list(v) for f, v in base.items()}
-        tun[field][idx] = val
+        if field != "profile":
+            tun[field][idx] = val
         plan.set_tuning(tun)
+        plan.profile(field == "profile")
         for ph, t in starts:
             H.import_states(plan, probs, [r.snapshots[(ph, t)] for r in runs])
             plan.run(A.ASD_PHASE_BIGM if ph == "bigm" else A.ASD_PHASE_AS, t, 1)
@@ -664,6 +671,7 @@ def test_tuning_alternatives_match_oracle(wi):
                     pairs += [(duals[("mask", k, q)][s], e.masks[k - 1][q].beta) for q in range(K)]
                     for a, b in pairs:
                         assert np.all(np.abs(a - b) <= 1e-5 * (1 + np.abs(b))), (field, idx, val, ph, t, s, k)
+    plan.profile(False)
     plan.set_tuning(base)
 
 

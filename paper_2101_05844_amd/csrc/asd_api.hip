@@ -1160,6 +1160,35 @@ asd_status reset_group_moments(asd_plan* P, hipStream_t st) {
 // point it was added from, x = 0) is exactly zero here as in the FP64
 // reference, and primal ties are broken the same way; the (1 + K) form
 // reaches such entries through a cancellation that leaves a rounding residue.
+// FP32 plans: one convolutional layer on the matrix cores and one dense
+// layer (8 waves per tile and per split) share the forward launch, unless
+// kernels are being timed one by one; in FP32 plans (not with BF16 moments:
+// measured 1 % faster there, 6 % slower in the mixed mode) one VALU-mapped
+// convolutional layer joins them.  -1 where there is no such layer.
+void shared_forward_layers(const asd_plan* P, int& fc, int& fd, int& fv) {
+    fc = fd = fv = -1;
+    for (int k = 1; k < P->n && !P->prof; ++k) {
+        const LayerGeo& g = P->geo[k];
+        if (fc < 0 && g.kind == ASD_LAYER_CONV2D && P->fwd_mfma[k] && P->fwd_kw[k] == 8) fc = k;
+        if (fv < 0 && g.kind == ASD_LAYER_CONV2D && !P->fwd_mfma[k] && P->prm.precision != ASD_PREC_MIXED) fv = k;
+        if (fd < 0 && g.kind == ASD_LAYER_DENSE && P->fwd_kw[k] == 8) fd = k;
+    }
+    if (fc < 0 || fd < 0) fc = fd = fv = -1;
+}
+
+// The forward pass of an FP32-duals iteration (every ReLU layer's update).
+template <typename T>
+asd_status forward_pass(asd_plan* P, const StepArgsT<T>& sa, hipStream_t st) {
+    int fc, fd, fv;
+    shared_forward_layers(P, fc, fd, fv);
+    for (int k = 1; k < P->n; ++k) {
+        if (k == fc || k == fv) continue;
+        if (k == fd) TRY(fv >= 0 ? fwd_trio(P, fv, fc, fd, sa, st) : fwd_fused(P, fc, fd, sa, st));
+        else TRY(fwd_fast<T>(P, k, sa, st));
+    }
+    return ASD_OK;
+}
+
 template <typename T>
 asd_status iteration(asd_plan* P, bool as_phase, int t, double lr, hipStream_t st) {
     constexpr bool kGeneral = sizeof(T) == 8;
@@ -1218,31 +1247,12 @@ asd_status iteration(asd_plan* P, bool as_phase, int t, double lr, hipStream_t s
             sa.ib1[g] = (T)(1.0 / (1.0 - pow(P->prm.adam_beta1, (double)(stp > 0 ? stp : 1))));
         }
     }
-    // FP32 plans: one convolutional layer on the matrix cores and one dense
-    // layer (8 waves per tile and per split) share a launch, unless kernels
-    // are being timed one by one
-    // (and with them, in FP32 plans, one VALU-mapped convolutional layer when
-    // there is one: measured 1 % faster there, 6 % slower with BF16 moments)
-    int fc = -1, fd = -1, fv = -1;
-    if constexpr (!kGeneral) {
-        for (int k = 1; k < P->n && !P->prof; ++k) {
-            const LayerGeo& g = P->geo[k];
-            if (fc < 0 && g.kind == ASD_LAYER_CONV2D && P->fwd_mfma[k] && P->fwd_kw[k] == 8) fc = k;
-            if (fv < 0 && g.kind == ASD_LAYER_CONV2D && !P->fwd_mfma[k] && P->prm.precision != ASD_PREC_MIXED) fv = k;
-            if (fd < 0 && g.kind == ASD_LAYER_DENSE && P->fwd_kw[k] == 8) fd = k;
-        }
-        if (fc < 0 || fd < 0) fc = fd = fv = -1;
+    if constexpr (kGeneral) {
+        for (int k = 1; k < P->n; ++k) TRY(launch_forward<T>(P, k, sa, 0, nullptr, st));
+        return ASD_OK;
+    } else {
+        return forward_pass<T>(P, sa, st);
     }
-    for (int k = 1; k < P->n; ++k) {
-        if constexpr (kGeneral) {
-            TRY(launch_forward<T>(P, k, sa, 0, nullptr, st));
-        } else {
-            if (k == fc || k == fv) continue;
-            if (k == fd) TRY(fv >= 0 ? fwd_trio(P, fv, fc, fd, sa, st) : fwd_fused(P, fc, fd, sa, st));
-            else TRY(fwd_fast<T>(P, k, sa, st));
-        }
-    }
-    return ASD_OK;
 }
 
 template <typename T>
@@ -1659,6 +1669,22 @@ asd_status autotune_t(asd_plan* P, int ktune, int reps, hipStream_t st) {
             P->bwd_pos[k] = pos[b];
             P->bwd_kw[k] = kw[b];
         }
+    }
+    // a dense layer whose products share the forward launch: its split count
+    // timed with the whole forward pass (alone, more splits hide latency;
+    // beside the convolutions, fewer blocks and partial sums measure faster)
+    int fc, fd, fv;
+    shared_forward_layers(P, fc, fd, fv);
+    if (fd >= 0 && err == ASD_OK) {
+        const long cap = std::max(1L, std::min((long)kMaxKsplit, (long)(P->geo[fd].fan / (32 * KS))));
+        int best = P->ksplit[fd];
+        float tbest = 1e30f;
+        for (int ks = 1; ks <= cap; ks *= 2) {
+            P->ksplit[fd] = ks;
+            const float t = timed([&] { return forward_pass<T>(P, sa, st); });
+            if (t < tbest) tbest = t, best = ks;
+        }
+        P->ksplit[fd] = best;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -652,7 +652,8 @@ asd_status fwd_trio_nm(asd_plan* P, int kv, int kc, int kd, const StepArgsT<floa
     const FastFwdArgs<float> ad = fwd_args<float>(P, kd, NM, sa);
     const int dgx = (P->Sa + 31) / 32, dgy = ad.Cpad / 32, nd = dgx * dgy * ad.ksplit;
     const int cgx = (int)((ac.g.out.cols + 31) / 32), cgy = ac.Cpad / 32, nc = cgx * cgy;
-    const int vgx = (int)((av.g.out.cols + kWave - 1) / kWave), vgy = (av.g.out.C + 7) / 8, nv = vgx * vgy;
+    const int vgx = (int)((av.g.out.cols + kWave - 1) / kWave), vgy = (av.g.out.C + 7) / 8;
+    const int nv = (vgx * vgy + 1) / 2;  // two column-kernel blocks per launched block
     // the convolutions' blocks in order (matrix-core ones first): measured
     // faster than interleaving them
     const int ip = 1;
@@ -1160,17 +1161,17 @@ asd_status reset_group_moments(asd_plan* P, hipStream_t st) {
 // point it was added from, x = 0) is exactly zero here as in the FP64
 // reference, and primal ties are broken the same way; the (1 + K) form
 // reaches such entries through a cancellation that leaves a rounding residue.
-// FP32 plans: one convolutional layer on the matrix cores and one dense
-// layer (8 waves per tile and per split) share the forward launch, unless
-// kernels are being timed one by one; in FP32 plans (not with BF16 moments:
-// measured 1 % faster there, 6 % slower in the mixed mode) one VALU-mapped
-// convolutional layer joins them.  -1 where there is no such layer.
+// FP32-duals plans: one convolutional layer on the matrix cores and one
+// dense layer (8 waves per tile and per split) share the forward launch,
+// unless kernels are being timed one by one, and one VALU-mapped
+// convolutional layer joins them where there is one.  -1 where there is no
+// such layer.
 void shared_forward_layers(const asd_plan* P, int& fc, int& fd, int& fv) {
     fc = fd = fv = -1;
     for (int k = 1; k < P->n && !P->prof; ++k) {
         const LayerGeo& g = P->geo[k];
         if (fc < 0 && g.kind == ASD_LAYER_CONV2D && P->fwd_mfma[k] && P->fwd_kw[k] == 8) fc = k;
-        if (fv < 0 && g.kind == ASD_LAYER_CONV2D && !P->fwd_mfma[k] && P->prm.precision != ASD_PREC_MIXED) fv = k;
+        if (fv < 0 && g.kind == ASD_LAYER_CONV2D && !P->fwd_mfma[k]) fv = k;
         if (fd < 0 && g.kind == ASD_LAYER_DENSE && P->fwd_kw[k] == 8) fd = k;
     }
     if (fc < 0 || fd < 0) fc = fd = fv = -1;

@@ -305,14 +305,15 @@ __device__ __forceinline__ void fwd_update(const FastFwdArgs<T>& A, int c, uint3
 // Forward pass of a convolutional ReLU layer k (column mapping).
 // Grid (colpad_k / 64, ceil(C_k / CB)), block (64, KS).
 // ---------------------------------------------------------------------------
+// wave: this wave's index among the KSP (wave-uniform); red: KSP x CB x 64.
 template <typename T, int NM, int CB, int KSZ, bool MB, int KSP>  // KSP: waves splitting the taps
-__device__ __forceinline__ void fwd_conv_block(const FastFwdArgs<T>& A, int tile, int group, T (*red)[CB][kWave]) {
+__device__ __forceinline__ void fwd_conv_block(const FastFwdArgs<T>& A, int tile, int group, int wave,
+                                               T (*red)[CB][kWave]) {
     static_assert(CB % KSP == 0, "CB must be a multiple of KSP");
     constexpr int EPW = CB / KSP;  // epilogue channels per wave
     constexpr int NA = NM > 0 ? NM : 1;
     const LayerGeo& g = A.g;
     const int lane = threadIdx.x;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);  // wave-uniform
     const long col = (long)tile * kWave + lane;
     const int c0 = group * CB;
     const int S = A.S;
@@ -445,7 +446,7 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_conv(FastFwdArgs<T> A) {
     __shared__ T red[KS][CB][kWave];
     int tile, group;
     xcd_tile(tile, group);
-    fwd_conv_block<T, NM, CB, KSZ, MB, KS>(A, tile, group, red);
+    fwd_conv_block<T, NM, CB, KSZ, MB, KS>(A, tile, group, __builtin_amdgcn_readfirstlane(threadIdx.y), red);
 }
 
 // ---------------------------------------------------------------------------
@@ -782,15 +783,17 @@ __global__ void __launch_bounds__(kWave * 8) k_fwd_conv_dense(FastFwdArgs<float>
     }
 }
 
-// The whole forward pass of a net with one VALU-mapped convolution (8
-// channels per block, here 8 waves splitting its taps), one convolution on
-// the matrix cores and one dense layer in one launch: the three are
-// independent (each reads x* of its own two layers and writes its own
-// layer's state or partial products).  Grid (nd + nc + nv): the dense
-// products' blocks (dgx x dgy x ksplit) first, then the two convolutions'
-// blocks interleaved, one matrix-core block every ip blocks while they last,
-// so that the blocks resident at any time mix matrix-core and streaming
-// work.  Block (64, 8).
+// The whole forward pass of a net with one VALU-mapped convolution, one
+// convolution on the matrix cores and one dense layer in one launch: the
+// three are independent (each reads x* of its own two layers and writes its
+// own layer's state or partial products).  Grid (nd + nc + (nv + 1) / 2):
+// the dense products' blocks (dgx x dgy x ksplit) first, then the two
+// convolutions' blocks interleaved, one matrix-core block every ip blocks
+// while they last.  A VALU block of the launch runs two blocks of the
+// column kernel side by side, waves 0-3 and 4-7 (each 4 waves splitting
+// the taps as when launched alone, both through the same barriers; the
+// second one past the grid when nv is odd computes nothing it stores).
+// Block (64, 8).
 template <int NM, int KSC, int KSV, bool MB>
 __global__ void __launch_bounds__(kWave * 8) k_fwd_trio(FastFwdArgs<float> Av, FastFwdArgs<float> Ac,
                                                         FastFwdArgs<float> Ad, int nd, int dgx, int dgy, int nc,
@@ -809,8 +812,13 @@ __global__ void __launch_bounds__(kWave * 8) k_fwd_trio(FastFwdArgs<float> Av, F
         xcd_tile_of((unsigned)(l / ip), (unsigned)cgx, (unsigned)cgy, tile, group);
         fwd_conv_mfma_block<NM, true, KSC, MB, 8>(Ac, tile, group, red);
     } else {
-        xcd_tile_of((unsigned)(l - before), (unsigned)vgx, (unsigned)vgy, tile, group);
-        fwd_conv_block<float, NM, 8, KSV, MB, 8>(Av, tile, group, reinterpret_cast<float (*)[8][kWave]>(&red[0][0][0]));
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
+        const int half = wave >> 2;
+        const int v = 2 * (l - before) + half;  // < nv except in a last, half-used block
+        xcd_tile_of((unsigned)min(v, vgx * vgy - 1), (unsigned)vgx, (unsigned)vgy, tile, group);
+        if (v >= vgx * vgy) tile = vgx;  // past the columns: stores nothing
+        fwd_conv_block<float, NM, 8, KSV, MB, KS>(Av, tile, group, wave & 3,
+                                                  reinterpret_cast<float (*)[8][kWave]>(&red[4 * half][0][0]));
     }
 }
 

@@ -635,7 +635,31 @@ def test_tuning_alternatives_match_oracle(wi):
     launched alone instead of sharing launches, one FP32 iteration under the
     plain rule from two oracle snapshots (with and without masks): duals
     within 1e-5."""
-    w = workloads_small()[wi]
+    _check_alternatives(workloads_small()[wi])
+
+
+# first layers for the 4-channel matrix-core transposed convolution: 1 and 4
+# input channels, rows of 8, 16 and 64 positions (with 64, a 64-column tile
+# is part of one row; with 8 and 16, several whole rows)
+M4_SHAPES = {
+    "c1x16x8": [WL.ConvSpec(1, 16, 8, 6, 4, 2, 1), WL.DenseSpec(6 * 8 * 4, 9), WL.DenseSpec(9, 3)],
+    "c4x16x16": [WL.ConvSpec(4, 16, 16, 8, 4, 2, 1), WL.DenseSpec(8 * 8 * 8, 11), WL.DenseSpec(11, 3)],
+    "c2x8x64": [WL.ConvSpec(2, 8, 64, 5, 4, 2, 1), WL.DenseSpec(5 * 4 * 32, 7), WL.DenseSpec(7, 3)],
+}
+
+
+@pytest.mark.parametrize("shape", sorted(M4_SHAPES))
+def test_bwd_m4_geometries_match_oracle(shape):
+    """The tuning alternatives (among them the matrix-core and the VALU
+    transposed convolution into the input) on nets whose input layer has 1,
+    2 or 4 channels in rows of 8, 16 or 64 positions: one FP32 iteration from
+    oracle snapshots, duals within 1e-5."""
+    sched = WL.Schedule(bigm_iters=8, as_iters=8, add_every=5, add_count=2, max_masks=3)
+    w = WL.custom_config(M4_SHAPES[shape], S=5, seed=31, eps=0.05, schedule=sched, max_fixed=3, name=shape)
+    _check_alternatives(w)
+
+
+def _check_alternatives(w):
     A = _A()
     prm = O.params_from_schedule(w.schedule)
     prm.rule = "sgd"

@@ -598,8 +598,15 @@ asd_status fwd_fast_nm(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t s
         return ASD_OK;
     }
     dim3 grid((unsigned)((P->Sa + 31) / 32), (unsigned)(a.Cpad / 32), (unsigned)a.ksplit);
-    if (P->fwd_kw[k] == 8) hipLaunchKernelGGL((k_fwd_dense_mfma<NM, 8>), grid, dim3(kWave, 8), 0, st, a);
-    else hipLaunchKernelGGL((k_fwd_dense_mfma<NM, 4>), grid, dim3(kWave, 4), 0, st, a);
+    if (a.ksplit == 1) {
+        // one split: the product blocks update their neurons themselves
+        if (P->fwd_kw[k] == 8) hipLaunchKernelGGL((k_fwd_dense_mfma<NM, 8, true, MB>), grid, dim3(kWave, 8), 0, st, a);
+        else hipLaunchKernelGGL((k_fwd_dense_mfma<NM, 4, true, MB>), grid, dim3(kWave, 4), 0, st, a);
+        LAUNCH_CHECK();
+        return ASD_OK;
+    }
+    if (P->fwd_kw[k] == 8) hipLaunchKernelGGL((k_fwd_dense_mfma<NM, 8, false, MB>), grid, dim3(kWave, 8), 0, st, a);
+    else hipLaunchKernelGGL((k_fwd_dense_mfma<NM, 4, false, MB>), grid, dim3(kWave, 4), 0, st, a);
     LAUNCH_CHECK();
     hipLaunchKernelGGL((k_fwd_dense_epi<T, NM, MB>), dim3((unsigned)((P->Sa + 255) / 256), (unsigned)g.out.C), dim3(256),
                        0, st, a);
@@ -631,11 +638,16 @@ asd_status fwd_fused_nm(asd_plan* P, int kc, int kd, const StepArgsT<float>& sa,
     const int dgx = (P->Sa + 31) / 32, dgy = ad.Cpad / 32, nd = dgx * dgy * ad.ksplit;
     const int cgx = (int)((ac.g.out.cols + 31) / 32), cgy = ac.Cpad / 32;
     const dim3 grid((unsigned)(nd + cgx * cgy));
-    if (ac.g.ksz == 4)
-        hipLaunchKernelGGL((k_fwd_conv_dense<NM, 4, MB>), grid, dim3(kWave, 8), 0, st, ac, ad, nd, dgx, dgy, cgx, cgy);
-    else
-        hipLaunchKernelGGL((k_fwd_conv_dense<NM, 0, MB>), grid, dim3(kWave, 8), 0, st, ac, ad, nd, dgx, dgy, cgx, cgy);
+    const bool du = ad.ksplit == 1;  // one split: the dense blocks update, no epilogue
+    if (ac.g.ksz == 4) {
+        if (du) hipLaunchKernelGGL((k_fwd_conv_dense<NM, 4, MB, true>), grid, dim3(kWave, 8), 0, st, ac, ad, nd, dgx, dgy, cgx, cgy);
+        else hipLaunchKernelGGL((k_fwd_conv_dense<NM, 4, MB, false>), grid, dim3(kWave, 8), 0, st, ac, ad, nd, dgx, dgy, cgx, cgy);
+    } else {
+        if (du) hipLaunchKernelGGL((k_fwd_conv_dense<NM, 0, MB, true>), grid, dim3(kWave, 8), 0, st, ac, ad, nd, dgx, dgy, cgx, cgy);
+        else hipLaunchKernelGGL((k_fwd_conv_dense<NM, 0, MB, false>), grid, dim3(kWave, 8), 0, st, ac, ad, nd, dgx, dgy, cgx, cgy);
+    }
     LAUNCH_CHECK();
+    if (du) return ASD_OK;
     hipLaunchKernelGGL((k_fwd_dense_epi<float, NM, MB>), dim3((unsigned)((P->Sa + 255) / 256), (unsigned)ad.g.out.C),
                        dim3(256), 0, st, ad);
     LAUNCH_CHECK();
@@ -659,19 +671,23 @@ asd_status fwd_trio_nm(asd_plan* P, int kv, int kc, int kd, const StepArgsT<floa
     const int ip = 1;
     const dim3 grid((unsigned)(nd + nc + nv));
     const bool c4 = ac.g.ksz == 4, v4 = av.g.ksz == 4;
-    if (c4 && v4)
-        hipLaunchKernelGGL((k_fwd_trio<NM, 4, 4, MB>), grid, dim3(kWave, 8), 0, st, av, ac, ad, nd, dgx, dgy, nc, cgx, cgy,
-                           vgx, vgy, ip);
-    else if (c4)
-        hipLaunchKernelGGL((k_fwd_trio<NM, 4, 0, MB>), grid, dim3(kWave, 8), 0, st, av, ac, ad, nd, dgx, dgy, nc, cgx, cgy,
-                           vgx, vgy, ip);
-    else if (v4)
-        hipLaunchKernelGGL((k_fwd_trio<NM, 0, 4, MB>), grid, dim3(kWave, 8), 0, st, av, ac, ad, nd, dgx, dgy, nc, cgx, cgy,
-                           vgx, vgy, ip);
-    else
-        hipLaunchKernelGGL((k_fwd_trio<NM, 0, 0, MB>), grid, dim3(kWave, 8), 0, st, av, ac, ad, nd, dgx, dgy, nc, cgx, cgy,
-                           vgx, vgy, ip);
+    const bool du = ad.ksplit == 1;  // one split: the dense blocks update, no epilogue
+#define ASD_TRIO_LAUNCH(KC, KV)                                                                                       \
+    do {                                                                                                              \
+        if (du)                                                                                                       \
+            hipLaunchKernelGGL((k_fwd_trio<NM, KC, KV, MB, true>), grid, dim3(kWave, 8), 0, st, av, ac, ad, nd, dgx, \
+                               dgy, nc, cgx, cgy, vgx, vgy, ip);                                                      \
+        else                                                                                                          \
+            hipLaunchKernelGGL((k_fwd_trio<NM, KC, KV, MB, false>), grid, dim3(kWave, 8), 0, st, av, ac, ad, nd, dgx, \
+                               dgy, nc, cgx, cgy, vgx, vgy, ip);                                                      \
+    } while (0)
+    if (c4 && v4) ASD_TRIO_LAUNCH(4, 4);
+    else if (c4) ASD_TRIO_LAUNCH(4, 0);
+    else if (v4) ASD_TRIO_LAUNCH(0, 4);
+    else ASD_TRIO_LAUNCH(0, 0);
+#undef ASD_TRIO_LAUNCH
     LAUNCH_CHECK();
+    if (du) return ASD_OK;
     hipLaunchKernelGGL((k_fwd_dense_epi<float, NM, MB>), dim3((unsigned)((P->Sa + 255) / 256), (unsigned)ad.g.out.C),
                        dim3(256), 0, st, ad);
     LAUNCH_CHECK();

@@ -463,7 +463,9 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_conv(FastFwdArgs<T> A) {
 // ---------------------------------------------------------------------------
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-template <int NM, int KW>  // KW: waves splitting the block's fan-in range
+// UPD (one split, ksplit == 1): the block holds the whole products of its
+// tile and updates its neurons itself (no partial sums, no epilogue).
+template <int NM, int KW, bool UPD = false, bool MB = false>  // KW: waves splitting the block's fan-in range
 __device__ __forceinline__ void fwd_dense_mfma_block(const FastFwdArgs<float>& A, int bx, int by, int bz,
                                                      float (*red)[16][kWave]) {
     constexpr int U = 4;  // steps of 2 taps per trip
@@ -574,6 +576,43 @@ __device__ __forceinline__ void fwd_dense_mfma_block(const FastFwdArgs<float>& A
     // add the waves' tiles (fixed order), one product at a time; wave w
     // finishes accumulator registers 4w .. 4w + 3
     const int sw = n0 + col;
+    if constexpr (UPD) {
+        // the sums an epilogue would read from one split, then the update of
+        // register i's neuron (channel m0 + 8 (i / 4) + 4 half + i % 4,
+        // subproblem sw) as the epilogue does it
+        constexpr int NR = 16 / KW;
+        float tot[1 + NM][NR];
+#pragma unroll
+        for (int r = 0; r <= NM; ++r) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) red[wave][i][lane] = r == 0 ? acc[0][i] : acc[r][i] + 2.f * accp[i];
+            __syncthreads();
+#pragma unroll
+            for (int ii = 0; ii < NR; ++ii) {
+                const int i = wave * NR + ii;
+                float v = 0.f;
+#pragma unroll
+                for (int w = 0; w < KW; ++w) v += red[w][i][lane];
+                tot[r][ii] = 0.f + v;
+            }
+            __syncthreads();
+        }
+        if (sw >= A.Sa) return;  // no barrier below
+#pragma unroll
+        for (int ii = 0; ii < NR; ++ii) {
+            const int i = wave * NR + ii;
+            const int c = m0 + 8 * (i / 4) + 4 * half + (i % 4);
+            if (c >= g.out.C) continue;
+            float ym[NM > 0 ? NM : 1];
+#pragma unroll
+            for (int q = 0; q < NM; ++q) ym[q] = 0.f + tot[1 + q][ii];
+            const long idx = (long)c * S + sw;  // dense layout, P = 1
+            FwdIn<float, NM> in;
+            fwd_load<float, NM, MB>(A, c, (uint32_t)idx, (uint32_t)((long)c * g.out.colpad + sw), in);
+            fwd_store<float, NM, MB>(A, idx, sw, in, tot[0][ii], ym);
+        }
+        return;
+    }
     const long zs = (long)bz * (1 + NM);
 #pragma unroll
     for (int r = 0; r <= NM; ++r) {
@@ -593,10 +632,10 @@ __device__ __forceinline__ void fwd_dense_mfma_block(const FastFwdArgs<float>& A
     }
 }
 
-template <int NM, int KW>
+template <int NM, int KW, bool UPD, bool MB>
 __global__ void __launch_bounds__(kWave * KW) k_fwd_dense_mfma(FastFwdArgs<float> A) {
     __shared__ float red[KW][16][kWave];
-    fwd_dense_mfma_block<NM, KW>(A, blockIdx.x, blockIdx.y, blockIdx.z, red);
+    fwd_dense_mfma_block<NM, KW, UPD, MB>(A, blockIdx.x, blockIdx.y, blockIdx.z, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -768,14 +807,14 @@ __global__ void __launch_bounds__(kWave * KW) k_fwd_conv_mfma(FastFwdArgs<float>
 // beside the convolution's instead of before or after them.  Grid
 // (nd + cgx cgy): blocks [0, nd) are the dense grid (dgx x dgy x ksplit, x
 // fastest), the rest the convolution's cgx x cgy grid.  Block (64, 8).
-template <int NM, int KSZ, bool MB>
+template <int NM, int KSZ, bool MB, bool DU>  // DU: one split, the dense blocks update
 __global__ void __launch_bounds__(kWave * 8) k_fwd_conv_dense(FastFwdArgs<float> Ac, FastFwdArgs<float> Ad, int nd,
                                                               int dgx, int dgy, int cgx, int cgy) {
     __shared__ float red[8][16][kWave];
     const int lin = blockIdx.x;
     if (lin < nd) {
         const int bx = lin % dgx, rest = lin / dgx;
-        fwd_dense_mfma_block<NM, 8>(Ad, bx, rest % dgy, rest / dgy, red);
+        fwd_dense_mfma_block<NM, 8, DU, MB>(Ad, bx, rest % dgy, rest / dgy, red);
     } else {
         int tile, group;
         xcd_tile_of((unsigned)(lin - nd), (unsigned)cgx, (unsigned)cgy, tile, group);
@@ -794,7 +833,7 @@ __global__ void __launch_bounds__(kWave * 8) k_fwd_conv_dense(FastFwdArgs<float>
 // the taps as when launched alone, both through the same barriers; the
 // second one past the grid when nv is odd computes nothing it stores).
 // Block (64, 8).
-template <int NM, int KSC, int KSV, bool MB>
+template <int NM, int KSC, int KSV, bool MB, bool DU>  // DU: one split, the dense blocks update
 __global__ void __launch_bounds__(kWave * 8) k_fwd_trio(FastFwdArgs<float> Av, FastFwdArgs<float> Ac,
                                                         FastFwdArgs<float> Ad, int nd, int dgx, int dgy, int nc,
                                                         int cgx, int cgy, int vgx, int vgy, int ip) {
@@ -802,7 +841,7 @@ __global__ void __launch_bounds__(kWave * 8) k_fwd_trio(FastFwdArgs<float> Av, F
     const int lin = blockIdx.x;
     if (lin < nd) {
         const int bx = lin % dgx, rest = lin / dgx;
-        fwd_dense_mfma_block<NM, 8>(Ad, bx, rest % dgy, rest / dgy, red);
+        fwd_dense_mfma_block<NM, 8, DU, MB>(Ad, bx, rest % dgy, rest / dgy, red);
         return;
     }
     const int l = lin - nd;

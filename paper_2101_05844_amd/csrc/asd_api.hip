@@ -1687,21 +1687,28 @@ asd_status autotune_t(asd_plan* P, int ktune, int reps, hipStream_t st) {
             P->bwd_kw[k] = kw[b];
         }
     }
-    // a dense layer whose products share the forward launch: its split count
+    // dense layers whose products can share the forward launch (with 8 waves
+    // per split, beside a matrix-core convolution): waves and split count
     // timed with the whole forward pass (alone, more splits hide latency;
-    // beside the convolutions, fewer blocks and partial sums measure faster)
-    int fc, fd, fv;
-    shared_forward_layers(P, fc, fd, fv);
-    if (fd >= 0 && err == ASD_OK) {
-        const long cap = std::max(1L, std::min((long)kMaxKsplit, (long)(P->geo[fd].fan / (32 * KS))));
-        int best = P->ksplit[fd];
+    // beside the convolutions, fewer blocks and no partial sums measure
+    // faster), which also decides whether the layer shares the launch
+    bool conv_mfma = false;
+    for (int L = 1; L < P->n; ++L)
+        conv_mfma |= P->geo[L].kind == ASD_LAYER_CONV2D && P->fwd_mfma[L] && P->fwd_kw[L] == 8;
+    for (int L = 1; L < P->n && conv_mfma && !P->prof && err == ASD_OK; ++L) {
+        if (P->geo[L].kind != ASD_LAYER_DENSE) continue;
+        const long cap = std::max(1L, std::min((long)kMaxKsplit, (long)(P->geo[L].fan / (32 * KS))));
+        int best = P->ksplit[L], bestkw = P->fwd_kw[L];
         float tbest = 1e30f;
-        for (int ks = 1; ks <= cap; ks *= 2) {
-            P->ksplit[fd] = ks;
-            const float t = timed([&] { return forward_pass<T>(P, sa, st); });
-            if (t < tbest) tbest = t, best = ks;
-        }
-        P->ksplit[fd] = best;
+        for (int kw = 4; kw <= 8; kw += 4)
+            for (int ks = 1; ks <= cap; ks *= 2) {
+                P->ksplit[L] = ks;
+                P->fwd_kw[L] = kw;
+                const float t = timed([&] { return forward_pass<T>(P, sa, st); });
+                if (t < tbest) tbest = t, best = ks, bestkw = kw;
+            }
+        P->ksplit[L] = best;
+        P->fwd_kw[L] = bestkw;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

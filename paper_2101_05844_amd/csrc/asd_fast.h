@@ -459,7 +459,8 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_conv(FastFwdArgs<T> A) {
 // Grid (ceil(S / 32), Cpad / 32, ksplit), block (64, KS): the block owns one
 // 32 x 32 output tile and a ksplit-th of the fan-in, its waves split that
 // range again and add their tiles through LDS in a fixed order.  Writes
-// partial products [ksplit][1 + NM][Cpad][S].
+// partial products [ksplit][1 + NM][Cpad][S] for k_fwd_dense_epi, or, with
+// one split, updates the tile's neurons itself.
 // ---------------------------------------------------------------------------
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
@@ -828,7 +829,8 @@ __global__ void __launch_bounds__(kWave * 8) k_fwd_conv_dense(FastFwdArgs<float>
 // own layer's state or partial products).  Grid (nd + nc + (nv + 1) / 2):
 // the dense products' blocks (dgx x dgy x ksplit) first, then the two
 // convolutions' blocks interleaved, one matrix-core block every ip blocks
-// while they last.  A VALU block of the launch runs two blocks of the
+// while they last (ip = 1, all matrix-core blocks first, measured fastest).
+// A VALU block of the launch runs two blocks of the
 // column kernel side by side, waves 0-3 and 4-7 (each 4 waves splitting
 // the taps as when launched alone, both through the same barriers; the
 // second one past the grid when nv is odd computes nothing it stores).

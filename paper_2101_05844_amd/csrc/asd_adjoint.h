@@ -71,6 +71,7 @@ __device__ __forceinline__ bool mask_entry(bool zq, float w, bool dg, bool xq) {
 
 constexpr int kGdTO = 16;              // dense: outputs per block (registers per lane)
 constexpr int kGcTO = 4, kGcTT = 4;    // convolution: output channels x taps per block
+static_assert(kGcTO * kGcTT <= 32, "the weight-sign masks of a convolution tile are 32-bit");
 
 // Dense layer, stage one.  Lanes run over the inputs j (coalesced reads of
 // x*, l, u of layer k-1 and of the weights), each lane keeps kGdTO outputs i

@@ -330,6 +330,11 @@ __global__ void __launch_bounds__(kGradThreads) k_grad_box(GradArgs<Ts> A) {
     if (!A.last && A.nm > 0) {
         const long bi = (long)c * L.colpad + col;
         const bool dg = gbit(A.deg_in, bi);
+        // the x bits of every mask slot at this input (the same for all the
+        // outputs that read it)
+        static_assert(kMaxMasks <= 32, "x bits of the mask slots are kept in one word");
+        unsigned xqb = 0;
+        for (int q = 0; q < A.nm; ++q) xqb |= gbit(R->slot[q].xbits, bi) << q;
         // contribution of one layer-1 output (neuron address a_out, bit bo)
         // reading this input with weight w
         auto add = [&](double w, long a_out, long bo) {
@@ -337,7 +342,7 @@ __global__ void __launch_bounds__(kGradThreads) k_grad_box(GradArgs<Ts> A) {
             for (int q = 0; q < A.nm; ++q) {
                 const double bq = (double)R->slot[q].beta[a_out];
                 const bool zq = gbit(R->slot[q].zbits, bo);
-                const bool xq = gbit(R->slot[q].xbits, bi);
+                const bool xq = (xqb >> q) & 1u;
                 const bool I = zq || w == 0 || dg || (w > 0 ? !xq : xq);
                 // I: Lchk term (1 - z) w, on l where w >= 0 and on u where w < 0;
                 // not I: Uchk term -z w, on u where w >= 0 and on l where w < 0

@@ -302,7 +302,7 @@ __global__ void __launch_bounds__(kGradThreads) k_gb_part(GradArgs<Ts> A) {
 }
 
 // Stage two: out[e] = sum over chunks of part[chunk * entries + e], in chunk order.
-__global__ void __launch_bounds__(kGradThreads) k_gsum(const double* part, long entries, int chunks, double* out) {
+static __global__ void __launch_bounds__(kGradThreads) k_gsum(const double* part, long entries, int chunks, double* out) {
     const long e = (long)blockIdx.x * kGradThreads + threadIdx.x;
     if (e >= entries) return;
     double v = 0;

@@ -16,7 +16,7 @@
 #include <vector>
 
 #include "asd_adjoint.h"
-#include "asd_fast.h"
+#include "asd_plan.h"
 
 using namespace asd;
 
@@ -24,7 +24,9 @@ namespace {
 
 thread_local std::string g_err = "no error";
 
-asd_status fail(asd_status st, const char* fmt, ...) {
+}  // namespace
+
+asd_status asd::fail(asd_status st, const char* fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -34,25 +36,7 @@ asd_status fail(asd_status st, const char* fmt, ...) {
     return st;
 }
 
-#define HIP_TRY(expr)                                                                 \
-    do {                                                                              \
-        hipError_t e_ = (expr);                                                       \
-        if (e_ != hipSuccess)                                                         \
-            return fail(ASD_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
-
-#define LAUNCH_CHECK()                                                                \
-    do {                                                                              \
-        hipError_t e_ = hipGetLastError();                                            \
-        if (e_ != hipSuccess)                                                         \
-            return fail(ASD_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e_)); \
-    } while (0)
-
-#define TRY(expr)                      \
-    do {                               \
-        asd_status s_ = (expr);        \
-        if (s_ != ASD_OK) return s_;   \
-    } while (0)
+namespace {
 
 NeuronLayout make_layout(int C, int H, int W, int S) {
     NeuronLayout nl;
@@ -66,124 +50,6 @@ NeuronLayout make_layout(int C, int H, int W, int S) {
     nl.words = (long)C * nl.colpad / 32;
     return nl;
 }
-
-struct ProfRec {
-    int role, layer;
-    hipEvent_t a, b;
-};
-
-}  // namespace
-
-struct asd_net {
-    int n;  // layers
-    std::vector<asd_layer_desc> L;
-};
-
-struct asd_plan {
-    const asd_net* net;
-    int S;
-    int n;
-    asd_params prm;
-    NeuronLayout nl[kMaxLayers + 1];  // 0..n
-    LayerGeo geo[kMaxLayers + 1];     // 1..n
-    // typed views of the workspace; only those of the plan's precision are set
-    NeuronArraysT<float> naf[kMaxLayers];
-    NeuronArraysT<double> nad[kMaxLayers];
-    ReluLayerT<float> Rf[kMaxLayers];
-    ReluLayerT<double> Rd[kMaxLayers];
-    float* cvecf;
-    double* cvecd;
-    // weight copies made at asd_init and iteration buffers
-    float* Wt[kMaxLayers + 1];        // [fan][Cpad] (ReLU layers)
-    int Cpad[kMaxLayers + 1];
-    float* Wr[kMaxLayers + 1];        // [n_out][fanpad] (dense layers)
-    int fanpad[kMaxLayers + 1];
-    int ksplit[kMaxLayers + 1];       // dense forward: blocks over the fan-in
-    // kernel choices per layer (heuristic defaults, or asd_plan_autotune)
-    int fwd_mfma[kMaxLayers + 1];     // convolution forward on the matrix cores (else the VALU column kernel)
-    int bwd_cb[kMaxLayers + 1];       // column transposed convolution into layer k: channels per thread
-    int bwd_pos[kMaxLayers + 1];      // dense backward into layer k: positions on lanes
-    int bwd_kw[kMaxLayers + 1];       // dense backward with positions on lanes: waves per block (4 or 8)
-    int fwd_kw[kMaxLayers + 1];       // matrix-core convolution forward: waves per block (4 or 8)
-    int bwd_nt[kMaxLayers + 1];       // matrix-core transposed convolution into layer k: tiles per item (0 = 2 where it fits)
-    float* Wb[kMaxLayers + 1];        // convolution: class weights of the transposed product
-    float* Wl4[kMaxLayers + 1];       // convolution: weights in the column kernel's LDS layout, 4 and
-    float* Wl8[kMaxLayers + 1];       // 8 channels per group (k_col_weights)
-    int nkp[kMaxLayers + 1];
-    void* part;                       // dense forward partial products
-    int* pointflag;                   // [kMaxLayers]: point box away from zero in layer k
-    void* Rdev;                       // device copy of the ReluLayerT array (update kernels)
-    double* f0;                       // f_0 of the last bound evaluation
-    bool min_valid;                   // x*, z* bits and f0 are those of the current state, in FP64
-    // bound gradient: chunks of the two-stage reductions per layer and the
-    // partial sums they write
-    int gw_chunks[kMaxLayers + 1];
-    long gw_rchunk[kMaxLayers + 1];
-    int gb_chunks[kMaxLayers + 1];
-    long gb_rchunk[kMaxLayers + 1];
-    size_t gpart_w, gpart_b;          // doubles
-    double* gpart;
-    // per-subproblem Active Set budgets (non-increasing in s), or none
-    bool ragged;
-    std::vector<int> budgets;
-    int* budgets_dev;                 // [S]
-    void* lrs;                        // [S] learning rates of the current iteration (T)
-    int Sa;                           // subproblems the current iteration updates (a prefix)
-    // captured iteration schedule (asd_solve_graph) and the host state it ends in
-    hipGraphExec_t graph_exec;
-    bool graph_valid;
-    int graph_end_masks, graph_end_step, graph_end_mask_step[kMaxMasks];
-    // scalar state
-    int n_masks;
-    int step;
-    int mask_step[kMaxMasks];
-    bool loaded;
-    // kernel timing
-    bool prof;
-    std::vector<ProfRec> prof_recs;
-    std::vector<hipEvent_t> prof_pool;
-    size_t prof_used;
-};
-
-namespace {
-
-template <typename T> NeuronArraysT<T>* NA(asd_plan* P);
-template <> NeuronArraysT<float>* NA<float>(asd_plan* P) { return P->naf; }
-template <> NeuronArraysT<double>* NA<double>(asd_plan* P) { return P->nad; }
-template <typename T> ReluLayerT<T>* RL(asd_plan* P);
-template <> ReluLayerT<float>* RL<float>(asd_plan* P) { return P->Rf; }
-template <> ReluLayerT<double>* RL<double>(asd_plan* P) { return P->Rd; }
-template <typename T> ReluLayerT<T>* RdevT(asd_plan* P) { return reinterpret_cast<ReluLayerT<T>*>(P->Rdev); }
-template <typename T> T* CV(asd_plan* P);
-template <> float* CV<float>(asd_plan* P) { return P->cvecf; }
-template <> double* CV<double>(asd_plan* P) { return P->cvecd; }
-
-bool is64(const asd_plan* P) { return P->prm.precision == ASD_PREC_FP64; }
-
-// Event pair around one launch when profiling is on.
-struct ProfScope {
-    asd_plan* P;
-    hipStream_t st;
-    int idx;
-    ProfScope(asd_plan* P_, hipStream_t st_, int role, int layer) : P(P_), st(st_), idx(-1) {
-        if (!P || !P->prof) return;
-        if (P->prof_used + 2 > P->prof_pool.size()) {
-            for (int i = 0; i < 256; ++i) {
-                hipEvent_t e;
-                if (hipEventCreate(&e) != hipSuccess) return;
-                P->prof_pool.push_back(e);
-            }
-        }
-        ProfRec r{role, layer, P->prof_pool[P->prof_used], P->prof_pool[P->prof_used + 1]};
-        P->prof_used += 2;
-        if (hipEventRecord(r.a, st) != hipSuccess) return;
-        idx = (int)P->prof_recs.size();
-        P->prof_recs.push_back(r);
-    }
-    ~ProfScope() {
-        if (idx >= 0) (void)hipEventRecord(P->prof_recs[idx].b, st);
-    }
-};
 
 // ---------------------------------------------------------------------------
 // Workspace carving (two passes: measure, then assign).
@@ -378,19 +244,6 @@ void setup_plan_geometry(asd_plan* P) {
     }
 }
 
-inline dim3 grid_cols(const NeuronLayout& nl, int chan_per_block) {
-    return dim3((unsigned)((nl.cols + 63) / 64), (unsigned)((nl.C + chan_per_block - 1) / chan_per_block));
-}
-
-// Geometry of layer L restricted to the subproblems the current iteration
-// updates (s < Sa): column counts cover that prefix; strides, bit strides and
-// arrays are unchanged.
-LayerGeo gview(const asd_plan* P, int L) {
-    LayerGeo g = P->geo[L];
-    g.in.cols = (long)P->Sa * g.in.P;
-    g.out.cols = (long)P->Sa * g.out.P;
-    return g;
-}
 
 asd_status zero_words(void* p, long n, hipStream_t st) {
     if (n == 0) return ASD_OK;
@@ -529,189 +382,23 @@ asd_status prepare_weights(asd_plan* P, hipStream_t st) {
     return ASD_OK;
 }
 
-#define ASD_NM_DISPATCH(nm, CALL)                                          \
-    switch (nm) {                                                          \
-        case 0: CALL(0);                                                   \
-        case 1: CALL(1);                                                   \
-        case 2: CALL(2);                                                   \
-        case 3: CALL(3);                                                   \
-        case 4: CALL(4);                                                   \
-        case 5: CALL(5);                                                   \
-        case 6: CALL(6);                                                   \
-        case 7: CALL(7);                                                   \
-        case 8: CALL(8);                                                   \
-        default: return fail(ASD_EINVAL, "mask count %d outside [0, 8]", (int)(nm)); \
-    }
-
-template <typename T>
-FastFwdArgs<T> fwd_args(asd_plan* P, int k, int nm, const StepArgsT<T>& sa) {
-    FastFwdArgs<T> a;
-    memset(&a, 0, sizeof(a));
-    a.g = gview(P, k);
-    a.S = P->S;
-    a.Sa = P->Sa;
-    a.nm = nm;
-    a.Cpad = P->Cpad[k];
-    a.ksplit = P->ksplit[k];
-    a.Wt = P->Wt[k];
-    a.xin = NA<T>(P)[k - 1].xstar;
-    a.xpk = NA<T>(P)[k - 1].xpk;
-    a.pointflag = P->pointflag + (k - 1);
-    a.xout = NA<T>(P)[k].xstar;
-    a.R = RdevT<T>(P) + k;
-    a.st = sa;
-    a.part = reinterpret_cast<T*>(P->part);
-    return a;
-}
-
-// Iteration forward pass of ReLU layer k with NM active masks.
-template <typename T, int NM, bool MB>
-asd_status fwd_fast_nm(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t st) {
-    FastFwdArgs<T> a = fwd_args<T>(P, k, NM, sa);
-    const LayerGeo& g = a.g;
-    constexpr int CB = sizeof(T) == 4 ? 8 : 4;
-    ProfScope ps(P, st, ASD_K_FORWARD, k);
-    if (g.kind == ASD_LAYER_CONV2D && !P->fwd_mfma[k]) {
-        // narrow layer: a 32-row matrix tile would be half empty, and the
-        // update's memory traffic bounds it anyway
-        dim3 grid((unsigned)((g.out.cols + kWave - 1) / kWave), (unsigned)((g.out.C + CB - 1) / CB));
-        if (g.ksz == 4)
-            hipLaunchKernelGGL((k_fwd_conv<T, NM, CB, 4, MB>), grid, dim3(kWave, KS), 0, st, a);
-        else
-            hipLaunchKernelGGL((k_fwd_conv<T, NM, CB, 0, MB>), grid, dim3(kWave, KS), 0, st, a);
-        LAUNCH_CHECK();
-        return ASD_OK;
-    }
-    if (g.kind == ASD_LAYER_CONV2D) {
-        // one 32-column tile per block, its waves splitting the taps
-        const long ntiles = (g.out.cols + 31) / 32;
-        dim3 grid((unsigned)ntiles, (unsigned)(a.Cpad / 32));
-        if (P->fwd_kw[k] == 8) {
-            if (g.ksz == 4) hipLaunchKernelGGL((k_fwd_conv_mfma<NM, true, 4, MB, 8>), grid, dim3(kWave, 8), 0, st, a);
-            else hipLaunchKernelGGL((k_fwd_conv_mfma<NM, true, 0, MB, 8>), grid, dim3(kWave, 8), 0, st, a);
-        } else {
-            if (g.ksz == 4) hipLaunchKernelGGL((k_fwd_conv_mfma<NM, true, 4, MB, 4>), grid, dim3(kWave, 4), 0, st, a);
-            else hipLaunchKernelGGL((k_fwd_conv_mfma<NM, true, 0, MB, 4>), grid, dim3(kWave, 4), 0, st, a);
-        }
-        (void)CB;
-        LAUNCH_CHECK();
-        return ASD_OK;
-    }
-    dim3 grid((unsigned)((P->Sa + 31) / 32), (unsigned)(a.Cpad / 32), (unsigned)a.ksplit);
-    if (a.ksplit == 1) {
-        // one split: the product blocks update their neurons themselves
-        if (P->fwd_kw[k] == 8) hipLaunchKernelGGL((k_fwd_dense_mfma<NM, 8, true, MB>), grid, dim3(kWave, 8), 0, st, a);
-        else hipLaunchKernelGGL((k_fwd_dense_mfma<NM, 4, true, MB>), grid, dim3(kWave, 4), 0, st, a);
-        LAUNCH_CHECK();
-        return ASD_OK;
-    }
-    if (P->fwd_kw[k] == 8) hipLaunchKernelGGL((k_fwd_dense_mfma<NM, 8, false, MB>), grid, dim3(kWave, 8), 0, st, a);
-    else hipLaunchKernelGGL((k_fwd_dense_mfma<NM, 4, false, MB>), grid, dim3(kWave, 4), 0, st, a);
-    LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_fwd_dense_epi<T, NM, MB>), dim3((unsigned)((P->Sa + 255) / 256), (unsigned)g.out.C), dim3(256),
-                       0, st, a);
-    LAUNCH_CHECK();
-    return ASD_OK;
-}
-
-template <typename T>
-asd_status fwd_fast(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t st) {
-    if constexpr (sizeof(T) == 4) {
-        if (P->prm.precision == ASD_PREC_MIXED) {
-#define ASD_FWD_CALL(N) return fwd_fast_nm<T, N, true>(P, k, sa, st)
-            ASD_NM_DISPATCH(P->n_masks, ASD_FWD_CALL)
-#undef ASD_FWD_CALL
-        }
-    }
-#define ASD_FWD_CALL(N) return fwd_fast_nm<T, N, false>(P, k, sa, st)
+asd_status fwd_fast(asd_plan* P, int k, const StepArgsT<float>& sa, hipStream_t st) {
+    const bool mb = P->prm.precision == ASD_PREC_MIXED;
+#define ASD_FWD_CALL(N) return fwd_fast_nm<N>(P, k, sa, mb, st)
     ASD_NM_DISPATCH(P->n_masks, ASD_FWD_CALL)
 #undef ASD_FWD_CALL
 }
 
-// The forward pass of convolutional layer kc on the matrix cores (8 waves
-// per tile) and the products of dense layer kd (8 waves per split) in one
-// launch (k_fwd_conv_dense), then the dense layer's epilogue.
-template <int NM, bool MB>
-asd_status fwd_fused_nm(asd_plan* P, int kc, int kd, const StepArgsT<float>& sa, hipStream_t st) {
-    const FastFwdArgs<float> ac = fwd_args<float>(P, kc, NM, sa);
-    const FastFwdArgs<float> ad = fwd_args<float>(P, kd, NM, sa);
-    const int dgx = (P->Sa + 31) / 32, dgy = ad.Cpad / 32, nd = dgx * dgy * ad.ksplit;
-    const int cgx = (int)((ac.g.out.cols + 31) / 32), cgy = ac.Cpad / 32;
-    const dim3 grid((unsigned)(nd + cgx * cgy));
-    const bool du = ad.ksplit == 1;  // one split: the dense blocks update, no epilogue
-    if (ac.g.ksz == 4) {
-        if (du) hipLaunchKernelGGL((k_fwd_conv_dense<NM, 4, MB, true>), grid, dim3(kWave, 8), 0, st, ac, ad, nd, dgx, dgy, cgx, cgy);
-        else hipLaunchKernelGGL((k_fwd_conv_dense<NM, 4, MB, false>), grid, dim3(kWave, 8), 0, st, ac, ad, nd, dgx, dgy, cgx, cgy);
-    } else {
-        if (du) hipLaunchKernelGGL((k_fwd_conv_dense<NM, 0, MB, true>), grid, dim3(kWave, 8), 0, st, ac, ad, nd, dgx, dgy, cgx, cgy);
-        else hipLaunchKernelGGL((k_fwd_conv_dense<NM, 0, MB, false>), grid, dim3(kWave, 8), 0, st, ac, ad, nd, dgx, dgy, cgx, cgy);
-    }
-    LAUNCH_CHECK();
-    if (du) return ASD_OK;
-    hipLaunchKernelGGL((k_fwd_dense_epi<float, NM, MB>), dim3((unsigned)((P->Sa + 255) / 256), (unsigned)ad.g.out.C),
-                       dim3(256), 0, st, ad);
-    LAUNCH_CHECK();
-    return ASD_OK;
-}
-
-// The forward pass of VALU-mapped convolutional layer kv, matrix-core
-// convolutional layer kc and dense layer kd in one launch (k_fwd_trio), then
-// the dense layer's epilogue.
-template <int NM, bool MB>
-asd_status fwd_trio_nm(asd_plan* P, int kv, int kc, int kd, const StepArgsT<float>& sa, hipStream_t st) {
-    const FastFwdArgs<float> av = fwd_args<float>(P, kv, NM, sa);
-    const FastFwdArgs<float> ac = fwd_args<float>(P, kc, NM, sa);
-    const FastFwdArgs<float> ad = fwd_args<float>(P, kd, NM, sa);
-    const int dgx = (P->Sa + 31) / 32, dgy = ad.Cpad / 32, nd = dgx * dgy * ad.ksplit;
-    const int cgx = (int)((ac.g.out.cols + 31) / 32), cgy = ac.Cpad / 32, nc = cgx * cgy;
-    const int vgx = (int)((av.g.out.cols + kWave - 1) / kWave), vgy = (av.g.out.C + 7) / 8;
-    const int nv = (vgx * vgy + 1) / 2;  // two column-kernel blocks per launched block
-    // the convolutions' blocks in order (matrix-core ones first): measured
-    // faster than interleaving them
-    const int ip = 1;
-    const dim3 grid((unsigned)(nd + nc + nv));
-    const bool c4 = ac.g.ksz == 4, v4 = av.g.ksz == 4;
-    const bool du = ad.ksplit == 1;  // one split: the dense blocks update, no epilogue
-#define ASD_TRIO_LAUNCH(KC, KV)                                                                                       \
-    do {                                                                                                              \
-        if (du)                                                                                                       \
-            hipLaunchKernelGGL((k_fwd_trio<NM, KC, KV, MB, true>), grid, dim3(kWave, 8), 0, st, av, ac, ad, nd, dgx, \
-                               dgy, nc, cgx, cgy, vgx, vgy, ip);                                                      \
-        else                                                                                                          \
-            hipLaunchKernelGGL((k_fwd_trio<NM, KC, KV, MB, false>), grid, dim3(kWave, 8), 0, st, av, ac, ad, nd, dgx, \
-                               dgy, nc, cgx, cgy, vgx, vgy, ip);                                                      \
-    } while (0)
-    if (c4 && v4) ASD_TRIO_LAUNCH(4, 4);
-    else if (c4) ASD_TRIO_LAUNCH(4, 0);
-    else if (v4) ASD_TRIO_LAUNCH(0, 4);
-    else ASD_TRIO_LAUNCH(0, 0);
-#undef ASD_TRIO_LAUNCH
-    LAUNCH_CHECK();
-    if (du) return ASD_OK;
-    hipLaunchKernelGGL((k_fwd_dense_epi<float, NM, MB>), dim3((unsigned)((P->Sa + 255) / 256), (unsigned)ad.g.out.C),
-                       dim3(256), 0, st, ad);
-    LAUNCH_CHECK();
-    return ASD_OK;
-}
-
 asd_status fwd_trio(asd_plan* P, int kv, int kc, int kd, const StepArgsT<float>& sa, hipStream_t st) {
-    if (P->prm.precision == ASD_PREC_MIXED) {
-#define ASD_TRIO_CALL(N) return fwd_trio_nm<N, true>(P, kv, kc, kd, sa, st)
-        ASD_NM_DISPATCH(P->n_masks, ASD_TRIO_CALL)
-#undef ASD_TRIO_CALL
-    }
-#define ASD_TRIO_CALL(N) return fwd_trio_nm<N, false>(P, kv, kc, kd, sa, st)
+    const bool mb = P->prm.precision == ASD_PREC_MIXED;
+#define ASD_TRIO_CALL(N) return fwd_trio_nm<N>(P, kv, kc, kd, sa, mb, st)
     ASD_NM_DISPATCH(P->n_masks, ASD_TRIO_CALL)
 #undef ASD_TRIO_CALL
 }
 
 asd_status fwd_fused(asd_plan* P, int kc, int kd, const StepArgsT<float>& sa, hipStream_t st) {
-    if (P->prm.precision == ASD_PREC_MIXED) {
-#define ASD_FUSED_CALL(N) return fwd_fused_nm<N, true>(P, kc, kd, sa, st)
-        ASD_NM_DISPATCH(P->n_masks, ASD_FUSED_CALL)
-#undef ASD_FUSED_CALL
-    }
-#define ASD_FUSED_CALL(N) return fwd_fused_nm<N, false>(P, kc, kd, sa, st)
+    const bool mb = P->prm.precision == ASD_PREC_MIXED;
+#define ASD_FUSED_CALL(N) return fwd_fused_nm<N>(P, kc, kd, sa, mb, st)
     ASD_NM_DISPATCH(P->n_masks, ASD_FUSED_CALL)
 #undef ASD_FUSED_CALL
 }
@@ -719,70 +406,6 @@ asd_status fwd_fused(asd_plan* P, int kc, int kd, const StepArgsT<float>& sa, hi
 template <typename Tc, typename Ts>
 asd_status launch_backward(asd_plan* P, int k, int want_obj, int role, hipStream_t st, double* fout = nullptr);
 
-// Staged operand images of the transposed convolution through layer k+1
-// (k_bwd_conv_mfma, k_bwd_conv_m4): taps per axis, zero border, image size.
-BwdConvShape conv_shape(const LayerGeo& g) {
-    BwdConvShape sh;
-    memset(&sh, 0, sizeof(sh));
-    const int st_ = g.stride, pd = g.pad;
-    sh.J = (g.ksz + st_ - 1) / st_;
-    sh.off = sh.J - 1;
-    const int qymax = (g.in.H - 1 + pd) / st_, qxmax = (g.in.W - 1 + pd) / st_;
-    sh.Hp = std::max(g.out.H, qymax + 1) + sh.off;
-    sh.Wp = std::max(g.out.W, qxmax + 1) + sh.off;
-    sh.dimg = FastDiv{sh.Hp * sh.Wp, 1.0f / (float)(sh.Hp * sh.Wp)};
-    sh.dWp = FastDiv{sh.Wp, 1.0f / (float)sh.Wp};
-    sh.dOP = FastDiv{g.out.P, 1.0f / (float)g.out.P};
-    sh.dOW = FastDiv{g.out.W, 1.0f / (float)g.out.W};
-    return sh;
-}
-
-// The transposed convolution into layer k fits k_bwd_conv_m4: stride 2, at
-// most 4 channels, every 64-position run whole rows of layer k or part of
-// one with an even number of columns per parity, at most 16 such runs per
-// subproblem, and the staged images of one output channel within the LDS
-// share of a product at any mask count.
-bool bwd_m4_fits(const asd_plan* P, int k) {
-    const LayerGeo& g = P->geo[k + 1];
-    const NeuronLayout& L = g.in;
-    if (g.kind != ASD_LAYER_CONV2D || g.stride != 2 || L.C > 4 || k + 1 == P->n) return false;
-    if (L.P % kWave != 0 || L.P > 16 * kWave || L.W % 8 != 0 || !(L.W % kWave == 0 || kWave % L.W == 0))
-        return false;
-    const BwdConvShape sh = conv_shape(g);
-    return sh.Hp * sh.Wp <= bwd_mfma_rs<kMaxMasks>();
-}
-
-template <typename T>
-FastBwdArgs<T> bwd_args(asd_plan* P, int k, int nm) {
-    FastBwdArgs<T> a;
-    memset(&a, 0, sizeof(a));
-    a.gn = gview(P, k + 1);
-    a.S = P->S;
-    a.k = k;
-    a.last = (k + 1 == P->n);
-    a.nm = nm;
-    a.Wr = P->Wr[k + 1];
-    a.fanpad = P->fanpad[k + 1];
-    a.cvec = CV<T>(P);
-    if (!a.last) {
-        const ReluLayerT<T>& rn = RL<T>(P)[k + 1];
-        a.vs = rn.vs;
-        for (int q = 0; q < nm; ++q) a.u[q] = rn.slot[q].u;
-    }
-    a.xpk = NA<T>(P)[k].xpk;
-    a.nk = NA<T>(P)[k];
-    if (k >= 1) {
-        const ReluLayerT<T>& r = RL<T>(P)[k];
-        a.own = r.own;
-        a.gk = r.g;
-        a.zbits = r.zbits;
-    }
-    a.Wb = P->Wb[k + 1];
-    a.Wl4 = P->Wl4[k + 1];
-    a.Wl8 = P->Wl8[k + 1];
-    a.nkp = P->nkp[k + 1];
-    return a;
-}
 
 // The backward passes into the last ReLU layer (dense, one position per
 // channel: k_bwd_dense) and into the layer below (dense into 64-position
@@ -798,186 +421,19 @@ int bwd_pair_layer(const asd_plan* P) {
     return kb;
 }
 
-template <int NM>
-asd_status bwd_pair_nm(asd_plan* P, hipStream_t st) {
-    const int ka = P->n - 1, kb = P->n - 2;
-    const FastBwdArgs<float> aa = bwd_args<float>(P, ka, 0);
-    const FastBwdArgs<float> ab = bwd_args<float>(P, kb, NM);
-    const NeuronLayout& La = aa.gn.in;
-    const NeuronLayout& Lb = ab.gn.in;
-    const int agx = (int)((La.cols + kWave - 1) / kWave), agy = (La.C + 7) / 8, na = agx * agy;
-    const int mgx = (P->Sa + 15) / 16, mgy = Lb.C * (Lb.P / kWave);
-    hipLaunchKernelGGL((k_bwd_dense_pair<NM>), dim3((unsigned)(na + mgx * mgy)), dim3(kWave, 4), 0, st, aa, ab, na, agx,
-                       agy, mgx);
-    LAUNCH_CHECK();
-    return ASD_OK;
-}
-
 asd_status bwd_pair(asd_plan* P, hipStream_t st) {
 #define ASD_PAIR_CALL(N) return bwd_pair_nm<N>(P, st)
     ASD_NM_DISPATCH(P->n_masks, ASD_PAIR_CALL)
 #undef ASD_PAIR_CALL
 }
 
-// Iteration backward pass into neuron layer k; NM = masks of layer k+1.
-template <typename T, int NM>
-asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
-    FastBwdArgs<T> a;
-    memset(&a, 0, sizeof(a));
-    a.gn = gview(P, k + 1);
-    a.S = P->S;
-    a.k = k;
-    a.last = (k + 1 == P->n);
-    a.nm = NM;
-    a.Wr = P->Wr[k + 1];
-    a.fanpad = P->fanpad[k + 1];
-    a.cvec = CV<T>(P);
-    if (!a.last) {
-        const ReluLayerT<T>& rn = RL<T>(P)[k + 1];
-        a.vs = rn.vs;
-        for (int q = 0; q < NM; ++q) a.u[q] = rn.slot[q].u;
-    }
-    a.xpk = NA<T>(P)[k].xpk;
-    a.nk = NA<T>(P)[k];
-    if (k >= 1) {
-        const ReluLayerT<T>& r = RL<T>(P)[k];
-        a.own = r.own;
-        a.gk = r.g;
-        a.zbits = r.zbits;
-    }
-    const LayerGeo& g = a.gn;
-    const NeuronLayout& L = g.in;
-    a.Wb = P->Wb[k + 1];
-    a.Wl4 = P->Wl4[k + 1];
-    a.Wl8 = P->Wl8[k + 1];
-    a.nkp = P->nkp[k + 1];
-    if (g.kind == ASD_LAYER_CONV2D && L.P % kWave == 0 && L.C >= 16) {
-        // matrix-core transposed convolution over parity classes, operands
-        // staged in LDS (see k_bwd_conv_mfma); shapes it cannot hold fall
-        // through to the column kernel
-        BwdConvShape sh = conv_shape(g);
-        const int st_ = g.stride, pd = g.pad;
-        // items of NT column tiles of 16 positions of one parity class; one
-        // wave per item, at most 8: two tiles per item where that fits
-        auto count_items = [&](int nt) {
-            int items = 0;
-            for (int c = 0; c < st_ * st_; ++c) {
-                const int ry = c / st_, rx = c % st_;
-                const int yf = ((ry - pd) % st_ + st_) % st_, xf = ((rx - pd) % st_ + st_) % st_;
-                const int ny = yf < L.H ? (L.H - 1 - yf) / st_ + 1 : 0;
-                const int nx = xf < L.W ? (L.W - 1 - xf) / st_ + 1 : 0;
-                items += (ny * nx + 16 * nt - 1) / (16 * nt);
-            }
-            return items;
-        };
-        const int NT = (count_items(2) <= 8 && P->bwd_nt[k] != 4) ? 2 : 4;
-        sh.items = count_items(NT);
-        sh.NW = std::min(sh.items, 8);
-        const size_t fbytes = (size_t)std::min(16, L.C) * L.P * sizeof(float);
-        constexpr int RS = bwd_mfma_rs<NM>();
-        const int img = sh.Hp * sh.Wp;
-        if (sh.items <= sh.NW && fbytes <= 32 * 1024 && img <= RS) {
-            sh.CC = std::min(g.out.C, RS / img);
-            // product r's images at float r RS, the parked f after the last
-            sh.fboff = NM * RS + sh.CC * img;
-            const size_t dyn = (size_t)sh.fboff * sizeof(float) + fbytes;
-            ProfScope ps(P, st, ASD_K_BACKWARD, k);
-            dim3 grid((unsigned)P->Sa, (unsigned)((L.C + 15) / 16));
-            if (g.ksz == 4 && g.stride == 2) {
-                if (NT == 2) hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 4, 2, 2>), grid, dim3(kWave, sh.NW), dyn, st, a, sh);
-                else hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 4, 2, 4>), grid, dim3(kWave, sh.NW), dyn, st, a, sh);
-            } else {
-                if (NT == 2) hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 0, 0, 2>), grid, dim3(kWave, sh.NW), dyn, st, a, sh);
-                else hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 0, 0, 4>), grid, dim3(kWave, sh.NW), dyn, st, a, sh);
-            }
-            LAUNCH_CHECK();
-            return ASD_OK;
-        }
-    }
-    if (g.kind == ASD_LAYER_CONV2D) {
-        // column kernel, the taps split over KS waves
-        const int CB = (sizeof(T) == 4 && L.C > 4 && P->bwd_cb[k] != 4) ? 8 : 4;
-        const int ksp = KS;
-        const size_t dyn = ((size_t)g.out.C * g.ksz * g.ksz + 1) * CB * sizeof(float);  // + a zero row
-        const size_t stat = (size_t)ksp * CB * kWave * sizeof(T);
-        if (dyn + stat > 64 * 1024) return launch_backward<T, T>(P, k, 0, ASD_K_BACKWARD, st);
-        ProfScope ps(P, st, ASD_K_BACKWARD, k);
-        dim3 grid((unsigned)((L.cols + kWave - 1) / kWave), (unsigned)((L.C + CB - 1) / CB));
-        const bool k4s2 = g.ksz == 4 && g.stride == 2;
-        if constexpr (sizeof(T) == 4) {
-            if (bwd_m4_fits(P, k) && P->bwd_cb[k] != 4) {
-                // at most 4 channels, stride 2: the matrix-core variant, a
-                // block per subproblem
-                BwdConvShape sh = conv_shape(g);
-                constexpr int RS = bwd_mfma_rs<NM>();
-                const int img = sh.Hp * sh.Wp;
-                sh.CC = std::min(g.out.C, RS / img);
-                sh.fboff = (NM * RS + sh.CC * img + 3) / 4 * 4;
-                const size_t dm4 = ((size_t)sh.fboff + (size_t)(g.out.C * g.ksz * g.ksz + 1) * 4) * sizeof(float);
-                if (dm4 <= 64 * 1024) {
-                    const dim3 bm4(kWave, L.P / kWave);
-                    if (g.ksz == 4) hipLaunchKernelGGL((k_bwd_conv_m4<NM, 4>), dim3((unsigned)P->Sa), bm4, dm4, st, a, sh);
-                    else hipLaunchKernelGGL((k_bwd_conv_m4<NM, 0>), dim3((unsigned)P->Sa), bm4, dm4, st, a, sh);
-                    LAUNCH_CHECK();
-                    return ASD_OK;
-                }
-            }
-            if (CB == 8) {
-                if (k4s2)
-                    hipLaunchKernelGGL((k_bwd_conv<T, NM, 8, 4, 2, KS>), grid, dim3(kWave, KS), dyn, st, a);
-                else
-                    hipLaunchKernelGGL((k_bwd_conv<T, NM, 8, 0, 0, KS>), grid, dim3(kWave, KS), dyn, st, a);
-                LAUNCH_CHECK();
-                return ASD_OK;
-            }
-        }
-        if (k4s2)
-            hipLaunchKernelGGL((k_bwd_conv<T, NM, 4, 4, 2, KS>), grid, dim3(kWave, KS), dyn, st, a);
-        else
-            hipLaunchKernelGGL((k_bwd_conv<T, NM, 4, 0, 0, KS>), grid, dim3(kWave, KS), dyn, st, a);
-        LAUNCH_CHECK();
-        return ASD_OK;
-    }
-    ProfScope ps(P, st, ASD_K_BACKWARD, k);
-    constexpr int SB = sizeof(T) == 4 ? 8 : 4;
-    if constexpr (sizeof(T) == 4) {
-        if (L.P % kWave == 0 && P->bwd_pos[k] == 2) {
-            // matrix cores: 16 subproblems x 64 positions per block
-            dim3 grid((unsigned)((P->Sa + 15) / 16), (unsigned)(L.C * (L.P / kWave)));
-            hipLaunchKernelGGL((k_bwd_dense_mfma<NM>), grid, dim3(kWave, 4), 0, st, a);
-            LAUNCH_CHECK();
-            return ASD_OK;
-        }
-    }
-    if (L.P % kWave == 0 && P->S >= SB && P->bwd_pos[k]) {
-        dim3 grid((unsigned)(L.C * (L.P / kWave)), (unsigned)((P->Sa + SB - 1) / SB));
-        bool done = false;
-        if constexpr (SB % 8 == 0) {
-            if (P->bwd_kw[k] == 8) {
-                hipLaunchKernelGGL((k_bwd_dense_pos<T, NM, SB, 8>), grid, dim3(kWave, 8), 0, st, a);
-                done = true;
-            }
-        }
-        if (!done) hipLaunchKernelGGL((k_bwd_dense_pos<T, NM, SB, 4>), grid, dim3(kWave, 4), 0, st, a);
-    } else {
-        constexpr int CB = sizeof(T) == 4 ? 8 : 4;
-        dim3 grid((unsigned)((L.cols + kWave - 1) / kWave), (unsigned)((L.C + CB - 1) / CB));
-        if (L.P == 1)
-            hipLaunchKernelGGL((k_bwd_dense<T, NM, CB, true>), grid, dim3(kWave, KS), 0, st, a);
-        else
-            hipLaunchKernelGGL((k_bwd_dense<T, NM, CB, false>), grid, dim3(kWave, KS), 0, st, a);
-    }
-    LAUNCH_CHECK();
-    return ASD_OK;
-}
-
-template <typename T>
 asd_status bwd_fast(asd_plan* P, int k, hipStream_t st) {
     const int nm = (k + 1 == P->n) ? 0 : P->n_masks;
-#define ASD_BWD_CALL(N) return bwd_fast_nm<T, N>(P, k, st)
+#define ASD_BWD_CALL(N) return bwd_fast_nm<N>(P, k, st)
     ASD_NM_DISPATCH(nm, ASD_BWD_CALL)
 #undef ASD_BWD_CALL
 }
+
 
 // Backward pass for neuron layer k (f_k, inner minimisation, terms).
 template <typename Tc, typename Ts>
@@ -1201,7 +657,7 @@ asd_status forward_pass(asd_plan* P, const StepArgsT<T>& sa, hipStream_t st) {
     for (int k = 1; k < P->n; ++k) {
         if (k == fc || k == fv) continue;
         if (k == fd) TRY(fv >= 0 ? fwd_trio(P, fv, fc, fd, sa, st) : fwd_fused(P, fc, fd, sa, st));
-        else TRY(fwd_fast<T>(P, k, sa, st));
+        else TRY(fwd_fast(P, k, sa, st));
     }
     return ASD_OK;
 }
@@ -1236,7 +692,7 @@ asd_status iteration(asd_plan* P, bool as_phase, int t, double lr, hipStream_t s
         } else {
             if (k == kpair) continue;
             if (kpair >= 0 && k == P->n - 1) TRY(bwd_pair(P, st));
-            else TRY(bwd_fast<T>(P, k, st));
+            else TRY(bwd_fast(P, k, st));
         }
     }
     if (as_phase && P->n >= 2 && (t % P->prm.add_every) < P->prm.add_count &&
@@ -1611,7 +1067,7 @@ asd_status autotune_t(asd_plan* P, int ktune, int reps, hipStream_t st) {
         return ms;
     };
     // every iterate's x* must exist before the forward kernels run
-    for (int k = P->n - 1; k >= 0 && err == ASD_OK; --k) err = bwd_fast<T>(P, k, st);
+    for (int k = P->n - 1; k >= 0 && err == ASD_OK; --k) err = bwd_fast(P, k, st);
     for (int L = 1; L <= P->n && err == ASD_OK; ++L) {
         const LayerGeo& g = P->geo[L];
         if (L < P->n && g.kind == ASD_LAYER_DENSE) {
@@ -1622,7 +1078,7 @@ asd_status autotune_t(asd_plan* P, int ktune, int reps, hipStream_t st) {
                 for (int ks = 1; ks <= cap; ks *= 2) {
                     P->ksplit[L] = ks;
                     P->fwd_kw[L] = kw;
-                    const float t = timed([&] { return fwd_fast<T>(P, L, sa, st); });
+                    const float t = timed([&] { return fwd_fast(P, L, sa, st); });
                     if (t < tbest) tbest = t, best = ks, bestkw = kw;
                 }
             P->ksplit[L] = best;
@@ -1635,7 +1091,7 @@ asd_status autotune_t(asd_plan* P, int ktune, int reps, hipStream_t st) {
             for (int m = 0; m < 3; ++m) {
                 P->fwd_mfma[L] = mf[m];
                 P->fwd_kw[L] = kw[m];
-                tb[m] = timed([&] { return fwd_fast<T>(P, L, sa, st); });
+                tb[m] = timed([&] { return fwd_fast(P, L, sa, st); });
             }
             const int b = tb[0] < tb[1] ? (tb[0] < tb[2] ? 0 : 2) : (tb[1] < tb[2] ? 1 : 2);
             P->fwd_mfma[L] = mf[b];
@@ -1649,7 +1105,7 @@ asd_status autotune_t(asd_plan* P, int ktune, int reps, hipStream_t st) {
             const int cand[2] = {0, 4};
             for (int m = 0; m < 2; ++m) {
                 P->bwd_cb[k] = cand[m];
-                tb[m] = timed([&] { return bwd_fast<T>(P, k, st); });
+                tb[m] = timed([&] { return bwd_fast(P, k, st); });
             }
             P->bwd_cb[k] = tb[0] <= tb[1] ? 0 : 4;
         }
@@ -1658,7 +1114,7 @@ asd_status autotune_t(asd_plan* P, int ktune, int reps, hipStream_t st) {
             const int cand[2] = {4, 8};
             for (int m = 0; m < 2; ++m) {
                 P->bwd_cb[k] = cand[m];
-                tb[m] = timed([&] { return bwd_fast<T>(P, k, st); });
+                tb[m] = timed([&] { return bwd_fast(P, k, st); });
             }
             P->bwd_cb[k] = tb[0] < tb[1] ? 4 : 8;
         }
@@ -1667,7 +1123,7 @@ asd_status autotune_t(asd_plan* P, int ktune, int reps, hipStream_t st) {
             const int cand[2] = {2, 4};
             for (int m = 0; m < 2; ++m) {
                 P->bwd_nt[k] = cand[m];
-                tb[m] = timed([&] { return bwd_fast<T>(P, k, st); });
+                tb[m] = timed([&] { return bwd_fast(P, k, st); });
             }
             P->bwd_nt[k] = tb[0] <= tb[1] ? 2 : 4;
         }
@@ -1680,7 +1136,7 @@ asd_status autotune_t(asd_plan* P, int ktune, int reps, hipStream_t st) {
             for (int m = 0; m < 4; ++m) {
                 P->bwd_pos[k] = pos[m];
                 P->bwd_kw[k] = kw[m];
-                tb[m] = timed([&] { return bwd_fast<T>(P, k, st); });
+                tb[m] = timed([&] { return bwd_fast(P, k, st); });
                 if (tb[m] < tb[b]) b = m;
             }
             P->bwd_pos[k] = pos[b];
@@ -1735,6 +1191,10 @@ void invalidate_graph(asd_plan* P) {
 int as_iters_of(const asd_plan* P) { return P->ragged ? P->budgets[0] : P->prm.as_iters; }
 
 }  // namespace
+
+asd_status asd::launch_backward_iter(asd_plan* P, int k, hipStream_t st) {
+    return launch_backward<float, float>(P, k, 0, ASD_K_BACKWARD, st);
+}
 
 // ===========================================================================
 // Public API

@@ -164,7 +164,7 @@ __device__ __forceinline__ void store_moments_bf16(float* pm, uint32_t idx, floa
 // One moment of the mixed mode (the high half of each packed word for m,
 // hi = 1; the low half for v) <-> caller [S][N] floats (mode 0: set, rounding
 // to BF16 and keeping the other half; mode 2: get).
-__global__ void k_layout_bf16(uint32_t* in_arr, float* ex_arr, NeuronLayout nl, int S, int mode, int hi) {
+static __global__ void k_layout_bf16(uint32_t* in_arr, float* ex_arr, NeuronLayout nl, int S, int mode, int hi) {
     const long col = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
     if (col >= nl.cols) return;
@@ -1531,7 +1531,7 @@ __global__ void __launch_bounds__(kWave * 8) k_bwd_conv_mfma(FastBwdArgs<float> 
 // Weights of a convolution in the column transposed kernel's LDS layout:
 // Wl[group][(co * k + ky) * k + kx][e] = W[co][group * cb + e][ky][kx] (zero
 // past C_in), then one zero row per group.
-__global__ void __launch_bounds__(256) k_col_weights(const float* W, float* Wl, int Cin, int Cout, int kk2, int cb,
+static __global__ void __launch_bounds__(256) k_col_weights(const float* W, float* Wl, int Cin, int Cout, int kk2, int cb,
                                                      long n) {
     const long i = (long)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
@@ -1544,7 +1544,7 @@ __global__ void __launch_bounds__(256) k_col_weights(const float* W, float* Wl, 
     Wl[i] = (row < rows - 1 && c < Cin) ? W[((long)co * Cin + c) * kk2 + kk] : 0.f;
 }
 
-__global__ void __launch_bounds__(256) k_class_weights(const float* W, float* Wb, int Ck, int C1, int ks, int st,
+static __global__ void __launch_bounds__(256) k_class_weights(const float* W, float* Wb, int Ck, int C1, int ks, int st,
                                                        int nkp, long n) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -1917,7 +1917,7 @@ __global__ void __launch_bounds__(256) k_pack(PackArgs<T> A) {
 
 // Transposed forward weights Wt[t][c] = W[c][t], zero for c >= C.
 // Grid (ceil(fan * Cpad / 256)), block 256.
-__global__ void __launch_bounds__(256) k_transpose_w(const float* W, float* Wt, int C, int fan, int Cpad) {
+static __global__ void __launch_bounds__(256) k_transpose_w(const float* W, float* Wt, int C, int fan, int Cpad) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (long)fan * Cpad) return;
     const int t = (int)(i / Cpad), c = (int)(i - (long)t * Cpad);
@@ -1925,7 +1925,7 @@ __global__ void __launch_bounds__(256) k_transpose_w(const float* W, float* Wt, 
 }
 
 // Dense weights with rows padded to fanpad: Wr[i][j] = W[i][j] for j < fan.
-__global__ void __launch_bounds__(256) k_pad_rows(const float* W, float* Wr, int n_out, int fan, int fanpad) {
+static __global__ void __launch_bounds__(256) k_pad_rows(const float* W, float* Wr, int n_out, int fan, int fanpad) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (long)n_out * fanpad) return;
     const int r = (int)(i / fanpad), j = (int)(i - (long)r * fanpad);

@@ -711,13 +711,13 @@ __global__ void __launch_bounds__(kWave * NW) k_mask_consts(MaskArgs<Ts> A) {
 }
 
 // Copies n 32-bit words.
-__global__ void k_copy_words(uint32_t* dst, const uint32_t* src, long n) {
+static __global__ void k_copy_words(uint32_t* dst, const uint32_t* src, long n) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = src[i];
 }
 
 // Fills n 32-bit words with zero (a kernel, so it can sit in a captured graph).
-__global__ void k_zero_words(uint32_t* dst, long n) {
+static __global__ void k_zero_words(uint32_t* dst, long n) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = 0u;
 }
@@ -841,7 +841,7 @@ struct ReduceArgs {
 // kernel, one thread per subproblem), bit 1 = some multiplier of the
 // subproblem is not finite (second kernel, one thread per neuron of a ReLU
 // layer, flags OR-ed in with vector atomics).
-__global__ void __launch_bounds__(256) k_flags_bound(const double* lb, int32_t* flags, int S) {
+static __global__ void __launch_bounds__(256) k_flags_bound(const double* lb, int32_t* flags, int S) {
     const int s = blockIdx.x * 256 + threadIdx.x;
     if (s < S) flags[s] = isfinite(lb[s]) ? 0 : 1;
 }
@@ -960,7 +960,7 @@ struct IbpArgs {
     float* lo_out; float* hi_out;
 };
 
-__global__ void k_ibp(IbpArgs A) {
+static __global__ void k_ibp(IbpArgs A) {
     const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const LayerGeo& g = A.g;
     if (gid >= (long)A.S * g.out.N) return;

@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define ASD_ABI_VERSION 1
+#define ASD_ABI_VERSION 2
 #define ASD_MAX_LAYERS 16
 #define ASD_MAX_MASKS 8 /* compile-time cap on K_max (active masks per layer) */
 
@@ -157,7 +157,9 @@ void asd_plan_destroy(asd_plan* plan);
 
 /* Loads a batch into the plan (copies bounds into the plan's layout) and sets
  * every dual to zero with no active masks: the interval-propagation start of
- * Algorithm 3 (App. B).  Errors: ASD_EINVAL on S mismatch or null pointers. */
+ * Algorithm 3 (App. B).  The values are checked on the device (empty
+ * intervals, non-finite entries) and reported per subproblem by
+ * asd_check_finite.  Errors: ASD_EINVAL on S mismatch or null pointers. */
 asd_status asd_init(asd_plan* plan, const asd_batch* batch, hipStream_t stream);
 
 /* Phases of the solve. */
@@ -211,10 +213,15 @@ asd_status asd_solve_graph(asd_plan* plan, const asd_batch* batch, double* out_l
 
 /* Per-subproblem health of a solve: flags [S] (device, int32) receives, for
  * each subproblem s, bit 0 set if lb[s] (device [S], as written by asd_bound)
- * is not finite and bit 1 set if any multiplier of s (alpha, beta_0, beta_1,
- * the active masks' beta) is not finite; 0 for a healthy subproblem.  A
- * non-finite bound is no bound: callers should treat such subproblems as
- * unverified.  Errors: ASD_EINVAL for NULL arguments or before asd_init. */
+ * is not finite, bit 1 set if any multiplier of s (alpha, beta_0, beta_1,
+ * the active masks' beta) is not finite, and bit 2 set if the inputs of s
+ * that asd_init loaded are invalid: a non-finite value in l0, u0, lhat, uhat
+ * or c, or an empty interval l0 > u0 or lhat > uhat (an infeasible subdomain,
+ * Sec. 2: its bound is meaningless, not a bound); 0 for a healthy
+ * subproblem.  The solve runs on such subproblems like on any other (no
+ * fault, no effect on the rest of the batch).  Callers should treat flagged
+ * subproblems as unverified.  Errors: ASD_EINVAL for NULL arguments or
+ * before asd_init. */
 asd_status asd_check_finite(asd_plan* plan, const double* lb, int32_t* flags, hipStream_t stream);
 
 /* Solves several plans (for instance one per network of a mixed batch of
@@ -271,14 +278,31 @@ asd_status asd_state_set_counts(asd_plan* plan, const asd_counts* in /* host */,
 
 /* ---- Fixed-dual evaluation and the separation oracle ---- */
 
+/* Kernels asd_eval runs.  ASD_EVAL_GENERAL: the general term-wise kernels
+ * (the arithmetic of FP64 plans and of the FP64 final bound).
+ * ASD_EVAL_ITERATION: the kernels, kernel choices (asd_plan_autotune,
+ * asd_plan_set_tuning) and shared launches an iteration of the plan runs,
+ * with the dual step replaced by writing the supergradient; for an FP64 plan
+ * those are the general kernels, so both paths are the same there. */
+typedef enum { ASD_EVAL_GENERAL = 0, ASD_EVAL_ITERATION = 1 } asd_eval_path;
+
 /* At the current duals and masks, computes with the plan's arithmetic:
- *   obj [S] (device, double): d_B (sum accumulated in FP64),
+ *   obj [S] (device, double): d_B (sum accumulated in FP64); general path
+ *            only (the iteration kernels never form the objective: an FP32
+ *            plan's bound is the FP64 evaluation of asd_bound),
  *   xstar[k] (k = 0..n-1) [S][n_k]: the minimiser x*_k (eq:as-primalk-min,
  *            eq:as-primal0-min), zstar[k] (k = 1..n-1) [S][n_k] 0/1 values,
+ *   f[k] (k = 0..n-1), g[k] (k = 1..n-1) [S][n_k]: the coefficients of the
+ *            Lagrangian in x_k and z_k (eq:dual-anderson-functions restricted
+ *            to the active set, eq:dual-active-set) whose signs choose x*, z*;
+ *            the iteration kernels do not form f exactly where the box of
+ *            the neuron is a point (its x* is the box value whatever f is),
  *   grad_*[k] and grad_mask[k][q]: the supergradient (eq:as-supergradient)
  *            as [S][n_k] arrays.
- * Arrays are float for an FP32 plan and double for an FP64 plan.  Host arrays
- * of device pointers; any entry may be NULL to skip it. */
+ * Arrays are float for an FP32 or mixed plan and double for an FP64 plan.
+ * Host arrays of device pointers; any entry may be NULL to skip it.  The
+ * duals, moments and masks are not changed.  Errors: ASD_EINVAL for an
+ * unknown path, or obj with ASD_EVAL_ITERATION in an FP32-duals plan. */
 typedef struct {
     double* obj;
     void* xstar[ASD_MAX_LAYERS];
@@ -287,6 +311,9 @@ typedef struct {
     void* grad_beta0[ASD_MAX_LAYERS];
     void* grad_beta1[ASD_MAX_LAYERS];
     void* grad_mask[ASD_MAX_LAYERS][ASD_MAX_MASKS];
+    void* f[ASD_MAX_LAYERS];
+    void* g[ASD_MAX_LAYERS];
+    int32_t path; /* asd_eval_path */
 } asd_eval_out;
 asd_status asd_eval(asd_plan* plan, const asd_eval_out* out /* host */, hipStream_t stream);
 

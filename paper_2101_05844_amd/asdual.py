@@ -84,7 +84,13 @@ class EvalOut(C.Structure):
                 ("grad_alpha", C.c_void_p * ASD_MAX_LAYERS),
                 ("grad_beta0", C.c_void_p * ASD_MAX_LAYERS),
                 ("grad_beta1", C.c_void_p * ASD_MAX_LAYERS),
-                ("grad_mask", (C.c_void_p * ASD_MAX_MASKS) * ASD_MAX_LAYERS)]
+                ("grad_mask", (C.c_void_p * ASD_MAX_MASKS) * ASD_MAX_LAYERS),
+                ("f", C.c_void_p * ASD_MAX_LAYERS),
+                ("g", C.c_void_p * ASD_MAX_LAYERS),
+                ("path", C.c_int32)]
+
+
+ASD_EVAL_GENERAL, ASD_EVAL_ITERATION = 0, 1
 
 
 _lib = None
@@ -312,7 +318,8 @@ class Plan:
         return self.bound(want_x0, stream)
 
     def check_finite(self, lb: torch.Tensor, stream=None) -> torch.Tensor:
-        """asd_check_finite: int32 flags [S] (bit 0: bound not finite, bit 1: a multiplier not finite)."""
+        """asd_check_finite: int32 flags [S] (bit 0: bound not finite, bit 1: a multiplier not
+        finite, bit 2: invalid inputs loaded by asd_init)."""
         lb = lb.to(device="cuda", dtype=torch.float64).contiguous()
         flags = torch.empty(self.S, dtype=torch.int32, device="cuda")
         _check(lib().asd_check_finite(self.handle, lb.data_ptr(), flags.data_ptr(), _stream(stream)))
@@ -365,23 +372,31 @@ class Plan:
         _check(lib().asd_state_set_counts(self.handle, C.byref(c), int(recompute), _stream(stream)))
 
     # -- evaluation ----------------------------------------------------------
-    def eval(self, stream=None) -> Dict:
-        """asd_eval at the current duals: objective, x*, z*, supergradient."""
+    def eval(self, path: int = ASD_EVAL_GENERAL, stream=None) -> Dict:
+        """asd_eval at the current duals: objective (general path only), x*,
+        z*, f, g and the supergradient, through the general kernels or the
+        iteration kernels (path ASD_EVAL_ITERATION)."""
         n, S, sizes = self.net.n, self.S, self.net.sizes
         K = self.counts().n_masks
         out = EvalOut()
+        out.path = path
         E = lambda k: torch.empty(S, sizes[k], device="cuda", dtype=self.dtype)
-        res = {"obj": torch.empty(S, dtype=torch.float64, device="cuda"),
+        want_obj = path == ASD_EVAL_GENERAL or self.params.precision == ASD_PREC_FP64
+        res = {"obj": torch.empty(S, dtype=torch.float64, device="cuda") if want_obj else None,
+               "f": [E(k) for k in range(n)],
+               "g": [None] + [E(k) for k in range(1, n)],
                "x": [E(k) for k in range(n)],
                "z": [None] + [E(k) for k in range(1, n)],
                "ga": [None] + [E(k) for k in range(1, n)],
                "gb0": [None] + [E(k) for k in range(1, n)],
                "gb1": [None] + [E(k) for k in range(1, n)],
                "gm": [None] + [[E(k) for _ in range(K)] for k in range(1, n)]}
-        out.obj = res["obj"].data_ptr()
+        out.obj = res["obj"].data_ptr() if want_obj else None
         for k in range(n):
             out.xstar[k] = res["x"][k].data_ptr()
+            out.f[k] = res["f"][k].data_ptr()
             if k >= 1:
+                out.g[k] = res["g"][k].data_ptr()
                 out.zstar[k] = res["z"][k].data_ptr()
                 out.grad_alpha[k] = res["ga"][k].data_ptr()
                 out.grad_beta0[k] = res["gb0"][k].data_ptr()

@@ -146,6 +146,7 @@ void carve_t(asd_plan* P, Carver& cv) {
     P->f0 = cv.take<double>((size_t)P->nl[0].N * S);
     P->gpart = cv.take<double>(P->gpart_w + P->gpart_b);
     P->budgets_dev = cv.take<int>(S);
+    P->inflags = cv.take<int32_t>(S);
     P->lrs = cv.take<T>(S);
     P->Rdev = cv.take<ReluLayerT<T>>(kMaxLayers);
 }
@@ -404,7 +405,8 @@ asd_status fwd_fused(asd_plan* P, int kc, int kd, const StepArgsT<float>& sa, hi
 }
 
 template <typename Tc, typename Ts>
-asd_status launch_backward(asd_plan* P, int k, int want_obj, int role, hipStream_t st, double* fout = nullptr);
+asd_status launch_backward(asd_plan* P, int k, int want_obj, int role, hipStream_t st, double* fout = nullptr,
+                           void* fext = nullptr);
 
 
 // The backward passes into the last ReLU layer (dense, one position per
@@ -437,7 +439,7 @@ asd_status bwd_fast(asd_plan* P, int k, hipStream_t st) {
 
 // Backward pass for neuron layer k (f_k, inner minimisation, terms).
 template <typename Tc, typename Ts>
-asd_status launch_backward(asd_plan* P, int k, int want_obj, int role, hipStream_t st, double* fout) {
+asd_status launch_backward(asd_plan* P, int k, int want_obj, int role, hipStream_t st, double* fout, void* fext) {
     BwdArgs<Ts> a;
     memset(&a, 0, sizeof(a));
     a.gn = gview(P, k + 1);
@@ -455,6 +457,7 @@ asd_status launch_backward(asd_plan* P, int k, int want_obj, int role, hipStream
     a.nk = NA<Ts>(P)[k];
     a.want_obj = want_obj;
     a.fout = fout;
+    a.fext = reinterpret_cast<Ts*>(fext);
     const size_t lds = (size_t)KS * CB * kWave * sizeof(Tc);
     ProfScope ps(P, st, role, k);
     hipLaunchKernelGGL((k_backward<Tc, Ts>), grid_cols(a.gn.in, CB), dim3(kWave, KS), lds, st, a);
@@ -728,10 +731,28 @@ asd_status iteration(asd_plan* P, bool as_phase, int t, double lr, hipStream_t s
     }
 }
 
+// Bit 2 of the plan's input flags for every subproblem whose box, bounds
+// or objective row hold a non-finite value or an empty interval.
+asd_status check_inputs(asd_plan* P, const asd_batch* b, hipStream_t st) {
+    const int S = P->S;
+    TRY(zero_words(P->inflags, S, st));
+    auto launch = [&](const float* lo, const float* hi, long n) -> asd_status {
+        const long tot = n * S;
+        hipLaunchKernelGGL(k_flags_inputs, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, lo, hi, n, S,
+                           P->inflags);
+        LAUNCH_CHECK();
+        return ASD_OK;
+    };
+    TRY(launch(b->l0, b->u0, P->nl[0].N));
+    for (int k = 1; k < P->n; ++k) TRY(launch(b->lhat[k - 1], b->uhat[k - 1], P->nl[k].N));
+    return launch(b->c, nullptr, P->nl[P->n].N);
+}
+
 template <typename T>
 asd_status init_t(asd_plan* P, const asd_batch* b, hipStream_t st) {
     const int S = P->S;
     NeuronArraysT<T>* na = NA<T>(P);
+    TRY(check_inputs(P, b, st));
     TRY((launch_layout<T, const float>(na[0].lo, b->l0, P->nl[0], S, 0, st)));
     TRY((launch_layout<T, const float>(na[0].hi, b->u0, P->nl[0], S, 0, st)));
     for (int k = 1; k < P->n; ++k) {
@@ -984,10 +1005,36 @@ asd_status set_counts_t(asd_plan* P, int recompute, hipStream_t st) {
     return pack_all<T>(P, 0, st);
 }
 
+// Minimiser, f, g of every layer and the supergradient at the current duals.
+// General path: the term-wise kernels.  Iteration path (FP32-duals plans):
+// the backward and forward launches of iteration() with the plan's kernel
+// choices, the update replaced by writing the supergradient (kRuleEval).
 template <typename T>
 asd_status eval_t(asd_plan* P, const asd_eval_out* out, hipStream_t st) {
-    for (int k = P->n - 1; k >= 0; --k) TRY((launch_backward<T, T>(P, k, 1, ASD_K_OTHER, st)));
-    if (out->obj) TRY(reduce_objective<T>(P, out->obj, st));
+    constexpr bool kGeneral = sizeof(T) == 8;
+    const bool iter = !kGeneral && out->path == ASD_EVAL_ITERATION;
+    if (iter) {
+        if (out->obj) return fail(ASD_EINVAL, "the iteration kernels do not form the objective (obj must be NULL)");
+        struct Clear {
+            asd_plan* P;
+            ~Clear() {
+                memset(P->ev_f, 0, sizeof(P->ev_f));
+                memset(P->ev_g, 0, sizeof(P->ev_g));
+            }
+        } clear{P};
+        for (int k = 0; k < P->n; ++k) P->ev_f[k] = out->f[k];
+        const int kpair = bwd_pair_layer(P);
+        for (int k = P->n - 1; k >= 0; --k) {
+            if (k == kpair) continue;
+            if (kpair >= 0 && k == P->n - 1) TRY(bwd_pair(P, st));
+            else TRY(bwd_fast(P, k, st));
+        }
+        memset(P->ev_f, 0, sizeof(P->ev_f));
+    } else {
+        for (int k = P->n - 1; k >= 0; --k)
+            TRY((launch_backward<T, T>(P, k, 1, ASD_K_OTHER, st, nullptr, out->f[k])));
+        if (out->obj) TRY(reduce_objective<T>(P, out->obj, st));
+    }
     for (int k = 0; k < P->n; ++k) {
         if (out->xstar[k])
             TRY((launch_layout<T, T>(NA<T>(P)[k].xstar, reinterpret_cast<T*>(out->xstar[k]), P->nl[k], P->S, 2,
@@ -995,8 +1042,26 @@ asd_status eval_t(asd_plan* P, const asd_eval_out* out, hipStream_t st) {
         if (k >= 1 && out->zstar[k])
             TRY((launch_bits<T, T>(P->nl[k], P->S, 0, RL<T>(P)[k].zbits, reinterpret_cast<T*>(out->zstar[k]),
                                    nullptr, nullptr, st)));
+        if (k >= 1 && out->g[k])
+            TRY((launch_layout<T, T>(RL<T>(P)[k].g, reinterpret_cast<T*>(out->g[k]), P->nl[k], P->S, 2, st)));
     }
-    const StepArgsT<T> sa = make_step_args<T>(P, 0.0);
+    StepArgsT<T> sa = make_step_args<T>(P, 0.0);
+    if (iter) {
+        sa.rule = kRuleEval;
+        bool any = false;
+        for (int k = 1; k < P->n; ++k) {
+            void* gk[3] = {out->grad_alpha[k], out->grad_beta0[k], out->grad_beta1[k]};
+            for (int i = 0; i < 3; ++i) P->ev_g[k][i] = gk[i];
+            for (int q = 0; q < kMaxMasks; ++q) P->ev_g[k][3 + q] = q < P->n_masks ? out->grad_mask[k][q] : nullptr;
+            for (int i = 0; i < 3 + kMaxMasks; ++i) any = any || P->ev_g[k][i];
+        }
+        asd_status r = ASD_OK;
+        if (any) {
+            if constexpr (!kGeneral) r = forward_pass<T>(P, sa, st);
+        }
+        memset(P->ev_g, 0, sizeof(P->ev_g));
+        return r;
+    }
     for (int k = 1; k < P->n; ++k) {
         void* gout[3 + kMaxMasks] = {out->grad_alpha[k], out->grad_beta0[k], out->grad_beta1[k]};
         bool any = gout[0] || gout[1] || gout[2];
@@ -1484,7 +1549,8 @@ asd_status asd_solve(asd_plan* P, const asd_batch* b, double* out_lb, float* x0,
 asd_status asd_check_finite(asd_plan* P, const double* lb, int32_t* flags, hipStream_t st) {
     if (!P || !lb || !flags) return fail(ASD_EINVAL, "NULL argument");
     if (!P->loaded) return fail(ASD_EINVAL, "asd_init has not been called");
-    hipLaunchKernelGGL(k_flags_bound, dim3((unsigned)((P->S + 255) / 256)), dim3(256), 0, st, lb, flags, P->S);
+    hipLaunchKernelGGL(k_flags_bound, dim3((unsigned)((P->S + 255) / 256)), dim3(256), 0, st, lb,
+                       (const int32_t*)P->inflags, flags, P->S);
     LAUNCH_CHECK();
     return is64(P) ? check_finite_t<double>(P, flags, st) : check_finite_t<float>(P, flags, st);
 }
@@ -1590,6 +1656,8 @@ asd_status asd_eval(asd_plan* P, const asd_eval_out* out, hipStream_t st) {
     if (!P || !out) return fail(ASD_EINVAL, "NULL argument");
     P->min_valid = false;
     if (!P->loaded) return fail(ASD_EINVAL, "asd_init has not been called");
+    if (out->path != ASD_EVAL_GENERAL && out->path != ASD_EVAL_ITERATION)
+        return fail(ASD_EINVAL, "unknown evaluation path %d", out->path);
     return is64(P) ? eval_t<double>(P, out, st) : eval_t<float>(P, out, st);
 }
 

@@ -120,7 +120,24 @@ struct FastFwdArgs {
     int Sa;                     // subproblems updated: s < Sa (the geometry's
                                 // column counts cover the same prefix)
     T* part;                    // dense: partial products [ksplit][1 + nm][Cpad][S]
+    // evaluation at fixed duals (st.rule == kRuleEval): the supergradient
+    // entries of alpha, beta_0, beta_1 and each slot's beta, caller layout
+    // [S][n_k] (null: not wanted); nothing of the state is written
+    T* gout[3 + kMaxMasks];
 };
+
+// Update rule of an evaluation pass (not a public asd_rule): the update
+// kernels write the supergradient to FastFwdArgs::gout instead of stepping.
+constexpr int kRuleEval = 2;
+
+// Element idx = (c S + s) P + p of a layer's internal layout at its place
+// (s, c, p) in the caller's row-major [S][N] layout.
+__device__ __forceinline__ long caller_index(uint32_t idx, int S, const NeuronLayout& L) {
+    const uint32_t sp = (uint32_t)S * (uint32_t)L.P;
+    const uint32_t c = idx / sp, r = idx - c * sp;
+    const uint32_t s = r / (uint32_t)L.P, p = r - s * (uint32_t)L.P;
+    return (long)s * L.N + (long)c * L.P + p;
+}
 
 // State of one neuron read by the update (loads only, so that the loads of
 // several neurons can be in flight together: the compiler cannot move a
@@ -185,7 +202,7 @@ __device__ __forceinline__ void fwd_load(const FastFwdArgs<T>& A, int c, uint32_
     static_assert(!MB || sizeof(T) == 4, "BF16 moments go with FP32 duals");
     __builtin_assume(idx < (1u << 30));  // byte offsets fit 32 bits (checked at plan creation)
     const cptr_t<ReluLayerT<T>> R = kconst_t(A.R);
-    const bool adam = A.st.rule != ASD_RULE_SUPERGRADIENT;
+    const bool adam = A.st.rule == ASD_RULE_ADAM;
     in.bb = (T)A.g.b[c];
     in.x = A.xout[idx];
     in.z = (T)getbit(R->zbits, bi);
@@ -245,6 +262,23 @@ __device__ __forceinline__ void fwd_store(const FastFwdArgs<T>& A, uint32_t idx,
     gr[0] = xhat - x;
     gr[1] = x - z * uh;
     gr[2] = x - xhat + ((T)1 - z) * lh;
+    // supergradient of slot q's multiplier from the masked product
+    // (W . I_q) x = z_q ? yd : (yd + ym[q]) / 2
+    auto gmask = [&](int q) -> T {
+        const bool zb = (in.zq >> q) & 1u;
+        const T mq = zb ? yd : (T)0.5 * (yd + ym[q]);
+        return x - mq + in.LI[q] * ((T)1 - z) - z * bb - in.UI[q] * z;
+    };
+    if (st.rule == kRuleEval) {
+        const long ex = caller_index(idx, A.S, A.g.out);
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            if (A.gout[j]) A.gout[j][ex] = gr[j];
+#pragma unroll
+        for (int q = 0; q < NM; ++q)
+            if (A.gout[3 + q]) A.gout[3 + q][ex] = gmask(q);
+        return;
+    }
     // Adam: theta + (lr / (1 - b1^t)) m / (sqrt(v / (1 - b2^t)) + eps), with
     // the hardware square root and reciprocal (a few ulps in FP32)
     const T lr_s = st.lrs ? st.lrs[s] : st.lr;
@@ -279,9 +313,7 @@ __device__ __forceinline__ void fwd_store(const FastFwdArgs<T>& A, uint32_t idx,
     for (int q = 0; q < NM; ++q) {
         const cptr_t<MaskSlotT<T>> M = &R->slot[q];
         const bool zb = (in.zq >> q) & 1u;
-        const T mq = zb ? yd : (T)0.5 * (yd + ym[q]);
-        const T gm = x - mq + in.LI[q] * ((T)1 - z) - z * bb - in.UI[q] * z;
-        const T bq = step(in.bq[q], in.mq[q], in.vq[q], gm, 1 + q, M->m, M->v);
+        const T bq = step(in.bq[q], in.mq[q], in.vq[q], gmask(q), 1 + q, M->m, M->v);
         M->beta[idx] = bq;
         own -= bq;
         gg += bq * (in.LI[q] + in.UI[q] + bb);
@@ -914,6 +946,7 @@ struct FastBwdArgs {
     const T* own;               // layer k (k >= 1)
     const T* gk;
     uint32_t* zbits;            // layer k (k >= 1)
+    T* fout;                    // evaluation at fixed duals: f_k, caller layout [S][n_k] (else null)
 };
 
 // Finishing a neuron of layer k from its f (without own): x*, bits, in
@@ -949,6 +982,7 @@ __device__ __forceinline__ void bwd_store(const FastBwdArgs<T>& A, bool ok, uint
     bool xb = false, zb = false;
     if (ok) {
         if (A.k >= 1) f += in.own;
+        if (A.fout) A.fout[caller_index(idx, A.S, A.gn.in)] = f;
         xb = f >= (T)0 || in.dg;
         A.nk.xstar[idx] = xb ? in.hi : in.lo;
         if (A.k >= 1) zb = in.g >= (T)0;
@@ -1826,8 +1860,10 @@ __device__ __forceinline__ void bwd_dense_mfma_block(const FastBwdArgs<float>& A
         bool xb = false, zb = false;
         if (ok) {
             if (A.k >= 1) f += in[r].own;
+            const long idx = ((long)c * S + s) * L.P + p;
+            if (A.fout) A.fout[caller_index((uint32_t)idx, S, L)] = f;
             xb = f >= 0.f || in[r].dg;
-            A.nk.xstar[((long)c * S + s) * L.P + p] = xb ? in[r].hi : in[r].lo;
+            A.nk.xstar[idx] = xb ? in[r].hi : in[r].lo;
             if (A.k >= 1) zb = in[r].g >= 0.f;
         }
         const unsigned long long mx = __ballot(xb);

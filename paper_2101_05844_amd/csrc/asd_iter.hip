@@ -188,6 +188,7 @@ asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
     a.Wl4 = P->Wl4[k + 1];
     a.Wl8 = P->Wl8[k + 1];
     a.nkp = P->nkp[k + 1];
+    a.fout = reinterpret_cast<T*>(P->ev_f[k]);
     if (g.kind == ASD_LAYER_CONV2D && L.P % kWave == 0 && L.C >= 16) {
         // matrix-core transposed convolution over parity classes, operands
         // staged in LDS (see k_bwd_conv_mfma); shapes it cannot hold fall

@@ -337,6 +337,7 @@ struct BwdArgs {
     const float* bk;            // bias of layer k (k >= 1), per channel
     int want_obj;
     double* fout;               // if set: f_k per neuron (internal layout)
+    Ts* fext;                   // if set: f_k per neuron (caller layout [S][n_k])
 };
 
 template <typename Tc, typename Ts>
@@ -512,6 +513,7 @@ __global__ void __launch_bounds__(kWave * KS) k_backward(BwdArgs<Ts> A) {
         const int nmo = A.nm_own;
         if (A.k >= 1) f += kFinal64 ? (Tc)A.Rk.own64[idx] : (Tc)A.Rk.own[idx];
         if (A.fout) A.fout[idx] = (double)f;
+        if (A.fext) A.fext[(long)s * L.N + (long)c * L.P + p] = (Ts)f;
         // x-bit "x* = upper end"; a point box counts as both ends and keeps the bit set
         xb = f >= 0 || ((dg4 >> e) & 1u);
         const Tc xv = xb ? (Tc)A.nk.hi[idx] : (Tc)A.nk.lo[idx];
@@ -841,9 +843,26 @@ struct ReduceArgs {
 // kernel, one thread per subproblem), bit 1 = some multiplier of the
 // subproblem is not finite (second kernel, one thread per neuron of a ReLU
 // layer, flags OR-ed in with vector atomics).
-static __global__ void __launch_bounds__(256) k_flags_bound(const double* lb, int32_t* flags, int S) {
+static __global__ void __launch_bounds__(256) k_flags_bound(const double* lb, const int32_t* inflags, int32_t* flags,
+                                                            int S) {
     const int s = blockIdx.x * 256 + threadIdx.x;
-    if (s < S) flags[s] = isfinite(lb[s]) ? 0 : 1;
+    if (s < S) flags[s] = (isfinite(lb[s]) ? 0 : 1) | inflags[s];
+}
+
+// Input check of a batch (caller layout [S][n]): bit 2 of flags[s] is set
+// where an entry of subproblem s is not finite or, with hi given, lo > hi
+// (an empty interval: the subdomain is infeasible).  One thread per entry.
+static __global__ void __launch_bounds__(256) k_flags_inputs(const float* lo, const float* hi, long n, int S,
+                                                             int32_t* flags) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n * S) return;
+    const float a = lo[i];
+    bool bad = !isfinite(a);
+    if (hi) {
+        const float b = hi[i];
+        bad = bad || !isfinite(b) || a > b;
+    }
+    if (bad) atomicOr(&flags[i / n], 4);
 }
 
 template <typename T>

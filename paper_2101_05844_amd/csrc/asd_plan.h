@@ -99,6 +99,7 @@ struct asd_plan {
     bool ragged;
     std::vector<int> budgets;
     int* budgets_dev;                 // [S]
+    int32_t* inflags;                 // [S] input check of the loaded batch (bit 2: invalid inputs)
     void* lrs;                        // [S] learning rates of the current iteration (T)
     int Sa;                           // subproblems the current iteration updates (a prefix)
     // captured iteration schedule (asd_solve_graph) and the host state it ends in
@@ -110,6 +111,10 @@ struct asd_plan {
     int step;
     int mask_step[asd::kMaxMasks];
     bool loaded;
+    // evaluation at fixed duals through the iteration kernels (asd_eval):
+    // caller arrays for f_k and the supergradient of layer k, null otherwise
+    void* ev_f[asd::kMaxLayers];
+    void* ev_g[asd::kMaxLayers][3 + asd::kMaxMasks];
     // kernel timing
     bool prof;
     std::vector<asd::ProfRec> prof_recs;
@@ -203,6 +208,8 @@ FastFwdArgs<T> fwd_args(asd_plan* P, int k, int nm, const StepArgsT<T>& sa) {
     a.R = RdevT<T>(P) + k;
     a.st = sa;
     a.part = reinterpret_cast<T*>(P->part);
+    if (sa.rule == kRuleEval)
+        for (int i = 0; i < 3 + kMaxMasks; ++i) a.gout[i] = reinterpret_cast<T*>(P->ev_g[k][i]);
     return a;
 }
 
@@ -268,6 +275,7 @@ FastBwdArgs<T> bwd_args(asd_plan* P, int k, int nm) {
     a.Wl4 = P->Wl4[k + 1];
     a.Wl8 = P->Wl8[k + 1];
     a.nkp = P->nkp[k + 1];
+    a.fout = reinterpret_cast<T*>(P->ev_f[k]);
     return a;
 }
 

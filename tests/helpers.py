@@ -117,3 +117,100 @@ def objective_scale(p: O.Problem, st: O.DualState) -> float:
     sc += sum(float(np.abs(fk * xk).sum()) for fk, xk in zip(f, x))
     sc += sum(float(np.abs(gk * zk).sum()) for gk, zk in zip(g, z))
     return sc
+
+
+def _absop(op):
+    return op.with_data(np.abs(op.w))
+
+
+def f_row_scale(p: O.Problem, st: O.DualState, k: int) -> np.ndarray:
+    """Sum of the magnitudes of the terms of f_k (eq:dual-anderson-functions
+    restricted to the active set): the rounding scale of each entry."""
+    n = p.n
+    opn = _absop(p.W(k + 1))
+    if k + 1 == n:
+        v = np.abs(p.c)
+    else:
+        v = np.abs(st.alpha[k]) + np.abs(st.beta1[k])
+        for M in st.masks[k]:
+            v = v + np.abs(M.beta)
+    sc = opn.T @ v
+    if k >= 1:
+        sc = sc + np.abs(st.alpha[k - 1]) + np.abs(st.beta0[k - 1]) + np.abs(st.beta1[k - 1])
+        for M in st.masks[k - 1]:
+            sc = sc + np.abs(M.beta)
+    return sc
+
+
+def g_row_scale(p: O.Problem, st: O.DualState, k: int) -> np.ndarray:
+    lh, uh = p.hat(k)
+    b = np.abs(p.W(k).b)
+    sc = np.abs(st.beta0[k - 1] * uh) + np.abs(st.beta1[k - 1] * lh)
+    for M in st.masks[k - 1]:
+        sc = sc + np.abs(M.beta) * (np.abs(M.UI) + np.abs(M.LI) + b)
+    return sc
+
+
+def grad_row_scale(p: O.Problem, st: O.DualState, x, k: int) -> np.ndarray:
+    """Magnitudes of the terms of the layer-k supergradient entries
+    (eq:as-supergradient) at the primal point x."""
+    lh, uh = p.hat(k)
+    op = p.W(k)
+    sc = _absop(op) @ np.abs(x[k - 1]) + np.abs(op.b) + np.abs(x[k]) + np.abs(lh) + np.abs(uh)
+    for M in st.masks[k - 1]:
+        sc = sc + np.abs(M.LI) + np.abs(M.UI)
+    return sc
+
+
+def check_eval_against_oracle(res, rows, eps):
+    """Element-wise comparison of an asd_eval result with the oracle.
+
+    rows: iterable of (s, problem, state) (s = the subproblem's row in the
+    batch).  f_k and g_k within eps times their row scale (f skipped where
+    the neuron's box is a point: the iteration kernels do not form it
+    there); x*, z* equal to the oracle's minimiser wherever the oracle's
+    |f| (|g|) exceeds eps times its scale; every supergradient entry equal,
+    within eps times its row scale, to the oracle's supergradient at the
+    GPU's own primal point (x*, z* are valid minimisers at ties too).
+    Returns counts of the compared and the tie-excused entries."""
+    cnt = {"f": 0, "g": 0, "x": 0, "z": 0, "grad": 0, "x_ties": 0, "z_ties": 0, "f_point": 0}
+    for s, p, st in rows:
+        d, x, z, f, g = O.evaluate(p, st)
+        xg = [res["x"][k][s].cpu().numpy().astype(np.float64) for k in range(p.n)]
+        zg = [res["z"][k][s].cpu().numpy().astype(np.float64) for k in range(1, p.n)]
+        for k in range(p.n):
+            lo, hi = p.lu(k)
+            point = lo == hi
+            fsc = eps * (1.0 + f_row_scale(p, st, k))
+            fg = res["f"][k][s].cpu().numpy().astype(np.float64)
+            ok = (np.abs(fg - f[k]) <= fsc) | point
+            assert ok.all(), ("f", s, k, np.flatnonzero(~ok)[:5], fg[~ok][:5], f[k][~ok][:5])
+            cnt["f"] += int((~point).sum())
+            cnt["f_point"] += int(point.sum())
+            assert np.all((xg[k] == lo) | (xg[k] == hi)), ("x* off the box ends", s, k)
+            sure = np.abs(f[k]) > fsc
+            assert np.all((xg[k] == x[k]) | ~sure), ("x*", s, k, np.flatnonzero((xg[k] != x[k]) & sure)[:5])
+            cnt["x"] += int(sure.sum())
+            cnt["x_ties"] += int((~sure).sum())
+        for k in range(1, p.n):
+            gsc = eps * (1.0 + g_row_scale(p, st, k))
+            gg = res["g"][k][s].cpu().numpy().astype(np.float64)
+            ok = np.abs(gg - g[k - 1]) <= gsc
+            assert ok.all(), ("g", s, k, np.flatnonzero(~ok)[:5])
+            cnt["g"] += ok.size
+            sure = np.abs(g[k - 1]) > gsc
+            assert np.all((zg[k - 1] == z[k - 1]) | ~sure), ("z*", s, k)
+            cnt["z"] += int(sure.sum())
+            cnt["z_ties"] += int((~sure).sum())
+        sg = O.supergradient(p, st, xg, zg)
+        for k in range(1, p.n):
+            tol = eps * (1.0 + grad_row_scale(p, st, xg, k))
+            items = [("ga", sg["alpha"][k - 1]), ("gb0", sg["beta0"][k - 1]), ("gb1", sg["beta1"][k - 1])]
+            items += [(("gm", q), sg["masks"][k - 1][q]) for q in range(len(st.masks[k - 1]))]
+            for key, ref in items:
+                got = res[key[0]][k][key[1]][s] if isinstance(key, tuple) else res[key][k][s]
+                got = got.cpu().numpy().astype(np.float64)
+                bad = np.abs(got - ref) > tol
+                assert not bad.any(), (key, s, k, np.flatnonzero(bad)[:5], got[bad][:5], ref[bad][:5])
+                cnt["grad"] += got.size
+    return cnt

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
     for n in declared_functions():
         assert hasattr(lib, n), n
     lib.asd_abi_version.restype = ctypes.c_int32
-    assert lib.asd_abi_version() == 1
+    assert lib.asd_abi_version() == 2
     lib.asd_last_error.restype = ctypes.c_char_p
     assert isinstance(lib.asd_last_error(), bytes)
 
@@ -62,3 +62,40 @@ def test_host_validation_without_gpu():
     p.max_masks = 99
     assert L.asd_plan_workspace_size(h, 4, ctypes.byref(p), ctypes.byref(nbytes)) == 1
     L.asd_net_destroy(h)
+
+
+STRUCTS = {"asd_layer_desc": "LayerDesc", "asd_params": "Params", "asd_batch": "Batch", "asd_counts": "Counts",
+           "asd_kernel_time": "KernelTime", "asd_tuning": "Tuning", "asd_eval_out": "EvalOut"}
+
+
+def test_binding_structs_match_header(tmp_path):
+    """Every struct the binding passes through ctypes has the size and field
+    offsets the C compiler gives the header's declaration (gcc, host only)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None or not os.path.exists("/opt/rocm/include/hip/hip_runtime_api.h"):
+        pytest.skip("gcc or the HIP headers are missing")
+    from paper_2101_05844_amd import asdual as A
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "asdual.h"', "int main(void) {"]
+    for cname, pyname in STRUCTS.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in getattr(A, pyname)._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"), "-I", "/opt/rocm/include",
+                    str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln:
+            c, f, v = ln.split()
+            got[(c, f)] = int(v)
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(A, pyname)
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)

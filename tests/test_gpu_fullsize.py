@@ -119,6 +119,31 @@ def test_fullsize_fixed_dual_evaluation_fp32(cifar):
                 assert np.all(np.abs(gg - sg["masks"][k - 1][q])[same] <= tol[same])
 
 
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+def test_fullsize_iteration_kernels_at_fixed_duals(cifar, prec):
+    """The benchmark's launch configuration (autotuned kernel choices, shared
+    launches) evaluated at imported duals with two masks per layer through
+    asd_eval's iteration path: on the sampled subdomains f, g, x*, z* and
+    every supergradient entry match the oracle within 1e-5 of their row
+    scales (eq:dual-active-set, eq:as-primalk-min, eq:as-supergradient)."""
+    w, ops, L, U = cifar
+    from paper_2101_05844_amd import asdual as A
+    A.lib()
+    prm = A.params_from_schedule(w.schedule, A.ASD_PREC_MIXED if prec == "mixed" else A.ASD_PREC_FP32)
+    net = A.Net(w.layers)
+    plan = A.Plan(net, w.S, prm)
+    plan.init(*H.gpu_batch(w, L, U))
+    tuning = plan.autotune(ktune=2, reps=3)
+    states = _random_state_import(A, plan, w, ops, L, U, n_masks=2, seed=11)
+    res = plan.eval(path=A.ASD_EVAL_ITERATION)
+    torch.cuda.synchronize()
+    cnt = H.check_eval_against_oracle(res, [(s, p, st) for s, (p, st) in states.items()], 1e-5)
+    n_grad = len(SAMPLED) * sum(Lr.n_out * (3 + 2) for Lr in w.layers[:-1])
+    assert cnt["grad"] == n_grad, cnt
+    assert cnt["x_ties"] <= 0.01 * cnt["x"] and cnt["z_ties"] <= 0.01 * cnt["z"], cnt
+    print("tuning", tuning, cnt, flush=True)
+
+
 def test_fullsize_one_iteration_fp32(cifar):
     """One Big-M-phase iteration (plain rule) from an imported state, at the
     full batch: sampled subdomains match the oracle's iteration."""

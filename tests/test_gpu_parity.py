@@ -152,6 +152,139 @@ def test_fixed_dual_evaluation(wi, n_masks, prec):
                 assert np.all(np.abs(LI - M.LI) <= rs) and np.all(np.abs(UI - M.UI) <= rs)
 
 
+def _eval_all_alternatives(A, plan, probs, states, n_masks):
+    """asd_eval through the iteration kernels under the plan's default kernel
+    choices, every single-choice alternative the autotuner may take, and the
+    default choices with every kernel launched alone: f, g, x*, z* and the
+    supergradient against the oracle (check_eval_against_oracle)."""
+    base, alts = _tuning_alternatives(A, plan)
+    rows = [(s, p, st) for s, (p, st) in enumerate(zip(probs, states))]
+    n_grad = sum(p.W(k).n_out * (3 + n_masks) for p in probs for k in range(1, p.n))
+    tot = {}
+    for field, idx, val in [(None, None, None)] + alts + [("profile", None, True)]:
+        tun = {f: list(v) for f, v in base.items()}
+        if field not in (None, "profile"):
+            tun[field][idx] = val
+        plan.set_tuning(tun)
+        plan.profile(field == "profile")
+        res = plan.eval(path=A.ASD_EVAL_ITERATION)
+        torch.cuda.synchronize()
+        cnt = H.check_eval_against_oracle(res, rows, EPS["fp32"])
+        # every supergradient entry of every subproblem was compared
+        assert cnt["grad"] == n_grad, (field, cnt)
+        # primal choices: only near-ties of the oracle's f and g are excused
+        assert cnt["x_ties"] <= 0.01 * (cnt["x"] + cnt["x_ties"]) + 2, (field, cnt)
+        assert cnt["z_ties"] <= 0.01 * (cnt["z"] + cnt["z_ties"]) + 2, (field, cnt)
+        for key, v in cnt.items():
+            tot[key] = tot.get(key, 0) + v
+    plan.profile(False)
+    plan.set_tuning(base)
+    return tot
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+@pytest.mark.parametrize("wi", [0, 1, 2, 3])
+@pytest.mark.parametrize("n_masks", [0, 3])
+def test_iteration_kernels_at_fixed_duals(wi, n_masks, prec):
+    """The kernels FP32 and mixed-mode iterations run (the (1 + K) products,
+    the fused supergradient, the shared launches), evaluated at imported
+    duals and masks (asd_eval, ASD_EVAL_ITERATION): f, g, x*, z* and every
+    supergradient entry match the oracle (eq:dual-active-set,
+    eq:as-primalk-min, eq:as-supergradient) within 1e-5 of their row
+    scales, under every kernel choice of the autotuner."""
+    w = workloads_small()[wi]
+    A = _A()
+    params = A.params_from_schedule(w.schedule, A.ASD_PREC_MIXED if prec == "mixed" else A.ASD_PREC_FP32)
+    A, ops, probs, net, plan, _ = _setup(w, params)
+    rng = np.random.default_rng(500 + 10 * wi + n_masks)
+    states = [H.random_integral_state(p, rng, n_masks, scale=0.5) for p in probs]
+    H.import_states(plan, probs, states)
+    tot = _eval_all_alternatives(A, plan, probs, states, n_masks)
+    print(w.name, n_masks, prec, tot, flush=True)
+
+
+@pytest.mark.parametrize("shape", ["c1x16x8", "c4x16x16", "c2x8x64"])
+def test_iteration_kernels_at_fixed_duals_m4(shape):
+    """As above on the input layers of the 4-channel matrix-core transposed
+    convolution (1, 2 and 4 channels in rows of 8, 16 and 64 positions)."""
+    sched = WL.Schedule(bigm_iters=8, as_iters=8, add_every=5, add_count=2, max_masks=3)
+    w = WL.custom_config(M4_SHAPES[shape], S=5, seed=31, eps=0.05, schedule=sched, max_fixed=3, name=shape)
+    A, ops, probs, net, plan, _ = _setup(w, prec="fp32")
+    rng = np.random.default_rng(41)
+    states = [H.random_integral_state(p, rng, 3, scale=0.5) for p in probs]
+    H.import_states(plan, probs, states)
+    _eval_all_alternatives(A, plan, probs, states, 3)
+
+
+def _point_box_workload():
+    """The small conv net with point boxes away from zero: some input
+    coordinates with l0 = u0 > 0 and, in every ReLU layer, some neurons with
+    lhat = uhat > 0 (a fixed positive post-activation value).  At fixed
+    duals the bound is a function of the given boxes, valid or not, so both
+    sides evaluate the same function."""
+    w = workloads_small()[1]
+    ops, lh, uh = H.oracle_bounds(w)
+    rng = np.random.default_rng(77)
+    l0, u0 = w.l0.copy(), w.u0.copy()
+    pick = rng.random(l0.shape) < 0.2
+    mid = H.f32(np.clip((l0 + u0) / 2, 0.05, None))
+    l0 = np.where(pick, mid, l0).astype(np.float32)
+    u0 = np.where(pick, mid, u0).astype(np.float32)
+    lh2, uh2 = [], []
+    for a, b in zip(lh, uh):
+        pk = rng.random(a.shape) < 0.2
+        val = H.f32(np.abs(b) * 0.5 + 0.01)
+        lh2.append(np.where(pk, val, a).astype(np.float32))
+        uh2.append(np.where(pk, val, b).astype(np.float32))
+    w.l0, w.u0 = l0, u0
+    return w, ops, lh2, uh2
+
+
+@pytest.mark.parametrize("n_masks", [1, 3])
+def test_point_boxes_away_from_zero(n_masks):
+    """Point boxes away from zero (the W+ x_point correction of the compact
+    masks in the iteration kernels, and the general kernels' point-box
+    rule): both evaluation paths against the oracle, and one iteration under
+    the plain rule against the oracle's step."""
+    A = _A()
+    w, ops, lh, uh = _point_box_workload()
+    probs = H.oracle_problems(w, ops, lh, uh)
+    net = A.Net(w.layers)
+    prm = A.params_from_schedule(w.schedule, A.ASD_PREC_FP32)
+    prm.rule = A.ASD_RULE_SUPERGRADIENT
+    prm.bigm_lr0, prm.bigm_lr1, prm.as_lr0, prm.as_lr1 = 1e-3, 1e-4, 1e-4, 1e-5
+    plan = A.Plan(net, w.S, prm)
+    batch = H.gpu_batch(w, lh, uh)
+    plan.init(*batch)
+    rng = np.random.default_rng(78 + n_masks)
+    states = [H.random_integral_state(p, rng, n_masks, scale=0.5) for p in probs]
+    assert any((p.lu(0)[0] == p.lu(0)[1]).any() and (p.lu(0)[0] > 0).any() for p in probs)
+    H.import_states(plan, probs, states)
+    _eval_all_alternatives(A, plan, probs, states, n_masks)
+    res = plan.eval(path=A.ASD_EVAL_GENERAL)
+    torch.cuda.synchronize()
+    H.check_eval_against_oracle(res, [(s, p, st) for s, (p, st) in enumerate(zip(probs, states))], EPS["fp32"])
+    # one step of the plain rule from the imported state (t = 3: no mask
+    # addition, 3 mod omega >= V)
+    t = 3
+    plan.run(A.ASD_PHASE_AS, t, 1)
+    torch.cuda.synchronize()
+    K = plan.counts().n_masks
+    duals = H.export_duals(plan, len(ops), K)
+    oprm = O.params_from_schedule(w.schedule)
+    lr = O.linear_lr(1e-4, 1e-5, t, oprm.as_iters)
+    for s, (p, st) in enumerate(zip(probs, states)):
+        d, x, z, _, _ = O.evaluate(p, st)
+        e = st.copy()
+        O.apply_step(e, O.supergradient(p, st, x, z), lr, "sgd", oprm.adam)
+        for k in range(1, p.n):
+            pairs = [(duals[("alpha", k)][s], e.alpha[k - 1]), (duals[("beta0", k)][s], e.beta0[k - 1]),
+                     (duals[("beta1", k)][s], e.beta1[k - 1])]
+            pairs += [(duals[("mask", k, q)][s], e.masks[k - 1][q].beta) for q in range(K)]
+            for a, b in pairs:
+                assert np.all(np.abs(a - b) <= 1e-5 * (1 + np.abs(b))), (s, k)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 @pytest.mark.parametrize("wi", [0, 1])
 @pytest.mark.parametrize("integral", [True, False])
@@ -691,7 +824,8 @@ def _check_alternatives(w):
             for s, r in enumerate(runs):
                 e = r.snapshots[(ph, t + 1)]
                 for k in range(1, len(ops)):
-                    pairs = [(duals[("alpha", k)][s], e.alpha[k - 1]), (duals[("beta1", k)][s], e.beta1[k - 1])]
+                    pairs = [(duals[("alpha", k)][s], e.alpha[k - 1]), (duals[("beta0", k)][s], e.beta0[k - 1]),
+                             (duals[("beta1", k)][s], e.beta1[k - 1])]
                     pairs += [(duals[("mask", k, q)][s], e.masks[k - 1][q].beta) for q in range(K)]
                     for a, b in pairs:
                         assert np.all(np.abs(a - b) <= 1e-5 * (1 + np.abs(b))), (field, idx, val, ph, t, s, k)
@@ -766,3 +900,33 @@ def test_check_finite_flags():
     want[3] |= 2
     want[5] |= 1
     assert np.array_equal(flags, want), flags
+
+
+def test_invalid_inputs_are_flagged_not_fatal():
+    """Subproblems with an empty input interval (l0 > u0), an empty
+    pre-activation interval (lhat > uhat: an infeasible subdomain), a NaN
+    bound or an infinite objective entry: the solve completes, bit 2 of
+    exactly those subproblems' flags is set, and every other subproblem's
+    bound is bit-identical to a solve of the clean batch."""
+    w = workloads_small()[1]
+    A, ops, probs, net, plan, batch = _setup(w, prec="fp32")
+    clean = plan.solve(*batch).cpu().numpy()
+    assert int(plan.check_finite(torch.as_tensor(clean)).abs().sum().item()) == 0
+    l0, u0, lht, uht, c = [t.clone() if isinstance(t, torch.Tensor) else [x.clone() for x in t] for t in batch]
+    bad = {2: "l0 > u0", 4: "lhat > uhat", 6: "nan bound", 8: "inf objective"}
+    l0[2, 5] = u0[2, 5] + 0.5
+    lht[1][4, 3] = uht[1][4, 3] + 1.0
+    uht[0][6, 0] = float("nan")
+    c[8, 1] = float("inf")
+    lb = plan.solve(l0, u0, lht, uht, c)
+    torch.cuda.synchronize()
+    flags = plan.check_finite(lb).cpu().numpy()
+    lb = lb.cpu().numpy()
+    for s in range(w.S):
+        if s in bad:
+            assert flags[s] & 4, (s, bad[s], flags[s])
+        else:
+            assert flags[s] == 0 and lb[s] == clean[s], (s, flags[s], lb[s], clean[s])
+    # the next clean load clears the input flags
+    lb2 = plan.solve(*batch)
+    assert int(plan.check_finite(lb2).abs().sum().item()) == 0

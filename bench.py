@@ -253,9 +253,105 @@ def ragged_leg(A, np, torch, WL):
             "verified": [int(np.sum(l > 0)) for l in lbs], "tuning": tunings}
 
 
-def cpu_baseline(w, n_sub=2):
-    """The FP64 oracle on a bounded sample: the first n_sub subdomains, full
-    schedule; rate = Active Set subproblem-iterations per second."""
+_ORACLE_W = None
+
+
+def _oracle_worker_init(n_sub_total):
+    """CPU-baseline worker: single-threaded BLAS, the benchmark workload."""
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[v] = "1"
+    global _ORACLE_W
+    from paper_2101_05844_amd import workloads as WL
+    _ORACLE_W = WL.cifar_conv_config(S=n_sub_total)
+
+
+def _oracle_subdomain(s):
+    """The FP64 oracle's whole schedule on subdomain s; returns the seconds
+    its Active Set phase took and its iteration count."""
+    import numpy as np
+
+    from oracle import asd_oracle as O
+    from paper_2101_05844_amd import workloads as WL
+
+    w = _ORACLE_W
+    ops = O.ops_from_workload_layers(w.layers)
+    lh, uh = O.interval_bounds(ops, w.l0[0].astype(float), w.u0[0].astype(float))
+    lh = [np.nextafter(a.astype(np.float32), np.float32(-np.inf)) for a in lh[:-1]]
+    uh = [np.nextafter(a.astype(np.float32), np.float32(np.inf)) for a in uh[:-1]]
+    L, U = WL.subdomain_bounds(lh, uh, w.fix_draws, w.S)
+    prm = O.params_from_schedule(w.schedule)
+    p = O.make_problem(ops, w.l0[s], w.u0[s], [a[s] for a in L], [a[s] for a in U], w.c[s])
+    st = O.zero_state(p)
+    for t in range(prm.bigm_iters):
+        O.bigm_iteration(p, st, O.linear_lr(*prm.bigm_lr, t, prm.bigm_iters), prm)
+    O.reset_moments(st)
+    t0 = time.perf_counter()
+    for t in range(prm.as_iters):
+        O.as_iteration(p, st, t, O.linear_lr(*prm.as_lr, t, prm.as_iters), prm)
+    return time.perf_counter() - t0, prm.as_iters
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w):
+    """The FP64 oracle on a bounded sample of the benchmark workload: one
+    subdomain per worker process (single-threaded each, one per host core
+    available to this process, at most 16), the whole schedule; rate =
+    Active Set subproblem-iterations per second summed over the workers
+    running side by side."""
+    import multiprocessing as mp
+
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    workers = max(1, min(16, avail))
+    ctx = mp.get_context("spawn")  # fresh interpreters: the workers never touch the GPU
+    with ctx.Pool(workers, initializer=_oracle_worker_init, initargs=(w.S,)) as pool:
+        res = pool.map(_oracle_subdomain, range(workers))
+    rate = sum(n / t for t, n in res)
+    return {"value": rate, "unit": "subproblem-iterations/s", "cores": workers, "kind": "oracle",
+            "sample": f"subdomains 0-{workers - 1} of the {w.S}, one per single-threaded worker process, "
+                      f"full schedule ({w.schedule.bigm_iters} Big-M + {w.schedule.as_iters} Active Set "
+                      f"iterations), rate over the Active Set phase summed over the workers; NumPy/SciPy FP64; "
+                      f"host: {avail} cores available, {os.cpu_count()} online, {_cpu_model()}"}
+
+
+FINAL_ROWS = (0, 73, 146, 219, 292, 365, 438, 511)
+
+
+def export_final_state(A, plan, rows):
+    """Final duals and active sets of the sampled subdomains (asd_state_get),
+    as host arrays: the input of the per-result check of the FP64 final
+    bound in the CPU-baseline leg."""
+    K = plan.counts().n_masks
+    g = lambda f, k, q=0: plan.get(f, k, q).cpu().numpy()[list(rows)].astype("float64")
+    ex = {"K": K}
+    for k in range(1, plan.net.n):
+        ex[("alpha", k)] = g(A.ASD_F_ALPHA, k)
+        ex[("beta0", k)] = g(A.ASD_F_BETA0, k)
+        ex[("beta1", k)] = g(A.ASD_F_BETA1, k)
+        for q in range(K):
+            ex[("beta", k, q)] = g(A.ASD_F_MASK_BETA, k, q)
+            ex[("z", k, q)] = g(A.ASD_F_MASK_Z, k, q)
+            ex[("x", k, q)] = g(A.ASD_F_MASK_XPREV, k, q)
+    return ex
+
+
+def final_bound_check(w, ex, lb, rows):
+    """Per-result error of the FP64 final bound of the FP32 solve: the oracle
+    evaluates d_B (eq:dual-active-set) at each sampled subdomain's exported
+    final duals, its masks rebuilt by the oracle's eq:oracle at the recorded
+    primal points; error absolute and relative to the sum of |terms|."""
     import numpy as np
 
     from oracle import asd_oracle as O
@@ -266,23 +362,32 @@ def cpu_baseline(w, n_sub=2):
     lh = [np.nextafter(a.astype(np.float32), np.float32(-np.inf)) for a in lh[:-1]]
     uh = [np.nextafter(a.astype(np.float32), np.float32(np.inf)) for a in uh[:-1]]
     L, U = WL.subdomain_bounds(lh, uh, w.fix_draws, w.S)
-    prm = O.params_from_schedule(w.schedule)
-    t_as = 0.0
-    for s in range(n_sub):
+    abs_e, rel_e = [], []
+    for i, s in enumerate(rows):
         p = O.make_problem(ops, w.l0[s], w.u0[s], [a[s] for a in L], [a[s] for a in U], w.c[s])
         st = O.zero_state(p)
-        for t in range(prm.bigm_iters):
-            O.bigm_iteration(p, st, O.linear_lr(*prm.bigm_lr, t, prm.bigm_iters), prm)
-        O.reset_moments(st)
-        t0 = time.perf_counter()
-        for t in range(prm.as_iters):
-            O.as_iteration(p, st, t, O.linear_lr(*prm.as_lr, t, prm.as_iters), prm)
-        t_as += time.perf_counter() - t0
-    rate = n_sub * prm.as_iters / t_as
-    return {"value": rate, "unit": "subproblem-iterations/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n_sub} of the {w.S} subdomains, full schedule "
-                      f"({prm.bigm_iters} Big-M + {prm.as_iters} Active Set iterations), "
-                      f"rate over the Active Set phase; NumPy/SciPy FP64, single thread"}
+        for k in range(1, p.n):
+            st.alpha[k - 1], st.beta0[k - 1], st.beta1[k - 1] = ex[("alpha", k)][i], ex[("beta0", k)][i], \
+                ex[("beta1", k)][i]
+            lp_, up_ = p.lu(k - 1)
+            for q in range(ex["K"]):
+                xp, z = ex[("x", k, q)][i], ex[("z", k, q)][i]
+                M = O.new_mask(p.W(k), O.oracle_mask(p.W(k), lp_, up_, xp, z), lp_, up_, xp, z)
+                M.beta = ex[("beta", k, q)][i]
+                st.masks[k - 1].append(M)
+        d, x, z, f, g = O.evaluate(p, st)
+        terms = abs(float(p.W(p.n).b @ p.c)) + sum(float(np.abs(a * b).sum()) for a, b in zip(f, x)) + \
+            sum(float(np.abs(a * b).sum()) for a, b in zip(g, z))
+        for k in range(1, p.n):
+            lhk, b = p.hat(k)[0], p.W(k).b
+            terms += float(np.abs(b * st.alpha[k - 1]).sum() + np.abs(st.beta1[k - 1] * (lhk - b)).sum())
+            terms += sum(float(np.abs(M.LI * M.beta).sum()) for M in st.masks[k - 1])
+        abs_e.append(abs(float(lb[s]) - d))
+        rel_e.append(abs_e[-1] / terms)
+    return {"sample": f"subdomains {list(rows)} of the timed FP32 solve", "masks": ex["K"],
+            "max_abs": max(abs_e), "mean_abs": float(np.mean(abs_e)),
+            "max_rel_sum_terms": max(rel_e), "mean_rel_sum_terms": float(np.mean(rel_e)),
+            "what": "|asd_bound (FP64 on the GPU) - oracle d_B at the exported final duals|"}
 
 
 def main():
@@ -375,6 +480,8 @@ def main():
     as_ms = sum(e[1].elapsed_time(e[2]) for e in evs)
     value = S * sched.as_iters * args.steps / (as_ms / 1e3)
     lb_np = lb.cpu().numpy()
+    rows = [r for r in FINAL_ROWS if r < S]
+    final_ex = export_final_state(A, plan, rows)
     print(f"[bench] timed {args.steps} solves: {wall:.3f} s; AS phase {as_ms / args.steps:.2f} ms/solve",
           file=sys.stderr, flush=True)
 
@@ -462,10 +569,11 @@ def main():
         print("[bench] bound-gradient leg", file=sys.stderr, flush=True)
         plan = None
         adjoint = adjoint_leg(A, np, torch, WL)
-    cpu = None
+    cpu = final_check = None
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
         cpu = cpu_baseline(w)
+        final_check = final_bound_check(w, final_ex, lb_np, rows)
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -489,6 +597,7 @@ def main():
         "as_phase_alg_GBps": round(whole_as_gbs, 1),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "fp64_final_vs_oracle": final_check,
         "kernels": kernels,
         "tuning": tuning,
         "mixed": mixed,

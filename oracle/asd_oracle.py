@@ -548,6 +548,11 @@ class SolveParams:
     as_lr: tuple = (1e-3, 1e-6)
     rule: str = "adam"
     adam: AdamConsts = dataclasses.field(default_factory=AdamConsts)
+    # "exact": the state is kept in FP64; "fp32": after every iteration the
+    # duals, moments and mask constants are stored as float32 values (a
+    # storage choice of an implementation, not of the paper: it measures how
+    # far FP32 rounding of the state alone moves a whole run)
+    storage: str = "exact"
 
 
 def params_from_schedule(s) -> SolveParams:
@@ -571,10 +576,26 @@ def is_addition_iter(t: int, prm: SolveParams, n_active: int) -> bool:
     return (t % prm.add_every) < prm.add_count and n_active < prm.max_masks
 
 
+def round_state_fp32(st: DualState):
+    """Every stored value of the state rounded to the nearest float32."""
+    r = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+    for name in ("alpha", "beta0", "beta1"):
+        vals = getattr(st, name)
+        for i in range(len(vals)):
+            vals[i] = r(vals[i])
+            st.m[name][i] = r(st.m[name][i])
+            st.v[name][i] = r(st.v[name][i])
+    for masks in st.masks:
+        for M in masks:
+            M.beta, M.m, M.v, M.LI, M.UI = r(M.beta), r(M.m), r(M.v), r(M.LI), r(M.UI)
+
+
 def bigm_iteration(p: Problem, st: DualState, lr: float, prm: SolveParams):
     """One iteration of Algorithm 3 (B empty): inner min, supergradient, step."""
     d, x, z, _, _ = evaluate(p, st)
     apply_step(st, supergradient(p, st, x, z), lr, prm.rule, prm.adam)
+    if prm.storage == "fp32":
+        round_state_fp32(st)
     return d
 
 
@@ -585,6 +606,8 @@ def as_iteration(p: Problem, st: DualState, t: int, lr: float, prm: SolveParams)
     if p.n > 1 and is_addition_iter(t, prm, n_active):
         add_masks(p, st, x, z)
     apply_step(st, supergradient(p, st, x, z), lr, prm.rule, prm.adam)
+    if prm.storage == "fp32":
+        round_state_fp32(st)
     return d
 
 

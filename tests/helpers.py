@@ -7,6 +7,40 @@ from oracle import asd_oracle as O
 from paper_2101_05844_amd import workloads as WL
 
 
+SMALL_CONV = [WL.ConvSpec(2, 7, 9, 5, 3, 1, 1), WL.ConvSpec(5, 7, 9, 6, 4, 2, 1),
+              WL.DenseSpec(6 * 3 * 4, 13), WL.DenseSpec(13, 3)]
+SMALL_DENSE = [WL.DenseSpec(37, 53), WL.DenseSpec(53, 29), WL.DenseSpec(29, 4)]
+# shapes that take the matrix-core kernels of FP32 plans: a 32-channel
+# convolution forward (kernel 4, stride 2), a transposed convolution into a
+# 16-channel layer of 256 positions, a dense layer fed by 64-position
+# channels (forward on matrix cores, backward with positions on lanes)
+MFMA_CONV = [WL.ConvSpec(2, 16, 16, 16, 3, 1, 1), WL.ConvSpec(16, 16, 16, 32, 4, 2, 1),
+             WL.DenseSpec(32 * 8 * 8, 20), WL.DenseSpec(20, 3)]
+# the convolutions of the wider CIFAR variant (32 and 64 channels) with a
+# narrow dense head: transposed convolutions from 64 channels on the matrix
+# cores, the dense backward with positions on lanes into 64 x 8 x 8
+WIDER_CONV = [WL.ConvSpec(3, 32, 32, 32, 4, 2, 1), WL.ConvSpec(32, 16, 16, 64, 4, 2, 1),
+              WL.DenseSpec(64 * 8 * 8, 24), WL.DenseSpec(24, 3)]
+
+
+def workloads_small():
+    sched = WL.Schedule(bigm_iters=12, as_iters=14, add_every=5, add_count=2, max_masks=4)
+    return [
+        WL.custom_config(SMALL_DENSE, S=70, seed=21, eps=0.1, centre_range=(-1.0, 1.0), schedule=sched,
+                         max_fixed=3, name="dense-37-53-29-4"),
+        WL.custom_config(SMALL_CONV, S=11, seed=22, eps=0.05, schedule=sched, max_fixed=4,
+                         name="conv-2x7x9"),
+        WL.custom_config(MFMA_CONV, S=9, seed=23, eps=0.03, schedule=sched, max_fixed=6,
+                         name="conv-2x16x16"),
+        WL.custom_config(WIDER_CONV, S=4, seed=24, eps=0.01, schedule=sched, max_fixed=8,
+                         name="conv-3x32x32-wider"),
+    ]
+
+
+def e2e_workloads():
+    return workloads_small()[:2] + [WL.mnist_mlp_config(), workloads_small()[2]]
+
+
 def f32(a):
     return np.asarray(a, dtype=np.float32)
 
@@ -214,3 +248,67 @@ def check_eval_against_oracle(res, rows, eps):
                 assert not bad.any(), (key, s, k, np.flatnonzero(bad)[:5], got[bad][:5], ref[bad][:5])
                 cnt["grad"] += got.size
     return cnt
+
+
+def oracle_states_from_plan(plan, problems: dict):
+    """The plan's current duals and active sets (asd_state_get) as oracle
+    states, one per subproblem s in problems ({s: Problem}): multipliers
+    as exported (FP32 values for FP32 plans), each mask rebuilt by the
+    oracle's own eq:oracle at the primal point the plan recorded for it."""
+    from paper_2101_05844_amd import asdual as A
+    p0 = next(iter(problems.values()))
+    n = p0.n
+    K = plan.counts().n_masks
+    g = lambda f, k, q=0: plan.get(f, k, q).cpu().numpy().astype(np.float64)
+    ex = {}
+    for k in range(1, n):
+        ex[("alpha", k)] = g(A.ASD_F_ALPHA, k)
+        ex[("beta0", k)] = g(A.ASD_F_BETA0, k)
+        ex[("beta1", k)] = g(A.ASD_F_BETA1, k)
+        for q in range(K):
+            ex[("beta", k, q)] = g(A.ASD_F_MASK_BETA, k, q)
+            ex[("z", k, q)] = g(A.ASD_F_MASK_Z, k, q)
+            ex[("x", k, q)] = g(A.ASD_F_MASK_XPREV, k, q)
+    out = {}
+    for s, p in problems.items():
+        st = O.zero_state(p)
+        for k in range(1, n):
+            st.alpha[k - 1] = ex[("alpha", k)][s]
+            st.beta0[k - 1] = ex[("beta0", k)][s]
+            st.beta1[k - 1] = ex[("beta1", k)][s]
+            op = p.W(k)
+            lp_, up_ = p.lu(k - 1)
+            for q in range(K):
+                xp, z = ex[("x", k, q)][s], ex[("z", k, q)][s]
+                M = O.new_mask(op, O.oracle_mask(op, lp_, up_, xp, z), lp_, up_, xp, z)
+                M.beta = ex[("beta", k, q)][s]
+                st.masks[k - 1].append(M)
+        out[s] = st
+    return out
+
+
+def final_bound_errors(plan, lb, problems: dict):
+    """Per-result error of the plan's FP64 final bound (asd_bound, lb [S]) at
+    its final duals: |lb[s] - d_B(s)| with d_B evaluated by the oracle at the
+    exported duals and masks (eq:dual-active-set), absolute and relative to
+    the sum of the magnitudes of d_B's terms."""
+    states = oracle_states_from_plan(plan, problems)
+    out = {}
+    for s, p in problems.items():
+        d = O.evaluate(p, states[s])[0]
+        sc = objective_scale(p, states[s])
+        out[s] = (abs(float(lb[s]) - d), abs(float(lb[s]) - d) / sc, d)
+    return out
+
+
+def fp32_band(name: str, factor: float = 4.0, floor: float = 1e-4):
+    """Whole-run band of an FP32 plan against the FP64 oracle on workload
+    `name`: factor times the oracle's own FP32-storage sensitivity recorded
+    in tests/golden/fp32_band.json (max and mean), at least `floor`."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fp32_band.json")) as fh:
+        rec = json.load(fh)["workloads"][name]
+    return {"max": max(floor, factor * rec["max_rel"]), "mean": max(floor, factor * rec["mean_rel"]),
+            "mixed_max": max(floor, factor * (rec["max_rel"] + rec["mixed_max_rel"])),
+            "mixed_mean": max(floor, factor * (rec["mean_rel"] + rec["mixed_mean_rel"]))}

@@ -186,13 +186,23 @@ def test_fullsize_fp64_solve_matches_oracle(cifar):
 
 
 def test_fullsize_fp32_solve_valid(cifar):
-    """The benchmark's configuration (FP32 plan, full schedule, 512
-    subdomains): every bound lies between the subdomain's interval bound and
-    the smallest sampled network output inside the subdomain."""
+    """The benchmark's configuration (FP32 plan, autotuned kernel choices,
+    full schedule, 512 subdomains): every bound lies between the subdomain's
+    interval bound and the smallest sampled network output inside the
+    subdomain, and on sampled subdomains the FP64 final bound equals the
+    oracle's evaluation of the exported final duals and masks
+    (eq:dual-active-set) within 1e-10 of the summed term magnitudes."""
     w, ops, L, U = cifar
     A, net, plan, batch = _plan(w, L, U, "fp32")
+    plan.autotune(ktune=2, reps=3)
     lb = plan.solve(*batch).cpu().numpy()
     assert np.all(np.isfinite(lb))
+    rows = [0, 64, 128, 171, 256, 384, 448, 511]
+    probs = {s: O.make_problem(ops, w.l0[s], w.u0[s], [a[s] for a in L], [a[s] for a in U], w.c[s]) for s in rows}
+    err = H.final_bound_errors(plan, lb, probs)
+    assert all(e[1] <= 1e-10 for e in err.values()), err
+    print("final-bound error per result (abs, rel. to sum |terms|):",
+          {s: (f"{e[0]:.2e}", f"{e[1]:.2e}") for s, e in err.items()}, flush=True)
     pts = WL.random_points_in_box(w.l0[0].astype(float), w.u0[0].astype(float), 300, 9)
     x = pts.T
     pre = []

@@ -25,20 +25,8 @@ from tests import helpers as H
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-SMALL_CONV = [WL.ConvSpec(2, 7, 9, 5, 3, 1, 1), WL.ConvSpec(5, 7, 9, 6, 4, 2, 1),
-              WL.DenseSpec(6 * 3 * 4, 13), WL.DenseSpec(13, 3)]
-SMALL_DENSE = [WL.DenseSpec(37, 53), WL.DenseSpec(53, 29), WL.DenseSpec(29, 4)]
-# shapes that take the matrix-core kernels of FP32 plans: a 32-channel
-# convolution forward (kernel 4, stride 2), a transposed convolution into a
-# 16-channel layer of 256 positions, a dense layer fed by 64-position
-# channels (forward on matrix cores, backward with positions on lanes)
-MFMA_CONV = [WL.ConvSpec(2, 16, 16, 16, 3, 1, 1), WL.ConvSpec(16, 16, 16, 32, 4, 2, 1),
-             WL.DenseSpec(32 * 8 * 8, 20), WL.DenseSpec(20, 3)]
-# the convolutions of the wider CIFAR variant (32 and 64 channels) with a
-# narrow dense head: transposed convolutions from 64 channels on the matrix
-# cores, the dense backward with positions on lanes into 64 x 8 x 8
-WIDER_CONV = [WL.ConvSpec(3, 32, 32, 32, 4, 2, 1), WL.ConvSpec(32, 16, 16, 64, 4, 2, 1),
-              WL.DenseSpec(64 * 8 * 8, 24), WL.DenseSpec(24, 3)]
+SMALL_CONV, SMALL_DENSE, MFMA_CONV, WIDER_CONV = H.SMALL_CONV, H.SMALL_DENSE, H.MFMA_CONV, H.WIDER_CONV
+workloads_small, e2e_workloads = H.workloads_small, H.e2e_workloads
 
 
 def _A():
@@ -60,20 +48,6 @@ def _setup(w, params=None, prec="fp32"):
     l0, u0, lht, uht, c = H.gpu_batch(w, lh, uh)
     plan.init(l0, u0, lht, uht, c)
     return A, ops, probs, net, plan, (l0, u0, lht, uht, c)
-
-
-def workloads_small():
-    sched = WL.Schedule(bigm_iters=12, as_iters=14, add_every=5, add_count=2, max_masks=4)
-    return [
-        WL.custom_config(SMALL_DENSE, S=70, seed=21, eps=0.1, centre_range=(-1.0, 1.0), schedule=sched,
-                         max_fixed=3, name="dense-37-53-29-4"),
-        WL.custom_config(SMALL_CONV, S=11, seed=22, eps=0.05, schedule=sched, max_fixed=4,
-                         name="conv-2x7x9"),
-        WL.custom_config(MFMA_CONV, S=9, seed=23, eps=0.03, schedule=sched, max_fixed=6,
-                         name="conv-2x16x16"),
-        WL.custom_config(WIDER_CONV, S=4, seed=24, eps=0.01, schedule=sched, max_fixed=8,
-                         name="conv-3x32x32-wider"),
-    ]
 
 
 @pytest.mark.parametrize("wi", [0, 1])
@@ -499,10 +473,6 @@ def _sampled_min(ops, p, l0, u0, seed, n=400):
     return outs[keep].min() if keep.any() else np.inf
 
 
-def e2e_workloads():
-    return workloads_small()[:2] + [WL.mnist_mlp_config(), workloads_small()[2]]
-
-
 @pytest.mark.parametrize("wi", [0, 1, 2, 3])
 def test_end_to_end_fp64(wi):
     """Whole runs (Big-M, Active Set with additions, final bound) in an FP64
@@ -521,49 +491,64 @@ def test_end_to_end_fp64(wi):
 
 @pytest.mark.parametrize("wi", [0, 1, 2, 3])
 def test_end_to_end_fp32(wi):
-    """Whole runs in an FP32 plan: validity, plus a sanity band against the
-    FP64 oracle.  A run's final bound depends on every near-tie the
-    iteration meets, so FP32 and FP64 runs part at the first one (rounding
-    the FP64 oracle's own duals to FP32 after each step already moves MNIST
-    bounds by up to 1e-2 relative); parity of the FP32 arithmetic itself is
-    asserted at fixed duals and over short windows, and whole-run parity on
-    FP64 plans.  Checked here: never above a sampled output, never below
-    the interval bound, within 5e-2 of the oracle per subproblem and 2e-2 on
-    the mean."""
+    """Whole runs in an FP32 plan.  The final bound (the FP64 evaluation of
+    the run's final duals) matches the oracle's evaluation of the same
+    exported duals within 1e-10 of the summed term magnitudes, per result.
+    The run itself parts from the FP64 oracle's run at the first near-tie
+    it meets, so its distance from the oracle's bound is held to a band
+    measured from the oracle alone: tests/golden/fp32_band.json records how
+    far storing the oracle's own state as float32 after every iteration
+    moves its final bounds on these workloads (max and mean over the
+    subproblems); the band is four times that, at least 1e-4.  Also: never
+    above a sampled output, never below the interval bound."""
     w = e2e_workloads()[wi]
     A, ops, probs, net, plan, batch = _setup(w, prec="fp32")
     lb = plan.solve(*batch).cpu().numpy()
+    # the FP64 final bound of the FP32 run is the dual objective of its final
+    # duals: per result, against the oracle's evaluation at the same duals
+    err = H.final_bound_errors(plan, lb, dict(enumerate(probs[:12])))
+    assert all(e[1] <= 1e-10 for e in err.values()), err
     prm = O.params_from_schedule(w.schedule)
+    band = H.fp32_band(w.name)
     ora = []
     for s, p in enumerate(probs[:12]):
         r = O.solve(p, prm)
         ora.append(r.bound)
         assert lb[s] <= _sampled_min(ops, p, w.l0[s], w.u0[s], s) + 1e-6
         assert lb[s] >= O.evaluate(p, O.zero_state(p))[0] - 1e-5 * max(1.0, abs(lb[s]))
-        assert abs(lb[s] - r.bound) <= 5e-2 * max(1.0, abs(r.bound)), (s, lb[s], r.bound)
+        assert abs(lb[s] - r.bound) <= band["max"] * max(1.0, abs(r.bound)), (s, lb[s], r.bound, band)
     ora = np.array(ora)
     n = len(ora)
-    assert abs(lb[:n].mean() - ora.mean()) <= 2e-2 * max(1.0, abs(ora.mean()))
+    rel = np.abs(lb[:n] - ora) / np.maximum(1.0, np.abs(ora))
+    assert rel.mean() <= band["mean"], (rel.mean(), band)
+    print(w.name, "FP32 whole run vs FP64 oracle: max rel", rel.max(), "mean rel", rel.mean(), "band", band,
+          "final-bound error (rel. to sum |terms|) max", max(e[1] for e in err.values()), flush=True)
 
 
 @pytest.mark.parametrize("wi", [0, 1, 2, 3])
 def test_end_to_end_mixed(wi):
     """Whole runs with BF16-stored Adam moments: the final bound is the FP64
-    evaluation of valid duals, so it never exceeds a sampled output and
-    never falls below the interval bound; it stays within the FP32 form's
-    sensitivity band of the FP32 run (5e-2 per subproblem, 2e-2 on the
-    mean)."""
+    evaluation of valid duals (checked per result against the oracle's
+    evaluation of the exported duals), so it never exceeds a sampled output
+    and never falls below the interval bound.  Its distance from the FP32
+    run is held to the sum of the two forms' measured bands against the
+    FP64 oracle (tests/golden/fp32_band.json: the oracle's own runs with
+    FP32 state, and with FP32 state and BF16 moments)."""
     w = e2e_workloads()[wi]
     A, ops, probs, net, plan, batch = _setup(w, prec="fp32")
     lb32 = plan.solve(*batch).cpu().numpy()
     prm = A.params_from_schedule(w.schedule, A.ASD_PREC_MIXED)
     plan_m = A.Plan(net, w.S, prm)
     lbm = plan_m.solve(*batch).cpu().numpy()
+    err = H.final_bound_errors(plan_m, lbm, dict(enumerate(probs[:12])))
+    assert all(e[1] <= 1e-10 for e in err.values()), err
     for s, p in enumerate(probs[:12]):
         assert lbm[s] <= _sampled_min(ops, p, w.l0[s], w.u0[s], s) + 1e-6
         assert lbm[s] >= O.evaluate(p, O.zero_state(p))[0] - 1e-5 * max(1.0, abs(lbm[s]))
-    assert np.all(np.abs(lbm - lb32) <= 5e-2 * np.maximum(1.0, np.abs(lb32)))
-    assert abs(np.mean(lbm - lb32)) <= 2e-2 * max(1.0, float(np.mean(np.abs(lb32))))
+    band = H.fp32_band(w.name)
+    rel = np.abs(lbm - lb32) / np.maximum(1.0, np.abs(lb32))
+    assert np.all(rel <= band["max"] + band["mixed_max"]), (rel.max(), band)
+    assert rel.mean() <= band["mean"] + band["mixed_mean"], (rel.mean(), band)
     print(f"mean fp32 - mixed {np.mean(lb32 - lbm):.3e}, max |diff| {np.max(np.abs(lb32 - lbm)):.3e}", flush=True)
 
 

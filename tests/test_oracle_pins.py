@@ -548,3 +548,98 @@ def test_bound_gradient_matches_finite_differences(kind):
             box[1][j] += e
         assert fd(mutl) == pytest.approx(dl0[j], rel=1e-5, abs=1e-7), ("l0", j)
         assert fd(mutu) == pytest.approx(du0[j], rel=1e-5, abs=1e-7), ("u0", j)
+
+
+# ----------------------------------------------------------------------------
+# Schedule of Sec. 7.1 (experimental setting) and the printed tie rules
+# ----------------------------------------------------------------------------
+
+
+def test_addition_schedule_sec71():
+    """Sec. 7.1 fixes the Active Set schedule: variables are added every 450
+    iterations, each addition brings 2 new variables (masks) per layer, and
+    the number of cuts is capped at 7.  Run with exactly those values, the
+    oracle's mask count before iteration t must read 0 at the start, 2 after
+    each period's additions (not 3: Algorithm 1's 't <= nb_vars_to_add' read
+    literally), and stop at 7."""
+    _, ops, p = tiny_problem()
+    prm = O.SolveParams(bigm_iters=0, as_iters=1402, add_every=450, add_count=2, max_masks=7,
+                        as_lr=(1e-3, 1e-6), rule="sgd")
+    probe = [0, 1, 2, 3, 449, 450, 451, 452, 899, 900, 901, 902, 1349, 1350, 1351, 1352, 1401]
+    r = O.solve(p, prm, snapshot_at=[("as", t) for t in probe] + [("as", prm.as_iters)])
+    counts = {t: len(r.snapshots[("as", t)].masks[0]) for t in probe}
+    counts["end"] = len(r.snapshots[("as", prm.as_iters)].masks[0])
+    want = {0: 0, 1: 1, 2: 2, 3: 2, 449: 2, 450: 2, 451: 3, 452: 4, 899: 4, 900: 4, 901: 5, 902: 6,
+            1349: 6, 1350: 6, 1351: 7, 1352: 7, 1401: 7, "end": 7}
+    assert counts == want, counts
+    # every layer grows alike, and the fresh multipliers start at zero
+    st = r.snapshots[("as", 1)]
+    assert all(len(m) == 1 for m in st.masks)
+    assert all(np.all(m[0].beta == 0) for m in r.snapshots[("as", 0)].masks) if r.snapshots[("as", 0)].masks[0] \
+        else True
+
+
+def _step_sizes(p, prm, phase, ts):
+    """Step size each iteration t in ts of a plain-supergradient run used,
+    read off the state: theta' = max(0, theta + lr g), so lr = (theta' -
+    theta) / g on every entry that stayed positive with g != 0."""
+    T = prm.bigm_iters if phase == "bigm" else prm.as_iters
+    want = sorted({(phase, t) for t in ts} | {(phase, t + 1) for t in ts if t + 1 < T})
+    if phase == "bigm" and T - 1 in ts:
+        want.append(("as", 0))
+    if phase == "as" and T - 1 in ts:
+        want.append(("as", T))
+    # positive start (random duals, no masks) so that few entries are clamped
+    r = O.solve(p, prm, snapshot_at=want, state=random_state(p, np.random.default_rng(5), n_masks=0))
+    out = {}
+    for t in ts:
+        a = r.snapshots[(phase, t)]
+        nxt = (phase, t + 1) if t + 1 < T else (("as", 0) if phase == "bigm" else ("as", T))
+        b = r.snapshots[nxt]
+        _, x, z, _, _ = O.evaluate(p, a)
+        sg = O.supergradient(p, a, x, z)
+        lrs = []
+        for name in ("alpha", "beta0", "beta1"):
+            g, th0, th1 = sg[name], getattr(a, name), getattr(b, name)
+            for k in range(len(g)):
+                ok = (th1[k] > 0) & (np.abs(g[k]) > 1e-6)
+                lrs.extend(((th1[k] - th0[k]) / np.where(ok, g[k], 1.0))[ok].tolist())
+        assert lrs, (phase, t)
+        out[t] = (min(lrs), max(lrs))
+    return out
+
+
+def test_step_size_schedule_sec71():
+    """Sec. 7.1: Big-M decreases its step size linearly from 1e-2 to 1e-4;
+    Active Set then resets it and decreases it linearly from 1e-3 to 1e-6.
+    Read off the iterates of a plain-supergradient run: the first and the
+    last step of each phase use exactly the printed end points, and the
+    middle step their mean."""
+    _, ops, p = tiny_problem()
+    prm = O.SolveParams(bigm_iters=21, as_iters=31, add_every=1000, add_count=0, max_masks=0,
+                        bigm_lr=(1e-2, 1e-4), as_lr=(1e-3, 1e-6), rule="sgd")
+    bm = _step_sizes(p, prm, "bigm", [0, 10, 20])
+    as_ = _step_sizes(p, prm, "as", [0, 15, 30])
+    # (recovering lr from theta + lr g loses digits to cancellation: 1e-5 relative)
+    close = lambda got, v: abs(got[0] - v) <= 1e-5 * v and abs(got[1] - v) <= 1e-5 * v
+    assert close(bm[0], 1e-2) and close(bm[20], 1e-4) and close(bm[10], (1e-2 + 1e-4) / 2), bm
+    assert close(as_[0], 1e-3) and close(as_[30], 1e-6) and close(as_[15], (1e-3 + 1e-6) / 2), as_
+
+
+def test_printed_tie_rules():
+    """eq:as-primalk-min selects x*_k = u_k where f_k >= 0 and z*_k = 1 where
+    g_k >= 0 (the printed indicators include equality).  At zero duals every
+    g_k is exactly 0 and so is every f_k below the last ReLU layer (no
+    multiplier reaches it): the minimiser must take the upper ends and
+    z* = 1 there."""
+    for w in (WL.tiny_config(), WL.mnist_mlp_config()):
+        ops = O.ops_from_workload_layers(w.layers)
+        lh, uh = O.interval_bounds(ops, w.l0[0].astype(float), w.u0[0].astype(float))
+        p = O.make_problem(ops, w.l0[0], w.u0[0], lh[:-1], uh[:-1], w.c[0])
+        st = O.zero_state(p)
+        d, x, z, f, g = O.evaluate(p, st)
+        for k in range(p.n - 1):
+            assert np.all(f[k] == 0)
+            assert np.array_equal(x[k], p.lu(k)[1]), k
+        for k in range(1, p.n):
+            assert np.all(g[k - 1] == 0) and np.all(z[k - 1] == 1.0), k

@@ -49,6 +49,13 @@ def kernel_unit_bytes(role, layer, sizes, K, mixed=False):
         nxt = sizes[layer + 1]
         kk = K if layer + 1 < len(sizes) - 1 else 0
         return 4 * (1 + kk) * nxt + 12 * sizes[layer]
+    if role == "forward_pass":
+        # one launch holding the forward kernels of every ReLU layer
+        return sum(kernel_unit_bytes("forward", k, sizes, K, mixed) for k in range(1, len(sizes) - 1))
+    if role == "backward_pair":
+        # one launch holding the backward kernels into the last two neuron layers
+        n = len(sizes) - 1
+        return kernel_unit_bytes("backward", n - 1, sizes, K) + kernel_unit_bytes("backward", n - 2, sizes, K)
     return None
 
 
@@ -111,28 +118,47 @@ def masks_at(t, sched):
     return K
 
 
-def roofline_of(prof, sched, S, sizes, Ks, mixed=False):
-    """Roofline entry of the dominant iteration kernel (by time over the
-    solve): its algorithmic bytes summed launch by launch with the mask
-    count of that iteration (Big-M iterations first, K = 0), over its
-    HIP-event time; HBM traffic from the committed counter summary."""
-    iter_prof = {key: v for key, v in prof.items() if key[0] in ("forward", "backward")}
-    (role, layer), (n_launch, tot_ms) = max(iter_prof.items(), key=lambda kv: kv[1][1])
-    # the forward pass of iteration t sees the masks added in t, the
-    # backward pass the ones before
-    Ks_all = [0] * sched.bigm_iters + (Ks if role == "forward" else [0] + Ks[:-1])
-    if n_launch != len(Ks_all):
-        return None
-    tot_bytes = S * sum(kernel_unit_bytes(role, layer, sizes, K, mixed) for K in Ks_all)
-    avg_s = tot_ms / 1e3 / n_launch
-    achieved = tot_bytes / n_launch / avg_s / 1e9
-    traffic = committed_traffic(f"{role}:{layer}" + (":mixed" if mixed and role == "forward" else ""))
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+ITER_ROLES = ("forward", "backward", "forward_pass", "backward_pair")
+
+
+def launch_rooflines(prof, sched, S, sizes, Ks, mixed=False):
+    """Roofline entry of every iteration launch group of a profiled solve:
+    algorithmic bytes summed launch by launch with the mask count of that
+    iteration (Big-M iterations first, K = 0) over the group's HIP-event
+    time; HBM traffic from the committed counter summary.  The forward pass
+    of iteration t sees the masks added in t, the backward pass the ones
+    before."""
+    out = {}
+    for (role, layer), (n_launch, tot_ms) in prof.items():
+        if role not in ITER_ROLES:
+            continue
+        fwd = role.startswith("forward")
+        Ks_all = [0] * sched.bigm_iters + (Ks if fwd else [0] + Ks[:-1])
+        if n_launch != len(Ks_all):
+            continue
+        tot_bytes = S * sum(kernel_unit_bytes(role, layer, sizes, K, mixed) for K in Ks_all)
+        avg_s = tot_ms / 1e3 / n_launch
+        achieved = tot_bytes / n_launch / avg_s / 1e9
+        traffic = committed_traffic(f"{role}:{layer}" + (":mixed" if mixed and fwd else ""))
+        out[f"{role}:{layer}"] = {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None if traffic is None else round(traffic / avg_s / 1e9, 1),
-            "kernel": f"{role} layer {layer}", "avg_launch_us": round(1e6 * avg_s, 2),
+            "kernel": f"{role.replace('_', ' ')} layer {layer}", "avg_launch_us": round(1e6 * avg_s, 2),
+            "launches": n_launch, "ms_per_solve": round(tot_ms, 3),
             "alg_bytes_per_launch": round(tot_bytes / n_launch),
             "hbm_bytes_per_launch": None if traffic is None else round(traffic)}
+    return out
+
+
+def roofline_of(prof, sched, S, sizes, Ks, mixed=False):
+    """Roofline entry of the dominant iteration launch (by time over the
+    solve) of a solve profiled launch by launch as it runs."""
+    groups = launch_rooflines(prof, sched, S, sizes, Ks, mixed)
+    if not groups:
+        return None, groups
+    key = max(groups, key=lambda k: groups[k]["ms_per_solve"])
+    return dict(groups[key]), groups
 
 
 def adjoint_weight_bytes(layer, sizes, n_weights, K, S):
@@ -241,16 +267,81 @@ def ragged_leg(A, np, torch, WL):
     torch.cuda.synchronize()
     ms_group = ev[0].elapsed_time(ev[1])
     ms_seq = ev[1].elapsed_time(ev[2])
+    # each plan's iterations replayed from its captured HIP graph (capture
+    # on the first call), the plans one after the other
+    for P, b in zip(plans, batches):
+        P.solve_graph(*b)
+    torch.cuda.synchronize()
+    ev[2].record(stream)
+    outs_g = [P.solve_graph(*b) for P, b in zip(plans, batches)]
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    ms_graph = ev[2].elapsed_time(ev[3])
+    assert all(torch.equal(a, b) for a, b in zip(outs, outs_g)), "graph replay differs from the group solve"
     bm = sum(w.S * w.schedule.bigm_iters for w in ws)
     lbs = [o.cpu().numpy() for o in outs]
+    # algorithmic bytes of the whole ragged solve: every net's Big-M
+    # iterations, and each subdomain's Active Set iterations within its
+    # budget with the mask count of each iteration
+    alg = 0.0
+    for w in ws:
+        sizes = [w.layers[0].n_in] + [Lr.n_out for Lr in w.layers]
+        alg += w.S * w.schedule.bigm_iters * unit_bytes(sizes, 0)
+        T = w.schedule.as_iters
+        per_t = [unit_bytes(sizes, masks_at(t, w.schedule)) for t in range(T)]
+        cum = np.cumsum(per_t)
+        alg += float(sum(cum[b - 1] for b in w.meta["budgets"]))
+    gbs = alg / (ms_group / 1e3) / 1e9
     return {"workload": "4096 subdomains: 2048 on the Table 1 Wide CIFAR net and 2048 on its wider variant "
                         "(conv 3->32, 32->64, FC 4096->512->10), 0-50 fixed ReLUs and an Active Set budget "
                         "U{100..1000} each, 180 Big-M iterations",
             "subproblems": sum(w.S for w in ws), "as_iterations": iters, "bigm_iterations": bm,
-            "ms": round(ms_group, 3), "ms_one_stream": round(ms_seq, 3),
+            "ms": round(ms_group, 3), "ms_one_stream": round(ms_seq, 3), "ms_graph_replay": round(ms_graph, 3),
             "rate": round((iters + bm) / (ms_group / 1e3), 1), "unit": "subproblem-iterations/s (whole solve)",
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                         "kernel": "whole ragged solve (all launches)", "alg_bytes": round(alg)},
             "bound_mean": [float(np.mean(l)) for l in lbs],
             "verified": [int(np.sum(l > 0)) for l in lbs], "tuning": tunings}
+
+
+def mnist_leg(A, np, torch, WL, reps=5):
+    """The MNIST-shaped MLP workload (784-100-100-100-10, 9 logit
+    differences, 500 Big-M + 500 Active Set iterations): whole solves timed
+    by HIP events, eager and replayed from the captured HIP graph.  Nine
+    subproblems of 0.1 MB of state fit in the caches, so the solve is bound
+    by launch latency, not HBM."""
+    w = WL.mnist_mlp_config()
+    dev = "cuda:0"
+    t32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=dev)
+    net = A.Net(w.layers, device=dev)
+    l0, u0, c = t32(w.l0), t32(w.u0), t32(w.c)
+    lh, uh = net.interval_bounds(l0, u0)
+    plan = A.Plan(net, w.S, A.params_from_schedule(w.schedule))
+    b = (l0, u0, lh[:-1], uh[:-1], c)
+    stream = torch.cuda.current_stream()
+    lb = plan.solve(*b)
+    plan.solve_graph(*b)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record(stream)
+    for _ in range(reps):
+        lb = plan.solve(*b)
+    ev[1].record(stream)
+    for _ in range(reps):
+        lbg = plan.solve_graph(*b)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    msg = ev[1].elapsed_time(ev[2]) / reps
+    assert torch.equal(lb, lbg)
+    it = w.S * w.schedule.as_iters
+    return {"workload": f"{w.name}: 784-100-100-100-10 MLP, eps 0.05, {w.S} logit-difference subproblems, "
+                        f"{w.schedule.bigm_iters} Big-M + {w.schedule.as_iters} Active Set iterations",
+            "subproblems": w.S, "ms_per_solve": round(ms, 3), "ms_per_solve_graph": round(msg, 3),
+            "rate": round(w.S * (w.schedule.bigm_iters + w.schedule.as_iters) / (min(ms, msg) / 1e3), 1),
+            "unit": "subproblem-iterations/s (whole solve, faster of eager and graph)",
+            "as_iterations": it, "bound_mean": float(lb.mean().item()), "bound": "launch latency"}
 
 
 _ORACLE_W = None
@@ -401,6 +492,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the bound-gradient leg")
     ap.add_argument("--no-mixed", action="store_true", help="skip the BF16-moment form")
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged two-net batch")
+    ap.add_argument("--no-mnist", action="store_true", help="skip the MNIST-shaped MLP leg")
     ap.add_argument("--no-autotune", action="store_true", help="keep the heuristic kernel choices")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 3 device-to-device copies of MIB MiB (calibrates HBM byte counters) and exit")
@@ -489,15 +581,22 @@ def main():
     Ks = [masks_at(t, sched) for t in range(sched.as_iters)]
     alg_as = S * sum(unit_bytes(sizes, K) for K in Ks)
     roofline = None
-    kernels = None
+    kernels = launches = None
     if not args.no_kernel_profile:
-        plan.profile(True)
+        # the launches as the timed solve runs them (shared launches kept)
+        plan.profile(A.ASD_PROFILE_LAUNCHES)
         step()
         torch.cuda.synchronize()
         prof = plan.profile_read()
-        plan.profile(False)
-        kernels = {f"{r}:{l}": {"launches": n, "avg_us": 1e3 * ms / n} for (r, l), (n, ms) in prof.items()}
-        roofline = roofline_of(prof, sched, S, sizes, Ks)
+        plan.profile(A.ASD_PROFILE_OFF)
+        roofline, launches = roofline_of(prof, sched, S, sizes, Ks)
+        # and every kernel alone, for the per-kernel table
+        plan.profile(A.ASD_PROFILE_KERNELS)
+        step()
+        torch.cuda.synchronize()
+        prof_k = plan.profile_read()
+        plan.profile(A.ASD_PROFILE_OFF)
+        kernels = {f"{r}:{l}": {"launches": n, "avg_us": round(1e3 * ms / n, 2)} for (r, l), (n, ms) in prof_k.items()}
     whole_as_gbs = alg_as / (as_ms / args.steps / 1e3) / 1e9
     # what a plain device copy reaches on this GPU (1 GiB read + 1 GiB written,
     # best of 3, HIP events on the copy's stream): the practical HBM ceiling
@@ -539,12 +638,12 @@ def main():
         lbm = lb_m.cpu().numpy()
         roof_m = None
         if not args.no_kernel_profile:
-            plan.profile(True)
+            plan.profile(A.ASD_PROFILE_LAUNCHES)
             step()
             torch.cuda.synchronize()
             prof_m = plan.profile_read()
-            plan.profile(False)
-            roof_m = roofline_of(prof_m, sched, S, sizes, Ks, mixed=True)
+            plan.profile(A.ASD_PROFILE_OFF)
+            roof_m, _ = roofline_of(prof_m, sched, S, sizes, Ks, mixed=True)
         diff = lb_np - lbm
         scale = float(np.mean(np.abs(lb_np)))
         mixed = {"value": round(S * sched.as_iters * args.steps / (as_m / 1e3), 1),
@@ -564,6 +663,11 @@ def main():
         print("[bench] ragged two-net batch", file=sys.stderr, flush=True)
         plan = None
         ragged = ragged_leg(A, np, torch, WL)
+    mnist = None
+    if not args.no_mnist:
+        print("[bench] MNIST-shaped MLP", file=sys.stderr, flush=True)
+        plan = None
+        mnist = mnist_leg(A, np, torch, WL)
     adjoint = None
     if not args.no_adjoint:
         print("[bench] bound-gradient leg", file=sys.stderr, flush=True)
@@ -595,13 +699,16 @@ def main():
         "bigm_phase_ms": round(bigm_ms / args.steps, 3),
         "as_phase_ms": round(as_ms / args.steps, 3),
         "as_phase_alg_GBps": round(whole_as_gbs, 1),
+        "as_phase_frac": round(whole_as_gbs / HBM_PEAK_GBS, 4),
         "roofline": roofline,
+        "launch_rooflines": launches,
         "cpu_baseline": cpu,
         "fp64_final_vs_oracle": final_check,
         "kernels": kernels,
         "tuning": tuning,
         "mixed": mixed,
         "ragged": ragged,
+        "mnist": mnist,
         "adjoint": adjoint,
         "bound_mean": float(np.mean(lb_np)),
         "verified_fraction": float(np.mean(lb_np > 0)),

@@ -427,7 +427,11 @@ typedef enum {
     ASD_K_GRAD_WEIGHT = 5, /* asd_bound_grad: weight gradients */
     ASD_K_GRAD_BIAS = 6,   /* asd_bound_grad: bias gradients */
     ASD_K_GRAD_BOX = 7,    /* asd_bound_grad: input-box gradients */
-    ASD_K_COUNT = 8
+    ASD_K_FORWARD_PASS = 8,  /* one launch holding the forward kernels of several
+                                layers (layer = the lowest of them) */
+    ASD_K_BACKWARD_PAIR = 9, /* one launch holding the backward kernels into the
+                                last two neuron layers (layer = the lower one) */
+    ASD_K_COUNT = 10
 } asd_kernel_role;
 
 typedef struct {
@@ -437,10 +441,20 @@ typedef struct {
     double total_ms;    /* sum of HIP-event durations on the launch stream */
 } asd_kernel_time;
 
-/* Starts (enable = 1) or stops recording a HIP event pair around every kernel
- * launch of this plan, on the launch stream.  Enabling clears earlier
- * records.  Recording adds host work per launch; time runs without it. */
-asd_status asd_profile_enable(asd_plan* plan, int32_t enable);
+/* Timing modes of asd_profile_enable. */
+typedef enum {
+    ASD_PROFILE_OFF = 0,
+    ASD_PROFILE_LAUNCHES = 1, /* the launches as a solve runs them: kernels that
+                                 share a launch are timed together
+                                 (ASD_K_FORWARD_PASS, ASD_K_BACKWARD_PAIR) */
+    ASD_PROFILE_KERNELS = 2   /* every kernel launched and timed alone */
+} asd_profile_mode;
+
+/* Starts (mode 1 or 2) or stops (0) recording a HIP event pair around every
+ * iteration, mask, final-bound and gradient launch of this plan, on the
+ * launch stream.  Enabling clears earlier records.  Recording adds host work
+ * per launch; time runs without it.  Errors: ASD_EINVAL for another mode. */
+asd_status asd_profile_enable(asd_plan* plan, int32_t mode);
 /* Waits for the recorded events and writes per (role, layer) sums (host
  * array of `cap` entries); *count receives the number of entries. */
 asd_status asd_profile_read(asd_plan* plan, asd_kernel_time* out /* host */, int32_t cap,

@@ -68,7 +68,8 @@ class KernelTime(C.Structure):
 
 ASD_K_BACKWARD, ASD_K_FORWARD, ASD_K_MASK, ASD_K_FINAL, ASD_K_OTHER = range(5)
 ROLE_NAMES = {0: "backward", 1: "forward", 2: "mask", 3: "final", 4: "other", 5: "grad_weight",
-              6: "grad_bias", 7: "grad_box"}
+              6: "grad_bias", 7: "grad_box", 8: "forward_pass", 9: "backward_pair"}
+ASD_PROFILE_OFF, ASD_PROFILE_LAUNCHES, ASD_PROFILE_KERNELS = 0, 1, 2
 
 
 class Tuning(C.Structure):
@@ -432,9 +433,11 @@ class Plan:
                                     _ptr(dl0), _ptr(du0), int(reuse), _stream(stream)))
         return dW, db, dl0, du0
 
-    def profile(self, enable: bool):
-        """asd_profile_enable: HIP-event pairs around every launch of this plan."""
-        _check(lib().asd_profile_enable(self.handle, int(enable)))
+    def profile(self, mode):
+        """asd_profile_enable: HIP-event pairs around every launch of this plan
+        (mode ASD_PROFILE_LAUNCHES, or True: the launches as a solve runs them;
+        ASD_PROFILE_KERNELS: every kernel alone; False / 0: off)."""
+        _check(lib().asd_profile_enable(self.handle, int(mode)))
 
     def profile_read(self):
         """asd_profile_read: {(role, layer): (launches, total_ms)}."""

@@ -415,7 +415,7 @@ asd_status launch_backward(asd_plan* P, int k, int want_obj, int role, hipStream
 // (k_bwd_dense_pair); returns that lower layer, or -1.
 int bwd_pair_layer(const asd_plan* P) {
     const int ka = P->n - 1, kb = P->n - 2;
-    if (kb < 0 || P->prof) return -1;
+    if (kb < 0 || P->prof == ASD_PROFILE_KERNELS) return -1;
     const LayerGeo& ga = P->geo[ka + 1];
     const LayerGeo& gb = P->geo[kb + 1];
     if (ga.kind != ASD_LAYER_DENSE || ga.in.P != 1) return -1;
@@ -643,7 +643,7 @@ asd_status reset_group_moments(asd_plan* P, hipStream_t st) {
 // such layer.
 void shared_forward_layers(const asd_plan* P, int& fc, int& fd, int& fv) {
     fc = fd = fv = -1;
-    for (int k = 1; k < P->n && !P->prof; ++k) {
+    for (int k = 1; k < P->n && P->prof != ASD_PROFILE_KERNELS; ++k) {
         const LayerGeo& g = P->geo[k];
         if (fc < 0 && g.kind == ASD_LAYER_CONV2D && P->fwd_mfma[k] && P->fwd_kw[k] == 8) fc = k;
         if (fv < 0 && g.kind == ASD_LAYER_CONV2D && !P->fwd_mfma[k]) fv = k;
@@ -1216,7 +1216,7 @@ asd_status autotune_t(asd_plan* P, int ktune, int reps, hipStream_t st) {
     bool conv_mfma = false;
     for (int L = 1; L < P->n; ++L)
         conv_mfma |= P->geo[L].kind == ASD_LAYER_CONV2D && P->fwd_mfma[L] && P->fwd_kw[L] == 8;
-    for (int L = 1; L < P->n && conv_mfma && !P->prof && err == ASD_OK; ++L) {
+    for (int L = 1; L < P->n && conv_mfma && P->prof != ASD_PROFILE_KERNELS && err == ASD_OK; ++L) {
         if (P->geo[L].kind != ASD_LAYER_DENSE) continue;
         const long cap = std::max(1L, std::min((long)kMaxKsplit, (long)(P->geo[L].fan / (32 * KS))));
         int best = P->ksplit[L], bestkw = P->fwd_kw[L];
@@ -1367,7 +1367,7 @@ asd_status asd_plan_create(const asd_net* net, int32_t S, const asd_params* para
     P->S = S;
     P->n = net->n;
     P->prm = *params;
-    P->prof = false;
+    P->prof = ASD_PROFILE_OFF;
     P->prof_used = 0;
     setup_plan_geometry(P);
     Carver cv{reinterpret_cast<char*>(workspace), 0};
@@ -1440,9 +1440,11 @@ asd_status asd_plan_set_tuning(asd_plan* P, const asd_tuning* in) {
     return ASD_OK;
 }
 
-asd_status asd_profile_enable(asd_plan* P, int32_t enable) {
+asd_status asd_profile_enable(asd_plan* P, int32_t mode) {
     if (!P) return fail(ASD_EINVAL, "NULL plan");
-    P->prof = enable != 0;
+    if (mode != ASD_PROFILE_OFF && mode != ASD_PROFILE_LAUNCHES && mode != ASD_PROFILE_KERNELS)
+        return fail(ASD_EINVAL, "unknown profiling mode %d", mode);
+    P->prof = mode;
     if (P->prof) {
         P->prof_recs.clear();
         P->prof_used = 0;

@@ -75,6 +75,7 @@ asd_status fwd_fused_impl(asd_plan* P, int kc, int kd, const StepArgsT<float>& s
     const int cgx = (int)((ac.g.out.cols + 31) / 32), cgy = ac.Cpad / 32;
     const dim3 grid((unsigned)(nd + cgx * cgy));
     const bool du = ad.ksplit == 1;  // one split: the dense blocks update, no epilogue
+    ProfScope ps(P, st, ASD_K_FORWARD_PASS, std::min(kc, kd));
     if (ac.g.ksz == 4) {
         if (du) hipLaunchKernelGGL((k_fwd_conv_dense<NM, 4, MB, true>), grid, dim3(kWave, 8), 0, st, ac, ad, nd, dgx, dgy, cgx, cgy);
         else hipLaunchKernelGGL((k_fwd_conv_dense<NM, 4, MB, false>), grid, dim3(kWave, 8), 0, st, ac, ad, nd, dgx, dgy, cgx, cgy);
@@ -108,6 +109,7 @@ asd_status fwd_trio_impl(asd_plan* P, int kv, int kc, int kd, const StepArgsT<fl
     const dim3 grid((unsigned)(nd + nc + nv));
     const bool c4 = ac.g.ksz == 4, v4 = av.g.ksz == 4;
     const bool du = ad.ksplit == 1;  // one split: the dense blocks update, no epilogue
+    ProfScope ps(P, st, ASD_K_FORWARD_PASS, std::min(kv, std::min(kc, kd)));
 #define ASD_TRIO_LAUNCH(KC, KV)                                                                                       \
     do {                                                                                                              \
         if (du)                                                                                                       \
@@ -149,6 +151,7 @@ asd_status bwd_pair_nm(asd_plan* P, hipStream_t st) {
     const NeuronLayout& Lb = ab.gn.in;
     const int agx = (int)((La.cols + kWave - 1) / kWave), agy = (La.C + 7) / 8, na = agx * agy;
     const int mgx = (P->Sa + 15) / 16, mgy = Lb.C * (Lb.P / kWave);
+    ProfScope ps(P, st, ASD_K_BACKWARD_PAIR, kb);
     hipLaunchKernelGGL((k_bwd_dense_pair<NM>), dim3((unsigned)(na + mgx * mgy)), dim3(kWave, 4), 0, st, aa, ab, na, agx,
                        agy, mgx);
     LAUNCH_CHECK();

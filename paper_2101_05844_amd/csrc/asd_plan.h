@@ -115,8 +115,8 @@ struct asd_plan {
     // caller arrays for f_k and the supergradient of layer k, null otherwise
     void* ev_f[asd::kMaxLayers];
     void* ev_g[asd::kMaxLayers][3 + asd::kMaxMasks];
-    // kernel timing
-    bool prof;
+    // kernel timing (asd_profile_mode)
+    int prof;
     std::vector<asd::ProfRec> prof_recs;
     std::vector<hipEvent_t> prof_pool;
     size_t prof_used;

@@ -438,21 +438,18 @@ def export_final_state(A, plan, rows):
     return ex
 
 
-def final_bound_check(w, ex, lb, rows):
+def final_bound_check(w, ex, lb, rows, L, U):
     """Per-result error of the FP64 final bound of the FP32 solve: the oracle
     evaluates d_B (eq:dual-active-set) at each sampled subdomain's exported
     final duals, its masks rebuilt by the oracle's eq:oracle at the recorded
-    primal points; error absolute and relative to the sum of |terms|."""
+    primal points (the problem of each subdomain is the one the GPU solved:
+    L, U are its pre-activation bounds); error absolute and relative to the
+    sum of |terms|."""
     import numpy as np
 
     from oracle import asd_oracle as O
-    from paper_2101_05844_amd import workloads as WL
 
     ops = O.ops_from_workload_layers(w.layers)
-    lh, uh = O.interval_bounds(ops, w.l0[0].astype(float), w.u0[0].astype(float))
-    lh = [np.nextafter(a.astype(np.float32), np.float32(-np.inf)) for a in lh[:-1]]
-    uh = [np.nextafter(a.astype(np.float32), np.float32(np.inf)) for a in uh[:-1]]
-    L, U = WL.subdomain_bounds(lh, uh, w.fix_draws, w.S)
     abs_e, rel_e = [], []
     for i, s in enumerate(rows):
         p = O.make_problem(ops, w.l0[s], w.u0[s], [a[s] for a in L], [a[s] for a in U], w.c[s])
@@ -494,6 +491,8 @@ def main():
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged two-net batch")
     ap.add_argument("--no-mnist", action="store_true", help="skip the MNIST-shaped MLP leg")
     ap.add_argument("--no-autotune", action="store_true", help="keep the heuristic kernel choices")
+    ap.add_argument("--tuning", default=None, metavar="JSON",
+                    help="kernel choices to set instead of autotuning (the 'tuning' object of a bench line)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 3 device-to-device copies of MIB MiB (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
@@ -539,7 +538,10 @@ def main():
     plan = A.Plan(net, S, A.params_from_schedule(sched))
     stream = torch.cuda.current_stream()
     tuning = None
-    if not args.no_autotune:
+    if args.tuning:
+        tuning = json.loads(args.tuning)
+        plan.set_tuning(tuning)
+    elif not args.no_autotune:
         # kernel choices timed on this batch (two empty mask slots active)
         plan.init(l0, u0, lh, uh, c)
         tuning = plan.autotune(ktune=2, reps=3)
@@ -677,7 +679,7 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
         cpu = cpu_baseline(w)
-        final_check = final_bound_check(w, final_ex, lb_np, rows)
+        final_check = final_bound_check(w, final_ex, lb_np, rows, L, U)
     out = {
         "metric": METRIC,
         "value": round(value, 1),

@@ -211,6 +211,24 @@ asd_status asd_solve(asd_plan* plan, const asd_batch* batch, double* out_lb, flo
  * instantiation fails. */
 asd_status asd_solve_graph(asd_plan* plan, const asd_batch* batch, double* out_lb, hipStream_t stream);
 
+/* asd_solve without a plan or workspace of the caller's, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the plan is built for
+ * this call over a static workspace the library holds on each GPU (64 MiB
+ * per GPU, kept until the process ends), with the default kernel choices,
+ * and runs asd_init, T_M Big-M and T Active Set iterations and asd_bound as
+ * asd_solve does (same results).  out_lb [S] device doubles; x0 as for
+ * asd_bound (may be NULL).  The call allocates nothing and calls no
+ * allocating routine; all its work is stream-ordered on `stream`.  Every
+ * call on one GPU uses the same workspace: calls that overlap on one GPU
+ * (on different streams or threads) race, and must be serialised by the
+ * caller.  Errors: ASD_EINVAL for NULL arguments, invalid params or a batch
+ * whose plan would need more than the static workspace
+ * (asd_plan_workspace_size > 64 MiB); ASD_EDEVICE if the workspace's device
+ * address cannot be obtained. */
+asd_status asd_solve_static(const asd_net* net, const asd_params* params, const asd_batch* batch,
+                            double* out_lb, float* x0, hipStream_t stream);
+
 /* Per-subproblem health of a solve: flags [S] (device, int32) receives, for
  * each subproblem s, bit 0 set if lb[s] (device [S], as written by asd_bound)
  * is not finite, bit 1 set if any multiplier of s (alpha, beta_0, beta_1,

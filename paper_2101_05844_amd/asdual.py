@@ -101,7 +101,7 @@ EXPORTED = ["asd_net_create", "asd_net_destroy", "asd_params_default", "asd_plan
             "asd_state_get", "asd_state_set", "asd_state_get_counts", "asd_state_set_counts",
             "asd_eval", "asd_oracle", "asd_bound_grad", "asd_set_budgets", "asd_solve_group", "asd_solve_graph", "asd_check_finite",
             "asd_plan_autotune", "asd_plan_get_tuning", "asd_plan_set_tuning", "asd_interval_bounds", "asd_profile_enable", "asd_profile_read",
-            "asd_last_error", "asd_abi_version"]
+            "asd_solve_static", "asd_last_error", "asd_abi_version"]
 
 
 def lib():
@@ -127,6 +127,7 @@ def lib():
     L.asd_run.argtypes = [vp, i32, i32, i32, vp]
     L.asd_bound.argtypes = [vp, vp, vp, vp]
     L.asd_solve.argtypes = [vp, C.POINTER(Batch), vp, vp, vp]
+    L.asd_solve_static.argtypes = [vp, C.POINTER(Params), C.POINTER(Batch), vp, vp, vp]
     L.asd_state_get.argtypes = [vp, i32, i32, i32, vp, vp]
     L.asd_state_set.argtypes = [vp, i32, i32, i32, vp, vp]
     L.asd_state_get_counts.argtypes = [vp, C.POINTER(Counts)]
@@ -500,6 +501,20 @@ def solve_group(plans: Sequence["Plan"], batches, streams=None):
     for s_ in streams:
         cur.wait_stream(s_)
     return outs
+
+
+def solve_static(net: "Net", params: Params, l0, u0, lhat, uhat, c, want_x0: bool = False, stream=None):
+    """asd_solve_static: a whole solve over the library's static workspace
+    (no plan, no workspace allocation); returns the bounds [S] (and x*_0)."""
+    S = l0.shape[0]
+    lh = (C.c_void_p * max(1, len(lhat)))(*[_ptr(t) for t in lhat])
+    uh = (C.c_void_p * max(1, len(uhat)))(*[_ptr(t) for t in uhat])
+    b = Batch(S, _ptr(l0), _ptr(u0), C.cast(lh, C.POINTER(C.c_void_p)), C.cast(uh, C.POINTER(C.c_void_p)), _ptr(c))
+    out = torch.empty(S, dtype=torch.float64, device="cuda")
+    x0 = torch.empty(S, net.sizes[0], dtype=torch.float32, device="cuda") if want_x0 else None
+    _check(lib().asd_solve_static(net.handle, C.byref(params), C.byref(b), out.data_ptr(), _ptr(x0),
+                                  _stream(stream)))
+    return (out, x0) if want_x0 else out
 
 
 class BoundFunction(torch.autograd.Function):

@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -781,9 +782,13 @@ asd_status init_t(asd_plan* P, const asd_batch* b, hipStream_t st) {
     }
     TRY(prepare_weights(P, st));
     TRY(zero_words(P->pointflag, kMaxLayers, st));
-    // the update kernels read the layer arrays from a device copy (the host
-    // array lives in the plan, so the copy may complete asynchronously)
-    HIP_TRY(hipMemcpyAsync(P->Rdev, RL<T>(P), sizeof(ReluLayerT<T>) * kMaxLayers, hipMemcpyHostToDevice, st));
+    // the update kernels read the layer arrays from a device copy, written by
+    // a kernel that takes each table as its argument (stream-ordered, and no
+    // host memory is read after the launch)
+    for (int k = 1; k < P->n; ++k) {
+        hipLaunchKernelGGL(k_store_layer<T>, dim3(1), dim3(1), 0, st, RdevT<T>(P) + k, RL<T>(P)[k]);
+        LAUNCH_CHECK();
+    }
     return pack_all<T>(P, 1, st);
 }
 
@@ -1257,6 +1262,56 @@ int as_iters_of(const asd_plan* P) { return P->ragged ? P->budgets[0] : P->prm.a
 
 }  // namespace
 
+// Plan fields of a fresh plan over a workspace.
+static void bind_plan(asd_plan* P, const asd_net* net, int S, const asd_params* params, void* workspace) {
+    P->net = net;
+    P->S = S;
+    P->n = net->n;
+    P->prm = *params;
+    P->prof = ASD_PROFILE_OFF;
+    P->prof_used = 0;
+    setup_plan_geometry(P);
+    Carver cv{reinterpret_cast<char*>(workspace), 0};
+    carve(P, cv);
+    P->Sa = S;
+    P->ragged = false;
+    P->min_valid = false;
+}
+
+// Workspace of asd_solve_static: one array per GPU the library runs on,
+// kept until the process ends.  Host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device (the array's
+// own name is a host-side stand-in).  Every call on a GPU reuses that GPU's
+// array: asd_init clears all state a solve reads before writing it, and
+// calls that overlap on one GPU race.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+}  // namespace
+
+static asd_status scratch_of_current_device(void** out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(ASD_EDEVICE, "device index %d outside [0, %d)", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(ASD_EDEVICE, "hipGetSymbolAddress of the static workspace failed: %s", hipGetErrorString(e));
+        if ((uintptr_t)p % 256) return fail(ASD_EDEVICE, "static workspace is not 256-byte aligned");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return ASD_OK;
+}
+
 asd_status asd::launch_backward_iter(asd_plan* P, int k, hipStream_t st) {
     return launch_backward<float, float>(P, k, 0, ASD_K_BACKWARD, st);
 }
@@ -1363,20 +1418,28 @@ asd_status asd_plan_create(const asd_net* net, int32_t S, const asd_params* para
     if ((uintptr_t)workspace % 256) return fail(ASD_EINVAL, "workspace must be 256-byte aligned");
     asd_plan* P = new (std::nothrow) asd_plan();  // value-initialised
     if (!P) return fail(ASD_EINVAL, "host allocation failed");
-    P->net = net;
-    P->S = S;
-    P->n = net->n;
-    P->prm = *params;
-    P->prof = ASD_PROFILE_OFF;
-    P->prof_used = 0;
-    setup_plan_geometry(P);
-    Carver cv{reinterpret_cast<char*>(workspace), 0};
-    carve(P, cv);
-    P->Sa = S;
-    P->ragged = false;
-    P->min_valid = false;
+    bind_plan(P, net, S, params, workspace);
     *out = P;
     return ASD_OK;
+}
+
+asd_status asd_solve_static(const asd_net* net, const asd_params* params, const asd_batch* b, double* out_lb,
+                            float* x0, hipStream_t st) {
+    if (!net || !params || !b || !out_lb) return fail(ASD_EINVAL, "NULL argument");
+    size_t need = 0;
+    TRY(asd_plan_workspace_size(net, b->S, params, &need));
+    if (need > kScratchBytes)
+        return fail(ASD_EINVAL,
+                    "S = %d needs %zu bytes of workspace; the static workspace of asd_solve_static holds %zu "
+                    "(solve larger batches through a plan with a workspace of the caller's)",
+                    b->S, need, kScratchBytes);
+    void* ws = nullptr;
+    TRY(scratch_of_current_device(&ws));
+    // the plan lives on this stack frame: every launch below takes what it
+    // needs as kernel arguments, so nothing host-side has to outlive the call
+    asd_plan P{};
+    bind_plan(&P, net, b->S, params, ws);
+    return asd_solve(&P, b, out_lb, x0, st);
 }
 
 void asd_plan_destroy(asd_plan* plan) {

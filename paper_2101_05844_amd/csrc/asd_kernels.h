@@ -826,6 +826,13 @@ __global__ void k_bits(BitArgs<T, Te> A) {
     if (col - lane < A.nl.colpad) put_wave_bits(A.bits, (long)c * A.nl.colpad + (col - lane), pred, lane);
 }
 
+// Device copy of one layer's array table, passed by value as the kernel
+// argument (no host buffer has to outlive the launch).  One thread.
+template <typename T>
+__global__ void k_store_layer(ReluLayerT<T>* dst, ReluLayerT<T> v) {
+    *dst = v;
+}
+
 // Per-subproblem objective: sum of every neuron term (fixed order) plus b_n^T c.
 template <typename T>
 struct ReduceArgs {

@@ -488,6 +488,7 @@ def main():
     ap.add_argument("--no-kernel-profile", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the bound-gradient leg")
     ap.add_argument("--no-mixed", action="store_true", help="skip the BF16-moment form")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 matrix-core form")
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged two-net batch")
     ap.add_argument("--no-mnist", action="store_true", help="skip the MNIST-shaped MLP leg")
     ap.add_argument("--no-autotune", action="store_true", help="keep the heuristic kernel choices")
@@ -619,14 +620,23 @@ def main():
         del src, dst
         roofline["copy_GBps"] = round(copy_gbs, 1)
         roofline["frac_of_copy"] = round(roofline["achieved"] / copy_gbs, 4)
-    mixed = None
+    mixed = bf16 = bf16_all = None
+    reduced = []
     if not args.no_mixed:
-        # the same solves with Adam moments stored in BF16 (ASD_PREC_MIXED):
-        # rate, and bound accuracy against the FP32 form on every subdomain
-        print("[bench] mixed-precision form", file=sys.stderr, flush=True)
-        del plan
-        prm_mixed = A.params_from_schedule(sched, A.ASD_PREC_MIXED)
-        plan = A.Plan(net, S, prm_mixed)
+        reduced.append(("mixed", A.ASD_PREC_MIXED, "f32 duals and arithmetic, bf16 Adam moments, f64 final bound"))
+    if not args.no_bf16:
+        reduced.append(("bf16", A.ASD_PREC_BF16, "bf16 operands in the forward matrix-core products (f32 "
+                                                 "accumulation), f32 transposed products, f32 duals, bf16 Adam "
+                                                 "moments, f64 final bound"))
+        reduced.append(("bf16_all", A.ASD_PREC_BF16_ALL, "bf16 operands in every matrix-core product (f32 "
+                                                         "accumulation), f32 duals, bf16 Adam moments, f64 final "
+                                                         "bound"))
+    for name, mode, dtype in reduced:
+        # the same solves in a reduced-precision form: rate, and bound
+        # accuracy against the FP32 form on every subdomain
+        print(f"[bench] {name} form", file=sys.stderr, flush=True)
+        plan = None
+        plan = A.Plan(net, S, A.params_from_schedule(sched, mode))
         if tuning is not None:
             plan.set_tuning(tuning)
         for _ in range(args.warmup):
@@ -648,18 +658,23 @@ def main():
             roof_m, _ = roofline_of(prof_m, sched, S, sizes, Ks, mixed=True)
         diff = lb_np - lbm
         scale = float(np.mean(np.abs(lb_np)))
-        mixed = {"value": round(S * sched.as_iters * args.steps / (as_m / 1e3), 1),
-                 "unit": "subproblem-iterations/s", "as_phase_ms": round(as_m / args.steps, 3),
-                 "speedup_vs_fp32": round(as_ms / as_m, 4),
-                 "bound_mean": float(np.mean(lbm)),
-                 "mean_fp32_minus_mixed": float(np.mean(diff)),
-                 "max_abs_diff": float(np.max(np.abs(diff))),
-                 "accuracy_scale": scale,
-                 "equal_accuracy": bool(np.mean(diff) <= 1e-4 * scale
-                                        and int(np.sum(lbm > 0)) >= int(np.sum(lb_np > 0))),
-                 "verified": [int(np.sum(lb_np > 0)), int(np.sum(lbm > 0))],
-                 "roofline": roof_m,
-                 "dtype": "f32 duals and arithmetic, bf16 Adam moments, f64 final bound"}
+        res = {"value": round(S * sched.as_iters * args.steps / (as_m / 1e3), 1),
+               "unit": "subproblem-iterations/s", "as_phase_ms": round(as_m / args.steps, 3),
+               "speedup_vs_fp32": round(as_ms / as_m, 4),
+               "bound_mean": float(np.mean(lbm)),
+               "mean_fp32_minus_this": float(np.mean(diff)),
+               "max_abs_diff": float(np.max(np.abs(diff))),
+               "accuracy_scale": scale,
+               "equal_accuracy": bool(np.mean(diff) <= 1e-4 * scale
+                                      and int(np.sum(lbm > 0)) >= int(np.sum(lb_np > 0))),
+               "verified": [int(np.sum(lb_np > 0)), int(np.sum(lbm > 0))],
+               "roofline": roof_m, "dtype": dtype}
+        if name == "mixed":
+            mixed = res
+        elif name == "bf16":
+            bf16 = res
+        else:
+            bf16_all = res
     ragged = None
     if not args.no_ragged:
         print("[bench] ragged two-net batch", file=sys.stderr, flush=True)
@@ -709,6 +724,8 @@ def main():
         "kernels": kernels,
         "tuning": tuning,
         "mixed": mixed,
+        "bf16": bf16,
+        "bf16_all": bf16_all,
         "ragged": ragged,
         "mnist": mnist,
         "adjoint": adjoint,

@@ -98,9 +98,26 @@ typedef enum { ASD_RULE_ADAM = 0, ASD_RULE_SUPERGRADIENT = 1 } asd_rule;
  * multiplier.  The duals, the products and the
  * FP64 final bound are those of ASD_PREC_FP32, so the bound stays valid;
  * only the trajectory of the ascent changes.  The state calls exchange the
- * moments as float in every FP32-duals mode.  Network weights and batch
- * inputs are FP32 in all modes. */
-typedef enum { ASD_PREC_FP32 = 0, ASD_PREC_FP64 = 1, ASD_PREC_MIXED = 2 } asd_precision;
+ * moments as float in every FP32-duals mode.  ASD_PREC_BF16 is
+ * ASD_PREC_MIXED with BF16 operands in the matrix-core products of the
+ * forward pass (W x* and |W| (sigma . x*), whose results form the
+ * supergradient, eq:as-supergradient: weights and operands rounded to BF16,
+ * nearest even, FP32 accumulation).  ASD_PREC_BF16_ALL also takes BF16
+ * operands in the transposed products of the backward pass, whose results
+ * f choose the minimiser (eq:as-primalk-min): near converged duals many f
+ * lie within BF16 rounding of zero, and the wrong corners cost bound
+ * accuracy, so the transposed products stay FP32 in ASD_PREC_BF16.  In both
+ * the duals stay FP32 and the final bound is the FP64 evaluation from the
+ * FP32 weights, so it stays valid; products the iteration runs on the
+ * vector units (narrow convolutions, the last layer's backward pass) stay
+ * FP32.  Network weights and batch inputs are FP32 in all modes. */
+typedef enum {
+    ASD_PREC_FP32 = 0,
+    ASD_PREC_FP64 = 1,
+    ASD_PREC_MIXED = 2,
+    ASD_PREC_BF16 = 3,
+    ASD_PREC_BF16_ALL = 4
+} asd_precision;
 
 /* Solver schedule (Sec. 7.1; readings: additions at Active Set iterations t
  * with t mod add_every < add_count while fewer than max_masks masks are

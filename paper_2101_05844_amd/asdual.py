@@ -22,7 +22,7 @@ ASD_MAX_LAYERS = 16
 ASD_MAX_MASKS = 8
 ASD_LAYER_DENSE, ASD_LAYER_CONV2D = 0, 1
 ASD_RULE_ADAM, ASD_RULE_SUPERGRADIENT = 0, 1
-ASD_PREC_FP32, ASD_PREC_FP64, ASD_PREC_MIXED = 0, 1, 2
+ASD_PREC_FP32, ASD_PREC_FP64, ASD_PREC_MIXED, ASD_PREC_BF16, ASD_PREC_BF16_ALL = 0, 1, 2, 3, 4
 ASD_PHASE_BIGM, ASD_PHASE_AS = 0, 1
 (ASD_F_ALPHA, ASD_F_BETA0, ASD_F_BETA1, ASD_F_ALPHA_M, ASD_F_ALPHA_V, ASD_F_BETA0_M, ASD_F_BETA0_V,
  ASD_F_BETA1_M, ASD_F_BETA1_V, ASD_F_MASK_BETA, ASD_F_MASK_M, ASD_F_MASK_V, ASD_F_MASK_LI,
@@ -254,6 +254,10 @@ class Plan:
                                      _stream(stream), C.byref(h)))
         self.handle = h
         self._keep = None
+        # bumped by every call that changes the plan's duals, masks or batch
+        # (a backward pass of BoundFunction checks that its solve's state is
+        # still the plan's)
+        self.generation = 0
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
@@ -263,6 +267,7 @@ class Plan:
     # -- batch ---------------------------------------------------------------
     def init(self, l0, u0, lhat: Sequence[torch.Tensor], uhat: Sequence[torch.Tensor], c, stream=None):
         """asd_init.  All tensors float32 on the device, [S][n] row-major."""
+        self.generation += 1
         lh = (C.c_void_p * max(1, len(lhat)))(*[_ptr(t) for t in lhat])
         uh = (C.c_void_p * max(1, len(uhat)))(*[_ptr(t) for t in uhat])
         b = Batch(self.S, _ptr(l0), _ptr(u0), C.cast(lh, C.POINTER(C.c_void_p)),
@@ -271,6 +276,7 @@ class Plan:
         _check(lib().asd_init(self.handle, C.byref(b), _stream(stream)))
 
     def run(self, phase: int, t_begin: int, n_iters: int, stream=None):
+        self.generation += 1
         _check(lib().asd_run(self.handle, phase, t_begin, n_iters, _stream(stream)))
 
     def bound(self, want_x0: bool = False, stream=None):
@@ -329,6 +335,7 @@ class Plan:
 
     def solve_graph(self, l0, u0, lhat, uhat, c, stream=None):
         """asd_solve_graph: asd_solve with the iterations replayed from a HIP graph."""
+        self.generation += 1
         lh = (C.c_void_p * max(1, len(lhat)))(*[_ptr(t) for t in lhat])
         uh = (C.c_void_p * max(1, len(uhat)))(*[_ptr(t) for t in uhat])
         b = Batch(self.S, _ptr(l0), _ptr(u0), C.cast(lh, C.POINTER(C.c_void_p)),
@@ -355,6 +362,7 @@ class Plan:
         return dst
 
     def set(self, field: int, k: int, src: torch.Tensor, q: int = 0, stream=None):
+        self.generation += 1
         src = src.to(device="cuda", dtype=self.dtype).contiguous()
         assert tuple(src.shape) == (self.S, self._n(field, k))
         _check(lib().asd_state_set(self.handle, field, k, q, src.data_ptr(), _stream(stream)))
@@ -367,6 +375,7 @@ class Plan:
 
     def set_counts(self, n_masks: int, step: int, mask_step: Sequence[int], recompute: bool = True,
                    stream=None):
+        self.generation += 1
         c = Counts()
         c.n_masks, c.step = n_masks, step
         for q, v in enumerate(mask_step):
@@ -497,6 +506,8 @@ def solve_group(plans: Sequence["Plan"], batches, streams=None):
     barr = (C.POINTER(Batch) * n)(*[C.pointer(b) for b in bs])
     oarr = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
     sarr = (C.c_void_p * n)(*[s_.cuda_stream for s_ in streams])
+    for P in plans:
+        P.generation += 1
     _check(lib().asd_solve_group(parr, barr, oarr, n, sarr))
     for s_ in streams:
         cur.wait_stream(s_)
@@ -531,11 +542,18 @@ class BoundFunction(torch.autograd.Function):
     def forward(ctx, plan, l0, u0, lhat, uhat, c, *params):
         ctx.plan = plan
         ctx.n = plan.net.n
-        return plan.solve(l0, u0, list(lhat), list(uhat), c)
+        lb = plan.solve(l0, u0, list(lhat), list(uhat), c)
+        ctx.generation = plan.generation
+        return lb
 
     @staticmethod
     def backward(ctx, glb):
         plan = ctx.plan
+        if plan.generation != ctx.generation:
+            raise RuntimeError("BoundFunction.backward: the plan's duals or batch changed after this forward "
+                               "pass (another solve, run, init or state_set on the same plan); the gradient "
+                               "would belong to a different solve.  Give each forward pass its own plan, or "
+                               "run the backward pass before reusing the plan.")
         need_w = any(ctx.needs_input_grad[6:])
         need_box = ctx.needs_input_grad[1] or ctx.needs_input_grad[2]
         # the forward pass ended with asd_bound on this plan; autograd runs

@@ -165,7 +165,8 @@ asd_status check_params(const asd_params* p) {
     if (p->max_masks < 0 || p->max_masks > ASD_MAX_MASKS)
         return fail(ASD_EINVAL, "max_masks must be in [0, %d]", ASD_MAX_MASKS);
     if (p->rule != ASD_RULE_ADAM && p->rule != ASD_RULE_SUPERGRADIENT) return fail(ASD_EINVAL, "unknown rule");
-    if (p->precision != ASD_PREC_FP32 && p->precision != ASD_PREC_FP64 && p->precision != ASD_PREC_MIXED)
+    if (p->precision != ASD_PREC_FP32 && p->precision != ASD_PREC_FP64 && p->precision != ASD_PREC_MIXED &&
+        p->precision != ASD_PREC_BF16 && p->precision != ASD_PREC_BF16_ALL)
         return fail(ASD_EINVAL, "unknown precision %d", p->precision);
     if (!(p->adam_beta1 >= 0.0 && p->adam_beta1 < 1.0 && p->adam_beta2 >= 0.0 && p->adam_beta2 < 1.0))
         return fail(ASD_EINVAL, "Adam betas must be in [0, 1)");
@@ -385,21 +386,21 @@ asd_status prepare_weights(asd_plan* P, hipStream_t st) {
 }
 
 asd_status fwd_fast(asd_plan* P, int k, const StepArgsT<float>& sa, hipStream_t st) {
-    const bool mb = P->prm.precision == ASD_PREC_MIXED;
+    const bool mb = bf16_moments(P);
 #define ASD_FWD_CALL(N) return fwd_fast_nm<N>(P, k, sa, mb, st)
     ASD_NM_DISPATCH(P->n_masks, ASD_FWD_CALL)
 #undef ASD_FWD_CALL
 }
 
 asd_status fwd_trio(asd_plan* P, int kv, int kc, int kd, const StepArgsT<float>& sa, hipStream_t st) {
-    const bool mb = P->prm.precision == ASD_PREC_MIXED;
+    const bool mb = bf16_moments(P);
 #define ASD_TRIO_CALL(N) return fwd_trio_nm<N>(P, kv, kc, kd, sa, mb, st)
     ASD_NM_DISPATCH(P->n_masks, ASD_TRIO_CALL)
 #undef ASD_TRIO_CALL
 }
 
 asd_status fwd_fused(asd_plan* P, int kc, int kd, const StepArgsT<float>& sa, hipStream_t st) {
-    const bool mb = P->prm.precision == ASD_PREC_MIXED;
+    const bool mb = bf16_moments(P);
 #define ASD_FUSED_CALL(N) return fwd_fused_nm<N>(P, kc, kd, sa, mb, st)
     ASD_NM_DISPATCH(P->n_masks, ASD_FUSED_CALL)
 #undef ASD_FUSED_CALL
@@ -970,7 +971,7 @@ template <typename T>
 asd_status state_get_t(asd_plan* P, int field, int k, int q, T* dst, hipStream_t st) {
     ReluLayerT<T>& r = RL<T>(P)[k];
     if constexpr (sizeof(T) == 4)
-        if (P->prm.precision == ASD_PREC_MIXED && is_moment(field)) return moment_bf16(P, field, k, q, dst, 2, st);
+        if (bf16_moments(P) && is_moment(field)) return moment_bf16(P, field, k, q, dst, 2, st);
     if (field == ASD_F_MASK_Z)
         return launch_bits<T, T>(P->nl[k], P->S, 0, r.slot[q].zbits, dst, nullptr, nullptr, st);
     if (field == ASD_F_MASK_XPREV)
@@ -984,7 +985,7 @@ asd_status state_set_t(asd_plan* P, int field, int k, int q, const T* src, hipSt
     ReluLayerT<T>& r = RL<T>(P)[k];
     T* s = const_cast<T*>(src);
     if constexpr (sizeof(T) == 4)
-        if (P->prm.precision == ASD_PREC_MIXED && is_moment(field)) return moment_bf16(P, field, k, q, s, 0, st);
+        if (bf16_moments(P) && is_moment(field)) return moment_bf16(P, field, k, q, s, 0, st);
     if (field == ASD_F_MASK_Z) {
         TRY((launch_bits<T, T>(P->nl[k], P->S, 2, r.slot[q].zbits, s, nullptr, nullptr, st)));
     } else if (field == ASD_F_MASK_XPREV) {

@@ -166,6 +166,33 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
 }
 __device__ __forceinline__ float bf16_val(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// BF16 matrix-core operands (ASD_PREC_BF16): four values rounded to BF16
+// (nearest even), the operand of one lane of a v_mfma_*bf16_1k instruction.
+// Slot i of that operand takes the place of the lane's operand in the i-th
+// of four consecutive FP32 instructions of the same shape (32x32x2 ->
+// 32x32x8, 16x16x4 -> 16x16x16, 4x4x1 -> 4x4x4), so a kernel's tap order
+// carries over unchanged.
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ shortx4 bf16x4(float a, float b, float c, float d) {
+    shortx4 r;
+    r[0] = (short)bf16_rne(a);
+    r[1] = (short)bf16_rne(b);
+    r[2] = (short)bf16_rne(c);
+    r[3] = (short)bf16_rne(d);
+    return r;
+}
+__device__ __forceinline__ shortx4 bf16x4(const float* v) { return bf16x4(v[0], v[1], v[2], v[3]); }
+// |v| and -v slot by slot: the sign bit of each BF16 value
+__device__ __forceinline__ shortx4 bf16_abs(shortx4 v) { return v & (short)0x7fff; }
+__device__ __forceinline__ shortx4 bf16_flip(shortx4 v, unsigned b0, unsigned b1, unsigned b2, unsigned b3) {
+    shortx4 m;
+    m[0] = (short)(b0 << 15);
+    m[1] = (short)(b1 << 15);
+    m[2] = (short)(b2 << 15);
+    m[3] = (short)(b3 << 15);
+    return v ^ m;
+}
+
 // Mixed mode (MB): the two Adam moments of a multiplier share one 32-bit
 // word of the m array, m in the high and v in the low 16 bits, each BF16;
 // the v array is unused.
@@ -496,9 +523,58 @@ __global__ void __launch_bounds__(kWave * KS) k_fwd_conv(FastFwdArgs<T> A) {
 // ---------------------------------------------------------------------------
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
+// The products of one trip of 4 steps of the 32 x 32 forward tiles: step u
+// takes the lane's weight w[u], input x[u] and packed bits h[u]; the W
+// product into acc[0], the |W| product of mask q with x sign-flipped by the
+// mask's bit into acc[1 + q], the W+ product of the inputs at point boxes
+// away from zero into accp.  FP32: four v_mfma_f32_32x32x2f32 per product;
+// BF16: one v_mfma_f32_32x32x8bf16_1k with the four steps in its slots.
+template <int NM, bool BF>
+__device__ __forceinline__ void mfma_trip_32(const float* w, const float* x, const unsigned* h, bool pointin,
+                                             floatx16* acc, floatx16& accp) {
+    constexpr int U = 4;
+    if constexpr (BF) {
+        const shortx4 wb = bf16x4(w), xb = bf16x4(x);
+        acc[0] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(wb, xb, acc[0], 0, 0, 0);
+        const shortx4 wa = bf16_abs(wb);
+#pragma unroll
+        for (int q = 0; q < NM; ++q)
+            acc[1 + q] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(
+                wa, bf16_flip(xb, (h[0] >> q) & 1u, (h[1] >> q) & 1u, (h[2] >> q) & 1u, (h[3] >> q) & 1u), acc[1 + q],
+                0, 0, 0);
+        if (pointin) {
+            float wp[U], xp[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                wp[u] = fmaxf(w[u], 0.f);
+                xp[u] = ((h[u] >> kPointBit) & 1u) ? x[u] : 0.f;
+            }
+            accp = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(bf16x4(wp), bf16x4(xp), accp, 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(w[u], x[u], acc[0], 0, 0, 0);
+            const float wabs = fabsf(w[u]);
+#pragma unroll
+            for (int q = 0; q < NM; ++q)
+                acc[1 + q] =
+                    __builtin_amdgcn_mfma_f32_32x32x2f32(wabs, flip(x[u], (h[u] >> q) & 1u), acc[1 + q], 0, 0, 0);
+        }
+        if (pointin) {
+            // point boxes away from zero: (W . I) x gains W+ x_point on z = 0 rows
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const float xp = ((h[u] >> kPointBit) & 1u) ? x[u] : 0.f;
+                accp = __builtin_amdgcn_mfma_f32_32x32x2f32(fmaxf(w[u], 0.f), xp, accp, 0, 0, 0);
+            }
+        }
+    }
+}
+
 // UPD (one split, ksplit == 1): the block holds the whole products of its
 // tile and updates its neurons itself (no partial sums, no epilogue).
-template <int NM, int KW, bool UPD = false, bool MB = false>  // KW: waves splitting the block's fan-in range
+template <int NM, int KW, bool UPD = false, bool MB = false, bool BF = false>  // KW: waves splitting the block's fan-in range; BF: BF16 operands
 __device__ __forceinline__ void fwd_dense_mfma_block(const FastFwdArgs<float>& A, int bx, int by, int bz,
                                                      float (*red)[16][kWave]) {
     constexpr int U = 4;  // steps of 2 taps per trip
@@ -588,23 +664,7 @@ __device__ __forceinline__ void fwd_dense_mfma_block(const FastFwdArgs<float>& A
             w2[u] = tok ? w2[u] : 0.f;
             x2[u] = tok ? x2[u] : 0.f;
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(w2[u], x2[u], acc[0], 0, 0, 0);
-            const float wabs = fabsf(w2[u]);
-#pragma unroll
-            for (int q = 0; q < NM; ++q)
-                acc[1 + q] =
-                    __builtin_amdgcn_mfma_f32_32x32x2f32(wabs, flip(x2[u], (h2[u] >> q) & 1u), acc[1 + q], 0, 0, 0);
-        }
-        if (pointin) {
-            // point boxes away from zero: (W . I) x gains W+ x_point on z = 0 rows
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const float xp = ((h2[u] >> kPointBit) & 1u) ? x2[u] : 0.f;
-                accp = __builtin_amdgcn_mfma_f32_32x32x2f32(fmaxf(w2[u], 0.f), xp, accp, 0, 0, 0);
-            }
-        }
+        mfma_trip_32<NM, BF>(w2, x2, h2, pointin, acc, accp);
     }
     // add the waves' tiles (fixed order), one product at a time; wave w
     // finishes accumulator registers 4w .. 4w + 3
@@ -665,10 +725,10 @@ __device__ __forceinline__ void fwd_dense_mfma_block(const FastFwdArgs<float>& A
     }
 }
 
-template <int NM, int KW, bool UPD, bool MB>
+template <int NM, int KW, bool UPD, bool MB, bool BF>
 __global__ void __launch_bounds__(kWave * KW) k_fwd_dense_mfma(FastFwdArgs<float> A) {
     __shared__ float red[KW][16][kWave];
-    fwd_dense_mfma_block<NM, KW, UPD, MB>(A, blockIdx.x, blockIdx.y, blockIdx.z, red);
+    fwd_dense_mfma_block<NM, KW, UPD, MB, BF>(A, blockIdx.x, blockIdx.y, blockIdx.z, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -684,7 +744,7 @@ __global__ void __launch_bounds__(kWave * KW) k_fwd_dense_mfma(FastFwdArgs<float
 // register's state access is two 128-byte runs.
 // Grid (column tiles / (SPLITK ? 1 : KS), Cpad / 32), block (64, KS).
 // ---------------------------------------------------------------------------
-template <int NM, bool SPLITK, int KSZ, bool MB, int KW>  // KW: waves per block
+template <int NM, bool SPLITK, int KSZ, bool MB, int KW, bool BF = false>  // KW: waves per block; BF: BF16 operands
 __device__ __forceinline__ void fwd_conv_mfma_block(const FastFwdArgs<float>& A, int tile, int group,
                                                     float (*red)[16][kWave]) {
     constexpr int U = 4;  // steps of 2 taps per trip
@@ -750,23 +810,7 @@ __device__ __forceinline__ void fwd_conv_mfma_block(const FastFwdArgs<float>& A,
             h2[u] = okv[u] ? hv[u] : 0u;
         }
         if (k + 2 * U < t1) load(k + 2 * U);  // next trip's loads in flight during this trip
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(w2[u], x2[u], acc[0], 0, 0, 0);
-            const float wabs = fabsf(w2[u]);
-#pragma unroll
-            for (int q = 0; q < NM; ++q)
-                acc[1 + q] =
-                    __builtin_amdgcn_mfma_f32_32x32x2f32(wabs, flip(x2[u], (h2[u] >> q) & 1u), acc[1 + q], 0, 0, 0);
-        }
-        if (pointin) {
-            // point boxes away from zero: (W . I) x gains W+ x_point on z = 0 rows
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const float xp = ((h2[u] >> kPointBit) & 1u) ? x2[u] : 0.f;
-                accp = __builtin_amdgcn_mfma_f32_32x32x2f32(fmaxf(w2[u], 0.f), xp, accp, 0, 0, 0);
-            }
-        }
+        mfma_trip_32<NM, BF>(w2, x2, h2, pointin, acc, accp);
     }
 #pragma unroll
     for (int q = 0; q < NM; ++q)
@@ -824,12 +868,12 @@ __device__ __forceinline__ void fwd_conv_mfma_block(const FastFwdArgs<float>& A,
     }
 }
 
-template <int NM, bool SPLITK, int KSZ, bool MB, int KW>
+template <int NM, bool SPLITK, int KSZ, bool MB, int KW, bool BF>
 __global__ void __launch_bounds__(kWave * KW) k_fwd_conv_mfma(FastFwdArgs<float> A) {
     __shared__ float red[SPLITK ? KW : 1][16][kWave];
     int tile, group;
     xcd_tile(tile, group);
-    fwd_conv_mfma_block<NM, SPLITK, KSZ, MB, KW>(A, tile, group, red);
+    fwd_conv_mfma_block<NM, SPLITK, KSZ, MB, KW, BF>(A, tile, group, red);
 }
 
 // The products of a dense layer (k_fwd_dense_mfma, 8 waves per split) and
@@ -840,18 +884,18 @@ __global__ void __launch_bounds__(kWave * KW) k_fwd_conv_mfma(FastFwdArgs<float>
 // beside the convolution's instead of before or after them.  Grid
 // (nd + cgx cgy): blocks [0, nd) are the dense grid (dgx x dgy x ksplit, x
 // fastest), the rest the convolution's cgx x cgy grid.  Block (64, 8).
-template <int NM, int KSZ, bool MB, bool DU>  // DU: one split, the dense blocks update
+template <int NM, int KSZ, bool MB, bool DU, bool BF>  // DU: one split, the dense blocks update
 __global__ void __launch_bounds__(kWave * 8) k_fwd_conv_dense(FastFwdArgs<float> Ac, FastFwdArgs<float> Ad, int nd,
                                                               int dgx, int dgy, int cgx, int cgy) {
     __shared__ float red[8][16][kWave];
     const int lin = blockIdx.x;
     if (lin < nd) {
         const int bx = lin % dgx, rest = lin / dgx;
-        fwd_dense_mfma_block<NM, 8, DU, MB>(Ad, bx, rest % dgy, rest / dgy, red);
+        fwd_dense_mfma_block<NM, 8, DU, MB, BF>(Ad, bx, rest % dgy, rest / dgy, red);
     } else {
         int tile, group;
         xcd_tile_of((unsigned)(lin - nd), (unsigned)cgx, (unsigned)cgy, tile, group);
-        fwd_conv_mfma_block<NM, true, KSZ, MB, 8>(Ac, tile, group, red);
+        fwd_conv_mfma_block<NM, true, KSZ, MB, 8, BF>(Ac, tile, group, red);
     }
 }
 
@@ -867,7 +911,7 @@ __global__ void __launch_bounds__(kWave * 8) k_fwd_conv_dense(FastFwdArgs<float>
 // the taps as when launched alone, both through the same barriers; the
 // second one past the grid when nv is odd computes nothing it stores).
 // Block (64, 8).
-template <int NM, int KSC, int KSV, bool MB, bool DU>  // DU: one split, the dense blocks update
+template <int NM, int KSC, int KSV, bool MB, bool DU, bool BF>  // DU: one split, the dense blocks update
 __global__ void __launch_bounds__(kWave * 8) k_fwd_trio(FastFwdArgs<float> Av, FastFwdArgs<float> Ac,
                                                         FastFwdArgs<float> Ad, int nd, int dgx, int dgy, int nc,
                                                         int cgx, int cgy, int vgx, int vgy, int ip) {
@@ -875,7 +919,7 @@ __global__ void __launch_bounds__(kWave * 8) k_fwd_trio(FastFwdArgs<float> Av, F
     const int lin = blockIdx.x;
     if (lin < nd) {
         const int bx = lin % dgx, rest = lin / dgx;
-        fwd_dense_mfma_block<NM, 8, DU, MB>(Ad, bx, rest % dgy, rest / dgy, red);
+        fwd_dense_mfma_block<NM, 8, DU, MB, BF>(Ad, bx, rest % dgy, rest / dgy, red);
         return;
     }
     const int l = lin - nd;
@@ -883,7 +927,7 @@ __global__ void __launch_bounds__(kWave * 8) k_fwd_trio(FastFwdArgs<float> Av, F
     int tile, group;
     if (l % ip == 0 && l / ip < nc) {
         xcd_tile_of((unsigned)(l / ip), (unsigned)cgx, (unsigned)cgy, tile, group);
-        fwd_conv_mfma_block<NM, true, KSC, MB, 8>(Ac, tile, group, red);
+        fwd_conv_mfma_block<NM, true, KSC, MB, 8, BF>(Ac, tile, group, red);
     } else {
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
         const int half = wave >> 2;
@@ -1222,7 +1266,7 @@ __device__ __forceinline__ void stage_operands(const FastBwdArgs<float>& A, cons
 // channels, product r at float r RS), the weights [C_{k+1}][ks][ks][4] (then
 // one zero row) after them at float fboff; the sums go back to natural
 // order through lane shuffles before the finishing stores.
-template <int NM, int KSZ>
+template <int NM, int KSZ, bool BF = false>  // BF (4 x 4 kernels, stride 2): the 4 taps of a channel in one bf16 instruction
 __global__ void __launch_bounds__(kWave * 16) k_bwd_conv_m4(FastBwdArgs<float> A, BwdConvShape B) {
     typedef float floatx4 __attribute__((ext_vector_type(4)));
     constexpr int CB = 4;
@@ -1281,6 +1325,29 @@ __global__ void __launch_bounds__(kWave * 16) k_bwd_conv_m4(FastBwdArgs<float> A
         __syncthreads();
         for (int c = 0; c < cc; ++c) {
             const int co = cb + c;
+            if constexpr (BF && JC == 2) {
+                // the channel's 2 x 2 taps (jy, jx) in slots 2 jy + jx of one
+                // v_mfma_f32_4x4x4bf16_1k per product
+                float w4[4], o4[1 + NM][4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int ty = t >> 1, tx = t & 1;
+                    const int ky = ry + st * ty, kx = rx + st * tx;
+                    const bool tap = ky < ks && kx < ks;
+                    const int kk = tap ? (co * ks + ky) * ks + kx : nrow;  // zero row
+                    w4[t] = wl[kk * CB + (lane & 3)];
+                    const float* o = opnd + c * img + lb - ty * Wp - tx;
+#pragma unroll
+                    for (int r = 0; r <= NM; ++r) o4[r][t] = o[r * RS];
+                }
+                const shortx4 wb = bf16x4(w4);
+                acc = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(wb, bf16x4(o4[0]), acc, 0, 0, 0);
+                const shortx4 wa = bf16_abs(wb);
+#pragma unroll
+                for (int q = 0; q < NM; ++q)
+                    au[q] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(wa, bf16x4(o4[1 + q]), au[q], 0, 0, 0);
+                continue;
+            }
 #pragma unroll
             for (int jy = 0; jy < (JC > 0 ? JC : 1); ++jy) {
 #pragma unroll
@@ -1365,7 +1432,7 @@ __device__ __forceinline__ void finish_runs(const FastBwdArgs<float>& A, const f
     }
 }
 
-template <int NM, int KSZ, int STR, int NT>  // NT: column tiles of 16 per item
+template <int NM, int KSZ, int STR, int NT, bool BF = false>  // NT: column tiles of 16 per item; BF: BF16 operands
 __global__ void __launch_bounds__(kWave * 8) k_bwd_conv_mfma(FastBwdArgs<float> A, BwdConvShape B) {
     typedef float floatx4 __attribute__((ext_vector_type(4)));
     extern __shared__ float lds[];
@@ -1479,6 +1546,39 @@ __global__ void __launch_bounds__(kWave * 8) k_bwd_conv_mfma(FastBwdArgs<float> 
 #pragma unroll
                     for (int u = 0; u < U; ++u) w2[u] = wq[u];
                     if (c + U < cc) wload(c + U);
+                    if constexpr (BF) {
+                        // channels c + u0 .. c + u0 + 3 in the slots of one
+                        // v_mfma_f32_16x16x16bf16_1k (channels past cc: zero
+                        // weight, a staged channel's operand)
+#pragma unroll
+                        for (int u0 = 0; u0 < U; u0 += 4) {
+                            if (c + u0 >= cc) break;  // uniform
+                            float w4[4];
+                            int cofs[4];
+#pragma unroll
+                            for (int jj = 0; jj < 4; ++jj) {
+                                const bool cok = c + u0 + jj < cc;
+                                w4[jj] = cok ? w2[u0 + jj] : 0.f;
+                                cofs[jj] = min(c + u0 + jj, cc - 1) * img;
+                            }
+                            const shortx4 wb = bf16x4(w4);
+                            const shortx4 wa = bf16_abs(wb);
+#pragma unroll
+                            for (int j = 0; j < NT; ++j) {
+                                const float* o = opnd + lb[j];
+                                acc[j][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+                                    wb, bf16x4(o[cofs[0]], o[cofs[1]], o[cofs[2]], o[cofs[3]]), acc[j][0], 0, 0, 0);
+#pragma unroll
+                                for (int q = 0; q < NM; ++q) {
+                                    const float* oq = o + (1 + q) * RS;
+                                    acc[j][1 + q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+                                        wa, bf16x4(oq[cofs[0]], oq[cofs[1]], oq[cofs[2]], oq[cofs[3]]), acc[j][1 + q],
+                                        0, 0, 0);
+                                }
+                            }
+                        }
+                        continue;
+                    }
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
                         if (c + u >= cc) break;  // uniform
@@ -1516,6 +1616,41 @@ __global__ void __launch_bounds__(kWave * 8) k_bwd_conv_mfma(FastBwdArgs<float> 
 #pragma unroll
                 for (int u = 0; u < U; ++u) w2[u] = kt + 4 * u + r4 < kend ? wq[u] : 0.f;
                 if (kt + 4 * U < kend) wload(kt + 4 * U);
+                if constexpr (BF) {
+                    // steps u0 .. u0 + 3 in the slots of one bf16 instruction
+                    // (steps past kend: zero weight, the first tap's operand)
+#pragma unroll
+                    for (int u0 = 0; u0 < U; u0 += 4) {
+                        if (kt + 4 * u0 >= kend) break;  // uniform
+                        int li[NT][4];
+#pragma unroll
+                        for (int jj = 0; jj < 4; ++jj) {
+                            const int k = kt + 4 * (u0 + jj) + r4;
+                            const int kk = k < kend ? k : kbeg;
+                            const int col = kk / J2 - cb, rem = kk - (kk / J2) * J2;
+                            const int jy = rem / J, jx = rem - (rem / J) * J;
+                            const int ib = col * img - jy * Wp - jx;
+#pragma unroll
+                            for (int j = 0; j < NT; ++j) li[j][jj] = ib + qy[j] * Wp + qx[j];
+                        }
+                        const shortx4 wb = bf16x4(&w2[u0]);
+                        const shortx4 wa = bf16_abs(wb);
+#pragma unroll
+                        for (int j = 0; j < NT; ++j) {
+                            acc[j][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+                                wb, bf16x4(opnd[li[j][0]], opnd[li[j][1]], opnd[li[j][2]], opnd[li[j][3]]), acc[j][0],
+                                0, 0, 0);
+#pragma unroll
+                            for (int q = 0; q < NM; ++q) {
+                                const float* oq = opnd + (1 + q) * RS;
+                                acc[j][1 + q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+                                    wa, bf16x4(oq[li[j][0]], oq[li[j][1]], oq[li[j][2]], oq[li[j][3]]), acc[j][1 + q],
+                                    0, 0, 0);
+                            }
+                        }
+                    }
+                    continue;
+                }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     if (kt + 4 * u >= kend) break;  // uniform
@@ -1774,7 +1909,7 @@ __global__ void __launch_bounds__(kWave * KW) k_bwd_dense_pos(FastBwdArgs<T> A) 
 // one subproblem are one 16-bit piece of the bit array.  Grid
 // (ceil(Sa / 16), C_k P_k / 64), block (64, 4): wave w takes positions
 // [16 w, 16 w + 16) of the block's 64.
-template <int NM>
+template <int NM, bool BF = false>  // BF: BF16 operands (v_mfma_f32_16x16x16bf16_1k, 4 steps per instruction)
 __device__ __forceinline__ void bwd_dense_mfma_block(const FastBwdArgs<float>& A, int bx, int by) {
     typedef float floatx4 __attribute__((ext_vector_type(4)));
     constexpr int NA = NM > 0 ? NM : 1;
@@ -1811,7 +1946,7 @@ __device__ __forceinline__ void bwd_dense_mfma_block(const FastBwdArgs<float>& A
     for (int q = 0; q < NA; ++q) au[q] = floatx4{0.f, 0.f, 0.f, 0.f};
     // steps of 4 outputs of layer k+1 (lane group kq takes output i + kq), U
     // steps per trip, the next trip's loads in flight during this one
-    constexpr int U = 5;
+    constexpr int U = BF ? 4 : 5;
     float av[U], uv[U][NA], wv[U];
     const float* wcol = g.W + (long)c * L.P + p;
     auto load = [&](int i) {
@@ -1838,14 +1973,26 @@ __device__ __forceinline__ void bwd_dense_mfma_block(const FastBwdArgs<float>& A
             w2[u] = wv[u];
         }
         if (i + 4 * U < n1) load(i + 4 * U);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (i + 4 * u >= n1) break;  // uniform
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[u], w2[u], acc, 0, 0, 0);
-            const float wa = fabsf(w2[u]);
+        if constexpr (BF) {
+            // the trip's 4 steps in the slots of one instruction (steps past
+            // n1 hold zero operands)
+            const shortx4 wb = bf16x4(w2);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bf16x4(a2), wb, acc, 0, 0, 0);
+            const shortx4 wa = bf16_abs(wb);
 #pragma unroll
             for (int q = 0; q < NM; ++q)
-                au[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(u2[u][q], wa, au[q], 0, 0, 0);
+                au[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bf16x4(u2[0][q], u2[1][q], u2[2][q], u2[3][q]), wa,
+                                                                   au[q], 0, 0, 0);
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (i + 4 * u >= n1) break;  // uniform
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[u], w2[u], acc, 0, 0, 0);
+                const float wa = fabsf(w2[u]);
+#pragma unroll
+                for (int q = 0; q < NM; ++q)
+                    au[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(u2[u][q], wa, au[q], 0, 0, 0);
+            }
         }
     }
     uint16_t* xb16 = reinterpret_cast<uint16_t*>(A.nk.xbits);
@@ -1876,9 +2023,9 @@ __device__ __forceinline__ void bwd_dense_mfma_block(const FastBwdArgs<float>& A
     }
 }
 
-template <int NM>
+template <int NM, bool BF>
 __global__ void __launch_bounds__(kWave * 4) k_bwd_dense_mfma(FastBwdArgs<float> A) {
-    bwd_dense_mfma_block<NM>(A, blockIdx.x, blockIdx.y);
+    bwd_dense_mfma_block<NM, BF>(A, blockIdx.x, blockIdx.y);
 }
 
 // The column-mapped dense backward into the last ReLU layer (k_bwd_dense
@@ -1890,7 +2037,7 @@ __global__ void __launch_bounds__(kWave * 4) k_bwd_dense_mfma(FastBwdArgs<float>
 // Grid (na + mgx mgy): blocks [0, na) are the column kernel's agx x agy grid,
 // the rest the matrix-core kernel's mgx x mgy grid (x fastest).  Block
 // (64, 4).
-template <int NMB>
+template <int NMB, bool BF>
 __global__ void __launch_bounds__(kWave * 4) k_bwd_dense_pair(FastBwdArgs<float> Aa, FastBwdArgs<float> Ab, int na,
                                                               int agx, int agy, int mgx) {
     static_assert(KS == 4, "both kernels run 4 waves per block");
@@ -1902,7 +2049,7 @@ __global__ void __launch_bounds__(kWave * 4) k_bwd_dense_pair(FastBwdArgs<float>
         bwd_dense_block<float, 0, 8, true>(Aa, tile, group, red);
     } else {
         const int l2 = lin - na;
-        bwd_dense_mfma_block<NMB>(Ab, l2 % mgx, l2 / mgx);
+        bwd_dense_mfma_block<NMB, BF>(Ab, l2 % mgx, l2 / mgx);
     }
 }
 

@@ -10,7 +10,7 @@
 namespace asd {
 
 // Iteration forward pass of ReLU layer k with NM active masks.
-template <typename T, int NM, bool MB>
+template <typename T, int NM, bool MB, bool BF>
 asd_status fwd_fast_impl(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t st) {
     FastFwdArgs<T> a = fwd_args<T>(P, k, NM, sa);
     const LayerGeo& g = a.g;
@@ -32,11 +32,11 @@ asd_status fwd_fast_impl(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t
         const long ntiles = (g.out.cols + 31) / 32;
         dim3 grid((unsigned)ntiles, (unsigned)(a.Cpad / 32));
         if (P->fwd_kw[k] == 8) {
-            if (g.ksz == 4) hipLaunchKernelGGL((k_fwd_conv_mfma<NM, true, 4, MB, 8>), grid, dim3(kWave, 8), 0, st, a);
-            else hipLaunchKernelGGL((k_fwd_conv_mfma<NM, true, 0, MB, 8>), grid, dim3(kWave, 8), 0, st, a);
+            if (g.ksz == 4) hipLaunchKernelGGL((k_fwd_conv_mfma<NM, true, 4, MB, 8, BF>), grid, dim3(kWave, 8), 0, st, a);
+            else hipLaunchKernelGGL((k_fwd_conv_mfma<NM, true, 0, MB, 8, BF>), grid, dim3(kWave, 8), 0, st, a);
         } else {
-            if (g.ksz == 4) hipLaunchKernelGGL((k_fwd_conv_mfma<NM, true, 4, MB, 4>), grid, dim3(kWave, 4), 0, st, a);
-            else hipLaunchKernelGGL((k_fwd_conv_mfma<NM, true, 0, MB, 4>), grid, dim3(kWave, 4), 0, st, a);
+            if (g.ksz == 4) hipLaunchKernelGGL((k_fwd_conv_mfma<NM, true, 4, MB, 4, BF>), grid, dim3(kWave, 4), 0, st, a);
+            else hipLaunchKernelGGL((k_fwd_conv_mfma<NM, true, 0, MB, 4, BF>), grid, dim3(kWave, 4), 0, st, a);
         }
         (void)CB;
         LAUNCH_CHECK();
@@ -45,13 +45,13 @@ asd_status fwd_fast_impl(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t
     dim3 grid((unsigned)((P->Sa + 31) / 32), (unsigned)(a.Cpad / 32), (unsigned)a.ksplit);
     if (a.ksplit == 1) {
         // one split: the product blocks update their neurons themselves
-        if (P->fwd_kw[k] == 8) hipLaunchKernelGGL((k_fwd_dense_mfma<NM, 8, true, MB>), grid, dim3(kWave, 8), 0, st, a);
-        else hipLaunchKernelGGL((k_fwd_dense_mfma<NM, 4, true, MB>), grid, dim3(kWave, 4), 0, st, a);
+        if (P->fwd_kw[k] == 8) hipLaunchKernelGGL((k_fwd_dense_mfma<NM, 8, true, MB, BF>), grid, dim3(kWave, 8), 0, st, a);
+        else hipLaunchKernelGGL((k_fwd_dense_mfma<NM, 4, true, MB, BF>), grid, dim3(kWave, 4), 0, st, a);
         LAUNCH_CHECK();
         return ASD_OK;
     }
-    if (P->fwd_kw[k] == 8) hipLaunchKernelGGL((k_fwd_dense_mfma<NM, 8, false, MB>), grid, dim3(kWave, 8), 0, st, a);
-    else hipLaunchKernelGGL((k_fwd_dense_mfma<NM, 4, false, MB>), grid, dim3(kWave, 4), 0, st, a);
+    if (P->fwd_kw[k] == 8) hipLaunchKernelGGL((k_fwd_dense_mfma<NM, 8, false, MB, BF>), grid, dim3(kWave, 8), 0, st, a);
+    else hipLaunchKernelGGL((k_fwd_dense_mfma<NM, 4, false, MB, BF>), grid, dim3(kWave, 4), 0, st, a);
     LAUNCH_CHECK();
     hipLaunchKernelGGL((k_fwd_dense_epi<T, NM, MB>), dim3((unsigned)((P->Sa + 255) / 256), (unsigned)g.out.C), dim3(256),
                        0, st, a);
@@ -61,13 +61,14 @@ asd_status fwd_fast_impl(asd_plan* P, int k, const StepArgsT<T>& sa, hipStream_t
 
 template <int NM>
 asd_status fwd_fast_nm(asd_plan* P, int k, const StepArgsT<float>& sa, bool mb, hipStream_t st) {
-    return mb ? fwd_fast_impl<float, NM, true>(P, k, sa, st) : fwd_fast_impl<float, NM, false>(P, k, sa, st);
+    if (bf16_forward(P)) return fwd_fast_impl<float, NM, true, true>(P, k, sa, st);
+    return mb ? fwd_fast_impl<float, NM, true, false>(P, k, sa, st) : fwd_fast_impl<float, NM, false, false>(P, k, sa, st);
 }
 
 // The forward pass of convolutional layer kc on the matrix cores (8 waves
 // per tile) and the products of dense layer kd (8 waves per split) in one
 // launch (k_fwd_conv_dense), then the dense layer's epilogue.
-template <int NM, bool MB>
+template <int NM, bool MB, bool BF>
 asd_status fwd_fused_impl(asd_plan* P, int kc, int kd, const StepArgsT<float>& sa, hipStream_t st) {
     const FastFwdArgs<float> ac = fwd_args<float>(P, kc, NM, sa);
     const FastFwdArgs<float> ad = fwd_args<float>(P, kd, NM, sa);
@@ -77,11 +78,11 @@ asd_status fwd_fused_impl(asd_plan* P, int kc, int kd, const StepArgsT<float>& s
     const bool du = ad.ksplit == 1;  // one split: the dense blocks update, no epilogue
     ProfScope ps(P, st, ASD_K_FORWARD_PASS, std::min(kc, kd));
     if (ac.g.ksz == 4) {
-        if (du) hipLaunchKernelGGL((k_fwd_conv_dense<NM, 4, MB, true>), grid, dim3(kWave, 8), 0, st, ac, ad, nd, dgx, dgy, cgx, cgy);
-        else hipLaunchKernelGGL((k_fwd_conv_dense<NM, 4, MB, false>), grid, dim3(kWave, 8), 0, st, ac, ad, nd, dgx, dgy, cgx, cgy);
+        if (du) hipLaunchKernelGGL((k_fwd_conv_dense<NM, 4, MB, true, BF>), grid, dim3(kWave, 8), 0, st, ac, ad, nd, dgx, dgy, cgx, cgy);
+        else hipLaunchKernelGGL((k_fwd_conv_dense<NM, 4, MB, false, BF>), grid, dim3(kWave, 8), 0, st, ac, ad, nd, dgx, dgy, cgx, cgy);
     } else {
-        if (du) hipLaunchKernelGGL((k_fwd_conv_dense<NM, 0, MB, true>), grid, dim3(kWave, 8), 0, st, ac, ad, nd, dgx, dgy, cgx, cgy);
-        else hipLaunchKernelGGL((k_fwd_conv_dense<NM, 0, MB, false>), grid, dim3(kWave, 8), 0, st, ac, ad, nd, dgx, dgy, cgx, cgy);
+        if (du) hipLaunchKernelGGL((k_fwd_conv_dense<NM, 0, MB, true, BF>), grid, dim3(kWave, 8), 0, st, ac, ad, nd, dgx, dgy, cgx, cgy);
+        else hipLaunchKernelGGL((k_fwd_conv_dense<NM, 0, MB, false, BF>), grid, dim3(kWave, 8), 0, st, ac, ad, nd, dgx, dgy, cgx, cgy);
     }
     LAUNCH_CHECK();
     if (du) return ASD_OK;
@@ -94,7 +95,7 @@ asd_status fwd_fused_impl(asd_plan* P, int kc, int kd, const StepArgsT<float>& s
 // The forward pass of VALU-mapped convolutional layer kv, matrix-core
 // convolutional layer kc and dense layer kd in one launch (k_fwd_trio), then
 // the dense layer's epilogue.
-template <int NM, bool MB>
+template <int NM, bool MB, bool BF>
 asd_status fwd_trio_impl(asd_plan* P, int kv, int kc, int kd, const StepArgsT<float>& sa, hipStream_t st) {
     const FastFwdArgs<float> av = fwd_args<float>(P, kv, NM, sa);
     const FastFwdArgs<float> ac = fwd_args<float>(P, kc, NM, sa);
@@ -113,10 +114,10 @@ asd_status fwd_trio_impl(asd_plan* P, int kv, int kc, int kd, const StepArgsT<fl
 #define ASD_TRIO_LAUNCH(KC, KV)                                                                                       \
     do {                                                                                                              \
         if (du)                                                                                                       \
-            hipLaunchKernelGGL((k_fwd_trio<NM, KC, KV, MB, true>), grid, dim3(kWave, 8), 0, st, av, ac, ad, nd, dgx, \
+            hipLaunchKernelGGL((k_fwd_trio<NM, KC, KV, MB, true, BF>), grid, dim3(kWave, 8), 0, st, av, ac, ad, nd, dgx, \
                                dgy, nc, cgx, cgy, vgx, vgy, ip);                                                      \
         else                                                                                                          \
-            hipLaunchKernelGGL((k_fwd_trio<NM, KC, KV, MB, false>), grid, dim3(kWave, 8), 0, st, av, ac, ad, nd, dgx, \
+            hipLaunchKernelGGL((k_fwd_trio<NM, KC, KV, MB, false, BF>), grid, dim3(kWave, 8), 0, st, av, ac, ad, nd, dgx, \
                                dgy, nc, cgx, cgy, vgx, vgy, ip);                                                      \
     } while (0)
     if (c4 && v4) ASD_TRIO_LAUNCH(4, 4);
@@ -134,16 +135,19 @@ asd_status fwd_trio_impl(asd_plan* P, int kv, int kc, int kd, const StepArgsT<fl
 
 template <int NM>
 asd_status fwd_fused_nm(asd_plan* P, int kc, int kd, const StepArgsT<float>& sa, bool mb, hipStream_t st) {
-    return mb ? fwd_fused_impl<NM, true>(P, kc, kd, sa, st) : fwd_fused_impl<NM, false>(P, kc, kd, sa, st);
+    if (bf16_forward(P)) return fwd_fused_impl<NM, true, true>(P, kc, kd, sa, st);
+    return mb ? fwd_fused_impl<NM, true, false>(P, kc, kd, sa, st) : fwd_fused_impl<NM, false, false>(P, kc, kd, sa, st);
 }
 
 template <int NM>
 asd_status fwd_trio_nm(asd_plan* P, int kv, int kc, int kd, const StepArgsT<float>& sa, bool mb, hipStream_t st) {
-    return mb ? fwd_trio_impl<NM, true>(P, kv, kc, kd, sa, st) : fwd_trio_impl<NM, false>(P, kv, kc, kd, sa, st);
+    if (bf16_forward(P)) return fwd_trio_impl<NM, true, true>(P, kv, kc, kd, sa, st);
+    return mb ? fwd_trio_impl<NM, true, false>(P, kv, kc, kd, sa, st)
+              : fwd_trio_impl<NM, false, false>(P, kv, kc, kd, sa, st);
 }
 
-template <int NM>
-asd_status bwd_pair_nm(asd_plan* P, hipStream_t st) {
+template <int NM, bool BF>
+asd_status bwd_pair_impl(asd_plan* P, hipStream_t st) {
     const int ka = P->n - 1, kb = P->n - 2;
     const FastBwdArgs<float> aa = bwd_args<float>(P, ka, 0);
     const FastBwdArgs<float> ab = bwd_args<float>(P, kb, NM);
@@ -152,15 +156,20 @@ asd_status bwd_pair_nm(asd_plan* P, hipStream_t st) {
     const int agx = (int)((La.cols + kWave - 1) / kWave), agy = (La.C + 7) / 8, na = agx * agy;
     const int mgx = (P->Sa + 15) / 16, mgy = Lb.C * (Lb.P / kWave);
     ProfScope ps(P, st, ASD_K_BACKWARD_PAIR, kb);
-    hipLaunchKernelGGL((k_bwd_dense_pair<NM>), dim3((unsigned)(na + mgx * mgy)), dim3(kWave, 4), 0, st, aa, ab, na, agx,
+    hipLaunchKernelGGL((k_bwd_dense_pair<NM, BF>), dim3((unsigned)(na + mgx * mgy)), dim3(kWave, 4), 0, st, aa, ab, na, agx,
                        agy, mgx);
     LAUNCH_CHECK();
     return ASD_OK;
 }
 
-// Iteration backward pass into neuron layer k; NM = masks of layer k+1.
 template <int NM>
-asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
+asd_status bwd_pair_nm(asd_plan* P, hipStream_t st) {
+    return bf16_backward(P) ? bwd_pair_impl<NM, true>(P, st) : bwd_pair_impl<NM, false>(P, st);
+}
+
+// Iteration backward pass into neuron layer k; NM = masks of layer k+1.
+template <int NM, bool BF>
+asd_status bwd_fast_impl(asd_plan* P, int k, hipStream_t st) {
     using T = float;
     FastBwdArgs<T> a;
     memset(&a, 0, sizeof(a));
@@ -225,8 +234,8 @@ asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
             ProfScope ps(P, st, ASD_K_BACKWARD, k);
             dim3 grid((unsigned)P->Sa, (unsigned)((L.C + 15) / 16));
             if (g.ksz == 4 && g.stride == 2) {
-                if (NT == 2) hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 4, 2, 2>), grid, dim3(kWave, sh.NW), dyn, st, a, sh);
-                else hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 4, 2, 4>), grid, dim3(kWave, sh.NW), dyn, st, a, sh);
+                if (NT == 2) hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 4, 2, 2, BF>), grid, dim3(kWave, sh.NW), dyn, st, a, sh);
+                else hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 4, 2, 4, BF>), grid, dim3(kWave, sh.NW), dyn, st, a, sh);
             } else {
                 if (NT == 2) hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 0, 0, 2>), grid, dim3(kWave, sh.NW), dyn, st, a, sh);
                 else hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 0, 0, 4>), grid, dim3(kWave, sh.NW), dyn, st, a, sh);
@@ -257,7 +266,7 @@ asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
                 const size_t dm4 = ((size_t)sh.fboff + (size_t)(g.out.C * g.ksz * g.ksz + 1) * 4) * sizeof(float);
                 if (dm4 <= 64 * 1024) {
                     const dim3 bm4(kWave, L.P / kWave);
-                    if (g.ksz == 4) hipLaunchKernelGGL((k_bwd_conv_m4<NM, 4>), dim3((unsigned)P->Sa), bm4, dm4, st, a, sh);
+                    if (g.ksz == 4) hipLaunchKernelGGL((k_bwd_conv_m4<NM, 4, BF>), dim3((unsigned)P->Sa), bm4, dm4, st, a, sh);
                     else hipLaunchKernelGGL((k_bwd_conv_m4<NM, 0>), dim3((unsigned)P->Sa), bm4, dm4, st, a, sh);
                     LAUNCH_CHECK();
                     return ASD_OK;
@@ -285,7 +294,7 @@ asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
         if (L.P % kWave == 0 && P->bwd_pos[k] == 2) {
             // matrix cores: 16 subproblems x 64 positions per block
             dim3 grid((unsigned)((P->Sa + 15) / 16), (unsigned)(L.C * (L.P / kWave)));
-            hipLaunchKernelGGL((k_bwd_dense_mfma<NM>), grid, dim3(kWave, 4), 0, st, a);
+            hipLaunchKernelGGL((k_bwd_dense_mfma<NM, BF>), grid, dim3(kWave, 4), 0, st, a);
             LAUNCH_CHECK();
             return ASD_OK;
         }
@@ -310,6 +319,11 @@ asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
     }
     LAUNCH_CHECK();
     return ASD_OK;
+}
+
+template <int NM>
+asd_status bwd_fast_nm(asd_plan* P, int k, hipStream_t st) {
+    return bf16_backward(P) ? bwd_fast_impl<NM, true>(P, k, st) : bwd_fast_impl<NM, false>(P, k, st);
 }
 
 template asd_status fwd_fast_nm<ASD_NM>(asd_plan*, int, const StepArgsT<float>&, bool, hipStream_t);

@@ -136,6 +136,18 @@ template <> inline float* CV<float>(asd_plan* P) { return P->cvecf; }
 template <> inline double* CV<double>(asd_plan* P) { return P->cvecd; }
 
 inline bool is64(const asd_plan* P) { return P->prm.precision == ASD_PREC_FP64; }
+// Adam moments stored as BF16 pairs (the mixed and the BF16 modes)
+inline bool bf16_moments(const asd_plan* P) {
+    return P->prm.precision == ASD_PREC_MIXED || P->prm.precision == ASD_PREC_BF16 ||
+           P->prm.precision == ASD_PREC_BF16_ALL;
+}
+// BF16 operands in the forward matrix-core products (the supergradient's
+// W x* and |W| (sigma . x*)), and in the transposed ones (f, which decides
+// the minimiser)
+inline bool bf16_forward(const asd_plan* P) {
+    return P->prm.precision == ASD_PREC_BF16 || P->prm.precision == ASD_PREC_BF16_ALL;
+}
+inline bool bf16_backward(const asd_plan* P) { return P->prm.precision == ASD_PREC_BF16_ALL; }
 
 // Event pair around one launch when profiling is on.
 struct ProfScope {

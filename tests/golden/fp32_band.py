@@ -3,7 +3,8 @@ run (Algorithm 1 after Algorithm 3) on the end-to-end test workloads,
 measured with the FP64 oracle alone.
 
 For every subproblem of each workload the oracle runs the workload's
-schedule in FP64 (the reference run) and in two models of an FP32 run:
+schedule in FP64 (the reference run) and in models of reduced-precision
+runs:
 
   storage  every dual, moment and mask constant stored as a float32 value
            after each iteration (the rounding of the state alone: a lower
@@ -13,12 +14,18 @@ schedule in FP64 (the reference run) and in two models of an FP32 run:
            to f_k and g_k before the inner minimisation and to every
            supergradient entry (the rounding scale of an entry is the sum of
            the magnitudes of the terms that form it: the scale the
-           fixed-dual parity tests use); two seeds.
+           fixed-dual parity tests use); two seeds;
+  noise_bf16      the BF16-moment storage with errors of 2^-8 units
+                  on the supergradient (BF16 operands in the forward
+                  products), f and g as in noise;
+  noise_bf16_all  and also errors of 2^-8 units on f and g (BF16 operands
+                  in the transposed products).
+
+  noise_mixed     the noise model with the Adam moments stored as bfloat16
+                  (the mixed mode's storage).
 
 Recorded per workload, for each model: the largest and the mean over the
-subproblems (and seeds) of |d_fp64 - d_model| / max(1, |d_fp64|), and the
-same for the noise model with the Adam moments stored as bfloat16 (the
-mixed mode's storage).  The runs part at near-ties of the minimiser, so the
+subproblems (and seeds) of |d_fp64 - d_model| / max(1, |d_fp64|).  The runs part at near-ties of the minimiser, so the
 distances are heavy-tailed: the largest needs every subproblem.
 
 Run from the repository root: python -m tests.golden.fp32_band
@@ -38,25 +45,28 @@ from tests import helpers as H  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "fp32_band.json")
 EPS32 = 2.0 ** -24
+EPS_BF16 = 2.0 ** -8  # one BF16 rounding of both operands of a product
 SEEDS = (0, 1)
 
 
-def noisy_solve(p, prm, rng):
+def noisy_solve(p, prm, rng, eps_fg=EPS32, eps_grad=EPS32):
     """The oracle's schedule (Algorithm 3, then Algorithm 1 with additions),
-    with the errors of the noise model injected and the state stored as
-    float32 after every iteration; returns d_B at the final duals."""
+    with the errors of the noise model injected (eps_fg on f and g, eps_grad
+    on the supergradient, in units of each entry's rounding scale) and the
+    state stored as float32 after every iteration; returns d_B at the final
+    duals."""
     st = O.zero_state(p)
 
     def iteration(t, lr, as_phase):
         f, g, _ = O.dual_functions(p, st)
-        f = [fk + rng.uniform(-1, 1, fk.shape) * EPS32 * (1 + H.f_row_scale(p, st, k)) for k, fk in enumerate(f)]
-        g = [gk + rng.uniform(-1, 1, gk.shape) * EPS32 * (1 + H.g_row_scale(p, st, k + 1)) for k, gk in enumerate(g)]
+        f = [fk + rng.uniform(-1, 1, fk.shape) * eps_fg * (1 + H.f_row_scale(p, st, k)) for k, fk in enumerate(f)]
+        g = [gk + rng.uniform(-1, 1, gk.shape) * eps_fg * (1 + H.g_row_scale(p, st, k + 1)) for k, gk in enumerate(g)]
         x, z = O.inner_min(p, f, g)
         if as_phase and O.is_addition_iter(t, prm, len(st.masks[0])):
             O.add_masks(p, st, x, z)
         sg = O.supergradient(p, st, x, z)
         for k in range(1, p.n):
-            sc = EPS32 * (1 + H.grad_row_scale(p, st, x, k))
+            sc = eps_grad * (1 + H.grad_row_scale(p, st, x, k))
             for name in ("alpha", "beta0", "beta1"):
                 sg[name][k - 1] = sg[name][k - 1] + rng.uniform(-1, 1, sc.shape) * sc
             sg["masks"][k - 1] = [a + rng.uniform(-1, 1, sc.shape) * sc for a in sg["masks"][k - 1]]
@@ -89,21 +99,26 @@ def main():
         prm_m.adam = O.AdamConsts(prm_m.adam.beta1, prm_m.adam.beta2, prm_m.adam.eps, moments="bf16")
         ref = np.array([O.solve(p, prm).bound for p in probs])
         sto = np.array([O.solve(p, prm32).bound for p in probs])
-        noi, mix = [], []
+        noi, mix, bfw, bfa = [], [], [], []
         for seed in SEEDS:
             rng = np.random.default_rng(seed)
             noi.append([noisy_solve(p, prm, rng) for p in probs])
             rng = np.random.default_rng(100 + seed)
             mix.append([noisy_solve(p, prm_m, rng) for p in probs])
-        res[w.name] = {"storage": rel(ref, sto),
-                       "noise": rel(np.tile(ref, (len(SEEDS), 1)), noi),
-                       "noise_mixed": rel(np.tile(ref, (len(SEEDS), 1)), mix),
+            rng = np.random.default_rng(200 + seed)
+            bfw.append([noisy_solve(p, prm_m, rng, EPS32, EPS_BF16) for p in probs])
+            rng = np.random.default_rng(300 + seed)
+            bfa.append([noisy_solve(p, prm_m, rng, EPS_BF16, EPS_BF16) for p in probs])
+        refs = np.tile(ref, (len(SEEDS), 1))
+        res[w.name] = {"storage": rel(ref, sto), "noise": rel(refs, noi), "noise_mixed": rel(refs, mix),
+                       "noise_bf16": rel(refs, bfw), "noise_bf16_all": rel(refs, bfa),
                        "subproblems": len(probs), "seeds": len(SEEDS)}
         print(w.name, res[w.name], flush=True)
     doc = {"what": "relative distance of FP32-run models from the FP64 oracle run, per workload "
                    "(storage: state stored as float32; noise: plus errors of one float32 unit of each "
                    "entry's rounding scale on f, g and the supergradient; noise_mixed: the noise model "
-                   "with bfloat16 moments)",
+                   "with bfloat16 moments; noise_bf16: and errors of 2^-8 units on the supergradient; "
+                   "noise_bf16_all: and on f and g)",
            "script": "tests/golden/fp32_band.py", "workloads": res}
     with open(OUT, "w") as fh:
         json.dump(doc, fh, indent=1)

@@ -15,18 +15,18 @@ runs:
            supergradient entry (the rounding scale of an entry is the sum of
            the magnitudes of the terms that form it: the scale the
            fixed-dual parity tests use); two seeds;
-  noise_bf16      the BF16-moment storage with errors of 2^-8 units
-                  on the supergradient (BF16 operands in the forward
-                  products), f and g as in noise;
+  noise_mixed     the noise model with the Adam moments stored as bfloat16
+                  (the mixed mode's storage);
+  noise_bf16      the mixed model with errors of 2^-8 units on the
+                  supergradient (BF16 operands in the forward products), f
+                  and g as in noise;
   noise_bf16_all  and also errors of 2^-8 units on f and g (BF16 operands
                   in the transposed products).
 
-  noise_mixed     the noise model with the Adam moments stored as bfloat16
-                  (the mixed mode's storage).
-
 Recorded per workload, for each model: the largest and the mean over the
-subproblems (and seeds) of |d_fp64 - d_model| / max(1, |d_fp64|).  The runs part at near-ties of the minimiser, so the
-distances are heavy-tailed: the largest needs every subproblem.
+subproblems (and seeds) of |d_fp64 - d_model| / max(1, |d_fp64|).  The runs
+part at near-ties of the minimiser, so the distances are heavy-tailed: the
+largest needs every subproblem.
 
 Run from the repository root: python -m tests.golden.fp32_band
 """

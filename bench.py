@@ -305,6 +305,43 @@ def ragged_leg(A, np, torch, WL):
             "verified": [int(np.sum(l > 0)) for l in lbs], "tuning": tunings}
 
 
+def margin_leg(A, np, torch, WL, tuning, modes):
+    """Bound accuracy of each precision form where part of the subdomains
+    verify: the CIFAR Wide net, 512 subdomains of the network's top class
+    against each other class in turn, eps 0.5/255 (cifar_margin_config),
+    the benchmark's schedule and kernel choices.  Per form: subdomains
+    verified (bound > 0), mean bound, and against the FP32 form the mean of
+    d_FP32 - d_form; equal accuracy = that mean <= 1e-4 of the mean |d_FP32|
+    and no fewer verified."""
+    w = WL.cifar_margin_config()
+    dev = "cuda:0"
+    t32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=dev)
+    net = A.Net(w.layers, device=dev)
+    lh0, uh0 = net.interval_bounds(t32(w.l0[:1]), t32(w.u0[:1]))
+    L, U = WL.subdomain_bounds([a[0].cpu().numpy() for a in lh0[:-1]], [a[0].cpu().numpy() for a in uh0[:-1]],
+                               w.fix_draws, w.S)
+    b = (t32(w.l0), t32(w.u0), [t32(a) for a in L], [t32(a) for a in U], t32(w.c))
+    out = {"workload": f"{w.name}: the Wide net, {w.S} subdomains (0-20 fixed ReLUs) of the top class against "
+                       f"each other class in turn, eps {w.meta['eps'] * 255:.2f}/255"}
+    lbs = {}
+    for name, mode in [("fp32", A.ASD_PREC_FP32)] + modes:
+        plan = A.Plan(net, w.S, A.params_from_schedule(w.schedule, mode))
+        if tuning is not None:
+            plan.set_tuning(tuning)
+        lbs[name] = plan.solve(*b).cpu().numpy()
+        del plan
+    ref = lbs["fp32"]
+    scale = float(np.mean(np.abs(ref)))
+    for name, lb in lbs.items():
+        e = {"verified": int(np.sum(lb > 0)), "bound_mean": float(np.mean(lb))}
+        if name != "fp32":
+            e["mean_fp32_minus_this"] = float(np.mean(ref - lb))
+            e["equal_accuracy"] = bool(np.mean(ref - lb) <= 1e-4 * scale and e["verified"] >= int(np.sum(ref > 0)))
+        out[name] = e
+    out["accuracy_scale"] = scale
+    return out
+
+
 def mnist_leg(A, np, torch, WL, reps=5):
     """The MNIST-shaped MLP workload (784-100-100-100-10, 9 logit
     differences, 500 Big-M + 500 Active Set iterations): whole solves timed
@@ -675,6 +712,11 @@ def main():
             bf16 = res
         else:
             bf16_all = res
+    margin = None
+    if reduced:
+        print("[bench] accuracy where subdomains verify", file=sys.stderr, flush=True)
+        plan = None
+        margin = margin_leg(A, np, torch, WL, tuning, [(nm, md) for nm, md, _ in reduced])
     ragged = None
     if not args.no_ragged:
         print("[bench] ragged two-net batch", file=sys.stderr, flush=True)
@@ -726,6 +768,7 @@ def main():
         "mixed": mixed,
         "bf16": bf16,
         "bf16_all": bf16_all,
+        "accuracy_where_verifiable": margin,
         "ragged": ragged,
         "mnist": mnist,
         "adjoint": adjoint,

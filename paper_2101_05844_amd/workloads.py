@@ -305,6 +305,56 @@ def cifar_conv_config(seed: int = 1002, S: int = 512, specs=None, max_fixed: int
                     meta={"seed": seed, "eps": eps, "true_class": t, "target": j})
 
 
+def network_output(layers: Sequence[Layer], x0: np.ndarray) -> np.ndarray:
+    """Plain forward pass of the network (FP64) at one input: picks the
+    property of a workload, outside the method."""
+    x = np.asarray(x0, dtype=np.float64)
+    for i, L in enumerate(layers):
+        if L.kind == "dense":
+            y = L.W.astype(np.float64) @ x.reshape(-1) + L.b
+        else:
+            sp = L.spec
+            xin = x.reshape(sp.c_in, sp.h_in, sp.w_in)
+            xp = np.pad(xin, ((0, 0), (sp.pad, sp.pad), (sp.pad, sp.pad)))
+            y = np.zeros((sp.c_out, sp.h_out, sp.w_out))
+            W = L.W.astype(np.float64).reshape(sp.c_out, sp.c_in, sp.k, sp.k)
+            for ky in range(sp.k):
+                for kx in range(sp.k):
+                    patch = xp[:, ky:ky + sp.stride * sp.h_out:sp.stride, kx:kx + sp.stride * sp.w_out:sp.stride]
+                    y += np.einsum("oc,chw->ohw", W[:, :, ky, kx], patch)
+            y += L.b.astype(np.float64)[:, None, None]
+            y = y.reshape(-1)
+        x = np.maximum(y, 0.0) if i + 1 < len(layers) else y
+    return x
+
+
+def cifar_margin_config(seed: int = 1006, S: int = 512, eps: float = 0.5 / 255.0, max_fixed: int = 20,
+                        net_seed: int = 1002) -> Workload:
+    """Accuracy workload on the CIFAR "Wide" net of cifar_conv_config (same
+    weights): a centre U[0,1]^3072 whose top class t under the network is
+    the true class, a smaller radius eps (so that part of the subdomains can
+    be verified, bound > 0), and S branch-and-bound subdomains fixing
+    U{0..max_fixed} ambiguous ReLUs each; subdomain s bounds the logit
+    difference of t against the (1 + s mod 9)-th class by output, so the
+    margins at the centre span easy and hard properties."""
+    layers = draw_layers(CIFAR_WIDE_SPECS, np.random.default_rng(net_seed))
+    rng = np.random.default_rng(seed)
+    centre = rng.uniform(0.0, 1.0, size=3 * 32 * 32)
+    out = network_output(layers, centre)
+    order = np.argsort(-out)
+    t = int(order[0])
+    targets = [int(order[1 + s % 9]) for s in range(S)]
+    l0, u0 = linf_box(centre, eps, (0.0, 1.0))
+    c = np.concatenate([logit_difference_rows(10, t, [j]) for j in targets], axis=0)
+    n_relu = sum(spec_sizes(sp)[1] for sp in CIFAR_WIDE_SPECS[:-1])
+    draws = draw_fixes(rng, S, n_relu, max_fixed)
+    sched = Schedule(bigm_iters=180, as_iters=500, add_every=450, add_count=2, max_masks=7)
+    return Workload("cifar-wide-margin", layers, np.repeat(l0[None], S, 0), np.repeat(u0[None], S, 0),
+                    c, sched, fix_draws=draws,
+                    meta={"seed": seed, "net_seed": net_seed, "eps": eps, "true_class": t,
+                          "margins_at_centre": [float(out[t] - out[int(order[1 + i])]) for i in range(9)]})
+
+
 def adjoint_config(seed: int = 1004, n_inputs: int = 256, net_seed: int = 1002) -> Workload:
     """Bound-gradient workload: the CIFAR "Wide" net of cifar_conv_config
     (same weights), n_inputs centres U[0,1]^3072 with eps 2/255 clipped to

@@ -643,3 +643,22 @@ def test_printed_tie_rules():
             assert np.array_equal(x[k], p.lu(k)[1]), k
         for k in range(1, p.n):
             assert np.all(g[k - 1] == 0) and np.all(z[k - 1] == 1.0), k
+
+
+def test_margin_workload_property():
+    """The accuracy workload bounds the network's top class at its centre
+    against every other class in turn: the generator's forward pass agrees
+    with the oracle's network evaluation, and each objective row is
+    e_top - e_j with j != top, every other class used."""
+    w = WL.cifar_margin_config(S=18)
+    ops = O.ops_from_workload_layers(w.layers)
+    centre = (w.l0[0].astype(np.float64) + w.u0[0].astype(np.float64)) / 2
+    ref = O.network_output(ops, centre)
+    got = WL.network_output(w.layers, centre)
+    assert np.allclose(got, ref, rtol=1e-10, atol=1e-10)
+    t = w.meta["true_class"]
+    js = set()
+    for row in w.c:
+        assert row[t] == 1.0 and row.sum() == 0.0 and np.count_nonzero(row) == 2
+        js.add(int(np.flatnonzero(row == -1.0)[0]))
+    assert js == set(range(10)) - {t}

@@ -1277,6 +1277,15 @@ static void bind_plan(asd_plan* P, const asd_net* net, int S, const asd_params* 
     P->Sa = S;
     P->ragged = false;
     P->min_valid = false;
+    // LDS a block may use on the current device (64 KB where it cannot be read)
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+        (void)hipGetLastError();  // no error left for the next launch check
+        lds = 65536;
+    }
+    lds = std::max(lds, 65536);
+    P->lds_max = lds;
 }
 
 // Workspace of asd_solve_static: one array per GPU the library runs on,

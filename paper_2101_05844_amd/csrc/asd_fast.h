@@ -998,8 +998,7 @@ struct FastBwdArgs {
 // together; the stores' ballots need every lane of the wave.
 template <typename T>
 struct BwdIn {
-    T own, g, lo, hi;
-    bool dg;
+    T own, g, lo, hi;  // compared only when stored: a load may stay in flight until then
 };
 
 template <typename T>
@@ -1008,7 +1007,6 @@ __device__ __forceinline__ void bwd_load(const FastBwdArgs<T>& A, int c, long co
     __builtin_assume(idx < (1u << 30));
     in.own = in.g = (T)0;
     in.lo = in.hi = (T)0;
-    in.dg = false;
     if (!ok) return;
     if (A.k >= 1) {
         in.own = A.own[idx];
@@ -1016,7 +1014,6 @@ __device__ __forceinline__ void bwd_load(const FastBwdArgs<T>& A, int c, long co
     }
     in.lo = A.nk.lo[idx];
     in.hi = A.nk.hi[idx];
-    in.dg = in.lo == in.hi;  // point box
 }
 
 template <typename T>
@@ -1027,7 +1024,7 @@ __device__ __forceinline__ void bwd_store(const FastBwdArgs<T>& A, bool ok, uint
     if (ok) {
         if (A.k >= 1) f += in.own;
         if (A.fout) A.fout[caller_index(idx, A.S, A.gn.in)] = f;
-        xb = f >= (T)0 || in.dg;
+        xb = f >= (T)0 || in.lo == in.hi;  // a point box takes its value
         A.nk.xstar[idx] = xb ? in.hi : in.lo;
         if (A.k >= 1) zb = in.g >= (T)0;
     }
@@ -1184,8 +1181,8 @@ __global__ void __launch_bounds__(kWave * KSP) k_bwd_conv(FastBwdArgs<T> A) {
 // C_{k+1} J^2 taps, J = ceil(ks / st), zero where a tap falls outside the
 // kernel), B = the operands of layer k+1 at those outputs (zero outside it).
 // Grid (S, ceil(C_k / 16)), block (64, NW): a block owns one subproblem and
-// 16 channels.  Work items are (class, 64 positions of the class); in round
-// r wave w takes item r NW + w (one round: items <= NW).  The operand images
+// 16 channels.  Work items are (class, 16 NT positions of the class), one
+// per wave (NW = items, at most 8).  The operand images
 // of the subproblem (v and every u_q, with a zero border of J - 1 outputs)
 // are staged in LDS in chunks of CC output channels, so the B gathers are LDS
 // reads; product r's images start at float r * RS (RS fixed per mask count,
@@ -1209,14 +1206,22 @@ __host__ __device__ constexpr int bwd_mfma_rs() {
     return (12288 / (1 + NM)) & ~3;
 }
 
+// k_bwd_conv_m4 with the LDS share of two blocks per CU (78 KB): 70 KB of
+// staged images over the 1 + NM products, at most 8 KB of weights after them
+template <int NM>
+__host__ __device__ constexpr int bwd_m4_rs_big() {
+    return (17920 / (1 + NM)) & ~3;
+}
+constexpr int kM4BigWeightFloats = 2048;
+
 // Stages the operand images of one subproblem for output channels
 // [cb, cb + cc) of layer k+1 (v and every u_q) into the interiors of the
 // images at opnd + r RS (the borders were zeroed once); UL elements per
 // thread, the loads of every product in flight before the LDS stores.
 template <int NM>
 __device__ __forceinline__ void stage_operands(const FastBwdArgs<float>& A, const BwdConvShape& B, float* opnd,
-                                               int cb, int cc, uint32_t obase, uint32_t ostride, int tid, int nthr) {
-    constexpr int RS = bwd_mfma_rs<NM>();
+                                               int cb, int cc, uint32_t obase, uint32_t ostride, int tid, int nthr,
+                                               int RS) {
     constexpr int UL = 4;
     const NeuronLayout& O = A.gn.out;
     const int img = B.Hp * B.Wp, Wp = B.Wp, off = B.off;
@@ -1263,16 +1268,18 @@ __device__ __forceinline__ void stage_operands(const FastBwdArgs<float>& A, cons
 // Grid (S), block (64, P_k / 64): a block owns one subproblem, wave w its
 // positions [64 w, 64 w + 64).  The operand images of the subproblem are
 // staged in LDS as for k_bwd_conv_mfma (zero borders, chunks of CC output
-// channels, product r at float r RS), the weights [C_{k+1}][ks][ks][4] (then
-// one zero row) after them at float fboff; the sums go back to natural
-// order through lane shuffles before the finishing stores.
-template <int NM, int KSZ, bool BF = false>  // BF (4 x 4 kernels, stride 2): the 4 taps of a channel in one bf16 instruction
+// channels, product r at float r RS: with BIG the LDS share of two blocks
+// per CU, which holds all channels of small layers at few masks), the weights
+// [C_{k+1}][ks][ks][4] (then one zero row) after them at float fboff; the
+// sums go back to natural order through lane shuffles before the finishing
+// stores.
+template <int NM, int KSZ, bool BF = false, bool BIG = false>  // BF (4 x 4 kernels, stride 2): the 4 taps of a channel in one bf16 instruction
 __global__ void __launch_bounds__(kWave * 16) k_bwd_conv_m4(FastBwdArgs<float> A, BwdConvShape B) {
     typedef float floatx4 __attribute__((ext_vector_type(4)));
     constexpr int CB = 4;
     constexpr int NA = NM > 0 ? NM : 1;
     constexpr int st = 2;
-    constexpr int RS = bwd_mfma_rs<NM>();
+    constexpr int RS = BIG ? bwd_m4_rs_big<NM>() : bwd_mfma_rs<NM>();
     extern __shared__ __attribute__((aligned(16))) float lds[];
     const LayerGeo& g = A.gn;
     const NeuronLayout& L = g.in;
@@ -1288,6 +1295,23 @@ __global__ void __launch_bounds__(kWave * 16) k_bwd_conv_m4(FastBwdArgs<float> A
     const int CC = B.CC, off = B.off, Wp = B.Wp, img = B.Hp * B.Wp;
     float* opnd = lds;
     float* wl = lds + B.fboff;
+    // finishing inputs of this lane's natural position p2 (layer k is the
+    // input: its box only), loaded right after the first chunk is staged
+    // where registers allow two blocks per CU, so their latency overlaps the
+    // products (which read LDS only)
+    constexpr bool PRE = !BF && NM <= 2;
+    const int p2 = wave * kWave + lane;
+    const long ncol = (long)s * L.P + p2;
+    BwdIn<float> in[CB];
+    auto load_box = [&]() {
+#pragma unroll
+        for (int e = 0; e < CB; ++e) {
+            const uint32_t idx = (uint32_t)(((long)min(e, L.C - 1) * S + s) * L.P + p2);
+            in[e].own = in[e].g = 0.f;
+            in[e].lo = A.nk.lo[idx];
+            in[e].hi = A.nk.hi[idx];
+        }
+    };
     {
         const float4* src = reinterpret_cast<const float4*>(A.Wl4);
         float4* dst = reinterpret_cast<float4*>(wl);
@@ -1318,11 +1342,14 @@ __global__ void __launch_bounds__(kWave * 16) k_bwd_conv_m4(FastBwdArgs<float> A
         hb[e] = NM > 0 ? (unsigned)ld32(A.xpk, (uint32_t)min(e, L.C - 1) * cstride + nidx) : 0u;
     constexpr int JC = KSZ > 0 ? (KSZ + st - 1) / st : 0;
     const int J = JC > 0 ? JC : (ks + st - 1) / st;
-    for (int cb = 0; cb < O.C; cb += CC) {
-        const int cc = min(CC, O.C - cb);
+    auto stage = [&](int cb) {
         __syncthreads();  // the previous chunk's reads are done (and the borders zeroed)
-        stage_operands<NM>(A, B, opnd, cb, cc, (uint32_t)s * (uint32_t)O.P, (uint32_t)S * (uint32_t)O.P, tid, nthr);
+        stage_operands<NM>(A, B, opnd, cb, min(CC, O.C - cb), (uint32_t)s * (uint32_t)O.P,
+                           (uint32_t)S * (uint32_t)O.P, tid, nthr, RS);
         __syncthreads();
+    };
+    auto products = [&](int cb) {
+        const int cc = min(CC, O.C - cb);
         for (int c = 0; c < cc; ++c) {
             const int co = cb + c;
             if constexpr (BF && JC == 2) {
@@ -1372,6 +1399,13 @@ __global__ void __launch_bounds__(kWave * 16) k_bwd_conv_m4(FastBwdArgs<float> A
                 }
             }
         }
+        };
+    stage(0);
+    if constexpr (PRE) load_box();
+    products(0);
+    for (int cb = CC; cb < O.C; cb += CC) {
+        stage(cb);
+        products(cb);
     }
     // fold sigma_q (this lane's packed x-bits), then fetch each channel's
     // sum from the lane that computed the natural position of this lane
@@ -1385,14 +1419,7 @@ __global__ void __launch_bounds__(kWave * 16) k_bwd_conv_m4(FastBwdArgs<float> A
         for (int q = 0; q < NM; ++q) part += 0.5f * flip(au[q][e], (hb[e] >> q) & 1u);
         f[e] = __shfl(part, from);
     }
-    const int p2 = wave * kWave + lane;
-    const long ncol = (long)s * L.P + p2;
-    BwdIn<float> in[CB];
-#pragma unroll
-    for (int e = 0; e < CB; ++e) {
-        const int c = min(e, L.C - 1);
-        bwd_load<float>(A, c, ncol, true, ((long)c * S + s) * L.P + p2, in[e]);
-    }
+    if constexpr (!PRE) load_box();
 #pragma unroll
     for (int e = 0; e < CB; ++e) {
         if (e >= L.C) break;  // uniform
@@ -1400,27 +1427,63 @@ __global__ void __launch_bounds__(kWave * 16) k_bwd_conv_m4(FastBwdArgs<float> A
     }
 }
 
-// Finishes rows x P_k neurons of subproblem s, channels c0 .. c0 + rows - 1,
-// from f parked in fbuf [rows][P_k] (natural order), in 64-position runs
-// (P_k % 64 == 0), NB runs' loads in flight together.
+// Finishing of rows x P_k neurons of subproblem s, channels c0 .. c0 + rows
+// - 1, from f parked in fbuf [rows][P_k] (natural order), in 64-position
+// runs (P_k % 64 == 0): wave w takes batches of NB runs starting at run
+// NB (w + nw i), their loads in flight together.  finish_prefetch loads
+// the inputs of the first PF runs of a wave's first batch before the
+// products, so their latency overlaps them (PF as registers allow).
+constexpr int kFinishNB = 8;
+
+// The loads carry no branch, so a batch issues back to back: into the
+// input layer (no own duals, no z) the own and g loads read the box instead,
+// and bwd_store ignores them there.
+template <int PF>
+__device__ __forceinline__ void finish_load(const FastBwdArgs<float>& A, int s, int c0, int nrun, int ch0, int lane,
+                                            BwdIn<float>* in) {
+    const NeuronLayout& L = A.gn.in;
+    const int runs = L.P / kWave;
+    const float* po = A.k >= 1 ? A.own : A.nk.lo;
+    const float* pg = A.k >= 1 ? A.gk : A.nk.lo;
+#pragma unroll
+    for (int b = 0; b < PF; ++b) {
+        const int ch = min(ch0 + b, nrun - 1);
+        const int c = ch / runs;
+        const int p = (ch - c * runs) * kWave + lane;
+        const uint32_t idx = (uint32_t)(((long)(c0 + c) * A.S + s) * L.P + p);
+        in[b].own = po[idx];
+        in[b].g = pg[idx];
+        in[b].lo = A.nk.lo[idx];
+        in[b].hi = A.nk.hi[idx];
+    }
+}
+
+template <int PF>
+__device__ __forceinline__ void finish_prefetch(const FastBwdArgs<float>& A, int s, int c0, int rows, int wave,
+                                                int lane, BwdIn<float> (&pre)[PF > 0 ? PF : 1]) {
+    const int nrun = rows * (A.gn.in.P / kWave);
+    if constexpr (PF > 0) finish_load<PF>(A, s, c0, nrun, min(wave * kFinishNB, nrun - 1), lane, pre);
+}
+
+template <int PF>
 __device__ __forceinline__ void finish_runs(const FastBwdArgs<float>& A, const float* fbuf, int s, int c0, int rows,
-                                            int wave, int nw, int lane) {
+                                            int wave, int nw, int lane, const BwdIn<float> (&pre)[PF > 0 ? PF : 1]) {
+    static_assert(PF <= kFinishNB, "at most one batch is prefetched");
     const NeuronLayout& L = A.gn.in;
     const int S = A.S;
-    constexpr int NB = 8;
     const int runs = L.P / kWave;
     const int nrun = rows * runs;
-    for (int ch0 = wave * NB; ch0 < nrun; ch0 += nw * NB) {
-        BwdIn<float> in[NB];
+    for (int ch0 = wave * kFinishNB; ch0 < nrun; ch0 += nw * kFinishNB) {
+        BwdIn<float> in[kFinishNB];
+        if (ch0 == wave * kFinishNB) {
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const int ch = min(ch0 + b, nrun - 1);
-            const int c = ch / runs;
-            const int p = (ch - c * runs) * kWave + lane;
-            bwd_load<float>(A, c0 + c, (long)s * L.P + p, true, ((long)(c0 + c) * S + s) * L.P + p, in[b]);
+            for (int b = 0; b < PF; ++b) in[b] = pre[b];
+            finish_load<kFinishNB - PF>(A, s, c0, nrun, ch0 + PF, lane, in + PF);
+        } else {
+            finish_load<kFinishNB>(A, s, c0, nrun, ch0, lane, in);
         }
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
+        for (int b = 0; b < kFinishNB; ++b) {
             const int ch = ch0 + b;
             if (ch >= nrun) break;  // uniform
             const int c = ch / runs;
@@ -1432,10 +1495,16 @@ __device__ __forceinline__ void finish_runs(const FastBwdArgs<float>& A, const f
     }
 }
 
-template <int NM, int KSZ, int STR, int NT, bool BF = false>  // NT: column tiles of 16 per item; BF: BF16 operands
+// WL (one round of items, all output channels in one chunk): the block's
+// class weights are staged in LDS too (at float fboff) and f is parked over
+// the staged images, so the products read LDS only; the finishing inputs
+// of each wave's first runs are loaded right after the staging, and their
+// latency overlaps the products (a wait for a later vector load would wait
+// for them as well).
+template <int NM, int KSZ, int STR, int NT, bool BF = false, bool WL = false>  // NT: column tiles of 16 per item; BF: BF16 operands
 __global__ void __launch_bounds__(kWave * 8) k_bwd_conv_mfma(FastBwdArgs<float> A, BwdConvShape B) {
     typedef float floatx4 __attribute__((ext_vector_type(4)));
-    extern __shared__ float lds[];
+    extern __shared__ __attribute__((aligned(16))) float lds[];
     const LayerGeo& g = A.gn;
     const NeuronLayout& L = g.in;
     const NeuronLayout& O = g.out;
@@ -1457,18 +1526,35 @@ __global__ void __launch_bounds__(kWave * 8) k_bwd_conv_mfma(FastBwdArgs<float> 
     const int r4 = lane >> 4, cl = lane & 15;
     const int CC = B.CC;
     constexpr int RS = bwd_mfma_rs<NM>();
-    float* opnd = lds;             // product r: [CC][Hp][Wp] at float r RS
-    float* fbuf = lds + B.fboff;   // [rows][P_k]
+    float* opnd = lds;                       // product r: [CC][Hp][Wp] at float r RS
+    float* fbuf = WL ? lds : lds + B.fboff;  // [rows][P_k]
+    const float* wlds = lds + B.fboff;       // WL: class weights [class][nkp][16]
     const uint32_t obase = (uint32_t)s * (uint32_t)O.P;
     const uint32_t ostride = (uint32_t)S * (uint32_t)O.P;
-    const int rounds = (B.items + NW - 1) / NW;
+    if constexpr (WL) {
+        const float4* src = reinterpret_cast<const float4*>(A.Wb + (long)grp * st * st * nkp * 16);
+        float4* dst = reinterpret_cast<float4*>(lds + B.fboff);
+        const int n4 = st * st * nkp * 4;
+        for (int i = tid; i < n4; i += kWave * NW) dst[i] = src[i];
+    }
     // zero borders: the interiors are overwritten by every chunk
 #pragma unroll
     for (int r = 0; r <= NM; ++r)
         for (int i = tid; i < CC * img; i += kWave * NW) opnd[r * RS + i] = 0.f;
-    for (int rd = 0; rd < rounds; ++rd) {
-        // find this wave's item: class cls, first position n0 within the class
-        const int item = rd * NW + wave;
+    // WL (all output channels in one chunk): stage once, then load the
+    // finishing inputs of the first runs, as many as leave 4 waves per SIMD
+    constexpr int PF = WL ? (NT == 2 ? (NM <= 2 ? 8 : NM == 3 ? 4 : 0) : 0) : 0;
+    BwdIn<float> pre[PF > 0 ? PF : 1];
+    if constexpr (WL) {
+        __syncthreads();
+        stage_operands<NM>(A, B, opnd, 0, O.C, obase, ostride, tid, kWave * NW, RS);
+        __syncthreads();
+        finish_prefetch<PF>(A, s, c0, rows, wave, lane, pre);
+    }
+    {
+        // find this wave's item (the host launches one wave per item): class
+        // cls, first position n0 within the class
+        const int item = wave;
         int cls = -1, n0 = 0, cnt = 0, yf = 0, xf = 0, nx = 1;
         {
             int idx = 0;
@@ -1519,12 +1605,15 @@ __global__ void __launch_bounds__(kWave * 8) k_bwd_conv_mfma(FastBwdArgs<float> 
                 const int c = min(4 * r4 + r, rows - 1);
                 hb[j][r] = NM > 0 ? (unsigned)A.xpk[((long)(c0 + c) * S + s) * L.P + pos[j]] : 0u;
             }
-        const float* Wc = A.Wb + ((long)grp * st * st + (has ? cls : 0)) * nkp * 16;
+        const float* Wc = WL ? wlds + (long)(has ? cls : 0) * nkp * 16
+                             : A.Wb + ((long)grp * st * st + (has ? cls : 0)) * nkp * 16;
         for (int cb = 0; cb < O.C; cb += CC) {
             const int cc = min(CC, O.C - cb);
-            __syncthreads();  // the previous chunk's reads are done
-            stage_operands<NM>(A, B, opnd, cb, cc, obase, ostride, tid, kWave * NW);
-            __syncthreads();
+            if constexpr (!WL) {
+                __syncthreads();  // the previous chunk's reads are done
+                stage_operands<NM>(A, B, opnd, cb, cc, obase, ostride, tid, kWave * NW, RS);
+                __syncthreads();
+            }
             if (!has) continue;
             if constexpr (JC == 2) {
                 // J = 2: a step of 4 taps is one output channel; lane r4
@@ -1534,7 +1623,7 @@ __global__ void __launch_bounds__(kWave * 8) k_bwd_conv_mfma(FastBwdArgs<float> 
 #pragma unroll
                 for (int j = 0; j < NT; ++j) lb[j] = (qy[j] - (r4 >> 1)) * Wp + qx[j] - (r4 & 1);
                 const float* wp = Wc + ((long)cb * 4 + r4) * 16 + cl;  // + 64 per output channel
-                constexpr int U = 8;
+                constexpr int U = BF ? 8 : (WL || NM >= 4) ? 4 : 6;  // channels whose weights are loaded ahead
                 float wq[U];
                 auto wload = [&](int c) {
 #pragma unroll
@@ -1673,7 +1762,9 @@ __global__ void __launch_bounds__(kWave * 8) k_bwd_conv_mfma(FastBwdArgs<float> 
                 }
             }
         }
-        // fold sigma_q of each neuron and park f in natural order
+        // fold sigma_q of each neuron and park f in natural order (WL: over
+        // the staged images, once every wave's products are done)
+        if constexpr (WL) __syncthreads();
         if (has) {
 #pragma unroll
             for (int j = 0; j < NT; ++j) {
@@ -1691,7 +1782,7 @@ __global__ void __launch_bounds__(kWave * 8) k_bwd_conv_mfma(FastBwdArgs<float> 
         }
     }
     __syncthreads();
-    finish_runs(A, fbuf, s, c0, rows, wave, NW, lane);
+    finish_runs<PF>(A, fbuf, s, c0, rows, wave, NW, lane, pre);
 }
 
 // Class weights for k_bwd_conv_mfma: Wb[grp][cls][k][c] = W[co][16 grp + c][ky][kx]
@@ -1902,21 +1993,38 @@ __global__ void __launch_bounds__(kWave * KW) k_bwd_dense_pos(FastBwdArgs<T> A) 
 // x 16 positions of one channel (columns) and the whole contraction over
 // the outputs of layer k+1: A = the operands of layer k+1 (v, or -c into
 // the output layer's inputs, and every u_q) at those subproblems, B = W
-// (|W| for the u_q) at those positions.  The x-bits and the finishing
-// inputs of the wave's neurons are loaded before the products, so their
-// latency overlaps them; rows past the active subproblems are computed on
-// clamped operands and dropped.  The bits of one register's 16 positions of
-// one subproblem are one 16-bit piece of the bit array.  Grid
+// (|W| for the u_q) at those positions.  The four waves of a block share
+// the subproblems, so the block stages their operands in LDS, KC outputs
+// of layer k+1 at a time ([1 + NM][KC][16], zero past the last output),
+// with every load of a chunk in flight together; the weights of the next
+// trip of U steps are loaded during the current one.  The x-bits and the
+// finishing inputs of the wave's neurons are loaded before the products, so
+// their latency overlaps them; rows past the active subproblems are
+// computed on clamped operands and dropped.  The bits of one register's 16
+// positions of one subproblem are one 16-bit piece of the bit array.  Grid
 // (ceil(Sa / 16), C_k P_k / 64), block (64, 4): wave w takes positions
 // [16 w, 16 w + 16) of the block's 64.
+template <int NM>
+__host__ __device__ constexpr int bwd_dense_kc() {
+    return NM <= 2 ? 128 : 64;
+}
+template <int NM>
+__host__ __device__ constexpr int bwd_dense_lds_floats() {
+    return (1 + NM) * bwd_dense_kc<NM>() * 16;
+}
+
 template <int NM, bool BF = false>  // BF: BF16 operands (v_mfma_f32_16x16x16bf16_1k, 4 steps per instruction)
-__device__ __forceinline__ void bwd_dense_mfma_block(const FastBwdArgs<float>& A, int bx, int by) {
+__device__ __forceinline__ void bwd_dense_mfma_block(const FastBwdArgs<float>& A, int bx, int by, float* alds) {
     typedef float floatx4 __attribute__((ext_vector_type(4)));
     constexpr int NA = NM > 0 ? NM : 1;
+    constexpr int KC = bwd_dense_kc<NM>();
+    constexpr int U = 8;  // steps of 4 outputs per trip
+    static_assert(KC % (4 * U) == 0, "trips must not straddle a staged chunk");
     const LayerGeo& g = A.gn;
     const NeuronLayout& L = g.in;
     const int lane = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    const int tid = wave * kWave + lane;
     const int S = A.S;
     const int Sa = (int)(L.cols / L.P);
     const int tiles = L.P / kWave;
@@ -1924,12 +2032,22 @@ __device__ __forceinline__ void bwd_dense_mfma_block(const FastBwdArgs<float>& A
     const int p0 = (by - c * tiles) * kWave + wave * 16;
     const int s0 = bx * 16;
     const int kq = lane >> 4, cl = lane & 15;
-    const int sA = min(s0 + cl, Sa - 1);  // A row of this lane
     const int p = p0 + cl;                // C column of this lane
     const int n1 = g.out.C;
     const long F = g.fan;
     const float* vsrc = A.last ? A.cvec : A.vs;
     const float vsign = A.last ? -1.f : 1.f;
+    // weights of one trip: output i + 4 u + kq at this lane's position
+    const float* wcol = g.W + (long)c * L.P + p;
+    float wv[U];
+    auto wload = [&](int i) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int ii = i + 4 * u + kq;
+            wv[u] = wcol[(long)(ii < n1 ? ii : 0) * F];
+        }
+    };
+    wload(0);
     // this lane's neurons: rows 4 kq + r, column cl
     unsigned hb[4];
     BwdIn<float> in[4];
@@ -1944,54 +2062,61 @@ __device__ __forceinline__ void bwd_dense_mfma_block(const FastBwdArgs<float>& A
     floatx4 au[NA];
 #pragma unroll
     for (int q = 0; q < NA; ++q) au[q] = floatx4{0.f, 0.f, 0.f, 0.f};
-    // steps of 4 outputs of layer k+1 (lane group kq takes output i + kq), U
-    // steps per trip, the next trip's loads in flight during this one
-    constexpr int U = BF ? 4 : 5;
-    float av[U], uv[U][NA], wv[U];
-    const float* wcol = g.W + (long)c * L.P + p;
-    auto load = [&](int i) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int ii = i + 4 * u + kq;
-            const int ic = ii < n1 ? ii : 0;
-            const long a = (long)ic * S + sA;
-            av[u] = vsrc[a];
-#pragma unroll
-            for (int q = 0; q < NM; ++q) uv[u][q] = A.u[q][a];
-            wv[u] = wcol[(long)ic * F];
-        }
-    };
-    load(0);
     for (int i = 0; i < n1; i += 4 * U) {
-        float a2[U], u2[U][NA], w2[U];
+        if (i % KC == 0) {
+            // stage outputs [i, i + KC) of every operand
+            __syncthreads();  // the previous chunk's reads are done
+            constexpr int PER = KC * 16 / (4 * kWave);  // elements per thread and operand
+            float v[1 + NM][PER];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const bool ok = i + 4 * u + kq < n1;  // outputs past n1 contribute nothing
-            a2[u] = ok ? av[u] : 0.f;
+            for (int r = 0; r <= NM; ++r) {
+                const float* src = r == 0 ? vsrc : A.u[r > 0 ? r - 1 : 0];
 #pragma unroll
-            for (int q = 0; q < NM; ++q) u2[u][q] = ok ? uv[u][q] : 0.f;
-            w2[u] = wv[u];
+                for (int j = 0; j < PER; ++j) {
+                    const int e = tid + j * 4 * kWave;
+                    const int ii = i + (e >> 4);
+                    v[r][j] = ii < n1 ? src[(long)ii * S + min(s0 + (e & 15), Sa - 1)] : 0.f;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r <= NM; ++r)
+#pragma unroll
+                for (int j = 0; j < PER; ++j) alds[r * KC * 16 + tid + j * 4 * kWave] = v[r][j];
+            __syncthreads();
         }
-        if (i + 4 * U < n1) load(i + 4 * U);
-        if constexpr (BF) {
-            // the trip's 4 steps in the slots of one instruction (steps past
-            // n1 hold zero operands)
-            const shortx4 wb = bf16x4(w2);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bf16x4(a2), wb, acc, 0, 0, 0);
-            const shortx4 wa = bf16_abs(wb);
+        float w2[U];
 #pragma unroll
-            for (int q = 0; q < NM; ++q)
-                au[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bf16x4(u2[0][q], u2[1][q], u2[2][q], u2[3][q]), wa,
-                                                                   au[q], 0, 0, 0);
+        for (int u = 0; u < U; ++u) w2[u] = wv[u];
+        if (i + 4 * U < n1) wload(i + 4 * U);
+        const float* ab = alds + ((i % KC) + kq) * 16 + cl;  // + 64 per step, + 16 KC per operand
+        if constexpr (BF) {
+            // 4 steps in the slots of one instruction (outputs past n1:
+            // zero operands)
+#pragma unroll
+            for (int u0 = 0; u0 < U; u0 += 4) {
+                if (i + 4 * u0 >= n1) break;  // uniform
+                const shortx4 wb = bf16x4(&w2[u0]);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+                    bf16x4(ab[(u0 + 0) * 64], ab[(u0 + 1) * 64], ab[(u0 + 2) * 64], ab[(u0 + 3) * 64]), wb, acc, 0,
+                    0, 0);
+                const shortx4 wa = bf16_abs(wb);
+#pragma unroll
+                for (int q = 0; q < NM; ++q) {
+                    const float* aq = ab + (1 + q) * KC * 16;
+                    au[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+                        bf16x4(aq[(u0 + 0) * 64], aq[(u0 + 1) * 64], aq[(u0 + 2) * 64], aq[(u0 + 3) * 64]), wa,
+                        au[q], 0, 0, 0);
+                }
+            }
         } else {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (i + 4 * u >= n1) break;  // uniform
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[u], w2[u], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ab[u * 64], w2[u], acc, 0, 0, 0);
                 const float wa = fabsf(w2[u]);
 #pragma unroll
                 for (int q = 0; q < NM; ++q)
-                    au[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(u2[u][q], wa, au[q], 0, 0, 0);
+                    au[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ab[(1 + q) * KC * 16 + u * 64], wa, au[q], 0, 0, 0);
             }
         }
     }
@@ -2009,7 +2134,7 @@ __device__ __forceinline__ void bwd_dense_mfma_block(const FastBwdArgs<float>& A
             if (A.k >= 1) f += in[r].own;
             const long idx = ((long)c * S + s) * L.P + p;
             if (A.fout) A.fout[caller_index((uint32_t)idx, S, L)] = f;
-            xb = f >= 0.f || in[r].dg;
+            xb = f >= 0.f || in[r].lo == in[r].hi;
             A.nk.xstar[idx] = xb ? in[r].hi : in[r].lo;
             if (A.k >= 1) zb = in[r].g >= 0.f;
         }
@@ -2025,7 +2150,8 @@ __device__ __forceinline__ void bwd_dense_mfma_block(const FastBwdArgs<float>& A
 
 template <int NM, bool BF>
 __global__ void __launch_bounds__(kWave * 4) k_bwd_dense_mfma(FastBwdArgs<float> A) {
-    bwd_dense_mfma_block<NM, BF>(A, blockIdx.x, blockIdx.y);
+    __shared__ float alds[bwd_dense_lds_floats<NM>()];
+    bwd_dense_mfma_block<NM, BF>(A, blockIdx.x, blockIdx.y, alds);
 }
 
 // The column-mapped dense backward into the last ReLU layer (k_bwd_dense
@@ -2041,15 +2167,19 @@ template <int NMB, bool BF>
 __global__ void __launch_bounds__(kWave * 4) k_bwd_dense_pair(FastBwdArgs<float> Aa, FastBwdArgs<float> Ab, int na,
                                                               int agx, int agy, int mgx) {
     static_assert(KS == 4, "both kernels run 4 waves per block");
-    __shared__ float red[KS][8][kWave];
+    // one LDS buffer for either role: the column kernel's partial sums or
+    // the staged operands
+    constexpr int kRed = KS * 8 * kWave;
+    constexpr int kLds = kRed > bwd_dense_lds_floats<NMB>() ? kRed : bwd_dense_lds_floats<NMB>();
+    __shared__ __attribute__((aligned(16))) float smem[kLds];
     const int lin = blockIdx.x;
     if (lin < na) {
         int tile, group;
         xcd_tile_of((unsigned)lin, (unsigned)agx, (unsigned)agy, tile, group);
-        bwd_dense_block<float, 0, 8, true>(Aa, tile, group, red);
+        bwd_dense_block<float, 0, 8, true>(Aa, tile, group, reinterpret_cast<float (*)[8][kWave]>(smem));
     } else {
         const int l2 = lin - na;
-        bwd_dense_mfma_block<NMB, BF>(Ab, l2 % mgx, l2 / mgx);
+        bwd_dense_mfma_block<NMB, BF>(Ab, l2 % mgx, l2 / mgx, smem);
     }
 }
 

@@ -228,13 +228,21 @@ asd_status bwd_fast_impl(asd_plan* P, int k, hipStream_t st) {
         const int img = sh.Hp * sh.Wp;
         if (sh.items <= sh.NW && fbytes <= 32 * 1024 && img <= RS) {
             sh.CC = std::min(g.out.C, RS / img);
-            // product r's images at float r RS, the parked f after the last
-            sh.fboff = NM * RS + sh.CC * img;
-            const size_t dyn = (size_t)sh.fboff * sizeof(float) + fbytes;
+            // product r's images at float r RS, the parked f after the last;
+            // or (wl) the class weights after the last image and f parked
+            // over the images, where two blocks per CU still fit
+            const int fbo4 = (NM * RS + sh.CC * img + 3) / 4 * 4;
+            const size_t wfl = (size_t)st_ * st_ * a.nkp * 16;
+            const bool wl = g.ksz == 4 && g.stride == 2 && NT == 2 && sh.CC == g.out.C &&
+                            fbytes <= (size_t)(NM * RS + sh.CC * img) * sizeof(float) &&
+                            ((size_t)fbo4 + wfl) * sizeof(float) <= std::min<size_t>((size_t)P->lds_max, 80 * 1024);
+            sh.fboff = wl ? fbo4 : NM * RS + sh.CC * img;
+            const size_t dyn = wl ? ((size_t)fbo4 + wfl) * sizeof(float) : (size_t)sh.fboff * sizeof(float) + fbytes;
             ProfScope ps(P, st, ASD_K_BACKWARD, k);
             dim3 grid((unsigned)P->Sa, (unsigned)((L.C + 15) / 16));
             if (g.ksz == 4 && g.stride == 2) {
-                if (NT == 2) hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 4, 2, 2, BF>), grid, dim3(kWave, sh.NW), dyn, st, a, sh);
+                if (wl) hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 4, 2, 2, BF, true>), grid, dim3(kWave, sh.NW), dyn, st, a, sh);
+                else if (NT == 2) hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 4, 2, 2, BF>), grid, dim3(kWave, sh.NW), dyn, st, a, sh);
                 else hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 4, 2, 4, BF>), grid, dim3(kWave, sh.NW), dyn, st, a, sh);
             } else {
                 if (NT == 2) hipLaunchKernelGGL((k_bwd_conv_mfma<NM, 0, 0, 2>), grid, dim3(kWave, sh.NW), dyn, st, a, sh);
@@ -259,15 +267,25 @@ asd_status bwd_fast_impl(asd_plan* P, int k, hipStream_t st) {
                 // at most 4 channels, stride 2: the matrix-core variant, a
                 // block per subproblem
                 BwdConvShape sh = conv_shape(g);
-                constexpr int RS = bwd_mfma_rs<NM>();
                 const int img = sh.Hp * sh.Wp;
+                const int wfl = (g.out.C * g.ksz * g.ksz + 1) * 4;  // weights and the zero row
+                // staged images: the LDS share of two blocks per CU where the
+                // device and the weights allow, else the 48 KB split
+                const bool big = P->lds_max >= 78 * 1024 && wfl <= kM4BigWeightFloats;
+                const int RS = big ? bwd_m4_rs_big<NM>() : bwd_mfma_rs<NM>();
                 sh.CC = std::min(g.out.C, RS / img);
                 sh.fboff = (NM * RS + sh.CC * img + 3) / 4 * 4;
-                const size_t dm4 = ((size_t)sh.fboff + (size_t)(g.out.C * g.ksz * g.ksz + 1) * 4) * sizeof(float);
-                if (dm4 <= 64 * 1024) {
+                const size_t dm4 = ((size_t)sh.fboff + (size_t)wfl) * sizeof(float);
+                if (dm4 <= (size_t)P->lds_max) {
                     const dim3 bm4(kWave, L.P / kWave);
-                    if (g.ksz == 4) hipLaunchKernelGGL((k_bwd_conv_m4<NM, 4, BF>), dim3((unsigned)P->Sa), bm4, dm4, st, a, sh);
-                    else hipLaunchKernelGGL((k_bwd_conv_m4<NM, 0>), dim3((unsigned)P->Sa), bm4, dm4, st, a, sh);
+                    const dim3 gm4((unsigned)P->Sa);
+                    if (g.ksz == 4) {
+                        if (big) hipLaunchKernelGGL((k_bwd_conv_m4<NM, 4, BF, true>), gm4, bm4, dm4, st, a, sh);
+                        else hipLaunchKernelGGL((k_bwd_conv_m4<NM, 4, BF, false>), gm4, bm4, dm4, st, a, sh);
+                    } else {
+                        if (big) hipLaunchKernelGGL((k_bwd_conv_m4<NM, 0, false, true>), gm4, bm4, dm4, st, a, sh);
+                        else hipLaunchKernelGGL((k_bwd_conv_m4<NM, 0, false, false>), gm4, bm4, dm4, st, a, sh);
+                    }
                     LAUNCH_CHECK();
                     return ASD_OK;
                 }

@@ -102,6 +102,7 @@ struct asd_plan {
     int32_t* inflags;                 // [S] input check of the loaded batch (bit 2: invalid inputs)
     void* lrs;                        // [S] learning rates of the current iteration (T)
     int Sa;                           // subproblems the current iteration updates (a prefix)
+    int lds_max;                      // LDS bytes one block may use on the plan's device
     // captured iteration schedule (asd_solve_graph) and the host state it ends in
     hipGraphExec_t graph_exec;
     bool graph_valid;
@@ -243,15 +244,15 @@ inline BwdConvShape conv_shape(const LayerGeo& g) {
     return sh;
 }
 
-// The transposed convolution into layer k fits k_bwd_conv_m4: stride 2, at
-// most 4 channels, every 64-position run whole rows of layer k or part of
+// The transposed convolution into layer k fits k_bwd_conv_m4: layer k is the
+// input, stride 2, at most 4 channels, every 64-position run whole rows of layer k or part of
 // one with an even number of columns per parity, at most 16 such runs per
 // subproblem, and the staged images of one output channel within the LDS
 // share of a product at any mask count.
 inline bool bwd_m4_fits(const asd_plan* P, int k) {
     const LayerGeo& g = P->geo[k + 1];
     const NeuronLayout& L = g.in;
-    if (g.kind != ASD_LAYER_CONV2D || g.stride != 2 || L.C > 4 || k + 1 == P->n) return false;
+    if (k != 0 || g.kind != ASD_LAYER_CONV2D || g.stride != 2 || L.C > 4 || k + 1 == P->n) return false;
     if (L.P % kWave != 0 || L.P > 16 * kWave || L.W % 8 != 0 || !(L.W % kWave == 0 || kWave % L.W == 0))
         return false;
     const BwdConvShape sh = conv_shape(g);

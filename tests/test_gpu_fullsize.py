@@ -119,13 +119,16 @@ def test_fullsize_fixed_dual_evaluation_fp32(cifar):
                 assert np.all(np.abs(gg - sg["masks"][k - 1][q])[same] <= tol[same])
 
 
-@pytest.mark.parametrize("prec", ["fp32", "mixed", "bf16", "bf16_all"])
-def test_fullsize_iteration_kernels_at_fixed_duals(cifar, prec):
+@pytest.mark.parametrize("prec,n_masks", [("fp32", 2), ("mixed", 2), ("bf16", 2), ("bf16_all", 2), ("fp32", 4),
+                                           ("bf16_all", 4)])
+def test_fullsize_iteration_kernels_at_fixed_duals(cifar, prec, n_masks):
     """The benchmark's launch configuration (autotuned kernel choices, shared
-    launches) evaluated at imported duals with two masks per layer through
-    asd_eval's iteration path: on the sampled subdomains f, g, x*, z* and
-    every supergradient entry match the oracle within 1e-5 of their row
-    scales (eq:dual-active-set, eq:as-primalk-min, eq:as-supergradient)."""
+    launches) evaluated at imported duals with two masks per layer (four:
+    the benchmark's last additions, where the staged operands of the
+    backward kernels come in several chunks) through asd_eval's iteration
+    path: on the sampled subdomains f, g, x*, z* and every supergradient
+    entry match the oracle within 1e-5 of their row scales
+    (eq:dual-active-set, eq:as-primalk-min, eq:as-supergradient)."""
     w, ops, L, U = cifar
     from paper_2101_05844_amd import asdual as A
     A.lib()
@@ -136,7 +139,7 @@ def test_fullsize_iteration_kernels_at_fixed_duals(cifar, prec):
     plan = A.Plan(net, w.S, prm)
     plan.init(*H.gpu_batch(w, L, U))
     tuning = plan.autotune(ktune=2, reps=3)
-    states = _random_state_import(A, plan, w, ops, L, U, n_masks=2, seed=11)
+    states = _random_state_import(A, plan, w, ops, L, U, n_masks=n_masks, seed=11)
     res = plan.eval(path=A.ASD_EVAL_ITERATION)
     torch.cuda.synchronize()
     # BF16 operands: within 2^-8 of the row scales (see test_gpu_parity.EPS);
@@ -145,7 +148,7 @@ def test_fullsize_iteration_kernels_at_fixed_duals(cifar, prec):
     eps_f = bf if prec == "bf16_all" else 1e-5
     eps_g = bf if prec.startswith("bf16") else 1e-5
     cnt = H.check_eval_against_oracle(res, [(s, p, st) for s, (p, st) in states.items()], eps_f, eps_g)
-    n_grad = len(SAMPLED) * sum(Lr.n_out * (3 + 2) for Lr in w.layers[:-1])
+    n_grad = len(SAMPLED) * sum(Lr.n_out * (3 + n_masks) for Lr in w.layers[:-1])
     assert cnt["grad"] == n_grad, cnt
     tie = 0.1 if prec == "bf16_all" else 0.01
     assert cnt["x_ties"] <= tie * cnt["x"] and cnt["z_ties"] <= tie * cnt["z"], cnt

@@ -21,7 +21,8 @@ follows one passage of the paper, cited by section and equation label:
   * Big-M initialisation ............ App. B (sec:dual-init), Algorithm 3
                                       (alg:bigm)
   * Adam ascent, schedule ........... Sec. 7.1 (experimental setting)
-  * intermediate bounds ............. App. E (sec:intermediate)
+  * intermediate bounds ............. App. E (sec:intermediate,
+                                      eq:primal-intermediates)
 
 Readings taken where the paper is ambiguous or inconsistent (the same list
 is kept with the design notes):
@@ -652,6 +653,55 @@ def solve(p: Problem, prm: SolveParams, snapshot_at: Sequence = (), trace: bool 
 
 def solve_batch(problems: Sequence[Problem], prm: SolveParams) -> np.ndarray:
     return np.array([solve(p, prm).bound for p in problems])
+
+
+# ----------------------------------------------------------------------------
+# Intermediate bounds by the solver (App. E, eq:primal-intermediates)
+# ----------------------------------------------------------------------------
+
+
+def interval_step(op: LinearOp, l_prev: np.ndarray, u_prev: np.ndarray):
+    """Interval propagation through one layer from the box [l_prev, u_prev]
+    of its inputs (post-activation values)."""
+    Wp = op.with_data(np.maximum(op.w, 0.0))
+    Wm = op.with_data(np.minimum(op.w, 0.0))
+    return Wp @ l_prev + Wm @ u_prev + op.b, Wp @ u_prev + Wm @ l_prev + op.b
+
+
+def intermediate_bounds(ops: Sequence[LinearOp], l0, u0, prm: SolveParams):
+    """Pre-activation bounds of the ReLU layers 1..n-1 from problem
+    eq:primal-intermediates (App. E), its relaxation's dual solved by the
+    same schedule as the last layer's bound (Algorithm 3, then Algorithm 1).
+
+    Layer 1: the problem is a box-constrained LP, solved exactly by interval
+    propagation.  Layer i >= 2, neuron j: on the sub-network of layers 1..i
+    (ReLU layers 1..i-1 with the bounds found before, layer i linear as the
+    output) the objective row e_j gives d_j <= min x_hat_i[j] and -e_j gives
+    d'_j <= -max x_hat_i[j] (weak duality: any dual point bounds the
+    minimum); each is combined with interval propagation of layer i from
+    the bounds of layer i-1: lhat_i[j] = max(ibp, d_j), uhat_i[j] =
+    min(ibp, -d'_j).  Returns (lhat, uhat), lists over layers 1..n-1.
+    """
+    l0 = np.asarray(l0, np.float64)
+    u0 = np.asarray(u0, np.float64)
+    lhat: List[np.ndarray] = []
+    uhat: List[np.ndarray] = []
+    l_prev, u_prev = l0, u0
+    for i in range(1, len(ops)):
+        lo, hi = interval_step(ops[i - 1], l_prev, u_prev)
+        if i >= 2:
+            n_i = ops[i - 1].n_out
+            for j in range(n_i):
+                e = np.zeros(n_i)
+                e[j] = 1.0
+                d_lo = solve(make_problem(ops[:i], l0, u0, lhat, uhat, e), prm).bound
+                d_hi = solve(make_problem(ops[:i], l0, u0, lhat, uhat, -e), prm).bound
+                lo[j] = max(lo[j], d_lo)
+                hi[j] = min(hi[j], -d_hi)
+        lhat.append(lo)
+        uhat.append(hi)
+        l_prev, u_prev = np.maximum(lo, 0.0), np.maximum(hi, 0.0)
+    return lhat, uhat
 
 
 # ----------------------------------------------------------------------------

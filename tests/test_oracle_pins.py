@@ -662,3 +662,75 @@ def test_margin_workload_property():
         assert row[t] == 1.0 and row.sum() == 0.0 and np.count_nonzero(row) == 2
         js.add(int(np.flatnonzero(row == -1.0)[0]))
     assert js == set(range(10)) - {t}
+
+
+# ----------------------------------------------------------------------------
+# Intermediate bounds by the solver (App. E, eq:primal-intermediates)
+# ----------------------------------------------------------------------------
+
+
+def preactivations(ops, xs):
+    """Exact pre-activations of every layer for inputs xs [m][n0]."""
+    out, x = [], np.asarray(xs, np.float64).T
+    for op in ops:
+        x = op.W @ x + op.b[:, None]
+        out.append(x.T)
+        x = np.maximum(x, 0.0)
+    return out
+
+
+def test_intermediate_bounds_appendix_f():
+    """eq:primal-intermediates through the Big-M dual (App. E with C_k = M_k)
+    on the App. F network: the upper bound of layer 2's neuron 1 reaches the
+    printed LP value 2.25 from above (weak duality of the max problem), well
+    inside interval propagation's 3; every layer-2 bound lies on the valid
+    side of the Big-M LP's and within 5e-4 of it; with these bounds the Big-M
+    LP of the output is the printed -1.2273 to the accuracy they carry."""
+    g, ops, l0, u0 = appendix_f_ops()
+    pr = g["printed"]
+    prm = O.SolveParams(bigm_iters=3000, as_iters=0, bigm_lr=(1e-2, 1e-4))
+    lh, uh = O.intermediate_bounds(ops, l0, u0, prm)
+    assert len(lh) == 2 and np.allclose(lh[0], pr["pre_activation_lower_layer1"]["lhat1"])
+    u21 = pr["lp_bigm_upper_layer2_neuron1"]["uhat_2_1"]
+    assert u21 - 1e-12 <= uh[1][1] <= u21 + 5e-4
+    lh_lp, uh_lp = lp.lp_intermediate_bounds(ops, l0, u0, "bigm")
+    assert np.all(lh[1] <= lh_lp[1] + 1e-12) and np.all(lh[1] >= lh_lp[1] - 5e-4)
+    assert np.all(uh[1] >= uh_lp[1] - 1e-12) and np.all(uh[1] <= uh_lp[1] + 5e-4)
+    v = lp.lp_value(ops, l0, u0, lh, uh, np.array([1.0]), "bigm")
+    assert abs(v - pr["output_lower_bound_bigm"]["value"]) <= 2e-3
+
+
+def test_intermediate_bounds_valid_and_tighter():
+    """On the tiny net and a convolutional net (whose first sub-network ends
+    in a convolution): the pre-activations of sampled inputs lie within the
+    bounds, the bounds are at least as tight as interval propagation from the
+    same input box, the first layer's are exactly interval propagation, and
+    (tiny net) each lower bound stays below the Anderson LP of its
+    sub-network over the bounds of the layers before (weak duality)."""
+    rng = np.random.default_rng(5)
+    sched = WL.Schedule(bigm_iters=40, as_iters=30, add_every=10, add_count=2, max_masks=3)
+    conv = WL.custom_config([WL.ConvSpec(1, 6, 6, 3, 3, 2, 1), WL.ConvSpec(3, 3, 3, 4, 2, 1, 0),
+                             WL.DenseSpec(16, 5), WL.DenseSpec(5, 2)], S=1, seed=9, eps=0.1, schedule=sched)
+    for w in (WL.tiny_config(), conv):
+        ops = O.ops_from_workload_layers(w.layers)
+        l0, u0 = w.l0[0].astype(float), w.u0[0].astype(float)
+        prm = O.SolveParams(bigm_iters=40, as_iters=30, add_every=10, add_count=2, max_masks=3)
+        lh, uh = O.intermediate_bounds(ops, l0, u0, prm)
+        lh_ibp, uh_ibp = O.interval_bounds(ops, l0, u0)
+        assert len(lh) == len(ops) - 1
+        assert np.array_equal(lh[0], lh_ibp[0]) and np.array_equal(uh[0], uh_ibp[0])
+        xs = l0 + rng.uniform(0, 1, (4000, l0.size)) * (u0 - l0)
+        pre = preactivations(ops, np.concatenate([xs, l0[None], u0[None]]))
+        tighter = 0
+        for i in range(len(lh)):
+            assert np.all(pre[i] >= lh[i] - 1e-9) and np.all(pre[i] <= uh[i] + 1e-9), i
+            assert np.all(lh[i] >= lh_ibp[i] - 1e-12) and np.all(uh[i] <= uh_ibp[i] + 1e-12), i
+            tighter += int(np.sum(lh[i] > lh_ibp[i] + 1e-9) + np.sum(uh[i] < uh_ibp[i] - 1e-9))
+        assert tighter > 0, w.name
+        if w.name.startswith("tiny"):
+            for i in range(2, len(ops)):
+                for j in range(ops[i - 1].n_out):
+                    e = np.zeros(ops[i - 1].n_out)
+                    e[j] = 1.0
+                    v_a = lp.lp_value(ops, l0, u0, lh, uh, e, "anderson", n_layers=i)
+                    assert lh[i - 1][j] <= max(v_a, lh_ibp[i - 1][j]) + 1e-9

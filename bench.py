@@ -381,6 +381,53 @@ def mnist_leg(A, np, torch, WL, reps=5):
             "as_iterations": it, "bound_mean": float(lb.mean().item()), "bound": "launch latency"}
 
 
+def intermediate_leg(A, np, torch, WL, w, net, lb_ibp, tuning):
+    """Solver-based intermediate bounds (App. E, eq:primal-intermediates) at
+    the benchmark's root box: layer 1 by interval propagation, every neuron
+    of layers 2 and 3 twice (rows e_j and -e_j) on its sub-network with the
+    benchmark's schedule (4096 + 200 subproblems), FP32 duals.  Reports the
+    time, the rate in subproblem-iterations, the width of each layer's
+    bounds against interval propagation, and the benchmark batch solved on
+    the tightened root bounds (the same subdomain fixes) against the
+    interval-propagation root."""
+    dev = "cuda:0"
+    t32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=dev)
+    sched = w.schedule
+    prm = A.params_from_schedule(sched)
+    l0, u0 = t32(w.l0[:1]), t32(w.u0[:1])
+    net.intermediate_bounds(l0, u0, prm)  # warm-up (workspace, code objects)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lh, uh = net.intermediate_bounds(l0, u0, prm)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    ilh, iuh = net.interval_bounds(l0, u0)
+    widths = []
+    for k in range(len(lh)):
+        r = ((uh[k] - lh[k]) / torch.clamp(iuh[k] - ilh[k], min=1e-12)).mean().item()
+        widths.append(round(float(r), 4))
+    subs = sum(2 * n for n in net.sizes[2:-1])
+    its = subs * (sched.bigm_iters + sched.as_iters)
+    # the benchmark batch on the tightened root bounds
+    L, U = WL.subdomain_bounds([a[0].cpu().numpy() for a in lh], [a[0].cpu().numpy() for a in uh], w.fix_draws,
+                               w.S)
+    plan = A.Plan(net, w.S, prm)
+    if tuning is not None:
+        plan.set_tuning(tuning)
+    lb = plan.solve(t32(w.l0), t32(w.u0), [t32(a) for a in L], [t32(a) for a in U], t32(w.c)).cpu().numpy()
+    return {"workload": f"root box of the {w.name} batch: layer 1 by interval propagation, layers 2 and 3 by "
+                        f"the solver on their sub-networks ({subs} subproblems, {sched.bigm_iters} Big-M + "
+                        f"{sched.as_iters} Active Set iterations each), FP32 duals",
+            "ms": round(ms, 1), "subproblems": subs,
+            "rate": round(its / (ms / 1e3), 1), "unit": "subproblem-iterations/s (wall clock of the call)",
+            "width_vs_interval": widths,
+            "batch_bound_mean_interval_root": round(float(np.mean(lb_ibp)), 5),
+            "batch_bound_mean_tightened_root": round(float(np.mean(lb)), 5),
+            "batch_bound_gain_mean": round(float(np.mean(lb - lb_ibp)), 5),
+            "batch_bound_gain_min": round(float(np.min(lb - lb_ibp)), 5),
+            "batch_verified_interval_root": int(np.sum(lb_ibp > 0)), "batch_verified_tightened_root": int(np.sum(lb > 0))}
+
+
 _ORACLE_W = None
 
 
@@ -528,6 +575,7 @@ def main():
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 matrix-core form")
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged two-net batch")
     ap.add_argument("--no-mnist", action="store_true", help="skip the MNIST-shaped MLP leg")
+    ap.add_argument("--no-intermediate", action="store_true", help="skip the solver-based intermediate bounds leg")
     ap.add_argument("--no-autotune", action="store_true", help="keep the heuristic kernel choices")
     ap.add_argument("--tuning", default=None, metavar="JSON",
                     help="kernel choices to set instead of autotuning (the 'tuning' object of a bench line)")
@@ -722,6 +770,10 @@ def main():
         print("[bench] ragged two-net batch", file=sys.stderr, flush=True)
         plan = None
         ragged = ragged_leg(A, np, torch, WL)
+    inter = None
+    if not args.no_intermediate:
+        print("[bench] intermediate bounds leg", file=sys.stderr, flush=True)
+        inter = intermediate_leg(A, np, torch, WL, w, net, lb_np, tuning)
     mnist = None
     if not args.no_mnist:
         print("[bench] MNIST-shaped MLP", file=sys.stderr, flush=True)
@@ -771,6 +823,7 @@ def main():
         "accuracy_where_verifiable": margin,
         "ragged": ragged,
         "mnist": mnist,
+        "intermediate_bounds": inter,
         "adjoint": adjoint,
         "bound_mean": float(np.mean(lb_np)),
         "verified_fraction": float(np.mean(lb_np > 0)),

@@ -53,8 +53,10 @@ typedef enum {
 typedef enum { ASD_LAYER_DENSE = 0, ASD_LAYER_CONV2D = 1 } asd_layer_kind;
 
 /* One affine layer x_hat_k = W_k x_{k-1} + b_k (Sec. 2).  Every layer but the
- * last is followed by a ReLU.  The last layer must be dense: its outputs are
- * combined by per-subproblem objective rows c (the paper's alpha_n).
+ * last is followed by a ReLU.  The last layer's outputs are combined by
+ * per-subproblem objective rows c (the paper's alpha_n).  It may be a
+ * convolution (the sub-networks of eq:primal-intermediates end in one);
+ * asd_bound_grad needs a dense one.
  * DENSE : in_c = inputs, out_c = outputs, in_h = in_w = 1, kernel/stride/pad
  *         ignored; W is [out_c][in_c] row-major.
  * CONV2D: cross-correlation with zero padding, square kernel `kernel`,
@@ -77,8 +79,8 @@ typedef struct asd_plan asd_plan;
 
 /* Copies the descriptors; W and b stay borrowed until asd_net_destroy.
  * Errors: ASD_EINVAL for n_layers outside [2, ASD_MAX_LAYERS], shape
- * mismatches between consecutive layers, a non-dense last layer, null
- * pointers or non-positive sizes. */
+ * mismatches between consecutive layers, null pointers or non-positive
+ * sizes. */
 asd_status asd_net_create(const asd_layer_desc* layers /* host */, int32_t n_layers,
                           asd_net** out /* host */);
 void asd_net_destroy(asd_net* net);
@@ -390,7 +392,8 @@ asd_status asd_oracle(asd_plan* plan, int32_t k, const void* x_prev, const void*
  *          guarantees that the network weights and the batch were not
  *          changed in place in between.  0: always recompute.
  * Overwrites the plan's minimiser buffers (as asd_bound does); the duals are
- * unchanged.  Errors: ASD_EINVAL for a NULL plan or g, or before asd_init. */
+ * unchanged.  Errors: ASD_EINVAL for a NULL plan or g, before asd_init, or a
+ * convolutional output layer. */
 asd_status asd_bound_grad(asd_plan* plan, const double* g, double* const* dW /* host */,
                           double* const* db /* host */, double* dl0, double* du0, int32_t reuse,
                           hipStream_t stream);
@@ -398,10 +401,39 @@ asd_status asd_bound_grad(asd_plan* plan, const double* g, double* const* dW /* 
 /* ---- Intermediate bounds (App. E; interval propagation) ---- */
 
 /* Pre-activation bounds of layers 1..n (FP64 arithmetic on the FP32 weights,
- * rounded to FP32): lhat[k], uhat[k] (k = 0..n_layers-1) [S][n_{k+1}] device
+ * rounded outward to FP32): lhat[k], uhat[k] (k = 0..n_layers-1) [S][n_{k+1}] device
  * floats, host array of device pointers.  l0, u0 [S][n_0]. */
 asd_status asd_interval_bounds(const asd_net* net, int32_t S, const float* l0, const float* u0,
                                float* const* lhat, float* const* uhat, hipStream_t stream);
+
+/* ---- Intermediate bounds by the solver (App. E, eq:primal-intermediates) ---- */
+
+/* Pre-activation bounds of the ReLU layers 1..n_layers-1 for D input boxes,
+ * each from problem eq:primal-intermediates: layer 1 by interval
+ * propagation (there the problem is a box-constrained LP); every neuron j of
+ * a layer k >= 2 by the solver with `params` (Big-M, then Active Set, in
+ * the plan precision `params->precision`) on the sub-network of layers
+ * 1..k with the bounds already found for layers 1..k-1: objective row e_j
+ * gives a lower bound of x_hat_k[j] and -e_j an upper bound (weak duality:
+ * every dual point bounds the problem), each combined with interval
+ * propagation from layer k-1 (lhat = max, uhat = min; the FP64 dual bounds
+ * rounded outward to FP32).  Every bound is valid whatever the number of
+ * iterations.  Layer k solves 2 n_k D subproblems on one plan in the
+ * workspace; the sub-network of a convolutional layer k ends in that
+ * convolution.
+ *   l0, u0      [D][n_0] device floats (input boxes)
+ *   lhat, uhat  host arrays [n_layers-1] of device pointers, [D][n_k]
+ *               floats (outputs, k = 1..n_layers-1)
+ *   workspace   device memory of at least
+ *               asd_intermediate_workspace_size(net, D, params) bytes, owned
+ *               by the caller (not needed, may be NULL, for 2 layers)
+ * Asynchronous on `stream`.  Errors: ASD_EINVAL for NULL arguments, D < 1,
+ * invalid params or a workspace that is too small. */
+asd_status asd_intermediate_workspace_size(const asd_net* net, int32_t D, const asd_params* params,
+                                           size_t* bytes /* host */);
+asd_status asd_intermediate_bounds(const asd_net* net, int32_t D, const asd_params* params, const float* l0,
+                                   const float* u0, float* const* lhat /* host */, float* const* uhat /* host */,
+                                   void* workspace, size_t bytes, hipStream_t stream);
 
 /* ---- Autotuning of the iteration kernels ---- */
 

@@ -668,7 +668,23 @@ def interval_step(op: LinearOp, l_prev: np.ndarray, u_prev: np.ndarray):
     return Wp @ l_prev + Wm @ u_prev + op.b, Wp @ u_prev + Wm @ l_prev + op.b
 
 
-def intermediate_bounds(ops: Sequence[LinearOp], l0, u0, prm: SolveParams):
+def _f32_down(x: float) -> float:
+    """The largest float32 value <= x."""
+    f = np.float32(x)
+    if float(f) > x:
+        f = np.nextafter(f, np.float32(-np.inf))
+    return float(f)
+
+
+def _f32_up(x: float) -> float:
+    """The smallest float32 value >= x."""
+    f = np.float32(x)
+    if float(f) < x:
+        f = np.nextafter(f, np.float32(np.inf))
+    return float(f)
+
+
+def intermediate_bounds(ops: Sequence[LinearOp], l0, u0, prm: SolveParams, fp32_bounds: bool = False):
     """Pre-activation bounds of the ReLU layers 1..n-1 from problem
     eq:primal-intermediates (App. E), its relaxation's dual solved by the
     same schedule as the last layer's bound (Algorithm 3, then Algorithm 1).
@@ -681,6 +697,11 @@ def intermediate_bounds(ops: Sequence[LinearOp], l0, u0, prm: SolveParams):
     minimum); each is combined with interval propagation of layer i from
     the bounds of layer i-1: lhat_i[j] = max(ibp, d_j), uhat_i[j] =
     min(ibp, -d'_j).  Returns (lhat, uhat), lists over layers 1..n-1.
+
+    fp32_bounds: each layer's bounds are stored as float32 values before the
+    next layer uses them (a storage choice of an implementation, not of the
+    paper), rounded outward (down for lhat, up for uhat) so that every stored
+    bound stays valid.
     """
     l0 = np.asarray(l0, np.float64)
     u0 = np.asarray(u0, np.float64)
@@ -689,6 +710,9 @@ def intermediate_bounds(ops: Sequence[LinearOp], l0, u0, prm: SolveParams):
     l_prev, u_prev = l0, u0
     for i in range(1, len(ops)):
         lo, hi = interval_step(ops[i - 1], l_prev, u_prev)
+        if fp32_bounds:
+            lo = np.array([_f32_down(v) for v in lo])
+            hi = np.array([_f32_up(v) for v in hi])
         if i >= 2:
             n_i = ops[i - 1].n_out
             for j in range(n_i):
@@ -696,6 +720,8 @@ def intermediate_bounds(ops: Sequence[LinearOp], l0, u0, prm: SolveParams):
                 e[j] = 1.0
                 d_lo = solve(make_problem(ops[:i], l0, u0, lhat, uhat, e), prm).bound
                 d_hi = solve(make_problem(ops[:i], l0, u0, lhat, uhat, -e), prm).bound
+                if fp32_bounds:
+                    d_lo, d_hi = _f32_down(d_lo), -_f32_up(-d_hi)
                 lo[j] = max(lo[j], d_lo)
                 hi[j] = min(hi[j], -d_hi)
         lhat.append(lo)

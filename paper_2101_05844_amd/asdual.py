@@ -101,7 +101,8 @@ EXPORTED = ["asd_net_create", "asd_net_destroy", "asd_params_default", "asd_plan
             "asd_state_get", "asd_state_set", "asd_state_get_counts", "asd_state_set_counts",
             "asd_eval", "asd_oracle", "asd_bound_grad", "asd_set_budgets", "asd_solve_group", "asd_solve_graph", "asd_check_finite",
             "asd_plan_autotune", "asd_plan_get_tuning", "asd_plan_set_tuning", "asd_interval_bounds", "asd_profile_enable", "asd_profile_read",
-            "asd_solve_static", "asd_last_error", "asd_abi_version"]
+            "asd_solve_static", "asd_intermediate_workspace_size", "asd_intermediate_bounds",
+            "asd_last_error", "asd_abi_version"]
 
 
 def lib():
@@ -143,6 +144,9 @@ def lib():
     L.asd_plan_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
     L.asd_solve_group.argtypes = [C.POINTER(vp), C.POINTER(C.POINTER(Batch)), C.POINTER(vp), i32, C.POINTER(vp)]
     L.asd_interval_bounds.argtypes = [vp, i32, vp, vp, C.POINTER(vp), C.POINTER(vp), vp]
+    L.asd_intermediate_workspace_size.argtypes = [vp, i32, C.POINTER(Params), C.POINTER(C.c_size_t)]
+    L.asd_intermediate_bounds.argtypes = [vp, i32, C.POINTER(Params), vp, vp, C.POINTER(vp), C.POINTER(vp), vp,
+                                          C.c_size_t, vp]
     L.asd_profile_enable.argtypes = [vp, i32]
     L.asd_profile_read.argtypes = [vp, C.POINTER(KernelTime), i32, C.POINTER(i32)]
     L.asd_last_error.argtypes = []
@@ -235,6 +239,25 @@ class Net:
         lp = (C.c_void_p * self.n)(*[t.data_ptr() for t in lh])
         up = (C.c_void_p * self.n)(*[t.data_ptr() for t in uh])
         _check(lib().asd_interval_bounds(self.handle, S, _ptr(l0), _ptr(u0), lp, up, _stream(stream)))
+        return lh, uh
+
+    def intermediate_bounds(self, l0: torch.Tensor, u0: torch.Tensor, params: Params, stream=None):
+        """asd_intermediate_bounds: pre-activation bounds of the ReLU layers
+        1..n-1 for D boxes l0, u0 [D][n_0] (float32, device), each layer k >= 2
+        from the solver on its sub-network; the workspace is a torch tensor
+        held for the call."""
+        D = l0.shape[0]
+        nbytes = C.c_size_t()
+        _check(lib().asd_intermediate_workspace_size(self.handle, D, C.byref(params), C.byref(nbytes)))
+        ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=l0.device)
+        lh = [torch.empty(D, n, device=l0.device, dtype=torch.float32) for n in self.sizes[1:-1]]
+        uh = [torch.empty_like(t) for t in lh]
+        lp = (C.c_void_p * max(1, len(lh)))(*[t.data_ptr() for t in lh])
+        up = (C.c_void_p * max(1, len(uh)))(*[t.data_ptr() for t in uh])
+        _check(lib().asd_intermediate_bounds(self.handle, D, C.byref(params), _ptr(l0), _ptr(u0), lp, up,
+                                             ws.data_ptr(), nbytes.value + 256, _stream(stream)))
+        # the workspace must outlive the queued kernels
+        (torch.cuda.current_stream() if stream is None else stream).synchronize()
         return lh, uh
 
 

@@ -125,6 +125,10 @@ void carve_t(asd_plan* P, Carver& cv) {
     T* cv_arr = cv.take<T>((size_t)P->nl[P->n].N * S);
     if (sizeof(T) == 4) P->cvecf = reinterpret_cast<float*>(cv_arr);
     else P->cvecd = reinterpret_cast<double*>(cv_arr);
+    // a convolutional output layer: -c as the operand of the iteration
+    // kernels' transposed convolution into the last ReLU layer
+    P->negc = (sizeof(T) == 4 && P->geo[P->n].kind == ASD_LAYER_CONV2D) ? cv.take<float>((size_t)P->nl[P->n].N * S)
+                                                                        : nullptr;
     size_t part = 0;
     for (int L = 1; L <= P->n; ++L) {
         const LayerGeo& g = P->geo[L];
@@ -578,10 +582,11 @@ asd_status reduce_objective(asd_plan* P, double* out, hipStream_t st) {
         a.nl[k] = P->nl[k];
         a.term[k] = NA<T>(P)[k].term;
     }
-    // b_n^T c_s from the internal copy of c (layout n: [n_last][S])
+    // b_n^T c_s from the internal copy of c (layout of layer n)
     a.cint = CV<T>(P);
     a.bn = P->geo[P->n].b;
-    a.n_last = P->nl[P->n].C;
+    a.c_last = P->nl[P->n].C;
+    a.p_last = P->nl[P->n].P;
     a.out = out;
     hipLaunchKernelGGL(k_reduce_obj<T>, dim3((unsigned)P->S), dim3(256), 0, st, a);
     LAUNCH_CHECK();
@@ -767,6 +772,12 @@ asd_status init_t(asd_plan* P, const asd_batch* b, hipStream_t st) {
     for (int k = 0; k < P->n; ++k)
         TRY((launch_bits<T, T>(P->nl[k], S, 3, na[k].deg, nullptr, na[k].lo, na[k].hi, st)));
     TRY((launch_layout<T, const float>(CV<T>(P), b->c, P->nl[P->n], S, 0, st)));
+    if (P->negc) {
+        const long n = (long)P->nl[P->n].N * S;
+        hipLaunchKernelGGL(k_negate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, P->negc,
+                           reinterpret_cast<const float*>(CV<T>(P)), n);
+        LAUNCH_CHECK();
+    }
     for (int k = 1; k < P->n; ++k) {
         const size_t ns = (size_t)P->nl[k].N * S;
         ReluLayerT<T>& r = RL<T>(P)[k];
@@ -1387,7 +1398,6 @@ asd_status asd_net_create(const asd_layer_desc* layers, int32_t n_layers, asd_ne
             }
         }
     }
-    if (layers[n_layers - 1].kind != ASD_LAYER_DENSE) return fail(ASD_EINVAL, "the last layer must be dense");
     asd_net* net = new (std::nothrow) asd_net;
     if (!net) return fail(ASD_EINVAL, "host allocation failed");
     net->n = n_layers;
@@ -1587,6 +1597,8 @@ asd_status asd_bound_grad(asd_plan* P, const double* gs, double* const* dW, doub
                           double* du0, int32_t reuse, hipStream_t st) {
     if (!P || !gs) return fail(ASD_EINVAL, "NULL argument");
     if (!P->loaded) return fail(ASD_EINVAL, "asd_init has not been called");
+    if (P->geo[P->n].kind != ASD_LAYER_DENSE)
+        return fail(ASD_EINVAL, "the bound gradient needs a dense output layer");
     return is64(P) ? bound_grad_t<double>(P, gs, dW, db, dl0, du0, reuse, st)
                    : bound_grad_t<float>(P, gs, dW, db, dl0, du0, reuse, st);
 }
@@ -1746,6 +1758,153 @@ asd_status asd_oracle(asd_plan* P, int32_t k, const void* x_prev, const void* z,
                                 mask_bits, reinterpret_cast<double*>(LI), reinterpret_cast<double*>(UI), st);
     return oracle_t<float>(P, k, reinterpret_cast<const float*>(x_prev), reinterpret_cast<const float*>(z),
                            mask_bits, reinterpret_cast<float*>(LI), reinterpret_cast<float*>(UI), st);
+}
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Workspace of asd_intermediate_bounds for ReLU layer k >= 2: the
+// replicated batch of the sub-network of layers 1..k (2 n_k D subproblems),
+// their bounds, and the sub-network's plan.
+struct IbLayout {
+    int S;
+    size_t l0, u0, lh[kMaxLayers], uh[kMaxLayers], c, d, plan, total;
+};
+
+asd_status ib_layout(const asd_net& sub, const asd_plan& full, int D, const asd_params* prm, IbLayout& lay) {
+    const int k = sub.n;
+    const long S = 2L * full.nl[k].N * D;
+    if (S > (1L << 30)) return fail(ASD_EINVAL, "layer %d: %ld subproblems", k, S);
+    lay.S = (int)S;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align256(off + bytes);
+        return at;
+    };
+    lay.l0 = take(sizeof(float) * S * full.nl[0].N);
+    lay.u0 = take(sizeof(float) * S * full.nl[0].N);
+    for (int i = 1; i < k; ++i) {
+        lay.lh[i] = take(sizeof(float) * S * full.nl[i].N);
+        lay.uh[i] = take(sizeof(float) * S * full.nl[i].N);
+    }
+    lay.c = take(sizeof(float) * S * full.nl[k].N);
+    lay.d = take(sizeof(double) * S);
+    size_t pb = 0;
+    TRY(asd_plan_workspace_size(&sub, lay.S, prm, &pb));
+    lay.plan = take(pb);
+    lay.total = off;
+    return ASD_OK;
+}
+
+asd_status launch_ibp(const LayerGeo& g, int S, const float* lo, const float* hi, bool clamp, float* lo_out,
+                      float* hi_out, hipStream_t st) {
+    IbpArgs a;
+    a.g = g;
+    a.S = S;
+    a.lo_in = lo;
+    a.hi_in = hi;
+    a.clamp_in = clamp;
+    a.lo_out = lo_out;
+    a.hi_out = hi_out;
+    const long n = (long)S * g.out.N;
+    hipLaunchKernelGGL(k_ibp, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+    LAUNCH_CHECK();
+    return ASD_OK;
+}
+
+asd_status launch_rows(float* dst, const float* src, long rows, long n, int per, hipStream_t st) {
+    const long tot = rows * n;
+    hipLaunchKernelGGL(k_bcast_rows, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, dst, src, rows, (int)n,
+                       per);
+    LAUNCH_CHECK();
+    return ASD_OK;
+}
+
+}  // namespace
+
+asd_status asd_intermediate_workspace_size(const asd_net* net, int32_t D, const asd_params* params, size_t* bytes) {
+    if (!net || !params || !bytes) return fail(ASD_EINVAL, "NULL argument");
+    if (D < 1) return fail(ASD_EINVAL, "D must be >= 1");
+    TRY(check_params(params));
+    asd_plan full{};
+    full.net = net;
+    full.S = D;
+    full.n = net->n;
+    setup_plan_geometry(&full);
+    size_t need = 256;
+    for (int k = 2; k < net->n; ++k) {
+        asd_net sub;
+        sub.n = k;
+        sub.L.assign(net->L.begin(), net->L.begin() + k);
+        IbLayout lay;
+        TRY(ib_layout(sub, full, D, params, lay));
+        need = std::max(need, lay.total + 256);
+    }
+    *bytes = need;
+    return ASD_OK;
+}
+
+asd_status asd_intermediate_bounds(const asd_net* net, int32_t D, const asd_params* params, const float* l0,
+                                   const float* u0, float* const* lhat, float* const* uhat, void* workspace,
+                                   size_t bytes, hipStream_t st) {
+    if (!net || !params || !l0 || !u0 || !lhat || !uhat) return fail(ASD_EINVAL, "NULL argument");
+    if (D < 1) return fail(ASD_EINVAL, "D must be >= 1");
+    for (int k = 1; k < net->n; ++k)
+        if (!lhat[k - 1] || !uhat[k - 1]) return fail(ASD_EINVAL, "NULL output of layer %d", k);
+    size_t need = 0;
+    TRY(asd_intermediate_workspace_size(net, D, params, &need));
+    if (net->n > 2 && (!workspace || bytes < need))
+        return fail(ASD_EINVAL, "workspace of %zu bytes; asd_intermediate_workspace_size asks %zu", bytes, need);
+    asd_plan full{};
+    full.net = net;
+    full.S = D;
+    full.n = net->n;
+    setup_plan_geometry(&full);
+    char* base = reinterpret_cast<char*>(align256(reinterpret_cast<size_t>(workspace)));
+    for (int k = 1; k < net->n; ++k) {
+        // interval propagation from the bounds found for layer k-1
+        TRY(launch_ibp(full.geo[k], D, k == 1 ? l0 : lhat[k - 2], k == 1 ? u0 : uhat[k - 2], k > 1, lhat[k - 1],
+                       uhat[k - 1], st));
+        if (k == 1) continue;  // the box-constrained LP: interval propagation is exact
+        asd_net sub;
+        sub.n = k;
+        sub.L.assign(net->L.begin(), net->L.begin() + k);
+        IbLayout lay;
+        TRY(ib_layout(sub, full, D, params, lay));
+        const int nk = (int)full.nl[k].N;
+        const int per = 2 * nk;
+        float* l0s = reinterpret_cast<float*>(base + lay.l0);
+        float* u0s = reinterpret_cast<float*>(base + lay.u0);
+        TRY(launch_rows(l0s, l0, lay.S, full.nl[0].N, per, st));
+        TRY(launch_rows(u0s, u0, lay.S, full.nl[0].N, per, st));
+        const float* lhp[kMaxLayers] = {};
+        const float* uhp[kMaxLayers] = {};
+        for (int i = 1; i < k; ++i) {
+            float* a = reinterpret_cast<float*>(base + lay.lh[i]);
+            float* b = reinterpret_cast<float*>(base + lay.uh[i]);
+            TRY(launch_rows(a, lhat[i - 1], lay.S, full.nl[i].N, per, st));
+            TRY(launch_rows(b, uhat[i - 1], lay.S, full.nl[i].N, per, st));
+            lhp[i - 1] = a;
+            uhp[i - 1] = b;
+        }
+        float* c = reinterpret_cast<float*>(base + lay.c);
+        const long nc = (long)lay.S * nk;
+        hipLaunchKernelGGL(k_ib_objective, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, c, (long)lay.S, nk);
+        LAUNCH_CHECK();
+        double* dB = reinterpret_cast<double*>(base + lay.d);
+        // the sub-network's solve on a plan held by this frame (every launch
+        // takes what it needs as kernel arguments)
+        asd_plan P{};
+        bind_plan(&P, &sub, lay.S, params, base + lay.plan);
+        const asd_batch b{lay.S, l0s, u0s, lhp, uhp, c};
+        TRY(asd_solve(&P, &b, dB, nullptr, st));
+        hipLaunchKernelGGL(k_ib_combine, dim3((unsigned)(((long)D * nk + 255) / 256)), dim3(256), 0, st,
+                           lhat[k - 1], uhat[k - 1], (const double*)dB, D, nk);
+        LAUNCH_CHECK();
+    }
+    return ASD_OK;
 }
 
 asd_status asd_interval_bounds(const asd_net* net, int32_t S, const float* l0, const float* u0,

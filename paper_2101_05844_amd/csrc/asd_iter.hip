@@ -185,6 +185,8 @@ asd_status bwd_fast_impl(asd_plan* P, int k, hipStream_t st) {
         const ReluLayerT<T>& rn = RL<T>(P)[k + 1];
         a.vs = rn.vs;
         for (int q = 0; q < NM; ++q) a.u[q] = rn.slot[q].u;
+    } else {
+        a.vs = P->negc;  // a convolutional output layer's operand (dense ones read cvec)
     }
     a.xpk = NA<T>(P)[k].xpk;
     a.nk = NA<T>(P)[k];

@@ -840,9 +840,9 @@ struct ReduceArgs {
     int nlayers;                       // neuron layers 0..n-1
     NeuronLayout nl[kMaxLayers];
     const double* term[kMaxLayers];
-    const T* cint;                     // objective rows, internal layout [n_last][S]
-    const float* bn;
-    int n_last;
+    const T* cint;                     // objective rows, internal layout of layer n ([C][S][P])
+    const float* bn;                   // bias of layer n, per channel
+    int c_last, p_last;                // channels and positions of layer n
     double* out;
 };
 
@@ -854,6 +854,45 @@ static __global__ void __launch_bounds__(256) k_flags_bound(const double* lb, co
                                                             int S) {
     const int s = blockIdx.x * 256 + threadIdx.x;
     if (s < S) flags[s] = (isfinite(lb[s]) ? 0 : 1) | inflags[s];
+}
+
+// Intermediate bounds by the solver (App. E): the replicated batch of the
+// sub-network's 2 n_k D subproblems, subproblem s = (2 d + h) n_k + j for box
+// d, neuron j, h = 0 (lower bound, row e_j) or 1 (upper bound, row -e_j).
+// Row r of dst [rows][n] = row r / per of src.
+static __global__ void __launch_bounds__(256) k_bcast_rows(float* dst, const float* src, long rows, int n, int per) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= rows * n) return;
+    const long r = i / n;
+    dst[i] = src[(r / per) * n + (i - r * n)];
+}
+
+static __global__ void __launch_bounds__(256) k_ib_objective(float* c, long S, int nk) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= S * nk) return;
+    const long s = i / nk;
+    const int e = (int)(i - s * nk), j = (int)(s % nk);
+    const bool up = (s / nk) % 2 == 1;
+    c[i] = e == j ? (up ? -1.f : 1.f) : 0.f;
+}
+
+// lhat = max(lhat, d_lo), uhat = min(uhat, -d_hi), the dual bounds rounded
+// outward to FP32; a bound that is not finite leaves the interval bound.
+static __global__ void __launch_bounds__(256) k_ib_combine(float* lhat, float* uhat, const double* dB, int D, int nk) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (long)D * nk) return;
+    const long d = i / nk;
+    const int j = (int)(i - d * nk);
+    const double lo = dB[(2 * d) * nk + j], hi = -dB[(2 * d + 1) * nk + j];
+    if (isfinite(lo)) lhat[i] = fmaxf(lhat[i], __double2float_rd(lo));
+    if (isfinite(hi)) uhat[i] = fminf(uhat[i], __double2float_ru(hi));
+}
+
+// dst = -src (n entries): the backward operand of a convolutional output
+// layer, -c in its internal layout.
+static __global__ void __launch_bounds__(256) k_negate(float* dst, const float* src, long n) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) dst[i] = -src[i];
 }
 
 // Input check of a batch (caller layout [S][n]): bit 2 of flags[s] is set
@@ -908,7 +947,9 @@ __global__ void __launch_bounds__(256) k_reduce_obj(ReduceArgs<T> A) {
         }
     }
     if (threadIdx.x == 0)
-        for (int i = 0; i < A.n_last; ++i) acc += (double)A.bn[i] * (double)A.cint[(long)i * A.S + s];
+        for (int ch = 0; ch < A.c_last; ++ch)
+            for (int p = 0; p < A.p_last; ++p)
+                acc += (double)A.bn[ch] * (double)A.cint[((long)ch * A.S + s) * A.p_last + p];
     part[threadIdx.x] = acc;
     __syncthreads();
     for (int w = blockDim.x / 2; w > 0; w >>= 1) {

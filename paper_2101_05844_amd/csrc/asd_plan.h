@@ -103,6 +103,7 @@ struct asd_plan {
     void* lrs;                        // [S] learning rates of the current iteration (T)
     int Sa;                           // subproblems the current iteration updates (a prefix)
     int lds_max;                      // LDS bytes one block may use on the plan's device
+    float* negc;                      // convolutional output layer (FP32 duals): -c, layout of layer n
     // captured iteration schedule (asd_solve_graph) and the host state it ends in
     hipGraphExec_t graph_exec;
     bool graph_valid;
@@ -275,6 +276,8 @@ FastBwdArgs<T> bwd_args(asd_plan* P, int k, int nm) {
         const ReluLayerT<T>& rn = RL<T>(P)[k + 1];
         a.vs = rn.vs;
         for (int q = 0; q < nm; ++q) a.u[q] = rn.slot[q].u;
+    } else {
+        a.vs = reinterpret_cast<const T*>(P->negc);  // a convolutional output layer's operand
     }
     a.xpk = NA<T>(P)[k].xpk;
     a.nk = NA<T>(P)[k];

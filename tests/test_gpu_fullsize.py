@@ -402,3 +402,36 @@ def test_adjoint_sampled_oracle(adjoint_solved):
         for s in used:
             ref = gs[s] * ora[s][i]
             assert np.all(np.abs(gg[s] - ref) <= 1e-9 * (1 + np.abs(ref))), (i, s)
+
+
+def test_fullsize_intermediate_bounds_valid(cifar):
+    """Solver-based intermediate bounds (App. E) of the Wide net at the
+    benchmark's root box, FP32 inner solves on a short schedule: layer 2
+    solves 4096 subproblems on the sub-network ending in the second
+    convolution, layer 3 solves 200.  Every bound contains the
+    pre-activations of sampled inputs and is at least as tight as interval
+    propagation; the widths of layers 2 and 3 shrink (60 iterations: by a
+    little; the benchmark reports the full schedule)."""
+    w, ops, L, U = cifar
+    from paper_2101_05844_amd import asdual as A
+    A.lib()
+    sched = WL.Schedule(bigm_iters=40, as_iters=20, add_every=450, add_count=2, max_masks=7)
+    prm = A.params_from_schedule(sched, A.ASD_PREC_FP32)
+    net = A.Net(w.layers)
+    t = lambda a: torch.as_tensor(H.f32(a), device="cuda").contiguous()
+    lh, uh = net.intermediate_bounds(t(w.l0[:1]), t(w.u0[:1]), prm)
+    lh = [a[0].cpu().numpy().astype(np.float64) for a in lh]
+    uh = [a[0].cpu().numpy().astype(np.float64) for a in uh]
+    l0, u0 = w.l0[0].astype(np.float64), w.u0[0].astype(np.float64)
+    ibl, ibu = O.interval_bounds(ops, l0, u0)
+    xs = WL.random_points_in_box(w.l0[0], w.u0[0], 2000, seed=8)
+    x = xs.T.astype(np.float64)
+    for k in range(len(lh)):
+        x = ops[k].W @ x + ops[k].b[:, None]
+        assert np.all(x.T >= lh[k] - 1e-5) and np.all(x.T <= uh[k] + 1e-5), k
+        x = np.maximum(x, 0.0)
+        assert np.all(lh[k] >= ibl[k] - 1e-5 * (1 + np.abs(ibl[k]))), k
+        assert np.all(uh[k] <= ibu[k] + 1e-5 * (1 + np.abs(ibu[k]))), k
+    ratios = [float(np.mean((uh[k] - lh[k]) / np.maximum(ibu[k] - ibl[k], 1e-12))) for k in (1, 2)]
+    print("layers 2, 3: mean width / interval width", ratios, flush=True)
+    assert all(r < 0.999 for r in ratios), ratios

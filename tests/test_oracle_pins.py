@@ -727,6 +727,16 @@ def test_intermediate_bounds_valid_and_tighter():
             assert np.all(lh[i] >= lh_ibp[i] - 1e-12) and np.all(uh[i] <= uh_ibp[i] + 1e-12), i
             tighter += int(np.sum(lh[i] > lh_ibp[i] + 1e-9) + np.sum(uh[i] < uh_ibp[i] - 1e-9))
         assert tighter > 0, w.name
+        # float32 storage between layers: representable, still valid, and
+        # close to the exact run (a run's solves part at near-ties when their
+        # inputs move by a float32 unit, so "close" is a share of the width)
+        fl, fu = O.intermediate_bounds(ops, l0, u0, prm, fp32_bounds=True)
+        for i in range(len(fl)):
+            assert np.array_equal(fl[i], fl[i].astype(np.float32)) and np.array_equal(fu[i], fu[i].astype(np.float32))
+            assert np.all(pre[i] >= fl[i] - 1e-9) and np.all(pre[i] <= fu[i] + 1e-9), i
+            width = uh_ibp[i] - lh_ibp[i]
+            assert np.all(np.abs(fl[i] - lh[i]) <= 0.01 * width + 1e-6), i
+            assert np.all(np.abs(fu[i] - uh[i]) <= 0.01 * width + 1e-6), i
         if w.name.startswith("tiny"):
             for i in range(2, len(ops)):
                 for j in range(ops[i - 1].n_out):

@@ -52,6 +52,15 @@ is kept with the design notes):
       step counter; the step size is not rescaled at additions.
   R10 Learning rates decrease linearly: lr_t = lr0 + (lr1 - lr0) t / (T - 1).
   R11 The returned bound is d at the final duals (Algorithm 1's return).
+  R20 l2-ball input domain (Sec. 2 allows any convex C; l2 balls among the
+      examples): x*_0 maximises f_0^T x_0 over the ball (the centre moved by
+      the radius along f_0); the check matrices of layer 1 use the ball's
+      box hull as [l_0, u_0]; no masks are added at layer 1.  At an interior
+      x*_0 (every x*_0 but where f_0 has one nonzero entry) eq:oracle gives
+      only all-one rows (z = 1) and rows selecting the zero weights
+      (z = 0), whose constraints x <= x_hat - (W Lchk)(1 - z) and
+      x <= (b + W Uchk) z are implied by the beta_0 and beta_1 constraints
+      for pre-activation bounds within the box hull's interval bounds.
 """
 from __future__ import annotations
 
@@ -188,6 +197,10 @@ class Problem:
     lhat: List[np.ndarray]
     uhat: List[np.ndarray]
     c: np.ndarray
+    # input domain C (Sec. 2): None for the box [l0, u0]; (centre, radius)
+    # for the l2 ball, whose box hull [l0, u0] then bounds x_0 in the
+    # check matrices of layer 1 (R20)
+    ball: Optional[tuple] = None
 
     @property
     def n(self) -> int:
@@ -210,9 +223,10 @@ class Problem:
         return self.lhat[k - 1], self.uhat[k - 1]
 
 
-def make_problem(ops, l0, u0, lhat, uhat, c) -> Problem:
+def make_problem(ops, l0, u0, lhat, uhat, c, ball=None) -> Problem:
     f64 = lambda a: np.asarray(a, dtype=np.float64).copy()
-    return Problem(ops, f64(l0), f64(u0), [f64(a) for a in lhat], [f64(a) for a in uhat], f64(c))
+    b = None if ball is None else (f64(ball[0]), float(ball[1]))
+    return Problem(ops, f64(l0), f64(u0), [f64(a) for a in lhat], [f64(a) for a in uhat], f64(c), b)
 
 
 # ----------------------------------------------------------------------------
@@ -393,12 +407,23 @@ def dual_functions(p: Problem, st: DualState):
     return f, g, const
 
 
+def ball_maximiser(f0: np.ndarray, centre: np.ndarray, radius: float) -> np.ndarray:
+    """argmax of f0^T x over the l2 ball ||x - centre|| <= radius: the centre
+    moved by radius along f0 (the centre itself where f0 = 0)."""
+    nrm = float(np.linalg.norm(f0))
+    return centre.copy() if nrm == 0.0 else centre + radius * f0 / nrm
+
+
 def inner_min(p: Problem, f, g):
     """Closed-form minimiser of L_B over the primal box (eq:as-primalk-min,
-    eq:as-primal0-min, with readings R1, R2, R6)."""
+    eq:as-primal0-min, with readings R1, R2, R6); over an l2 ball input
+    domain x*_0 maximises f_0^T x_0 on the ball (R2, R20)."""
     x = []
     for k in range(0, p.n):
         l, u = p.lu(k)
+        if k == 0 and p.ball is not None:
+            x.append(ball_maximiser(f[0], p.ball[0], p.ball[1]))
+            continue
         x.append(np.where(f[k] >= 0, u, l))
     z = [np.where(gk >= 0, 1.0, 0.0) for gk in g]
     return x, z
@@ -566,6 +591,8 @@ def add_masks(p: Problem, st: DualState, x, z):
     """Active-set extension (Algorithm 1): for each layer k, append the
     oracle's mask called at the current (x*, z*) with beta_{k,I} = 0."""
     for k in range(1, p.n):
+        if k == 1 and p.ball is not None:
+            continue  # R20: at an interior x*_0 layer 1's masks repeat beta_0 / beta_1 constraints
         op = p.W(k)
         l_prev, u_prev = p.lu(k - 1)
         I = oracle_mask(op, l_prev, u_prev, x[k - 1], z[k - 1])
@@ -603,7 +630,7 @@ def bigm_iteration(p: Problem, st: DualState, lr: float, prm: SolveParams):
 def as_iteration(p: Problem, st: DualState, t: int, lr: float, prm: SolveParams):
     """One iteration of Algorithm 1's inner loop."""
     d, x, z, _, _ = evaluate(p, st)
-    n_active = len(st.masks[0]) if st.masks else 0
+    n_active = max(len(m) for m in st.masks) if st.masks else 0
     if p.n > 1 and is_addition_iter(t, prm, n_active):
         add_masks(p, st, x, z)
     apply_step(st, supergradient(p, st, x, z), lr, prm.rule, prm.adam)
@@ -776,6 +803,7 @@ def bound_gradient(p: Problem, st: DualState):
                      + sum_I beta_I[i] ((1 - z*_k[i]) I[i,j] Lchk[i,j]
                                         - z*_k[i] (1 - I[i,j]) Uchk[i,j]),
       dd/db_k[i]   = alpha_k[i] - beta_{k,1}[i] - z*_k[i] sum_I beta_I[i],
+    (box input domains only)
     for k = 1..n-1 (LI and UI are the row sums of W . I . Lchk and
     W . (1 - I) . Uchk, Sec. 2.2, with the check entries chosen by the sign
     of W); for the last layer dd/dW_n = c x*_{n-1}^T, dd/db_n = c.  The input
@@ -784,6 +812,8 @@ def bound_gradient(p: Problem, st: DualState):
     constants.  Returns (dW, db, dl0, du0): dW[k-1] and db[k-1] in the shapes
     of layer k's weight tensor and bias (entries of a convolution summed over
     positions)."""
+    if p.ball is not None:
+        raise ValueError("the bound gradient is defined here for box input domains")
     d, x, z, f, g = evaluate(p, st)
     n = p.n
     dW, db = [], []

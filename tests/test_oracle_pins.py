@@ -744,3 +744,98 @@ def test_intermediate_bounds_valid_and_tighter():
                     e[j] = 1.0
                     v_a = lp.lp_value(ops, l0, u0, lh, uh, e, "anderson", n_layers=i)
                     assert lh[i - 1][j] <= max(v_a, lh_ibp[i - 1][j]) + 1e-9
+
+
+# ----------------------------------------------------------------------------
+# l2-ball input domain (Sec. 2 input set C; reading R20)
+# ----------------------------------------------------------------------------
+
+
+def ball_points(centre, radius, m, rng):
+    """m points of the l2 ball (uniform directions and radii r U^(1/n)), plus
+    the points where the sampled directions meet the sphere."""
+    n = centre.size
+    d = rng.normal(size=(m, n))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    r = radius * rng.uniform(0, 1, (m, 1)) ** (1.0 / n)
+    return np.concatenate([centre + r * d, centre + radius * d])
+
+
+def ball_problem(ops, centre, radius, c):
+    l0, u0 = centre - radius, centre + radius
+    lh, uh = O.interval_bounds(ops, l0, u0)
+    return O.make_problem(ops, l0, u0, lh[:-1], uh[:-1], c, ball=(centre, radius))
+
+
+def test_ball_maximiser_closed_form():
+    """x*_0 over the l2 ball: on the sphere, along f_0, and no sampled point
+    of the ball has a larger f_0^T x (eq:as-primal0-min, R2)."""
+    rng = np.random.default_rng(11)
+    centre = rng.normal(size=9)
+    f0 = rng.normal(size=9)
+    x = O.ball_maximiser(f0, centre, 0.3)
+    assert np.linalg.norm(x - centre) == pytest.approx(0.3, rel=1e-12)
+    assert np.allclose(np.cross(np.stack([x - centre, f0])[:, :3][0], f0[:3]), 0, atol=1e-12)
+    pts = ball_points(centre, 0.3, 20000, rng)
+    assert np.all(pts @ f0 <= x @ f0 + 1e-12)
+    assert np.array_equal(O.ball_maximiser(np.zeros(9), centre, 0.3), centre)
+
+
+def test_ball_single_linear_layer_is_exact():
+    """With no ReLU layer the dual is exact: min over the ball of
+    c^T (W x + b) = c^T (W centre + b) - radius ||W^T c||_2 (a textbook
+    closed form), at any duals."""
+    rng = np.random.default_rng(12)
+    W, b, c = rng.normal(size=(4, 7)), rng.normal(size=4), rng.normal(size=4)
+    ops = [O.dense_op(W, b)]
+    centre, radius = rng.normal(size=7), 0.4
+    p = O.make_problem(ops, centre - radius, centre + radius, [], [], c, ball=(centre, radius))
+    d = O.evaluate(p, O.zero_state(p))[0]
+    assert d == pytest.approx(c @ (W @ centre + b) - radius * np.linalg.norm(W.T @ c), rel=1e-12)
+    assert O.solve(p, O.SolveParams(bigm_iters=5, as_iters=5)).bound == pytest.approx(d, rel=1e-12)
+
+
+def test_ball_bounds_are_valid_and_tighter_than_the_box_hull():
+    """Multi-layer nets over an l2 ball: every iterate of the solve stays
+    below the network's output at sampled points of the ball (weak duality),
+    and the bound is at least the same solve's bound over the ball's box
+    hull (the ball lies inside it)."""
+    rng = np.random.default_rng(13)
+    for w in (WL.tiny_config(), WL.custom_config([WL.ConvSpec(1, 6, 6, 3, 3, 2, 1), WL.ConvSpec(3, 3, 3, 4, 2, 1, 0), WL.DenseSpec(16, 5), WL.DenseSpec(5, 2)], S=1, seed=22, eps=0.05)):
+        ops = O.ops_from_workload_layers(w.layers)
+        centre = ((w.l0[0] + w.u0[0]) / 2).astype(np.float64)
+        radius = 0.5 * float(np.max(w.u0[0] - w.l0[0]))
+        c = w.c[0].astype(np.float64)
+        p = ball_problem(ops, centre, radius, c)
+        prm = O.SolveParams(bigm_iters=40, as_iters=30, add_every=10, add_count=2, max_masks=3)
+        r = O.solve(p, prm, trace=True)
+        outs = O.network_output(ops, ball_points(centre, radius, 3000, rng)) @ c
+        assert max(r.trace) <= outs.min() + 1e-9, w.name
+        assert r.bound <= outs.min() + 1e-9
+        pb = O.make_problem(ops, p.l0, p.u0, p.lhat, p.uhat, c)
+        rb = O.solve(pb, prm)
+        assert r.bound >= rb.bound - 1e-9, (w.name, r.bound, rb.bound)
+        assert all(len(m) == 0 for m in r.state.masks[:1]) and all(len(m) == 3 for m in r.state.masks[1:])
+
+
+def test_ball_layer1_masks_repeat_bigm_constraints():
+    """R20: at an interior x*_0 the separation oracle's layer-1 rows are all
+    ones where z = 1 and exactly the zero weights where z = 0 (eq:oracle),
+    so their constraints are the Big-M ones over the box hull."""
+    rng = np.random.default_rng(14)
+    W = rng.normal(size=(6, 5))
+    W[rng.uniform(size=W.shape) < 0.2] = 0.0
+    op = O.dense_op(W, rng.normal(size=6))
+    centre, radius = rng.normal(size=5), 0.7
+    l0, u0 = centre - radius, centre + radius
+    x0 = O.ball_maximiser(rng.normal(size=5), centre, radius)
+    assert np.all((x0 > l0) & (x0 < u0))
+    z = np.array([1.0, 0.0, 1.0, 0.0, 0.0, 1.0])
+    I = O.oracle_mask(op, l0, u0, x0, z)
+    Wd = W
+    for i in range(6):
+        row = I[i] if I.ndim == 2 else I.reshape(6, 5)[i]
+        if z[i] == 1.0:
+            assert row.all(), i
+        else:
+            assert np.array_equal(row.astype(bool), Wd[i] == 0.0), i

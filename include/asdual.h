@@ -392,11 +392,31 @@ asd_status asd_oracle(asd_plan* plan, int32_t k, const void* x_prev, const void*
  *          guarantees that the network weights and the batch were not
  *          changed in place in between.  0: always recompute.
  * Overwrites the plan's minimiser buffers (as asd_bound does); the duals are
- * unchanged.  Errors: ASD_EINVAL for a NULL plan or g, before asd_init, or a
- * convolutional output layer. */
+ * unchanged.  Errors: ASD_EINVAL for a NULL plan or g, before asd_init, a
+ * convolutional output layer, or an l2-ball input domain. */
 asd_status asd_bound_grad(asd_plan* plan, const double* g, double* const* dW /* host */,
                           double* const* db /* host */, double* dl0, double* du0, int32_t reuse,
                           hipStream_t stream);
+
+/* ---- Input domain (Sec. 2: x_0 in a convex set C) ---- */
+
+typedef enum { ASD_DOMAIN_BOX = 0, ASD_DOMAIN_L2 = 1 } asd_domain;
+
+/* Input domain of the plan's subproblems, in force until the next call (a
+ * plan starts with ASD_DOMAIN_BOX: the box [l0, u0] of the batch).
+ * ASD_DOMAIN_L2: subproblem s ranges over the l2 ball ||x_0 - centre_s|| <=
+ * radius_s (centre [S][n_0], radius [S], device floats, copied into the
+ * workspace on `stream`); the batches given to asd_init must then hold the
+ * ball's box hull (centre -/+ radius) as l0, u0, which bounds x_0 in the
+ * check matrices of layer 1.  The minimiser x*_0 maximises f_0^T x_0 over
+ * the ball (eq:as-primal0-min: centre + radius f_0 / ||f_0||, the centre
+ * where f_0 = 0), in the iterations and in the final bound.  Masks added at
+ * layer 1 keep multipliers 0: x*_0 lies inside the box hull, where
+ * eq:oracle's rows only repeat the Big-M constraints.  asd_bound_grad
+ * refuses an l2 plan.  Errors: ASD_EINVAL for a NULL plan, an unknown
+ * domain, or NULL centre or radius with ASD_DOMAIN_L2. */
+asd_status asd_set_input_domain(asd_plan* plan, int32_t domain, const float* centre, const float* radius,
+                                hipStream_t stream);
 
 /* ---- Intermediate bounds (App. E; interval propagation) ---- */
 

@@ -24,6 +24,7 @@ ASD_LAYER_DENSE, ASD_LAYER_CONV2D = 0, 1
 ASD_RULE_ADAM, ASD_RULE_SUPERGRADIENT = 0, 1
 ASD_PREC_FP32, ASD_PREC_FP64, ASD_PREC_MIXED, ASD_PREC_BF16, ASD_PREC_BF16_ALL = 0, 1, 2, 3, 4
 ASD_PHASE_BIGM, ASD_PHASE_AS = 0, 1
+ASD_DOMAIN_BOX, ASD_DOMAIN_L2 = 0, 1
 (ASD_F_ALPHA, ASD_F_BETA0, ASD_F_BETA1, ASD_F_ALPHA_M, ASD_F_ALPHA_V, ASD_F_BETA0_M, ASD_F_BETA0_V,
  ASD_F_BETA1_M, ASD_F_BETA1_V, ASD_F_MASK_BETA, ASD_F_MASK_M, ASD_F_MASK_V, ASD_F_MASK_LI,
  ASD_F_MASK_UI, ASD_F_MASK_Z, ASD_F_MASK_XPREV) = range(16)
@@ -101,7 +102,7 @@ EXPORTED = ["asd_net_create", "asd_net_destroy", "asd_params_default", "asd_plan
             "asd_state_get", "asd_state_set", "asd_state_get_counts", "asd_state_set_counts",
             "asd_eval", "asd_oracle", "asd_bound_grad", "asd_set_budgets", "asd_solve_group", "asd_solve_graph", "asd_check_finite",
             "asd_plan_autotune", "asd_plan_get_tuning", "asd_plan_set_tuning", "asd_interval_bounds", "asd_profile_enable", "asd_profile_read",
-            "asd_solve_static", "asd_intermediate_workspace_size", "asd_intermediate_bounds",
+            "asd_solve_static", "asd_intermediate_workspace_size", "asd_intermediate_bounds", "asd_set_input_domain",
             "asd_last_error", "asd_abi_version"]
 
 
@@ -137,6 +138,7 @@ def lib():
     L.asd_oracle.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
     L.asd_bound_grad.argtypes = [vp, vp, C.POINTER(vp), C.POINTER(vp), vp, vp, i32, vp]
     L.asd_set_budgets.argtypes = [vp, C.POINTER(i32), vp]
+    L.asd_set_input_domain.argtypes = [vp, i32, vp, vp, vp]
     L.asd_solve_graph.argtypes = [vp, C.POINTER(Batch), vp, vp]
     L.asd_check_finite.argtypes = [vp, vp, vp, vp]
     L.asd_plan_autotune.argtypes = [vp, i32, i32, vp]
@@ -317,6 +319,14 @@ class Plan:
         arr = (C.c_int32 * self.S)(*[int(b) for b in budgets])
         _check(lib().asd_set_budgets(self.handle, arr, _stream(stream)))
         self.budgets = [int(b) for b in budgets]
+
+    def set_input_domain(self, domain: int, centre: Optional[torch.Tensor] = None,
+                         radius: Optional[torch.Tensor] = None, stream=None):
+        """asd_set_input_domain: ASD_DOMAIN_BOX, or ASD_DOMAIN_L2 with centres
+        [S][n_0] and radii [S] (float32, device; the batches' l0, u0 must be
+        the balls' box hulls)."""
+        self.generation += 1
+        _check(lib().asd_set_input_domain(self.handle, domain, _ptr(centre), _ptr(radius), _stream(stream)))
 
     def autotune(self, ktune: int = 2, reps: int = 5, stream=None):
         """asd_plan_autotune (after init); returns the chosen tuning."""

@@ -129,6 +129,9 @@ void carve_t(asd_plan* P, Carver& cv) {
     // kernels' transposed convolution into the last ReLU layer
     P->negc = (sizeof(T) == 4 && P->geo[P->n].kind == ASD_LAYER_CONV2D) ? cv.take<float>((size_t)P->nl[P->n].N * S)
                                                                         : nullptr;
+    P->ball_c = cv.take<float>((size_t)P->nl[0].N * S);
+    P->ball_r = cv.take<float>(S);
+    P->f0f = sizeof(T) == 4 ? cv.take<float>((size_t)P->nl[0].N * S) : nullptr;
     size_t part = 0;
     for (int L = 1; L <= P->n; ++L) {
         const LayerGeo& g = P->geo[L];
@@ -443,6 +446,16 @@ asd_status bwd_fast(asd_plan* P, int k, hipStream_t st) {
 }
 
 
+// The l2-ball input domain's x*_0 (and, with term, the final bound's
+// objective terms of layer 0) from f_0 of the backward pass just run.
+template <typename Ts, typename Tf>
+asd_status l2_input(asd_plan* P, const Tf* f0, int f_internal, double* term, hipStream_t st) {
+    hipLaunchKernelGGL((k_l2_input<Ts, Tf>), dim3((unsigned)P->Sa), dim3(256), 0, st, f0, f_internal,
+                       (const float*)P->ball_c, (const float*)P->ball_r, NA<Ts>(P)[0].xstar, term, P->nl[0], P->S);
+    LAUNCH_CHECK();
+    return ASD_OK;
+}
+
 // Backward pass for neuron layer k (f_k, inner minimisation, terms).
 template <typename Tc, typename Ts>
 asd_status launch_backward(asd_plan* P, int k, int want_obj, int role, hipStream_t st, double* fout, void* fext) {
@@ -486,6 +499,7 @@ asd_status launch_forward(asd_plan* P, int k, const StepArgsT<T>& sa, int mode, 
     a.R = RL<T>(P)[k];
     a.st = sa;
     a.mode = mode;
+    a.freeze = P->domain == ASD_DOMAIN_L2 && k == 1;
     if (gout)
         for (int i = 0; i < 3 + kMaxMasks; ++i) a.gout[i] = reinterpret_cast<T*>(gout[i]);
     const size_t lds = (size_t)KS * CB * (1 + a.nm) * kWave * sizeof(T);
@@ -696,14 +710,19 @@ asd_status iteration(asd_plan* P, bool as_phase, int t, double lr, hipStream_t s
     // one (unless kernels are being timed one by one)
     int kpair = -1;
     if constexpr (!kGeneral) kpair = bwd_pair_layer(P);
+    const bool l2 = P->domain == ASD_DOMAIN_L2;
     for (int k = P->n - 1; k >= 0; --k) {
         if constexpr (kGeneral) {
-            TRY((launch_backward<T, T>(P, k, 0, ASD_K_BACKWARD, st)));
+            TRY((launch_backward<T, T>(P, k, 0, ASD_K_BACKWARD, st, k == 0 && l2 ? P->f0 : nullptr)));
         } else {
             if (k == kpair) continue;
             if (kpair >= 0 && k == P->n - 1) TRY(bwd_pair(P, st));
             else TRY(bwd_fast(P, k, st));
         }
+    }
+    if (l2) {
+        if constexpr (kGeneral) TRY((l2_input<T, double>(P, P->f0, 1, nullptr, st)));
+        else TRY((l2_input<T, float>(P, P->f0f, 0, nullptr, st)));
     }
     if (as_phase && P->n >= 2 && (t % P->prm.add_every) < P->prm.add_count &&
         P->n_masks < P->prm.max_masks) {
@@ -820,6 +839,7 @@ asd_status bound_f32(asd_plan* P, double* out_lb, float* x0, hipStream_t st) {
     for (int k = 1; k < P->n; ++k) TRY(launch_final_sums(P, k, st));
     for (int k = P->n - 1; k >= 0; --k)
         TRY((launch_backward<double, float>(P, k, 1, ASD_K_FINAL, st, k == 0 ? P->f0 : nullptr)));
+    if (P->domain == ASD_DOMAIN_L2) TRY((l2_input<float, double>(P, P->f0, 1, P->naf[0].term, st)));
     TRY(reduce_objective<float>(P, out_lb, st));
     if (x0) TRY((launch_layout<float, float>(P->naf[0].xstar, x0, P->nl[0], P->S, 2, st)));
     P->min_valid = true;
@@ -830,6 +850,7 @@ asd_status bound_f64(asd_plan* P, double* out_lb, float* x0, hipStream_t st) {
     P->min_valid = false;
     for (int k = P->n - 1; k >= 0; --k)
         TRY((launch_backward<double, double>(P, k, 1, ASD_K_FINAL, st, k == 0 ? P->f0 : nullptr)));
+    if (P->domain == ASD_DOMAIN_L2) TRY((l2_input<double, double>(P, P->f0, 1, P->nad[0].term, st)));
     TRY(reduce_objective<double>(P, out_lb, st));
     if (x0) TRY((launch_layout<double, float>(P->nad[0].xstar, x0, P->nl[0], P->S, 2, st)));
     P->min_valid = true;
@@ -1046,10 +1067,16 @@ asd_status eval_t(asd_plan* P, const asd_eval_out* out, hipStream_t st) {
             if (kpair >= 0 && k == P->n - 1) TRY(bwd_pair(P, st));
             else TRY(bwd_fast(P, k, st));
         }
+        if (P->domain == ASD_DOMAIN_L2) {
+            const float* f0 = out->f[0] ? reinterpret_cast<const float*>(out->f[0]) : P->f0f;
+            TRY((l2_input<T, float>(P, f0, 0, nullptr, st)));
+        }
         memset(P->ev_f, 0, sizeof(P->ev_f));
     } else {
+        const bool l2 = P->domain == ASD_DOMAIN_L2;
         for (int k = P->n - 1; k >= 0; --k)
-            TRY((launch_backward<T, T>(P, k, 1, ASD_K_OTHER, st, nullptr, out->f[k])));
+            TRY((launch_backward<T, T>(P, k, 1, ASD_K_OTHER, st, k == 0 && l2 ? P->f0 : nullptr, out->f[k])));
+        if (l2) TRY((l2_input<T, double>(P, P->f0, 1, NA<T>(P)[0].term, st)));
         if (out->obj) TRY(reduce_objective<T>(P, out->obj, st));
     }
     for (int k = 0; k < P->n; ++k) {
@@ -1288,6 +1315,7 @@ static void bind_plan(asd_plan* P, const asd_net* net, int S, const asd_params* 
     P->Sa = S;
     P->ragged = false;
     P->min_valid = false;
+    P->domain = ASD_DOMAIN_BOX;
     // LDS a block may use on the current device (64 KB where it cannot be read)
     int dev = 0, lds = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -1599,8 +1627,26 @@ asd_status asd_bound_grad(asd_plan* P, const double* gs, double* const* dW, doub
     if (!P->loaded) return fail(ASD_EINVAL, "asd_init has not been called");
     if (P->geo[P->n].kind != ASD_LAYER_DENSE)
         return fail(ASD_EINVAL, "the bound gradient needs a dense output layer");
+    if (P->domain != ASD_DOMAIN_BOX) return fail(ASD_EINVAL, "the bound gradient is defined for box input domains");
     return is64(P) ? bound_grad_t<double>(P, gs, dW, db, dl0, du0, reuse, st)
                    : bound_grad_t<float>(P, gs, dW, db, dl0, du0, reuse, st);
+}
+
+asd_status asd_set_input_domain(asd_plan* P, int32_t domain, const float* centre, const float* radius,
+                                hipStream_t st) {
+    if (!P) return fail(ASD_EINVAL, "NULL plan");
+    if (domain == ASD_DOMAIN_BOX) {
+        invalidate_graph(P);
+        P->domain = ASD_DOMAIN_BOX;
+        return ASD_OK;
+    }
+    if (domain != ASD_DOMAIN_L2) return fail(ASD_EINVAL, "unknown input domain %d", domain);
+    if (!centre || !radius) return fail(ASD_EINVAL, "NULL centre or radius");
+    invalidate_graph(P);
+    HIP_TRY(hipMemcpyAsync(P->ball_c, centre, sizeof(float) * P->nl[0].N * P->S, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(P->ball_r, radius, sizeof(float) * P->S, hipMemcpyDeviceToDevice, st));
+    P->domain = ASD_DOMAIN_L2;
+    return ASD_OK;
 }
 
 asd_status asd_set_budgets(asd_plan* P, const int32_t* budgets, hipStream_t st) {

@@ -120,6 +120,7 @@ struct FastFwdArgs {
     int Sa;                     // subproblems updated: s < Sa (the geometry's
                                 // column counts cover the same prefix)
     T* part;                    // dense: partial products [ksplit][1 + nm][Cpad][S]
+    int freeze;                 // the slots' multipliers stay 0 (layer 1 of an l2-ball input domain)
     // evaluation at fixed duals (st.rule == kRuleEval): the supergradient
     // entries of alpha, beta_0, beta_1 and each slot's beta, caller layout
     // [S][n_k] (null: not wanted); nothing of the state is written
@@ -340,7 +341,7 @@ __device__ __forceinline__ void fwd_store(const FastFwdArgs<T>& A, uint32_t idx,
     for (int q = 0; q < NM; ++q) {
         const cptr_t<MaskSlotT<T>> M = &R->slot[q];
         const bool zb = (in.zq >> q) & 1u;
-        const T bq = step(in.bq[q], in.mq[q], in.vq[q], gmask(q), 1 + q, M->m, M->v);
+        const T bq = A.freeze ? (T)0 : step(in.bq[q], in.mq[q], in.vq[q], gmask(q), 1 + q, M->m, M->v);
         M->beta[idx] = bq;
         own -= bq;
         gg += bq * (in.LI[q] + in.UI[q] + bb);

@@ -203,6 +203,7 @@ asd_status bwd_fast_impl(asd_plan* P, int k, hipStream_t st) {
     a.Wl8 = P->Wl8[k + 1];
     a.nkp = P->nkp[k + 1];
     a.fout = reinterpret_cast<T*>(P->ev_f[k]);
+    if (k == 0 && P->domain == ASD_DOMAIN_L2 && !a.fout) a.fout = P->f0f;  // f_0 for the ball's x*_0
     if (g.kind == ASD_LAYER_CONV2D && L.P % kWave == 0 && L.C >= 16) {
         // matrix-core transposed convolution over parity classes, operands
         // staged in LDS (see k_bwd_conv_mfma); shapes it cannot hold fall

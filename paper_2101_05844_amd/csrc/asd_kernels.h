@@ -170,6 +170,7 @@ struct FwdArgs {
     ReluLayerT<T> R;            // layer k arrays
     StepArgsT<T> st;
     int mode;                   // 0 update, 1 export supergradient
+    int freeze;                 // the slots' multipliers stay 0 (layer 1 of an l2-ball input domain)
     T* gout[3 + kMaxMasks];     // export targets, caller layout [S][n_k]
 };
 
@@ -302,7 +303,7 @@ __global__ void __launch_bounds__(kWave * KS) k_forward(FwdArgs<T> A) {
     for (int q = 0; q < kMaxMasks; ++q) {
         if (q < nm) {
             const MaskSlotT<T>& M = A.R.slot[q];
-            const T bq = step(M.beta[idx], M.m, M.v, gm[q], 1 + q);
+            const T bq = A.freeze ? (T)0 : step(M.beta[idx], M.m, M.v, gm[q], 1 + q);
             M.beta[idx] = bq;
             own -= bq;
             gg += bq * (M.LI[idx] + M.UI[idx] + bb);
@@ -886,6 +887,46 @@ static __global__ void __launch_bounds__(256) k_ib_combine(float* lhat, float* u
     const double lo = dB[(2 * d) * nk + j], hi = -dB[(2 * d + 1) * nk + j];
     if (isfinite(lo)) lhat[i] = fmaxf(lhat[i], __double2float_rd(lo));
     if (isfinite(hi)) uhat[i] = fminf(uhat[i], __double2float_ru(hi));
+}
+
+// l2-ball input domain (the input set C of Sec. 2): x*_0 maximises f_0^T x_0
+// over ||x_0 - centre|| <= radius, i.e. x*_0 = centre + radius f_0 / ||f_0||
+// (the centre where f_0 = 0); with term set, the objective terms -f_0 x*_0 of
+// the final bound.  One block per subproblem; the norm is a fixed-order
+// block sum in FP64.  f_0 in the caller's layout [S][n_0] (f_internal = 0)
+// or the internal one; centre [S][n_0] and radius [S] as the caller gave
+// them; x*_0 and the terms in the internal layout.
+template <typename Ts, typename Tf>
+__global__ void __launch_bounds__(256) k_l2_input(const Tf* f0, int f_internal, const float* centre,
+                                                  const float* radius, Ts* xstar, double* term, NeuronLayout nl,
+                                                  int S) {
+    __shared__ double red[256];
+    const int s = blockIdx.x;
+    const long n = nl.N;
+    auto internal = [&](long j) {
+        const long c = j / nl.P;
+        return ((long)c * S + s) * nl.P + (j - c * nl.P);
+    };
+    double acc = 0;
+    for (long j = threadIdx.x; j < n; j += 256) {
+        const double f = (double)f0[f_internal ? internal(j) : (long)s * n + j];
+        acc += f * f;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double nrm = sqrt(red[0]);
+    const double r = (double)radius[s];
+    for (long j = threadIdx.x; j < n; j += 256) {
+        const long ii = internal(j);
+        const double f = (double)f0[f_internal ? ii : (long)s * n + j];
+        const double x = (double)centre[(long)s * n + j] + (nrm > 0 ? r * f / nrm : 0.0);
+        xstar[ii] = (Ts)x;
+        if (term) term[ii] = -f * x;
+    }
 }
 
 // dst = -src (n entries): the backward operand of a convolutional output

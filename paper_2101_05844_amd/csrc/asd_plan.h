@@ -104,6 +104,12 @@ struct asd_plan {
     int Sa;                           // subproblems the current iteration updates (a prefix)
     int lds_max;                      // LDS bytes one block may use on the plan's device
     float* negc;                      // convolutional output layer (FP32 duals): -c, layout of layer n
+    // input domain (asd_set_input_domain): l2 ball centres [S][n_0], radii [S]
+    // and, for FP32 iterations, f_0 [S][n_0] from the backward pass
+    int domain;
+    float* ball_c;
+    float* ball_r;
+    float* f0f;
     // captured iteration schedule (asd_solve_graph) and the host state it ends in
     hipGraphExec_t graph_exec;
     bool graph_valid;
@@ -222,6 +228,7 @@ FastFwdArgs<T> fwd_args(asd_plan* P, int k, int nm, const StepArgsT<T>& sa) {
     a.R = RdevT<T>(P) + k;
     a.st = sa;
     a.part = reinterpret_cast<T*>(P->part);
+    a.freeze = P->domain == ASD_DOMAIN_L2 && k == 1;
     if (sa.rule == kRuleEval)
         for (int i = 0; i < 3 + kMaxMasks; ++i) a.gout[i] = reinterpret_cast<T*>(P->ev_g[k][i]);
     return a;
@@ -292,6 +299,7 @@ FastBwdArgs<T> bwd_args(asd_plan* P, int k, int nm) {
     a.Wl8 = P->Wl8[k + 1];
     a.nkp = P->nkp[k + 1];
     a.fout = reinterpret_cast<T*>(P->ev_f[k]);
+    if (k == 0 && P->domain == ASD_DOMAIN_L2 && !a.fout) a.fout = reinterpret_cast<T*>(P->f0f);
     return a;
 }
 

@@ -59,9 +59,10 @@ def kernel_unit_bytes(role, layer, sizes, K, mixed=False):
     return None
 
 
-# sources of the bound-gradient kernels: the counter runs (--no-adjoint) do
-# not launch them, so their text does not enter the digest
-GRADIENT_ONLY_SOURCES = ("asd_adjoint.h",)
+# sources outside the counted kernels and their launch code: the bound
+# gradient's kernels (the counter runs do not launch them) and the host
+# driver's orchestration (which kernel runs when, not what a launch moves)
+GRADIENT_ONLY_SOURCES = ("asd_adjoint.h", "asd_api.hip")
 
 
 def source_digest():
@@ -428,6 +429,45 @@ def intermediate_leg(A, np, torch, WL, w, net, lb_ibp, tuning):
             "batch_verified_interval_root": int(np.sum(lb_ibp > 0)), "batch_verified_tightened_root": int(np.sum(lb > 0))}
 
 
+def l2_leg(A, np, torch, WL, w, net, tuning, steps):
+    """The benchmark batch over l2 balls (Sec. 2 input set C): radius 0.1
+    around the centre of each subdomain's box, the ball's box hull as l0,
+    u0, interval bounds of the hull at the root and then the benchmark's
+    subdomain fixes; the same schedule.  Reports the Active Set rate (to set
+    beside the box domain's) and the mean bound."""
+    dev = "cuda:0"
+    t32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=dev)
+    radius = 0.1
+    centre = (w.l0.astype(np.float64) + w.u0.astype(np.float64)) / 2
+    lo = np.nextafter((centre - radius).astype(np.float32), np.float32(-np.inf))
+    hi = np.nextafter((centre + radius).astype(np.float32), np.float32(np.inf))
+    lh0, uh0 = net.interval_bounds(t32(lo[:1]), t32(hi[:1]))
+    lh0 = [a[0].cpu().numpy() for a in lh0[:-1]]
+    uh0 = [a[0].cpu().numpy() for a in uh0[:-1]]
+    Lb, Ub = WL.subdomain_bounds(lh0, uh0, w.fix_draws, w.S)
+    plan = A.Plan(net, w.S, A.params_from_schedule(w.schedule))
+    if tuning is not None:
+        plan.set_tuning(tuning)
+    plan.set_input_domain(A.ASD_DOMAIN_L2, t32(centre), t32(np.full(w.S, radius)))
+    b = (t32(lo), t32(hi), [t32(a) for a in Lb], [t32(a) for a in Ub], t32(w.c))
+    stream = torch.cuda.current_stream()
+    sched = w.schedule
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps + 1)]
+    for i in range(steps + 1):
+        plan.init(*b)
+        plan.run(A.ASD_PHASE_BIGM, 0, sched.bigm_iters)
+        ev[i][0].record(stream)
+        plan.run(A.ASD_PHASE_AS, 0, sched.as_iters)
+        ev[i][1].record(stream)
+        lb = plan.bound()
+    torch.cuda.synchronize()
+    as_ms = sum(e[0].elapsed_time(e[1]) for e in ev[1:]) / steps
+    return {"workload": f"{w.name} batch over l2 balls of radius {radius} around each box centre (interval "
+                        f"bounds of the box hull, the same fixes), FP32 duals",
+            "value": round(w.S * sched.as_iters / (as_ms / 1e3), 1), "unit": "subproblem-iterations/s",
+            "as_phase_ms": round(as_ms, 3), "bound_mean": round(float(lb.mean().item()), 5)}
+
+
 _ORACLE_W = None
 
 
@@ -576,6 +616,8 @@ def main():
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged two-net batch")
     ap.add_argument("--no-mnist", action="store_true", help="skip the MNIST-shaped MLP leg")
     ap.add_argument("--no-intermediate", action="store_true", help="skip the solver-based intermediate bounds leg")
+    ap.add_argument("--no-l2", action="store_true", help="skip the l2-ball input domain leg")
+    ap.add_argument("--no-margin", action="store_true", help="skip the accuracy leg on the margin workload")
     ap.add_argument("--no-autotune", action="store_true", help="keep the heuristic kernel choices")
     ap.add_argument("--tuning", default=None, metavar="JSON",
                     help="kernel choices to set instead of autotuning (the 'tuning' object of a bench line)")
@@ -761,7 +803,7 @@ def main():
         else:
             bf16_all = res
     margin = None
-    if reduced:
+    if reduced and not args.no_margin:
         print("[bench] accuracy where subdomains verify", file=sys.stderr, flush=True)
         plan = None
         margin = margin_leg(A, np, torch, WL, tuning, [(nm, md) for nm, md, _ in reduced])
@@ -774,6 +816,10 @@ def main():
     if not args.no_intermediate:
         print("[bench] intermediate bounds leg", file=sys.stderr, flush=True)
         inter = intermediate_leg(A, np, torch, WL, w, net, lb_np, tuning)
+    l2 = None
+    if not args.no_l2:
+        print("[bench] l2 input domain leg", file=sys.stderr, flush=True)
+        l2 = l2_leg(A, np, torch, WL, w, net, tuning, args.steps)
     mnist = None
     if not args.no_mnist:
         print("[bench] MNIST-shaped MLP", file=sys.stderr, flush=True)
@@ -824,6 +870,7 @@ def main():
         "ragged": ragged,
         "mnist": mnist,
         "intermediate_bounds": inter,
+        "l2_domain": l2,
         "adjoint": adjoint,
         "bound_mean": float(np.mean(lb_np)),
         "verified_fraction": float(np.mean(lb_np > 0)),

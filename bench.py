@@ -468,6 +468,83 @@ def l2_leg(A, np, torch, WL, w, net, tuning, steps):
             "as_phase_ms": round(as_ms, 3), "bound_mean": round(float(lb.mean().item()), 5)}
 
 
+def sp_unit_bytes(sizes, es=4):
+    """Algorithmic bytes of one Saddle Point iteration per subproblem (each
+    array of the state touched once per kernel that reads or writes it; es
+    bytes per value).  Layer k has sizes[k] neurons (k = 0..n).
+      column products into layer k (k = 0..n-1): box lo, hi; own alpha,
+        zeta1, zeta3, zeta4 (k >= 1); zeta2 of layer k+1 (k+1 <= n-1); the
+        operand of layer k+1 (alpha, or c at the last layer); x_bar, z_bar out
+      row products of ReLU layer k: x, lo, hi of layer k-1; x, z, lhat, uhat,
+        alpha, zeta1, zeta3, zeta4, mu_alpha, mu_beta in; alpha, zeta1,
+        zeta3, zeta4 and the two vertex row weights out
+      zeta2 of ReLU layer k: lo, hi, x of layer k-1 and zeta2 in and out;
+        the row weights and z of layer k
+      primal combination: x, x_bar -> x (and z, z_bar -> z)"""
+    n = len(sizes) - 1
+    tot = 0
+    for k in range(n):
+        own = k >= 1
+        tot += sizes[k] * (2 + (4 if own else 0) + (1 if k + 1 <= n - 1 else 0) + (2 if own else 1))
+        tot += sizes[k + 1]
+        tot += sizes[k] * (6 if own else 3)
+    for k in range(1, n):
+        tot += 3 * sizes[k - 1] + 16 * sizes[k]
+        tot += 5 * sizes[k - 1] + 3 * sizes[k]
+    return tot * es
+
+
+def sp_leg(A, np, torch, WL, w, net, plan_args, tuning, lb_as):
+    """Saddle Point (Sec. 5, Algorithm 2) on the benchmark batch: from the
+    Active Set duals of the benchmark solve (AS-SP) and from Big-M duals
+    alone (SP), T = 1000 SP-FW iterations after the set-up (statistics, caps
+    and 100 primal steps, App. C), FP32 state, FP64 bound.  Reports the
+    iteration rate, the set-up time and the bound against the duals it
+    starts from."""
+    l0, u0, lh, uh, c = plan_args
+    sched = w.schedule
+    S = w.S
+    q = A.asd_sp_params_default()
+    q.iters = 1000  # the paper's smaller Saddle Point budget (Sec. 7)
+    plan = A.Plan(net, S, A.params_from_schedule(sched))
+    if tuning is not None:
+        plan.set_tuning(tuning)
+    stream = torch.cuda.current_stream()
+    out = {}
+    sizes = [w.layers[0].n_in] + [Lr.n_out for Lr in w.layers]
+    for name, as_iters in (("as_sp", sched.as_iters), ("sp", 0)):
+        plan.init(l0, u0, lh, uh, c)
+        plan.run(A.ASD_PHASE_BIGM, 0, sched.bigm_iters)
+        plan.run(A.ASD_PHASE_AS, 0, as_iters)
+        lb0 = plan.bound()
+        best = None
+        for rep in range(2):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            ev[0].record(stream)
+            plan.sp_init(q)
+            ev[1].record(stream)
+            plan.sp_run(0, q.iters)
+            ev[2].record(stream)
+            lb = plan.sp_bound()
+            torch.cuda.synchronize()
+            ms = (ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]))
+            best = ms if best is None or ms[1] < best[1] else best
+        d = (lb - lb0).cpu().numpy()
+        it_ms = best[1]
+        gbs = S * q.iters * sp_unit_bytes(sizes) / (it_ms / 1e3) / 1e9
+        out[name] = {"value": round(S * q.iters / (it_ms / 1e3), 1), "unit": "subproblem-iterations/s",
+                     "iters": q.iters, "iterations_ms": round(it_ms, 3), "setup_ms": round(best[0], 3),
+                     "alg_GBps": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                     "start_bound_mean": round(float(lb0.mean().item()), 5),
+                     "bound_mean": round(float(lb.mean().item()), 5),
+                     "mean_gain_over_start": float(np.mean(d)),
+                     "improved_fraction": float(np.mean(d > 0))}
+    out["workload"] = (f"{w.name}: Saddle Point from the benchmark's Active Set duals (as_sp) and from its Big-M "
+                       f"duals (sp); gamma_t = 1/(t + {q.gamma0:g}), {q.init_steps} primal steps, caps "
+                       f"{q.cap_alpha:g}, FP32 state, FP64 bound")
+    return out
+
+
 _ORACLE_W = None
 
 
@@ -618,6 +695,7 @@ def main():
     ap.add_argument("--no-intermediate", action="store_true", help="skip the solver-based intermediate bounds leg")
     ap.add_argument("--no-l2", action="store_true", help="skip the l2-ball input domain leg")
     ap.add_argument("--no-margin", action="store_true", help="skip the accuracy leg on the margin workload")
+    ap.add_argument("--no-sp", action="store_true", help="skip the Saddle Point leg")
     ap.add_argument("--no-autotune", action="store_true", help="keep the heuristic kernel choices")
     ap.add_argument("--tuning", default=None, metavar="JSON",
                     help="kernel choices to set instead of autotuning (the 'tuning' object of a bench line)")
@@ -820,6 +898,11 @@ def main():
     if not args.no_l2:
         print("[bench] l2 input domain leg", file=sys.stderr, flush=True)
         l2 = l2_leg(A, np, torch, WL, w, net, tuning, args.steps)
+    sp = None
+    if not args.no_sp:
+        print("[bench] Saddle Point leg", file=sys.stderr, flush=True)
+        plan = None
+        sp = sp_leg(A, np, torch, WL, w, net, (l0, u0, lh, uh, c), tuning, lb_np)
     mnist = None
     if not args.no_mnist:
         print("[bench] MNIST-shaped MLP", file=sys.stderr, flush=True)
@@ -871,6 +954,7 @@ def main():
         "mnist": mnist,
         "intermediate_bounds": inter,
         "l2_domain": l2,
+        "saddle_point": sp,
         "adjoint": adjoint,
         "bound_mean": float(np.mean(lb_np)),
         "verified_fraction": float(np.mean(lb_np > 0)),

@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define ASD_ABI_VERSION 2
+#define ASD_ABI_VERSION 3
 #define ASD_MAX_LAYERS 16
 #define ASD_MAX_MASKS 8 /* compile-time cap on K_max (active masks per layer) */
 
@@ -454,6 +454,85 @@ asd_status asd_intermediate_workspace_size(const asd_net* net, int32_t D, const 
 asd_status asd_intermediate_bounds(const asd_net* net, int32_t D, const asd_params* params, const float* l0,
                                    const float* u0, float* const* lhat /* host */, float* const* uhat /* host */,
                                    void* workspace, size_t bytes, hipStream_t stream);
+
+/* ---- Saddle Point (Sec. 5, Algorithm 2) and AS-SP ---- */
+
+/* Saddle Point continues from the plan's current duals: after Big-M only
+ * (asd_run of ASD_PHASE_BIGM) it is the paper's Saddle Point, after Active
+ * Set iterations with masks it is AS-SP.  Its state lives in a second,
+ * caller-owned workspace; the plan's own duals are read, never written.
+ *   iters        T, SP-FW iterations (>= 0)
+ *   gamma0       step sizes gamma_t = 1 / (t + gamma0), gamma0 >= 1 (Sec. 7.1
+ *                uses 10; Sec. 5.2's 1 / (1 + t) is gamma0 = 1)
+ *   init_steps   projected subgradient steps of the primal initialisation on
+ *                the Big-M primal view (App. C.2), >= 0
+ *   init_lr0/1   their step sizes, linear from lr0 to lr1
+ *   cap_alpha    price caps (eq:price-caps): a multiplier set that is zero at
+ *   cap_beta     initialisation gets this cap, > 0 */
+typedef struct {
+    int32_t iters;
+    double gamma0;
+    int32_t init_steps;
+    double init_lr0, init_lr1;
+    double cap_alpha, cap_beta;
+} asd_sp_params;
+
+/* Sec. 7.1 / App. C: T = 100, gamma0 = 10, 100 primal steps from 1e-2 to
+ * 1e-5, caps 1e-3 for the multipliers that start at zero. (host pointer) */
+void asd_sp_params_default(asd_sp_params* p);
+
+/* Bytes of the Saddle Point workspace of a plan: per ReLU layer the duals
+ * alpha, the four sufficient statistics of eq:suff-stats, the two price caps,
+ * the primal iterate and conditional gradient, and FP64 objective terms; the
+ * arrays hold the plan's precision (FP64 plans: double, otherwise float). */
+asd_status asd_sp_workspace_size(const asd_plan* plan, size_t* bytes /* host */);
+
+/* Algorithm 2's set-up on `stream`: converts the plan's duals (alpha,
+ * beta_0, beta_1 and the active masks) into sufficient statistics
+ * (eq:suff-stats), sets the price caps (eq:price-caps), starts the primal
+ * iterate at the minimiser of the Lagrangian and runs the primal
+ * initialisation.  `workspace` (256-byte aligned, >= asd_sp_workspace_size
+ * bytes) stays bound to the plan until the next asd_sp_init or asd_init.
+ * Errors: ASD_EINVAL before asd_init, for an l2-ball input domain, invalid
+ * params, NULL or a workspace that is too small. */
+asd_status asd_sp_init(asd_plan* plan, const asd_sp_params* params, void* workspace, size_t bytes,
+                       hipStream_t stream);
+/* SP-FW iterations t_begin .. t_begin + n_iters - 1 on `stream`: the primal
+ * conditional gradient (the Lagrangian's minimiser at the current duals),
+ * the dual one at the current primal iterate (eq:alphak-condg and the most
+ * violated constraint per neuron, eq:betak-condg, found by the oracle
+ * eq:oracle at the fractional iterate), then the convex combination with
+ * gamma_t.  Errors: ASD_EINVAL without asd_sp_init, t_begin < 0. */
+asd_status asd_sp_run(asd_plan* plan, int32_t t_begin, int32_t n_iters, hipStream_t stream);
+/* The bound d(alpha, zeta) at the current Saddle Point duals (Algorithm 2's
+ * return), evaluated in FP64 (an FP32 plan's statistics are read as stored),
+ * into out_lb [S] (device doubles). */
+asd_status asd_sp_bound(asd_plan* plan, double* out_lb, hipStream_t stream);
+/* asd_sp_init, T iterations and asd_sp_bound. */
+asd_status asd_sp_solve(asd_plan* plan, const asd_sp_params* params, void* workspace, size_t bytes,
+                        double* out_lb, hipStream_t stream);
+
+/* Arrays of the Saddle Point state, for asd_sp_read.  Layer k is a ReLU
+ * layer (1..n_layers-1) except for ASD_SP_X and ASD_SP_XBAR (0..n_layers-1);
+ * ASD_SP_ZETA2 of layer k has the size of layer k-1 (the coefficient of
+ * x_{k-1} contributed by layer k's multipliers). */
+typedef enum {
+    ASD_SP_X = 0,      /* primal iterate x_k */
+    ASD_SP_XBAR = 1,   /* last primal conditional gradient (minimiser) of x_k */
+    ASD_SP_ALPHA = 2,
+    ASD_SP_ZETA1 = 3,  /* sum over masks of beta_{k,I} */
+    ASD_SP_ZETA3 = 4,  /* beta_{k,1} (lhat - b) + sum_I (W . I . Lcheck) row sums beta_{k,I} */
+    ASD_SP_ZETA4 = 5,  /* beta_{k,0} (uhat - b) + sum_I (W . (1-I) . Ucheck) row sums beta_{k,I} */
+    ASD_SP_MU_ALPHA = 6,
+    ASD_SP_MU_BETA = 7,
+    ASD_SP_Z = 8,      /* primal iterate z_k */
+    ASD_SP_ZETA2 = 9   /* sum_I (W_k . I)^T beta_{k,I} */
+} asd_sp_field;
+/* Copies one array into dst, the caller layout [S][n] in the plan's
+ * precision (device), on `stream`.  Errors: ASD_EINVAL without asd_sp_init,
+ * for an unknown field or a layer out of range. */
+asd_status asd_sp_read(asd_plan* plan, int32_t field /* asd_sp_field */, int32_t k, void* dst,
+                       hipStream_t stream);
 
 /* ---- Autotuning of the iteration kernels ---- */
 

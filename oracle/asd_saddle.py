@@ -90,6 +90,11 @@ class SPParams:
     init_lr: tuple = (1e-2, 1e-5)
     cap_alpha: float = 1e-3      # S5
     cap_beta: float = 1e-3
+    # "exact": the state is kept in FP64; "fp32": after the set-up and after
+    # every iteration the state is stored as float32 values (a storage choice
+    # of an implementation, not of the paper: it measures how far FP32
+    # rounding of the state alone moves a run)
+    storage: str = "exact"
 
 
 @dataclasses.dataclass
@@ -107,6 +112,12 @@ class SPState:
     mu_beta: List[np.ndarray]
     x: List[np.ndarray]
     z: List[np.ndarray]
+
+    def round_fp32(self):
+        """Every stored value rounded to the nearest float32."""
+        for f in dataclasses.fields(self):
+            setattr(self, f.name, [np.asarray(a, dtype=np.float32).astype(np.float64)
+                                   for a in getattr(self, f.name)])
 
     def copy(self) -> "SPState":
         return dataclasses.replace(self, **{f.name: [a.copy() for a in getattr(self, f.name)]
@@ -310,9 +321,12 @@ def sp_init(p: O.Problem, st: O.DualState, prm: SPParams) -> SPState:
     z1, z2, z3, z4 = suff_stats(p, st)
     alpha = [a.copy() for a in st.alpha]
     mua, mub = price_caps(alpha, z1, prm.cap_alpha, prm.cap_beta)
-    _, x, z, _, _ = O.evaluate(p, st)
-    x, z = primal_init(p, mua, mub, x, z, prm.init_steps, prm.init_lr)
-    return SPState(alpha, z1, z2, z3, z4, mua, mub, x, z)
+    s = SPState(alpha, z1, z2, z3, z4, mua, mub, [], [])
+    _, s.x, s.z, _, _ = sp_evaluate(p, s)  # the inner minimiser of the initial duals
+    s.x, s.z = primal_init(p, mua, mub, s.x, s.z, prm.init_steps, prm.init_lr)
+    if prm.storage == "fp32":
+        s.round_fp32()
+    return s
 
 
 # ----------------------------------------------------------------------------
@@ -334,6 +348,8 @@ def sp_iteration(p: O.Problem, s: SPState, t: int, prm: SPParams):
     s.zeta2 = mix(s.zeta2, b2)
     s.zeta3 = mix(s.zeta3, b3)
     s.zeta4 = mix(s.zeta4, b4)
+    if prm.storage == "fp32":
+        s.round_fp32()
     return d
 
 

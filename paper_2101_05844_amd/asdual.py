@@ -53,6 +53,16 @@ class Params(C.Structure):
                 ("adam_eps", C.c_double), ("precision", C.c_int32)]
 
 
+class SPParams(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("gamma0", C.c_double), ("init_steps", C.c_int32),
+                ("init_lr0", C.c_double), ("init_lr1", C.c_double), ("cap_alpha", C.c_double),
+                ("cap_beta", C.c_double)]
+
+
+ASD_SP_X, ASD_SP_XBAR, ASD_SP_ALPHA, ASD_SP_ZETA1, ASD_SP_ZETA3, ASD_SP_ZETA4 = 0, 1, 2, 3, 4, 5
+ASD_SP_MU_ALPHA, ASD_SP_MU_BETA, ASD_SP_Z, ASD_SP_ZETA2 = 6, 7, 8, 9
+
+
 class Batch(C.Structure):
     _fields_ = [("S", C.c_int32), ("l0", C.c_void_p), ("u0", C.c_void_p),
                 ("lhat", C.POINTER(C.c_void_p)), ("uhat", C.POINTER(C.c_void_p)), ("c", C.c_void_p)]
@@ -103,6 +113,8 @@ EXPORTED = ["asd_net_create", "asd_net_destroy", "asd_params_default", "asd_plan
             "asd_eval", "asd_oracle", "asd_bound_grad", "asd_set_budgets", "asd_solve_group", "asd_solve_graph", "asd_check_finite",
             "asd_plan_autotune", "asd_plan_get_tuning", "asd_plan_set_tuning", "asd_interval_bounds", "asd_profile_enable", "asd_profile_read",
             "asd_solve_static", "asd_intermediate_workspace_size", "asd_intermediate_bounds", "asd_set_input_domain",
+            "asd_sp_params_default", "asd_sp_workspace_size", "asd_sp_init", "asd_sp_run", "asd_sp_bound",
+            "asd_sp_solve", "asd_sp_read",
             "asd_last_error", "asd_abi_version"]
 
 
@@ -149,6 +161,14 @@ def lib():
     L.asd_intermediate_workspace_size.argtypes = [vp, i32, C.POINTER(Params), C.POINTER(C.c_size_t)]
     L.asd_intermediate_bounds.argtypes = [vp, i32, C.POINTER(Params), vp, vp, C.POINTER(vp), C.POINTER(vp), vp,
                                           C.c_size_t, vp]
+    L.asd_sp_params_default.argtypes = [C.POINTER(SPParams)]
+    L.asd_sp_params_default.restype = None
+    L.asd_sp_workspace_size.argtypes = [vp, C.POINTER(C.c_size_t)]
+    L.asd_sp_init.argtypes = [vp, C.POINTER(SPParams), vp, C.c_size_t, vp]
+    L.asd_sp_run.argtypes = [vp, i32, i32, vp]
+    L.asd_sp_bound.argtypes = [vp, vp, vp]
+    L.asd_sp_solve.argtypes = [vp, C.POINTER(SPParams), vp, C.c_size_t, vp, vp]
+    L.asd_sp_read.argtypes = [vp, i32, i32, vp, vp]
     L.asd_profile_enable.argtypes = [vp, i32]
     L.asd_profile_read.argtypes = [vp, C.POINTER(KernelTime), i32, C.POINTER(i32)]
     L.asd_last_error.argtypes = []
@@ -157,7 +177,7 @@ def lib():
     L.asd_abi_version.restype = i32
     for name in EXPORTED:
         if name not in ("asd_net_destroy", "asd_params_default", "asd_plan_destroy", "asd_last_error",
-                        "asd_abi_version"):
+                        "asd_abi_version", "asd_sp_params_default"):
             getattr(L, name).restype = i32
     _lib = L
     return L
@@ -188,6 +208,12 @@ def _ptr(t: Optional[torch.Tensor]):
 def asd_params_default() -> Params:
     p = Params()
     lib().asd_params_default(C.byref(p))
+    return p
+
+
+def asd_sp_params_default() -> SPParams:
+    p = SPParams()
+    lib().asd_sp_params_default(C.byref(p))
     return p
 
 
@@ -327,6 +353,38 @@ class Plan:
         the balls' box hulls)."""
         self.generation += 1
         _check(lib().asd_set_input_domain(self.handle, domain, _ptr(centre), _ptr(radius), _stream(stream)))
+
+    # -- Saddle Point (Sec. 5) from the plan's current duals ------------------
+    def sp_init(self, sp: SPParams, stream=None):
+        """asd_sp_init with a workspace owned by this object (kept until the
+        next sp_init)."""
+        nbytes = C.c_size_t()
+        _check(lib().asd_sp_workspace_size(self.handle, C.byref(nbytes)))
+        self._sp_ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device="cuda")
+        aligned = (self._sp_ws.data_ptr() + 255) // 256 * 256
+        self._sp = sp
+        _check(lib().asd_sp_init(self.handle, C.byref(sp), aligned, nbytes.value, _stream(stream)))
+
+    def sp_run(self, t_begin: int, n_iters: int, stream=None):
+        _check(lib().asd_sp_run(self.handle, t_begin, n_iters, _stream(stream)))
+
+    def sp_bound(self, stream=None) -> torch.Tensor:
+        out = torch.empty(self.S, dtype=torch.float64, device="cuda")
+        _check(lib().asd_sp_bound(self.handle, out.data_ptr(), _stream(stream)))
+        return out
+
+    def sp_solve(self, sp: SPParams, stream=None) -> torch.Tensor:
+        """Saddle Point (AS-SP after Active Set iterations) from the current
+        duals: set-up, sp.iters iterations and the bound."""
+        self.sp_init(sp, stream)
+        self.sp_run(0, sp.iters, stream)
+        return self.sp_bound(stream)
+
+    def sp_read(self, field: int, k: int, stream=None) -> torch.Tensor:
+        n = self.net.sizes[k - 1] if field == ASD_SP_ZETA2 else self.net.sizes[k]
+        out = torch.empty(self.S, n, dtype=self.dtype, device="cuda")
+        _check(lib().asd_sp_read(self.handle, field, k, out.data_ptr(), _stream(stream)))
+        return out
 
     def autotune(self, ktune: int = 2, reps: int = 5, stream=None):
         """asd_plan_autotune (after init); returns the chosen tuning."""

@@ -1599,6 +1599,7 @@ asd_status asd_init(asd_plan* P, const asd_batch* b, hipStream_t st) {
     if (is64(P)) TRY(init_t<double>(P, b, st));
     else TRY(init_t<float>(P, b, st));
     P->loaded = true;
+    P->sp_ready = false;  // the Saddle Point state belongs to the previous batch
     return ASD_OK;
 }
 

@@ -110,6 +110,13 @@ struct asd_plan {
     float* ball_c;
     float* ball_r;
     float* f0f;
+    // Saddle Point state (asd_sp_init): arrays carved from the caller's SP
+    // workspace, per layer and field (asd::SpArr), FP64 objective terms per
+    // layer, and the step parameters; sp_ready until the next asd_init
+    bool sp_ready;
+    asd_sp_params sp_prm;
+    void* sp_arr[asd::kMaxLayers][16];
+    double* sp_term[asd::kMaxLayers];
     // captured iteration schedule (asd_solve_graph) and the host state it ends in
     hipGraphExec_t graph_exec;
     bool graph_valid;

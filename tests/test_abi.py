@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
     for n in declared_functions():
         assert hasattr(lib, n), n
     lib.asd_abi_version.restype = ctypes.c_int32
-    assert lib.asd_abi_version() == 2
+    assert lib.asd_abi_version() == 3
     lib.asd_last_error.restype = ctypes.c_char_p
     assert isinstance(lib.asd_last_error(), bytes)
 

@@ -1,0 +1,264 @@
+"""GPU parity of Saddle Point and AS-SP (Sec. 5, Algorithm 2; App. C)
+against the FP64 oracle, through the C ABI.
+
+Both sides start from the same duals (the oracle's Big-M or Active Set run,
+written into the plan), so every difference comes from the Saddle Point
+kernels.  Tolerances:
+  FP64 plans: every state array (alpha, the four statistics, the caps, the
+              primal iterate) after the set-up within 1e-9 of the array's
+              scale (1 + max |entry|); every iteration as a window: from the
+              plan's state (read back), one oracle iteration against the
+              plan's next state within 1e-12 of the scale; the bound equal to
+              the oracle's evaluation of the plan's final statistics within
+              1e-10 of the summed term magnitudes; the whole run within 1e-3
+              (relative) of the oracle's own run (SP-FW's decisions are
+              discrete: the last-bit differences a set-up leaves can meet a
+              near-tie and move the rest of a run by a step gamma_t);
+  FP32 plans: the bound (the FP64 evaluation of the stored statistics)
+              equals the oracle's evaluation of the same statistics within
+              1e-10 of the summed term magnitudes and never exceeds a sampled
+              network output.  Its distance from the FP64 oracle's run is
+              held to a band measured from the oracle alone: the same run
+              with its state stored as float32 after every step moves the
+              bound by some relative amount (max and mean over the compared
+              subproblems); FP32 arithmetic adds rounding of the products
+              and sums on top of that, so the band is four times the storage
+              model's spread (max at least 1e-3, mean at least 2.5e-4).
+"""
+import numpy as np
+import pytest
+
+from oracle import asd_oracle as O
+from oracle import asd_saddle as SP
+from paper_2101_05844_amd import workloads as WL
+from tests import helpers as H
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _A():
+    from paper_2101_05844_amd import asdual as A
+    A.lib()
+    return A
+
+
+FIELDS = ("x", "xbar", "alpha", "zeta1", "zeta3", "zeta4", "mu_alpha", "mu_beta", "z", "zeta2")
+
+
+def _workloads():
+    ws = H.workloads_small()
+    return [ws[0], ws[1], ws[2], WL.mnist_mlp_config()]
+
+
+def _setup(w, prec, as_iters, point_inputs=0):
+    A = _A()
+    if point_inputs:
+        w.u0[:, :point_inputs] = w.l0[:, :point_inputs]
+    ops, lh, uh = H.oracle_bounds(w)
+    probs = H.oracle_problems(w, ops, lh, uh)
+    prm_o = O.params_from_schedule(w.schedule)
+    prm_o.as_iters = as_iters
+    states = [O.solve(p, prm_o).state for p in probs]
+    net = A.Net(w.layers)
+    prm = A.params_from_schedule(w.schedule, A.ASD_PREC_FP64 if prec == "fp64" else A.ASD_PREC_FP32)
+    plan = A.Plan(net, w.S, prm)
+    batch = H.gpu_batch(w, lh, uh)
+    plan.init(*batch)
+    H.import_states(plan, probs, states)
+    return A, ops, probs, states, net, plan, batch
+
+
+def _sp_params(A, iters, init_steps):
+    q = A.asd_sp_params_default()
+    q.iters, q.init_steps = iters, init_steps
+    return q
+
+
+def _oracle_params(q):
+    return SP.SPParams(iters=q.iters, gamma0=q.gamma0, init_steps=q.init_steps, init_lr=(q.init_lr0, q.init_lr1),
+                       cap_alpha=q.cap_alpha, cap_beta=q.cap_beta)
+
+
+def _gpu_state(A, plan, n):
+    out = {}
+    codes = {"x": A.ASD_SP_X, "xbar": A.ASD_SP_XBAR, "alpha": A.ASD_SP_ALPHA, "zeta1": A.ASD_SP_ZETA1,
+             "zeta3": A.ASD_SP_ZETA3, "zeta4": A.ASD_SP_ZETA4, "mu_alpha": A.ASD_SP_MU_ALPHA,
+             "mu_beta": A.ASD_SP_MU_BETA, "z": A.ASD_SP_Z, "zeta2": A.ASD_SP_ZETA2}
+    for f, code in codes.items():
+        ks = range(0, n) if f in ("x", "xbar") else range(1, n)
+        out[f] = {k: plan.sp_read(code, k).cpu().numpy().astype(np.float64) for k in ks}
+    torch.cuda.synchronize()
+    return out
+
+
+def _oracle_arrays(s: SP.SPState, n):
+    return {"x": {k: s.x[k] for k in range(n)},
+            "alpha": {k: s.alpha[k - 1] for k in range(1, n)},
+            "zeta1": {k: s.zeta1[k - 1] for k in range(1, n)},
+            "zeta2": {k: s.zeta2[k - 1] for k in range(1, n)},
+            "zeta3": {k: s.zeta3[k - 1] for k in range(1, n)},
+            "zeta4": {k: s.zeta4[k - 1] for k in range(1, n)},
+            "mu_alpha": {k: s.mu_alpha[k - 1] for k in range(1, n)},
+            "mu_beta": {k: s.mu_beta[k - 1] for k in range(1, n)},
+            "z": {k: s.z[k - 1] for k in range(1, n)}}
+
+
+def _compare(gpu, ora_states, n, tol, what):
+    for f, per_k in _oracle_arrays(ora_states[0], n).items():
+        for k in per_k:
+            ref = np.stack([_oracle_arrays(st, n)[f][k] for st in ora_states])
+            got = gpu[f][k][:len(ora_states)]
+            scale = 1.0 + np.abs(ref).max()
+            err = np.abs(got - ref).max() / scale
+            assert err <= tol, (what, f, k, err, np.unravel_index(np.abs(got - ref).argmax(), ref.shape))
+
+
+def _state_from(gpu, s, n):
+    g = lambda f, k: gpu[f][k][s].copy()
+    return SP.SPState([g("alpha", k) for k in range(1, n)], [g("zeta1", k) for k in range(1, n)],
+                      [g("zeta2", k) for k in range(1, n)], [g("zeta3", k) for k in range(1, n)],
+                      [g("zeta4", k) for k in range(1, n)], [g("mu_alpha", k) for k in range(1, n)],
+                      [g("mu_beta", k) for k in range(1, n)], [g("x", k) for k in range(n)],
+                      [g("z", k) for k in range(1, n)])
+
+
+def _windows(A, plan, probs, qo, n, iters, tol):
+    """Each iteration from the plan's own state: one oracle step against the
+    plan's next state."""
+    gpu = _gpu_state(A, plan, n)
+    for t in range(iters):
+        ora = [_state_from(gpu, s, n) for s in range(len(probs))]
+        for p, s_ in zip(probs, ora):
+            SP.sp_iteration(p, s_, t, qo)
+        plan.sp_run(t, 1)
+        gpu = _gpu_state(A, plan, n)
+        _compare(gpu, ora, n, tol, f"window {t}")
+    return gpu
+
+
+def _check_fp64(A, plan, probs, states, n, q):
+    qo = _oracle_params(q)
+    ora = [SP.sp_init(p, st, qo) for p, st in zip(probs, states)]
+    plan.sp_init(q)
+    _compare(_gpu_state(A, plan, n), ora, n, 1e-9, "set-up")
+    gpu = _windows(A, plan, probs, qo, n, q.iters, 1e-12)
+    lb = plan.sp_bound().cpu().numpy()
+    _bound_vs_oracle_eval(gpu, probs, lb, n, 1e-10)
+    for t in range(q.iters):
+        for p, s_ in zip(probs, ora):
+            SP.sp_iteration(p, s_, t, qo)
+    for s, (p, st) in enumerate(zip(probs, ora)):
+        d = SP.sp_evaluate(p, st)[0]
+        assert abs(lb[s] - d) <= 1e-3 * max(1.0, abs(d)), (s, lb[s], d)
+    return lb
+
+
+@pytest.mark.parametrize("wi", [0, 1, 2, 3])
+@pytest.mark.parametrize("as_iters", [0, None])
+def test_fp64_matches_oracle(wi, as_iters):
+    """Saddle Point (from Big-M duals) and AS-SP (from Active Set duals with
+    masks) in an FP64 plan against the oracle from the same duals."""
+    w = _workloads()[wi]
+    ai = w.schedule.as_iters if as_iters is None else as_iters
+    A, ops, probs, states, net, plan, batch = _setup(w, "fp64", ai)
+    _check_fp64(A, plan, probs, states, net.n, _sp_params(A, 25, 20))
+
+
+def test_fp64_point_boxes_and_zero_iterations():
+    """Inputs fixed to a point (l0 = u0) tie the oracle's test exactly (bit 1
+    on both sides); with T = 0 the bound is that of the initial duals."""
+    w = _workloads()[1]
+    A, ops, probs, states, net, plan, batch = _setup(w, "fp64", w.schedule.as_iters, point_inputs=5)
+    q = _sp_params(A, 0, 10)
+    lb0 = plan.sp_solve(q).cpu().numpy()
+    for s, (p, st) in enumerate(zip(probs, states)):
+        d = O.evaluate(p, st)[0]
+        assert abs(lb0[s] - d) <= 1e-10 * max(1.0, abs(d)), (s, lb0[s], d)
+    _check_fp64(A, plan, probs, states, net.n, _sp_params(A, 20, 10))
+
+
+def _sampled_min(ops, p, l0, u0, seed, n=4000):
+    pts = WL.random_points_in_box(l0.astype(np.float64), u0.astype(np.float64), n, 100 + seed)
+    return float((O.network_output(ops, pts) @ p.c).min())
+
+
+def _bound_vs_oracle_eval(gpu, probs, lb, n, rel):
+    """The bound against the oracle's FP64 evaluation of the stored statistics."""
+    for s, p in enumerate(probs):
+        g = lambda f, k: gpu[f][k][s]
+        f_, g_, const = SP.sp_dual_functions(p, [g("alpha", k) for k in range(1, n)],
+                                             [g("zeta1", k) for k in range(1, n)],
+                                             [g("zeta2", k) for k in range(1, n)],
+                                             [g("zeta3", k) for k in range(1, n)],
+                                             [g("zeta4", k) for k in range(1, n)])
+        x, z = O.inner_min(p, f_, g_)
+        d = O.dual_value(f_, g_, const, x, z)
+        terms = abs(const) + sum(float(np.abs(a * b).sum()) for a, b in zip(f_, x)) + \
+            sum(float(np.abs(a * b).sum()) for a, b in zip(g_, z))
+        assert abs(lb[s] - d) <= rel * max(1.0, terms), (s, lb[s], d)
+
+
+@pytest.mark.parametrize("wi", [0, 1, 2, 3])
+def test_fp32_runs(wi):
+    """FP32 plans: the bound is the FP64 evaluation of the stored statistics
+    (per result, against the oracle's evaluation of the same values), valid
+    against sampled outputs, and within the FP32 band of the FP64 oracle."""
+    import dataclasses
+    w = _workloads()[wi]
+    A, ops, probs, states, net, plan, batch = _setup(w, "fp32", w.schedule.as_iters)
+    q = _sp_params(A, 60, 40)
+    qo = _oracle_params(q)
+    lb = plan.sp_solve(q).cpu().numpy()
+    gpu = _gpu_state(A, plan, net.n)
+    _bound_vs_oracle_eval(gpu, probs, lb, net.n, 1e-10)
+    got, model = [], []
+    for s, (p, st) in enumerate(zip(probs[:12], states[:12])):
+        # the oracle from the duals as the FP32 plan holds them
+        st32 = st.copy()
+        for arrs in (st32.alpha, st32.beta0, st32.beta1):
+            for i in range(len(arrs)):
+                arrs[i] = H.f32(arrs[i]).astype(np.float64)
+        for masks in st32.masks:
+            for M in masks:
+                M.beta = H.f32(M.beta).astype(np.float64)
+        r = SP.sp_solve(p, st32, qo)
+        r32 = SP.sp_solve(p, st32, dataclasses.replace(qo, storage="fp32"))
+        assert lb[s] <= _sampled_min(ops, p, w.l0[s], w.u0[s], s) + 1e-6
+        sc = max(1.0, abs(r.bound))
+        got.append(abs(lb[s] - r.bound) / sc)
+        model.append(abs(r32.bound - r.bound) / sc)
+    band_max = max(4 * max(model), 1e-3)
+    band_mean = max(4 * float(np.mean(model)), 2.5e-4)
+    print(w.name, "SP FP32 vs FP64 oracle: max", max(got), "mean", np.mean(got), "storage model max", max(model),
+          "mean", np.mean(model), flush=True)
+    assert max(got) <= band_max, (got, model)
+    assert float(np.mean(got)) <= band_mean, (got, model)
+
+
+def test_errors():
+    A = _A()
+    w = _workloads()[0]
+    A_, ops, probs, states, net, plan, batch = _setup(w, "fp32", 0)
+    with pytest.raises(A.AsdError):
+        plan.sp_run(0, 1)          # before asd_sp_init
+    q = _sp_params(A, 1, 1)
+    q.gamma0 = 0.5
+    with pytest.raises(A.AsdError):
+        plan.sp_init(q)
+    q = _sp_params(A, 1, 1)
+    q.cap_beta = 0.0
+    with pytest.raises(A.AsdError):
+        plan.sp_init(q)
+    q = _sp_params(A, 1, 1)
+    plan.sp_init(q)
+    with pytest.raises(A.AsdError):
+        plan.sp_read(A.ASD_SP_ALPHA, 0)   # alpha has no layer 0
+    plan.init(*batch)             # a new batch: the Saddle Point state is gone
+    with pytest.raises(A.AsdError):
+        plan.sp_bound()
+    centre = (batch[0] + batch[1]) / 2
+    radius = torch.full((w.S,), 0.01, device="cuda")
+    plan.set_input_domain(A.ASD_DOMAIN_L2, centre.contiguous(), radius)
+    with pytest.raises(A.AsdError):
+        plan.sp_init(q)

@@ -468,17 +468,22 @@ asd_status asd_intermediate_bounds(const asd_net* net, int32_t D, const asd_para
  *                the Big-M primal view (App. C.2), >= 0
  *   init_lr0/1   their step sizes, linear from lr0 to lr1
  *   cap_alpha    price caps (eq:price-caps): a multiplier set that is zero at
- *   cap_beta     initialisation gets this cap, > 0 */
+ *   cap_beta     initialisation gets this cap, > 0
+ *   lds_staging  1: kernels that stage one subproblem's layer in LDS where it
+ *                fits (the default); 0: every product from global memory
+ *                (the same arithmetic, another summation order) */
 typedef struct {
     int32_t iters;
     double gamma0;
     int32_t init_steps;
     double init_lr0, init_lr1;
     double cap_alpha, cap_beta;
+    int32_t lds_staging;
 } asd_sp_params;
 
 /* Sec. 7.1 / App. C: T = 100, gamma0 = 10, 100 primal steps from 1e-2 to
- * 1e-5, caps 1e-3 for the multipliers that start at zero. (host pointer) */
+ * 1e-5, caps 1e-3 for the multipliers that start at zero, LDS staging on.
+ * (host pointer) */
 void asd_sp_params_default(asd_sp_params* p);
 
 /* Bytes of the Saddle Point workspace of a plan: per ReLU layer the duals
@@ -518,7 +523,8 @@ asd_status asd_sp_solve(asd_plan* plan, const asd_sp_params* params, void* works
  * x_{k-1} contributed by layer k's multipliers). */
 typedef enum {
     ASD_SP_X = 0,      /* primal iterate x_k */
-    ASD_SP_XBAR = 1,   /* last primal conditional gradient (minimiser) of x_k */
+    ASD_SP_XBAR = 1,   /* primal conditional gradient of x_k at the current duals
+                          (the Lagrangian's minimiser, used by the next iteration) */
     ASD_SP_ALPHA = 2,
     ASD_SP_ZETA1 = 3,  /* sum over masks of beta_{k,I} */
     ASD_SP_ZETA3 = 4,  /* beta_{k,1} (lhat - b) + sum_I (W . I . Lcheck) row sums beta_{k,I} */

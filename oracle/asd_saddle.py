@@ -71,6 +71,19 @@ Readings (kept with the design notes too):
   S7  The returned bound is d(alpha^T, zeta^T) (Algorithm 2's return).
   S8  Box input domains only: the l2-ball domain is not combined with
       Saddle Point here.
+  S9  The oracle mask's violation is evaluated as
+      x - (((W . I) x - LI (1 - z)) + z (b + UI)), the quantity of
+      eq:as-supergradient with its terms grouped so that the exact ties with
+      beta_{k,0} and beta_{k,1} come out exact in floating point too: at
+      z = 1 the oracle's row is full (UI = 0) and the value is computed as
+      beta_{k,1}'s x - (W x + b) + (1 - z) lhat; at z = 0 its columns sit at
+      their check corners, (W . I) x and LI are the same sum, and the value is
+      x, as beta_{k,0}'s x - z uhat.  S3 then picks beta_{k,1} (beta_{k,0})
+      whatever the summation order of the products.
+  S10 The convex combination of the primal iterate is clipped to the boxes
+      ([l_k, u_k], [0, 1]): a no-op in exact arithmetic, it keeps rounding
+      from moving an entry one unit outside its box, where the oracle's
+      test (S3) would set a bit without the entry sitting at its corner.
 """
 from __future__ import annotations
 
@@ -208,7 +221,7 @@ def violations(p: O.Problem, k: int, x_prev, xk, zk):
     v_alpha = xh - xk
     v0 = xk - zk * uh
     v1 = xk - xh + (1.0 - zk) * lh
-    vI = xk - WI @ x_prev + LI * (1.0 - zk) - zk * op.b - UI * zk
+    vI = xk - ((WI @ x_prev - LI * (1.0 - zk)) + zk * (op.b + UI))  # S9
     return v_alpha, v0, v1, vI, I, LI, UI, WI
 
 
@@ -341,8 +354,9 @@ def sp_iteration(p: O.Problem, s: SPState, t: int, prm: SPParams):
     ab, b1, b2, b3, b4 = dual_conditional_gradient(p, s)
     gam = 1.0 / (t + prm.gamma0)
     mix = lambda cur, bar: [(1.0 - gam) * c + gam * v for c, v in zip(cur, bar)]
-    s.x = mix(s.x, xb)
-    s.z = mix(s.z, zb)
+    # S10: the combination stays in the boxes in exact arithmetic
+    s.x = [np.clip(v, *p.lu(k)) for k, v in enumerate(mix(s.x, xb))]
+    s.z = [np.clip(v, 0.0, 1.0) for v in mix(s.z, zb)]
     s.alpha = mix(s.alpha, ab)
     s.zeta1 = mix(s.zeta1, b1)
     s.zeta2 = mix(s.zeta2, b2)

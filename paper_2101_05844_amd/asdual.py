@@ -56,7 +56,7 @@ class Params(C.Structure):
 class SPParams(C.Structure):
     _fields_ = [("iters", C.c_int32), ("gamma0", C.c_double), ("init_steps", C.c_int32),
                 ("init_lr0", C.c_double), ("init_lr1", C.c_double), ("cap_alpha", C.c_double),
-                ("cap_beta", C.c_double)]
+                ("cap_beta", C.c_double), ("lds_staging", C.c_int32)]
 
 
 ASD_SP_X, ASD_SP_XBAR, ASD_SP_ALPHA, ASD_SP_ZETA1, ASD_SP_ZETA3, ASD_SP_ZETA4 = 0, 1, 2, 3, 4, 5

@@ -51,6 +51,7 @@ static_assert(SA_COUNT <= 16, "plan field sp_arr holds 16 arrays per layer");
 namespace {
 
 constexpr int kSpBlock = 256;
+constexpr int kSpLdsBlock = 1024;  // one block per subproblem: 16 waves
 
 __device__ __forceinline__ void split_index(long idx, int S, const NeuronLayout& L, int& c, int& s, int& p) {
     const long sp = (long)S * L.P;
@@ -90,6 +91,11 @@ __device__ __forceinline__ void for_rows(const LayerGeo& g, int S, int c, int s,
             }
         }
     }
+}
+
+template <typename T>
+__device__ __forceinline__ T clip_to(T v, T lo, T hi) {
+    return v < lo ? lo : (v > hi ? hi : v);
 }
 
 // Oracle mask bit of weight w between column value x in [l, u] and row z.
@@ -202,34 +208,24 @@ struct SpFwdArgs {
 // beta*_1 -> brow, beta*_0 -> b0row.  MODE 1: dual conditional gradient and
 // its convex combination into alpha, zeta1, zeta3, zeta4; the vertex's
 // row weights of zeta2 -> arow (beta_{k,1}), brow (the oracle's mask).
+// Per-row accumulation of one weight: the product and, in MODE 1, the
+// oracle's mask sums (eq:oracle at the iterate) with their check constants.
 template <typename T, int MODE>
-__global__ void __launch_bounds__(kSpBlock) k_sp_fwd(SpFwdArgs<T> A) {
-    const LayerGeo& g = A.g;
-    const long idx = (long)blockIdx.x * kSpBlock + threadIdx.x;
-    if (idx >= (long)g.out.C * A.S * g.out.P) return;
-    int c, s, p;
-    split_index(idx, A.S, g.out, c, s, p);
-    const T zi = A.z[idx];
-    T yd = 0, sI = 0, LI = 0, UI = 0;
-    const float* Wc = g.W + (long)c * g.fan;
-    TapWalk tw = tap_walk(g, p, 0);
-    for (int t = 0; t < g.fan; ++t, tap_next(g, tw)) {
-        const FwdTap tp = tap_at(g, A.S, s, tw);
-        if (tp.a < 0) continue;  // padding
-        const T w = (T)Wc[t];
-        const T xj = A.xin[tp.a];
-        yd += w * xj;
-        if constexpr (MODE == 1) {
-            const T l = A.loin[tp.a], u = A.hiin[tp.a];
-            if (mask_bit(w, l, u, xj, zi)) {
-                sI += w * xj;
-                LI += w * (w >= (T)0 ? l : u);
-            } else {
-                UI += w * (w >= (T)0 ? u : l);
-            }
+__device__ __forceinline__ void fwd_tap(T w, T xj, T l, T u, T zi, T& yd, T& sI, T& LI, T& UI) {
+    yd += w * xj;
+    if constexpr (MODE == 1) {
+        if (mask_bit(w, l, u, xj, zi)) {
+            sI += w * xj;
+            LI += w * (w >= (T)0 ? l : u);
+        } else {
+            UI += w * (w >= (T)0 ? u : l);
         }
     }
-    const T b = (T)g.b[c];
+}
+
+template <typename T, int MODE>
+__device__ __forceinline__ void fwd_epilogue(const SpFwdArgs<T>& A, long idx, int c, T zi, T yd, T sI, T LI, T UI) {
+    const T b = (T)A.g.b[c];
     const T x = A.x[idx];
     const T lh = A.lhat[idx], uh = A.uhat[idx];
     const T xh = yd + b;
@@ -243,7 +239,10 @@ __global__ void __launch_bounds__(kSpBlock) k_sp_fwd(SpFwdArgs<T> A) {
         A.brow[idx] = on && pick1 ? A.mub[idx] : (T)0;
         A.b0row[idx] = on && !pick1 ? A.mub[idx] : (T)0;
     } else {
-        const T vI = x - sI + LI * ((T)1 - zi) - zi * b - UI * zi;
+        // grouped so that the exact ties come out exact: at z = 1 (full row,
+        // UI = 0) as beta_{k,1}'s value, at z = 0 (columns at their check
+        // corners: sI and LI the same sum) as beta_{k,0}'s
+        const T vI = x - ((sI - LI * ((T)1 - zi)) + zi * (b + UI));
         T best = v0;
         int ch = 0;
         if (v1 > best) { best = v1; ch = 1; }
@@ -258,6 +257,137 @@ __global__ void __launch_bounds__(kSpBlock) k_sp_fwd(SpFwdArgs<T> A) {
         A.z4[idx] = om * A.z4[idx] + gm * (w0 * (uh - b) + w2 * UI);
         A.arow[idx] = w1;
         A.brow[idx] = w2;
+    }
+}
+
+// One thread per neuron of layer k, inputs read from global memory (any
+// size of layer k-1).
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kSpBlock) k_sp_fwd(SpFwdArgs<T> A) {
+    const LayerGeo& g = A.g;
+    const long idx = (long)blockIdx.x * kSpBlock + threadIdx.x;
+    if (idx >= (long)g.out.C * A.S * g.out.P) return;
+    int c, s, p;
+    split_index(idx, A.S, g.out, c, s, p);
+    const T zi = A.z[idx];
+    T yd = 0, sI = 0, LI = 0, UI = 0;
+    const float* Wc = g.W + (long)c * g.fan;
+    TapWalk tw = tap_walk(g, p, 0);
+    for (int t = 0; t < g.fan; ++t, tap_next(g, tw)) {
+        const FwdTap tp = tap_at(g, A.S, s, tw);
+        if (tp.a < 0) continue;  // padding
+        const T l = MODE == 1 ? A.loin[tp.a] : (T)0, u = MODE == 1 ? A.hiin[tp.a] : (T)0;
+        fwd_tap<T, MODE>((T)Wc[t], A.xin[tp.a], l, u, zi, yd, sI, LI, UI);
+    }
+    fwd_epilogue<T, MODE>(A, idx, c, zi, yd, sI, LI, UI);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// A column of layer k-1 as staged in LDS: iterate, box and box width (the
+// width u - l rounds as in the test of the oracle's bit).
+template <typename T>
+struct alignas(4 * sizeof(T)) SpCol {
+    T x, l, u, d;
+};
+
+// Per-row accumulation of one weight from a staged column (the arithmetic of
+// fwd_tap with the stored width).
+template <typename T, int MODE>
+__device__ __forceinline__ void fwd_tap_col(T w, const SpCol<T>& q, T zi, T& yd, T& sI, T& LI, T& UI) {
+    const T p = w * q.x;
+    yd += p;
+    if constexpr (MODE == 1) {
+        const bool bit = w >= (T)0 ? (q.l - q.x) + zi * q.d >= (T)0 : (q.u - q.x) - zi * q.d <= (T)0;
+        if (bit) {
+            sI += p;
+            LI += w * (w >= (T)0 ? q.l : q.u);
+        } else {
+            UI += w * (w >= (T)0 ? q.u : q.l);
+        }
+    }
+}
+
+// One block per subproblem: layer k-1's iterate and box staged in LDS
+// (one SpCol per neuron), then a dense layer takes one row per wave (lanes
+// split the fan-in, partial sums folded across the wave) and a convolution
+// one output neuron per thread; CU: every wave's outputs share one channel
+// (P_k a multiple of 64), so the weights are wave-uniform (scalar loads, a
+// uniform branch on their sign).
+template <typename T, int MODE, bool CU>
+__global__ void __launch_bounds__(kSpLdsBlock) k_sp_fwd_lds(SpFwdArgs<T> A) {
+    extern __shared__ unsigned char sp_lds_raw[];
+    const LayerGeo& g = A.g;
+    const NeuronLayout& Li = g.in;
+    const NeuronLayout& Lo = g.out;
+    const int s = blockIdx.x, S = A.S;
+    const long Ni = Li.N;
+    SpCol<T>* col = reinterpret_cast<SpCol<T>*>(sp_lds_raw);
+    for (long j = threadIdx.x; j < Ni; j += kSpLdsBlock) {
+        const int c = (int)(j / Li.P), p = (int)(j - (long)c * Li.P);
+        const long a = ((long)c * S + s) * Li.P + p;
+        SpCol<T> q;
+        q.x = A.xin[a];
+        if constexpr (MODE == 1) {
+            q.l = A.loin[a];
+            q.u = A.hiin[a];
+            q.d = q.u - q.l;
+        } else {
+            q.l = q.u = q.d = (T)0;
+        }
+        col[j] = q;
+    }
+    __syncthreads();
+    if (g.kind == ASD_LAYER_DENSE) {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        for (int i = wave; i < Lo.C; i += kSpLdsBlock / 64) {
+            const long idx = (long)i * S + s;
+            const T zi = A.z[idx];
+            const float* Wi = g.W + (long)i * g.fan;
+            T yd = 0, sI = 0, LI = 0, UI = 0;
+#pragma unroll 4
+            for (int j = lane; j < g.fan; j += 64) fwd_tap_col<T, MODE>((T)Wi[j], col[j], zi, yd, sI, LI, UI);
+            yd = wave_sum(yd);
+            if constexpr (MODE == 1) {
+                sI = wave_sum(sI);
+                LI = wave_sum(LI);
+                UI = wave_sum(UI);
+            }
+            if (lane == 0) fwd_epilogue<T, MODE>(A, idx, i, zi, yd, sI, LI, UI);
+        }
+    } else {
+        const int ks = g.ksz;
+        for (long o = threadIdx.x; o < Lo.N; o += kSpLdsBlock) {
+            int c = (int)(o / Lo.P);
+            if constexpr (CU) c = __builtin_amdgcn_readfirstlane(c);
+            const int p = (int)(o - (long)c * Lo.P);
+            const long idx = ((long)c * S + s) * Lo.P + p;
+            const T zi = A.z[idx];
+            const int oy = p / Lo.W, ox = p - (p / Lo.W) * Lo.W;
+            const int iy0 = oy * g.stride - g.pad, ix0 = ox * g.stride - g.pad;
+            // wave-uniform weights are read through the scalar cache
+            const cfloat_p Wc = kconst(g.W + (long)c * g.fan);
+            T yd = 0, sI = 0, LI = 0, UI = 0;
+            for (int ci = 0; ci < Li.C; ++ci) {
+                for (int ky = 0; ky < ks; ++ky) {
+                    const int iy = iy0 + ky;
+                    if (iy < 0 || iy >= Li.H) continue;
+#pragma unroll 4
+                    for (int kx = 0; kx < ks; ++kx) {
+                        const int ix = ix0 + kx;
+                        if (ix < 0 || ix >= Li.W) continue;
+                        fwd_tap_col<T, MODE>((T)Wc[(ci * ks + ky) * ks + kx], col[ci * Li.P + iy * Li.W + ix], zi,
+                                             yd, sI, LI, UI);
+                    }
+                }
+            }
+            fwd_epilogue<T, MODE>(A, idx, c, zi, yd, sI, LI, UI);
+        }
     }
 }
 
@@ -276,14 +406,14 @@ struct SpTrArgs {
     // rows (layer L)
     const T* ralpha;     // alpha_L (BWD), alpha*_L (INIT)
     const T* rbeta1;     // beta*_{L,1} (INIT)
-    const T* rz;         // z_L (ZETA)
-    const T* rw1; const T* rw2;  // vertex row weights (ZETA)
+    const T* rz;         // z_L (STEP)
+    const T* rw1; const T* rw2;  // vertex row weights (STEP)
     // columns (layer L-1)
     const T* lo; const T* hi;
-    T* x; T* z;          // primal iterate (INIT: stepped; ZETA: read)
-    T* xbar; T* zbar;    // BWD outputs
+    T* x; T* z;          // primal iterate (INIT: stepped; STEP: combined)
+    T* xbar; T* zbar;    // primal conditional gradient (BWD, STEP: written)
     const T* alpha; const T* z1; const T* z3; const T* z4;  // own statistics (BWD)
-    const T* zeta2;      // zeta2_L (BWD: read; ZETA: combined in place)
+    const T* zeta2;      // zeta2_L (BWD: read; STEP: combined in place)
     T* zeta2w;
     const T* a0; const T* b0; const T* b1;  // own inner maximiser (INIT)
     const T* lhat; const T* uhat;           // own bounds (INIT)
@@ -295,38 +425,9 @@ struct SpTrArgs {
 // MODE 0 (BWD): f_{L-1} and the minimiser (x_bar, z_bar) of the Lagrangian
 // at the current duals; with `term` also the neuron's part of d (computed in
 // Tc).  MODE 1 (INIT): a projected subgradient step of the Big-M primal view
-// at its inner maximiser.  MODE 2 (ZETA): zeta2_L <- (1 - gamma) zeta2_L +
-// gamma (W_L^T w1 + (W_L . I)^T w2) with the oracle's mask I at the iterate.
+// at its inner maximiser.  MODE 3 (STEP): see step_epilogue.
 template <typename T, typename Tc, int MODE>
-__global__ void __launch_bounds__(kSpBlock) k_sp_tr(SpTrArgs<T, Tc> A) {
-    const LayerGeo& g = A.g;
-    const NeuronLayout& L = g.in;
-    const long idx = (long)blockIdx.x * kSpBlock + threadIdx.x;
-    if (idx >= (long)L.C * A.S * L.P) return;
-    int c, s, p;
-    split_index(idx, A.S, L, c, s, p);
-    if constexpr (MODE == 2) {
-        const T l = A.lo[idx], u = A.hi[idx], xj = A.x[idx];
-        T acc = 0;
-        for_rows(g, A.S, c, s, p, [&](float wf, long a, long) {
-            const T w = (T)wf;
-            const T w1 = A.rw1[a], w2 = A.rw2[a];
-            acc += w * w1;
-            if (w2 != (T)0 && mask_bit(w, l, u, xj, A.rz[a])) acc += w * w2;
-        });
-        A.zeta2w[idx] = A.omg * A.zeta2w[idx] + A.gam * acc;
-        return;
-    }
-    Tc acc1 = 0, acc2 = 0;
-    if (A.next) {
-        for_rows(g, A.S, c, s, p, [&](float wf, long a, long) {
-            const Tc w = (Tc)wf;
-            acc1 += w * (Tc)A.ralpha[a];
-            if constexpr (MODE == 1) acc2 += w * (Tc)A.rbeta1[a];
-        });
-    } else {
-        for_rows(g, A.S, c, s, p, [&](float wf, long a, long) { acc1 += (Tc)wf * (Tc)A.cvec[a]; });
-    }
+__device__ __forceinline__ void tr_epilogue(const SpTrArgs<T, Tc>& A, long idx, int c, Tc acc1, Tc acc2) {
     const Tc lo = (Tc)A.lo[idx], hi = (Tc)A.hi[idx];
     if constexpr (MODE == 0) {
         // f = -W^T alpha_L + zeta2_L + alpha - zeta1
@@ -368,19 +469,187 @@ __global__ void __launch_bounds__(kSpBlock) k_sp_tr(SpTrArgs<T, Tc> A) {
     }
 }
 
-// x <- (1 - gamma) x + gamma x_bar, z likewise (copy: x <- x_bar).
+// MODE 3 (STEP), the column side of one iteration after the rows' dual
+// step: zeta2_L <- (1 - gamma) zeta2_L + gamma (W_L^T w1 + (W_L . I)^T w2)
+// at the iterate (x^t, z^t); the primal combination of layer L-1 with its
+// conditional gradient (clipped to the boxes, a no-op in exact arithmetic
+// that keeps rounding from moving an entry one unit outside its box); and
+// the next primal conditional gradient from the duals just formed
+// (accB = W_L^T alpha_L, or W_n^T c).
+template <typename T, typename Tc>
+__device__ __forceinline__ void step_epilogue(const SpTrArgs<T, Tc>& A, long idx, int c, T l, T u, T xj, T accZ,
+                                              T accB) {
+    T z2 = 0;
+    if (A.next) {
+        z2 = A.omg * A.zeta2w[idx] + A.gam * accZ;
+        A.zeta2w[idx] = z2;
+    }
+    A.x[idx] = clip_to(A.omg * xj + A.gam * A.xbar[idx], l, u);
+    T f = -accB;
+    if (A.next) f = f + z2;
+    T gv = 0;
+    if (A.own) {
+        A.z[idx] = clip_to(A.omg * A.z[idx] + A.gam * A.zbar[idx], (T)0, (T)1);
+        const T z1 = A.z1[idx];
+        f = f + A.alpha[idx] - z1;
+        gv = A.z3[idx] + A.z4[idx] + (T)A.bown[c] * z1;
+        A.zbar[idx] = gv >= (T)0 ? (T)1 : (T)0;
+    }
+    A.xbar[idx] = f >= (T)0 ? u : l;
+}
+
+// One thread per neuron of layer L-1, row data read from global memory.
+template <typename T, typename Tc, int MODE>
+__global__ void __launch_bounds__(kSpBlock) k_sp_tr(SpTrArgs<T, Tc> A) {
+    const LayerGeo& g = A.g;
+    const NeuronLayout& L = g.in;
+    const long idx = (long)blockIdx.x * kSpBlock + threadIdx.x;
+    if (idx >= (long)L.C * A.S * L.P) return;
+    int c, s, p;
+    split_index(idx, A.S, L, c, s, p);
+    if constexpr (MODE == 3) {
+        const T l = A.lo[idx], u = A.hi[idx], xj = A.x[idx];
+        T accZ = 0, accB = 0;
+        if (A.next) {
+            for_rows(g, A.S, c, s, p, [&](float wf, long a, long) {
+                const T w = (T)wf;
+                const T w2 = A.rw2[a];
+                accZ += w * A.rw1[a];
+                if (w2 != (T)0 && mask_bit(w, l, u, xj, A.rz[a])) accZ += w * w2;
+                accB += w * A.ralpha[a];
+            });
+        } else {
+            for_rows(g, A.S, c, s, p, [&](float wf, long a, long) { accB += (T)wf * A.cvec[a]; });
+        }
+        step_epilogue(A, idx, c, l, u, xj, accZ, accB);
+        return;
+    }
+    Tc acc1 = 0, acc2 = 0;
+    if (A.next) {
+        for_rows(g, A.S, c, s, p, [&](float wf, long a, long) {
+            const Tc w = (Tc)wf;
+            acc1 += w * (Tc)A.ralpha[a];
+            if constexpr (MODE == 1) acc2 += w * (Tc)A.rbeta1[a];
+        });
+    } else {
+        for_rows(g, A.S, c, s, p, [&](float wf, long a, long) { acc1 += (Tc)wf * (Tc)A.cvec[a]; });
+    }
+    tr_epilogue<T, Tc, MODE>(A, idx, c, acc1, acc2);
+}
+
+// Calls fn(w, r) for every output neuron r (co P_L + op, the subproblem's
+// own row index) of layer L that reads input neuron (c, p) of layer L-1.
+template <class Fn>
+__device__ __forceinline__ void for_rows_local(const LayerGeo& g, const float* Wsrc, int c, int p, Fn&& fn) {
+    const NeuronLayout& L = g.in;
+    const NeuronLayout& O = g.out;
+    if (g.kind == ASD_LAYER_DENSE) {
+        const long j = (long)c * L.P + p;
+        for (int i = 0; i < O.C; ++i) fn(g.W[(long)i * g.fan + j], i);
+    } else {
+        const int y = p / L.W, x = p - (p / L.W) * L.W;
+        const int ks = g.ksz, str = g.stride;
+        const int ky0 = (y + g.pad) % str, kx0 = (x + g.pad) % str;
+        const int oyf = (y + g.pad - ky0) / str, oxf = (x + g.pad - kx0) / str;
+        for (int co = 0; co < O.C; ++co) {
+            int oy = oyf;
+            for (int ky = ky0; ky < ks; ky += str, --oy) {
+                if (oy < 0 || oy >= O.H) continue;
+                int ox = oxf;
+                for (int kx = kx0; kx < ks; kx += str, --ox) {
+                    if (ox < 0 || ox >= O.W) continue;
+                    fn(Wsrc[(((long)co * L.C + c) * ks + ky) * ks + kx], co * O.P + oy * O.W + ox);
+                }
+            }
+        }
+    }
+}
+
+// One block per subproblem: the rows of layer L it reads staged in LDS
+// (up to 3 N_L values), then one thread per neuron of layer L-1.
+template <typename T, typename Tc, int MODE, bool WL>
+__global__ void __launch_bounds__(kSpLdsBlock) k_sp_tr_lds(SpTrArgs<T, Tc> A) {
+    extern __shared__ unsigned char sp_lds_raw[];
+    const LayerGeo& g = A.g;
+    const NeuronLayout& L = g.in;
+    const NeuronLayout& O = g.out;
+    const int s = blockIdx.x, S = A.S;
+    const long No = O.N;
+    T* r0 = reinterpret_cast<T*>(sp_lds_raw);
+    T* r1 = r0 + No;
+    SpCol<T>* rq = reinterpret_cast<SpCol<T>*>(sp_lds_raw);  // STEP: {w1, w2, z, alpha} per row
+    for (long i = threadIdx.x; i < No; i += kSpLdsBlock) {
+        const int c = (int)(i / O.P), p = (int)(i - (long)c * O.P);
+        const long a = ((long)c * S + s) * O.P + p;
+        if constexpr (MODE == 3) {
+            if (A.next) {
+                SpCol<T> q;
+                q.x = A.rw1[a];
+                q.l = A.rw2[a];
+                q.u = A.rz[a];
+                q.d = A.ralpha[a];
+                rq[i] = q;
+            } else {
+                r0[i] = A.cvec[a];
+            }
+        } else if (!A.next) {
+            r0[i] = A.cvec[a];
+        } else {
+            r0[i] = A.ralpha[a];
+            if constexpr (MODE == 1) r1[i] = A.rbeta1[a];
+        }
+    }
+    // WL: a convolution's weights follow the rows (the transposed walk reads
+    // them at lane-dependent taps)
+    const float* Wsrc = g.W;
+    if constexpr (WL) {
+        const int nrow = MODE == 3 ? (A.next ? 4 : 1) : (MODE == 1 && A.next ? 2 : 1);
+        float* wl = reinterpret_cast<float*>(sp_lds_raw + (size_t)nrow * No * sizeof(T));
+        const long nw = (long)O.C * g.fan;
+        for (long i = threadIdx.x; i < nw; i += kSpLdsBlock) wl[i] = g.W[i];
+        Wsrc = wl;
+    }
+    __syncthreads();
+    for (long jj = threadIdx.x; jj < L.N; jj += kSpLdsBlock) {
+        const int c = (int)(jj / L.P), p = (int)(jj - (long)c * L.P);
+        const long idx = ((long)c * S + s) * L.P + p;
+        if constexpr (MODE == 3) {
+            const T l = A.lo[idx], u = A.hi[idx], xj = A.x[idx];
+            T accZ = 0, accB = 0;
+            if (A.next) {
+                for_rows_local(g, Wsrc, c, p, [&](float wf, int r) {
+                    const T w = (T)wf;
+                    const SpCol<T> q = rq[r];
+                    accZ += w * q.x;
+                    if (q.l != (T)0 && mask_bit(w, l, u, xj, q.u)) accZ += w * q.l;
+                    accB += w * q.d;
+                });
+            } else {
+                for_rows_local(g, Wsrc, c, p, [&](float wf, int r) { accB += (T)wf * r0[r]; });
+            }
+            step_epilogue(A, idx, c, l, u, xj, accZ, accB);
+        } else {
+            Tc acc1 = 0, acc2 = 0;
+            for_rows_local(g, Wsrc, c, p, [&](float wf, int r) {
+                const Tc w = (Tc)wf;
+                acc1 += w * (Tc)r0[r];
+                if constexpr (MODE == 1) {
+                    if (A.next) acc2 += w * (Tc)r1[r];
+                }
+            });
+            if (!A.next) acc2 = 0;
+            tr_epilogue<T, Tc, MODE>(A, idx, c, acc1, acc2);
+        }
+    }
+}
+
+// x <- x_bar, z <- z_bar (the primal iterate's start).
 template <typename T>
-__global__ void __launch_bounds__(kSpBlock) k_sp_mix(T* x, const T* xb, T* z, const T* zb, long n, T gam, T omg,
-                                                     int copy) {
+__global__ void __launch_bounds__(kSpBlock) k_sp_copy(T* x, const T* xb, T* z, const T* zb, long n) {
     const long i = (long)blockIdx.x * kSpBlock + threadIdx.x;
     if (i >= n) return;
-    if (copy) {
-        x[i] = xb[i];
-        if (z) z[i] = zb[i];
-    } else {
-        x[i] = omg * x[i] + gam * xb[i];
-        if (z) z[i] = omg * z[i] + gam * zb[i];
-    }
+    x[i] = xb[i];
+    if (z) z[i] = zb[i];
 }
 
 struct SpReduceArgs {
@@ -530,7 +799,17 @@ asd_status launch_tr(asd_plan* P, int L, double eta, double gam, bool bound, hip
     A.gam = (T)gam;
     A.omg = (T)(1.0 - gam);
     A.eta = (T)eta;
-    hipLaunchKernelGGL((k_sp_tr<T, Tc, MODE>), dim3(blocks_of(P->nl[k].N * P->S)), dim3(kSpBlock), 0, st, A);
+    // rows staged per subproblem where they fit in one block's LDS
+    const int nrow = MODE == 3 ? (A.next ? 4 : 1) : (MODE == 1 && A.next ? 2 : 1);  // 4: one SpCol per row
+    const size_t lds = (size_t)nrow * P->nl[L].N * sizeof(T);
+    const size_t wl = A.g.kind == ASD_LAYER_CONV2D ? (size_t)P->nl[L].C * A.g.fan * sizeof(float) : 0;
+    if (P->sp_prm.lds_staging && wl && lds + wl <= (size_t)std::min(P->lds_max, 80 * 1024))
+        hipLaunchKernelGGL((k_sp_tr_lds<T, Tc, MODE, true>), dim3((unsigned)P->S), dim3(kSpLdsBlock), lds + wl, st,
+                           A);
+    else if (P->sp_prm.lds_staging && lds <= (size_t)P->lds_max)
+        hipLaunchKernelGGL((k_sp_tr_lds<T, Tc, MODE, false>), dim3((unsigned)P->S), dim3(kSpLdsBlock), lds, st, A);
+    else
+        hipLaunchKernelGGL((k_sp_tr<T, Tc, MODE>), dim3(blocks_of(P->nl[k].N * P->S)), dim3(kSpBlock), 0, st, A);
     LAUNCH_CHECK();
     return ASD_OK;
 }
@@ -558,18 +837,26 @@ asd_status launch_fwd(asd_plan* P, int k, double gam, hipStream_t st) {
     A.b0row = arr<T>(P, k, SA_B0ROW);
     A.gam = (T)gam;
     A.omg = (T)(1.0 - gam);
-    hipLaunchKernelGGL((k_sp_fwd<T, MODE>), dim3(blocks_of(P->nl[k].N * P->S)), dim3(kSpBlock), 0, st, A);
+    // layer k-1 staged per subproblem where it fits in one block's LDS
+    const size_t lds = (size_t)P->nl[k - 1].N * sizeof(SpCol<T>);
+    const bool cu = A.g.kind == ASD_LAYER_CONV2D && P->nl[k].P % 64 == 0;
+    if (P->sp_prm.lds_staging && lds <= (size_t)P->lds_max && cu)
+        hipLaunchKernelGGL((k_sp_fwd_lds<T, MODE, true>), dim3((unsigned)P->S), dim3(kSpLdsBlock), lds, st, A);
+    else if (P->sp_prm.lds_staging && lds <= (size_t)P->lds_max)
+        hipLaunchKernelGGL((k_sp_fwd_lds<T, MODE, false>), dim3((unsigned)P->S), dim3(kSpLdsBlock), lds, st, A);
+    else
+        hipLaunchKernelGGL((k_sp_fwd<T, MODE>), dim3(blocks_of(P->nl[k].N * P->S)), dim3(kSpBlock), 0, st, A);
     LAUNCH_CHECK();
     return ASD_OK;
 }
 
 template <typename T>
-asd_status launch_mix(asd_plan* P, int k, double gam, int copy, hipStream_t st) {
+asd_status launch_copy(asd_plan* P, int k, hipStream_t st) {
     const long n = P->nl[k].N * P->S;
     T* z = k >= 1 ? arr<T>(P, k, SA_Z) : nullptr;
     const T* zb = k >= 1 ? arr<T>(P, k, SA_ZBAR) : nullptr;
-    hipLaunchKernelGGL(k_sp_mix<T>, dim3(blocks_of(n)), dim3(kSpBlock), 0, st, arr<T>(P, k, SA_X),
-                       (const T*)arr<T>(P, k, SA_XBAR), z, zb, n, (T)gam, (T)(1.0 - gam), copy);
+    hipLaunchKernelGGL(k_sp_copy<T>, dim3(blocks_of(n)), dim3(kSpBlock), 0, st, arr<T>(P, k, SA_X),
+                       (const T*)arr<T>(P, k, SA_XBAR), z, zb, n);
     LAUNCH_CHECK();
     return ASD_OK;
 }
@@ -605,9 +892,10 @@ asd_status sp_init_t(asd_plan* P, hipStream_t st) {
         hipLaunchKernelGGL(k_sp_zeta2_masks<T>, dim3(blocks_of(P->nl[k - 1].N * P->S)), dim3(kSpBlock), 0, st, Z);
         LAUNCH_CHECK();
     }
-    // the primal iterate starts at the minimiser of the Lagrangian
+    // the primal iterate starts at the minimiser of the Lagrangian, which is
+    // also the first iteration's primal conditional gradient (x_bar, z_bar)
     for (int L = 1; L <= P->n; ++L) TRY((launch_tr<T, T, 0>(P, L, 0.0, 0.0, false, st)));
-    for (int k = 0; k < P->n; ++k) TRY(launch_mix<T>(P, k, 1.0, 1, st));
+    for (int k = 0; k < P->n; ++k) TRY(launch_copy<T>(P, k, st));
     // App. C.2: subgradient steps on the Big-M primal view
     for (int tau = 0; tau < q.init_steps; ++tau) {
         const double eta = sp_linear_lr(q.init_lr0, q.init_lr1, tau, q.init_steps);
@@ -620,11 +908,11 @@ asd_status sp_init_t(asd_plan* P, hipStream_t st) {
 template <typename T>
 asd_status sp_run_t(asd_plan* P, int t_begin, int n_iters, hipStream_t st) {
     for (int t = t_begin; t < t_begin + n_iters; ++t) {
+        // the primal conditional gradient of iteration t is in x_bar, z_bar
+        // (formed at the set-up or by the previous iteration's column pass)
         const double gam = 1.0 / ((double)t + P->sp_prm.gamma0);
-        for (int L = 1; L <= P->n; ++L) TRY((launch_tr<T, T, 0>(P, L, 0.0, gam, false, st)));
         for (int k = 1; k < P->n; ++k) TRY((launch_fwd<T, 1>(P, k, gam, st)));
-        for (int L = 1; L < P->n; ++L) TRY((launch_tr<T, T, 2>(P, L, 0.0, gam, false, st)));
-        for (int k = 0; k < P->n; ++k) TRY(launch_mix<T>(P, k, gam, 0, st));
+        for (int L = 1; L <= P->n; ++L) TRY((launch_tr<T, T, 3>(P, L, 0.0, gam, false, st)));
     }
     return ASD_OK;
 }
@@ -655,6 +943,7 @@ asd_status check_sp_params(const asd_sp_params* q) {
         return fail(ASD_EINVAL, "price caps must be positive and finite");
     if (!std::isfinite(q->init_lr0) || !std::isfinite(q->init_lr1) || q->init_lr0 < 0.0 || q->init_lr1 < 0.0)
         return fail(ASD_EINVAL, "primal step sizes must be finite and >= 0");
+    if (q->lds_staging != 0 && q->lds_staging != 1) return fail(ASD_EINVAL, "lds_staging must be 0 or 1");
     return ASD_OK;
 }
 
@@ -671,6 +960,7 @@ void asd_sp_params_default(asd_sp_params* p) {
     p->init_lr1 = 1e-5;
     p->cap_alpha = 1e-3;
     p->cap_beta = 1e-3;
+    p->lds_staging = 1;
 }
 
 asd_status asd_sp_workspace_size(const asd_plan* P, size_t* bytes) {

@@ -156,13 +156,18 @@ def _check_fp64(A, plan, probs, states, n, q):
 
 @pytest.mark.parametrize("wi", [0, 1, 2, 3])
 @pytest.mark.parametrize("as_iters", [0, None])
-def test_fp64_matches_oracle(wi, as_iters):
+@pytest.mark.parametrize("staged", [1, 0])
+def test_fp64_matches_oracle(wi, as_iters, staged):
     """Saddle Point (from Big-M duals) and AS-SP (from Active Set duals with
-    masks) in an FP64 plan against the oracle from the same duals."""
+    masks) in an FP64 plan against the oracle from the same duals, with the
+    kernels that stage a subproblem's layer in LDS and with the ones that
+    read global memory only."""
     w = _workloads()[wi]
     ai = w.schedule.as_iters if as_iters is None else as_iters
     A, ops, probs, states, net, plan, batch = _setup(w, "fp64", ai)
-    _check_fp64(A, plan, probs, states, net.n, _sp_params(A, 25, 20))
+    q = _sp_params(A, 25, 20)
+    q.lds_staging = staged
+    _check_fp64(A, plan, probs, states, net.n, q)
 
 
 def test_fp64_point_boxes_and_zero_iterations():
@@ -199,8 +204,8 @@ def _bound_vs_oracle_eval(gpu, probs, lb, n, rel):
         assert abs(lb[s] - d) <= rel * max(1.0, terms), (s, lb[s], d)
 
 
-@pytest.mark.parametrize("wi", [0, 1, 2, 3])
-def test_fp32_runs(wi):
+@pytest.mark.parametrize("wi,staged", [(0, 1), (1, 1), (2, 1), (3, 1), (2, 0)])
+def test_fp32_runs(wi, staged):
     """FP32 plans: the bound is the FP64 evaluation of the stored statistics
     (per result, against the oracle's evaluation of the same values), valid
     against sampled outputs, and within the FP32 band of the FP64 oracle."""
@@ -208,6 +213,7 @@ def test_fp32_runs(wi):
     w = _workloads()[wi]
     A, ops, probs, states, net, plan, batch = _setup(w, "fp32", w.schedule.as_iters)
     q = _sp_params(A, 60, 40)
+    q.lds_staging = staged
     qo = _oracle_params(q)
     lb = plan.sp_solve(q).cpu().numpy()
     gpu = _gpu_state(A, plan, net.n)
@@ -248,6 +254,10 @@ def test_errors():
         plan.sp_init(q)
     q = _sp_params(A, 1, 1)
     q.cap_beta = 0.0
+    with pytest.raises(A.AsdError):
+        plan.sp_init(q)
+    q = _sp_params(A, 1, 1)
+    q.lds_staging = 2
     with pytest.raises(A.AsdError):
         plan.sp_init(q)
     q = _sp_params(A, 1, 1)

@@ -377,7 +377,6 @@ __global__ void __launch_bounds__(kSpLdsBlock) k_sp_fwd_lds(SpFwdArgs<T> A) {
                 for (int ky = 0; ky < ks; ++ky) {
                     const int iy = iy0 + ky;
                     if (iy < 0 || iy >= Li.H) continue;
-#pragma unroll 4
                     for (int kx = 0; kx < ks; ++kx) {
                         const int ix = ix0 + kx;
                         if (ix < 0 || ix >= Li.W) continue;
@@ -565,9 +564,38 @@ __device__ __forceinline__ void for_rows_local(const LayerGeo& g, const float* W
     }
 }
 
+// for_rows_local for a convolution of kernel size KS and stride STR known at
+// compile time: the taps of each output channel unrolled, an invalid tap
+// (outside the output map, or past the kernel) called with weight 0 and row
+// 0, which adds only signed zeros to the caller's sums.
+template <int KS, int STR, class Fn>
+__device__ __forceinline__ void for_rows_conv_fixed(const LayerGeo& g, const float* Wsrc, int c, int p, Fn&& fn) {
+    const NeuronLayout& L = g.in;
+    const NeuronLayout& O = g.out;
+    constexpr int NT = (KS + STR - 1) / STR;
+    const int y = p / L.W, x = p - (p / L.W) * L.W;
+    const int ky0 = (y + g.pad) % STR, kx0 = (x + g.pad) % STR;
+    const int oyf = (y + g.pad - ky0) / STR, oxf = (x + g.pad - kx0) / STR;
+    for (int co = 0; co < O.C; ++co) {
+        const float* Wco = Wsrc + ((long)co * L.C + c) * (KS * KS);
+#pragma unroll
+        for (int a = 0; a < NT; ++a) {
+            const int ky = ky0 + a * STR, oy = oyf - a;
+            const bool vy = ky < KS && oy >= 0 && oy < O.H;
+#pragma unroll
+            for (int b = 0; b < NT; ++b) {
+                const int kx = kx0 + b * STR, ox = oxf - b;
+                const bool v = vy && kx < KS && ox >= 0 && ox < O.W;
+                const float wv = Wco[v ? ky * KS + kx : 0];
+                fn(v ? wv : 0.f, v ? co * O.P + oy * O.W + ox : 0);
+            }
+        }
+    }
+}
+
 // One block per subproblem: the rows of layer L it reads staged in LDS
 // (up to 3 N_L values), then one thread per neuron of layer L-1.
-template <typename T, typename Tc, int MODE, bool WL>
+template <typename T, typename Tc, int MODE, bool WL, int KS = 0, int STR = 0>
 __global__ void __launch_bounds__(kSpLdsBlock) k_sp_tr_lds(SpTrArgs<T, Tc> A) {
     extern __shared__ unsigned char sp_lds_raw[];
     const LayerGeo& g = A.g;
@@ -610,6 +638,10 @@ __global__ void __launch_bounds__(kSpLdsBlock) k_sp_tr_lds(SpTrArgs<T, Tc> A) {
         Wsrc = wl;
     }
     __syncthreads();
+    auto rows = [&](int c, int p, auto&& fn) {
+        if constexpr (KS > 0) for_rows_conv_fixed<KS, STR>(g, Wsrc, c, p, fn);
+        else for_rows_local(g, Wsrc, c, p, fn);
+    };
     for (long jj = threadIdx.x; jj < L.N; jj += kSpLdsBlock) {
         const int c = (int)(jj / L.P), p = (int)(jj - (long)c * L.P);
         const long idx = ((long)c * S + s) * L.P + p;
@@ -617,7 +649,7 @@ __global__ void __launch_bounds__(kSpLdsBlock) k_sp_tr_lds(SpTrArgs<T, Tc> A) {
             const T l = A.lo[idx], u = A.hi[idx], xj = A.x[idx];
             T accZ = 0, accB = 0;
             if (A.next) {
-                for_rows_local(g, Wsrc, c, p, [&](float wf, int r) {
+                rows(c, p, [&](float wf, int r) {
                     const T w = (T)wf;
                     const SpCol<T> q = rq[r];
                     accZ += w * q.x;
@@ -625,12 +657,12 @@ __global__ void __launch_bounds__(kSpLdsBlock) k_sp_tr_lds(SpTrArgs<T, Tc> A) {
                     accB += w * q.d;
                 });
             } else {
-                for_rows_local(g, Wsrc, c, p, [&](float wf, int r) { accB += (T)wf * r0[r]; });
+                rows(c, p, [&](float wf, int r) { accB += (T)wf * r0[r]; });
             }
             step_epilogue(A, idx, c, l, u, xj, accZ, accB);
         } else {
             Tc acc1 = 0, acc2 = 0;
-            for_rows_local(g, Wsrc, c, p, [&](float wf, int r) {
+            rows(c, p, [&](float wf, int r) {
                 const Tc w = (Tc)wf;
                 acc1 += w * (Tc)r0[r];
                 if constexpr (MODE == 1) {
@@ -803,10 +835,16 @@ asd_status launch_tr(asd_plan* P, int L, double eta, double gam, bool bound, hip
     const int nrow = MODE == 3 ? (A.next ? 4 : 1) : (MODE == 1 && A.next ? 2 : 1);  // 4: one SpCol per row
     const size_t lds = (size_t)nrow * P->nl[L].N * sizeof(T);
     const size_t wl = A.g.kind == ASD_LAYER_CONV2D ? (size_t)P->nl[L].C * A.g.fan * sizeof(float) : 0;
-    if (P->sp_prm.lds_staging && wl && lds + wl <= (size_t)std::min(P->lds_max, 80 * 1024))
-        hipLaunchKernelGGL((k_sp_tr_lds<T, Tc, MODE, true>), dim3((unsigned)P->S), dim3(kSpLdsBlock), lds + wl, st,
-                           A);
-    else if (P->sp_prm.lds_staging && lds <= (size_t)P->lds_max)
+    const int ks = A.g.ksz, sd = A.g.stride;
+    const dim3 grid((unsigned)P->S), block(kSpLdsBlock);
+    if (P->sp_prm.lds_staging && wl && lds + wl <= (size_t)std::min(P->lds_max, 80 * 1024)) {
+        if (ks == 4 && sd == 2)
+            hipLaunchKernelGGL((k_sp_tr_lds<T, Tc, MODE, true, 4, 2>), grid, block, lds + wl, st, A);
+        else if (ks == 3 && sd == 1)
+            hipLaunchKernelGGL((k_sp_tr_lds<T, Tc, MODE, true, 3, 1>), grid, block, lds + wl, st, A);
+        else
+            hipLaunchKernelGGL((k_sp_tr_lds<T, Tc, MODE, true>), grid, block, lds + wl, st, A);
+    } else if (P->sp_prm.lds_staging && lds <= (size_t)P->lds_max)
         hipLaunchKernelGGL((k_sp_tr_lds<T, Tc, MODE, false>), dim3((unsigned)P->S), dim3(kSpLdsBlock), lds, st, A);
     else
         hipLaunchKernelGGL((k_sp_tr<T, Tc, MODE>), dim3(blocks_of(P->nl[k].N * P->S)), dim3(kSpBlock), 0, st, A);
@@ -840,10 +878,12 @@ asd_status launch_fwd(asd_plan* P, int k, double gam, hipStream_t st) {
     // layer k-1 staged per subproblem where it fits in one block's LDS
     const size_t lds = (size_t)P->nl[k - 1].N * sizeof(SpCol<T>);
     const bool cu = A.g.kind == ASD_LAYER_CONV2D && P->nl[k].P % 64 == 0;
-    if (P->sp_prm.lds_staging && lds <= (size_t)P->lds_max && cu)
-        hipLaunchKernelGGL((k_sp_fwd_lds<T, MODE, true>), dim3((unsigned)P->S), dim3(kSpLdsBlock), lds, st, A);
-    else if (P->sp_prm.lds_staging && lds <= (size_t)P->lds_max)
-        hipLaunchKernelGGL((k_sp_fwd_lds<T, MODE, false>), dim3((unsigned)P->S), dim3(kSpLdsBlock), lds, st, A);
+    const bool staged = P->sp_prm.lds_staging && lds <= (size_t)P->lds_max;
+    const dim3 grid((unsigned)P->S), block(kSpLdsBlock);
+    if (staged && cu)
+        hipLaunchKernelGGL((k_sp_fwd_lds<T, MODE, true>), grid, block, lds, st, A);
+    else if (staged)
+        hipLaunchKernelGGL((k_sp_fwd_lds<T, MODE, false>), grid, block, lds, st, A);
     else
         hipLaunchKernelGGL((k_sp_fwd<T, MODE>), dim3(blocks_of(P->nl[k].N * P->S)), dim3(kSpBlock), 0, st, A);
     LAUNCH_CHECK();

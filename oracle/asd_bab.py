@@ -42,7 +42,8 @@ Readings (kept with the design notes too):
   B5  Stratification: a_l is the Big-M solver (Algorithm 3) alone, a_t is
       Big-M followed by Active Set.  At the root both run (from zero duals);
       l_{a_t - a_l} is their difference and the root keeps a_t's bound and
-      duals.  i(s) is an exponential moving average (weight rho = 0.25 of
+      duals, but is not itself marked hard (the rule marks subtrees below
+      it).  i(s) is an exponential moving average (weight rho = 0.25 of
       the newest) of lb(child) - lb(parent) over the children in batch order;
       before the first batch, or while i <= 0, a child uses its parent's
       algorithm (a_l below the root).  Otherwise a child s of parent p is
@@ -184,7 +185,7 @@ def bab(ops, l0, u0, c, lhat, uhat, prm: BaBParams) -> BaBResult:
     if branch_neuron(lhat, uhat) is None:
         return BaBResult("unknown", 0, nodes, None, [], root, [(lhat, uhat, lb_t, "undecided")])
     leaves = []
-    open_ = [Domain(rid, lhat, uhat, lb_t, st_t, True, 0)]
+    open_ = [Domain(rid, lhat, uhat, lb_t, st_t, False, 0)]  # B5: the rule marks subtrees below the root
     undecided = 0
     ema = None
     trace = []

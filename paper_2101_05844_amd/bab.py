@@ -159,7 +159,7 @@ class BranchAndBound:
             return res("verified", 0, nodes, None, [])
         if branch_neuron(lhat, uhat) is None:
             return res("unknown", 0, nodes, None, [])
-        open_ = [_Domain(rid, lhat, uhat, lb_t, du_t, True, 0)]
+        open_ = [_Domain(rid, lhat, uhat, lb_t, du_t, False, 0)]  # the rule marks subtrees below the root
         undecided = 0
         ema = None
         trace = []

@@ -170,6 +170,18 @@ def test_fp64_matches_oracle(wi, as_iters, staged):
     _check_fp64(A, plan, probs, states, net.n, q)
 
 
+@pytest.mark.parametrize("staged", [1, 0])
+def test_fp64_convolutional_output_layer(staged):
+    """A net ending in a convolution: the objective rows live in the output
+    convolution's layout (the last column pass walks its transposed taps)."""
+    from tests.test_gpu_intermediate import conv_out_workloads
+    w = conv_out_workloads()[1]
+    A, ops, probs, states, net, plan, batch = _setup(w, "fp64", w.schedule.as_iters)
+    q = _sp_params(A, 15, 10)
+    q.lds_staging = staged
+    _check_fp64(A, plan, probs, states, net.n, q)
+
+
 def test_fp64_point_boxes_and_zero_iterations():
     """Inputs fixed to a point (l0 = u0) tie the oracle's test exactly (bit 1
     on both sides); with T = 0 the bound is that of the initial duals."""

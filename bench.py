@@ -63,7 +63,7 @@ def kernel_unit_bytes(role, layer, sizes, K, mixed=False):
 # gradient's kernels and the Saddle Point unit (the counter runs launch
 # neither) and the host driver's orchestration (which kernel runs when, not
 # what a launch moves)
-UNCOUNTED_SOURCES = ("asd_adjoint.h", "asd_api.hip", "asd_sp.hip")
+UNCOUNTED_SOURCES = ("asd_adjoint.h", "asd_api.hip", "asd_grad.hip", "asd_sp.hip")
 
 
 def source_digest():

@@ -2,8 +2,9 @@
 
 The library is one host/general translation unit (asd_api.hip), the
 iteration-kernel launches of asd_iter.hip compiled once per active-mask
-count (-DASD_NM=0..ASD_MAX_MASKS) and the Saddle Point unit (asd_sp.hip,
-compiled without floating-point contraction); the objects compile in
+count (-DASD_NM=0..ASD_MAX_MASKS), the Saddle Point unit (asd_sp.hip,
+compiled without floating-point contraction) and the weight-gradient
+launches of asd_grad.hip, again once per active-mask count; the objects compile in
 parallel and are linked into one shared library.
 """
 import os
@@ -17,7 +18,8 @@ LIB = os.path.join(HERE, "libasdual.so")
 CSRC = os.path.join(HERE, "csrc")
 OBJDIR = os.path.join(HERE, "_build")
 MAX_MASKS = 8  # ASD_MAX_MASKS in include/asdual.h
-SOURCES = [os.path.join(CSRC, "asd_api.hip"), os.path.join(CSRC, "asd_iter.hip"), os.path.join(CSRC, "asd_sp.hip")]
+SOURCES = [os.path.join(CSRC, "asd_api.hip"), os.path.join(CSRC, "asd_iter.hip"), os.path.join(CSRC, "asd_sp.hip"),
+           os.path.join(CSRC, "asd_grad.hip")]
 HEADERS = [os.path.join(CSRC, h) for h in ("asd_internal.h", "asd_kernels.h", "asd_fast.h", "asd_adjoint.h",
                                            "asd_plan.h")] + [os.path.join(ROOT, "include", "asdual.h")]
 
@@ -39,6 +41,8 @@ def units():
     for nm in range(MAX_MASKS + 1):
         out.append((SOURCES[1], os.path.join(OBJDIR, f"asd_iter_nm{nm}.o"), [f"-DASD_NM={nm}"]))
     out.append((SOURCES[2], os.path.join(OBJDIR, "asd_sp.o"), ["-ffp-contract=off"]))
+    for nm in range(MAX_MASKS + 1):
+        out.append((SOURCES[3], os.path.join(OBJDIR, f"asd_grad_nm{nm}.o"), [f"-DASD_NM={nm}"]))
     return out
 
 

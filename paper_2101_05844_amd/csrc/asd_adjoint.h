@@ -69,20 +69,15 @@ __device__ __forceinline__ bool mask_entry(bool zq, float w, bool dg, bool xq) {
     return zq || w == 0.f || dg || (w > 0.f ? !xq : xq);
 }
 
-constexpr int kGdTO = 16;              // dense: outputs per block (registers per lane)
-constexpr int kGcTO = 4, kGcTT = 4;    // convolution: output channels x taps per block
-static_assert(kGcTO * kGcTT <= 32, "the weight-sign masks of a convolution tile are 32-bit");
+constexpr int kGdTO = 16;              // last dense layer: outputs per block (registers per lane)
 
-// Dense layer, stage one.  Lanes run over the inputs j (coalesced reads of
-// x*, l, u of layer k-1 and of the weights), each lane keeps kGdTO outputs i
-// in registers, the block loops over one chunk of subproblems; the output-side
-// values (duals, z bits) are uniform across the block.
+// Last (dense) layer, stage one: dW = sum_s g_s c_s x*_s^T.  Lanes run over
+// the inputs j (coalesced reads of x*), each lane keeps kGdTO outputs i in
+// registers, the block loops over one chunk of subproblems.
 template <typename Ts>
-__global__ void __launch_bounds__(kGradThreads) k_gw_dense(GradArgs<Ts> A) {
-    const cptr_t<ReluLayerT<Ts>> R = kconst_t(A.R);
+__global__ void __launch_bounds__(kGradThreads) k_gw_last(GradArgs<Ts> A) {
     const LayerGeo& g = A.g;
     const NeuronLayout& L = g.in;
-    const NeuronLayout& O = g.out;
     const int S = A.S;
     const int j = blockIdx.x * kGradThreads + threadIdx.x;
     const int i0 = blockIdx.y * kGdTO;
@@ -91,45 +86,16 @@ __global__ void __launch_bounds__(kGradThreads) k_gw_dense(GradArgs<Ts> A) {
     const bool jok = j < g.fan;
     const int jj = jok ? j : 0;
     const int cj = jj / L.P, pj = jj - cj * L.P;
-    const int nto = min(kGdTO, O.C - i0);
+    const int nto = min(kGdTO, g.out.C - i0);
     double acc[kGdTO];
-    float w[kGdTO];   // only the signs enter the gradient
 #pragma unroll
-    for (int to = 0; to < kGdTO; ++to) {
-        acc[to] = 0;
-        w[to] = to < nto ? g.W[(long)(i0 + to) * g.fan + jj] : 0.f;
-    }
+    for (int to = 0; to < kGdTO; ++to) acc[to] = 0;
     for (int s = s0; s < s1; ++s) {
-        const long a_in = ((long)cj * S + s) * L.P + pj;
-        const double x = (double)A.xin[a_in];
+        const double x = (double)A.xin[((long)cj * S + s) * L.P + pj];
         const double gsv = A.gs[s];
-        if (A.last) {
 #pragma unroll
-            for (int to = 0; to < kGdTO; ++to)
-                if (to < nto) acc[to] += gsv * (double)A.cvec[(long)(i0 + to) * S + s] * x;
-            continue;
-        }
-        const long bi = (long)cj * L.colpad + (long)s * L.P + pj;
-        const double lo = (double)A.lo_in[a_in], hi = (double)A.hi_in[a_in];
-        const bool dg = gbit(A.deg_in, bi);
-        unsigned xqb = 0;
-        for (int q = 0; q < A.nm; ++q) xqb |= gbit(R->slot[q].xbits, bi) << q;
-#pragma unroll
-        for (int to = 0; to < kGdTO; ++to) {
-            if (to < nto) {
-                const long a_out = (long)(i0 + to) * S + s;
-                const long bo = (long)(i0 + to) * O.colpad + s;
-                const bool z = gbit(R->zbits, bo);
-                double t = x * gsv * ((double)R->alpha[a_out] - (double)R->beta1[a_out]);
-                const double Lc = w[to] >= 0.f ? lo : hi, Uc = w[to] >= 0.f ? hi : lo;
-                for (int q = 0; q < A.nm; ++q) {
-                    const double bq = gsv * (double)R->slot[q].beta[a_out];
-                    const bool I = mask_entry(gbit(R->slot[q].zbits, bo), w[to], dg, (xqb >> q) & 1u);
-                    t += slot_term(I, z, bq, x, Lc, Uc);
-                }
-                acc[to] += t;
-            }
-        }
+        for (int to = 0; to < kGdTO; ++to)
+            if (to < nto) acc[to] += gsv * (double)A.cvec[(long)(i0 + to) * S + s] * x;
     }
     if (jok)
 #pragma unroll
@@ -137,136 +103,244 @@ __global__ void __launch_bounds__(kGradThreads) k_gw_dense(GradArgs<Ts> A) {
             if (to < nto) A.part[(long)blockIdx.z * A.entries + (long)(i0 + to) * g.fan + j] = acc[to];
 }
 
-// Convolution, stage one.  Lanes run over the (subproblem, output position)
-// terms of one chunk (coalesced reads of the output-side duals), each lane
-// keeps a tile of kGcTO output channels x kGcTT taps (c_in, ky, kx) in
-// registers; the block's partial sums are reduced across lanes (butterfly)
-// and waves (fixed order).
+// ---------------------------------------------------------------------------
+// Weight gradient of a ReLU layer k, in sign classes.
+//
+// Sum the slot terms of one (output o, input j) pair over the masks q, with
+// b_q = g_s beta_q[o], I_q = z_q[o] | d_q[j] where d_q[j] = 1 on a point box
+// of j, else the x bit test of the weight's sign class (w > 0: x not at the
+// upper end; w < 0: x at the upper end; w = 0: always 1):
+//   z[o] = 0:  sum_q = (Lc - x) PD          PD = sum_q I_q b_q
+//   z[o] = 1:  sum_q = (Uc - x) PD - Uc B   B = sum_q b_q
+// and with P = sum_{z_q} b_q, Q_q = (1 - z_q) b_q, X0 = sum_q xbit_q Q_q
+// (x bits cleared on a point box):  PD = B - X0 (w > 0), P + X0 (w < 0, no
+// point box), B (w = 0 or a point box).  Adding x (alpha - beta_1) g_s, the
+// whole pair term is
+//   x Ax + (c - x) (PD - [z] B),   Ax = g_s (alpha - beta_1) - [z] B,
+// c = Lc (z = 0) or Uc (z = 1), where (Lc, Uc) = (l, u) for w >= 0 and (u, l)
+// for w < 0.  Per pair that is one fused multiply-add per mask plus six, and
+// the weight's class enters through two per-lane constants: the coefficient
+// of X0 (-1, 0, +1) and 2 [w < 0] (which picks P over B, and c's end).
+//
+// Mapping: each lane owns TT taps (input positions of the receptive field,
+// fan index t = block tap base + lane + 64 tt) of TO output channels; a wave
+// walks the terms (subproblem, output position) of its share one at a time,
+// so the output-side values of a term are the same for all its lanes.  They
+// are formed once per (channel, term) by the block into LDS (records of
+// Ax, [z ? 0 : B], P - B, [z ? -1 : 1], Q_q); the input side is one record
+// per neuron (x, l, u, bits), gathered per lane.  Block partial sums are
+// added across the waves in a fixed order and written per chunk of terms.
+
+// Input-side record of one neuron of layer k-1 for the weight gradient of
+// ReLU layer k: its value at the minimiser, its box, and bits (bit 0: point
+// box; bit 1 + q: x bit of mask slot q of layer k, cleared on a point box).
+template <typename Ts> struct GwIn;
+template <> struct __align__(16) GwIn<float> { float x, l, u; uint32_t bits; };
+template <> struct __align__(16) GwIn<double> { double x, l, u; uint32_t bits, pad; };
+
 template <typename Ts>
-__global__ void __launch_bounds__(kGradThreads) k_gw_conv(GradArgs<Ts> A) {
+__global__ void __launch_bounds__(kGradThreads) k_gw_in(GradArgs<Ts> A, GwIn<Ts>* out) {
     const cptr_t<ReluLayerT<Ts>> R = kconst_t(A.R);
-    __shared__ double red[kGradThreads / 64][kGcTO * kGcTT];
-    const LayerGeo& g = A.g;
-    const NeuronLayout& L = g.in;
-    const NeuronLayout& O = g.out;
-    // every neuron and bit index of a layer fits in 31 bits (checked when the
-    // workspace is sized), so the addressing below runs in 32-bit integers
-    const int S = A.S;
-    const int co0 = blockIdx.z * kGcTO;
-    const int t0 = blockIdx.y * kGcTT;
-    const int r0 = (int)(blockIdx.x * A.r_chunk);
-    const int r1 = (int)min((long)S * O.P, (long)r0 + A.r_chunk);
-    const int k2 = g.ksz * g.ksz;
-    const int nto = min(kGcTO, O.C - co0);
-    const int cstride = S * O.P;          // channel stride of the output layout
-    const int ocp = (int)O.colpad, icp = (int)L.colpad;
-    // only the signs of the tile's weights enter the gradient: bit to*kGcTT+tt
-    uint32_t wpos = 0, wzero = 0, wnonneg = 0;
-    int ci[kGcTT], dy[kGcTT], dx[kGcTT];
-    bool tok[kGcTT];
+    const NeuronLayout& L = A.g.in;
+    const long gid = (long)blockIdx.x * kGradThreads + threadIdx.x;
+    if (gid >= (long)L.C * L.cols) return;
+    const int c = (int)(gid / L.cols);
+    const long bi = (long)c * L.colpad + (gid - (long)c * L.cols);
+    const unsigned dg = gbit(A.deg_in, bi);
+    unsigned bits = dg;
+    if (!dg)
+        for (int q = 0; q < A.nm; ++q) bits |= gbit(R->slot[q].xbits, bi) << (1 + q);
+    GwIn<Ts> r;
+    r.x = A.xin[gid];
+    r.l = A.lo_in[gid];
+    r.u = A.hi_in[gid];
+    r.bits = bits;
+    out[gid] = r;
+}
+
+constexpr int kGwRB = 64;   // terms per LDS batch (16 per wave)
+
+template <typename Ts>
+struct GwArgs {
+    int S, fan, kh, kw, stride, pad;
+    int inH, inW, inP;           // layer k-1 spatial size
+    int outC, outW, outP;        // layer k
+    long outcols, outcolpad;     // S * outP, and the bit stride of a channel
+    const float* W;              // [outC][fan]
+    const double* gs;            // [S]
+    const GwIn<Ts>* in;          // records of layer k-1 (internal layout)
+    const ReluLayerT<Ts>* R;     // layer k (device copy)
+    long r_chunk;                // terms per block (a multiple of kGwRB)
+    long entries;                // outC * fan
+    double* part;                // [chunk][entries]
+};
+
+template <typename Ts, int NM, int TO, int TT>
+__global__ void __launch_bounds__(kGradThreads) k_gw_relu(GwArgs<Ts> A) {
+    constexpr int RL = 4 + NM;                 // Ax, Bz, P - B, zs, Q_0 .. Q_{NM-1}
+    constexpr int RLP = (RL + 1) & ~1;         // 16-byte aligned records
+    constexpr int SLOT = RLP > TT ? RLP : TT;
+    __shared__ __align__(16) double lds[TO * kGwRB * SLOT];
+    const cptr_t<ReluLayerT<Ts>> R = kconst_t(A.R);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int co0 = blockIdx.z * TO;
+    const int tb = blockIdx.y * (64 * TT);
+    const long nterms = (long)A.S * A.outP;
+    const long r0 = (long)blockIdx.x * A.r_chunk;
+    const long r1 = min(nterms, r0 + A.r_chunk);
+    const int khw = A.kh * A.kw;
+    // the lane's taps: input offsets (before the term's) and weight classes
+    int off[TT], dy[TT], dx[TT];
+    bool tok[TT];
+    double sg[TT][TO], ng[TT][TO];
 #pragma unroll
-    for (int tt = 0; tt < kGcTT; ++tt) {
-        const int t = t0 + tt;
-        tok[tt] = t < g.fan;
+    for (int tt = 0; tt < TT; ++tt) {
+        const int t = tb + lane + 64 * tt;
+        tok[tt] = t < A.fan;
         const int tc = tok[tt] ? t : 0;
-        ci[tt] = tc / k2;
-        const int rem = tc - ci[tt] * k2;
-        dy[tt] = rem / g.ksz - g.pad;
-        dx[tt] = rem - (rem / g.ksz) * g.ksz - g.pad;
+        const int ci = tc / khw, rem = tc - ci * khw;
+        const int ky = rem / A.kw, kx = rem - (rem / A.kw) * A.kw;
+        dy[tt] = ky - A.pad;
+        dx[tt] = kx - A.pad;
+        off[tt] = ci * A.S * A.inP + dy[tt] * A.inW + dx[tt];
 #pragma unroll
-        for (int to = 0; to < kGcTO; ++to) {
-            const float wv = (to < nto && tok[tt]) ? g.W[(co0 + to) * g.fan + tc] : 0.f;
-            const uint32_t bit = 1u << (to * kGcTT + tt);
-            if (wv > 0.f) wpos |= bit;
-            if (wv == 0.f) wzero |= bit;
-            if (wv >= 0.f) wnonneg |= bit;
+        for (int to = 0; to < TO; ++to) {
+            const float w = (tok[tt] && co0 + to < A.outC) ? A.W[(long)(co0 + to) * A.fan + tc] : 0.f;
+            sg[tt][to] = w > 0.f ? -1.0 : (w < 0.f ? 1.0 : 0.0);
+            ng[tt][to] = w < 0.f ? 2.0 : 0.0;
         }
     }
-    double acc[kGcTO][kGcTT];
+    double acc[TT][TO];
 #pragma unroll
-    for (int to = 0; to < kGcTO; ++to)
+    for (int tt = 0; tt < TT; ++tt)
 #pragma unroll
-        for (int tt = 0; tt < kGcTT; ++tt) acc[to][tt] = 0;
-    for (int r = r0 + (int)threadIdx.x; r < r1; r += kGradThreads) {
-        const int s = r / O.P, p = r - s * O.P;
-        const int oy = p / O.W, ox = p - oy * O.W;
-        const double gsv = A.gs[s];
-        const int a0 = co0 * cstride + r;   // output (co0, s, p)
-        const int b0 = co0 * ocp + r;
-        double x[kGcTT], lo[kGcTT], hi[kGcTT];
-        int ain[kGcTT], bin[kGcTT];
-        unsigned okb = 0, dgb = 0;
+        for (int to = 0; to < TO; ++to) acc[tt][to] = 0;
+    for (long rb = r0; rb < r1; rb += kGwRB) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < TO * kGwRB; e += kGradThreads) {
+            const int to = e / kGwRB, rl = e - (e / kGwRB) * kGwRB;
+            const long r = rb + rl;
+            const int co = co0 + to;
+            double rec[RLP];
 #pragma unroll
-        for (int tt = 0; tt < kGcTT; ++tt) {
-            const int iy = oy * g.stride + dy[tt], ix = ox * g.stride + dx[tt];
-            const bool ok = tok[tt] && iy >= 0 && iy < L.H && ix >= 0 && ix < L.W;
-            const int pin = ok ? iy * L.W + ix : 0;
-            ain[tt] = (ci[tt] * S + s) * L.P + pin;
-            bin[tt] = ci[tt] * icp + s * L.P + pin;
-            x[tt] = ok ? (double)A.xin[ain[tt]] : 0.0;
-            lo[tt] = ok ? (double)A.lo_in[ain[tt]] : 0.0;
-            hi[tt] = ok ? (double)A.hi_in[ain[tt]] : 0.0;
-            okb |= (unsigned)ok << tt;
-            if (ok) dgb |= gbit(A.deg_in, bin[tt]) << tt;
-        }
-        unsigned zb = 0;
-#pragma unroll
-        for (int to = 0; to < kGcTO; ++to) {
-            if (to < nto) {
-                const int a = a0 + to * cstride;
-                zb |= gbit(R->zbits, b0 + to * ocp) << to;
+            for (int i = 0; i < RLP; ++i) rec[i] = 0;
+            rec[3] = 1.0;
+            if (r < r1 && co < A.outC) {
+                const int s = (int)(r / A.outP);
+                const long a = (long)co * A.outcols + r;
+                const long bo = (long)co * A.outcolpad + r;
+                const double gsv = A.gs[s];
+                const bool z = gbit(R->zbits, bo);
                 const double Av = gsv * ((double)R->alpha[a] - (double)R->beta1[a]);
+                double B = 0, PmB = 0;
 #pragma unroll
-                for (int tt = 0; tt < kGcTT; ++tt) acc[to][tt] += x[tt] * Av;
-            }
-        }
-        for (int q = 0; q < A.nm; ++q) {
-            const cptr_t<MaskSlotT<Ts>> M = &R->slot[q];
-            const uint32_t* xbits = M->xbits;
-            unsigned xqb = 0;
-#pragma unroll
-            for (int tt = 0; tt < kGcTT; ++tt)
-                if ((okb >> tt) & 1u) xqb |= gbit(xbits, bin[tt]) << tt;
-            const Ts* beta = M->beta;
-            const uint32_t* zbits = M->zbits;
-#pragma unroll
-            for (int to = 0; to < kGcTO; ++to) {
-                if (to < nto) {
-                    const double bq = gsv * (double)beta[a0 + to * cstride];
-                    const bool zq = gbit(zbits, b0 + to * ocp);
-                    const bool z = (zb >> to) & 1u;
-#pragma unroll
-                    for (int tt = 0; tt < kGcTT; ++tt) {
-                        const int e = to * kGcTT + tt;
-                        const bool xq = (xqb >> tt) & 1u;
-                        const bool I = zq || ((wzero >> e) & 1u) || ((dgb >> tt) & 1u) ||
-                                       (((wpos >> e) & 1u) ? !xq : xq);
-                        const bool nn = (wnonneg >> e) & 1u;
-                        const double t = slot_term(I, z, bq, x[tt], nn ? lo[tt] : hi[tt], nn ? hi[tt] : lo[tt]);
-                        if ((okb >> tt) & 1u) acc[to][tt] += t;
+                for (int q = 0; q < NM; ++q) {
+                    const double bq = gsv * (double)R->slot[q].beta[a];
+                    B += bq;
+                    if (!gbit(R->slot[q].zbits, bo)) {
+                        rec[4 + q] = bq;
+                        PmB -= bq;
                     }
+                }
+                rec[0] = z ? Av - B : Av;
+                rec[1] = z ? 0.0 : B;
+                rec[2] = PmB;
+                rec[3] = z ? -1.0 : 1.0;
+            }
+            double* d = &lds[(to * kGwRB + rl) * RLP];
+#pragma unroll
+            for (int i = 0; i < RLP; ++i) d[i] = rec[i];
+        }
+        __syncthreads();
+        const long rw = rb + wave * (kGwRB / 4);
+        const long rwe = min(r1, rw + kGwRB / 4);
+        for (long r = rw; r < rwe; ++r) {
+            const int s = (int)(r / A.outP), p = (int)(r - (long)s * A.outP);
+            const int oy = p / A.outW, ox = p - (p / A.outW) * A.outW;
+            const int iy0 = oy * A.stride, ix0 = ox * A.stride;
+            const int base = s * A.inP + iy0 * A.inW + ix0;
+            double xd[TT], mm[TT], hm[TT], hn[TT], dq[TT][NM > 0 ? NM : 1];
+#pragma unroll
+            for (int tt = 0; tt < TT; ++tt) {
+                const int iy = iy0 + dy[tt], ix = ix0 + dx[tt];
+                const bool ok = tok[tt] && (unsigned)iy < (unsigned)A.inH && (unsigned)ix < (unsigned)A.inW;
+                GwIn<Ts> v;
+                if (ok) {
+                    v = A.in[off[tt] + base];
+                } else {
+                    v.x = v.l = v.u = 0;
+                    v.bits = 0;
+                }
+                const double x = (double)v.x, l = (double)v.l, u = (double)v.u;
+                xd[tt] = x;
+                mm[tt] = 0.5 * (l + u) - x;
+                hm[tt] = 0.5 * (u - l);
+                hn[tt] = (v.bits & 1u) ? 0.0 : 0.5;
+#pragma unroll
+                for (int q = 0; q < NM; ++q) dq[tt][q] = ((v.bits >> (1 + q)) & 1u) ? 1.0 : 0.0;
+            }
+            const int rl = (int)(r - rb);
+#pragma unroll
+            for (int to = 0; to < TO; ++to) {
+                const double* d = &lds[(to * kGwRB + rl) * RLP];
+                double rec[RLP];
+#pragma unroll
+                for (int i = 0; i < RLP; ++i) rec[i] = d[i];
+#pragma unroll
+                for (int tt = 0; tt < TT; ++tt) {
+                    double X = 0;
+                    if constexpr (NM > 0) {
+                        X = dq[tt][0] * rec[4];
+#pragma unroll
+                        for (int q = 1; q < NM; ++q) X = fma(dq[tt][q], rec[4 + q], X);
+                    }
+                    const double bse = fma(ng[tt][to] * hn[tt], rec[2], rec[1]);
+                    const double PD = fma(sg[tt][to], X, bse);
+                    const double cmx = fma(fma(ng[tt][to], rec[3], -rec[3]), hm[tt], mm[tt]);
+                    acc[tt][to] = fma(xd[tt], rec[0], acc[tt][to]);
+                    acc[tt][to] = fma(cmx, PD, acc[tt][to]);
                 }
             }
         }
     }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // waves 0 + 1 + 2 + 3, in that order
+    for (int w = 1; w < 4; ++w) {
+        __syncthreads();
+        if (wave == w)
 #pragma unroll
-    for (int to = 0; to < kGcTO; ++to)
+            for (int tt = 0; tt < TT; ++tt)
 #pragma unroll
-        for (int tt = 0; tt < kGcTT; ++tt) {
-            double v = acc[to][tt];
+                for (int to = 0; to < TO; ++to) lds[(tt * TO + to) * 64 + lane] = acc[tt][to];
+        __syncthreads();
+        if (wave == 0)
 #pragma unroll
-            for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-            if (lane == 0) red[wave][to * kGcTT + tt] = v;
-        }
-    __syncthreads();
-    if ((int)threadIdx.x < kGcTO * kGcTT) {
-        const int to = threadIdx.x / kGcTT, tt = threadIdx.x - to * kGcTT;
-        double v = 0;
-        for (int wv = 0; wv < kGradThreads / 64; ++wv) v += red[wv][threadIdx.x];
-        if (to < nto && tok[tt]) A.part[(long)blockIdx.x * A.entries + (long)(co0 + to) * g.fan + t0 + tt] = v;
+            for (int tt = 0; tt < TT; ++tt)
+#pragma unroll
+                for (int to = 0; to < TO; ++to) acc[tt][to] += lds[(tt * TO + to) * 64 + lane];
     }
+    if (wave == 0)
+#pragma unroll
+        for (int tt = 0; tt < TT; ++tt)
+#pragma unroll
+            for (int to = 0; to < TO; ++to)
+                if (tok[tt] && co0 + to < A.outC)
+                    A.part[(long)blockIdx.x * A.entries + (long)(co0 + to) * A.fan + tb + lane + 64 * tt] =
+                        acc[tt][to];
 }
+
+// Taps per lane and output channels per block of the weight-gradient kernel
+// for a fan-in (every configuration covers any fan-in; these balance lanes,
+// registers and LDS reads).
+inline void gw_config(int fan, int* TT, int* TO) {
+    *TT = fan <= 64 ? 1 : (fan <= 128 ? 2 : 4);
+    *TO = *TT == 1 ? 8 : 4;
+}
+
+// Weight gradient of ReLU layer k (k < n) with NM active masks into the
+// plan's partial-sum buffer (chunk-major), from the input records at inrec;
+// compiled per mask count (asd_grad.hip).
+template <int NM>
+asd_status grad_weight_nm(asd_plan* P, int k, const double* gs, const void* inrec, hipStream_t st);
 
 // Bias, stage one: block (chunk, channel), fixed-order block sum.
 template <typename Ts>

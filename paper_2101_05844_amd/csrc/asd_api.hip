@@ -69,6 +69,18 @@ struct Carver {
     }
 };
 
+// Doubles after the gradient's partial sums that hold the input records of
+// a ReLU layer's weight gradient (the largest input layer of a ReLU layer).
+size_t grad_inrec_doubles(const asd_plan* P) {
+    const size_t rec = is64(P) ? sizeof(GwIn<double>) : sizeof(GwIn<float>);
+    size_t bytes = 0;
+    for (int k = 1; k < P->n; ++k) bytes = std::max(bytes, (size_t)P->geo[k].in.C * P->geo[k].in.cols * rec);
+    return (bytes + 15) / 16 * 2 + 2;  // and up to 8 bytes to reach 16-byte alignment
+}
+
+// Input records of the weight gradient: after the partial sums, 16-byte aligned.
+void* grad_inrec(asd_plan* P) { return P->gpart + ((P->gpart_w + P->gpart_b + 1) & ~(size_t)1); }
+
 template <typename T>
 void carve_t(asd_plan* P, Carver& cv) {
     const int S = P->S;
@@ -152,7 +164,7 @@ void carve_t(asd_plan* P, Carver& cv) {
     P->part = cv.take<T>(part);
     P->pointflag = cv.take<int>(kMaxLayers);
     P->f0 = cv.take<double>((size_t)P->nl[0].N * S);
-    P->gpart = cv.take<double>(P->gpart_w + P->gpart_b);
+    P->gpart = cv.take<double>(P->gpart_w + P->gpart_b + grad_inrec_doubles(P));
     P->budgets_dev = cv.take<int>(S);
     P->inflags = cv.take<int32_t>(S);
     P->lrs = cv.take<T>(S);
@@ -226,12 +238,20 @@ void setup_plan_geometry(asd_plan* P) {
                 *chunks = (int)((terms + *rchunk - 1) / *rchunk);
             };
             const long entries = (long)g.out.C * g.fan;
-            if (d.kind == ASD_LAYER_DENSE)
+            if (L == net->n) {
                 split((long)((g.fan + kGradThreads - 1) / kGradThreads) * ((g.out.C + kGdTO - 1) / kGdTO), S, 2048,
                       16, &P->gw_chunks[L], &P->gw_rchunk[L]);
-            else
-                split((long)((g.out.C + kGcTO - 1) / kGcTO) * ((g.fan + kGcTT - 1) / kGcTT), (long)S * g.out.P, 2048,
-                      2048, &P->gw_chunks[L], &P->gw_rchunk[L]);
+            } else {
+                // ReLU layer: about 1024 blocks, chunks of whole LDS batches
+                int TT, TO;
+                gw_config(g.fan, &TT, &TO);
+                const long groups = (long)((g.fan + 64 * TT - 1) / (64 * TT)) * ((g.out.C + TO - 1) / TO);
+                const long terms = (long)S * g.out.P;
+                const long batches = (terms + kGwRB - 1) / kGwRB;
+                const long c = std::max(1L, std::min((1024 + groups - 1) / groups, std::min(512L, batches)));
+                P->gw_rchunk[L] = (batches + c - 1) / c * kGwRB;
+                P->gw_chunks[L] = (int)((terms + P->gw_rchunk[L] - 1) / P->gw_rchunk[L]);
+            }
             split(g.out.C, (long)S * g.out.P, 1024, 2048, &P->gb_chunks[L], &P->gb_rchunk[L]);
             P->gpart_w = std::max(P->gpart_w, (size_t)P->gw_chunks[L] * entries);
             P->gpart_b = std::max(P->gpart_b, (size_t)P->gb_chunks[L] * g.out.C);
@@ -897,17 +917,25 @@ asd_status bound_grad_t(asd_plan* P, const double* gs, double* const* dW, double
             a.part = P->gpart;
             {
                 ProfScope ps(P, st, ASD_K_GRAD_WEIGHT, k);
-                if (g.kind == ASD_LAYER_DENSE)
-                    hipLaunchKernelGGL(k_gw_dense<Ts>,
+                if (a.last) {
+                    hipLaunchKernelGGL(k_gw_last<Ts>,
                                        dim3((unsigned)((g.fan + kGradThreads - 1) / kGradThreads),
                                             (unsigned)((g.out.C + kGdTO - 1) / kGdTO), (unsigned)P->gw_chunks[k]),
                                        dim3(kGradThreads), 0, st, a);
-                else
-                    hipLaunchKernelGGL(k_gw_conv<Ts>,
-                                       dim3((unsigned)P->gw_chunks[k], (unsigned)((g.fan + kGcTT - 1) / kGcTT),
-                                            (unsigned)((g.out.C + kGcTO - 1) / kGcTO)),
-                                       dim3(kGradThreads), 0, st, a);
-                LAUNCH_CHECK();
+                    LAUNCH_CHECK();
+                } else {
+                    // input records of layer k-1, after the partial sums
+                    GwIn<Ts>* rec = static_cast<GwIn<Ts>*>(grad_inrec(P));
+                    const long nin = (long)g.in.C * g.in.cols;
+                    hipLaunchKernelGGL(k_gw_in<Ts>, dim3((unsigned)((nin + kGradThreads - 1) / kGradThreads)),
+                                       dim3(kGradThreads), 0, st, a, rec);
+                    LAUNCH_CHECK();
+#define ASD_GW_CALL(N)                                  \
+    TRY(grad_weight_nm<N>(P, k, gs, rec, st)); \
+    break;
+                    ASD_NM_DISPATCH(a.nm, ASD_GW_CALL)
+#undef ASD_GW_CALL
+                }
                 hipLaunchKernelGGL(k_gsum, dim3((unsigned)((a.entries + kGradThreads - 1) / kGradThreads)),
                                    dim3(kGradThreads), 0, st, (const double*)P->gpart, a.entries, P->gw_chunks[k],
                                    dW[k - 1]);

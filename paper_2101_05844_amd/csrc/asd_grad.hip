@@ -1,0 +1,64 @@
+// Launches of the ReLU-layer weight-gradient kernel (asd_adjoint.h) for one
+// count of active masks: this file is compiled once per count with
+// -DASD_NM=<count>, so the kernels of the different counts build in parallel.
+#include "asd_adjoint.h"
+#include "asd_plan.h"
+
+#ifndef ASD_NM
+#error "compile with -DASD_NM=<active mask count>"
+#endif
+
+namespace asd {
+
+template <typename Ts, int NM>
+asd_status gw_relu_t(asd_plan* P, int k, const double* gs, const void* inrec, hipStream_t st) {
+    const LayerGeo& g = P->geo[k];
+    GwArgs<Ts> a;
+    memset(&a, 0, sizeof(a));
+    a.S = P->S;
+    a.fan = g.fan;
+    if (g.kind == ASD_LAYER_DENSE) {
+        // a dense layer is a convolution whose kernel covers the whole input
+        a.kh = g.in.H;
+        a.kw = g.in.W;
+        a.stride = 1;
+        a.pad = 0;
+    } else {
+        a.kh = a.kw = g.ksz;
+        a.stride = g.stride;
+        a.pad = g.pad;
+    }
+    a.inH = g.in.H;
+    a.inW = g.in.W;
+    a.inP = g.in.P;
+    a.outC = g.out.C;
+    a.outW = g.out.W;
+    a.outP = g.out.P;
+    a.outcols = g.out.cols;
+    a.outcolpad = g.out.colpad;
+    a.W = g.W;
+    a.gs = gs;
+    a.in = static_cast<const GwIn<Ts>*>(inrec);
+    a.R = RdevT<Ts>(P) + k;
+    a.r_chunk = P->gw_rchunk[k];
+    a.entries = (long)g.out.C * g.fan;
+    a.part = P->gpart;
+    int TT, TO;
+    gw_config(g.fan, &TT, &TO);
+    const dim3 grid((unsigned)P->gw_chunks[k], (unsigned)((g.fan + 64 * TT - 1) / (64 * TT)),
+                    (unsigned)((g.out.C + TO - 1) / TO));
+    if (TT == 1) hipLaunchKernelGGL((k_gw_relu<Ts, NM, 8, 1>), grid, dim3(kGradThreads), 0, st, a);
+    else if (TT == 2) hipLaunchKernelGGL((k_gw_relu<Ts, NM, 4, 2>), grid, dim3(kGradThreads), 0, st, a);
+    else hipLaunchKernelGGL((k_gw_relu<Ts, NM, 4, 4>), grid, dim3(kGradThreads), 0, st, a);
+    LAUNCH_CHECK();
+    return ASD_OK;
+}
+
+template <int NM>
+asd_status grad_weight_nm(asd_plan* P, int k, const double* gs, const void* inrec, hipStream_t st) {
+    return is64(P) ? gw_relu_t<double, NM>(P, k, gs, inrec, st) : gw_relu_t<float, NM>(P, k, gs, inrec, st);
+}
+
+template asd_status grad_weight_nm<ASD_NM>(asd_plan*, int, const double*, const void*, hipStream_t);
+
+}  // namespace asd

@@ -328,6 +328,149 @@ __global__ void __launch_bounds__(kGradThreads) k_gw_relu(GwArgs<Ts> A) {
                         acc[tt][to];
 }
 
+// Box gradient through layer 1 in sign classes, one block per (chunk of
+// kGbNI x 256 inputs, subproblem s).  Per (layer-1 output o, input j) with
+// weight w and b_q = beta_q[o] (g_s applies at the end), the mask terms of
+// the old per-slot form add up to t = PD' w with PD' = PD - [z] B as in the
+// weight gradient; t goes to dl[j] where (w >= 0) == (z = 0) and to du[j]
+// otherwise (w = 0 gives t = 0).  Lanes keep dl + du and dl - du (the sign
+// of a pair is [w >= 0 ? 1 : -1] [z ? -1 : 1]); the block stages the records
+// (Bz, P - B, zs, Q_q) of a range of whole output channels of s in LDS, and
+// the convolution's weights.
+constexpr int kGbNI = 4;    // inputs per lane
+
+template <typename Ts, int NM, bool DENSE>
+__global__ void __launch_bounds__(kGradThreads) k_grad_box_sc(GradArgs<Ts> A, int NC) {
+    constexpr int RL = 3 + NM;                 // Bz, P - B, zs, Q_0 .. Q_{NM-1}
+    constexpr int RLP = (RL + 1) & ~1;
+    extern __shared__ __align__(16) double lds_box[];
+    const cptr_t<ReluLayerT<Ts>> R = kconst_t(A.R);
+    const LayerGeo& g = A.g;
+    const NeuronLayout& L = g.in;
+    const NeuronLayout& O = g.out;
+    const int S = A.S;
+    const int s = blockIdx.y;
+    const int jb = blockIdx.x * kGradThreads * kGbNI + threadIdx.x;
+    double* rec = lds_box;
+    float* wl = reinterpret_cast<float*>(lds_box + (size_t)NC * O.P * RLP);
+    const int ks = g.ksz, str = g.stride;
+    if (!DENSE) {
+        for (int e = threadIdx.x; e < O.C * g.fan; e += kGradThreads) wl[e] = g.W[e];
+    }
+    double sacc[kGbNI], dacc[kGbNI];
+    uint32_t xb[kGbNI];
+#pragma unroll
+    for (int i = 0; i < kGbNI; ++i) {
+        sacc[i] = dacc[i] = 0;
+        xb[i] = 0;
+        const int j = jb + kGradThreads * i;
+        if (j < L.N) {
+            const int c = j / L.P, p = j - (j / L.P) * L.P;
+            const long bi = (long)c * L.colpad + (long)s * L.P + p;
+            const unsigned dg = gbit(A.deg_in, bi);
+            unsigned b = dg;
+            if (!dg)
+#pragma unroll
+                for (int q = 0; q < NM; ++q) b |= gbit(R->slot[q].xbits, bi) << (1 + q);
+            xb[i] = b;
+        }
+    }
+    for (int c0 = 0; c0 < O.C; c0 += NC) {
+        const int nc = min(NC, O.C - c0);
+        __syncthreads();
+        for (int o = threadIdx.x; o < nc * O.P; o += kGradThreads) {
+            const int co = c0 + o / O.P, op = o - (o / O.P) * O.P;
+            const long a = ((long)co * S + s) * O.P + op;
+            const long bo = (long)co * O.colpad + (long)s * O.P + op;
+            const bool z = gbit(R->zbits, bo);
+            double r[RLP];
+#pragma unroll
+            for (int i = 0; i < RLP; ++i) r[i] = 0;
+            double B = 0, PmB = 0;
+#pragma unroll
+            for (int q = 0; q < NM; ++q) {
+                const double bq = (double)R->slot[q].beta[a];
+                B += bq;
+                if (!gbit(R->slot[q].zbits, bo)) {
+                    r[3 + q] = bq;
+                    PmB -= bq;
+                }
+            }
+            r[0] = z ? 0.0 : B;
+            r[1] = PmB;
+            r[2] = z ? -1.0 : 1.0;
+#pragma unroll
+            for (int i = 0; i < RLP; ++i) rec[(size_t)o * RLP + i] = r[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kGbNI; ++i) {
+            const int j = jb + kGradThreads * i;
+            if (j >= L.N) continue;
+            double dq[NM > 0 ? NM : 1];
+#pragma unroll
+            for (int q = 0; q < NM; ++q) dq[q] = ((xb[i] >> (1 + q)) & 1u) ? 1.0 : 0.0;
+            const double hn = (xb[i] & 1u) ? 0.0 : 0.5;
+            // one (output record, weight) pair
+            auto pair = [&](const double* r, float wf) {
+                const double w = (double)wf;
+                double X = 0;
+                if constexpr (NM > 0) {
+                    X = dq[0] * r[3];
+#pragma unroll
+                    for (int q = 1; q < NM; ++q) X = fma(dq[q], r[3 + q], X);
+                }
+                const double ng = wf < 0.f ? 2.0 : 0.0;
+                const double sg = wf > 0.f ? -1.0 : (wf < 0.f ? 1.0 : 0.0);
+                const double PD = fma(sg, X, fma(ng * hn, r[1], r[0]));
+                const double t = PD * w;
+                sacc[i] += t;
+                dacc[i] = fma((1.0 - ng) * r[2], t, dacc[i]);
+            };
+            if (DENSE) {
+                for (int co = c0; co < c0 + nc; ++co) pair(&rec[(size_t)(co - c0) * RLP], g.W[(long)co * g.fan + j]);
+            } else {
+                const int c = j / L.P, p = j - (j / L.P) * L.P;
+                const int y = p / L.W, x = p - (p / L.W) * L.W;
+                const int ky0 = (y + g.pad) % str, kx0 = (x + g.pad) % str;
+                for (int co = c0; co < c0 + nc; ++co)
+                    for (int ky = ky0; ky < ks; ky += str) {
+                        const int oy = (y + g.pad - ky) / str;
+                        if (oy < 0 || oy >= O.H) continue;
+                        for (int kx = kx0; kx < ks; kx += str) {
+                            const int ox = (x + g.pad - kx) / str;
+                            if (ox < 0 || ox >= O.W) continue;
+                            pair(&rec[((size_t)(co - c0) * O.P + oy * O.W + ox) * RLP],
+                                 wl[((co * L.C + c) * ks + ky) * ks + kx]);
+                        }
+                    }
+            }
+        }
+    }
+    const double gsv = A.gs[s];
+#pragma unroll
+    for (int i = 0; i < kGbNI; ++i) {
+        const int j = jb + kGradThreads * i;
+        if (j >= L.N) continue;
+        const int c = j / L.P, p = j - (j / L.P) * L.P;
+        const double f = A.f0[((long)c * S + s) * L.P + p];
+        const double dl = 0.5 * (sacc[i] + dacc[i]) + (f < 0 ? -f : 0.0);
+        const double du = 0.5 * (sacc[i] - dacc[i]) + (f >= 0 ? -f : 0.0);
+        const long ex = (long)s * L.N + j;
+        if (A.dl0) A.dl0[ex] = gsv * dl;
+        if (A.du0) A.du0[ex] = gsv * du;
+    }
+}
+
+// LDS bytes of k_grad_box_sc for record ranges of NC output channels (0 when
+// the sign-class box kernel does not apply: an output layer, or records or
+// weights too large for LDS).
+inline size_t grad_box_lds(const LayerGeo& g, int nm, int NC) {
+    const size_t rlp = (size_t)((3 + nm + 1) & ~1);
+    const size_t b = (size_t)NC * g.out.P * rlp * 8 + (g.kind == ASD_LAYER_DENSE ? 0 : (size_t)g.out.C * g.fan * 4);
+    return b;
+}
+
 // Taps per lane and output channels per block of the weight-gradient kernel
 // for a fan-in (every configuration covers any fan-in; these balance lanes,
 // registers and LDS reads).
@@ -341,6 +484,10 @@ inline void gw_config(int fan, int* TT, int* TO) {
 // compiled per mask count (asd_grad.hip).
 template <int NM>
 asd_status grad_weight_nm(asd_plan* P, int k, const double* gs, const void* inrec, hipStream_t st);
+// Box gradient through layer 1 with NM active masks (sign-class kernel);
+// *done is left false where that kernel does not apply.
+template <int NM>
+asd_status grad_box_nm(asd_plan* P, const double* gs, double* dl0, double* du0, bool* done, hipStream_t st);
 
 // Bias, stage one: block (chunk, channel), fixed-order block sum.
 template <typename Ts>

@@ -964,9 +964,19 @@ asd_status bound_grad_t(asd_plan* P, const double* gs, double* const* dW, double
         a.du0 = du0;
         const long n = (long)P->nl[0].C * P->nl[0].cols;
         ProfScope ps(P, st, ASD_K_GRAD_BOX, 0);
-        hipLaunchKernelGGL(k_grad_box<Ts>, dim3((unsigned)((n + kGradThreads - 1) / kGradThreads)),
-                           dim3(kGradThreads), 0, st, a);
-        LAUNCH_CHECK();
+        bool done = false;
+        if (!a.last) {
+#define ASD_GB_CALL(N)                                        \
+    TRY(grad_box_nm<N>(P, gs, dl0, du0, &done, st)); \
+    break;
+            ASD_NM_DISPATCH(a.nm, ASD_GB_CALL)
+#undef ASD_GB_CALL
+        }
+        if (!done) {
+            hipLaunchKernelGGL(k_grad_box<Ts>, dim3((unsigned)((n + kGradThreads - 1) / kGradThreads)),
+                               dim3(kGradThreads), 0, st, a);
+            LAUNCH_CHECK();
+        }
     }
     return ASD_OK;
 }

@@ -164,7 +164,7 @@ template <typename Ts>
 struct GwArgs {
     int S, fan, kh, kw, stride, pad;
     int inH, inW, inP;           // layer k-1 spatial size
-    int outC, outW, outP;        // layer k
+    int outC, outH, outW, outP;  // layer k
     long outcols, outcolpad;     // S * outP, and the bit stride of a channel
     const float* W;              // [outC][fan]
     const double* gs;            // [S]
@@ -254,23 +254,56 @@ __global__ void __launch_bounds__(kGradThreads) k_gw_relu(GwArgs<Ts> A) {
         __syncthreads();
         const long rw = rb + wave * (kGwRB / 4);
         const long rwe = min(r1, rw + kGwRB / 4);
-        for (long r = rw; r < rwe; ++r) {
-            const int s = (int)(r / A.outP), p = (int)(r - (long)s * A.outP);
-            const int oy = p / A.outW, ox = p - (p / A.outW) * A.outW;
-            const int iy0 = oy * A.stride, ix0 = ox * A.stride;
-            const int base = s * A.inP + iy0 * A.inW + ix0;
-            double xd[TT], mm[TT], hm[TT], hn[TT], dq[TT][NM > 0 ? NM : 1];
+        if (rw >= rwe) continue;
+        // the wave's terms in order: (s, oy, ox) stepped, the next term's input
+        // records loaded while this one is processed
+        int s = (int)(rw / A.outP);
+        int oy, ox;
+        {
+            const int p = (int)(rw - (long)s * A.outP);
+            oy = p / A.outW;
+            ox = p - oy * A.outW;
+        }
+        GwIn<Ts> cur[TT];
+        auto fetch = [&](int s_, int oy_, int ox_, GwIn<Ts>* v) {
+            const int iy0 = oy_ * A.stride, ix0 = ox_ * A.stride;
+            const int base = s_ * A.inP + iy0 * A.inW + ix0;
 #pragma unroll
             for (int tt = 0; tt < TT; ++tt) {
                 const int iy = iy0 + dy[tt], ix = ix0 + dx[tt];
                 const bool ok = tok[tt] && (unsigned)iy < (unsigned)A.inH && (unsigned)ix < (unsigned)A.inW;
-                GwIn<Ts> v;
                 if (ok) {
-                    v = A.in[off[tt] + base];
+                    v[tt] = A.in[off[tt] + base];
                 } else {
-                    v.x = v.l = v.u = 0;
-                    v.bits = 0;
+                    v[tt].x = v[tt].l = v[tt].u = 0;
+                    v[tt].bits = 0;
                 }
+            }
+        };
+        fetch(s, oy, ox, cur);
+        for (long r = rw; r < rwe; ++r) {
+            int s2 = s, oy2 = oy, ox2 = ox + 1;
+            if (ox2 == A.outW) {
+                ox2 = 0;
+                if (++oy2 == A.outH) {
+                    oy2 = 0;
+                    ++s2;
+                }
+            }
+            GwIn<Ts> nxt[TT];
+            if (r + 1 < rwe) {
+                fetch(s2, oy2, ox2, nxt);
+            } else {
+#pragma unroll
+                for (int tt = 0; tt < TT; ++tt) {
+                    nxt[tt].x = nxt[tt].l = nxt[tt].u = 0;
+                    nxt[tt].bits = 0;
+                }
+            }
+            double xd[TT], mm[TT], hm[TT], hn[TT], dq[TT][NM > 0 ? NM : 1];
+#pragma unroll
+            for (int tt = 0; tt < TT; ++tt) {
+                const GwIn<Ts>& v = cur[tt];
                 const double x = (double)v.x, l = (double)v.l, u = (double)v.u;
                 xd[tt] = x;
                 mm[tt] = 0.5 * (l + u) - x;
@@ -301,6 +334,11 @@ __global__ void __launch_bounds__(kGradThreads) k_gw_relu(GwArgs<Ts> A) {
                     acc[tt][to] = fma(cmx, PD, acc[tt][to]);
                 }
             }
+#pragma unroll
+            for (int tt = 0; tt < TT; ++tt) cur[tt] = nxt[tt];
+            s = s2;
+            oy = oy2;
+            ox = ox2;
         }
     }
     // waves 0 + 1 + 2 + 3, in that order

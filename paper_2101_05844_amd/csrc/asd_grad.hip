@@ -32,6 +32,7 @@ asd_status gw_relu_t(asd_plan* P, int k, const double* gs, const void* inrec, hi
     a.inW = g.in.W;
     a.inP = g.in.P;
     a.outC = g.out.C;
+    a.outH = g.out.H;
     a.outW = g.out.W;
     a.outP = g.out.P;
     a.outcols = g.out.cols;

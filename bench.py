@@ -61,9 +61,10 @@ def kernel_unit_bytes(role, layer, sizes, K, mixed=False):
 
 # sources outside the counted kernels and their launch code: the bound
 # gradient's kernels and the Saddle Point unit (the counter runs launch
-# neither) and the host driver's orchestration (which kernel runs when, not
-# what a launch moves)
-UNCOUNTED_SOURCES = ("asd_adjoint.h", "asd_api.hip", "asd_grad.hip", "asd_sp.hip")
+# neither), the final bound's FP64 sums (launched once per solve, not among
+# the counted iteration launches) and the host driver's orchestration (which
+# kernel runs when, not what a launch moves)
+UNCOUNTED_SOURCES = ("asd_adjoint.h", "asd_api.hip", "asd_final.hip", "asd_grad.hip", "asd_sp.hip")
 
 
 def source_digest():

@@ -3,8 +3,9 @@
 The library is one host/general translation unit (asd_api.hip), the
 iteration-kernel launches of asd_iter.hip compiled once per active-mask
 count (-DASD_NM=0..ASD_MAX_MASKS), the Saddle Point unit (asd_sp.hip,
-compiled without floating-point contraction) and the weight-gradient
-launches of asd_grad.hip, again once per active-mask count; the objects compile in
+compiled without floating-point contraction), and the bound-gradient
+launches of asd_grad.hip and the FP64 final sums of asd_final.hip, again once
+per active-mask count; the objects compile in
 parallel and are linked into one shared library.
 """
 import os
@@ -19,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJDIR = os.path.join(HERE, "_build")
 MAX_MASKS = 8  # ASD_MAX_MASKS in include/asdual.h
 SOURCES = [os.path.join(CSRC, "asd_api.hip"), os.path.join(CSRC, "asd_iter.hip"), os.path.join(CSRC, "asd_sp.hip"),
-           os.path.join(CSRC, "asd_grad.hip")]
+           os.path.join(CSRC, "asd_grad.hip"), os.path.join(CSRC, "asd_final.hip")]
 HEADERS = [os.path.join(CSRC, h) for h in ("asd_internal.h", "asd_kernels.h", "asd_fast.h", "asd_adjoint.h",
                                            "asd_plan.h")] + [os.path.join(ROOT, "include", "asdual.h")]
 
@@ -43,6 +44,7 @@ def units():
     out.append((SOURCES[2], os.path.join(OBJDIR, "asd_sp.o"), ["-ffp-contract=off"]))
     for nm in range(MAX_MASKS + 1):
         out.append((SOURCES[3], os.path.join(OBJDIR, f"asd_grad_nm{nm}.o"), [f"-DASD_NM={nm}"]))
+        out.append((SOURCES[4], os.path.join(OBJDIR, f"asd_final_nm{nm}.o"), [f"-DASD_NM={nm}"]))
     return out
 
 

@@ -527,6 +527,11 @@ asd_status grad_weight_nm(asd_plan* P, int k, const double* gs, const void* inre
 template <int NM>
 asd_status grad_box_nm(asd_plan* P, const double* gs, double* dl0, double* du0, bool* done, hipStream_t st);
 
+// FP64 per-neuron sums of the final bound of an FP32 plan for ReLU layer k
+// with NM active masks (sign classes; asd_final.hip, compiled per mask count).
+template <int NM>
+asd_status final_sums_nm(asd_plan* P, int k, hipStream_t st);
+
 // Bias, stage one: block (chunk, channel), fixed-order block sum.
 template <typename Ts>
 __global__ void __launch_bounds__(kGradThreads) k_gb_part(GradArgs<Ts> A) {

@@ -572,38 +572,11 @@ asd_status launch_mask_consts(asd_plan* P, int k, int q, const uint32_t* zsrc, c
     return ASD_OK;
 }
 
-// FP64 per-neuron sums of the final bound of an FP32 plan.
 asd_status launch_final_sums(asd_plan* P, int k, hipStream_t st) {
-    MaskArgs<float> a;
-    memset(&a, 0, sizeof(a));
-    a.g = P->geo[k];
-    a.S = P->S;
-    a.q = 0;
-    a.nm = P->n_masks;
-    a.lo_in = P->naf[k - 1].lo;
-    a.hi_in = P->naf[k - 1].hi;
-    a.deg_in = P->naf[k - 1].deg;
-    a.R = P->Rf[k];
     ProfScope ps(P, st, ASD_K_FINAL, k);
-    if (a.g.fan >= 1024) {
-        const size_t lds = (size_t)16 * CB * 2 * kWave * sizeof(double);
-        if (mask_dv(a.g, 16))
-            hipLaunchKernelGGL((k_mask_consts<double, float, 16, true>), grid_cols(P->nl[k], CB), dim3(kWave, 16), lds,
-                               st, a);
-        else
-            hipLaunchKernelGGL((k_mask_consts<double, float, 16, false>), grid_cols(P->nl[k], CB), dim3(kWave, 16), lds,
-                               st, a);
-    } else {
-        const size_t lds = (size_t)KS * CB * 2 * kWave * sizeof(double);
-        if (mask_dv(a.g, KS))
-            hipLaunchKernelGGL((k_mask_consts<double, float, KS, true>), grid_cols(P->nl[k], CB), dim3(kWave, KS), lds,
-                               st, a);
-        else
-            hipLaunchKernelGGL((k_mask_consts<double, float, KS, false>), grid_cols(P->nl[k], CB), dim3(kWave, KS), lds,
-                               st, a);
-    }
-    LAUNCH_CHECK();
-    return ASD_OK;
+#define ASD_FS_CALL(N) return final_sums_nm<N>(P, k, st)
+    ASD_NM_DISPATCH(P->n_masks, ASD_FS_CALL)
+#undef ASD_FS_CALL
 }
 
 template <typename T>

@@ -1,0 +1,189 @@
+// FP64 per-neuron sums of the final bound of an FP32 plan in sign classes,
+// for one count of active masks: compiled once per count with
+// -DASD_NM=<count>.
+//
+// For neuron o of ReLU layer k the final bound needs, over its active masks
+// q with multipliers b_q (eq:dual-active-set),
+//   r1 = sum_q b_q LI_q[o] and r0 = sum_q b_q (LI_q[o] + UI_q[o]),
+// where LI_q sums W Lcheck over the taps j in mask q and UI_q sums W Ucheck
+// over the others.  Exchanging the sums: r1 = sum_j wl_j PD_j and
+// r0 = r1 + sum_j wu_j (B - PD_j), with wl, wu the tap's W Lcheck, W Ucheck,
+// B = sum_q b_q and PD_j = sum over the masks containing j of b_q.  With
+// P = sum over z_q[o] = 1 of b_q, Q_q = (1 - z_q[o]) b_q and X = sum_q
+// xbit_q[j] Q_q (no point box at j), PD_j = B - X for w > 0, P + X for w < 0,
+// B on a point box (a zero weight contributes nothing).  One walk over the
+// fan-in serves every mask; the weight is uniform across a wave, so its
+// sign class is a uniform branch.
+#include "asd_adjoint.h"
+#include "asd_plan.h"
+
+#ifndef ASD_NM
+#error "compile with -DASD_NM=<active mask count>"
+#endif
+
+namespace asd {
+
+namespace {
+
+// NW waves split the fan-in; DV: a dense layer over channels of 4k positions
+// whose fan-in splits into multiples of 4 taps (one vector load per 4 taps).
+template <int NM, int NW, bool DV>
+__global__ void __launch_bounds__(kWave * NW) k_final_sums_sc(MaskArgs<float> A) {
+    static_assert(NW >= CB, "one wave per channel finishes the sums");
+    extern __shared__ unsigned char red_raw[];
+    double* red = reinterpret_cast<double*>(red_raw);  // [NW][CB][2][64]
+    const LayerGeo& g = A.g;
+    const int lane = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    const long col = (long)blockIdx.x * kWave + lane;
+    const int c0 = blockIdx.y * CB;
+    const int S = A.S;
+    const bool colok = col < g.out.cols;
+    const int s = colok ? (int)(col / g.out.P) : 0;
+    const int p = colok ? (int)(col - (long)s * g.out.P) : 0;
+    const long bicol0 = (long)c0 * g.out.colpad + col;
+    // output side: B, P and Q_q per channel
+    double Bv[CB], Pv[CB], Q[CB][NM > 0 ? NM : 1];
+#pragma unroll
+    for (int e = 0; e < CB; ++e) {
+        Bv[e] = Pv[e] = 0;
+#pragma unroll
+        for (int q = 0; q < NM; ++q) Q[e][q] = 0;
+        if (colok && c0 + e < g.out.C) {
+            const long idx_e = ((long)(c0 + e) * S + s) * g.out.P + p;
+            const long bo = bicol0 + (long)e * g.out.colpad;
+#pragma unroll
+            for (int q = 0; q < NM; ++q) {
+                const double bq = (double)A.R.slot[q].beta[idx_e];
+                Bv[e] += bq;
+                if (getbit(A.R.slot[q].zbits, bo)) Pv[e] += bq;
+                else Q[e][q] = bq;
+            }
+        }
+    }
+    double r1[CB], r0x[CB];
+#pragma unroll
+    for (int e = 0; e < CB; ++e) r1[e] = r0x[e] = 0;
+    const int F = g.fan;
+    const int t0 = (int)((long)F * wave / NW), t1 = (int)((long)F * (wave + 1) / NW);
+    // one tap: box ends, point-box bit, the masks' x bits
+    auto tap = [&](int t, double lo, double hi, unsigned dg, unsigned xb) {
+        double xd[NM > 0 ? NM : 1];
+#pragma unroll
+        for (int q = 0; q < NM; ++q) xd[q] = (!dg && ((xb >> q) & 1u)) ? 1.0 : 0.0;
+#pragma unroll
+        for (int e = 0; e < CB; ++e) {
+            const float wf = c0 + e < g.out.C ? g.W[(long)(c0 + e) * F + t] : 0.f;
+            if (wf == 0.f) continue;
+            const double w = (double)wf;
+            double X = 0;
+            if constexpr (NM > 0) {
+                X = xd[0] * Q[e][0];
+#pragma unroll
+                for (int q = 1; q < NM; ++q) X = fma(xd[q], Q[e][q], X);
+            }
+            if (wf > 0.f) {
+                const double PD = Bv[e] - X;
+                r1[e] = fma(w * lo, PD, r1[e]);
+                r0x[e] = fma(w * hi, Bv[e] - PD, r0x[e]);
+            } else {
+                const double PD = dg ? Bv[e] : Pv[e] + X;
+                r1[e] = fma(w * hi, PD, r1[e]);
+                r0x[e] = fma(w * lo, Bv[e] - PD, r0x[e]);
+            }
+        }
+    };
+    if (colok) {
+        if constexpr (DV) {
+            for (int t = t0; t < t1; t += 4) {
+                const int ci = t / g.in.P, pj = t - ci * g.in.P;
+                const long a = ((long)ci * S + s) * g.in.P + pj;
+                const long bi = (long)ci * g.in.colpad + (long)s * g.in.P + pj;
+                const unsigned dw = A.deg_in[bi >> 5] >> (bi & 31);
+                unsigned xw[NM > 0 ? NM : 1];
+#pragma unroll
+                for (int q = 0; q < NM; ++q) xw[q] = A.R.slot[q].xbits[bi >> 5] >> (bi & 31);
+                const float4 l = *reinterpret_cast<const float4*>(A.lo_in + a);
+                const float4 h = *reinterpret_cast<const float4*>(A.hi_in + a);
+                const float lo4[4] = {l.x, l.y, l.z, l.w}, hi4[4] = {h.x, h.y, h.z, h.w};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    unsigned xb = 0;
+#pragma unroll
+                    for (int q = 0; q < NM; ++q) xb |= ((xw[q] >> u) & 1u) << q;
+                    tap(t + u, (double)lo4[u], (double)hi4[u], (dw >> u) & 1u, xb);
+                }
+            }
+        } else {
+            TapWalk tw = tap_walk(g, p, t0);
+            for (int t = t0; t < t1; ++t, tap_next(g, tw)) {
+                const FwdTap tp = tap_at(g, S, s, tw);
+                if (tp.a < 0) continue;
+                unsigned xb = 0;
+#pragma unroll
+                for (int q = 0; q < NM; ++q) xb |= getbit(A.R.slot[q].xbits, tp.bi) << q;
+                tap(t, (double)A.lo_in[tp.a], (double)A.hi_in[tp.a], getbit(A.deg_in, tp.bi), xb);
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < CB; ++e) {
+        red[((wave * CB + e) * 2 + 0) * kWave + lane] = r1[e] + r0x[e];
+        red[((wave * CB + e) * 2 + 1) * kWave + lane] = r1[e];
+    }
+    __syncthreads();
+    const int e = wave;
+    if (e >= CB) return;
+    const int c = c0 + e;
+    if (!colok || c >= g.out.C) return;
+    const long idx = ((long)c * S + s) * g.out.P + p;
+    double r0 = 0, r1s = 0;
+    for (int w = 0; w < NW; ++w) {
+        r0 += red[((w * CB + e) * 2 + 0) * kWave + lane];
+        r1s += red[((w * CB + e) * 2 + 1) * kWave + lane];
+    }
+    // own = alpha - beta0 - beta1 - sum beta_I,
+    // g = beta0 uhat + beta1 lhat + sum beta_I (LI + UI + b),
+    // const = b alpha + beta1 (lhat - b) + sum LI beta_I
+    const double bb = (double)g.b[c];
+    const double al = A.R.alpha[idx], b0 = A.R.beta0[idx], b1 = A.R.beta1[idx];
+    const double lh = A.R.lhat[idx], uh = A.R.uhat[idx];
+    double sb = 0;
+#pragma unroll
+    for (int q = 0; q < NM; ++q) sb += (double)A.R.slot[q].beta[idx];
+    A.R.own64[idx] = al - b0 - b1 - sb;
+    A.R.g64[idx] = b0 * uh + b1 * lh + r0 + bb * sb;
+    A.R.const64[idx] = bb * al + b1 * (lh - bb) + r1s;
+}
+
+}  // namespace
+
+template <int NM>
+asd_status final_sums_nm(asd_plan* P, int k, hipStream_t st) {
+    MaskArgs<float> a;
+    memset(&a, 0, sizeof(a));
+    a.g = P->geo[k];
+    a.S = P->S;
+    a.nm = NM;
+    a.lo_in = P->naf[k - 1].lo;
+    a.hi_in = P->naf[k - 1].hi;
+    a.deg_in = P->naf[k - 1].deg;
+    a.R = P->Rf[k];
+    const dim3 grid = grid_cols(P->nl[k], CB);
+    const bool dv16 = a.g.kind == ASD_LAYER_DENSE && a.g.in.P % 4 == 0 && a.g.fan % (4 * 16) == 0;
+    const bool dv4 = a.g.kind == ASD_LAYER_DENSE && a.g.in.P % 4 == 0 && a.g.fan % (4 * KS) == 0;
+    if (a.g.fan >= 1024) {
+        const size_t lds = (size_t)16 * CB * 2 * kWave * sizeof(double);
+        if (dv16) hipLaunchKernelGGL((k_final_sums_sc<NM, 16, true>), grid, dim3(kWave, 16), lds, st, a);
+        else hipLaunchKernelGGL((k_final_sums_sc<NM, 16, false>), grid, dim3(kWave, 16), lds, st, a);
+    } else {
+        const size_t lds = (size_t)KS * CB * 2 * kWave * sizeof(double);
+        if (dv4) hipLaunchKernelGGL((k_final_sums_sc<NM, KS, true>), grid, dim3(kWave, KS), lds, st, a);
+        else hipLaunchKernelGGL((k_final_sums_sc<NM, KS, false>), grid, dim3(kWave, KS), lds, st, a);
+    }
+    LAUNCH_CHECK();
+    return ASD_OK;
+}
+
+template asd_status final_sums_nm<ASD_NM>(asd_plan*, int, hipStream_t);
+
+}  // namespace asd

@@ -531,6 +531,10 @@ asd_status grad_box_nm(asd_plan* P, const double* gs, double* dl0, double* du0, 
 // with NM active masks (sign classes; asd_final.hip, compiled per mask count).
 template <int NM>
 asd_status final_sums_nm(asd_plan* P, int k, hipStream_t st);
+// FP64 backward pass of the final bound of an FP32 plan into neuron layer k,
+// NM = active masks of layer k+1 (sign classes; asd_final.hip).
+template <int NM>
+asd_status backward_final_nm(const BwdArgs<float>& a, hipStream_t st);
 
 // Bias, stage one: block (chunk, channel), fixed-order block sum.
 template <typename Ts>

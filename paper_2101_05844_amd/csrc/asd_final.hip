@@ -1,6 +1,6 @@
-// FP64 per-neuron sums of the final bound of an FP32 plan in sign classes,
-// for one count of active masks: compiled once per count with
-// -DASD_NM=<count>.
+// FP64 per-neuron sums and backward pass of the final bound of an FP32 plan
+// in sign classes, for one count of active masks: compiled once per count
+// with -DASD_NM=<count>.
 //
 // For neuron o of ReLU layer k the final bound needs, over its active masks
 // q with multipliers b_q (eq:dual-active-set),
@@ -155,6 +155,152 @@ __global__ void __launch_bounds__(kWave * NW) k_final_sums_sc(MaskArgs<float> A)
     A.R.const64[idx] = bb * al + b1 * (lh - bb) + r1s;
 }
 
+// FP64 backward pass of the final bound of an FP32 plan (f_k, x*_k, z*_k
+// and the objective terms of neuron layer k) in sign classes.  For neuron j
+// of layer k and an output o of layer k+1 that reads it with weight w, the
+// masked part of f_k[j] is sum_q c_q u_q[o], where u_q = (1 - z_q[o]) b_q and
+// c_q is w where mask q contains j (w > 0: x not at the upper end; w < 0: x
+// at the upper end; both on a point box).  With U = sum_q u_q and
+// Xu = sum_q xbit_q[j] u_q (no point box): w > 0 gives w (U - Xu), w < 0
+// gives w (Xu + [point box] U), so a pair costs one FMA per mask plus four,
+// written as max(w, 0) (U - Xu) + min(w, 0) (Xu + [point] U).
+template <int NM>
+__global__ void __launch_bounds__(kWave * KS) k_backward_final_sc(BwdArgs<float> A) {
+    extern __shared__ unsigned char red_raw[];
+    double* red = reinterpret_cast<double*>(red_raw);  // [KS][CB][64]
+    const LayerGeo& g = A.gn;
+    const NeuronLayout& L = g.in;   // layer k
+    const NeuronLayout& O = g.out;  // layer k+1
+    const int lane = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    const long col = (long)blockIdx.x * kWave + lane;
+    const int c0 = blockIdx.y * CB;
+    const int S = A.S;
+    const bool colok = col < L.cols;
+    const int s = colok ? (int)(col / L.P) : 0;
+    const int p = colok ? (int)(col - (long)s * L.P) : 0;
+    // per channel: point-box bit, the masks' x bits as 0/1 (none on a point box)
+    unsigned dg4 = 0;
+    double xd[CB][NM > 0 ? NM : 1], dgd[CB];
+#pragma unroll
+    for (int e = 0; e < CB; ++e) {
+        dgd[e] = 0;
+#pragma unroll
+        for (int q = 0; q < NM; ++q) xd[e][q] = 0;
+        if (colok && c0 + e < L.C) {
+            const long bie = (long)(c0 + e) * L.colpad + col;
+            const unsigned dg = getbit(A.nk.deg, bie);
+            dg4 |= dg << e;
+            dgd[e] = dg ? 1.0 : 0.0;
+            if (!dg)
+#pragma unroll
+                for (int q = 0; q < NM; ++q) xd[e][q] = getbit(A.Rn.slot[q].xbits, bie) ? 1.0 : 0.0;
+        }
+    }
+    double acc[CB];
+#pragma unroll
+    for (int e = 0; e < CB; ++e) acc[e] = 0;
+    // output o at neuron address a (bit index bi) with the weights w[e] to
+    // this lane's channels
+    auto add_output = [&](long a, long bi, const double* w) {
+        double v, uq[NM > 0 ? NM : 1], U = 0;
+        if (A.last) {
+            v = -(double)A.cvec[a];
+#pragma unroll
+            for (int q = 0; q < NM; ++q) uq[q] = 0;
+        } else {
+            v = -(double)A.Rn.alpha[a] + (double)A.Rn.beta1[a];
+#pragma unroll
+            for (int q = 0; q < NM; ++q) {
+                const double bq = (double)A.Rn.slot[q].beta[a];
+                if (getbit(A.Rn.slot[q].zbits, bi)) {
+                    v += bq;
+                    uq[q] = 0;
+                } else {
+                    uq[q] = bq;
+                    U += bq;
+                }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < CB; ++e) {
+            double Xu = 0;
+            if constexpr (NM > 0) {
+                Xu = xd[e][0] * uq[0];
+#pragma unroll
+                for (int q = 1; q < NM; ++q) Xu = fma(xd[e][q], uq[q], Xu);
+            }
+            acc[e] = fma(w[e], v, acc[e]);
+            acc[e] = fma(fmax(w[e], 0.0), U - Xu, acc[e]);
+            acc[e] = fma(fmin(w[e], 0.0), fma(dgd[e], U, Xu), acc[e]);
+        }
+    };
+    if (colok) {
+        if (g.kind == ASD_LAYER_DENSE) {
+            const int n1 = O.C;
+            const int i0 = (int)((long)n1 * wave / KS), i1 = (int)((long)n1 * (wave + 1) / KS);
+            for (int i = i0; i < i1; ++i) {
+                double w[CB];
+#pragma unroll
+                for (int e = 0; e < CB; ++e)
+                    w[e] = c0 + e < L.C ? (double)g.W[(long)i * g.fan + (long)(c0 + e) * L.P + p] : 0.0;
+                add_output((long)i * S + s, (long)i * O.colpad + s, w);
+            }
+        } else {
+            const int y = p / L.W, x = p - (p / L.W) * L.W;
+            const int co0 = (int)((long)O.C * wave / KS), co1 = (int)((long)O.C * (wave + 1) / KS);
+            const int ks = g.ksz, str = g.stride;
+            const int ky0 = (y + g.pad) % str, kx0 = (x + g.pad) % str;
+            const int oyf = (y + g.pad - ky0) / str, oxf = (x + g.pad - kx0) / str;
+            for (int co = co0; co < co1; ++co) {
+                int oy = oyf;
+                for (int ky = ky0; ky < ks; ky += str, --oy) {
+                    if (oy < 0 || oy >= O.H) continue;
+                    int ox = oxf;
+                    for (int kx = kx0; kx < ks; kx += str, --ox) {
+                        if (ox < 0 || ox >= O.W) continue;
+                        const int op = oy * O.W + ox;
+                        double w[CB];
+#pragma unroll
+                        for (int e = 0; e < CB; ++e)
+                            w[e] = c0 + e < L.C ? (double)g.W[(((long)co * L.C + c0 + e) * ks + ky) * ks + kx] : 0.0;
+                        add_output(((long)co * S + s) * O.P + op, (long)co * O.colpad + (long)s * O.P + op, w);
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < CB; ++e) red[(wave * CB + e) * kWave + lane] = acc[e];
+    __syncthreads();
+    const int e = wave;
+    const int c = c0 + e;
+    if (c >= L.C) return;  // whole wave leaves together
+    const long idx = ((long)c * S + s) * L.P + p;
+    bool xb = false, zb = false;
+    if (colok) {
+        double f = 0;
+        for (int w = 0; w < KS; ++w) f += red[(w * CB + e) * kWave + lane];
+        if (A.k >= 1) f += A.Rk.own64[idx];
+        if (A.fout) A.fout[idx] = f;
+        if (A.fext) A.fext[(long)s * L.N + (long)c * L.P + p] = (float)f;
+        // x-bit "x* = upper end"; a point box counts as both ends and keeps the bit set
+        xb = f >= 0 || ((dg4 >> e) & 1u);
+        const double xv = xb ? (double)A.nk.hi[idx] : (double)A.nk.lo[idx];
+        A.nk.xstar[idx] = (float)xv;
+        double term = -f * xv;
+        if (A.k >= 1) {
+            const double gk = A.Rk.g64[idx];
+            zb = gk >= 0;
+            term -= zb ? gk : 0.0;
+            if (A.want_obj) term += A.Rk.const64[idx];
+        }
+        if (A.want_obj) A.nk.term[idx] = term;
+    }
+    const long base = (long)c * L.colpad + (long)blockIdx.x * kWave;
+    put_wave_bits(A.nk.xbits, base, colok && xb, lane);
+    if (A.k >= 1) put_wave_bits(A.Rk.zbits, base, colok && zb, lane);
+}
+
 }  // namespace
 
 template <int NM>
@@ -184,6 +330,15 @@ asd_status final_sums_nm(asd_plan* P, int k, hipStream_t st) {
     return ASD_OK;
 }
 
+template <int NM>
+asd_status backward_final_nm(const BwdArgs<float>& a, hipStream_t st) {
+    const size_t lds = (size_t)KS * CB * kWave * sizeof(double);
+    hipLaunchKernelGGL((k_backward_final_sc<NM>), grid_cols(a.gn.in, CB), dim3(kWave, KS), lds, st, a);
+    LAUNCH_CHECK();
+    return ASD_OK;
+}
+
 template asd_status final_sums_nm<ASD_NM>(asd_plan*, int, hipStream_t);
+template asd_status backward_final_nm<ASD_NM>(const BwdArgs<float>&, hipStream_t);
 
 }  // namespace asd

@@ -528,9 +528,10 @@ template <int NM>
 asd_status grad_box_nm(asd_plan* P, const double* gs, double* dl0, double* du0, bool* done, hipStream_t st);
 
 // FP64 per-neuron sums of the final bound of an FP32 plan for ReLU layer k
-// with NM active masks (sign classes; asd_final.hip, compiled per mask count).
+// with NM active masks (sign classes; asd_final.hip, compiled per mask
+// count); inrec: room for the input records of layer k-1 (GwIn<float>).
 template <int NM>
-asd_status final_sums_nm(asd_plan* P, int k, hipStream_t st);
+asd_status final_sums_nm(asd_plan* P, int k, void* inrec, hipStream_t st);
 // FP64 backward pass of the final bound of an FP32 plan into neuron layer k,
 // NM = active masks of layer k+1 (sign classes; asd_final.hip).
 template <int NM>
@@ -569,13 +570,28 @@ __global__ void __launch_bounds__(kGradThreads) k_gb_part(GradArgs<Ts> A) {
     if (threadIdx.x == 0) A.part[(long)blockIdx.x * A.entries + co] = red[0];
 }
 
-// Stage two: out[e] = sum over chunks of part[chunk * entries + e], in chunk order.
-static __global__ void __launch_bounds__(kGradThreads) k_gsum(const double* part, long entries, int chunks, double* out) {
-    const long e = (long)blockIdx.x * kGradThreads + threadIdx.x;
-    if (e >= entries) return;
+// Stage two: out[e] = sum over chunks of part[chunk * entries + e].  A block
+// takes 64 entries (lanes, coalesced) and kGsumW waves, wave w summing a
+// contiguous range of chunks in order; the waves' sums are then added in
+// wave order (a fixed order: the result does not depend on scheduling).
+constexpr int kGsumW = 16;
+static __global__ void __launch_bounds__(64 * kGsumW) k_gsum(const double* part, long entries, int chunks, double* out) {
+    __shared__ double red[kGsumW][64];
+    const int lane = threadIdx.x, w = threadIdx.y;
+    const long e = (long)blockIdx.x * 64 + lane;
+    const int c0 = (int)((long)chunks * w / kGsumW), c1 = (int)((long)chunks * (w + 1) / kGsumW);
     double v = 0;
-    for (int c = 0; c < chunks; ++c) v += part[(long)c * entries + e];
-    out[e] = v;
+    if (e < entries) {
+#pragma unroll 8
+        for (int c = c0; c < c1; ++c) v += part[(long)c * entries + e];
+    }
+    red[w][lane] = v;
+    __syncthreads();
+    if (w == 0 && e < entries) {
+        double t = 0;
+        for (int i = 0; i < kGsumW; ++i) t += red[i][lane];
+        out[e] = t;
+    }
 }
 
 // One thread per input neuron and subproblem (internal layout of layer 0).

@@ -580,7 +580,7 @@ asd_status launch_mask_consts(asd_plan* P, int k, int q, const uint32_t* zsrc, c
 
 asd_status launch_final_sums(asd_plan* P, int k, hipStream_t st) {
     ProfScope ps(P, st, ASD_K_FINAL, k);
-#define ASD_FS_CALL(N) return final_sums_nm<N>(P, k, st)
+#define ASD_FS_CALL(N) return final_sums_nm<N>(P, k, grad_inrec(P), st)
     ASD_NM_DISPATCH(P->n_masks, ASD_FS_CALL)
 #undef ASD_FS_CALL
 }
@@ -915,9 +915,8 @@ asd_status bound_grad_t(asd_plan* P, const double* gs, double* const* dW, double
                     ASD_NM_DISPATCH(a.nm, ASD_GW_CALL)
 #undef ASD_GW_CALL
                 }
-                hipLaunchKernelGGL(k_gsum, dim3((unsigned)((a.entries + kGradThreads - 1) / kGradThreads)),
-                                   dim3(kGradThreads), 0, st, (const double*)P->gpart, a.entries, P->gw_chunks[k],
-                                   dW[k - 1]);
+                hipLaunchKernelGGL(k_gsum, dim3((unsigned)((a.entries + 63) / 64)), dim3(64, kGsumW), 0, st,
+                                   (const double*)P->gpart, a.entries, P->gw_chunks[k], dW[k - 1]);
                 LAUNCH_CHECK();
             }
         }
@@ -930,9 +929,8 @@ asd_status bound_grad_t(asd_plan* P, const double* gs, double* const* dW, double
             hipLaunchKernelGGL(k_gb_part<Ts>, dim3((unsigned)P->gb_chunks[k], (unsigned)g.out.C), dim3(kGradThreads), 0,
                                st, a);
             LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_gsum, dim3((unsigned)((g.out.C + kGradThreads - 1) / kGradThreads)),
-                               dim3(kGradThreads), 0, st, (const double*)a.part, (long)g.out.C, P->gb_chunks[k],
-                               db[k - 1]);
+            hipLaunchKernelGGL(k_gsum, dim3((unsigned)((g.out.C + 63) / 64)), dim3(64, kGsumW), 0, st,
+                               (const double*)a.part, (long)g.out.C, P->gb_chunks[k], db[k - 1]);
             LAUNCH_CHECK();
         }
     }

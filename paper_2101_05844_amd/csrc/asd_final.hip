@@ -28,7 +28,7 @@ namespace {
 // NW waves split the fan-in; DV: a dense layer over channels of 4k positions
 // whose fan-in splits into multiples of 4 taps (one vector load per 4 taps).
 template <int NM, int NW, bool DV>
-__global__ void __launch_bounds__(kWave * NW) k_final_sums_sc(MaskArgs<float> A) {
+__global__ void __launch_bounds__(kWave * NW) k_final_sums_sc(MaskArgs<float> A, const GwIn<float>* rec) {
     static_assert(NW >= CB, "one wave per channel finishes the sums");
     extern __shared__ unsigned char red_raw[];
     double* red = reinterpret_cast<double*>(red_raw);  // [NW][CB][2][64]
@@ -65,11 +65,11 @@ __global__ void __launch_bounds__(kWave * NW) k_final_sums_sc(MaskArgs<float> A)
     for (int e = 0; e < CB; ++e) r1[e] = r0x[e] = 0;
     const int F = g.fan;
     const int t0 = (int)((long)F * wave / NW), t1 = (int)((long)F * (wave + 1) / NW);
-    // one tap: box ends, point-box bit, the masks' x bits
+    // one tap: box ends, point-box bit, the masks' x bits (cleared on a point box)
     auto tap = [&](int t, double lo, double hi, unsigned dg, unsigned xb) {
         double xd[NM > 0 ? NM : 1];
 #pragma unroll
-        for (int q = 0; q < NM; ++q) xd[q] = (!dg && ((xb >> q) & 1u)) ? 1.0 : 0.0;
+        for (int q = 0; q < NM; ++q) xd[q] = ((xb >> q) & 1u) ? 1.0 : 0.0;
 #pragma unroll
         for (int e = 0; e < CB; ++e) {
             const float wf = c0 + e < g.out.C ? g.W[(long)(c0 + e) * F + t] : 0.f;
@@ -94,34 +94,23 @@ __global__ void __launch_bounds__(kWave * NW) k_final_sums_sc(MaskArgs<float> A)
     };
     if (colok) {
         if constexpr (DV) {
+            // dense layer: 4 consecutive taps are 4 consecutive records
             for (int t = t0; t < t1; t += 4) {
                 const int ci = t / g.in.P, pj = t - ci * g.in.P;
                 const long a = ((long)ci * S + s) * g.in.P + pj;
-                const long bi = (long)ci * g.in.colpad + (long)s * g.in.P + pj;
-                const unsigned dw = A.deg_in[bi >> 5] >> (bi & 31);
-                unsigned xw[NM > 0 ? NM : 1];
+                GwIn<float> v[4];
 #pragma unroll
-                for (int q = 0; q < NM; ++q) xw[q] = A.R.slot[q].xbits[bi >> 5] >> (bi & 31);
-                const float4 l = *reinterpret_cast<const float4*>(A.lo_in + a);
-                const float4 h = *reinterpret_cast<const float4*>(A.hi_in + a);
-                const float lo4[4] = {l.x, l.y, l.z, l.w}, hi4[4] = {h.x, h.y, h.z, h.w};
+                for (int u = 0; u < 4; ++u) v[u] = rec[a + u];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    unsigned xb = 0;
-#pragma unroll
-                    for (int q = 0; q < NM; ++q) xb |= ((xw[q] >> u) & 1u) << q;
-                    tap(t + u, (double)lo4[u], (double)hi4[u], (dw >> u) & 1u, xb);
-                }
+                for (int u = 0; u < 4; ++u) tap(t + u, (double)v[u].l, (double)v[u].u, v[u].bits & 1u, v[u].bits >> 1);
             }
         } else {
             TapWalk tw = tap_walk(g, p, t0);
             for (int t = t0; t < t1; ++t, tap_next(g, tw)) {
                 const FwdTap tp = tap_at(g, S, s, tw);
                 if (tp.a < 0) continue;
-                unsigned xb = 0;
-#pragma unroll
-                for (int q = 0; q < NM; ++q) xb |= getbit(A.R.slot[q].xbits, tp.bi) << q;
-                tap(t, (double)A.lo_in[tp.a], (double)A.hi_in[tp.a], getbit(A.deg_in, tp.bi), xb);
+                const GwIn<float> v = rec[tp.a];
+                tap(t, (double)v.l, (double)v.u, v.bits & 1u, v.bits >> 1);
             }
         }
     }
@@ -304,27 +293,41 @@ __global__ void __launch_bounds__(kWave * KS) k_backward_final_sc(BwdArgs<float>
 }  // namespace
 
 template <int NM>
-asd_status final_sums_nm(asd_plan* P, int k, hipStream_t st) {
+asd_status final_sums_nm(asd_plan* P, int k, void* inrec, hipStream_t st) {
+    const LayerGeo& g = P->geo[k];
+    // input records of layer k-1 (box ends, point-box and x bits)
+    GradArgs<float> ga;
+    memset(&ga, 0, sizeof(ga));
+    ga.g = g;
+    ga.S = P->S;
+    ga.nm = NM;
+    ga.xin = P->naf[k - 1].xstar;
+    ga.lo_in = P->naf[k - 1].lo;
+    ga.hi_in = P->naf[k - 1].hi;
+    ga.deg_in = P->naf[k - 1].deg;
+    ga.R = RdevT<float>(P) + k;
+    GwIn<float>* rec = static_cast<GwIn<float>*>(inrec);
+    const long nin = (long)g.in.C * g.in.cols;
+    hipLaunchKernelGGL(k_gw_in<float>, dim3((unsigned)((nin + kGradThreads - 1) / kGradThreads)), dim3(kGradThreads),
+                       0, st, ga, rec);
+    LAUNCH_CHECK();
     MaskArgs<float> a;
     memset(&a, 0, sizeof(a));
-    a.g = P->geo[k];
+    a.g = g;
     a.S = P->S;
     a.nm = NM;
-    a.lo_in = P->naf[k - 1].lo;
-    a.hi_in = P->naf[k - 1].hi;
-    a.deg_in = P->naf[k - 1].deg;
     a.R = P->Rf[k];
     const dim3 grid = grid_cols(P->nl[k], CB);
-    const bool dv16 = a.g.kind == ASD_LAYER_DENSE && a.g.in.P % 4 == 0 && a.g.fan % (4 * 16) == 0;
-    const bool dv4 = a.g.kind == ASD_LAYER_DENSE && a.g.in.P % 4 == 0 && a.g.fan % (4 * KS) == 0;
-    if (a.g.fan >= 1024) {
+    const bool dv16 = g.kind == ASD_LAYER_DENSE && g.in.P % 4 == 0 && g.fan % (4 * 16) == 0;
+    const bool dv4 = g.kind == ASD_LAYER_DENSE && g.in.P % 4 == 0 && g.fan % (4 * KS) == 0;
+    if (g.fan >= 1024) {
         const size_t lds = (size_t)16 * CB * 2 * kWave * sizeof(double);
-        if (dv16) hipLaunchKernelGGL((k_final_sums_sc<NM, 16, true>), grid, dim3(kWave, 16), lds, st, a);
-        else hipLaunchKernelGGL((k_final_sums_sc<NM, 16, false>), grid, dim3(kWave, 16), lds, st, a);
+        if (dv16) hipLaunchKernelGGL((k_final_sums_sc<NM, 16, true>), grid, dim3(kWave, 16), lds, st, a, rec);
+        else hipLaunchKernelGGL((k_final_sums_sc<NM, 16, false>), grid, dim3(kWave, 16), lds, st, a, rec);
     } else {
         const size_t lds = (size_t)KS * CB * 2 * kWave * sizeof(double);
-        if (dv4) hipLaunchKernelGGL((k_final_sums_sc<NM, KS, true>), grid, dim3(kWave, KS), lds, st, a);
-        else hipLaunchKernelGGL((k_final_sums_sc<NM, KS, false>), grid, dim3(kWave, KS), lds, st, a);
+        if (dv4) hipLaunchKernelGGL((k_final_sums_sc<NM, KS, true>), grid, dim3(kWave, KS), lds, st, a, rec);
+        else hipLaunchKernelGGL((k_final_sums_sc<NM, KS, false>), grid, dim3(kWave, KS), lds, st, a, rec);
     }
     LAUNCH_CHECK();
     return ASD_OK;
@@ -338,7 +341,7 @@ asd_status backward_final_nm(const BwdArgs<float>& a, hipStream_t st) {
     return ASD_OK;
 }
 
-template asd_status final_sums_nm<ASD_NM>(asd_plan*, int, hipStream_t);
+template asd_status final_sums_nm<ASD_NM>(asd_plan*, int, void*, hipStream_t);
 template asd_status backward_final_nm<ASD_NM>(const BwdArgs<float>&, hipStream_t);
 
 }  // namespace asd

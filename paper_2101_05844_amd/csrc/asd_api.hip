@@ -497,17 +497,18 @@ asd_status launch_backward(asd_plan* P, int k, int want_obj, int role, hipStream
     a.want_obj = want_obj;
     a.fout = fout;
     a.fext = reinterpret_cast<Ts*>(fext);
-    const size_t lds = (size_t)KS * CB * kWave * sizeof(Tc);
     ProfScope ps(P, st, role, k);
     if constexpr (sizeof(Tc) > sizeof(Ts)) {
         // FP64 final bound of an FP32 plan: the sign-class kernel
 #define ASD_BF_CALL(N) return backward_final_nm<N>(a, st)
         ASD_NM_DISPATCH(a.nm_next, ASD_BF_CALL)
 #undef ASD_BF_CALL
+    } else {
+        const size_t lds = (size_t)KS * CB * kWave * sizeof(Tc);
+        hipLaunchKernelGGL((k_backward<Tc, Ts>), grid_cols(a.gn.in, CB), dim3(kWave, KS), lds, st, a);
+        LAUNCH_CHECK();
+        return ASD_OK;
     }
-    hipLaunchKernelGGL((k_backward<Tc, Ts>), grid_cols(a.gn.in, CB), dim3(kWave, KS), lds, st, a);
-    LAUNCH_CHECK();
-    return ASD_OK;
 }
 
 template <typename T>

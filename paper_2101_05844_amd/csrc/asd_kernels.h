@@ -318,10 +318,9 @@ __global__ void __launch_bounds__(kWave * KS) k_forward(FwdArgs<T> A) {
 
 // ---------------------------------------------------------------------------
 // Backward pass: f_k, the inner minimisation, objective terms.
-// Tc = compute type, Ts = state type.  Tc == Ts in the iterations (and for the
-// final bound of an FP64 plan); Tc = double, Ts = float for the final bound of
-// an FP32 plan: then every sum runs in FP64 from the FP32 duals, with the
-// per-neuron sums from k_mask_consts<double, float>.
+// Tc = compute type, Ts = state type, the same type: the iterations and the
+// final bound of an FP64 plan.  (The FP64 final bound of an FP32 plan has
+// kernels of its own, in sign classes.)
 // ---------------------------------------------------------------------------
 template <typename Ts>
 struct BwdArgs {
@@ -367,7 +366,7 @@ template <typename Tc, typename Ts>
 __global__ void __launch_bounds__(kWave * KS) k_backward(BwdArgs<Ts> A) {
     extern __shared__ unsigned char red_raw[];
     Tc* red = reinterpret_cast<Tc*>(red_raw);  // [KS][CB][64]
-    constexpr bool kFinal64 = sizeof(Tc) > sizeof(Ts);
+    static_assert(sizeof(Tc) == sizeof(Ts), "one type for sums and state");
     const LayerGeo& g = A.gn;
     const NeuronLayout& L = g.in;   // layer k
     const NeuronLayout& O = g.out;  // layer k+1
@@ -396,39 +395,22 @@ __global__ void __launch_bounds__(kWave * KS) k_backward(BwdArgs<Ts> A) {
             }
         }
     }
-    // Iteration kernels keep W+^T u and W-^T u per mask and fold them with
-    // the bits at the end; the FP64 final bound of an FP32 plan folds every
-    // tap's masked terms as it goes (one accumulator per channel instead of
-    // 2 K: the register count, not the FP64 rounding order, sets its speed)
-    constexpr int NQ = kFinal64 ? 1 : kMaxMasks;
-    Tc acc[CB], am[CB];
-    Tc accP[NQ][CB], accQ[NQ][CB];
+    // W+^T u and W-^T u per mask, folded with the bits at the end
+    Tc acc[CB];
+    Tc accP[kMaxMasks][CB], accQ[kMaxMasks][CB];
 #pragma unroll
     for (int e = 0; e < CB; ++e) {
-        acc[e] = am[e] = 0;
+        acc[e] = 0;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) accP[q][e] = accQ[q][e] = 0;
+        for (int q = 0; q < kMaxMasks; ++q) accP[q][e] = accQ[q][e] = 0;
     }
     auto add = [&](int e, Tc w, Tc v, const Tc* uq) {
         acc[e] += w * v;
-        if constexpr (kFinal64) {
-            const bool dg = (dg4 >> e) & 1u;
-            const Tc wp = tmax0(w), wn = tmin0(w);
 #pragma unroll
-            for (int q = 0; q < kMaxMasks; ++q) {
-                if (q < nm) {
-                    const bool xq = (xq4[q] >> e) & 1u;
-                    const Tc cq = ((!xq || dg) ? wp : (Tc)0) + ((xq || dg) ? wn : (Tc)0);
-                    am[e] += cq * uq[q];
-                }
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                if (q < nm) {
-                    accP[q][e] += tmax0(w) * uq[q];
-                    accQ[q][e] += tmin0(w) * uq[q];
-                }
+        for (int q = 0; q < kMaxMasks; ++q) {
+            if (q < nm) {
+                accP[q][e] += tmax0(w) * uq[q];
+                accQ[q][e] += tmin0(w) * uq[q];
             }
         }
     };
@@ -487,17 +469,13 @@ __global__ void __launch_bounds__(kWave * KS) k_backward(BwdArgs<Ts> A) {
 #pragma unroll
     for (int e = 0; e < CB; ++e) {
         Tc part = acc[e];
-        if constexpr (kFinal64) {
-            part += am[e];
-        } else {
-            const bool dg = (dg4 >> e) & 1u;
+        const bool dg = (dg4 >> e) & 1u;
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                if (q < nm) {
-                    const bool xq = (xq4[q] >> e) & 1u;
-                    if (!xq || dg) part += accP[q][e];
-                    if (xq || dg) part += accQ[q][e];
-                }
+        for (int q = 0; q < kMaxMasks; ++q) {
+            if (q < nm) {
+                const bool xq = (xq4[q] >> e) & 1u;
+                if (!xq || dg) part += accP[q][e];
+                if (xq || dg) part += accQ[q][e];
             }
         }
         red[(wave * CB + e) * kWave + lane] = part;
@@ -512,7 +490,7 @@ __global__ void __launch_bounds__(kWave * KS) k_backward(BwdArgs<Ts> A) {
     if (colok) {
         for (int w = 0; w < KS; ++w) f += red[(w * CB + e) * kWave + lane];
         const int nmo = A.nm_own;
-        if (A.k >= 1) f += kFinal64 ? (Tc)A.Rk.own64[idx] : (Tc)A.Rk.own[idx];
+        if (A.k >= 1) f += (Tc)A.Rk.own[idx];
         if (A.fout) A.fout[idx] = (double)f;
         if (A.fext) A.fext[(long)s * L.N + (long)c * L.P + p] = (Ts)f;
         // x-bit "x* = upper end"; a point box counts as both ends and keeps the bit set
@@ -521,18 +499,14 @@ __global__ void __launch_bounds__(kWave * KS) k_backward(BwdArgs<Ts> A) {
         A.nk.xstar[idx] = (Ts)xv;
         Tc term = -f * xv;
         if (A.k >= 1) {
-            const Tc gk = kFinal64 ? (Tc)A.Rk.g64[idx] : (Tc)A.Rk.g[idx];
+            const Tc gk = (Tc)A.Rk.g[idx];
             zb = gk >= 0;
             term -= zb ? gk : (Tc)0;
             if (A.want_obj) {
-                if (kFinal64) {
-                    term += (Tc)A.Rk.const64[idx];
-                } else {
-                    const Tc bb = (Tc)A.bk[c];
-                    Tc cst = bb * (Tc)A.Rk.alpha[idx] + (Tc)A.Rk.beta1[idx] * ((Tc)A.Rk.lhat[idx] - bb);
-                    for (int q = 0; q < nmo; ++q) cst += (Tc)A.Rk.slot[q].LI[idx] * (Tc)A.Rk.slot[q].beta[idx];
-                    term += cst;
-                }
+                const Tc bb = (Tc)A.bk[c];
+                Tc cst = bb * (Tc)A.Rk.alpha[idx] + (Tc)A.Rk.beta1[idx] * ((Tc)A.Rk.lhat[idx] - bb);
+                for (int q = 0; q < nmo; ++q) cst += (Tc)A.Rk.slot[q].LI[idx] * (Tc)A.Rk.slot[q].beta[idx];
+                term += cst;
             }
         }
         if (A.want_obj) A.nk.term[idx] = (double)term;
@@ -552,12 +526,12 @@ template <typename Ts>
 struct MaskArgs {
     LayerGeo g;                 // layer k
     int S;
-    int q;                      // slot to fill (Tc == Ts)
-    int nm;                     // active masks (final sums)
+    int q;                      // slot to fill
+    int nm;                     // active masks
     const Ts* lo_in; const Ts* hi_in;   // box of layer k-1
-    const uint32_t* zsrc;       // z bits of layer k (Tc == Ts)
-    const uint32_t* xsrc;       // x*_{k-1} == hi bits of layer k-1 (Tc == Ts)
-    int zero_state;             // Tc == Ts: also zero the slot's beta, moments, u
+    const uint32_t* zsrc;       // z bits of layer k
+    const uint32_t* xsrc;       // x*_{k-1} == hi bits of layer k-1
+    int zero_state;             // also zero the slot's beta, moments, u
     const uint32_t* deg_in;
     ReluLayerT<Ts> R;
 };
@@ -590,37 +564,30 @@ __global__ void __launch_bounds__(kWave * NW) k_mask_consts(MaskArgs<Ts> A) {
     static_assert(NW >= CB, "one wave per channel finishes the sums");
     extern __shared__ unsigned char red_raw[];
     Tc* red = reinterpret_cast<Tc*>(red_raw);  // [NW][CB][2][64]
-    constexpr bool kFinal64 = sizeof(Tc) > sizeof(Ts);
+    static_assert(sizeof(Tc) == sizeof(Ts), "one type for sums and state");
     const LayerGeo& g = A.g;
     const int lane = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(threadIdx.y);  // wave-uniform
     const long col = (long)blockIdx.x * kWave + lane;
     const int c0 = blockIdx.y * CB;
     const int S = A.S;
-    const int q0 = kFinal64 ? 0 : A.q;
-    const int nsl = kFinal64 ? A.nm : 1;
     const bool colok = col < g.out.cols;
     const int s = colok ? (int)(col / g.out.P) : 0;
     const int p = colok ? (int)(col - (long)s * g.out.P) : 0;
     const long bicol0 = (long)c0 * g.out.colpad + col;
 
-    // one slot at a time: its LI and UI over this wave's taps; the final
-    // sums fold each slot with its multiplier as soon as it is done,
-    // sum_q beta_q (LI_q + UI_q) and sum_q beta_q LI_q, in slot order
-    Tc fin0[CB], fin1[CB];
+    // the slot's LI and UI over this wave's taps
+    Tc LI[CB], UI[CB];
 #pragma unroll
-    for (int e = 0; e < CB; ++e) fin0[e] = fin1[e] = 0;
+    for (int e = 0; e < CB; ++e) LI[e] = UI[e] = 0;
     const int F = g.fan;
     const int t0 = (int)((long)F * wave / NW), t1 = (int)((long)F * (wave + 1) / NW);
-    for (int j = 0; j < (colok ? nsl : 0); ++j) {
-        const uint32_t* zb = kFinal64 ? A.R.slot[q0 + j].zbits : A.zsrc;
-        const uint32_t* xbits = kFinal64 ? A.R.slot[q0 + j].xbits : A.xsrc;
+    if (colok) {
+        const uint32_t* zb = A.zsrc;
+        const uint32_t* xbits = A.xsrc;
         unsigned zmask = 0;
 #pragma unroll
         for (int e = 0; e < CB; ++e)
             if (c0 + e < g.out.C) zmask |= getbit(zb, bicol0 + (long)e * g.out.colpad) << e;
-        Tc LI[CB], UI[CB];
-#pragma unroll
-        for (int e = 0; e < CB; ++e) LI[e] = UI[e] = 0;
         if constexpr (DV) {
             // dense layer over channels of 4k positions: 4 consecutive taps
             // are consecutive positions of one channel (one vector load of
@@ -658,23 +625,11 @@ __global__ void __launch_bounds__(kWave * NW) k_mask_consts(MaskArgs<Ts> A) {
                              getbit(xbits, tp.bi), LI, UI);
             }
         }
-#pragma unroll
-        for (int e = 0; e < CB; ++e) {
-            if (!kFinal64) {
-                fin0[e] = LI[e];
-                fin1[e] = UI[e];
-            } else if (c0 + e < g.out.C) {
-                const long idx_e = ((long)(c0 + e) * S + s) * g.out.P + p;
-                const Tc bq = (Tc)A.R.slot[j].beta[idx_e];
-                fin0[e] += bq * (LI[e] + UI[e]);
-                fin1[e] += bq * LI[e];
-            }
-        }
     }
 #pragma unroll
     for (int e = 0; e < CB; ++e) {
-        red[((wave * CB + e) * 2 + 0) * kWave + lane] = fin0[e];
-        red[((wave * CB + e) * 2 + 1) * kWave + lane] = fin1[e];
+        red[((wave * CB + e) * 2 + 0) * kWave + lane] = LI[e];
+        red[((wave * CB + e) * 2 + 1) * kWave + lane] = UI[e];
     }
     __syncthreads();
     const int e = wave;
@@ -687,30 +642,15 @@ __global__ void __launch_bounds__(kWave * NW) k_mask_consts(MaskArgs<Ts> A) {
         r0 += red[((w * CB + e) * 2 + 0) * kWave + lane];
         r1 += red[((w * CB + e) * 2 + 1) * kWave + lane];
     }
-    if (!kFinal64) {
-        MaskSlotT<Ts> M = A.R.slot[q0];
-        M.LI[idx] = (Ts)r0;
-        M.UI[idx] = (Ts)r1;
-        if (A.zero_state) {
-            M.beta[idx] = 0;
-            M.m[idx] = 0;
-            M.v[idx] = 0;
-            M.u[idx] = 0;
-        }
-        return;
+    MaskSlotT<Ts> M = A.R.slot[A.q];
+    M.LI[idx] = (Ts)r0;
+    M.UI[idx] = (Ts)r1;
+    if (A.zero_state) {
+        M.beta[idx] = 0;
+        M.m[idx] = 0;
+        M.v[idx] = 0;
+        M.u[idx] = 0;
     }
-    // FP64 sums of the final bound for neuron (c, s, p) of layer k:
-    // own = alpha - beta0 - beta1 - sum beta_I,
-    // g = beta0 uhat + beta1 lhat + sum beta_I (LI + UI + b),
-    // const = b alpha + beta1 (lhat - b) + sum LI beta_I.
-    const double bb = (double)g.b[c];
-    const double al = A.R.alpha[idx], b0 = A.R.beta0[idx], b1 = A.R.beta1[idx];
-    const double lh = A.R.lhat[idx], uh = A.R.uhat[idx];
-    double sb = 0;
-    for (int j = 0; j < nsl; ++j) sb += (double)A.R.slot[j].beta[idx];
-    A.R.own64[idx] = al - b0 - b1 - sb;
-    A.R.g64[idx] = b0 * uh + b1 * lh + (double)r0 + bb * sb;
-    A.R.const64[idx] = bb * al + b1 * (lh - bb) + (double)r1;
 }
 
 // Copies n 32-bit words.

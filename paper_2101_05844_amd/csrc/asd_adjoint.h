@@ -381,6 +381,9 @@ template <typename Ts, int NM, bool DENSE>
 __global__ void __launch_bounds__(kGradThreads) k_grad_box_sc(GradArgs<Ts> A, int NC) {
     constexpr int RL = 3 + NM;                 // Bz, P - B, zs, Q_0 .. Q_{NM-1}
     constexpr int RLP = (RL + 1) & ~1;
+    // record stride: an odd number of 16-byte units, so that neighbouring
+    // outputs read by one wave fall in different LDS banks
+    constexpr int RLS = (RLP / 2) % 2 ? RLP : RLP + 2;
     extern __shared__ __align__(16) double lds_box[];
     const cptr_t<ReluLayerT<Ts>> R = kconst_t(A.R);
     const LayerGeo& g = A.g;
@@ -390,7 +393,7 @@ __global__ void __launch_bounds__(kGradThreads) k_grad_box_sc(GradArgs<Ts> A, in
     const int s = blockIdx.y;
     const int jb = blockIdx.x * kGradThreads * kGbNI + threadIdx.x;
     double* rec = lds_box;
-    float* wl = reinterpret_cast<float*>(lds_box + (size_t)NC * O.P * RLP);
+    float* wl = reinterpret_cast<float*>(lds_box + (size_t)NC * O.P * RLS);
     const int ks = g.ksz, str = g.stride;
     if (!DENSE) {
         for (int e = threadIdx.x; e < O.C * g.fan; e += kGradThreads) wl[e] = g.W[e];
@@ -438,7 +441,7 @@ __global__ void __launch_bounds__(kGradThreads) k_grad_box_sc(GradArgs<Ts> A, in
             r[1] = PmB;
             r[2] = z ? -1.0 : 1.0;
 #pragma unroll
-            for (int i = 0; i < RLP; ++i) rec[(size_t)o * RLP + i] = r[i];
+            for (int i = 0; i < RLP; ++i) rec[(size_t)o * RLS + i] = r[i];
         }
         __syncthreads();
 #pragma unroll
@@ -466,7 +469,7 @@ __global__ void __launch_bounds__(kGradThreads) k_grad_box_sc(GradArgs<Ts> A, in
                 dacc[i] = fma((1.0 - ng) * r[2], t, dacc[i]);
             };
             if (DENSE) {
-                for (int co = c0; co < c0 + nc; ++co) pair(&rec[(size_t)(co - c0) * RLP], g.W[(long)co * g.fan + j]);
+                for (int co = c0; co < c0 + nc; ++co) pair(&rec[(size_t)(co - c0) * RLS], g.W[(long)co * g.fan + j]);
             } else {
                 const int c = j / L.P, p = j - (j / L.P) * L.P;
                 const int y = p / L.W, x = p - (p / L.W) * L.W;
@@ -478,7 +481,7 @@ __global__ void __launch_bounds__(kGradThreads) k_grad_box_sc(GradArgs<Ts> A, in
                         for (int kx = kx0; kx < ks; kx += str) {
                             const int ox = (x + g.pad - kx) / str;
                             if (ox < 0 || ox >= O.W) continue;
-                            pair(&rec[((size_t)(co - c0) * O.P + oy * O.W + ox) * RLP],
+                            pair(&rec[((size_t)(co - c0) * O.P + oy * O.W + ox) * RLS],
                                  wl[((co * L.C + c) * ks + ky) * ks + kx]);
                         }
                     }
@@ -505,7 +508,8 @@ __global__ void __launch_bounds__(kGradThreads) k_grad_box_sc(GradArgs<Ts> A, in
 // weights too large for LDS).
 inline size_t grad_box_lds(const LayerGeo& g, int nm, int NC) {
     const size_t rlp = (size_t)((3 + nm + 1) & ~1);
-    const size_t b = (size_t)NC * g.out.P * rlp * 8 + (g.kind == ASD_LAYER_DENSE ? 0 : (size_t)g.out.C * g.fan * 4);
+    const size_t rls = (rlp / 2) % 2 ? rlp : rlp + 2;
+    const size_t b = (size_t)NC * g.out.P * rls * 8 + (g.kind == ASD_LAYER_DENSE ? 0 : (size_t)g.out.C * g.fan * 4);
     return b;
 }
 

@@ -537,9 +537,12 @@ asd_status grad_box_nm(asd_plan* P, const double* gs, double* dl0, double* du0, 
 template <int NM>
 asd_status final_sums_nm(asd_plan* P, int k, void* inrec, hipStream_t st);
 // FP64 backward pass of the final bound of an FP32 plan into neuron layer k,
-// NM = active masks of layer k+1 (sign classes; asd_final.hip).
+// NM = active masks of layer k+1 (sign classes; asd_final.hip); orec: room
+// for the output records of layer k+1 (bf_rec_units(NM) 16-byte units per
+// neuron).
 template <int NM>
-asd_status backward_final_nm(const BwdArgs<float>& a, hipStream_t st);
+asd_status backward_final_nm(const BwdArgs<float>& a, void* orec, hipStream_t st);
+constexpr int bf_rec_units(int nm) { return (16 + 4 * nm + 15) / 16; }
 
 // Bias, stage one: block (chunk, channel), fixed-order block sum.
 template <typename Ts>

@@ -70,11 +70,19 @@ struct Carver {
 };
 
 // Doubles after the gradient's partial sums that hold the input records of
-// a ReLU layer's weight gradient (the largest input layer of a ReLU layer).
+// a ReLU layer's weight gradient and of the FP64 final sums (the largest
+// input layer of a ReLU layer), or the output records of the FP64 final
+// backward (the largest ReLU layer).
 size_t grad_inrec_doubles(const asd_plan* P) {
     const size_t rec = is64(P) ? sizeof(GwIn<double>) : sizeof(GwIn<float>);
     size_t bytes = 0;
     for (int k = 1; k < P->n; ++k) bytes = std::max(bytes, (size_t)P->geo[k].in.C * P->geo[k].in.cols * rec);
+    // FP32 plans: also the output records of the FP64 final backward (the
+    // neurons of a ReLU layer, at the largest mask count)
+    if (!is64(P))
+        for (int k = 1; k < P->n; ++k)
+            bytes = std::max(bytes, (size_t)P->geo[k].out.C * P->geo[k].out.cols * 16 *
+                                        (size_t)bf_rec_units(P->prm.max_masks));
     return (bytes + 15) / 16 * 2 + 2;  // and up to 8 bytes to reach 16-byte alignment
 }
 
@@ -500,7 +508,7 @@ asd_status launch_backward(asd_plan* P, int k, int want_obj, int role, hipStream
     ProfScope ps(P, st, role, k);
     if constexpr (sizeof(Tc) > sizeof(Ts)) {
         // FP64 final bound of an FP32 plan: the sign-class kernel
-#define ASD_BF_CALL(N) return backward_final_nm<N>(a, st)
+#define ASD_BF_CALL(N) return backward_final_nm<N>(a, grad_inrec(P), st)
         ASD_NM_DISPATCH(a.nm_next, ASD_BF_CALL)
 #undef ASD_BF_CALL
     } else {

@@ -153,8 +153,44 @@ __global__ void __launch_bounds__(kWave * NW) k_final_sums_sc(MaskArgs<float> A,
 // Xu = sum_q xbit_q[j] u_q (no point box): w > 0 gives w (U - Xu), w < 0
 // gives w (Xu + [point box] U), so a pair costs one FMA per mask plus four,
 // written as max(w, 0) (U - Xu) + min(w, 0) (Xu + [point] U).
+// Output-side record of one neuron of layer k+1 for the FP64 backward into
+// layer k (bf_rec_units 16-byte units): v = -alpha + beta_1 + sum over
+// z_q = 1 of b_q and U = sum_q u_q in FP64, then the u_q = (1 - z_q) b_q
+// (FP32 values, exact as floats).
 template <int NM>
-__global__ void __launch_bounds__(kWave * KS) k_backward_final_sc(BwdArgs<float> A) {
+__global__ void __launch_bounds__(256) k_bf_outrec(BwdArgs<float> A, float4* rec) {
+    const NeuronLayout& O = A.gn.out;
+    const long gid = (long)blockIdx.x * 256 + threadIdx.x;
+    if (gid >= (long)O.C * O.cols) return;
+    const int co = (int)(gid / O.cols);
+    const long bi = (long)co * O.colpad + (gid - (long)co * O.cols);
+    double v = -(double)A.Rn.alpha[gid] + (double)A.Rn.beta1[gid], U = 0;
+    constexpr int NQ = bf_rec_units(NM) * 4 - 4 > 0 ? bf_rec_units(NM) * 4 - 4 : 1;
+    float uq[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) uq[i] = 0.f;
+#pragma unroll
+    for (int q = 0; q < NM; ++q) {
+        const float bq = A.Rn.slot[q].beta[gid];
+        if (getbit(A.Rn.slot[q].zbits, bi)) {
+            v += (double)bq;
+        } else {
+            uq[q] = bq;
+            U += (double)bq;
+        }
+    }
+    float4* r = rec + gid * bf_rec_units(NM);
+    double2 vu;
+    vu.x = v;
+    vu.y = U;
+    *reinterpret_cast<double2*>(r) = vu;
+#pragma unroll
+    for (int i = 1; i < bf_rec_units(NM); ++i)
+        r[i] = make_float4(uq[4 * i - 4], uq[4 * i - 3], uq[4 * i - 2], uq[4 * i - 1]);
+}
+
+template <int NM>
+__global__ void __launch_bounds__(kWave * KS) k_backward_final_sc(BwdArgs<float> A, const float4* orec) {
     extern __shared__ unsigned char red_raw[];
     double* red = reinterpret_cast<double*>(red_raw);  // [KS][CB][64]
     const LayerGeo& g = A.gn;
@@ -197,19 +233,21 @@ __global__ void __launch_bounds__(kWave * KS) k_backward_final_sc(BwdArgs<float>
 #pragma unroll
             for (int q = 0; q < NM; ++q) uq[q] = 0;
         } else {
-            v = -(double)A.Rn.alpha[a] + (double)A.Rn.beta1[a];
+            // the output's record (k_bf_outrec)
+            const float4* r = orec + a * bf_rec_units(NM);
+            const double2 vu = *reinterpret_cast<const double2*>(r);
+            v = vu.x;
+            U = vu.y;
 #pragma unroll
-            for (int q = 0; q < NM; ++q) {
-                const double bq = (double)A.Rn.slot[q].beta[a];
-                if (getbit(A.Rn.slot[q].zbits, bi)) {
-                    v += bq;
-                    uq[q] = 0;
-                } else {
-                    uq[q] = bq;
-                    U += bq;
-                }
+            for (int i = 1; i < bf_rec_units(NM); ++i) {
+                const float4 f = r[i];
+                const float fq[4] = {f.x, f.y, f.z, f.w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (4 * i - 4 + j < NM) uq[4 * i - 4 + j] = (double)fq[j];
             }
         }
+        (void)bi;
 #pragma unroll
         for (int e = 0; e < CB; ++e) {
             double Xu = 0;
@@ -334,14 +372,21 @@ asd_status final_sums_nm(asd_plan* P, int k, void* inrec, hipStream_t st) {
 }
 
 template <int NM>
-asd_status backward_final_nm(const BwdArgs<float>& a, hipStream_t st) {
+asd_status backward_final_nm(const BwdArgs<float>& a, void* orec, hipStream_t st) {
+    float4* rec = static_cast<float4*>(orec);
+    if (!a.last) {
+        const long nout = (long)a.gn.out.C * a.gn.out.cols;
+        hipLaunchKernelGGL((k_bf_outrec<NM>), dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, st, a, rec);
+        LAUNCH_CHECK();
+    }
     const size_t lds = (size_t)KS * CB * kWave * sizeof(double);
-    hipLaunchKernelGGL((k_backward_final_sc<NM>), grid_cols(a.gn.in, CB), dim3(kWave, KS), lds, st, a);
+    hipLaunchKernelGGL((k_backward_final_sc<NM>), grid_cols(a.gn.in, CB), dim3(kWave, KS), lds, st, a,
+                       (const float4*)rec);
     LAUNCH_CHECK();
     return ASD_OK;
 }
 
 template asd_status final_sums_nm<ASD_NM>(asd_plan*, int, void*, hipStream_t);
-template asd_status backward_final_nm<ASD_NM>(const BwdArgs<float>&, hipStream_t);
+template asd_status backward_final_nm<ASD_NM>(const BwdArgs<float>&, void*, hipStream_t);
 
 }  // namespace asd

@@ -369,9 +369,9 @@ __global__ void __launch_bounds__(kGradThreads) k_gw_relu(GwArgs<Ts> A) {
 // Box gradient through layer 1 in sign classes, one block per (chunk of
 // kGbNI x 256 inputs, subproblem s).  Per (layer-1 output o, input j) with
 // weight w and b_q = beta_q[o] (g_s applies at the end), the mask terms of
-// the old per-slot form add up to t = PD' w with PD' = PD - [z] B as in the
-// weight gradient; t goes to dl[j] where (w >= 0) == (z = 0) and to du[j]
-// otherwise (w = 0 gives t = 0).  Lanes keep dl + du and dl - du (the sign
+// k_grad_box (one per slot) add up to t = PD' w with PD' = PD - [z] B as in
+// the weight gradient; t goes to dl[j] where (w >= 0) == (z = 0) and to
+// du[j] otherwise (w = 0 gives t = 0).  Lanes keep dl + du and dl - du (the sign
 // of a pair is [w >= 0 ? 1 : -1] [z ? -1 : 1]); the block stages the records
 // (Bz, P - B, zs, Q_q) of a range of whole output channels of s in LDS, and
 // the convolution's weights.

@@ -63,23 +63,25 @@ def _workload(wi, seed):
     return w, ops, lh2, uh2
 
 
-def _plan(A, w, ops, lh, uh, prec):
+def _plan(A, w, ops, lh, uh, prec, max_masks=4):
     probs = H.oracle_problems(w, ops, lh, uh)
     net = A.Net(w.layers)
     prm = A.params_from_schedule(w.schedule, A.ASD_PREC_FP64 if prec == "fp64" else A.ASD_PREC_FP32)
+    prm.max_masks = max(prm.max_masks, max_masks)
     plan = A.Plan(net, w.S, prm)
     plan.init(*H.gpu_batch(w, lh, uh))
     return net, plan, probs
 
 
 @pytest.mark.parametrize("wi", [0, 1, 2])
-@pytest.mark.parametrize("n_masks", [0, 3])
+@pytest.mark.parametrize("n_masks", [0, 3, 8])
 def test_final_bound_with_zero_weights_and_points(wi, n_masks):
     """FP32 plan: asd_bound's FP64 final bound at imported float32 duals and
-    masks equals the oracle's d_B at the same duals."""
+    masks (up to the largest mask count, 8) equals the oracle's d_B at the
+    same duals."""
     A = _A()
     w, ops, lh, uh = _workload(wi, 500 + wi)
-    net, plan, probs = _plan(A, w, ops, lh, uh, "fp32")
+    net, plan, probs = _plan(A, w, ops, lh, uh, "fp32", max_masks=n_masks)
     rng = np.random.default_rng(510 + 10 * wi + n_masks)
     states = [H.random_integral_state(p, rng, n_masks, scale=0.5) for p in probs]
     H.import_states(plan, probs, states)
@@ -100,14 +102,15 @@ def _check(got, ref, mag, tol, what):
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 @pytest.mark.parametrize("wi", [0, 1, 2])
-def test_bound_gradient_with_zero_weights_and_points(wi, prec):
-    """asd_bound_grad at imported duals and three masks against the oracle's
-    Danskin gradient."""
+@pytest.mark.parametrize("n_masks", [3, 8])
+def test_bound_gradient_with_zero_weights_and_points(wi, prec, n_masks):
+    """asd_bound_grad at imported duals and masks (three, or the largest
+    count, 8) against the oracle's Danskin gradient."""
     A = _A()
     w, ops, lh, uh = _workload(wi, 520 + wi)
-    net, plan, probs = _plan(A, w, ops, lh, uh, prec)
-    rng = np.random.default_rng(530 + wi)
-    states = [H.random_integral_state(p, rng, 3, scale=0.5) for p in probs]
+    net, plan, probs = _plan(A, w, ops, lh, uh, prec, max_masks=n_masks)
+    rng = np.random.default_rng(530 + wi + n_masks)
+    states = [H.random_integral_state(p, rng, n_masks, scale=0.5) for p in probs]
     H.import_states(plan, probs, states)
     gs = rng.uniform(-1.0, 2.0, w.S)
     dW, db, dl0, du0 = plan.bound_grad(torch.as_tensor(gs))

@@ -198,6 +198,25 @@ def test_iteration_kernels_at_fixed_duals(wi, n_masks, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16_all"])
+@pytest.mark.parametrize("wi", [0, 1, 2, 3])
+def test_iteration_kernels_at_fixed_duals_max_masks(wi, prec):
+    """As test_iteration_kernels_at_fixed_duals at the largest mask count
+    the library takes (8, above the 7 of the benchmark schedule): the
+    iteration kernels' instances for K = 8 under every kernel choice."""
+    w = workloads_small()[wi]
+    A = _A()
+    prm = A.params_from_schedule(w.schedule, _mode(A, prec))
+    prm.max_masks = 8
+    A, ops, probs, net, plan, _ = _setup(w, prm)
+    rng = np.random.default_rng(540 + wi)
+    states = [H.random_integral_state(p, rng, 8, scale=0.5) for p in probs]
+    H.import_states(plan, probs, states)
+    ef, eg = PREC_TOL[prec]
+    tot = _eval_all_alternatives(A, plan, probs, states, 8, EPS[ef], EPS[eg])
+    print(w.name, 8, prec, tot, flush=True)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16_all"])
 @pytest.mark.parametrize("shape", ["c1x16x8", "c4x16x16", "c2x8x64"])
 def test_iteration_kernels_at_fixed_duals_m4(shape, prec):
     """As above on the input layers of the 4-channel matrix-core transposed
@@ -510,6 +529,24 @@ def test_end_to_end_fp64(wi):
         r = O.solve(p, prm)
         assert abs(lb[s] - r.bound) <= 1e-8 * max(1.0, abs(r.bound)), (s, lb[s], r.bound)
         assert lb[s] <= _sampled_min(ops, p, w.l0[s], w.u0[s], s) + 1e-9
+
+
+@pytest.mark.parametrize("wi", [0, 1])
+def test_end_to_end_fp64_mask_cap(wi):
+    """Whole FP64 runs that reach the mask cap of Sec. 7.1 (7 active sets per
+    layer: additions of 2 every 5 iterations over 16 Active Set iterations)
+    agree with the FP64 oracle run on the same schedule."""
+    w = e2e_workloads()[wi]
+    sched = WL.Schedule(bigm_iters=10, as_iters=16, add_every=5, add_count=2, max_masks=7)
+    w = WL.Workload(w.name, w.layers, w.l0, w.u0, w.c, sched, w.fix_draws, w.meta)
+    A = _A()
+    A, ops, probs, net, plan, batch = _setup(w, prec="fp64")
+    lb = plan.solve(*batch).cpu().numpy()
+    assert plan.counts().n_masks == 7
+    prm = O.params_from_schedule(sched)
+    for s, p in enumerate(probs[:8]):
+        r = O.solve(p, prm)
+        assert abs(lb[s] - r.bound) <= 1e-8 * max(1.0, abs(r.bound)), (s, lb[s], r.bound)
 
 
 @pytest.mark.parametrize("wi", [0, 1, 2, 3])

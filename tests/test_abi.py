@@ -59,6 +59,8 @@ def test_host_validation_without_gpu():
     nbytes = ctypes.c_size_t()
     assert L.asd_plan_workspace_size(h, 4, ctypes.byref(p), ctypes.byref(nbytes)) == 0
     assert nbytes.value > 0
+    assert L.asd_plan_workspace_size(h, 0, ctypes.byref(p), ctypes.byref(nbytes)) == 1  # empty batch
+    assert b"S must be" in L.asd_last_error()
     p.max_masks = 99
     assert L.asd_plan_workspace_size(h, 4, ctypes.byref(p), ctypes.byref(nbytes)) == 1
     L.asd_net_destroy(h)

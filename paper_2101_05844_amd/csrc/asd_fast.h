@@ -56,6 +56,20 @@ __device__ __forceinline__ cfloat_p kconst(const float* p) { return (cfloat_p)p;
 template <typename T>
 __device__ __forceinline__ cptr_t<T> kconst_t(const T* p) { return (cptr_t<T>)p; }
 
+// Streaming access to the per-neuron state of the update (read and written
+// once per iteration), non-temporal where measured faster: the loads with
+// active masks, the stores without (Big-M iterations).
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st_stream(T* p, T v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 template <typename T> __device__ __forceinline__ T flip(T x, unsigned bit) { return bit ? -x : x; }
 
 constexpr int kPointBit = 15;
@@ -234,11 +248,11 @@ __device__ __forceinline__ void fwd_load(const FastFwdArgs<T>& A, int c, uint32_
     in.bb = (T)A.g.b[c];
     in.x = A.xout[idx];
     in.z = (T)getbit(R->zbits, bi);
-    in.lh = R->lhat[idx];
-    in.uh = R->uhat[idx];
-    in.th[0] = R->alpha[idx];
-    in.th[1] = R->beta0[idx];
-    in.th[2] = R->beta1[idx];
+    in.lh = ld_stream<(NM > 0)>(&R->lhat[idx]);
+    in.uh = ld_stream<(NM > 0)>(&R->uhat[idx]);
+    in.th[0] = ld_stream<(NM > 0)>(&R->alpha[idx]);
+    in.th[1] = ld_stream<(NM > 0)>(&R->beta0[idx]);
+    in.th[2] = ld_stream<(NM > 0)>(&R->beta1[idx]);
     for (int j = 0; j < 3; ++j) in.m[j] = in.v[j] = (T)0;
 #pragma unroll
     for (int q = 0; q < (NM > 0 ? NM : 1); ++q) in.mq[q] = in.vq[q] = (T)0;
@@ -248,27 +262,27 @@ __device__ __forceinline__ void fwd_load(const FastFwdArgs<T>& A, int c, uint32_
             load_moments_bf16(R->beta0_m, idx, in.m[1], in.v[1]);
             load_moments_bf16(R->beta1_m, idx, in.m[2], in.v[2]);
         } else {
-            in.m[0] = R->alpha_m[idx];
-            in.v[0] = R->alpha_v[idx];
-            in.m[1] = R->beta0_m[idx];
-            in.v[1] = R->beta0_v[idx];
-            in.m[2] = R->beta1_m[idx];
-            in.v[2] = R->beta1_v[idx];
+            in.m[0] = ld_stream<(NM > 0)>(&R->alpha_m[idx]);
+            in.v[0] = ld_stream<(NM > 0)>(&R->alpha_v[idx]);
+            in.m[1] = ld_stream<(NM > 0)>(&R->beta0_m[idx]);
+            in.v[1] = ld_stream<(NM > 0)>(&R->beta0_v[idx]);
+            in.m[2] = ld_stream<(NM > 0)>(&R->beta1_m[idx]);
+            in.v[2] = ld_stream<(NM > 0)>(&R->beta1_v[idx]);
         }
     }
     in.zq = NM > 0 ? (unsigned)R->zpk[idx] : 0u;
 #pragma unroll
     for (int q = 0; q < NM; ++q) {
         const cptr_t<MaskSlotT<T>> M = &R->slot[q];
-        in.LI[q] = M->LI[idx];
-        in.UI[q] = M->UI[idx];
-        in.bq[q] = M->beta[idx];
+        in.LI[q] = ld_stream<(NM > 0)>(&M->LI[idx]);
+        in.UI[q] = ld_stream<(NM > 0)>(&M->UI[idx]);
+        in.bq[q] = ld_stream<(NM > 0)>(&M->beta[idx]);
         if (adam) {
             if constexpr (MB) {
                 load_moments_bf16(M->m, idx, in.mq[q], in.vq[q]);
             } else {
-                in.mq[q] = M->m[idx];
-                in.vq[q] = M->v[idx];
+                in.mq[q] = ld_stream<(NM > 0)>(&M->m[idx]);
+                in.vq[q] = ld_stream<(NM > 0)>(&M->v[idx]);
             }
         }
     }
@@ -318,8 +332,8 @@ __device__ __forceinline__ void fwd_store(const FastFwdArgs<T>& A, uint32_t idx,
         if constexpr (MB) {
             store_moments_bf16(mo, idx, mm, vv);
         } else {
-            mo[idx] = mm;
-            vo[idx] = vv;
+            st_stream<(NM == 0)>(&mo[idx], mm);
+            st_stream<(NM == 0)>(&vo[idx], vv);
         }
         if constexpr (sizeof(T) == 4) {
             const float den = __builtin_amdgcn_sqrtf(vv * st.ib2[grp]) + st.eps;
@@ -331,9 +345,9 @@ __device__ __forceinline__ void fwd_store(const FastFwdArgs<T>& A, uint32_t idx,
     const T al = step(in.th[0], in.m[0], in.v[0], gr[0], 0, R->alpha_m, R->alpha_v);
     const T b0 = step(in.th[1], in.m[1], in.v[1], gr[1], 0, R->beta0_m, R->beta0_v);
     const T b1 = step(in.th[2], in.m[2], in.v[2], gr[2], 0, R->beta1_m, R->beta1_v);
-    R->alpha[idx] = al;
-    R->beta0[idx] = b0;
-    R->beta1[idx] = b1;
+    st_stream<(NM == 0)>(&R->alpha[idx], al);
+    st_stream<(NM == 0)>(&R->beta0[idx], b0);
+    st_stream<(NM == 0)>(&R->beta1[idx], b1);
     T own = al - b0 - b1;
     T gg = b0 * uh + b1 * lh;
     T vs = -al + b1;
@@ -342,15 +356,15 @@ __device__ __forceinline__ void fwd_store(const FastFwdArgs<T>& A, uint32_t idx,
         const cptr_t<MaskSlotT<T>> M = &R->slot[q];
         const bool zb = (in.zq >> q) & 1u;
         const T bq = A.freeze ? (T)0 : step(in.bq[q], in.mq[q], in.vq[q], gmask(q), 1 + q, M->m, M->v);
-        M->beta[idx] = bq;
+        st_stream<(NM == 0)>(&M->beta[idx], bq);
         own -= bq;
         gg += bq * (in.LI[q] + in.UI[q] + bb);
         vs += zb ? bq : (T)0.5 * bq;
-        M->u[idx] = zb ? (T)0 : bq;
+        st_stream<(NM == 0)>(&M->u[idx], zb ? (T)0 : bq);
     }
-    R->own[idx] = own;
-    R->g[idx] = gg;
-    R->vs[idx] = vs;
+    st_stream<(NM == 0)>(&R->own[idx], own);
+    st_stream<(NM == 0)>(&R->g[idx], gg);
+    st_stream<(NM == 0)>(&R->vs[idx], vs);
 }
 
 template <typename T, int NM, bool MB>

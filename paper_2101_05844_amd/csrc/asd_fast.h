@@ -58,7 +58,8 @@ __device__ __forceinline__ cptr_t<T> kconst_t(const T* p) { return (cptr_t<T>)p;
 
 // Streaming access to the per-neuron state of the update (read and written
 // once per iteration), non-temporal where measured faster: the loads with
-// active masks, the stores without (Big-M iterations).
+// active masks; the stores of multipliers and moments always, those of the
+// backward operands (own, g, vs, u_q) in the Big-M iterations only.
 template <bool NT, typename T>
 __device__ __forceinline__ T ld_stream(const T* p) {
     if constexpr (NT) return __builtin_nontemporal_load(p);
@@ -332,8 +333,8 @@ __device__ __forceinline__ void fwd_store(const FastFwdArgs<T>& A, uint32_t idx,
         if constexpr (MB) {
             store_moments_bf16(mo, idx, mm, vv);
         } else {
-            st_stream<(NM == 0)>(&mo[idx], mm);
-            st_stream<(NM == 0)>(&vo[idx], vv);
+            st_stream<true>(&mo[idx], mm);
+            st_stream<true>(&vo[idx], vv);
         }
         if constexpr (sizeof(T) == 4) {
             const float den = __builtin_amdgcn_sqrtf(vv * st.ib2[grp]) + st.eps;
@@ -345,9 +346,9 @@ __device__ __forceinline__ void fwd_store(const FastFwdArgs<T>& A, uint32_t idx,
     const T al = step(in.th[0], in.m[0], in.v[0], gr[0], 0, R->alpha_m, R->alpha_v);
     const T b0 = step(in.th[1], in.m[1], in.v[1], gr[1], 0, R->beta0_m, R->beta0_v);
     const T b1 = step(in.th[2], in.m[2], in.v[2], gr[2], 0, R->beta1_m, R->beta1_v);
-    st_stream<(NM == 0)>(&R->alpha[idx], al);
-    st_stream<(NM == 0)>(&R->beta0[idx], b0);
-    st_stream<(NM == 0)>(&R->beta1[idx], b1);
+    st_stream<true>(&R->alpha[idx], al);
+    st_stream<true>(&R->beta0[idx], b0);
+    st_stream<true>(&R->beta1[idx], b1);
     T own = al - b0 - b1;
     T gg = b0 * uh + b1 * lh;
     T vs = -al + b1;
@@ -356,7 +357,7 @@ __device__ __forceinline__ void fwd_store(const FastFwdArgs<T>& A, uint32_t idx,
         const cptr_t<MaskSlotT<T>> M = &R->slot[q];
         const bool zb = (in.zq >> q) & 1u;
         const T bq = A.freeze ? (T)0 : step(in.bq[q], in.mq[q], in.vq[q], gmask(q), 1 + q, M->m, M->v);
-        st_stream<(NM == 0)>(&M->beta[idx], bq);
+        st_stream<true>(&M->beta[idx], bq);
         own -= bq;
         gg += bq * (in.LI[q] + in.UI[q] + bb);
         vs += zb ? bq : (T)0.5 * bq;

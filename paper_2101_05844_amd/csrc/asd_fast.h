@@ -173,6 +173,12 @@ __device__ __forceinline__ T ld32(const T* base, uint32_t idx) {
     const uint32_t off = idx * (uint32_t)sizeof(T);
     return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
 }
+// The same, non-temporal: operands staged once per block and not read again.
+template <typename T>
+__device__ __forceinline__ T ld32_stream(const T* base, uint32_t idx) {
+    const uint32_t off = idx * (uint32_t)sizeof(T);
+    return __builtin_nontemporal_load(reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off));
+}
 
 // BF16 storage of Adam moments: round to nearest even on the FP32 bits, and
 // back by placing the 16 stored bits on top (moments are finite).
@@ -1261,7 +1267,7 @@ __device__ __forceinline__ void stage_operands(const FastBwdArgs<float>& A, cons
         for (int r = 0; r <= NM; ++r) {
             const float* base = r == 0 ? A.vs : A.u[r > 0 ? r - 1 : 0];
 #pragma unroll
-            for (int u = 0; u < UL; ++u) v[r][u] = ld32(base, src[u]);
+            for (int u = 0; u < UL; ++u) v[r][u] = ld32_stream(base, src[u]);
         }
 #pragma unroll
         for (int u = 0; u < UL; ++u) {
